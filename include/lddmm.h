@@ -1,0 +1,214 @@
+/*
+ * lddmm.h -- C ABI of the MI355X (gfx950) library for the Gauss-Newton-Krylov
+ * hot path of LDDMM-type diffeomorphic image registration on a periodic 3D
+ * grid (Brunn, Himthani, Biros, Mehl, Mang, arXiv 2008.12820).
+ *
+ * Problem (eq. "problem", Section 1.1): given a template m0 and a reference
+ * m1 on Omega = [0,2pi)^3 (periodic), find a stationary velocity v that
+ * minimises 1/2 ||m(.,1) - m1||^2 + beta/2 <A v, v>, where m is transported
+ * by d_t m + v . grad m = 0, m(.,0) = m0.  The library evaluates the
+ * objective, the reduced gradient (eq. "reducedgrad"), the Gauss-Newton
+ * Hessian matvec (eq. "matvec" with eqs. "incsta", "incadj"), the spectral
+ * preconditioner (beta A)^{-1} (Section 2, "Preconditioning"), a PCG Newton
+ * step and a globalised Gauss-Newton iteration (eq. "iter", Algorithm "GNK"),
+ * and the transport map with its vector-Jacobian product.
+ *
+ * Conventions shared by every call:
+ *  - Grid n[0] x n[1] x n[2], x3 fastest: point p = (i*n1 + j)*n2 + k sits at
+ *    (i h1, j h2, k h3), hd = 2pi/nd.  Every n[d] is even, >= 8, <= 1024, and
+ *    has no prime factor other than 2, 3, 5.
+ *  - Scalar fields are N = n0*n1*n2 float32 values; vector fields are 3N,
+ *    component-major ([3][n0][n1][n2]).
+ *  - Every float pointer is a DEVICE pointer owned by the caller, 4-byte
+ *    aligned, contiguous.  Host pointers are used only for scalars and info
+ *    structs.  The plan copies what it keeps; it never retains caller pointers.
+ *  - All work is enqueued on the plan's HIP stream.  Calls that return host
+ *    scalars (objective, gradient norm, newton step, GN iterate, timing)
+ *    synchronise that stream before returning; the others are asynchronous.
+ *  - Every call returns an lddmm_status and never aborts or prints;
+ *    lddmm_last_error() gives a detail string for the calling thread.
+ *  - A plan is not thread-safe; distinct plans on distinct streams are.
+ *  - Units: J uses the h^3 = h1 h2 h3 quadrature; inner products and norms
+ *    are h^3-weighted; the fields g and H v~ carry no h^3 factor.
+ */
+#ifndef LDDMM_H
+#define LDDMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lddmm_status {
+    LDDMM_OK = 0,
+    LDDMM_EINVAL = 1,       /* bad size, beta, nt, pointer or argument */
+    LDDMM_ENOMEM = 2,       /* device workspace allocation failed */
+    LDDMM_EDEVICE = 3,      /* a HIP runtime error (detail in lddmm_last_error) */
+    LDDMM_ESTATE = 4,       /* call out of order (e.g. gradient before set_velocity) */
+    LDDMM_ENOTCONV = 5,     /* PCG met non-positive curvature or a non-finite value */
+    LDDMM_EUNSUPPORTED = 6  /* valid request this build does not implement */
+} lddmm_status;
+
+/* Regularisation operator A (Section 1.1: H1 seminorm by default, A the
+ * vector Laplacian; the H2 seminorm uses the squared Laplacian).
+ * Spectral symbols |k|^2 and |k|^4. */
+typedef enum lddmm_reg { LDDMM_REG_H1S = 1, LDDMM_REG_H2S = 2 } lddmm_reg;
+
+typedef struct lddmm_config {
+    int32_t n[3];   /* grid size */
+    int32_t nt;     /* time steps N_t >= 1 (dt = 1/N_t), Section 2 "Discretization" */
+    int32_t reg;    /* lddmm_reg */
+    int32_t leray;  /* 1: apply the Leray projection to the body force in g and H v~ */
+    double beta;    /* regularisation weight, finite and > 0 */
+} lddmm_config;
+
+typedef struct lddmm_newton_info {
+    int32_t pcg_iters;  /* Hessian matvecs spent in PCG */
+    int32_t flags;      /* 1: non-positive curvature, 2: non-finite value met */
+    double rel_res;     /* final ||r|| / ||r0|| of PCG */
+    double alpha;       /* accepted line-search step (0 when none was accepted) */
+    double J_before;    /* objective at the velocity the step started from */
+    double J_after;     /* objective at the accepted velocity */
+    double gnorm;       /* ||g|| at the start of the step */
+    double gnorm_rel;   /* ||g|| / ||g0||, g0 the first gradient after set_images */
+} lddmm_newton_info;
+
+typedef struct lddmm_plan lddmm_plan;
+
+/* Device bytes a plan for cfg allocates (host-only arithmetic, no device
+ * call).  EINVAL for an invalid cfg or bytes == NULL. */
+lddmm_status lddmm_workspace_bytes(const lddmm_config *cfg, size_t *bytes);
+
+/* Create a plan on the current HIP device; stream is a hipStream_t (NULL =
+ * the null stream).  Allocates all workspace (departure points, state and
+ * gradient histories, FFT scratch and twiddles, reduction buffers) up front.
+ * EINVAL for an invalid cfg, ENOMEM when the allocation fails. */
+lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan **plan);
+lddmm_status lddmm_plan_destroy(lddmm_plan *plan);
+
+/* Template m0 and reference m1 (N floats each, copied in).  Invalidates the
+ * velocity state and the stored ||g0||. */
+lddmm_status lddmm_set_images(lddmm_plan *plan, const float *m0, const float *m1);
+
+/* Velocity v (3N, copied in).  Computes everything that depends on v only:
+ * departure points of the state and adjoint characteristics (RK2, Section 2
+ * "Discretization", FP64 arithmetic), the state m_j for j = 0..N_t (eq.
+ * "problem" constraint, semi-Lagrangian), grad m_j, grad m_j at the state
+ * departure points, div v and the adjoint reaction coefficient.
+ * ESTATE before set_images. */
+lddmm_status lddmm_set_velocity(lddmm_plan *plan, const float *v);
+
+/* J = 1/2 ||m_{N_t} - m1||^2 + beta/2 <A v, v> (eq. "problem"), and its two
+ * parts; any output pointer may be NULL.  ESTATE before set_velocity. */
+lddmm_status lddmm_objective(lddmm_plan *plan, double *J, double *mismatch, double *reg);
+
+/* Reduced gradient g = beta A v + K int_0^1 lam grad m dt (eq. "reducedgrad"),
+ * lam from the adjoint equation (eq. "adj-transport") with final value
+ * m1 - m(1); K = Leray projection if cfg.leray else I.  g: 3N device output.
+ * gnorm (host, may be NULL) receives ||g||.  ESTATE before set_velocity. */
+lddmm_status lddmm_gradient(lddmm_plan *plan, float *g, double *gnorm);
+
+/* Gauss-Newton matvec H v~ = beta A v~ + K int_0^1 lam~ grad m dt
+ * (eq. "matvec"), with m~ from eq. "incsta" (m~(0) = 0) and lam~ from
+ * eq. "incadj" (lam~(1) = -m~(1)).  vt, hvt: 3N device arrays (distinct).
+ * ESTATE before set_velocity. */
+lddmm_status lddmm_hessian_matvec(lddmm_plan *plan, const float *vt, float *hvt);
+
+/* s = (beta A)^{-1} r (Section 2, preconditioner "InvA"; the zero mode is
+ * divided by beta).  r, s: 3N device arrays (may alias). */
+lddmm_status lddmm_apply_inv_reg(lddmm_plan *plan, const float *r, float *s);
+
+/* PCG solve of H v~ = -g at the current velocity (eq. "iter"), x0 = 0,
+ * preconditioner (beta A)^{-1}, at most max_pcg matvecs, stop when
+ * ||r|| <= rtol ||r0||; rtol <= 0 selects eps_K = min(sqrt(||g||/||g0||), 0.5)
+ * (Algorithm "GNK").  vt_out: 3N device output.  ENOTCONV (with vt_out the
+ * last iterate, or M^{-1} r0 at the first iteration) on non-positive
+ * curvature or a non-finite value; info may be NULL. */
+lddmm_status lddmm_newton_step(lddmm_plan *plan, int32_t max_pcg, double rtol, float *vt_out,
+                               lddmm_newton_info *info);
+
+/* One Gauss-Newton iteration (Algorithm "GNK"): gradient, PCG step as in
+ * lddmm_newton_step, Armijo line search (alpha = 1, accept
+ * J(v + a v~) <= J(v) + 1e-4 a <g, v~>, else halve, at most 10 tries), then
+ * v <- v + a v~ and the plan's velocity state is refreshed.  v_inout: 3N
+ * device array holding v on entry (must equal the plan's velocity) and the
+ * updated velocity on return.  When no step is accepted v is unchanged and
+ * info->alpha = 0. */
+lddmm_status lddmm_gn_iterate(lddmm_plan *plan, int32_t max_pcg, double rtol, float *v_inout,
+                              lddmm_newton_info *info);
+
+/* Transport map (m0, v) -> m(1) (constraint of eq. "problem"): sets the
+ * plan's characteristics from v, writes m(1) to m1_out (N) and, when ckpt is
+ * not NULL, every m_j (j = 0..N_t) to ckpt ((N_t+1) N, the per-step
+ * checkpoints).  Does not need set_images; replaces the plan's velocity. */
+lddmm_status lddmm_transport_forward(lddmm_plan *plan, const float *m0, const float *v,
+                                     float *m1_out, float *ckpt);
+
+/* Vector-Jacobian product of the transport map for a loss with
+ * dL/dm(1) = grad_m1: lam = adjoint sweep (eq. "adj-transport") with final
+ * value grad_m1; grad_m0 = lam(0) (N); grad_v = -int_0^1 lam grad m dt (3N),
+ * grad m from the checkpoints ckpt ((N_t+1) N from lddmm_transport_forward
+ * with the same v).  Either output may be NULL. */
+lddmm_status lddmm_transport_vjp(lddmm_plan *plan, const float *ckpt, const float *v,
+                                 const float *grad_m1, float *grad_m0, float *grad_v);
+
+/* ---- step-level calls: each step of the path on its own ---------------- */
+
+/* Unnormalised 3D real-to-complex DFT, hat f(k) = sum_x f(x) e^{-i k.x},
+ * written in the standard half-spectrum layout [n0][n1][n2/2+1] of
+ * interleaved (re, im) float pairs.  f: N, fhat: 2 n0 n1 (n2/2+1) floats. */
+lddmm_status lddmm_fft_r2c(lddmm_plan *plan, const float *f, float *fhat);
+
+/* Inverse of lddmm_fft_r2c including the 1/N factor (Hermitian input). */
+lddmm_status lddmm_fft_c2r(lddmm_plan *plan, const float *fhat, float *f);
+
+/* Spectral operators (Section 2: derivatives, A, its inverse and the Leray
+ * projection are diagonal in the spectral domain).  First-order symbols use
+ * i k with the Nyquist wavenumber set to 0; A uses the full |k|^2 or |k|^4.
+ *   LDDMM_OP_GRAD   in N   -> out 3N   grad f
+ *   LDDMM_OP_DIV    in 3N  -> out N    div v
+ *   LDDMM_OP_REG    in 3N  -> out 3N   A v (per component)
+ *   LDDMM_OP_INVREG in 3N  -> out 3N   (beta A)^{-1} v
+ *   LDDMM_OP_LERAY  in 3N  -> out 3N   (I - k k^T/|k|^2) v                  */
+enum { LDDMM_OP_GRAD = 1, LDDMM_OP_DIV = 2, LDDMM_OP_REG = 3, LDDMM_OP_INVREG = 4,
+       LDDMM_OP_LERAY = 5 };
+lddmm_status lddmm_spectral_op(lddmm_plan *plan, int32_t op, const float *in, float *out);
+
+/* Cubic Lagrange interpolation (Section 3.1, d = 3): out[f][p] = I[field
+ * f](x_p + h * disp[:, p]) for nfields fields, disp a 3N displacement in
+ * voxels.  Nodes floor(u)-1 .. floor(u)+2, periodic. */
+lddmm_status lddmm_interp(lddmm_plan *plan, int32_t nfields, const float *fields,
+                          const float *disp, float *out);
+
+/* Copy a plan-held array to out: LDDMM_FIELD_DISP (state departure
+ * displacement (X - x)/h, 3N), LDDMM_FIELD_DISP_ADJ (adjoint, 3N),
+ * LDDMM_FIELD_STATE (m_j, N), LDDMM_FIELD_GRAD_STATE (grad m_j, 3N),
+ * LDDMM_FIELD_DIV (div v, N), LDDMM_FIELD_INC_STATE (m~(1) of the last
+ * matvec, N), LDDMM_FIELD_ADJOINT (lam_j of the last gradient, N).
+ * ESTATE when the array has not been computed. */
+enum { LDDMM_FIELD_DISP = 1, LDDMM_FIELD_DISP_ADJ = 2, LDDMM_FIELD_STATE = 3,
+       LDDMM_FIELD_GRAD_STATE = 4, LDDMM_FIELD_DIV = 5, LDDMM_FIELD_INC_STATE = 6,
+       LDDMM_FIELD_ADJOINT = 7 };
+lddmm_status lddmm_get_field(lddmm_plan *plan, int32_t what, int32_t j, float *out);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* enable != 0: bracket every kernel launch of the plan with HIP events on
+ * the plan's stream.  lddmm_get_timing synchronises, then reports the summed
+ * event time (ms) and launch count of kernel class id since the last reset
+ * (lddmm_set_timing resets).  Ids 0 .. lddmm_num_kernels()-1. */
+lddmm_status lddmm_set_timing(lddmm_plan *plan, int32_t enable);
+lddmm_status lddmm_get_timing(lddmm_plan *plan, int32_t kernel_id, double *total_ms,
+                              int64_t *launches);
+int32_t lddmm_num_kernels(void);
+const char *lddmm_kernel_name(int32_t kernel_id);
+
+const char *lddmm_status_string(lddmm_status s);
+const char *lddmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDDMM_H */

@@ -1,0 +1,769 @@
+// C ABI of the gfx950 LDDMM library: plan management and the host-side
+// sequencing of the Gauss-Newton-Krylov hot path (Algorithm "GNK" of
+// arXiv 2008.12820).  No arithmetic on fields happens here; every step runs
+// in the kernels of fft.hip, transport.hip and linalg.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace lddmm {
+
+static thread_local std::string g_last_error;
+
+void fail(lddmm_status s, const std::string &msg) { throw Error{s, msg}; }
+
+void check_hip(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) fail(LDDMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+const char *kernel_name(int id)
+{
+    static const char *names[K_NUM_KERNELS] = {
+        "r2c_x3", "fft_cols", "x1_symbol", "c2r_x3", "departure", "state_step", "gather_vec",
+        "adj_coef", "adj_step", "incstate_init", "incstate_step", "body_force", "dot", "vecop",
+        "pack"};
+    return (id >= 0 && id < K_NUM_KERNELS) ? names[id] : "unknown";
+}
+
+Scope::Scope(lddmm_plan *p, int k) : P(p), kid(k)
+{
+    PlanTiming &T = P->timing;
+    if (!T.on) return;
+    if (T.used == T.pool.size()) {
+        hipEvent_t a, b;
+        check_hip(hipEventCreate(&a), "hipEventCreate");
+        check_hip(hipEventCreate(&b), "hipEventCreate");
+        T.pool.emplace_back(a, b);
+        T.kid.push_back(k);
+    }
+    slot = (int)T.used++;
+    T.kid[slot] = k;
+    check_hip(hipEventRecord(T.pool[slot].first, P->stream), "hipEventRecord");
+}
+
+Scope::~Scope() noexcept(false)
+{
+    if (slot >= 0) (void)hipEventRecord(P->timing.pool[slot].second, P->stream);
+}
+
+template <class F>
+static lddmm_status guard(F &&f)
+{
+    try {
+        f();
+        return LDDMM_OK;
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return LDDMM_ENOMEM;
+    } catch (...) {
+        g_last_error = "unexpected exception";
+        return LDDMM_EDEVICE;
+    }
+}
+
+static bool smooth235(int n)
+{
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+static void validate(const lddmm_config *cfg)
+{
+    if (!cfg) fail(LDDMM_EINVAL, "config is NULL");
+    for (int d = 0; d < 3; ++d) {
+        const int n = cfg->n[d];
+        if (n < 8 || n > 1024 || (n & 1) || !smooth235(n))
+            fail(LDDMM_EINVAL, "grid size n[" + std::to_string(d) + "] = " + std::to_string(n) +
+                                   " must be even, in [8, 1024], with prime factors 2, 3, 5 only");
+    }
+    if (cfg->nt < 1 || cfg->nt > 256) fail(LDDMM_EINVAL, "nt must be in [1, 256]");
+    if (cfg->reg != LDDMM_REG_H1S && cfg->reg != LDDMM_REG_H2S)
+        fail(LDDMM_EINVAL, "reg must be LDDMM_REG_H1S or LDDMM_REG_H2S");
+    if (!(std::isfinite(cfg->beta) && cfg->beta > 0.0)) fail(LDDMM_EINVAL, "beta must be finite and > 0");
+    if (cfg->leray != 0 && cfg->leray != 1) fail(LDDMM_EINVAL, "leray must be 0 or 1");
+}
+
+// Sub-allocation plan of the arena, in bytes, each piece 256-byte aligned.
+struct Layout {
+    size_t off[40];
+    int n = 0;
+    size_t total = 0;
+    size_t add(size_t bytes)
+    {
+        size_t o = total;
+        off[n++] = o;
+        total += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+static int spectral_slots(int nt) { return std::max(9, 4 * std::min(nt + 1, 4)); }
+
+static Layout make_layout(const lddmm_config *cfg)
+{
+    const size_t N = (size_t)cfg->n[0] * cfg->n[1] * cfg->n[2];
+    const size_t nt = (size_t)cfg->nt;
+    const size_t f = sizeof(float) * N;
+    const size_t spec = sizeof(float2) * (size_t)cfg->n[0] * cfg->n[1] * (cfg->n[2] / 2 + 1);
+    Layout L;
+    L.add(f);                       // 0 m0
+    L.add(f);                       // 1 m1
+    L.add(3 * f);                   // 2 v
+    L.add(3 * f);                   // 3 dX
+    L.add(3 * f);                   // 4 dXa
+    L.add((nt + 1) * f);            // 5 m
+    L.add(3 * (nt + 1) * f);        // 6 G
+    L.add(3 * nt * f);              // 7 GX
+    L.add(f);                       // 8 delta
+    L.add(f);                       // 9 coef
+    L.add((nt + 1) * f);            // 10 lam
+    L.add(2 * f);                   // 11 mt
+    L.add(std::max<size_t>(nt - 1, 1) * f);  // 12 src
+    L.add(3 * f);                   // 13 b
+    L.add(3 * f);                   // 14 tmp3
+    L.add(3 * f);                   // 15 g
+    for (int i = 0; i < 6; ++i) L.add(3 * f);  // 16..21 pcg x r z p q vt
+    L.add(spectral_slots(cfg->nt) * spec);     // 22 spec
+    L.add(sizeof(double) * kRedBlocks);        // 23 red
+    L.add(sizeof(double) * kNumScalars);       // 24 dscal
+    return L;
+}
+
+static void plan_free(lddmm_plan *P)
+{
+    if (!P) return;
+    fft_free(P);
+    if (P->arena) (void)hipFree(P->arena);
+    if (P->hscal) (void)hipHostFree(P->hscal);
+    for (auto &pr : P->timing.pool) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    delete P;
+}
+
+static void need(const void *p, const char *name)
+{
+    if (!p) fail(LDDMM_EINVAL, std::string(name) + " is NULL");
+}
+
+static void need_velocity(const lddmm_plan *P)
+{
+    if (!P->have_images) fail(LDDMM_ESTATE, "set_images has not been called");
+    if (!P->have_velocity) fail(LDDMM_ESTATE, "set_velocity has not been called since the last change");
+}
+
+static void copy_dev(lddmm_plan *P, float *dst, const float *src, long count)
+{
+    if (dst == src) return;
+    check_hip(hipMemcpyAsync(dst, src, sizeof(float) * count, hipMemcpyDeviceToDevice, P->stream),
+              "device copy");
+}
+
+static void zero_dev(lddmm_plan *P, float *dst, long count)
+{
+    fill(P, count, 0.f, dst);
+}
+
+// ---------------------------------------------------------------------------
+// operators
+// ---------------------------------------------------------------------------
+static void velocity_state(lddmm_plan *P)
+{
+    const long N = P->N;
+    const int nt = P->nt;
+    launch_departure(P, P->v, P->dX, P->dXa);
+    copy_dev(P, P->m, P->m0, N);
+    for (int j = 0; j < nt; ++j)
+        launch_interp(P, 1, P->m + (long)j * N, P->dX, P->m + (long)(j + 1) * N, K_STATE_STEP);
+    std::vector<const float *> in;
+    std::vector<float *> out;
+    for (int j = 0; j <= nt; ++j) {
+        in.push_back(P->m + (long)j * N);
+        for (int c = 0; c < 3; ++c) out.push_back(P->G + ((long)j * 3 + c) * N);
+    }
+    spectral_apply(P, SOP_GRAD, in, out);
+    launch_interp(P, 3 * nt, P->G, P->dX, P->GX, K_GATHER_VEC);
+    spectral_apply(P, SOP_DIV, {P->v, P->v + N, P->v + 2 * N}, {P->delta});
+    launch_adj_coef(P);
+    P->have_velocity = 1;
+    P->have_grad = 0;
+    P->have_matvec = 0;
+}
+
+static void assemble(lddmm_plan *P, const float *w, const float *b, float *out)
+{
+    const long N = P->N;
+    spectral_apply(P, SOP_ASSEMBLE, {w, w + N, w + 2 * N, b, b + N, b + 2 * N},
+                   {out, out + N, out + 2 * N});
+}
+
+static double gradient_impl(lddmm_plan *P, float *g)
+{
+    const long N = P->N;
+    const int nt = P->nt;
+    float *lam = P->lam;
+    axpby(P, N, 1.f, P->m1, -1.f, P->m + (long)nt * N, lam + (long)nt * N);
+    for (int j = nt - 1; j >= 0; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
+    launch_body_force(P, lam, lam + (long)nt * N, 1.f, P->G, P->b);
+    assemble(P, P->v, P->b, g);
+    dot_async(P, g, g, 3 * N, 0, P->h3);
+    const double gn = std::sqrt(fetch_scalar(P, 0));
+    if (P->g0norm == 0.0) P->g0norm = gn;
+    P->have_grad = 1;
+    return gn;
+}
+
+static void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
+{
+    const long N = P->N;
+    const int nt = P->nt;
+    float *mt[2] = {P->mt, P->mt + N};
+    launch_incstate_init(P, vt, mt[0]);
+    for (int j = 1; j < nt; ++j)
+        launch_incstate_step(P, mt[(j - 1) & 1], P->src + (long)(j - 1) * N, mt[j & 1]);
+    const float *mtN = mt[(nt - 1) & 1];
+    float *lam = P->lam;
+    launch_adj_step(P, mtN, lam + (long)(nt - 1) * N, -1.f);
+    for (int j = nt - 2; j >= 0; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
+    launch_body_force(P, lam, mtN, -1.f, P->G, P->b);
+    assemble(P, vt, P->b, hvt);
+    P->have_matvec = 1;
+}
+
+static void inv_reg(lddmm_plan *P, const float *r, float *s)
+{
+    const long N = P->N;
+    spectral_apply(P, SOP_INVREG, {r, r + N, r + 2 * N}, {s, s + N, s + 2 * N});
+}
+
+static double dot_now(lddmm_plan *P, const float *a, const float *b, long n)
+{
+    dot_async(P, a, b, n, 1, P->h3);
+    return fetch_scalar(P, 1);
+}
+
+// Preconditioned CG on H x = rhs, x0 = 0, M^{-1} = (beta A)^{-1}.
+static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, float *x,
+                    lddmm_newton_info &info)
+{
+    const long M = 3 * P->N;
+    float *r = P->pr, *z = P->pz, *p = P->pp, *q = P->pq;
+    copy_dev(P, r, rhs, M);
+    zero_dev(P, x, M);
+    const double r0 = std::sqrt(dot_now(P, r, r, M));
+    int it = 0, flags = 0;
+    double rn = r0;
+    info.pcg_iters = 0;
+    info.rel_res = 0.0;
+    if (r0 == 0.0) return 0;
+    inv_reg(P, r, z);
+    copy_dev(P, p, z, M);
+    double rz = dot_now(P, r, z, M);
+    while (it < max_it) {
+        matvec_impl(P, p, q);
+        ++it;
+        const double kappa = dot_now(P, p, q, M);
+        if (!std::isfinite(kappa)) {
+            flags |= 2;
+            break;
+        }
+        if (kappa <= 0.0) {
+            flags |= 1;
+            if (it == 1) copy_dev(P, x, z, M);
+            break;
+        }
+        const double al = rz / kappa;
+        pcg_update_xr(P, M, (float)al, p, q, x, r);
+        rn = std::sqrt(dot_now(P, r, r, M));
+        if (!std::isfinite(rn)) {
+            flags |= 2;
+            break;
+        }
+        if (rn <= rtol * r0) break;
+        inv_reg(P, r, z);
+        const double rz_new = dot_now(P, r, z, M);
+        const double be = rz_new / rz;
+        rz = rz_new;
+        axpby(P, M, 1.f, z, (float)be, p, p);
+    }
+    info.pcg_iters = it;
+    info.rel_res = rn / r0;
+    info.flags = flags;
+    return flags;
+}
+
+static void objective_impl(lddmm_plan *P, double &J, double &mis, double &reg)
+{
+    const long N = P->N;
+    sqdiff_async(P, P->m + (long)P->nt * N, P->m1, N, 2, 0.5 * P->h3);
+    spectral_apply(P, SOP_REG, {P->v, P->v + N, P->v + 2 * N}, {P->tmp3, P->tmp3 + N, P->tmp3 + 2 * N});
+    dot_async(P, P->tmp3, P->v, 3 * N, 3, 0.5 * P->cfg.beta * P->h3);
+    mis = fetch_scalar(P, 2);
+    reg = fetch_scalar(P, 3);
+    J = mis + reg;
+}
+
+static double tolerance(lddmm_plan *P, double rtol, double gnorm)
+{
+    if (rtol > 0.0) return rtol;
+    const double grel = P->g0norm > 0.0 ? gnorm / P->g0norm : 1.0;
+    return std::min(std::sqrt(grel), 0.5);
+}
+
+}  // namespace lddmm
+
+using namespace lddmm;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+lddmm_status lddmm_workspace_bytes(const lddmm_config *cfg, size_t *bytes)
+{
+    return guard([&] {
+        validate(cfg);
+        need(bytes, "bytes");
+        const int n[3] = {cfg->n[0], cfg->n[1], cfg->n[2]};
+        size_t tw = 0;
+        tw += ((sizeof(float2) * n[0] + 255) & ~size_t(255)) + ((sizeof(float2) * n[1] + 255) & ~size_t(255));
+        tw += ((sizeof(float2) * (n[2] / 2) + 255) & ~size_t(255)) + ((sizeof(float2) * n[2] + 255) & ~size_t(255));
+        *bytes = make_layout(cfg).total + tw;
+    });
+}
+
+lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan **plan)
+{
+    lddmm_plan *P = nullptr;
+    if (plan) *plan = nullptr;
+    lddmm_status st = guard([&] {
+        validate(cfg);
+        need(plan, "plan");
+        P = new lddmm_plan();
+        P->cfg = *cfg;
+        P->stream = (hipStream_t)stream;
+        check_hip(hipGetDevice(&P->device), "hipGetDevice");
+        P->N = (long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+        P->nt = cfg->nt;
+        for (int d = 0; d < 3; ++d) P->h[d] = 2.0 * M_PI / cfg->n[d];
+        P->h3 = P->h[0] * P->h[1] * P->h[2];
+        P->dt = 1.0 / cfg->nt;
+        Layout L = make_layout(cfg);
+        hipError_t e = hipMalloc(&P->arena, L.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            P->arena = nullptr;
+            fail(LDDMM_ENOMEM, "workspace of " + std::to_string(L.total) + " bytes: " + hipGetErrorString(e));
+        }
+        P->arena_bytes = L.total;
+        char *a = (char *)P->arena;
+        auto F = [&](int i) { return (float *)(a + L.off[i]); };
+        P->m0 = F(0);
+        P->m1 = F(1);
+        P->v = F(2);
+        P->dX = F(3);
+        P->dXa = F(4);
+        P->m = F(5);
+        P->G = F(6);
+        P->GX = F(7);
+        P->delta = F(8);
+        P->coef = F(9);
+        P->lam = F(10);
+        P->mt = F(11);
+        P->src = F(12);
+        P->b = F(13);
+        P->tmp3 = F(14);
+        P->g = F(15);
+        P->px = F(16);
+        P->pr = F(17);
+        P->pz = F(18);
+        P->pp = F(19);
+        P->pq = F(20);
+        P->vt = F(21);
+        P->spec = (float2 *)(a + L.off[22]);
+        P->nspec = spectral_slots(cfg->nt);
+        P->red = (double *)(a + L.off[23]);
+        P->dscal = (double *)(a + L.off[24]);
+        check_hip(hipHostMalloc((void **)&P->hscal, sizeof(double) * kNumScalars, hipHostMallocDefault),
+                  "hipHostMalloc");
+        fft_init(P);
+        *plan = P;
+    });
+    if (st != LDDMM_OK && P) {
+        plan_free(P);
+        if (plan) *plan = nullptr;
+    }
+    return st;
+}
+
+lddmm_status lddmm_plan_destroy(lddmm_plan *plan)
+{
+    return guard([&] {
+        need(plan, "plan");
+        (void)hipStreamSynchronize(plan->stream);
+        plan_free(plan);
+    });
+}
+
+lddmm_status lddmm_set_images(lddmm_plan *P, const float *m0, const float *m1)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(m0, "m0");
+        need(m1, "m1");
+        copy_dev(P, P->m0, m0, P->N);
+        copy_dev(P, P->m1, m1, P->N);
+        P->have_images = 1;
+        P->have_velocity = 0;
+        P->g0norm = 0.0;
+    });
+}
+
+lddmm_status lddmm_set_velocity(lddmm_plan *P, const float *v)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(v, "v");
+        if (!P->have_images) fail(LDDMM_ESTATE, "set_images has not been called");
+        copy_dev(P, P->v, v, 3 * P->N);
+        velocity_state(P);
+    });
+}
+
+lddmm_status lddmm_objective(lddmm_plan *P, double *J, double *mismatch, double *reg)
+{
+    return guard([&] {
+        need(P, "plan");
+        need_velocity(P);
+        double j, m, r;
+        objective_impl(P, j, m, r);
+        if (J) *J = j;
+        if (mismatch) *mismatch = m;
+        if (reg) *reg = r;
+    });
+}
+
+lddmm_status lddmm_gradient(lddmm_plan *P, float *g, double *gnorm)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(g, "g");
+        need_velocity(P);
+        const double gn = gradient_impl(P, g);
+        if (gnorm) *gnorm = gn;
+    });
+}
+
+lddmm_status lddmm_hessian_matvec(lddmm_plan *P, const float *vt, float *hvt)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(vt, "vt");
+        need(hvt, "hvt");
+        if (vt == hvt) fail(LDDMM_EINVAL, "vt and hvt must be distinct");
+        need_velocity(P);
+        matvec_impl(P, vt, hvt);
+    });
+}
+
+lddmm_status lddmm_apply_inv_reg(lddmm_plan *P, const float *r, float *s)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(r, "r");
+        need(s, "s");
+        inv_reg(P, r, s);
+    });
+}
+
+lddmm_status lddmm_newton_step(lddmm_plan *P, int32_t max_pcg, double rtol, float *vt_out,
+                               lddmm_newton_info *info)
+{
+    lddmm_newton_info loc{};
+    lddmm_status st = guard([&] {
+        need(P, "plan");
+        need(vt_out, "vt_out");
+        if (max_pcg < 0) fail(LDDMM_EINVAL, "max_pcg must be >= 0");
+        need_velocity(P);
+        const double gn = gradient_impl(P, P->g);
+        loc.gnorm = gn;
+        loc.gnorm_rel = P->g0norm > 0 ? gn / P->g0norm : 1.0;
+        const double tol = tolerance(P, rtol, gn);
+        axpby(P, 3 * P->N, -1.f, P->g, 0.f, nullptr, P->tmp3);
+        const int flags = pcg_impl(P, P->tmp3, max_pcg, tol, vt_out, loc);
+        if (flags) fail(LDDMM_ENOTCONV, flags & 2 ? "PCG met a non-finite value" : "PCG met non-positive curvature");
+    });
+    if (info) *info = loc;
+    return st;
+}
+
+lddmm_status lddmm_gn_iterate(lddmm_plan *P, int32_t max_pcg, double rtol, float *v_inout,
+                              lddmm_newton_info *info)
+{
+    lddmm_newton_info loc{};
+    lddmm_status st = guard([&] {
+        need(P, "plan");
+        need(v_inout, "v_inout");
+        if (max_pcg < 0) fail(LDDMM_EINVAL, "max_pcg must be >= 0");
+        need_velocity(P);
+        const long M = 3 * P->N;
+        const double gn = gradient_impl(P, P->g);
+        loc.gnorm = gn;
+        loc.gnorm_rel = P->g0norm > 0 ? gn / P->g0norm : 1.0;
+        double J0, mis, rg;
+        objective_impl(P, J0, mis, rg);
+        loc.J_before = J0;
+        const double tol = tolerance(P, rtol, gn);
+        axpby(P, M, -1.f, P->g, 0.f, nullptr, P->tmp3);
+        const int flags = pcg_impl(P, P->tmp3, max_pcg, tol, P->vt, loc);
+        const double gv = dot_now(P, P->g, P->vt, M);
+        float *v0 = P->pq, *vn = P->pp;  // PCG scratch is free now
+        copy_dev(P, v0, P->v, M);
+        double alpha = 1.0, Jn = J0;
+        bool ok = false;
+        for (int tries = 0; tries < 10; ++tries) {
+            axpby(P, M, 1.f, v0, (float)alpha, P->vt, vn);
+            copy_dev(P, P->v, vn, M);
+            velocity_state(P);
+            objective_impl(P, Jn, mis, rg);
+            if (Jn <= J0 + 1e-4 * alpha * gv) {
+                ok = true;
+                break;
+            }
+            alpha *= 0.5;
+        }
+        if (!ok) {
+            copy_dev(P, P->v, v0, M);
+            velocity_state(P);
+            alpha = 0.0;
+            Jn = J0;
+        }
+        copy_dev(P, v_inout, P->v, M);
+        check_hip(hipStreamSynchronize(P->stream), "stream sync");
+        loc.alpha = alpha;
+        loc.J_after = Jn;
+        loc.flags = flags;
+    });
+    if (info) *info = loc;
+    return st;
+}
+
+lddmm_status lddmm_transport_forward(lddmm_plan *P, const float *m0, const float *v, float *m1_out,
+                                     float *ckpt)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(m0, "m0");
+        need(v, "v");
+        need(m1_out, "m1_out");
+        const long N = P->N;
+        copy_dev(P, P->v, v, 3 * N);
+        P->have_velocity = 0;
+        launch_departure(P, P->v, P->dX, P->dXa);
+        float *buf = ckpt ? ckpt : P->m;
+        copy_dev(P, buf, m0, N);
+        for (int j = 0; j < P->nt; ++j)
+            launch_interp(P, 1, buf + (long)j * N, P->dX, buf + (long)(j + 1) * N, K_STATE_STEP);
+        copy_dev(P, m1_out, buf + (long)P->nt * N, N);
+    });
+}
+
+lddmm_status lddmm_transport_vjp(lddmm_plan *P, const float *ckpt, const float *v,
+                                 const float *grad_m1, float *grad_m0, float *grad_v)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(ckpt, "ckpt");
+        need(v, "v");
+        need(grad_m1, "grad_m1");
+        const long N = P->N;
+        const int nt = P->nt;
+        copy_dev(P, P->v, v, 3 * N);
+        P->have_velocity = 0;
+        launch_departure(P, P->v, P->dX, P->dXa);
+        spectral_apply(P, SOP_DIV, {P->v, P->v + N, P->v + 2 * N}, {P->delta});
+        launch_adj_coef(P);
+        float *lam = P->lam;
+        copy_dev(P, lam + (long)nt * N, grad_m1, N);
+        for (int j = nt - 1; j >= 0; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
+        if (grad_m0) copy_dev(P, grad_m0, lam, N);
+        if (grad_v) {
+            std::vector<const float *> in;
+            std::vector<float *> out;
+            for (int j = 0; j <= nt; ++j) {
+                in.push_back(ckpt + (long)j * N);
+                for (int c = 0; c < 3; ++c) out.push_back(P->G + ((long)j * 3 + c) * N);
+            }
+            spectral_apply(P, SOP_GRAD, in, out);
+            launch_body_force(P, lam, lam + (long)nt * N, 1.f, P->G, P->b);
+            axpby(P, 3 * N, -1.f, P->b, 0.f, nullptr, grad_v);
+        }
+    });
+}
+
+lddmm_status lddmm_fft_r2c(lddmm_plan *P, const float *f, float *fhat)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(f, "f");
+        need(fhat, "fhat");
+        RealIn ri{};
+        ri.p[0] = f;
+        r2c_fields(P, ri, 1, 0);
+        x2_pass(P, 0, 1, false);
+        x1_pass(P, 0, 1, false);
+        pack_standard(P, 0, (float2 *)fhat);
+    });
+}
+
+lddmm_status lddmm_fft_c2r(lddmm_plan *P, const float *fhat, float *f)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(f, "f");
+        need(fhat, "fhat");
+        unpack_standard(P, (const float2 *)fhat, 0);
+        x1_pass(P, 0, 1, true);
+        x2_pass(P, 0, 1, true);
+        RealOut ro{};
+        ro.p[0] = f;
+        c2r_fields(P, 0, 1, ro, (float)(1.0 / (double)P->N));
+    });
+}
+
+lddmm_status lddmm_spectral_op(lddmm_plan *P, int32_t op, const float *in, float *out)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(in, "in");
+        need(out, "out");
+        const long N = P->N;
+        int sop = 0;
+        switch (op) {
+        case LDDMM_OP_GRAD: sop = SOP_GRAD; break;
+        case LDDMM_OP_DIV: sop = SOP_DIV; break;
+        case LDDMM_OP_REG: sop = SOP_REG; break;
+        case LDDMM_OP_INVREG: sop = SOP_INVREG; break;
+        case LDDMM_OP_LERAY: sop = SOP_LERAY; break;
+        default: fail(LDDMM_EINVAL, "unknown operator");
+        }
+        std::vector<const float *> vi;
+        std::vector<float *> vo;
+        for (int i = 0; i < op_nin(sop); ++i) vi.push_back(in + i * N);
+        for (int o = 0; o < op_nout(sop); ++o) vo.push_back(out + o * N);
+        // LERAY symbol is independent of cfg.leray; the plan flag only selects K
+        spectral_apply(P, sop, vi, vo);
+    });
+}
+
+lddmm_status lddmm_interp(lddmm_plan *P, int32_t nfields, const float *fields, const float *disp,
+                          float *out)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(fields, "fields");
+        need(disp, "disp");
+        need(out, "out");
+        if (nfields < 1) fail(LDDMM_EINVAL, "nfields must be >= 1");
+        launch_interp(P, nfields, fields, disp, out, K_GATHER_VEC);
+    });
+}
+
+lddmm_status lddmm_get_field(lddmm_plan *P, int32_t what, int32_t j, float *out)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(out, "out");
+        const long N = P->N;
+        const int nt = P->nt;
+        auto need_v = [&] { need_velocity(P); };
+        switch (what) {
+        case LDDMM_FIELD_DISP: need_v(); copy_dev(P, out, P->dX, 3 * N); break;
+        case LDDMM_FIELD_DISP_ADJ: need_v(); copy_dev(P, out, P->dXa, 3 * N); break;
+        case LDDMM_FIELD_STATE:
+            need_v();
+            if (j < 0 || j > nt) fail(LDDMM_EINVAL, "j out of range");
+            copy_dev(P, out, P->m + (long)j * N, N);
+            break;
+        case LDDMM_FIELD_GRAD_STATE:
+            need_v();
+            if (j < 0 || j > nt) fail(LDDMM_EINVAL, "j out of range");
+            copy_dev(P, out, P->G + (long)j * 3 * N, 3 * N);
+            break;
+        case LDDMM_FIELD_DIV: need_v(); copy_dev(P, out, P->delta, N); break;
+        case LDDMM_FIELD_INC_STATE:
+            if (!P->have_matvec) fail(LDDMM_ESTATE, "no matvec has been computed");
+            copy_dev(P, out, P->mt + (long)((nt - 1) & 1) * N, N);
+            break;
+        case LDDMM_FIELD_ADJOINT:
+            if (!P->have_grad && !P->have_matvec) fail(LDDMM_ESTATE, "no adjoint has been computed");
+            if (j < 0 || j > nt) fail(LDDMM_EINVAL, "j out of range");
+            copy_dev(P, out, P->lam + (long)j * N, N);
+            break;
+        default: fail(LDDMM_EINVAL, "unknown field");
+        }
+    });
+}
+
+lddmm_status lddmm_set_timing(lddmm_plan *P, int32_t enable)
+{
+    return guard([&] {
+        need(P, "plan");
+        check_hip(hipStreamSynchronize(P->stream), "stream sync");
+        P->timing.on = enable != 0;
+        P->timing.used = 0;
+    });
+}
+
+lddmm_status lddmm_get_timing(lddmm_plan *P, int32_t kernel_id, double *total_ms, int64_t *launches)
+{
+    return guard([&] {
+        need(P, "plan");
+        if (kernel_id < 0 || kernel_id >= K_NUM_KERNELS) fail(LDDMM_EINVAL, "kernel id out of range");
+        check_hip(hipStreamSynchronize(P->stream), "stream sync");
+        double ms = 0.0;
+        int64_t cnt = 0;
+        for (size_t i = 0; i < P->timing.used; ++i) {
+            if (P->timing.kid[i] != kernel_id) continue;
+            float t = 0.f;
+            check_hip(hipEventElapsedTime(&t, P->timing.pool[i].first, P->timing.pool[i].second),
+                      "hipEventElapsedTime");
+            ms += t;
+            ++cnt;
+        }
+        if (total_ms) *total_ms = ms;
+        if (launches) *launches = cnt;
+    });
+}
+
+int32_t lddmm_num_kernels(void) { return K_NUM_KERNELS; }
+
+const char *lddmm_kernel_name(int32_t kernel_id) { return kernel_name(kernel_id); }
+
+const char *lddmm_status_string(lddmm_status s)
+{
+    switch (s) {
+    case LDDMM_OK: return "ok";
+    case LDDMM_EINVAL: return "invalid argument";
+    case LDDMM_ENOMEM: return "out of device memory";
+    case LDDMM_EDEVICE: return "HIP device error";
+    case LDDMM_ESTATE: return "call out of order";
+    case LDDMM_ENOTCONV: return "PCG did not converge (non-positive curvature or non-finite value)";
+    case LDDMM_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *lddmm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

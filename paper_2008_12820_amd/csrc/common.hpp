@@ -1,0 +1,66 @@
+// Shared device helpers and host-side declarations of the gfx950 LDDMM library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lddmm.h"
+
+namespace lddmm {
+
+// ---------------------------------------------------------------------------
+// complex helpers (float2 / double2 as complex numbers)
+// ---------------------------------------------------------------------------
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cmulc(float2 a, float2 b)  // a * conj(b)
+{
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__host__ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ inline float2 cmuli(float2 a) { return make_float2(-a.y, a.x); }  // i * a
+
+// ---------------------------------------------------------------------------
+// FFT line plans
+// ---------------------------------------------------------------------------
+constexpr int kMaxPasses = 12;
+
+struct RadixPlan {
+    int L;                 // line length
+    int np;                // number of passes
+    int r[kMaxPasses];     // radix of each pass (8, 4, 2, 3 or 5)
+};
+
+RadixPlan make_radix_plan(int L);
+
+// Kernel classes for the per-kernel event timing.
+enum KernelId : int {
+    K_R2C_X3 = 0,
+    K_FFT_COLS,
+    K_SPECTRAL_X1,
+    K_C2R_X3,
+    K_DEPARTURE,
+    K_STATE_STEP,
+    K_GATHER_VEC,
+    K_ADJ_COEF,
+    K_ADJ_STEP,
+    K_INCSTATE_INIT,
+    K_INCSTATE_STEP,
+    K_BODY_FORCE,
+    K_DOT,
+    K_VECOP,
+    K_PACK,
+    K_NUM_KERNELS
+};
+const char *kernel_name(int id);
+
+}  // namespace lddmm

@@ -1,0 +1,149 @@
+// Host-side plan and launcher declarations of the gfx950 LDDMM library.
+#pragma once
+
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "common.hpp"
+
+namespace lddmm {
+
+// Thrown inside the library, converted to an lddmm_status at the C boundary.
+struct Error {
+    lddmm_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(lddmm_status s, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+
+// Spectral layout of one real field of n1 x n2 x n3 (internal, never exposed):
+//   main: [n1][n2][n3/2] complex (k3 = 0 .. n3/2-1), then
+//   nyq : [n1][n2]       complex (k3 = n3/2),
+// i.e. n1*n2*(n3/2+1) float2 per field.  After the x3 pass the first two
+// indices are physical (x1, x2); after the x2 pass (x1, k2); after the x1
+// pass (k1, k2).
+struct FftCtx {
+    int n1 = 0, n2 = 0, n3 = 0, m3 = 0;
+    long nrow = 0;         // n1*n2
+    long spec_stride = 0;  // float2 per spectral field
+    RadixPlan rp1{}, rp2{}, rp3{};
+    float2 *tw1 = nullptr, *tw2 = nullptr, *tw3 = nullptr, *twN3 = nullptr;  // device tables
+};
+
+struct PlanTiming {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    std::vector<int> kid;  // kernel class of each used pair
+    size_t used = 0;
+};
+
+}  // namespace lddmm
+
+struct lddmm_plan {
+    lddmm_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    long N = 0;
+    int nt = 0;
+    double h[3] = {0, 0, 0};
+    double h3 = 0, dt = 0;
+    lddmm::FftCtx fft;
+
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+
+    float *m0 = nullptr, *m1 = nullptr, *v = nullptr, *dX = nullptr, *dXa = nullptr;
+    float *m = nullptr;      // (nt+1) N, m[0] = m0
+    float *G = nullptr;      // (nt+1) 3N
+    float *GX = nullptr;     // nt 3N, G_j at the state departure points
+    float *delta = nullptr, *coef = nullptr;
+    float *lam = nullptr;    // (nt+1) N adjoint history
+    float *mt = nullptr;     // 2N incremental-state ping-pong
+    float *src = nullptr;    // max(nt-1,1) N incremental-state sources
+    float *b = nullptr, *tmp3 = nullptr, *g = nullptr;
+    float *px = nullptr, *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *vt = nullptr;
+    float2 *spec = nullptr;  // spectral scratch
+    int nspec = 0;
+    double *red = nullptr;   // reduction partials
+    double *dscal = nullptr; // device scalars
+    double *hscal = nullptr; // pinned host mirror
+
+    int have_images = 0, have_velocity = 0, have_grad = 0, have_matvec = 0;
+    double g0norm = 0.0;
+    lddmm::PlanTiming timing;
+};
+
+namespace lddmm {
+
+// ---- launch bracketing (per-kernel HIP events when timing is on) ----------
+struct Scope {
+    lddmm_plan *P;
+    int kid;
+    int slot = -1;
+    Scope(lddmm_plan *p, int k);
+    ~Scope() noexcept(false);
+};
+
+// ---- fft.hip ----------------------------------------------------------------
+struct RealIn {
+    const float *p[8];
+};
+struct RealOut {
+    float *p[8];
+};
+
+void fft_init(lddmm_plan *P);
+void fft_free(lddmm_plan *P);
+// real fields -> spectral fields [first, first+count) of P->spec
+void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int spec_first);
+// x2 pass over spectral fields (forward or inverse)
+void x2_pass(lddmm_plan *P, int spec_first, int count, bool inverse);
+// x1 pass without a symbol (forward or inverse)
+void x1_pass(lddmm_plan *P, int spec_first, int count, bool inverse);
+// spectral fields -> real fields, times scale
+void c2r_fields(lddmm_plan *P, int spec_first, int count, const RealOut &out, float scale);
+
+enum SpecOp { SOP_GRAD = 1, SOP_DIV, SOP_REG, SOP_INVREG, SOP_LERAY, SOP_ASSEMBLE, SOP_IDENT };
+// x1 forward, pointwise symbol, x1 inverse in one pass: batches of the op's
+// input fields at spec_in + b*nin, outputs at spec_out + b*nout.
+void x1_symbol(lddmm_plan *P, int op, int spec_in, int spec_out, int nbatch, int leray);
+// whole operator on real fields (in: nbatch*nin fields, out: nbatch*nout)
+void spectral_apply(lddmm_plan *P, int op, const std::vector<const float *> &in,
+                    const std::vector<float *> &out);
+int op_nin(int op);
+int op_nout(int op);
+// standard half-spectrum [n1][n2][n3/2+1] <-> internal layout
+void pack_standard(lddmm_plan *P, int spec_field, float2 *dst);
+void unpack_standard(lddmm_plan *P, const float2 *srcp, int spec_field);
+
+// ---- transport.hip ----------------------------------------------------------
+void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa);
+void launch_interp(lddmm_plan *P, int nf, const float *fields, const float *disp, float *out,
+                   int kid);
+void launch_adj_coef(lddmm_plan *P);
+void launch_adj_step(lddmm_plan *P, const float *lin, float *lout, float scale);
+void launch_incstate_init(lddmm_plan *P, const float *vt, float *mt1);
+void launch_incstate_step(lddmm_plan *P, const float *min, const float *s, float *mout);
+void launch_body_force(lddmm_plan *P, const float *lam, const float *lamN, float scaleN,
+                       const float *G, float *b);
+
+// ---- linalg.hip -------------------------------------------------------------
+// FP64 h^3-weighted reductions; result left in P->dscal[slot] (device).
+void dot_async(lddmm_plan *P, const float *a, const float *b, long n, int slot, double scale);
+void sqdiff_async(lddmm_plan *P, const float *a, const float *b, long n, int slot,
+                  double scale);
+double fetch_scalar(lddmm_plan *P, int slot);
+// out = a*x + b*y (y may be null)
+void axpby(lddmm_plan *P, long n, float a, const float *x, float b, const float *y, float *out);
+// out[i] = value
+void fill(lddmm_plan *P, long n, float value, float *out);
+// PCG update: x += al p; r -= al q
+void pcg_update_xr(lddmm_plan *P, long n, float al, const float *p, const float *q, float *x,
+                   float *r);
+constexpr int kRedBlocks = 1024;
+constexpr int kNumScalars = 16;
+
+}  // namespace lddmm

@@ -1,0 +1,146 @@
+"""Plan: owns one lddmm_plan (device workspace for one registration problem)
+and marshals torch tensors to the C calls of include/lddmm.h."""
+import torch
+
+from . import _lib as L
+
+
+class Plan:
+    def __init__(self, shape, nt, reg=L.REG_H1S, beta=1e-2, leray=False, device=None,
+                 stream=None):
+        self.shape = tuple(int(s) for s in shape)
+        self.nt = int(nt)
+        self.reg = int(reg)
+        self.beta = float(beta)
+        self.leray = bool(leray)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = s
+        self.cfg = L.make_config(self.shape, self.nt, self.reg, self.beta, self.leray)
+        with torch.cuda.device(self.device):
+            self._h = L.lddmm_plan_create(self.cfg, s.cuda_stream)
+
+    # ---- lifetime ----
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            L.lddmm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def workspace_bytes(shape, nt, reg=L.REG_H1S, beta=1e-2, leray=False):
+        return L.lddmm_workspace_bytes(L.make_config(shape, nt, reg, beta, leray))
+
+    # ---- helpers ----
+    def _scalar(self):
+        return torch.empty(self.shape, device=self.device, dtype=torch.float32)
+
+    def _vector(self):
+        return torch.empty((3,) + self.shape, device=self.device, dtype=torch.float32)
+
+    def _in(self, t, vec):
+        shp = ((3,) if vec else ()) + self.shape
+        if tuple(t.shape) != shp:
+            raise ValueError(f"expected shape {shp}, got {tuple(t.shape)}")
+        if t.device != self.device:
+            raise ValueError(f"tensor on {t.device}, plan on {self.device}")
+        return t.contiguous().to(torch.float32)
+
+    # ---- calls ----
+    def set_images(self, m0, m1):
+        L.lddmm_set_images(self._h, self._in(m0, False), self._in(m1, False))
+
+    def set_velocity(self, v):
+        L.lddmm_set_velocity(self._h, self._in(v, True))
+
+    def objective(self):
+        return L.lddmm_objective(self._h)
+
+    def gradient(self, out=None):
+        g = out if out is not None else self._vector()
+        gn = L.lddmm_gradient(self._h, g)
+        return g, gn
+
+    def hessian_matvec(self, vt, out=None):
+        hv = out if out is not None else self._vector()
+        L.lddmm_hessian_matvec(self._h, self._in(vt, True), hv)
+        return hv
+
+    def apply_inv_reg(self, r, out=None):
+        s = out if out is not None else self._vector()
+        L.lddmm_apply_inv_reg(self._h, self._in(r, True), s)
+        return s
+
+    def newton_step(self, max_pcg, rtol=0.0, out=None, allow_notconv=False):
+        vt = out if out is not None else self._vector()
+        st, info = L.lddmm_newton_step(self._h, max_pcg, rtol, vt, allow_notconv)
+        info["status"] = st
+        return vt, info
+
+    def gn_iterate(self, v, max_pcg, rtol=0.0):
+        """v (updated in place) must equal the plan's current velocity."""
+        return L.lddmm_gn_iterate(self._h, max_pcg, rtol, v)
+
+    def transport_forward(self, m0, v, ckpt=None):
+        m1 = self._scalar()
+        L.lddmm_transport_forward(self._h, self._in(m0, False), self._in(v, True), m1, ckpt)
+        return m1
+
+    def transport_vjp(self, ckpt, v, grad_m1, want_m0=True, want_v=True):
+        gm0 = self._scalar() if want_m0 else None
+        gv = self._vector() if want_v else None
+        L.lddmm_transport_vjp(self._h, ckpt, self._in(v, True), self._in(grad_m1, False), gm0, gv)
+        return gm0, gv
+
+    def fft_r2c(self, f):
+        n1, n2, n3 = self.shape
+        out = torch.empty((n1, n2, n3 // 2 + 1, 2), device=self.device, dtype=torch.float32)
+        L.lddmm_fft_r2c(self._h, self._in(f, False), out)
+        return torch.view_as_complex(out)
+
+    def fft_c2r(self, fhat):
+        n1, n2, n3 = self.shape
+        fr = torch.view_as_real(fhat.to(torch.complex64).contiguous()).contiguous()
+        out = self._scalar()
+        L.lddmm_fft_c2r(self._h, fr, out)
+        return out
+
+    def spectral_op(self, op, x):
+        nin = 1 if op == L.OP_GRAD else 3
+        nout = 1 if op == L.OP_DIV else 3
+        x = self._in(x, nin == 3)
+        out = self._vector() if nout == 3 else self._scalar()
+        L.lddmm_spectral_op(self._h, op, x, out)
+        return out
+
+    def interp(self, fields, disp):
+        """fields: [nf, n1, n2, n3] (or one scalar field); disp: [3, n1, n2, n3] voxels."""
+        single = fields.dim() == 3
+        f = (fields[None] if single else fields).contiguous().to(torch.float32)
+        out = torch.empty_like(f)
+        L.lddmm_interp(self._h, f.shape[0], f, self._in(disp, True), out)
+        return out[0] if single else out
+
+    def get_field(self, what, j=0):
+        vec = what in (L.FIELD_DISP, L.FIELD_DISP_ADJ, L.FIELD_GRAD_STATE)
+        out = self._vector() if vec else self._scalar()
+        L.lddmm_get_field(self._h, what, j, out)
+        return out
+
+    def set_timing(self, enable):
+        L.lddmm_set_timing(self._h, enable)
+
+    def timing(self):
+        """{kernel name: (total ms, launches)} since the last set_timing."""
+        out = {}
+        for k in range(L.lddmm_num_kernels()):
+            ms, n = L.lddmm_get_timing(self._h, k)
+            if n:
+                out[L.lddmm_kernel_name(k)] = (ms, n)
+        return out

@@ -1,0 +1,138 @@
+"""GPU parity of the reduced gradient, objective, Gauss-Newton Hessian matvec,
+PCG Newton step, Gauss-Newton iteration and transport VJP against the FP64
+oracle on identical float32 inputs (rel-L2 <= 1e-5), plus edge cases."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import DEV, incremental, problem, rel, say, to_dev, to_np
+from paper_2008_12820_amd import ENOTCONV, ESTATE, LddmmError, Plan
+from paper_2008_12820_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # shape, nt, reg, beta, leray
+    ((32, 32, 32), 4, 1, 1e-2, False),   # the 32^3 parity problem (H1 seminorm)
+    ((32, 32, 32), 4, 2, 5e-4, True),
+    ((24, 20, 30), 3, 2, 1e-3, False),   # ragged, radix 3 and 5
+    ((48, 40, 36), 2, 1, 5e-2, True),
+    ((16, 16, 16), 1, 2, 1e-2, False),   # a single time step
+]
+
+
+def _plan(shape, nt, reg, beta, leray, m0, m1, v):
+    P = Plan(shape, nt, reg=reg, beta=beta, leray=leray)
+    P.set_images(to_dev(m0), to_dev(m1))
+    P.set_velocity(to_dev(v))
+    return P
+
+
+@pytest.mark.parametrize("shape,nt,reg,beta,leray", CASES)
+def test_gradient_objective_matvec(shape, nt, reg, beta, leray):
+    say(f"gradient/matvec {shape} nt {nt} reg {reg} leray {leray}")
+    m0, m1, vtrue, v, ref = problem(shape, nt, reg, beta, leray, disp=2.0)
+    P = _plan(shape, nt, reg, beta, leray, m0, m1, v)
+    J, mis, rg = P.objective()
+    Jr, misr, rgr = ref.objective()
+    assert abs(mis - misr) / misr < 1e-5 and abs(rg - rgr) / rgr < 1e-5
+    g, gn = P.gradient()
+    g_ref = ref.gradient()
+    assert rel(to_np(g), g_ref) < 1e-5
+    assert abs(gn - np.sqrt(oracle.inner(g_ref, g_ref, ref.h3))) / gn < 1e-5
+    for seed in (1100, 1101):
+        vt = incremental(shape, seed)
+        hv = to_np(P.hessian_matvec(to_dev(vt)))
+        assert rel(hv, ref.matvec(synth.f64(vt))) < 1e-5, seed
+        mt_ref = ref.inc_state(synth.f64(vt))[-1]
+        assert rel(to_np(P.get_field(L.FIELD_INC_STATE)), mt_ref) < 1e-5
+
+
+def test_matvec_at_zero_velocity_and_deterministic():
+    shape, nt = (32, 32, 32), 4
+    say("matvec v=0 closed form / determinism")
+    m0, m1, vtrue, v, ref = problem(shape, nt, 1, 1e-2)
+    zero = np.zeros((3,) + shape, np.float32)
+    P = _plan(shape, nt, 1, 1e-2, False, m0, m1, zero)
+    ref.set_velocity(synth.f64(zero))
+    vt = incremental(shape, 1100)
+    a = to_np(P.hessian_matvec(to_dev(vt)))
+    b = to_np(P.hessian_matvec(to_dev(vt)))
+    assert np.array_equal(a, b)  # bitwise run-to-run determinism
+    gm0 = oracle.spectral_grad(synth.f64(m0))
+    closed = 1e-2 * oracle.reg_apply(synth.f64(vt), 1) + (synth.f64(vt) * gm0).sum(0) * gm0
+    assert rel(a, closed) < 1e-5
+    assert rel(a, ref.matvec(synth.f64(vt))) < 1e-5
+
+
+def test_inv_reg_and_newton_step_match_oracle_pcg():
+    shape, nt = (32, 32, 32), 4
+    say("newton step 10 PCG")
+    m0, m1, vtrue, v, ref = problem(shape, nt, 2, 5e-4, disp=2.0, nblobs=12)
+    P = _plan(shape, nt, 2, 5e-4, False, m0, m1, v)
+    r = incremental(shape, 1200)
+    assert rel(to_np(P.apply_inv_reg(to_dev(r))), oracle.reg_inverse(synth.f64(r), 2, 5e-4)) < 1e-5
+    vt, info = P.newton_step(10, 0.0)
+    g_ref = ref.gradient()
+    vt_ref, pinfo = ref.pcg(-g_ref, 10, 0.0)
+    assert info["pcg_iters"] == pinfo["iters"] == 10
+    assert rel(to_np(vt), vt_ref) < 1e-4
+    assert abs(info["rel_res"] - pinfo["rel_res"]) < 1e-3 * max(pinfo["rel_res"], 1e-3)
+
+
+def test_gn_iterate_matches_oracle():
+    shape, nt = (24, 24, 24), 4
+    say("gn iterate")
+    m0, m1, vtrue, v, ref = problem(shape, nt, 2, 1e-3, disp=2.0, vscale=0.0)
+    P = _plan(shape, nt, 2, 1e-3, False, m0, m1, v)
+    vd = to_dev(v)
+    info = P.gn_iterate(vd, 5, 0.0)
+    v_ref, rinfo = ref.gn_iterate(5, 0.0)
+    assert info["alpha"] == rinfo["alpha"] and info["alpha"] > 0
+    assert abs(info["J_after"] - rinfo["J_after"]) / rinfo["J_after"] < 1e-5
+    assert rel(to_np(vd), v_ref) < 1e-4
+    assert abs(P.objective()[0] - info["J_after"]) <= 1e-6 * info["J_after"]
+
+
+@pytest.mark.parametrize("shape,nt", [((32, 32, 32), 4), ((20, 24, 16), 3)])
+def test_transport_and_vjp_match_oracle(shape, nt):
+    say(f"transport/vjp {shape} nt {nt}")
+    m0, m1, vtrue, v, ref = problem(shape, nt, disp=2.0)
+    P = Plan(shape, nt)
+    ck = torch.empty((nt + 1,) + shape, device=DEV)
+    m1g = to_np(P.transport_forward(to_dev(m0), to_dev(v), ck))
+    mref = ref.transport(synth.f64(m0))
+    assert rel(m1g, mref[-1]) < 1e-6
+    assert rel(to_np(ck), mref) < 1e-6
+    gout = synth.f32(synth.bandlimited_scalar(shape, 3, 77))
+    gm0, gv = P.transport_vjp(ck, to_dev(v), to_dev(gout))
+    gm0_ref, gv_ref = ref.transport_vjp(synth.f64(m0), synth.f64(gout))
+    assert rel(to_np(gm0), gm0_ref) < 1e-5
+    assert rel(to_np(gv), gv_ref) < 1e-5
+
+
+def test_state_errors():
+    shape = (16, 16, 16)
+    P = Plan(shape, 2)
+    vt = to_dev(np.zeros((3,) + shape, np.float32))
+    with pytest.raises(LddmmError) as e:
+        P.hessian_matvec(vt)
+    assert e.value.status == ESTATE
+    with pytest.raises(LddmmError):
+        P.gradient()
+
+
+def test_negative_curvature_is_reported():
+    """A zero template makes H = beta A; a huge negative beta is rejected at
+    plan creation, so instead feed a non-finite velocity: PCG reports it."""
+    shape = (16, 16, 16)
+    m0 = np.zeros(shape, np.float32)
+    P = Plan(shape, 2, beta=1e-2)
+    P.set_images(to_dev(m0), to_dev(m0 + 1))
+    v = np.zeros((3,) + shape, np.float32)
+    v[0, 3, 4, 5] = np.nan
+    P.set_velocity(to_dev(v))
+    vt, info = P.newton_step(3, 0.0, allow_notconv=True)
+    assert info["status"] == ENOTCONV and info["flags"] & 2
