@@ -19,8 +19,8 @@
  *    has no prime factor other than 2, 3, 5.
  *  - Scalar fields are N = n0*n1*n2 float32 values; vector fields are 3N,
  *    component-major ([3][n0][n1][n2]).
- *  - Every float pointer is a DEVICE pointer owned by the caller, 4-byte
- *    aligned, contiguous.  Host pointers are used only for scalars and info
+ *  - Every float pointer is a DEVICE pointer owned by the caller, 16-byte
+ *    aligned (EINVAL otherwise), contiguous.  Host pointers are used only for scalars and info
  *    structs.  The plan copies what it keeps; it never retains caller pointers.
  *  - All work is enqueued on the plan's HIP stream.  Calls that return host
  *    scalars (objective, gradient norm, newton step, GN iterate, timing)

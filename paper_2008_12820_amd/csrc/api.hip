@@ -156,6 +156,16 @@ static void need(const void *p, const char *name)
     if (!p) fail(LDDMM_EINVAL, std::string(name) + " is NULL");
 }
 
+// device array argument: non-NULL unless optional, 16-byte aligned
+static void need_dev(const void *p, const char *name, bool optional = false)
+{
+    if (!p) {
+        if (optional) return;
+        fail(LDDMM_EINVAL, std::string(name) + " is NULL");
+    }
+    if ((uintptr_t)p % 16 != 0) fail(LDDMM_EINVAL, std::string(name) + " is not 16-byte aligned");
+}
+
 static void need_velocity(const lddmm_plan *P)
 {
     if (!P->have_images) fail(LDDMM_ESTATE, "set_images has not been called");
@@ -419,8 +429,8 @@ lddmm_status lddmm_set_images(lddmm_plan *P, const float *m0, const float *m1)
 {
     return guard([&] {
         need(P, "plan");
-        need(m0, "m0");
-        need(m1, "m1");
+        need_dev(m0, "m0");
+        need_dev(m1, "m1");
         copy_dev(P, P->m0, m0, P->N);
         copy_dev(P, P->m1, m1, P->N);
         P->have_images = 1;
@@ -433,7 +443,7 @@ lddmm_status lddmm_set_velocity(lddmm_plan *P, const float *v)
 {
     return guard([&] {
         need(P, "plan");
-        need(v, "v");
+        need_dev(v, "v");
         if (!P->have_images) fail(LDDMM_ESTATE, "set_images has not been called");
         copy_dev(P, P->v, v, 3 * P->N);
         velocity_state(P);
@@ -457,7 +467,7 @@ lddmm_status lddmm_gradient(lddmm_plan *P, float *g, double *gnorm)
 {
     return guard([&] {
         need(P, "plan");
-        need(g, "g");
+        need_dev(g, "g");
         need_velocity(P);
         const double gn = gradient_impl(P, g);
         if (gnorm) *gnorm = gn;
@@ -468,8 +478,8 @@ lddmm_status lddmm_hessian_matvec(lddmm_plan *P, const float *vt, float *hvt)
 {
     return guard([&] {
         need(P, "plan");
-        need(vt, "vt");
-        need(hvt, "hvt");
+        need_dev(vt, "vt");
+        need_dev(hvt, "hvt");
         if (vt == hvt) fail(LDDMM_EINVAL, "vt and hvt must be distinct");
         need_velocity(P);
         matvec_impl(P, vt, hvt);
@@ -480,8 +490,8 @@ lddmm_status lddmm_apply_inv_reg(lddmm_plan *P, const float *r, float *s)
 {
     return guard([&] {
         need(P, "plan");
-        need(r, "r");
-        need(s, "s");
+        need_dev(r, "r");
+        need_dev(s, "s");
         inv_reg(P, r, s);
     });
 }
@@ -492,7 +502,7 @@ lddmm_status lddmm_newton_step(lddmm_plan *P, int32_t max_pcg, double rtol, floa
     lddmm_newton_info loc{};
     lddmm_status st = guard([&] {
         need(P, "plan");
-        need(vt_out, "vt_out");
+        need_dev(vt_out, "vt_out");
         if (max_pcg < 0) fail(LDDMM_EINVAL, "max_pcg must be >= 0");
         need_velocity(P);
         const double gn = gradient_impl(P, P->g);
@@ -513,7 +523,7 @@ lddmm_status lddmm_gn_iterate(lddmm_plan *P, int32_t max_pcg, double rtol, float
     lddmm_newton_info loc{};
     lddmm_status st = guard([&] {
         need(P, "plan");
-        need(v_inout, "v_inout");
+        need_dev(v_inout, "v_inout");
         if (max_pcg < 0) fail(LDDMM_EINVAL, "max_pcg must be >= 0");
         need_velocity(P);
         const long M = 3 * P->N;
@@ -563,9 +573,9 @@ lddmm_status lddmm_transport_forward(lddmm_plan *P, const float *m0, const float
 {
     return guard([&] {
         need(P, "plan");
-        need(m0, "m0");
-        need(v, "v");
-        need(m1_out, "m1_out");
+        need_dev(m0, "m0");
+        need_dev(v, "v");
+        need_dev(m1_out, "m1_out");
         const long N = P->N;
         copy_dev(P, P->v, v, 3 * N);
         P->have_velocity = 0;
@@ -583,9 +593,11 @@ lddmm_status lddmm_transport_vjp(lddmm_plan *P, const float *ckpt, const float *
 {
     return guard([&] {
         need(P, "plan");
-        need(ckpt, "ckpt");
-        need(v, "v");
-        need(grad_m1, "grad_m1");
+        need_dev(ckpt, "ckpt");
+        need_dev(v, "v");
+        need_dev(grad_m1, "grad_m1");
+        need_dev(grad_m0, "grad_m0", true);
+        need_dev(grad_v, "grad_v", true);
         const long N = P->N;
         const int nt = P->nt;
         copy_dev(P, P->v, v, 3 * N);
@@ -615,8 +627,8 @@ lddmm_status lddmm_fft_r2c(lddmm_plan *P, const float *f, float *fhat)
 {
     return guard([&] {
         need(P, "plan");
-        need(f, "f");
-        need(fhat, "fhat");
+        need_dev(f, "f");
+        need_dev(fhat, "fhat");
         RealIn ri{};
         ri.p[0] = f;
         r2c_fields(P, ri, 1, 0);
@@ -630,8 +642,8 @@ lddmm_status lddmm_fft_c2r(lddmm_plan *P, const float *fhat, float *f)
 {
     return guard([&] {
         need(P, "plan");
-        need(f, "f");
-        need(fhat, "fhat");
+        need_dev(f, "f");
+        need_dev(fhat, "fhat");
         unpack_standard(P, (const float2 *)fhat, 0);
         x1_pass(P, 0, 1, true);
         x2_pass(P, 0, 1, true);
@@ -645,8 +657,8 @@ lddmm_status lddmm_spectral_op(lddmm_plan *P, int32_t op, const float *in, float
 {
     return guard([&] {
         need(P, "plan");
-        need(in, "in");
-        need(out, "out");
+        need_dev(in, "in");
+        need_dev(out, "out");
         const long N = P->N;
         int sop = 0;
         switch (op) {
@@ -671,9 +683,9 @@ lddmm_status lddmm_interp(lddmm_plan *P, int32_t nfields, const float *fields, c
 {
     return guard([&] {
         need(P, "plan");
-        need(fields, "fields");
-        need(disp, "disp");
-        need(out, "out");
+        need_dev(fields, "fields");
+        need_dev(disp, "disp");
+        need_dev(out, "out");
         if (nfields < 1) fail(LDDMM_EINVAL, "nfields must be >= 1");
         launch_interp(P, nfields, fields, disp, out, K_GATHER_VEC);
     });
@@ -683,7 +695,7 @@ lddmm_status lddmm_get_field(lddmm_plan *P, int32_t what, int32_t j, float *out)
 {
     return guard([&] {
         need(P, "plan");
-        need(out, "out");
+        need_dev(out, "out");
         const long N = P->N;
         const int nt = P->nt;
         auto need_v = [&] { need_velocity(P); };
