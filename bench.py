@@ -1,0 +1,303 @@
+"""Benchmark: Gauss-Newton Hessian matvecs/s and transport grid-points/s at
+256^3 FP32 on one MI355X, with the HBM roofline of the dominant kernel and
+the FP64 CPU oracle timed beside it.
+
+Workload (one "step" = one Hessian matvec, eqs. "matvec", "incsta",
+"incadj" of arXiv 2008.12820, on a fresh incremental velocity):
+  grid 256^3, N_t = 4 (and N_t = 8 reported alongside), cubic Lagrange
+  interpolation, H2 seminorm, beta = 5e-4, Leray projection on;
+  template: 120 periodic Gaussian blobs (sigma 3..12 voxels) in [0,1];
+  reference: a second blob image; velocity v = v_true / 2 with v_true
+  band-limited |k| <= 8 scaled to a 6-voxel maximum displacement;
+  incremental velocities band-limited |k| <= 8, unit RMS (4, reused cyclically).
+All inputs are resident in HBM before timing starts; the per-velocity
+precompute (set_velocity) is timed separately.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_bytes(cls, n, nt):
+    """Algorithmic (compulsory) bytes one Hessian matvec moves through each
+    kernel class: every field read once, every output written once; a gather
+    counts one read of its source field; FFT passes count their spectral
+    input and output once.  Leray on (assembly: 6 fields in, 3 out)."""
+    n1, n2, n3 = n
+    N = n1 * n2 * n3
+    S = n1 * n2 * (n3 // 2 + 1) * 8  # one half-spectrum field
+    return {
+        # dX 12 + v~ 12 + I[G_j](X) 12 nt + G_{j+1} 12 nt; writes m~_1 and s_j: 4 nt
+        "incstate_init": (24 + 28 * nt) * N,
+        # dX 12 + m~_j 4 + s_j 4 + m~_{j+1} 4
+        "incstate_step": 24 * N * (nt - 1),
+        # dXa 12 + lam~_{j+1} 4 + c 4 + lam~_j 4
+        "adj_step": 24 * N * nt,
+        # lam~_j (nt+1) + G_j 3 (nt+1) + b~ 3
+        "body_force": (16 * (nt + 1) + 12) * N,
+        "r2c_x3": 6 * (4 * N + S),
+        "fft_cols": (6 + 3) * 2 * S,
+        "x1_symbol": (6 + 3) * S,
+        "c2r_x3": 3 * (S + 4 * N),
+    }.get(cls)
+
+
+def source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCE = {
+    "incstate_init": ["paper_2008_12820_amd/csrc/transport.hip"],
+    "incstate_step": ["paper_2008_12820_amd/csrc/transport.hip"],
+    "adj_step": ["paper_2008_12820_amd/csrc/transport.hip"],
+    "body_force": ["paper_2008_12820_amd/csrc/transport.hip"],
+    "r2c_x3": ["paper_2008_12820_amd/csrc/fft.hip"],
+    "fft_cols": ["paper_2008_12820_amd/csrc/fft.hip"],
+    "x1_symbol": ["paper_2008_12820_amd/csrc/fft.hip"],
+    "c2r_x3": ["paper_2008_12820_amd/csrc/fft.hip"],
+}
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
+    summary (FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated), or None when
+    no summary exists or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    ent = data.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_hash") != source_hash(KERNEL_SOURCE[kernel]):
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def make_inputs(n, seed=3000):
+    import numpy as np
+    import synth
+    log(f"generating inputs {n}")
+    m0 = synth.f32(synth.blob_image(n, 120, seed))
+    m1 = synth.f32(synth.blob_image(n, 120, seed + 2))
+    vtrue = synth.bandlimited_vector(n, 8, seed + 1, max_disp=6.0)
+    v = synth.f32(0.5 * vtrue)
+    vts = [synth.f32(synth.unit_rms(synth.bandlimited_vector(n, 8, seed + 100 + r)))
+           for r in range(4)]
+    return m0, m1, v, vts
+
+
+def time_matvecs(plan, vts_dev, steps, warmup, torch):
+    out = torch.empty_like(vts_dev[0])
+    for i in range(warmup):
+        plan.hessian_matvec(vts_dev[i % len(vts_dev)], out)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        plan.hessian_matvec(vts_dev[i % len(vts_dev)], out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = plan.timing()
+    plan.set_timing(False)
+    return t1 - t0, kt
+
+
+def cpu_baseline(n, nt, m0, m1, v, vt, sample):
+    import numpy as np
+    import oracle
+    import synth
+    cores = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    shape = n if sample == "full" else tuple(s // 2 for s in n)
+    if sample != "full":
+        sl = (slice(None, None, 2),) * 3
+        m0, m1 = m0[sl], m1[sl]
+        v, vt = v[(slice(None),) + sl], vt[(slice(None),) + sl]
+    P = oracle.Problem(shape, nt, reg=2, beta=5e-4, leray=True)
+    P.set_images(synth.f64(m0), synth.f64(m1))
+    log(f"oracle precompute {shape} (untimed)")
+    P.set_velocity(synth.f64(v))
+    log("oracle matvec (timed)")
+    t0 = time.perf_counter()
+    P.matvec(synth.f64(vt))
+    dt = time.perf_counter() - t0
+    scale = float(np.prod(shape)) / float(np.prod(n))
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {
+        "value": scale / dt,
+        "unit": "matvecs/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"one FP64 oracle Hessian matvec at {shape[0]}^3, N_t={nt} (per-velocity "
+                   f"precompute untimed), {dt:.2f} s" +
+                   ("" if sample == "full" else "; scaled by the point-count ratio to 256^3")),
+        "seconds": dt,
+        "cpu_model": cpu,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--no-nt8", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", choices=["full", "half"], default="full")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU's share only (the whole grid on one device); "
+              "runs on more than one GPU are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2008_12820_amd import Plan
+
+    n = (args.size,) * 3
+    N = int(np.prod(n))
+    nt = 4
+    dev = torch.device("cuda", 0)
+    m0, m1, v, vts = make_inputs(n)
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    m0d, m1d, vd = to(m0), to(m1), to(v)
+    vtd = [to(a) for a in vts]
+
+    res_nt = {}
+    for nt_ in ([4] if args.no_nt8 else [4, 8]):
+        log(f"plan {n} nt={nt_}")
+        plan = Plan(n, nt_, reg=2, beta=5e-4, leray=True, device=dev)
+        plan.set_images(m0d, m1d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.set_velocity(vd)
+        torch.cuda.synchronize()
+        pre = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        g, gn = plan.gradient()
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        steps = args.steps if nt_ == 4 else max(5, args.steps // 2)
+        log(f"timing {steps} matvecs nt={nt_}")
+        el, kt = time_matvecs(plan, vtd, steps, args.warmup, torch)
+        res_nt[nt_] = dict(elapsed=el, steps=steps, kt=kt, precompute_s=pre, gradient_s=tg)
+        if nt_ == 4:
+            log("newton step, 10 PCG iterations")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            vt_out, info = plan.newton_step(10, 0.0)
+            torch.cuda.synchronize()
+            res_nt[nt_]["newton_step_s"] = time.perf_counter() - t0
+            res_nt[nt_]["newton_info"] = {k: info[k] for k in ("pcg_iters", "rel_res", "gnorm")}
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+
+    r4 = res_nt[4]
+    value = r4["steps"] / r4["elapsed"]
+    ms = 1e3 * r4["elapsed"] / r4["steps"]
+
+    def transport_rate(r, nt_):
+        kt = r["kt"]
+        t_inc = sum(kt.get(k, (0, 0))[0] for k in ("incstate_init", "incstate_step")) / r["steps"]
+        t_adj = kt.get("adj_step", (0, 0))[0] / r["steps"]
+        return {
+            "incstate_pts_per_s": N * nt_ / (t_inc * 1e-3),
+            "incadj_pts_per_s": N * nt_ / (t_adj * 1e-3),
+            "headline_pts_per_s": 2 * N * nt_ / ((t_inc + t_adj) * 1e-3),
+        }
+
+    # dominant kernel of the N_t = 4 matvec and its roofline
+    kt = r4["kt"]
+    dom = max((k for k in kt if kernel_bytes(k, n, nt) is not None), key=lambda k: kt[k][0])
+    t_dom_ms, launches = kt[dom]
+    per_matvec_bytes = kernel_bytes(dom, n, nt)
+    launches_per_matvec = launches / r4["steps"]
+    bytes_per_launch = per_matvec_bytes / launches_per_matvec
+    achieved = bytes_per_launch / (t_dom_ms / launches * 1e-3) / 1e9
+    workload = f"matvec_{n[0]}^3_nt{nt}"
+    traffic = measured_traffic(dom, workload)
+    kernels = {k: {"ms_per_matvec": kt[k][0] / r4["steps"],
+                   "launches_per_matvec": kt[k][1] / r4["steps"]} for k in kt}
+    for k in kernels:
+        b = kernel_bytes(k, n, nt)
+        if b is not None:
+            kernels[k]["alg_GBps"] = b / (kernels[k]["ms_per_matvec"] * 1e-3) / 1e9
+    matvec_alg_bytes = (136 + 132 * nt) * N  # whole-matvec algorithmic bytes (Leray on)
+
+    out = {
+        "metric": "Hessian matvecs/s and transport grid-pts/s at 256^3 FP32; % HBM roofline",
+        "value": value,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": r4["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"gauss-newton hessian matvec, {n[0]}^3, N_t={nt}, cubic "
+                               "Lagrange SL, H2 seminorm beta=5e-4, Leray on",
+                   "grid": list(n), "nt": nt, "parallelism": "single GPU (whole grid)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": dom,
+                     "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_ms": t_dom_ms / launches},
+        "transport": transport_rate(r4, 4),
+        "matvec_alg_hbm_frac": matvec_alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "kernels": kernels,
+        "precompute_ms": 1e3 * r4["precompute_s"],
+        "gradient_ms": 1e3 * r4["gradient_s"],
+        "newton_step_10pcg_ms": 1e3 * r4.get("newton_step_s", float("nan")),
+        "newton_info": r4.get("newton_info"),
+    }
+    if 8 in res_nt:
+        r8 = res_nt[8]
+        ms8 = 1e3 * r8["elapsed"] / r8["steps"]
+        out["nt8"] = {"matvecs_per_s": r8["steps"] / r8["elapsed"], "ms_per_matvec": ms8,
+                      "transport": transport_rate(r8, 8),
+                      "matvec_alg_hbm_frac": (136 + 132 * 8) * N / (ms8 * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                      "precompute_ms": 1e3 * r8["precompute_s"]}
+    if not args.no_cpu:
+        log("cpu baseline (FP64 oracle)")
+        out["cpu_baseline"] = cpu_baseline(n, nt, m0, m1, v, vts[0], args.cpu_sample)
+    else:
+        out["cpu_baseline"] = None
+    out["host"] = platform.node()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -132,7 +132,7 @@ static Layout make_layout(const lddmm_config *cfg)
     L.add(3 * f);                   // 14 tmp3
     L.add(3 * f);                   // 15 g
     for (int i = 0; i < 6; ++i) L.add(3 * f);  // 16..21 pcg x r z p q vt
-    L.add(spectral_slots(cfg->nt) * spec);     // 22 spec
+    L.add(spectral_slots(cfg->nt) * 2 * spec); // 22 spec (slots sized for FP64)
     L.add(sizeof(double) * kRedBlocks);        // 23 red
     L.add(sizeof(double) * kNumScalars);       // 24 dscal
     return L;
@@ -346,8 +346,10 @@ lddmm_status lddmm_workspace_bytes(const lddmm_config *cfg, size_t *bytes)
         need(bytes, "bytes");
         const int n[3] = {cfg->n[0], cfg->n[1], cfg->n[2]};
         size_t tw = 0;
-        tw += ((sizeof(float2) * n[0] + 255) & ~size_t(255)) + ((sizeof(float2) * n[1] + 255) & ~size_t(255));
-        tw += ((sizeof(float2) * (n[2] / 2) + 255) & ~size_t(255)) + ((sizeof(float2) * n[2] + 255) & ~size_t(255));
+        for (size_t cs : {sizeof(float2), sizeof(double2)}) {
+            tw += ((cs * n[0] + 255) & ~size_t(255)) + ((cs * n[1] + 255) & ~size_t(255));
+            tw += ((cs * (n[2] / 2) + 255) & ~size_t(255)) + ((cs * n[2] + 255) & ~size_t(255));
+        }
         *bytes = make_layout(cfg).total + tw;
     });
 }
@@ -400,8 +402,9 @@ lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan
         P->pp = F(19);
         P->pq = F(20);
         P->vt = F(21);
-        P->spec = (float2 *)(a + L.off[22]);
+        P->spec = a + L.off[22];
         P->nspec = spectral_slots(cfg->nt);
+        P->slot_bytes = (long)sizeof(double2) * cfg->n[0] * cfg->n[1] * (cfg->n[2] / 2 + 1);
         P->red = (double *)(a + L.off[23]);
         P->dscal = (double *)(a + L.off[24]);
         check_hip(hipHostMalloc((void **)&P->hscal, sizeof(double) * kNumScalars, hipHostMallocDefault),
@@ -631,9 +634,9 @@ lddmm_status lddmm_fft_r2c(lddmm_plan *P, const float *f, float *fhat)
         need_dev(fhat, "fhat");
         RealIn ri{};
         ri.p[0] = f;
-        r2c_fields(P, ri, 1, 0);
-        x2_pass(P, 0, 1, false);
-        x1_pass(P, 0, 1, false);
+        r2c_fields(P, ri, 1, 0, false);
+        x2_pass(P, 0, 1, false, false);
+        x1_pass(P, 0, 1, false, false);
         pack_standard(P, 0, (float2 *)fhat);
     });
 }
@@ -645,8 +648,8 @@ lddmm_status lddmm_fft_c2r(lddmm_plan *P, const float *fhat, float *f)
         need_dev(f, "f");
         need_dev(fhat, "fhat");
         unpack_standard(P, (const float2 *)fhat, 0);
-        x1_pass(P, 0, 1, true);
-        x2_pass(P, 0, 1, true);
+        x1_pass(P, 0, 1, true, false);
+        x2_pass(P, 0, 1, true, false);
         RealOut ro{};
         ro.p[0] = f;
         c2r_fields(P, 0, 1, ro, (float)(1.0 / (double)P->N));

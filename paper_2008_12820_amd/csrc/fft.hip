@@ -11,9 +11,18 @@
 //              Nyquist plane so the main rows stay n3/2 wide and aligned).
 //   fft_cols : complex pass along x2 (or x1) over tiles of TW adjacent k3
 //              columns, staged through LDS, Stockham autosort radix 8/4/2/3/5.
-//   x1_symbol: forward x1 pass, pointwise symbol over all fields of the
-//              operator, inverse x1 pass -- one HBM round trip instead of three.
+//   x1_*     : forward x1 pass, pointwise symbol over all fields of the
+//              operator, inverse x1 pass in one kernel -- one HBM round trip
+//              instead of three.
 //   c2r_x3   : the inverse of r2c_x3, with the output scale folded in.
+//
+// Precision: roundoff of an FP32 forward transform is spread evenly over all
+// wavenumbers, and an unbounded symbol (|k|, |k|^2, |k|^4) multiplies it by up
+// to |k_max|^p while the band-limited signal sits at small |k|.  So the
+// forward chain (r2c, x2, x1) of every field that meets such a symbol runs in
+// FP64 (FP64 storage between passes); bounded symbols (Leray, (beta A)^{-1})
+// and every inverse transform run in FP32, whose roundoff is relative to the
+// output.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -22,138 +31,133 @@
 namespace lddmm {
 
 // ---------------------------------------------------------------------------
+// complex arithmetic templated on float2 / double2
+// ---------------------------------------------------------------------------
+template <class C> struct RealOf;
+template <> struct RealOf<float2> { using type = float; };
+template <> struct RealOf<double2> { using type = double; };
+template <class R> struct CplxOf;
+template <> struct CplxOf<float> { using type = float2; };
+template <> struct CplxOf<double> { using type = double2; };
+
+template <class C>
+__device__ __forceinline__ C mk(typename RealOf<C>::type x, typename RealOf<C>::type y)
+{
+    C r;
+    r.x = x;
+    r.y = y;
+    return r;
+}
+template <class C> __device__ __forceinline__ C add(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <class C> __device__ __forceinline__ C sub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <class C> __device__ __forceinline__ C mul(C a, C b)
+{
+    return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <class C> __device__ __forceinline__ C mulc(C a, C b)  // a * conj(b)
+{
+    return mk<C>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <class C> __device__ __forceinline__ C conj_(C a) { return mk<C>(a.x, -a.y); }
+template <class C> __device__ __forceinline__ C scl(C a, typename RealOf<C>::type s) { return mk<C>(a.x * s, a.y * s); }
+template <class C> __device__ __forceinline__ C muli(C a) { return mk<C>(-a.y, a.x); }  // i * a
+template <class C, bool INV> __device__ __forceinline__ C mul_mi(C a)  // -i a forward, +i a inverse
+{
+    return INV ? mk<C>(-a.y, a.x) : mk<C>(a.y, -a.x);
+}
+__device__ __forceinline__ float2 to_f2(double2 a) { return make_float2((float)a.x, (float)a.y); }
+__device__ __forceinline__ float2 to_f2(float2 a) { return a; }
+
+// ---------------------------------------------------------------------------
 // small DFTs
 // ---------------------------------------------------------------------------
-template <bool INV>
-__device__ __forceinline__ float2 mul_mi(float2 a)  // a * (-i) forward, a * (+i) inverse
+template <class C, bool INV>
+__device__ __forceinline__ void dft2(C *v)
 {
-    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+    C a = v[0], b = v[1];
+    v[0] = add(a, b);
+    v[1] = sub(a, b);
 }
 
-template <int R, bool INV>
-__device__ __forceinline__ void dft_small(float2 *v);
-
-template <>
-__device__ __forceinline__ void dft_small<2, false>(float2 *v)
+template <class C, bool INV>
+__device__ __forceinline__ void dft4(C &v0, C &v1, C &v2, C &v3)
 {
-    float2 a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
-}
-template <>
-__device__ __forceinline__ void dft_small<2, true>(float2 *v)
-{
-    dft_small<2, false>(v);
+    C t0 = add(v0, v2), t1 = sub(v0, v2);
+    C t2 = add(v1, v3), t3 = mul_mi<C, INV>(sub(v1, v3));
+    v0 = add(t0, t2);
+    v2 = sub(t0, t2);
+    v1 = add(t1, t3);
+    v3 = sub(t1, t3);
 }
 
-template <bool INV>
-__device__ __forceinline__ void dft4(float2 &v0, float2 &v1, float2 &v2, float2 &v3)
+template <class C, bool INV>
+__device__ __forceinline__ void dft8(C *v)
 {
-    float2 t0 = cadd(v0, v2), t1 = csub(v0, v2);
-    float2 t2 = cadd(v1, v3), t3 = mul_mi<INV>(csub(v1, v3));
-    v0 = cadd(t0, t2);
-    v2 = csub(t0, t2);
-    v1 = cadd(t1, t3);
-    v3 = csub(t1, t3);
+    using R = typename RealOf<C>::type;
+    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<C, INV>(e0, e1, e2, e3);
+    dft4<C, INV>(o0, o1, o2, o3);
+    const R r = R(0.70710678118654752440);
+    const C w1 = INV ? mk<C>(r, r) : mk<C>(r, -r);
+    const C w3 = INV ? mk<C>(-r, r) : mk<C>(-r, -r);
+    o1 = mul(o1, w1);
+    o2 = mul_mi<C, INV>(o2);
+    o3 = mul(o3, w3);
+    v[0] = add(e0, o0);
+    v[4] = sub(e0, o0);
+    v[1] = add(e1, o1);
+    v[5] = sub(e1, o1);
+    v[2] = add(e2, o2);
+    v[6] = sub(e2, o2);
+    v[3] = add(e3, o3);
+    v[7] = sub(e3, o3);
 }
 
-template <>
-__device__ __forceinline__ void dft_small<4, false>(float2 *v)
+template <class C, bool INV>
+__device__ __forceinline__ void dft3(C *v)
 {
-    dft4<false>(v[0], v[1], v[2], v[3]);
-}
-template <>
-__device__ __forceinline__ void dft_small<4, true>(float2 *v)
-{
-    dft4<true>(v[0], v[1], v[2], v[3]);
-}
-
-template <bool INV>
-__device__ __forceinline__ void dft8(float2 *v)
-{
-    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
-    dft4<INV>(e0, e1, e2, e3);
-    dft4<INV>(o0, o1, o2, o3);
-    const float r = 0.70710678118654752440f;
-    // W8^k, W8 = exp(-+ 2 pi i / 8)
-    float2 w1 = INV ? make_float2(r, r) : make_float2(r, -r);
-    float2 w3 = INV ? make_float2(-r, r) : make_float2(-r, -r);
-    o1 = cmul(o1, w1);
-    o2 = mul_mi<INV>(o2);
-    o3 = cmul(o3, w3);
-    v[0] = cadd(e0, o0);
-    v[4] = csub(e0, o0);
-    v[1] = cadd(e1, o1);
-    v[5] = csub(e1, o1);
-    v[2] = cadd(e2, o2);
-    v[6] = csub(e2, o2);
-    v[3] = cadd(e3, o3);
-    v[7] = csub(e3, o3);
-}
-template <>
-__device__ __forceinline__ void dft_small<8, false>(float2 *v)
-{
-    dft8<false>(v);
-}
-template <>
-__device__ __forceinline__ void dft_small<8, true>(float2 *v)
-{
-    dft8<true>(v);
+    using R = typename RealOf<C>::type;
+    const R s = R(0.86602540378443864676);  // sin(2 pi / 3)
+    C t = add(v[1], v[2]);
+    C d = sub(v[1], v[2]);
+    C m = mk<C>(v[0].x - R(0.5) * t.x, v[0].y - R(0.5) * t.y);
+    C sd = mul_mi<C, INV>(scl(d, s));
+    v[0] = add(v[0], t);
+    v[1] = add(m, sd);
+    v[2] = sub(m, sd);
 }
 
-template <bool INV>
-__device__ __forceinline__ void dft3(float2 *v)
+template <class C, bool INV>
+__device__ __forceinline__ void dft5(C *v)
 {
-    const float s = 0.86602540378443864676f;  // sin(2 pi / 3)
-    float2 t = cadd(v[1], v[2]);
-    float2 d = csub(v[1], v[2]);
-    float2 m = make_float2(v[0].x - 0.5f * t.x, v[0].y - 0.5f * t.y);
-    float2 sd = mul_mi<INV>(cscale(d, s));  // -+ i s d
-    v[0] = cadd(v[0], t);
-    v[1] = cadd(m, sd);
-    v[2] = csub(m, sd);
-}
-template <>
-__device__ __forceinline__ void dft_small<3, false>(float2 *v)
-{
-    dft3<false>(v);
-}
-template <>
-__device__ __forceinline__ void dft_small<3, true>(float2 *v)
-{
-    dft3<true>(v);
+    using R = typename RealOf<C>::type;
+    const R c1 = R(0.30901699437494742410);   // cos(2 pi/5)
+    const R c2 = R(-0.80901699437494742410);  // cos(4 pi/5)
+    const R s1 = R(0.95105651629515357212);   // sin(2 pi/5)
+    const R s2 = R(0.58778525229247312917);   // sin(4 pi/5)
+    C t1 = add(v[1], v[4]), t2 = add(v[2], v[3]);
+    C d1 = sub(v[1], v[4]), d2 = sub(v[2], v[3]);
+    C a1 = mk<C>(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+    C a2 = mk<C>(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+    C b1 = mk<C>(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+    C b2 = mk<C>(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+    C ib1 = mul_mi<C, INV>(b1), ib2 = mul_mi<C, INV>(b2);
+    v[0] = add(v[0], add(t1, t2));
+    v[1] = add(a1, ib1);
+    v[4] = sub(a1, ib1);
+    v[2] = add(a2, ib2);
+    v[3] = sub(a2, ib2);
 }
 
-template <bool INV>
-__device__ __forceinline__ void dft5(float2 *v)
+template <int R, class C, bool INV>
+__device__ __forceinline__ void dft_small(C *v)
 {
-    const float c1 = 0.30901699437494742410f;   // cos(2 pi/5)
-    const float c2 = -0.80901699437494742410f;  // cos(4 pi/5)
-    const float s1 = 0.95105651629515357212f;   // sin(2 pi/5)
-    const float s2 = 0.58778525229247312917f;   // sin(4 pi/5)
-    float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-    float2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
-    float2 a1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
-    float2 a2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
-    float2 b1 = make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
-    float2 b2 = make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
-    float2 ib1 = mul_mi<INV>(b1), ib2 = mul_mi<INV>(b2);  // -+ i b
-    v[0] = cadd(v[0], cadd(t1, t2));
-    v[1] = cadd(a1, ib1);
-    v[4] = csub(a1, ib1);
-    v[2] = cadd(a2, ib2);
-    v[3] = csub(a2, ib2);
-}
-template <>
-__device__ __forceinline__ void dft_small<5, false>(float2 *v)
-{
-    dft5<false>(v);
-}
-template <>
-__device__ __forceinline__ void dft_small<5, true>(float2 *v)
-{
-    dft5<true>(v);
+    if constexpr (R == 2) dft2<C, INV>(v);
+    else if constexpr (R == 4) dft4<C, INV>(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8<C, INV>(v);
+    else if constexpr (R == 3) dft3<C, INV>(v);
+    else dft5<C, INV>(v);
 }
 
 // ---------------------------------------------------------------------------
@@ -161,10 +165,10 @@ __device__ __forceinline__ void dft_small<5, true>(float2 *v)
 // element (n, c) of line c sits at n*TW + c (CFAST: the columns are the
 // coalesced direction) or at c*LP + n (rows contiguous).
 // ---------------------------------------------------------------------------
-template <int R, bool INV, bool CFAST>
-__device__ __forceinline__ void stockham_pass(const float2 *__restrict__ src, float2 *__restrict__ dst,
-                                              int L, int TW, int logTW, int LP, int Ns,
-                                              const float2 *__restrict__ tw, int tid, int nthr)
+template <int R, class C, bool INV, bool CFAST>
+__device__ __forceinline__ void stockham_pass(const C *__restrict__ src, C *__restrict__ dst, int L,
+                                              int TW, int logTW, int LP, int Ns,
+                                              const C *__restrict__ tw, int tid, int nthr)
 {
     const int LR = L / R;
     const int step = L / (Ns * R);
@@ -179,7 +183,7 @@ __device__ __forceinline__ void stockham_pass(const float2 *__restrict__ src, fl
             c = b / LR;
         }
         const int jm = j % Ns;
-        float2 v[R];
+        C v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int n = j + r * LR;
@@ -188,11 +192,11 @@ __device__ __forceinline__ void stockham_pass(const float2 *__restrict__ src, fl
         if (Ns > 1) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = tw[jm * r * step];
-                v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+                const C w = tw[jm * r * step];
+                v[r] = INV ? mulc(v[r], w) : mul(v[r], w);
             }
         }
-        dft_small<R, INV>(v);
+        dft_small<R, C, INV>(v);
         const int idxD = (j - jm) * R + jm;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -205,24 +209,24 @@ __device__ __forceinline__ void stockham_pass(const float2 *__restrict__ src, fl
 // Full line FFT of a tile; the data start in A, B is scratch.  Returns the
 // buffer holding the result (A for an even pass count, B for an odd one).
 // Every thread of the block must call it; it ends with a barrier.
-template <bool INV, bool CFAST>
-__device__ float2 *lds_fft(float2 *A, float2 *B, int TW, int logTW, int LP, const RadixPlan &rp,
-                           const float2 *__restrict__ tw, int tid, int nthr)
+template <bool INV, bool CFAST, class C>
+__device__ C *lds_fft(C *A, C *B, int TW, int logTW, int LP, const RadixPlan &rp,
+                      const C *__restrict__ tw, int tid, int nthr)
 {
-    float2 *s = A, *d = B;
+    C *s = A, *d = B;
     int Ns = 1;
     const int L = rp.L;
     for (int p = 0; p < rp.np; ++p) {
         const int R = rp.r[p];
         switch (R) {
-        case 8: stockham_pass<8, INV, CFAST>(s, d, L, TW, logTW, LP, Ns, tw, tid, nthr); break;
-        case 4: stockham_pass<4, INV, CFAST>(s, d, L, TW, logTW, LP, Ns, tw, tid, nthr); break;
-        case 2: stockham_pass<2, INV, CFAST>(s, d, L, TW, logTW, LP, Ns, tw, tid, nthr); break;
-        case 3: stockham_pass<3, INV, CFAST>(s, d, L, TW, logTW, LP, Ns, tw, tid, nthr); break;
-        default: stockham_pass<5, INV, CFAST>(s, d, L, TW, logTW, LP, Ns, tw, tid, nthr); break;
+        case 8: stockham_pass<8, C, INV, CFAST>(s, d, L, TW, logTW, LP, Ns, tw, tid, nthr); break;
+        case 4: stockham_pass<4, C, INV, CFAST>(s, d, L, TW, logTW, LP, Ns, tw, tid, nthr); break;
+        case 2: stockham_pass<2, C, INV, CFAST>(s, d, L, TW, logTW, LP, Ns, tw, tid, nthr); break;
+        case 3: stockham_pass<3, C, INV, CFAST>(s, d, L, TW, logTW, LP, Ns, tw, tid, nthr); break;
+        default: stockham_pass<5, C, INV, CFAST>(s, d, L, TW, logTW, LP, Ns, tw, tid, nthr); break;
         }
         __syncthreads();
-        float2 *t = s;
+        C *t = s;
         s = d;
         d = t;
         Ns *= R;
@@ -230,44 +234,54 @@ __device__ float2 *lds_fft(float2 *A, float2 *B, int TW, int logTW, int LP, cons
     return s;
 }
 
+// first buffer to load into so that a forward transform ends in `home`
+template <class C>
+__device__ __forceinline__ C *load_target(const RadixPlan &rp, C *home, C *other)
+{
+    return (rp.np & 1) ? other : home;
+}
+
 constexpr int kFftThreads = 256;
 
 // ---------------------------------------------------------------------------
-// x3 pass: real rows -> half spectrum (main + Nyquist plane)
+// x3 pass: real rows -> half spectrum (main + Nyquist plane), computed in R
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, float2 *__restrict__ spec,
-                                                        long spec_stride, int field0, long nrow,
-                                                        int n3, int TWR, RadixPlan rp,
-                                                        const float2 *__restrict__ tw_m3,
-                                                        const float2 *__restrict__ tw_n3)
+template <class R>
+__global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, char *__restrict__ spec,
+                                                        long slot_bytes, int slot0, long nrow, int n3,
+                                                        int TWR, RadixPlan rp,
+                                                        const typename CplxOf<R>::type *__restrict__ tw_m3,
+                                                        const typename CplxOf<R>::type *__restrict__ tw_n3)
 {
-    extern __shared__ float2 lds[];
+    using C = typename CplxOf<R>::type;
+    extern __shared__ char lds_raw[];
+    C *lds = reinterpret_cast<C *>(lds_raw);
     const int m3 = n3 >> 1, LP = m3 + 1;
-    float2 *A = lds, *B = lds + TWR * LP;
+    C *A = lds, *B = lds + TWR * LP;
     const int f = blockIdx.y;
     const float *__restrict__ src = in.p[f];
     const long row0 = (long)blockIdx.x * TWR;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    float *Af = reinterpret_cast<float *>(A);
+    R *Af = reinterpret_cast<R *>(A);
     for (int idx = tid; idx < TWR * n3; idx += nthr) {
         const int c = idx / n3, x = idx - c * n3;
         const long row = row0 + c;
-        Af[(c * LP + (x >> 1)) * 2 + (x & 1)] = row < nrow ? src[row * n3 + x] : 0.f;
+        Af[(c * LP + (x >> 1)) * 2 + (x & 1)] = row < nrow ? (R)src[row * n3 + x] : R(0);
     }
     __syncthreads();
-    const float2 *Z = lds_fft<false, false>(A, B, TWR, 0, LP, rp, tw_m3, tid, nthr);
-    float2 *outm = spec + (long)(field0 + f) * spec_stride;
-    float2 *outq = outm + nrow * m3;
+    const C *Z = lds_fft<false, false, C>(A, B, TWR, 0, LP, rp, tw_m3, tid, nthr);
+    C *outm = reinterpret_cast<C *>(spec + (long)(slot0 + f) * slot_bytes);
+    C *outq = outm + nrow * m3;
     for (int idx = tid; idx < TWR * (m3 + 1); idx += nthr) {
         const int c = idx / (m3 + 1), k = idx - c * (m3 + 1);
         const long row = row0 + c;
         if (row >= nrow) continue;
-        const float2 zk = Z[c * LP + (k == m3 ? 0 : k)];
-        const float2 zc = cconj(Z[c * LP + (k == 0 ? 0 : m3 - k)]);
-        const float2 E = cscale(cadd(zk, zc), 0.5f);
-        const float2 D = cscale(csub(zk, zc), 0.5f);
-        const float2 O = make_float2(D.y, -D.x);  // D / i
-        const float2 X = cadd(E, cmul(tw_n3[k], O));
+        const C zk = Z[c * LP + (k == m3 ? 0 : k)];
+        const C zc = conj_(Z[c * LP + (k == 0 ? 0 : m3 - k)]);
+        const C E = scl(add(zk, zc), R(0.5));
+        const C D = scl(sub(zk, zc), R(0.5));
+        const C O = mk<C>(D.y, -D.x);  // D / i
+        const C X = add(E, mul(tw_n3[k], O));
         if (k < m3)
             outm[row * m3 + k] = X;
         else
@@ -276,22 +290,22 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, float2 *__res
 }
 
 // ---------------------------------------------------------------------------
-// x3 pass: half spectrum -> real rows, times scale
+// x3 pass: half spectrum (FP32) -> real rows, times scale
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const float2 *__restrict__ spec,
-                                                        long spec_stride, int field0, RealOut out,
-                                                        long nrow, int n3, int TWR, RadixPlan rp,
+__global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const char *__restrict__ spec, long slot_bytes,
+                                                        int slot0, RealOut out, long nrow, int n3,
+                                                        int TWR, RadixPlan rp,
                                                         const float2 *__restrict__ tw_m3,
-                                                        const float2 *__restrict__ tw_n3,
-                                                        float scale)
+                                                        const float2 *__restrict__ tw_n3, float scale)
 {
-    extern __shared__ float2 lds[];
+    extern __shared__ char lds_raw[];
+    float2 *lds = reinterpret_cast<float2 *>(lds_raw);
     const int m3 = n3 >> 1, LP = m3 + 1;
     float2 *A = lds, *B = lds + TWR * LP;
     const int f = blockIdx.y;
     const long row0 = (long)blockIdx.x * TWR;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const float2 *inm = spec + (long)(field0 + f) * spec_stride;
+    const float2 *inm = reinterpret_cast<const float2 *>(spec + (long)(slot0 + f) * slot_bytes);
     const float2 *inq = inm + nrow * m3;
     for (int idx = tid; idx < TWR * (m3 + 1); idx += nthr) {
         const int c = idx / (m3 + 1), k = idx - c * (m3 + 1);
@@ -304,13 +318,13 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const float2 *__restrict
     for (int idx = tid; idx < TWR * m3; idx += nthr) {
         const int c = idx / m3, k = idx - c * m3;
         const float2 Xk = B[c * LP + k];
-        const float2 Xc = cconj(B[c * LP + m3 - k]);
-        const float2 E = cadd(Xk, Xc);
-        const float2 O = cmulc(csub(Xk, Xc), tw_n3[k]);  // * exp(+2 pi i k / n3)
-        A[c * LP + k] = cadd(E, cmuli(O));
+        const float2 Xc = conj_(B[c * LP + m3 - k]);
+        const float2 E = add(Xk, Xc);
+        const float2 O = mulc(sub(Xk, Xc), tw_n3[k]);  // * exp(+2 pi i k / n3)
+        A[c * LP + k] = add(E, muli(O));
     }
     __syncthreads();
-    const float2 *z = lds_fft<true, false>(A, B, TWR, 0, LP, rp, tw_m3, tid, nthr);
+    const float2 *z = lds_fft<true, false, float2>(A, B, TWR, 0, LP, rp, tw_m3, tid, nthr);
     float *__restrict__ dst = out.p[f];
     for (int idx = tid; idx < TWR * m3; idx += nthr) {
         const int c = idx / m3, n = idx - c * m3;
@@ -325,235 +339,342 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const float2 *__restrict
 // Column pass (x2 or x1) over tiles of TW adjacent columns
 // ---------------------------------------------------------------------------
 struct ColDesc {
-    long base_off;  // offset of the sub-array (main: 0, Nyquist plane: nrow*m3)
+    long base_off;  // offset of the sub-array (main: 0, Nyquist plane: nrow*m3), in elements
     long ostride;   // stride between outer indices (blockIdx.y)
     long nstride;   // stride along the transformed line
     long cstride;   // stride between columns
     int ncols;      // columns per outer index
 };
 
-template <bool INV>
-__global__ __launch_bounds__(kFftThreads) void k_fft_cols(float2 *__restrict__ data, long fstride,
-                                                          int field0, ColDesc d, int TW, int logTW,
-                                                          RadixPlan rp,
-                                                          const float2 *__restrict__ tw)
+template <class C>
+__device__ __forceinline__ void tile_load(C *dst, const C *__restrict__ src, const ColDesc &d, int L,
+                                          int TW, int logTW, int col0, int tid, int nthr)
 {
-    extern __shared__ float2 lds[];
-    const int L = rp.L;
-    float2 *A = lds, *B = lds + L * TW;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    float2 *base = data + (long)(field0 + blockIdx.z) * fstride + d.base_off +
-                   (long)blockIdx.y * d.ostride;
-    const int col0 = blockIdx.x * TW;
     for (int idx = tid; idx < L * TW; idx += nthr) {
         const int n = idx >> logTW, c = idx & (TW - 1);
         const int col = col0 + c;
-        A[idx] = col < d.ncols ? base[n * d.nstride + col * d.cstride] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    const float2 *res = lds_fft<INV, true>(A, B, TW, logTW, 0, rp, tw, tid, nthr);
-    for (int idx = tid; idx < L * TW; idx += nthr) {
-        const int n = idx >> logTW, c = idx & (TW - 1);
-        const int col = col0 + c;
-        if (col < d.ncols) base[n * d.nstride + col * d.cstride] = res[idx];
+        dst[idx] = col < d.ncols ? src[n * d.nstride + col * d.cstride] : mk<C>(0, 0);
     }
 }
 
+template <class C>
+__device__ __forceinline__ void tile_store(C *__restrict__ dst, const C *src, const ColDesc &d, int L,
+                                           int TW, int logTW, int col0, int tid, int nthr)
+{
+    for (int idx = tid; idx < L * TW; idx += nthr) {
+        const int n = idx >> logTW, c = idx & (TW - 1);
+        const int col = col0 + c;
+        if (col < d.ncols) dst[n * d.nstride + col * d.cstride] = src[idx];
+    }
+}
+
+template <bool INV, class R>
+__global__ __launch_bounds__(kFftThreads) void k_fft_cols(char *__restrict__ spec, long slot_bytes,
+                                                          int slot0, ColDesc d, int TW, int logTW,
+                                                          RadixPlan rp,
+                                                          const typename CplxOf<R>::type *__restrict__ tw)
+{
+    using C = typename CplxOf<R>::type;
+    extern __shared__ char lds_raw[];
+    C *lds = reinterpret_cast<C *>(lds_raw);
+    const int L = rp.L;
+    C *A = lds, *B = lds + L * TW;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    C *base = reinterpret_cast<C *>(spec + (long)(slot0 + blockIdx.z) * slot_bytes) + d.base_off +
+              (long)blockIdx.y * d.ostride;
+    const int col0 = blockIdx.x * TW;
+    tile_load(A, base, d, L, TW, logTW, col0, tid, nthr);
+    __syncthreads();
+    const C *res = lds_fft<INV, true, C>(A, B, TW, logTW, 0, rp, tw, tid, nthr);
+    tile_store(base, res, d, L, TW, logTW, col0, tid, nthr);
+}
+
 // ---------------------------------------------------------------------------
-// Spectral symbols.  l1, l2, l3: indices of the spectral point (k3 index
-// l3 in [0, n3/2]).  scale = 1/N folds the inverse normalisation in.
+// Spectral symbols.  (l1, l2, l3) index a spectral point, l3 in [0, n3/2].
 // ---------------------------------------------------------------------------
 struct SymCtx {
     int n1, n2, n3;
-    float scale, beta;
+    double scale, beta;  // scale = 1/N folds the inverse normalisation in
     int reg, leray;
 };
 
-__device__ __forceinline__ float wn_full(int l, int n) { return (float)(l <= (n >> 1) ? l : l - n); }
-__device__ __forceinline__ float wn_odd(int l, int n)
+__device__ __forceinline__ double wn_full(int l, int n) { return (double)(l <= (n >> 1) ? l : l - n); }
+__device__ __forceinline__ double wn_odd(int l, int n)
 {
-    return (2 * l == n) ? 0.f : (float)(l <= (n >> 1) ? l : l - n);
+    return (2 * l == n) ? 0.0 : (double)(l <= (n >> 1) ? l : l - n);
 }
-
-__device__ __forceinline__ float reg_symbol(const SymCtx &s, int l1, int l2, int l3)
+__device__ __forceinline__ double reg_symbol(const SymCtx &s, int l1, int l2, int l3)
 {
-    const float k1 = wn_full(l1, s.n1), k2 = wn_full(l2, s.n2), k3 = wn_full(l3, s.n3);
-    const float kk = k1 * k1 + k2 * k2 + k3 * k3;
+    const double k1 = wn_full(l1, s.n1), k2 = wn_full(l2, s.n2), k3 = wn_full(l3, s.n3);
+    const double kk = k1 * k1 + k2 * k2 + k3 * k3;
     return s.reg == 2 ? kk * kk : kk;
 }
 
-__device__ __forceinline__ void leray_apply(const SymCtx &s, int l1, int l2, int l3, float2 *w)
+struct ColCtx {  // how a tile position maps to (l2, l3)
+    int nyq;     // 0: main array (columns are k3, blockIdx.y is k2); 1: Nyquist plane
+    __device__ __forceinline__ void l23(const SymCtx &s, int col, int &l2, int &l3) const
+    {
+        l2 = nyq ? col : (int)blockIdx.y;
+        l3 = nyq ? (s.n3 >> 1) : col;
+    }
+};
+
+// per-field real symbol, forward and inverse in R
+enum { SYM_REG = 0, SYM_INVREG = 1, SYM_IDENT = 2 };
+
+template <class R, int SYM>
+__global__ __launch_bounds__(kFftThreads) void k_x1_scalar(char *__restrict__ spec, long slot_bytes,
+                                                           int in0, int out0, ColDesc d, int nyq,
+                                                           int TW, int logTW, RadixPlan rp,
+                                                           const typename CplxOf<R>::type *__restrict__ tw,
+                                                           SymCtx sc)
 {
-    const float k[3] = {wn_odd(l1, s.n1), wn_odd(l2, s.n2), wn_odd(l3, s.n3)};
-    const float kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-    if (kk > 0.f) {
-        const float ikk = 1.f / kk;
-        const float2 kw = make_float2((k[0] * w[0].x + k[1] * w[1].x + k[2] * w[2].x) * ikk,
-                                      (k[0] * w[0].y + k[1] * w[1].y + k[2] * w[2].y) * ikk);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) w[c] = make_float2(w[c].x - k[c] * kw.x, w[c].y - k[c] * kw.y);
-    }
-}
-
-struct OpGrad {
-    static constexpr int NIN = 1, NOUT = 3;
-    __device__ void operator()(const SymCtx &s, int l1, int l2, int l3, const float2 *in,
-                               float2 *out) const
-    {
-        const float k[3] = {wn_odd(l1, s.n1), wn_odd(l2, s.n2), wn_odd(l3, s.n3)};
-        const float2 f = cscale(in[0], s.scale);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) out[d] = cmuli(cscale(f, k[d]));
-    }
-};
-
-struct OpDiv {
-    static constexpr int NIN = 3, NOUT = 1;
-    __device__ void operator()(const SymCtx &s, int l1, int l2, int l3, const float2 *in,
-                               float2 *out) const
-    {
-        const float k[3] = {wn_odd(l1, s.n1), wn_odd(l2, s.n2), wn_odd(l3, s.n3)};
-        float2 acc = make_float2(k[0] * in[0].x + k[1] * in[1].x + k[2] * in[2].x,
-                                 k[0] * in[0].y + k[1] * in[1].y + k[2] * in[2].y);
-        out[0] = cmuli(cscale(acc, s.scale));
-    }
-};
-
-struct OpReg {
-    static constexpr int NIN = 3, NOUT = 3;
-    __device__ void operator()(const SymCtx &s, int l1, int l2, int l3, const float2 *in,
-                               float2 *out) const
-    {
-        const float a = reg_symbol(s, l1, l2, l3) * s.scale;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] = cscale(in[c], a);
-    }
-};
-
-struct OpInvReg {
-    static constexpr int NIN = 3, NOUT = 3;
-    __device__ void operator()(const SymCtx &s, int l1, int l2, int l3, const float2 *in,
-                               float2 *out) const
-    {
-        const float a = reg_symbol(s, l1, l2, l3);
-        const float f = (a == 0.f ? 1.f / s.beta : 1.f / (s.beta * a)) * s.scale;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] = cscale(in[c], f);
-    }
-};
-
-struct OpLeray {
-    static constexpr int NIN = 3, NOUT = 3;
-    __device__ void operator()(const SymCtx &s, int l1, int l2, int l3, const float2 *in,
-                               float2 *out) const
-    {
-        float2 w[3] = {in[0], in[1], in[2]};
-        leray_apply(s, l1, l2, l3, w);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] = cscale(w[c], s.scale);
-    }
-};
-
-// beta A w + K b (K = Leray if s.leray): inputs w0..w2, b0..b2
-struct OpAssemble {
-    static constexpr int NIN = 6, NOUT = 3;
-    __device__ void operator()(const SymCtx &s, int l1, int l2, int l3, const float2 *in,
-                               float2 *out) const
-    {
-        const float a = s.beta * reg_symbol(s, l1, l2, l3);
-        float2 b[3] = {in[3], in[4], in[5]};
-        if (s.leray) leray_apply(s, l1, l2, l3, b);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            out[c] = make_float2((a * in[c].x + b[c].x) * s.scale, (a * in[c].y + b[c].y) * s.scale);
-    }
-};
-
-struct OpIdent {
-    static constexpr int NIN = 1, NOUT = 1;
-    __device__ void operator()(const SymCtx &s, int, int, int, const float2 *in, float2 *out) const
-    {
-        out[0] = cscale(in[0], s.scale);
-    }
-};
-
-// x1 forward -> symbol -> x1 inverse.  nyq = 0: main array, columns are k3
-// and blockIdx.y is k2; nyq = 1: Nyquist plane, columns are k2, k3 = n3/2.
-template <class Op>
-__global__ __launch_bounds__(kFftThreads) void k_x1_symbol(const float2 *__restrict__ in, int in_first,
-                                                           float2 *__restrict__ out, int out_first,
-                                                           long fstride, ColDesc d, int nyq, int TW,
-                                                           int logTW, RadixPlan rp,
-                                                           const float2 *__restrict__ tw, SymCtx sc,
-                                                           Op op)
-{
-    constexpr int NF = Op::NIN > Op::NOUT ? Op::NIN : Op::NOUT;
-    extern __shared__ float2 lds[];
-    const int L = rp.L;
-    const int tile = L * TW;
-    float2 *S = lds + NF * tile;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int col0 = blockIdx.x * TW;
+    using C = typename CplxOf<R>::type;
+    extern __shared__ char lds_raw[];
+    C *lds = reinterpret_cast<C *>(lds_raw);
+    const int L = rp.L, tile = L * TW;
+    C *A = lds, *B = lds + tile;
+    const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
     const long off = d.base_off + (long)blockIdx.y * d.ostride;
-    const bool odd = rp.np & 1;
-    for (int f = 0; f < Op::NIN; ++f) {
-        const float2 *src = in + (long)(in_first + blockIdx.z * Op::NIN + f) * fstride + off;
-        float2 *buf = lds + f * tile;
-        float2 *first = odd ? S : buf;
-        for (int idx = tid; idx < tile; idx += nthr) {
-            const int n = idx >> logTW, c = idx & (TW - 1);
-            const int col = col0 + c;
-            first[idx] = col < d.ncols ? src[n * d.nstride + col * d.cstride] : make_float2(0.f, 0.f);
+    const C *src = reinterpret_cast<const C *>(spec + (long)(in0 + blockIdx.z) * slot_bytes) + off;
+    float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + blockIdx.z) * slot_bytes) + off;
+    tile_load(load_target(rp, A, B), src, d, L, TW, logTW, col0, tid, nthr);
+    __syncthreads();
+    lds_fft<false, true, C>(load_target(rp, A, B), load_target(rp, B, A), TW, logTW, 0, rp, tw, tid, nthr);
+    const ColCtx cc{nyq};
+    for (int idx = tid; idx < tile; idx += nthr) {
+        const int n = idx >> logTW, c = idx & (TW - 1);
+        int l2, l3;
+        cc.l23(sc, col0 + c, l2, l3);
+        double f = sc.scale;
+        if (SYM == SYM_REG) {
+            f *= reg_symbol(sc, n, l2, l3);
+        } else if (SYM == SYM_INVREG) {
+            const double a = reg_symbol(sc, n, l2, l3);
+            f *= (a == 0.0) ? 1.0 / sc.beta : 1.0 / (sc.beta * a);
         }
-        __syncthreads();
-        lds_fft<false, true>(first, odd ? buf : S, TW, logTW, 0, rp, tw, tid, nthr);
+        A[idx] = scl(A[idx], (R)f);
     }
+    __syncthreads();
+    const C *res = lds_fft<true, true, C>(A, B, TW, logTW, 0, rp, tw, tid, nthr);
     for (int idx = tid; idx < tile; idx += nthr) {
         const int n = idx >> logTW, c = idx & (TW - 1);
         const int col = col0 + c;
-        if (col >= d.ncols) continue;
-        const int l2 = nyq ? col : (int)blockIdx.y;
-        const int l3 = nyq ? (sc.n3 >> 1) : col;
-        float2 vin[Op::NIN], vout[Op::NOUT];
+        if (col < d.ncols) dst[n * d.nstride + col * d.cstride] = to_f2(res[idx]);
+    }
+}
+
+// grad: one FP64 input field -> three FP32 output fields
+__global__ __launch_bounds__(kFftThreads) void k_x1_grad(char *__restrict__ spec, long slot_bytes, int in0,
+                                                         int out0, ColDesc d, int nyq, int TW, int logTW,
+                                                         RadixPlan rp, const double2 *__restrict__ twd,
+                                                         const float2 *__restrict__ twf, SymCtx sc)
+{
+    extern __shared__ char lds_raw[];
+    const int L = rp.L, tile = L * TW;
+    double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile;
+    float2 *O = reinterpret_cast<float2 *>(WB + tile);  // three float2 tiles
+    float2 *S = reinterpret_cast<float2 *>(WA);         // float scratch once WA/WB are free
+    const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
+    const long off = d.base_off + (long)blockIdx.y * d.ostride;
+    const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(in0 + blockIdx.z) * slot_bytes) + off;
+    tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
+    __syncthreads();
+    lds_fft<false, true, double2>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
+    const ColCtx cc{nyq};
+    for (int idx = tid; idx < tile; idx += nthr) {
+        const int n = idx >> logTW, c = idx & (TW - 1);
+        int l2, l3;
+        cc.l23(sc, col0 + c, l2, l3);
+        const double k[3] = {wn_odd(n, sc.n1), wn_odd(l2, sc.n2), wn_odd(l3, sc.n3)};
+        const double2 f = scl(WA[idx], sc.scale);
 #pragma unroll
-        for (int f = 0; f < Op::NIN; ++f) vin[f] = lds[f * tile + idx];
-        op(sc, n, l2, l3, vin, vout);
-#pragma unroll
-        for (int o = 0; o < Op::NOUT; ++o) lds[o * tile + idx] = vout[o];
+        for (int q = 0; q < 3; ++q) O[q * tile + idx] = to_f2(muli(scl(f, k[q])));
     }
     __syncthreads();
-    for (int o = 0; o < Op::NOUT; ++o) {
-        float2 *buf = lds + o * tile;
-        const float2 *res = lds_fft<true, true>(buf, S, TW, logTW, 0, rp, tw, tid, nthr);
-        float2 *dst = out + (long)(out_first + blockIdx.z * Op::NOUT + o) * fstride + off;
-        for (int idx = tid; idx < tile; idx += nthr) {
-            const int n = idx >> logTW, c = idx & (TW - 1);
-            const int col = col0 + c;
-            if (col < d.ncols) dst[n * d.nstride + col * d.cstride] = res[idx];
-        }
+    for (int q = 0; q < 3; ++q) {
+        const float2 *res = lds_fft<true, true, float2>(O + q * tile, S, TW, logTW, 0, rp, twf, tid, nthr);
+        float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + 3 * blockIdx.z + q) * slot_bytes) + off;
+        tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
     }
 }
 
-// standard half-spectrum layout <-> internal layout
-__global__ void k_pack_standard(const float2 *__restrict__ spec, float2 *__restrict__ dst, long nrow,
-                                int m3)
+// div: three FP64 input fields -> one FP32 output field (FP64 accumulation)
+__global__ __launch_bounds__(kFftThreads) void k_x1_div(char *__restrict__ spec, long slot_bytes, int in0,
+                                                        int out0, ColDesc d, int nyq, int TW, int logTW,
+                                                        RadixPlan rp, const double2 *__restrict__ twd,
+                                                        const float2 *__restrict__ twf, SymCtx sc)
+{
+    extern __shared__ char lds_raw[];
+    const int L = rp.L, tile = L * TW;
+    double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile, *ACC = WB + tile;
+    const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
+    const long off = d.base_off + (long)blockIdx.y * d.ostride;
+    const ColCtx cc{nyq};
+    for (int q = 0; q < 3; ++q) {
+        const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(in0 + 3 * blockIdx.z + q) * slot_bytes) + off;
+        tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
+        __syncthreads();
+        lds_fft<false, true, double2>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
+        for (int idx = tid; idx < tile; idx += nthr) {
+            const int n = idx >> logTW, c = idx & (TW - 1);
+            int l2, l3;
+            cc.l23(sc, col0 + c, l2, l3);
+            const double kq = q == 0 ? wn_odd(n, sc.n1) : (q == 1 ? wn_odd(l2, sc.n2) : wn_odd(l3, sc.n3));
+            const double2 t = muli(scl(WA[idx], kq * sc.scale));
+            ACC[idx] = q == 0 ? t : add(ACC[idx], t);
+        }
+        __syncthreads();
+    }
+    float2 *FA = reinterpret_cast<float2 *>(WA), *FB = FA + tile;
+    for (int idx = tid; idx < tile; idx += nthr) FA[idx] = to_f2(ACC[idx]);
+    __syncthreads();
+    const float2 *res = lds_fft<true, true, float2>(FA, FB, TW, logTW, 0, rp, twf, tid, nthr);
+    float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + blockIdx.z) * slot_bytes) + off;
+    tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
+}
+
+__device__ __forceinline__ void leray_coef(const SymCtx &sc, int n, int l2, int l3, double k[3], double &ikk)
+{
+    k[0] = wn_odd(n, sc.n1);
+    k[1] = wn_odd(l2, sc.n2);
+    k[2] = wn_odd(l3, sc.n3);
+    const double kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    ikk = kk > 0.0 ? 1.0 / kk : 0.0;
+}
+
+// Leray projection: three FP32 fields in and out
+__global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spec, long slot_bytes, int in0,
+                                                          int out0, ColDesc d, int nyq, int TW, int logTW,
+                                                          RadixPlan rp, const float2 *__restrict__ twf,
+                                                          SymCtx sc)
+{
+    extern __shared__ char lds_raw[];
+    const int L = rp.L, tile = L * TW;
+    float2 *T = reinterpret_cast<float2 *>(lds_raw);  // three field tiles, then scratch
+    float2 *S = T + 3 * tile;
+    const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
+    const long off = d.base_off + (long)blockIdx.y * d.ostride;
+    for (int q = 0; q < 3; ++q) {
+        const float2 *src = reinterpret_cast<const float2 *>(spec + (long)(in0 + 3 * blockIdx.z + q) * slot_bytes) + off;
+        float2 *home = T + q * tile;
+        tile_load(load_target(rp, home, S), src, d, L, TW, logTW, col0, tid, nthr);
+        __syncthreads();
+        lds_fft<false, true, float2>(load_target(rp, home, S), load_target(rp, S, home), TW, logTW, 0, rp, twf, tid, nthr);
+    }
+    const ColCtx cc{nyq};
+    for (int idx = tid; idx < tile; idx += nthr) {
+        const int n = idx >> logTW, c = idx & (TW - 1);
+        int l2, l3;
+        cc.l23(sc, col0 + c, l2, l3);
+        double k[3], ikk;
+        leray_coef(sc, n, l2, l3, k, ikk);
+        float2 w[3] = {T[idx], T[tile + idx], T[2 * tile + idx]};
+        const double sx = (k[0] * w[0].x + k[1] * w[1].x + k[2] * w[2].x) * ikk;
+        const double sy = (k[0] * w[0].y + k[1] * w[1].y + k[2] * w[2].y) * ikk;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            T[q * tile + idx] = make_float2((float)((w[q].x - k[q] * sx) * sc.scale),
+                                            (float)((w[q].y - k[q] * sy) * sc.scale));
+    }
+    __syncthreads();
+    for (int q = 0; q < 3; ++q) {
+        const float2 *res = lds_fft<true, true, float2>(T + q * tile, S, TW, logTW, 0, rp, twf, tid, nthr);
+        float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + 3 * blockIdx.z + q) * slot_bytes) + off;
+        tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
+        __syncthreads();
+    }
+}
+
+// Assembly beta A w + K b: w three FP64 fields, b three FP32 fields, out three
+// FP32 fields.  K = Leray if sc.leray.  The b components stream through one
+// working tile; the Leray correction accumulates s = k.b / |k|^2.
+__global__ __launch_bounds__(kFftThreads) void k_x1_assemble(char *__restrict__ spec, long slot_bytes,
+                                                             int w0, int b0, int out0, ColDesc d, int nyq,
+                                                             int TW, int logTW, RadixPlan rp,
+                                                             const double2 *__restrict__ twd,
+                                                             const float2 *__restrict__ twf, SymCtx sc)
+{
+    extern __shared__ char lds_raw[];
+    const int L = rp.L, tile = L * TW;
+    double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile;
+    float2 *FA = reinterpret_cast<float2 *>(WA), *FB = FA + tile;  // float view of the working pair
+    float2 *O = reinterpret_cast<float2 *>(WB + tile);             // three output tiles
+    float2 *Sd = O + 3 * tile;                                     // Leray accumulator
+    const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
+    const long off = d.base_off + (long)blockIdx.y * d.ostride;
+    const ColCtx cc{nyq};
+    for (int q = 0; q < 3; ++q) {
+        const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(w0 + q) * slot_bytes) + off;
+        tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
+        __syncthreads();
+        lds_fft<false, true, double2>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
+        for (int idx = tid; idx < tile; idx += nthr) {
+            const int n = idx >> logTW, c = idx & (TW - 1);
+            int l2, l3;
+            cc.l23(sc, col0 + c, l2, l3);
+            O[q * tile + idx] = to_f2(scl(WA[idx], sc.beta * reg_symbol(sc, n, l2, l3) * sc.scale));
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < 3; ++q) {
+        const float2 *src = reinterpret_cast<const float2 *>(spec + (long)(b0 + q) * slot_bytes) + off;
+        tile_load(load_target(rp, FA, FB), src, d, L, TW, logTW, col0, tid, nthr);
+        __syncthreads();
+        lds_fft<false, true, float2>(load_target(rp, FA, FB), load_target(rp, FB, FA), TW, logTW, 0, rp, twf, tid, nthr);
+        for (int idx = tid; idx < tile; idx += nthr) {
+            const float2 bq = FA[idx];
+            const float s = (float)sc.scale;
+            O[q * tile + idx] = add(O[q * tile + idx], scl(bq, s));
+            if (sc.leray) {
+                const int n = idx >> logTW, c = idx & (TW - 1);
+                int l2, l3;
+                cc.l23(sc, col0 + c, l2, l3);
+                double k[3], ikk;
+                leray_coef(sc, n, l2, l3, k, ikk);
+                const float2 t = scl(bq, (float)(k[q] * ikk * sc.scale));
+                Sd[idx] = q == 0 ? t : add(Sd[idx], t);
+            }
+        }
+        __syncthreads();
+    }
+    if (sc.leray) {
+        for (int idx = tid; idx < tile; idx += nthr) {
+            const int n = idx >> logTW, c = idx & (TW - 1);
+            int l2, l3;
+            cc.l23(sc, col0 + c, l2, l3);
+            double k[3], ikk;
+            leray_coef(sc, n, l2, l3, k, ikk);
+            const float2 s = Sd[idx];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) O[q * tile + idx] = sub(O[q * tile + idx], scl(s, (float)k[q]));
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < 3; ++q) {
+        const float2 *res = lds_fft<true, true, float2>(O + q * tile, FA, TW, logTW, 0, rp, twf, tid, nthr);
+        float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + q) * slot_bytes) + off;
+        tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
+        __syncthreads();
+    }
+}
+
+// standard half-spectrum layout <-> internal layout (FP32 slots)
+__global__ void k_pack_standard(const float2 *__restrict__ spec, float2 *__restrict__ dst, long nrow, int m3)
 {
     const long total = nrow * (m3 + 1);
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (long)gridDim.x * blockDim.x) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
         const long row = i / (m3 + 1);
         const int k = (int)(i - row * (m3 + 1));
         dst[i] = k < m3 ? spec[row * m3 + k] : spec[nrow * m3 + row];
     }
 }
 
-__global__ void k_unpack_standard(const float2 *__restrict__ srcp, float2 *__restrict__ spec,
-                                  long nrow, int m3)
+__global__ void k_unpack_standard(const float2 *__restrict__ srcp, float2 *__restrict__ spec, long nrow, int m3)
 {
     const long total = nrow * (m3 + 1);
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (long)gridDim.x * blockDim.x) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
         const long row = i / (m3 + 1);
         const int k = (int)(i - row * (m3 + 1));
         if (k < m3)
@@ -585,16 +706,18 @@ RadixPlan make_radix_plan(int L)
     return rp;
 }
 
-static float2 *upload_twiddles(int L, int count)
+template <class C>
+static C *upload_twiddles(int L)
 {
-    std::vector<float2> h(count);
-    for (int m = 0; m < count; ++m) {
+    std::vector<C> h(L);
+    for (int m = 0; m < L; ++m) {
         const double a = -2.0 * M_PI * (double)m / (double)L;
-        h[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+        h[m].x = (decltype(h[m].x))std::cos(a);
+        h[m].y = (decltype(h[m].y))std::sin(a);
     }
-    float2 *d = nullptr;
-    check_hip(hipMalloc(&d, sizeof(float2) * count), "hipMalloc twiddles");
-    check_hip(hipMemcpy(d, h.data(), sizeof(float2) * count, hipMemcpyHostToDevice), "twiddle upload");
+    C *d = nullptr;
+    check_hip(hipMalloc(&d, sizeof(C) * L), "hipMalloc twiddles");
+    check_hip(hipMemcpy(d, h.data(), sizeof(C) * L, hipMemcpyHostToDevice), "twiddle upload");
     return d;
 }
 
@@ -609,47 +732,32 @@ void fft_init(lddmm_plan *P)
     F.spec_stride = F.nrow * (F.m3 + 1);
     F.rp1 = make_radix_plan(F.n1);
     F.rp2 = make_radix_plan(F.n2);
-    F.rp3 = make_radix_plan(F.m3 > 1 ? F.m3 : 1);
-    F.tw1 = upload_twiddles(F.n1, F.n1);
-    F.tw2 = upload_twiddles(F.n2, F.n2);
-    F.tw3 = upload_twiddles(F.m3, F.m3);
-    F.twN3 = upload_twiddles(F.n3, F.n3);
+    F.rp3 = make_radix_plan(F.m3);
+    F.tw1 = upload_twiddles<float2>(F.n1);
+    F.tw2 = upload_twiddles<float2>(F.n2);
+    F.tw3 = upload_twiddles<float2>(F.m3);
+    F.twN3 = upload_twiddles<float2>(F.n3);
+    F.tw1d = upload_twiddles<double2>(F.n1);
+    F.tw2d = upload_twiddles<double2>(F.n2);
+    F.tw3d = upload_twiddles<double2>(F.m3);
+    F.twN3d = upload_twiddles<double2>(F.n3);
 }
 
 void fft_free(lddmm_plan *P)
 {
     FftCtx &F = P->fft;
-    for (float2 *p : {F.tw1, F.tw2, F.tw3, F.twN3})
+    for (void *p : {(void *)F.tw1, (void *)F.tw2, (void *)F.tw3, (void *)F.twN3, (void *)F.tw1d,
+                    (void *)F.tw2d, (void *)F.tw3d, (void *)F.twN3d})
         if (p) (void)hipFree(p);
     F.tw1 = F.tw2 = F.tw3 = F.twN3 = nullptr;
+    F.tw1d = F.tw2d = F.tw3d = F.twN3d = nullptr;
 }
-
-static constexpr size_t kLdsBudget = 64 * 1024;
 
 static int floor_pow2(long x)
 {
     int p = 1;
     while ((long)p * 2 <= x) p *= 2;
     return p;
-}
-
-static int rows_per_block(int m3)
-{
-    // two buffers of TWR * (m3 + 1) float2
-    long cap = (long)(kLdsBudget / (2 * sizeof(float2) * (m3 + 1)));
-    int t = floor_pow2(cap < 1 ? 1 : cap);
-    return t > 32 ? 32 : t;
-}
-
-static int col_tile(int L, int nbuf, int ncols)
-{
-    long cap = (long)(kLdsBudget / ((size_t)nbuf * sizeof(float2) * L));
-    int t = floor_pow2(cap < 1 ? 1 : cap);
-    if (t > 32) t = 32;
-    int nc = floor_pow2(ncols);
-    if (nc < ncols) nc *= 2;
-    if (t > nc) t = nc;
-    return t;
 }
 
 static int ilog2(int x)
@@ -659,86 +767,129 @@ static int ilog2(int x)
     return l;
 }
 
-void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int spec_first)
+// rows per block of the x3 passes: two buffers of TWR*(m3+1) complex values
+static int rows_per_block(int m3, size_t csize)
+{
+    long cap = (long)(kLdsBudget / (2 * csize * (m3 + 1)));
+    int t = floor_pow2(cap < 1 ? 1 : cap);
+    return t > 32 ? 32 : t;
+}
+
+// columns per tile when each column needs `bytes_per_elem` bytes of LDS per
+// line element (summed over all tiles the kernel holds)
+static int col_tile(int L, size_t bytes_per_elem, int ncols)
+{
+    long cap = (long)(kLdsBudget / (bytes_per_elem * (size_t)L));
+    int t = floor_pow2(cap < 1 ? 1 : cap);
+    if (t > 32) t = 32;
+    int nc = floor_pow2(ncols);
+    if (nc < ncols) nc *= 2;
+    if (t > nc) t = nc;
+    return t;
+}
+
+static void check_lds(size_t bytes, const char *what)
+{
+    if (bytes > kLdsBudget) fail(LDDMM_EUNSUPPORTED, std::string(what) + ": LDS tile exceeds the budget");
+}
+
+void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int slot0, bool dbl)
 {
     FftCtx &F = P->fft;
-    const int TWR = rows_per_block(F.m3);
-    const size_t lds = 2 * sizeof(float2) * TWR * (F.m3 + 1);
+    const size_t cs = dbl ? sizeof(double2) : sizeof(float2);
+    const int TWR = rows_per_block(F.m3, cs);
+    const size_t lds = 2 * cs * TWR * (F.m3 + 1);
+    check_lds(lds, "r2c_x3");
     dim3 grid((unsigned)((F.nrow + TWR - 1) / TWR), count);
     Scope s(P, K_R2C_X3);
-    hipLaunchKernelGGL(k_r2c_x3, grid, dim3(kFftThreads), lds, P->stream, in, P->spec,
-                       F.spec_stride, spec_first, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3);
+    if (dbl)
+        hipLaunchKernelGGL(k_r2c_x3<double>, grid, dim3(kFftThreads), lds, P->stream, in, P->spec,
+                           P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3d, F.twN3d);
+    else
+        hipLaunchKernelGGL(k_r2c_x3<float>, grid, dim3(kFftThreads), lds, P->stream, in, P->spec,
+                           P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3);
     check_hip(hipGetLastError(), "k_r2c_x3");
 }
 
-void c2r_fields(lddmm_plan *P, int spec_first, int count, const RealOut &out, float scale)
+void c2r_fields(lddmm_plan *P, int slot0, int count, const RealOut &out, float scale)
 {
     FftCtx &F = P->fft;
-    const int TWR = rows_per_block(F.m3);
+    const int TWR = rows_per_block(F.m3, sizeof(float2));
     const size_t lds = 2 * sizeof(float2) * TWR * (F.m3 + 1);
     dim3 grid((unsigned)((F.nrow + TWR - 1) / TWR), count);
     Scope s(P, K_C2R_X3);
-    hipLaunchKernelGGL(k_c2r_x3, grid, dim3(kFftThreads), lds, P->stream, P->spec, F.spec_stride,
-                       spec_first, out, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3, scale);
+    hipLaunchKernelGGL(k_c2r_x3, grid, dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes,
+                       slot0, out, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3, scale);
     check_hip(hipGetLastError(), "k_c2r_x3");
 }
 
 // column descriptors: main array and Nyquist plane, along x2 (axis 1) or x1 (axis 0)
-static void col_descs(const FftCtx &F, int axis, ColDesc &dm, ColDesc &dq, int &outer_m, int &outer_q)
+static void col_descs(const FftCtx &F, int axis, ColDesc dd[2], int outer[2])
 {
     if (axis == 1) {
-        dm = {0, (long)F.n2 * F.m3, F.m3, 1, F.m3};
-        outer_m = F.n1;
-        dq = {F.nrow * F.m3, 0, 1, F.n2, F.n1};
-        outer_q = 1;
+        dd[0] = {0, (long)F.n2 * F.m3, F.m3, 1, F.m3};
+        outer[0] = F.n1;
+        dd[1] = {F.nrow * F.m3, 0, 1, F.n2, F.n1};
+        outer[1] = 1;
     } else {
-        dm = {0, F.m3, (long)F.n2 * F.m3, 1, F.m3};
-        outer_m = F.n2;
-        dq = {F.nrow * F.m3, 0, F.n2, 1, F.n2};
-        outer_q = 1;
+        dd[0] = {0, F.m3, (long)F.n2 * F.m3, 1, F.m3};
+        outer[0] = F.n2;
+        dd[1] = {F.nrow * F.m3, 0, F.n2, 1, F.n2};
+        outer[1] = 1;
     }
 }
 
-static void cols_pass(lddmm_plan *P, int axis, int spec_first, int count, bool inverse)
+static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool inverse, bool dbl)
 {
     FftCtx &F = P->fft;
     const RadixPlan &rp = axis == 1 ? F.rp2 : F.rp1;
-    const float2 *tw = axis == 1 ? F.tw2 : F.tw1;
-    ColDesc dm, dq;
-    int om, oq;
-    col_descs(F, axis, dm, dq, om, oq);
+    ColDesc dd[2];
+    int outer[2];
+    col_descs(F, axis, dd, outer);
+    const size_t cs = dbl ? sizeof(double2) : sizeof(float2);
     for (int part = 0; part < 2; ++part) {
-        const ColDesc &d = part == 0 ? dm : dq;
-        const int outer = part == 0 ? om : oq;
-        const int TW = col_tile(rp.L, 2, d.ncols);
-        const size_t lds = 2 * sizeof(float2) * rp.L * TW;
-        dim3 grid((unsigned)((d.ncols + TW - 1) / TW), outer, count);
+        const ColDesc &d = dd[part];
+        const int TW = col_tile(rp.L, 2 * cs, d.ncols);
+        const size_t lds = 2 * cs * rp.L * TW;
+        check_lds(lds, "fft_cols");
+        dim3 grid((unsigned)((d.ncols + TW - 1) / TW), outer[part], count);
         Scope s(P, K_FFT_COLS);
-        if (inverse)
-            hipLaunchKernelGGL(k_fft_cols<true>, grid, dim3(kFftThreads), lds, P->stream, P->spec,
-                               F.spec_stride, spec_first, d, TW, ilog2(TW), rp, tw);
-        else
-            hipLaunchKernelGGL(k_fft_cols<false>, grid, dim3(kFftThreads), lds, P->stream, P->spec,
-                               F.spec_stride, spec_first, d, TW, ilog2(TW), rp, tw);
+        const int lt = ilog2(TW);
+        if (dbl) {
+            const double2 *tw = axis == 1 ? F.tw2d : F.tw1d;
+            if (inverse)
+                hipLaunchKernelGGL((k_fft_cols<true, double>), grid, dim3(kFftThreads), lds, P->stream,
+                                   P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+            else
+                hipLaunchKernelGGL((k_fft_cols<false, double>), grid, dim3(kFftThreads), lds, P->stream,
+                                   P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+        } else {
+            const float2 *tw = axis == 1 ? F.tw2 : F.tw1;
+            if (inverse)
+                hipLaunchKernelGGL((k_fft_cols<true, float>), grid, dim3(kFftThreads), lds, P->stream,
+                                   P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+            else
+                hipLaunchKernelGGL((k_fft_cols<false, float>), grid, dim3(kFftThreads), lds, P->stream,
+                                   P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+        }
         check_hip(hipGetLastError(), "k_fft_cols");
     }
 }
 
-void x2_pass(lddmm_plan *P, int spec_first, int count, bool inverse)
+void x2_pass(lddmm_plan *P, int slot0, int count, bool inverse, bool dbl)
 {
-    cols_pass(P, 1, spec_first, count, inverse);
+    cols_pass(P, 1, slot0, count, inverse, dbl);
 }
 
-void x1_pass(lddmm_plan *P, int spec_first, int count, bool inverse)
+void x1_pass(lddmm_plan *P, int slot0, int count, bool inverse, bool dbl)
 {
-    cols_pass(P, 0, spec_first, count, inverse);
+    cols_pass(P, 0, slot0, count, inverse, dbl);
 }
 
 int op_nin(int op)
 {
     switch (op) {
     case SOP_GRAD: return 1;
-    case SOP_DIV: return 3;
     case SOP_ASSEMBLE: return 6;
     case SOP_IDENT: return 1;
     default: return 3;
@@ -748,55 +899,103 @@ int op_nin(int op)
 int op_nout(int op)
 {
     switch (op) {
-    case SOP_GRAD: return 3;
     case SOP_DIV: return 1;
     case SOP_IDENT: return 1;
     default: return 3;
     }
 }
 
-template <class Op>
-static void launch_x1_symbol(lddmm_plan *P, int spec_in, int spec_out, int nbatch, const SymCtx &sc)
+// precision of the forward transform of input field i of op
+static bool input_is_fp64(int op, int i)
 {
-    FftCtx &F = P->fft;
-    constexpr int NF = Op::NIN > Op::NOUT ? Op::NIN : Op::NOUT;
-    ColDesc dm, dq;
-    int om, oq;
-    col_descs(F, 0, dm, dq, om, oq);
-    for (int part = 0; part < 2; ++part) {
-        const ColDesc &d = part == 0 ? dm : dq;
-        const int outer = part == 0 ? om : oq;
-        const int TW = col_tile(F.rp1.L, NF + 1, d.ncols);
-        const size_t lds = (size_t)(NF + 1) * sizeof(float2) * F.rp1.L * TW;
-        dim3 grid((unsigned)((d.ncols + TW - 1) / TW), outer, nbatch);
-        Scope s(P, K_SPECTRAL_X1);
-        hipLaunchKernelGGL(k_x1_symbol<Op>, grid, dim3(kFftThreads), lds, P->stream, P->spec,
-                           spec_in, P->spec, spec_out, F.spec_stride, d, part, TW, ilog2(TW), F.rp1,
-                           F.tw1, sc, Op{});
-        check_hip(hipGetLastError(), "k_x1_symbol");
+    switch (op) {
+    case SOP_GRAD:
+    case SOP_DIV:
+    case SOP_REG: return true;
+    case SOP_ASSEMBLE: return i < 3;
+    default: return false;
     }
 }
 
-void x1_symbol(lddmm_plan *P, int op, int spec_in, int spec_out, int nbatch, int leray)
+static SymCtx sym_ctx(lddmm_plan *P, int leray)
 {
     FftCtx &F = P->fft;
     SymCtx sc;
     sc.n1 = F.n1;
     sc.n2 = F.n2;
     sc.n3 = F.n3;
-    sc.scale = (float)(1.0 / ((double)F.n1 * F.n2 * F.n3));
-    sc.beta = (float)P->cfg.beta;
+    sc.scale = 1.0 / ((double)F.n1 * F.n2 * F.n3);
+    sc.beta = P->cfg.beta;
     sc.reg = P->cfg.reg;
     sc.leray = leray;
-    switch (op) {
-    case SOP_GRAD: launch_x1_symbol<OpGrad>(P, spec_in, spec_out, nbatch, sc); break;
-    case SOP_DIV: launch_x1_symbol<OpDiv>(P, spec_in, spec_out, nbatch, sc); break;
-    case SOP_REG: launch_x1_symbol<OpReg>(P, spec_in, spec_out, nbatch, sc); break;
-    case SOP_INVREG: launch_x1_symbol<OpInvReg>(P, spec_in, spec_out, nbatch, sc); break;
-    case SOP_LERAY: launch_x1_symbol<OpLeray>(P, spec_in, spec_out, nbatch, sc); break;
-    case SOP_ASSEMBLE: launch_x1_symbol<OpAssemble>(P, spec_in, spec_out, nbatch, sc); break;
-    case SOP_IDENT: launch_x1_symbol<OpIdent>(P, spec_in, spec_out, nbatch, sc); break;
-    default: fail(LDDMM_EINVAL, "unknown spectral operator");
+    return sc;
+}
+
+// x1 forward, symbol, x1 inverse for nbatch batches: inputs of batch b at
+// slots in0 + b*nin .. , outputs at out0 + b*nout ..
+void x1_symbol(lddmm_plan *P, int op, int in0, int out0, int nbatch, int leray)
+{
+    FftCtx &F = P->fft;
+    const RadixPlan &rp = F.rp1;
+    const int L = rp.L;
+    const SymCtx sc = sym_ctx(P, leray);
+    ColDesc dd[2];
+    int outer[2];
+    col_descs(F, 0, dd, outer);
+    for (int part = 0; part < 2; ++part) {
+        const ColDesc &d = dd[part];
+        size_t per;  // LDS bytes per tile element
+        switch (op) {
+        case SOP_GRAD: per = 2 * 16 + 3 * 8; break;
+        case SOP_DIV: per = 3 * 16; break;
+        case SOP_LERAY: per = 4 * 8; break;
+        case SOP_ASSEMBLE: per = 2 * 16 + 4 * 8; break;
+        case SOP_REG: per = 2 * 16; break;
+        default: per = 2 * 8; break;
+        }
+        const int TW = col_tile(L, per, d.ncols);
+        const size_t lds = per * L * TW;
+        check_lds(lds, "x1_symbol");
+        const int lt = ilog2(TW);
+        const unsigned gx = (unsigned)((d.ncols + TW - 1) / TW);
+        Scope s(P, K_SPECTRAL_X1);
+        switch (op) {
+        case SOP_GRAD:
+            hipLaunchKernelGGL(k_x1_grad, dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds, P->stream,
+                               P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d, F.tw1, sc);
+            break;
+        case SOP_DIV:
+            hipLaunchKernelGGL(k_x1_div, dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds, P->stream,
+                               P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d, F.tw1, sc);
+            break;
+        case SOP_LERAY:
+            hipLaunchKernelGGL(k_x1_leray, dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds, P->stream,
+                               P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1, sc);
+            break;
+        case SOP_ASSEMBLE:
+            for (int b = 0; b < nbatch; ++b)
+                hipLaunchKernelGGL(k_x1_assemble, dim3(gx, outer[part], 1), dim3(kFftThreads), lds, P->stream,
+                                   P->spec, P->slot_bytes, in0 + 6 * b, in0 + 6 * b + 3, out0 + 3 * b, d, part,
+                                   TW, lt, rp, F.tw1d, F.tw1, sc);
+            break;
+        case SOP_REG:  // three independent fields per batch
+            hipLaunchKernelGGL((k_x1_scalar<double, SYM_REG>), dim3(gx, outer[part], 3 * nbatch),
+                               dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part,
+                               TW, lt, rp, F.tw1d, sc);
+            break;
+        case SOP_INVREG:
+            hipLaunchKernelGGL((k_x1_scalar<float, SYM_INVREG>), dim3(gx, outer[part], 3 * nbatch),
+                               dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part,
+                               TW, lt, rp, F.tw1, sc);
+            break;
+        case SOP_IDENT:
+            hipLaunchKernelGGL((k_x1_scalar<float, SYM_IDENT>), dim3(gx, outer[part], nbatch),
+                               dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part,
+                               TW, lt, rp, F.tw1, sc);
+            break;
+        default: fail(LDDMM_EINVAL, "unknown spectral operator");
+        }
+        check_hip(hipGetLastError(), "x1_symbol");
     }
 }
 
@@ -811,44 +1010,49 @@ void spectral_apply(lddmm_plan *P, int op, const std::vector<const float *> &in,
     if ((int)in.size() != nbatch * nin || (int)out.size() != nbatch * nout)
         fail(LDDMM_EINVAL, "spectral_apply: field count mismatch");
     const int per = nin + nout;
-    int chunk = P->nspec / per;
+    const int chunk = P->nspec / per;
     if (chunk < 1) fail(LDDMM_EINVAL, "spectral scratch too small");
     for (int b0 = 0; b0 < nbatch; b0 += chunk) {
         const int nb = std::min(chunk, nbatch - b0);
         const int fin = nb * nin, fout = nb * nout;
-        for (int f0 = 0; f0 < fin; f0 += 8) {
+        // forward x3 and x2 passes, grouped by precision (consecutive runs)
+        int f0 = 0;
+        while (f0 < fin) {
+            const bool dbl = input_is_fp64(op, f0 % nin);
+            int f1 = f0 + 1;
+            while (f1 < fin && f1 - f0 < 8 && input_is_fp64(op, f1 % nin) == dbl) ++f1;
             RealIn ri{};
-            const int cnt = std::min(8, fin - f0);
-            for (int i = 0; i < cnt; ++i) ri.p[i] = in[(size_t)b0 * nin + f0 + i];
-            r2c_fields(P, ri, cnt, f0);
+            for (int i = f0; i < f1; ++i) ri.p[i - f0] = in[(size_t)b0 * nin + i];
+            r2c_fields(P, ri, f1 - f0, f0, dbl);
+            x2_pass(P, f0, f1 - f0, false, dbl);
+            f0 = f1;
         }
-        x2_pass(P, 0, fin, false);
         x1_symbol(P, op, 0, fin, nb, P->cfg.leray);
-        x2_pass(P, fin, fout, true);
-        for (int f0 = 0; f0 < fout; f0 += 8) {
+        x2_pass(P, fin, fout, true, false);
+        for (int g0 = 0; g0 < fout; g0 += 8) {
             RealOut ro{};
-            const int cnt = std::min(8, fout - f0);
-            for (int i = 0; i < cnt; ++i) ro.p[i] = out[(size_t)b0 * nout + f0 + i];
-            c2r_fields(P, fin + f0, cnt, ro, 1.0f);
+            const int cnt = std::min(8, fout - g0);
+            for (int i = 0; i < cnt; ++i) ro.p[i] = out[(size_t)b0 * nout + g0 + i];
+            c2r_fields(P, fin + g0, cnt, ro, 1.0f);
         }
     }
 }
 
-void pack_standard(lddmm_plan *P, int spec_field, float2 *dst)
+void pack_standard(lddmm_plan *P, int slot, float2 *dst)
 {
     FftCtx &F = P->fft;
     Scope s(P, K_PACK);
     hipLaunchKernelGGL(k_pack_standard, dim3(1024), dim3(256), 0, P->stream,
-                       P->spec + (long)spec_field * F.spec_stride, dst, F.nrow, F.m3);
+                       reinterpret_cast<const float2 *>(P->spec + (long)slot * P->slot_bytes), dst, F.nrow, F.m3);
     check_hip(hipGetLastError(), "k_pack_standard");
 }
 
-void unpack_standard(lddmm_plan *P, const float2 *srcp, int spec_field)
+void unpack_standard(lddmm_plan *P, const float2 *srcp, int slot)
 {
     FftCtx &F = P->fft;
     Scope s(P, K_PACK);
     hipLaunchKernelGGL(k_unpack_standard, dim3(1024), dim3(256), 0, P->stream, srcp,
-                       P->spec + (long)spec_field * F.spec_stride, F.nrow, F.m3);
+                       reinterpret_cast<float2 *>(P->spec + (long)slot * P->slot_bytes), F.nrow, F.m3);
     check_hip(hipGetLastError(), "k_unpack_standard");
 }
 

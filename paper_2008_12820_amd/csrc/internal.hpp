@@ -30,8 +30,12 @@ struct FftCtx {
     long nrow = 0;         // n1*n2
     long spec_stride = 0;  // float2 per spectral field
     RadixPlan rp1{}, rp2{}, rp3{};
-    float2 *tw1 = nullptr, *tw2 = nullptr, *tw3 = nullptr, *twN3 = nullptr;  // device tables
+    float2 *tw1 = nullptr, *tw2 = nullptr, *tw3 = nullptr, *twN3 = nullptr;      // device tables
+    double2 *tw1d = nullptr, *tw2d = nullptr, *tw3d = nullptr, *twN3d = nullptr;  // FP64 tables
 };
+
+// LDS bytes one FFT workgroup may use
+constexpr size_t kLdsBudget = 64 * 1024;
 
 struct PlanTiming {
     bool on = false;
@@ -65,7 +69,8 @@ struct lddmm_plan {
     float *src = nullptr;    // max(nt-1,1) N incremental-state sources
     float *b = nullptr, *tmp3 = nullptr, *g = nullptr;
     float *px = nullptr, *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *vt = nullptr;
-    float2 *spec = nullptr;  // spectral scratch
+    char *spec = nullptr;    // spectral scratch: nspec slots of slot_bytes (FP64-sized)
+    long slot_bytes = 0;
     int nspec = 0;
     double *red = nullptr;   // reduction partials
     double *dscal = nullptr; // device scalars
@@ -97,14 +102,14 @@ struct RealOut {
 
 void fft_init(lddmm_plan *P);
 void fft_free(lddmm_plan *P);
-// real fields -> spectral fields [first, first+count) of P->spec
-void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int spec_first);
-// x2 pass over spectral fields (forward or inverse)
-void x2_pass(lddmm_plan *P, int spec_first, int count, bool inverse);
+// real fields -> spectral slots [slot0, slot0+count), FP64 or FP32 arithmetic and storage
+void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int slot0, bool dbl);
+// x2 pass over spectral slots (forward or inverse)
+void x2_pass(lddmm_plan *P, int slot0, int count, bool inverse, bool dbl);
 // x1 pass without a symbol (forward or inverse)
-void x1_pass(lddmm_plan *P, int spec_first, int count, bool inverse);
-// spectral fields -> real fields, times scale
-void c2r_fields(lddmm_plan *P, int spec_first, int count, const RealOut &out, float scale);
+void x1_pass(lddmm_plan *P, int slot0, int count, bool inverse, bool dbl);
+// FP32 spectral slots -> real fields, times scale
+void c2r_fields(lddmm_plan *P, int slot0, int count, const RealOut &out, float scale);
 
 enum SpecOp { SOP_GRAD = 1, SOP_DIV, SOP_REG, SOP_INVREG, SOP_LERAY, SOP_ASSEMBLE, SOP_IDENT };
 // x1 forward, pointwise symbol, x1 inverse in one pass: batches of the op's
