@@ -164,6 +164,130 @@ def cpu_baseline(n, nt, m0, m1, v, vt, sample):
     }
 
 
+def bench_batched(torch, dev):
+    """64 registrations, sizes uniform over {64,96,128,160}^3, N_t = 4, H2
+    beta = 1e-3, 5 Gauss-Newton iterations of exactly 8 PCG iterations:
+    batched graph-captured form vs the same members run one after another
+    through the plain per-plan calls."""
+    import numpy as np
+    import synth
+    from paper_2008_12820_amd import Plan
+    from paper_2008_12820_amd.batch import Batch
+    rng = np.random.default_rng(4000)
+    sizes = [int(x) for x in rng.choice([64, 96, 128, 160], size=64)]
+    shapes = [(n, n, n) for n in sizes]
+    log(f"batched: generating {len(sizes)} members")
+    m0s, m1s = [], []
+    for b, s in enumerate(shapes):
+        seed = 4000 + 10 * b
+        m0 = torch.from_numpy(synth.f32(synth.blob_image(s, 40, seed))).to(dev)
+        vt = torch.from_numpy(synth.f32(synth.bandlimited_vector(s, 6, seed + 1, max_disp=4.0))).to(dev)
+        P = Plan(s, 4, reg=2, beta=1e-3, device=dev, transport_only=True)
+        m1s.append(P.transport_forward(m0, vt))
+        m0s.append(m0)
+        P.close()
+    torch.cuda.synchronize()
+    npts = sum(int(np.prod(s)) for s in shapes)
+    GN, PCG, TOL = 5, 8, 1e-30  # tiny rtol: exactly 8 PCG iterations per step
+
+    log("batched: sequential plain runs")
+    plans = [Plan(s, 4, reg=2, beta=1e-3, device=dev) for s in shapes]
+    vseq = [torch.zeros((3,) + s, device=dev) for s in shapes]
+    for b, P in enumerate(plans):
+        P.set_images(m0s[b], m1s[b])
+        P.set_velocity(vseq[b])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, P in enumerate(plans):
+        for _ in range(GN):
+            P.gn_iterate(vseq[b], PCG, TOL)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for P in plans:
+        P.close()
+    del plans
+    torch.cuda.empty_cache()
+
+    log("batched: graph-captured batch")
+    Bt = Batch(shapes, 4, reg=2, beta=1e-3, nstreams=8)
+    vb = [torch.zeros((3,) + s, device=dev) for s in shapes]
+    Bt.set_images(m0s, m1s)
+    Bt.set_velocity(vb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(GN):
+        infos = Bt.gn_iterate(vb, PCG, TOL, use_graph=True)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    diff = max(float(torch.linalg.vector_norm(vb[b] - vseq[b]) /
+                     torch.linalg.vector_norm(vseq[b]).clamp_min(1e-30)) for b in range(len(shapes)))
+    Bt.close()
+    return {
+        "members": len(shapes), "sizes": {str(n): sizes.count(n) for n in (64, 96, 128, 160)},
+        "gn_steps": GN, "pcg_per_step": PCG,
+        "batched_s": t_bat, "sequential_s": t_seq,
+        "registrations_per_s": len(shapes) / t_bat,
+        "sequential_registrations_per_s": len(shapes) / t_seq,
+        "speedup": t_seq / t_bat,
+        "aggregate_grid_pts_per_s": npts * GN / t_bat,
+        "max_rel_l2_vs_sequential": diff,
+        "accepted_steps": sum(1 for i in infos if i["alpha"] > 0),
+    }
+
+
+def bench_autograd(torch, dev, n=512, nt=8):
+    """TransportMap forward + backward at 512^3, N_t = 8, with the loss
+    0.5 ||m(1) - m1||^2 + beta H2(v), beta = 1e-4, against the plain reduced
+    gradient (set_velocity + gradient) on the same inputs."""
+    import numpy as np
+    import synth
+    from paper_2008_12820_amd import Plan
+    from paper_2008_12820_amd.autograd import TransportMap
+    shape = (n, n, n)
+    log(f"autograd: generating {shape}")
+    m0 = torch.from_numpy(synth.f32(synth.blob_image(shape, 120, 5000))).to(dev)
+    m1 = torch.from_numpy(synth.f32(synth.blob_image(shape, 120, 5002))).to(dev)
+    v = torch.from_numpy(synth.f32(synth.bandlimited_vector(shape, 8, 5001, max_disp=6.0))).to(dev)
+    beta = 1e-4
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    T = TransportMap(shape, nt, reg=2, beta=beta, device=dev)
+    ws_t = Plan.workspace_bytes(shape, nt, 2, beta, transport_only=True)
+    times = []
+    for it in range(3):
+        vv = v.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = 0.5 * ((T(m0, vv) - m1) ** 2).sum() + beta * T.reg_energy(vv)
+        loss.backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    torch_peak = torch.cuda.max_memory_allocated()
+    g_auto = vv.grad.detach().clone()
+    T.plan.close()
+    del T
+    torch.cuda.empty_cache()
+    log("autograd: plain reduced gradient")
+    P = Plan(shape, nt, reg=2, beta=beta, device=dev)
+    ws_p = Plan.workspace_bytes(shape, nt, 2, beta)
+    P.set_images(m0, m1)
+    tp = []
+    for it in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.set_velocity(v)
+        g, gn = P.gradient()
+        torch.cuda.synchronize()
+        tp.append(time.perf_counter() - t0)
+    # plain-sum loss gradient equals the reduced gradient (no h^3, K = I)
+    rel = float(torch.linalg.vector_norm(g_auto - g) / torch.linalg.vector_norm(g))
+    P.close()
+    return {"grid": list(shape), "nt": nt, "forward_backward_ms": 1e3 * min(times),
+            "plain_set_velocity_gradient_ms": 1e3 * min(tp),
+            "transport_plan_GB": ws_t / 1e9, "plain_plan_GB": ws_p / 1e9,
+            "torch_peak_GB": torch_peak / 1e9, "rel_l2_autograd_vs_plain_gradient": rel}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +297,8 @@ def main():
     ap.add_argument("--no-nt8", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", choices=["full", "half"], default="full")
+    ap.add_argument("--batched", action="store_true", help="add the 64-member batched run")
+    ap.add_argument("--autograd", action="store_true", help="add the 512^3 autograd run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU's share only (the whole grid on one device); "
@@ -290,6 +416,10 @@ def main():
                       "transport": transport_rate(r8, 8),
                       "matvec_alg_hbm_frac": (136 + 132 * 8) * N / (ms8 * 1e-3) / 1e9 / PEAK_HBM_GBS,
                       "precompute_ms": 1e3 * r8["precompute_s"]}
+    if args.batched:
+        out["batched"] = bench_batched(torch, dev)
+    if args.autograd:
+        out["autograd"] = bench_autograd(torch, dev)
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle)")
         out["cpu_baseline"] = cpu_baseline(n, nt, m0, m1, v, vts[0], args.cpu_sample)

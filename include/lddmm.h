@@ -56,11 +56,20 @@ typedef enum lddmm_status {
  * Spectral symbols |k|^2 and |k|^4. */
 typedef enum lddmm_reg { LDDMM_REG_H1S = 1, LDDMM_REG_H2S = 2 } lddmm_reg;
 
+/* lddmm_config.flags */
+enum {
+    /* Allocate only what the transport map, its VJP, the spectral operators
+     * and lddmm_reg_energy need; the Newton-path calls then return
+     * LDDMM_EUNSUPPORTED.  (Roughly half the workspace.) */
+    LDDMM_FLAG_TRANSPORT_ONLY = 1
+};
+
 typedef struct lddmm_config {
     int32_t n[3];   /* grid size */
     int32_t nt;     /* time steps N_t >= 1 (dt = 1/N_t), Section 2 "Discretization" */
     int32_t reg;    /* lddmm_reg */
     int32_t leray;  /* 1: apply the Leray projection to the body force in g and H v~ */
+    int32_t flags;  /* LDDMM_FLAG_* bits, 0 for the full plan */
     double beta;    /* regularisation weight, finite and > 0 */
 } lddmm_config;
 
@@ -154,6 +163,12 @@ lddmm_status lddmm_transport_forward(lddmm_plan *plan, const float *m0, const fl
 lddmm_status lddmm_transport_vjp(lddmm_plan *plan, const float *ckpt, const float *v,
                                  const float *grad_m1, float *grad_m0, float *grad_v);
 
+/* Regularisation energy E = 1/2 sum_x (A v) . v (plain sum over the grid, no
+ * h^3; beta not applied) and, when Av is not NULL, A v (3N) -- the beta/2
+ * reg(v) term of eq. "problem" up to the factors beta h^3, and its gradient
+ * for a caller that differentiates E (e.g. an autograd loss).  v: 3N. */
+lddmm_status lddmm_reg_energy(lddmm_plan *plan, const float *v, float *Av, double *energy);
+
 /* ---- step-level calls: each step of the path on its own ---------------- */
 
 /* Unnormalised 3D real-to-complex DFT, hat f(k) = sum_x f(x) e^{-i k.x},
@@ -192,6 +207,36 @@ enum { LDDMM_FIELD_DISP = 1, LDDMM_FIELD_DISP_ADJ = 2, LDDMM_FIELD_STATE = 3,
        LDDMM_FIELD_GRAD_STATE = 4, LDDMM_FIELD_DIV = 5, LDDMM_FIELD_INC_STATE = 6,
        LDDMM_FIELD_ADJOINT = 7 };
 lddmm_status lddmm_get_field(lddmm_plan *plan, int32_t what, int32_t j, float *out);
+
+/* ---- batched form --------------------------------------------------------- */
+
+/* B independent registrations advanced together; member b has its own
+ * config (grid sizes may differ) and a full plan on one of nstreams
+ * library-created HIP streams (default priority).  Per Gauss-Newton
+ * iteration, each member's gradient, eps_K, fixed-count PCG (device-resident
+ * scalars, no host round trip), <g, v~> and first Armijo trial are one
+ * sequence, replayed from a captured hipGraph when use_graph != 0; members on
+ * different streams overlap.  The batch calls synchronise the device on
+ * entry and their streams on return.  Arrays of device pointers are HOST
+ * arrays of B entries. */
+typedef struct lddmm_batch lddmm_batch;
+
+lddmm_status lddmm_batch_create(int32_t B, const lddmm_config *cfgs, int32_t nstreams,
+                                lddmm_batch **batch);
+lddmm_status lddmm_batch_destroy(lddmm_batch *batch);
+/* member b's plan (owned by the batch) for per-member calls such as
+ * lddmm_objective or lddmm_get_field */
+lddmm_status lddmm_batch_plan(lddmm_batch *batch, int32_t b, lddmm_plan **plan);
+lddmm_status lddmm_batch_set_images(lddmm_batch *batch, const float *const *m0,
+                                    const float *const *m1);
+lddmm_status lddmm_batch_set_velocity(lddmm_batch *batch, const float *const *v);
+/* One Gauss-Newton iteration per member, with the semantics of
+ * lddmm_gn_iterate (rtol <= 0: eps_K rule; PCG stops are predicated so the
+ * result equals the early-exit loop).  v_inout[b] receives member b's new
+ * velocity; infos (host, B entries, may be NULL) the per-member reports. */
+lddmm_status lddmm_batch_gn_iterate(lddmm_batch *batch, int32_t max_pcg, double rtol,
+                                    int32_t use_graph, float *const *v_inout,
+                                    lddmm_newton_info *infos);
 
 /* ---- measurement -------------------------------------------------------- */
 

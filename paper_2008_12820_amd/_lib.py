@@ -19,9 +19,12 @@ FIELD_DISP, FIELD_DISP_ADJ, FIELD_STATE, FIELD_GRAD_STATE, FIELD_DIV, FIELD_INC_
     FIELD_ADJOINT = 1, 2, 3, 4, 5, 6, 7
 
 
+FLAG_TRANSPORT_ONLY = 1
+
+
 class Config(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("nt", ctypes.c_int32), ("reg", ctypes.c_int32),
-                ("leray", ctypes.c_int32), ("beta", ctypes.c_double)]
+                ("leray", ctypes.c_int32), ("flags", ctypes.c_int32), ("beta", ctypes.c_double)]
 
 
 class NewtonInfo(ctypes.Structure):
@@ -67,11 +70,18 @@ def lib():
             "lddmm_gn_iterate": (st, [p, i32, d, p, P(NewtonInfo)]),
             "lddmm_transport_forward": (st, [p, p, p, p, p]),
             "lddmm_transport_vjp": (st, [p, p, p, p, p, p]),
+            "lddmm_reg_energy": (st, [p, p, p, P(d)]),
             "lddmm_fft_r2c": (st, [p, p, p]),
             "lddmm_fft_c2r": (st, [p, p, p]),
             "lddmm_spectral_op": (st, [p, i32, p, p]),
             "lddmm_interp": (st, [p, i32, p, p, p]),
             "lddmm_get_field": (st, [p, i32, i32, p]),
+            "lddmm_batch_create": (st, [i32, P(Config), i32, P(p)]),
+            "lddmm_batch_destroy": (st, [p]),
+            "lddmm_batch_plan": (st, [p, i32, P(p)]),
+            "lddmm_batch_set_images": (st, [p, P(p), P(p)]),
+            "lddmm_batch_set_velocity": (st, [p, P(p)]),
+            "lddmm_batch_gn_iterate": (st, [p, i32, d, i32, P(p), P(NewtonInfo)]),
             "lddmm_set_timing": (st, [p, i32]),
             "lddmm_get_timing": (st, [p, i32, P(d), P(ctypes.c_int64)]),
             "lddmm_num_kernels": (i32, []),
@@ -111,10 +121,11 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_config(n, nt, reg=REG_H1S, beta=1e-2, leray=False):
+def make_config(n, nt, reg=REG_H1S, beta=1e-2, leray=False, flags=0):
     c = Config()
     c.n[0], c.n[1], c.n[2] = (int(x) for x in n)
     c.nt, c.reg, c.leray, c.beta = int(nt), int(reg), int(bool(leray)), float(beta)
+    c.flags = int(flags)
     return c
 
 
@@ -191,6 +202,12 @@ def lddmm_transport_vjp(plan, ckpt, v, grad_m1, grad_m0=None, grad_v=None):
                                      _ptr(grad_v)), "transport_vjp")
 
 
+def lddmm_reg_energy(plan, v, Av=None):
+    e = ctypes.c_double()
+    _check(lib().lddmm_reg_energy(plan, _ptr(v), _ptr(Av), ctypes.byref(e)), "reg_energy")
+    return e.value
+
+
 def lddmm_fft_r2c(plan, f, fhat):
     _check(lib().lddmm_fft_r2c(plan, _ptr(f), _ptr(fhat)), "fft_r2c")
 
@@ -209,6 +226,45 @@ def lddmm_interp(plan, nfields, fields, disp, out):
 
 def lddmm_get_field(plan, what, j, out):
     _check(lib().lddmm_get_field(plan, int(what), int(j), _ptr(out)), "get_field")
+
+
+def _ptr_array(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = _ptr(t).value
+    return arr
+
+
+def lddmm_batch_create(cfgs, nstreams):
+    arr = (Config * len(cfgs))(*cfgs)
+    h = ctypes.c_void_p()
+    _check(lib().lddmm_batch_create(len(cfgs), arr, int(nstreams), ctypes.byref(h)), "batch_create")
+    return h
+
+
+def lddmm_batch_destroy(batch):
+    _check(lib().lddmm_batch_destroy(batch), "batch_destroy")
+
+
+def lddmm_batch_plan(batch, b):
+    h = ctypes.c_void_p()
+    _check(lib().lddmm_batch_plan(batch, int(b), ctypes.byref(h)), "batch_plan")
+    return h
+
+
+def lddmm_batch_set_images(batch, m0s, m1s):
+    _check(lib().lddmm_batch_set_images(batch, _ptr_array(m0s), _ptr_array(m1s)), "batch_set_images")
+
+
+def lddmm_batch_set_velocity(batch, vs):
+    _check(lib().lddmm_batch_set_velocity(batch, _ptr_array(vs)), "batch_set_velocity")
+
+
+def lddmm_batch_gn_iterate(batch, max_pcg, rtol, use_graph, vs):
+    infos = (NewtonInfo * len(vs))()
+    _check(lib().lddmm_batch_gn_iterate(batch, int(max_pcg), float(rtol), int(bool(use_graph)),
+                                        _ptr_array(vs), infos), "batch_gn_iterate")
+    return [i.as_dict() for i in infos]
 
 
 def lddmm_set_timing(plan, enable):

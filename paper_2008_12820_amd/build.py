@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblddmm.so")
-SOURCES = ["api.hip", "fft.hip", "transport.hip", "linalg.hip"]
+SOURCES = ["api.hip", "fft.hip", "transport.hip", "linalg.hip", "batch.hip"]
 ARCH = "gfx950"
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

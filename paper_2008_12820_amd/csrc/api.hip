@@ -15,6 +15,7 @@ namespace lddmm {
 static thread_local std::string g_last_error;
 
 void fail(lddmm_status s, const std::string &msg) { throw Error{s, msg}; }
+void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 void check_hip(hipError_t e, const char *what)
 {
@@ -90,51 +91,61 @@ static void validate(const lddmm_config *cfg)
         fail(LDDMM_EINVAL, "reg must be LDDMM_REG_H1S or LDDMM_REG_H2S");
     if (!(std::isfinite(cfg->beta) && cfg->beta > 0.0)) fail(LDDMM_EINVAL, "beta must be finite and > 0");
     if (cfg->leray != 0 && cfg->leray != 1) fail(LDDMM_EINVAL, "leray must be 0 or 1");
+    if (cfg->flags & ~LDDMM_FLAG_TRANSPORT_ONLY) fail(LDDMM_EINVAL, "unknown bits in flags");
 }
 
 // Sub-allocation plan of the arena, in bytes, each piece 256-byte aligned.
 struct Layout {
     size_t off[40];
+    size_t len[40];
     int n = 0;
     size_t total = 0;
     size_t add(size_t bytes)
     {
         size_t o = total;
+        len[n] = bytes;
         off[n++] = o;
         total += (bytes + 255) & ~size_t(255);
         return o;
     }
 };
 
-static int spectral_slots(int nt) { return std::max(9, 4 * std::min(nt + 1, 4)); }
+static bool transport_only(const lddmm_config *cfg) { return cfg->flags & LDDMM_FLAG_TRANSPORT_ONLY; }
 
+static int spectral_slots(const lddmm_config *cfg)
+{
+    return transport_only(cfg) ? 9 : std::max(9, 4 * std::min(cfg->nt + 1, 4));
+}
+
+// Pieces the transport-only plan does not need get zero bytes.
 static Layout make_layout(const lddmm_config *cfg)
 {
     const size_t N = (size_t)cfg->n[0] * cfg->n[1] * cfg->n[2];
     const size_t nt = (size_t)cfg->nt;
     const size_t f = sizeof(float) * N;
     const size_t spec = sizeof(float2) * (size_t)cfg->n[0] * cfg->n[1] * (cfg->n[2] / 2 + 1);
+    const size_t full = transport_only(cfg) ? 0 : 1;
     Layout L;
-    L.add(f);                       // 0 m0
-    L.add(f);                       // 1 m1
-    L.add(3 * f);                   // 2 v
-    L.add(3 * f);                   // 3 dX
-    L.add(3 * f);                   // 4 dXa
-    L.add((nt + 1) * f);            // 5 m
-    L.add(3 * (nt + 1) * f);        // 6 G
-    L.add(3 * nt * f);              // 7 GX
-    L.add(f);                       // 8 delta
-    L.add(f);                       // 9 coef
-    L.add((nt + 1) * f);            // 10 lam
-    L.add(2 * f);                   // 11 mt
-    L.add(std::max<size_t>(nt - 1, 1) * f);  // 12 src
-    L.add(3 * f);                   // 13 b
-    L.add(3 * f);                   // 14 tmp3
-    L.add(3 * f);                   // 15 g
-    for (int i = 0; i < 6; ++i) L.add(3 * f);  // 16..21 pcg x r z p q vt
-    L.add(spectral_slots(cfg->nt) * 2 * spec); // 22 spec (slots sized for FP64)
-    L.add(sizeof(double) * kRedBlocks);        // 23 red
-    L.add(sizeof(double) * kNumScalars);       // 24 dscal
+    L.add(full * f);                       // 0 m0
+    L.add(full * f);                       // 1 m1
+    L.add(3 * f);                          // 2 v
+    L.add(3 * f);                          // 3 dX
+    L.add(3 * f);                          // 4 dXa
+    L.add((nt + 1) * f);                   // 5 m
+    L.add(3 * (nt + 1) * f);               // 6 G
+    L.add(full * 3 * nt * f);              // 7 GX
+    L.add(f);                              // 8 delta
+    L.add(f);                              // 9 coef
+    L.add((nt + 1) * f);                   // 10 lam
+    L.add(full * 2 * f);                   // 11 mt
+    L.add(full * std::max<size_t>(nt - 1, 1) * f);  // 12 src
+    L.add(3 * f);                          // 13 b
+    L.add(3 * f);                          // 14 tmp3
+    L.add(full * 3 * f);                   // 15 g
+    for (int i = 0; i < 6; ++i) L.add(full * 3 * f);  // 16..21 pcg x r z p q vt
+    L.add(spectral_slots(cfg) * 2 * spec);  // 22 spec (slots sized for FP64)
+    L.add(sizeof(double) * kRedBlocks);     // 23 red
+    L.add(sizeof(double) * kNumScalars);    // 24 dscal
     return L;
 }
 
@@ -166,17 +177,25 @@ static void need_dev(const void *p, const char *name, bool optional = false)
     if ((uintptr_t)p % 16 != 0) fail(LDDMM_EINVAL, std::string(name) + " is not 16-byte aligned");
 }
 
+static void need_full(const lddmm_plan *P)
+{
+    if (transport_only(&P->cfg))
+        fail(LDDMM_EUNSUPPORTED, "this plan was created with LDDMM_FLAG_TRANSPORT_ONLY");
+}
+
 static void need_velocity(const lddmm_plan *P)
 {
+    need_full(P);
     if (!P->have_images) fail(LDDMM_ESTATE, "set_images has not been called");
     if (!P->have_velocity) fail(LDDMM_ESTATE, "set_velocity has not been called since the last change");
 }
 
+// device-to-device copies run as a kernel so that every sequence stays
+// capturable in a graph
 static void copy_dev(lddmm_plan *P, float *dst, const float *src, long count)
 {
     if (dst == src) return;
-    check_hip(hipMemcpyAsync(dst, src, sizeof(float) * count, hipMemcpyDeviceToDevice, P->stream),
-              "device copy");
+    copy_kernel(P, count, src, dst);
 }
 
 static void zero_dev(lddmm_plan *P, float *dst, long count)
@@ -187,7 +206,7 @@ static void zero_dev(lddmm_plan *P, float *dst, long count)
 // ---------------------------------------------------------------------------
 // operators
 // ---------------------------------------------------------------------------
-static void velocity_state(lddmm_plan *P)
+void velocity_state(lddmm_plan *P)
 {
     const long N = P->N;
     const int nt = P->nt;
@@ -217,7 +236,8 @@ static void assemble(lddmm_plan *P, const float *w, const float *b, float *out)
                    {out, out + N, out + 2 * N});
 }
 
-static double gradient_impl(lddmm_plan *P, float *g)
+// g and <g,g> (slot S_GG), no host synchronisation
+void gradient_enqueue(lddmm_plan *P, float *g)
 {
     const long N = P->N;
     const int nt = P->nt;
@@ -226,14 +246,22 @@ static double gradient_impl(lddmm_plan *P, float *g)
     for (int j = nt - 1; j >= 0; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
     launch_body_force(P, lam, lam + (long)nt * N, 1.f, P->G, P->b);
     assemble(P, P->v, P->b, g);
-    dot_async(P, g, g, 3 * N, 0, P->h3);
-    const double gn = std::sqrt(fetch_scalar(P, 0));
-    if (P->g0norm == 0.0) P->g0norm = gn;
+    dot_async(P, g, g, 3 * N, S_GG, P->h3);
     P->have_grad = 1;
+}
+
+static double gradient_impl(lddmm_plan *P, float *g)
+{
+    gradient_enqueue(P, g);
+    const double gn = std::sqrt(fetch_scalar(P, S_GG));
+    if (P->g0norm == 0.0) {
+        P->g0norm = gn;
+        dev_set_scalar(P, S_G0, gn);
+    }
     return gn;
 }
 
-static void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
+void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
 {
     const long N = P->N;
     const int nt = P->nt;
@@ -250,7 +278,7 @@ static void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
     P->have_matvec = 1;
 }
 
-static void inv_reg(lddmm_plan *P, const float *r, float *s)
+void inv_reg(lddmm_plan *P, const float *r, float *s)
 {
     const long N = P->N;
     spectral_apply(P, SOP_INVREG, {r, r + N, r + 2 * N}, {s, s + N, s + 2 * N});
@@ -312,15 +340,70 @@ static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, fl
     return flags;
 }
 
-static void objective_impl(lddmm_plan *P, double &J, double &mis, double &reg)
+// J into slot sj, its parts into smis and sreg; no host synchronisation
+void objective_enqueue(lddmm_plan *P, int sj, int smis, int sreg)
 {
     const long N = P->N;
-    sqdiff_async(P, P->m + (long)P->nt * N, P->m1, N, 2, 0.5 * P->h3);
+    sqdiff_async(P, P->m + (long)P->nt * N, P->m1, N, smis, 0.5 * P->h3);
     spectral_apply(P, SOP_REG, {P->v, P->v + N, P->v + 2 * N}, {P->tmp3, P->tmp3 + N, P->tmp3 + 2 * N});
-    dot_async(P, P->tmp3, P->v, 3 * N, 3, 0.5 * P->cfg.beta * P->h3);
-    mis = fetch_scalar(P, 2);
-    reg = fetch_scalar(P, 3);
+    dot_async(P, P->tmp3, P->v, 3 * N, sreg, 0.5 * P->cfg.beta * P->h3);
+    dev_sum(P, sj, smis, sreg);
+}
+
+static void objective_impl(lddmm_plan *P, double &J, double &mis, double &reg)
+{
+    objective_enqueue(P, S_E, S_MIS, S_REG);
+    mis = fetch_scalar(P, S_MIS);
+    reg = fetch_scalar(P, S_REG);
     J = mis + reg;
+}
+
+// PCG on H x = -g with every scalar on the device (no host round trip):
+// exactly max_it iterations are enqueued and the ones after a stop are
+// predicated off, which reproduces the early exit of the host loop.
+// g must hold the gradient and slot S_RTOL the tolerance.
+void pcg_enqueue(lddmm_plan *P, const float *g, int max_it, float *x)
+{
+    const long M = 3 * P->N;
+    float *r = P->pr, *z = P->pz, *p = P->pp, *q = P->pq;
+    axpby(P, M, -1.f, g, 0.f, nullptr, r);
+    fill(P, M, 0.f, x);
+    dot_async(P, r, r, M, S_RR, P->h3);
+    dev_pcg_init(P);
+    inv_reg(P, r, z);
+    copy_dev(P, p, z, M);
+    dot_async(P, r, z, M, S_RZ, P->h3);
+    for (int it = 0; it < max_it; ++it) {
+        matvec_impl(P, p, q);
+        dot_async(P, p, q, M, S_KAPPA, P->h3);
+        dev_pcg_alpha(P);
+        dev_pcg_xr(P, M, p, q, x, r);
+        dev_copy_if(P, M, z, x);
+        dot_async(P, r, r, M, S_RR, P->h3);
+        dev_pcg_conv(P);
+        inv_reg(P, r, z);
+        dot_async(P, r, z, M, S_RZN, P->h3);
+        dev_pcg_beta(P);
+        dev_pcg_p(P, M, z, p);
+    }
+}
+
+// One Gauss-Newton iteration up to and including the first line-search
+// trial (alpha = 1), all on the device: gradient, tolerance, J(v), PCG step
+// into P->vt, <g, v~>, the old velocity saved in v0, v <- v0 + v~, state
+// refresh and J(v0 + v~).  Scalars land in the S_* slots.
+void gn_trial_enqueue(lddmm_plan *P, int max_pcg, double rtol, float *v0)
+{
+    const long M = 3 * P->N;
+    gradient_enqueue(P, P->g);
+    dev_tolerance(P, rtol);
+    objective_enqueue(P, S_J0, S_MIS, S_REG);
+    pcg_enqueue(P, P->g, max_pcg, P->vt);
+    dot_async(P, P->g, P->vt, M, S_GV, P->h3);
+    copy_dev(P, v0, P->v, M);
+    axpby(P, M, 1.f, v0, 1.f, P->vt, P->v);
+    velocity_state(P);
+    objective_enqueue(P, S_J1, S_MIS1, S_REG1);
 }
 
 static double tolerance(lddmm_plan *P, double rtol, double gnorm)
@@ -379,7 +462,7 @@ lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan
         }
         P->arena_bytes = L.total;
         char *a = (char *)P->arena;
-        auto F = [&](int i) { return (float *)(a + L.off[i]); };
+        auto F = [&](int i) { return L.len[i] ? (float *)(a + L.off[i]) : nullptr; };
         P->m0 = F(0);
         P->m1 = F(1);
         P->v = F(2);
@@ -403,7 +486,7 @@ lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan
         P->pq = F(20);
         P->vt = F(21);
         P->spec = a + L.off[22];
-        P->nspec = spectral_slots(cfg->nt);
+        P->nspec = spectral_slots(cfg);
         P->slot_bytes = (long)sizeof(double2) * cfg->n[0] * cfg->n[1] * (cfg->n[2] / 2 + 1);
         P->red = (double *)(a + L.off[23]);
         P->dscal = (double *)(a + L.off[24]);
@@ -434,8 +517,10 @@ lddmm_status lddmm_set_images(lddmm_plan *P, const float *m0, const float *m1)
         need(P, "plan");
         need_dev(m0, "m0");
         need_dev(m1, "m1");
+        need_full(P);
         copy_dev(P, P->m0, m0, P->N);
         copy_dev(P, P->m1, m1, P->N);
+        dev_set_scalar(P, S_G0, 0.0);
         P->have_images = 1;
         P->have_velocity = 0;
         P->g0norm = 0.0;
@@ -447,6 +532,7 @@ lddmm_status lddmm_set_velocity(lddmm_plan *P, const float *v)
     return guard([&] {
         need(P, "plan");
         need_dev(v, "v");
+        need_full(P);
         if (!P->have_images) fail(LDDMM_ESTATE, "set_images has not been called");
         copy_dev(P, P->v, v, 3 * P->N);
         velocity_state(P);
@@ -623,6 +709,21 @@ lddmm_status lddmm_transport_vjp(lddmm_plan *P, const float *ckpt, const float *
             launch_body_force(P, lam, lam + (long)nt * N, 1.f, P->G, P->b);
             axpby(P, 3 * N, -1.f, P->b, 0.f, nullptr, grad_v);
         }
+    });
+}
+
+lddmm_status lddmm_reg_energy(lddmm_plan *P, const float *v, float *Av, double *energy)
+{
+    return guard([&] {
+        need(P, "plan");
+        need_dev(v, "v");
+        need_dev(Av, "Av", true);
+        need(energy, "energy");
+        const long N = P->N;
+        float *out = Av ? Av : P->tmp3;
+        spectral_apply(P, SOP_REG, {v, v + N, v + 2 * N}, {out, out + N, out + 2 * N});
+        dot_async(P, out, v, 3 * N, 4, 0.5);
+        *energy = fetch_scalar(P, 4);
     });
 }
 

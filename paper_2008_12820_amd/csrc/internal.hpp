@@ -17,6 +17,7 @@ struct Error {
 };
 
 [[noreturn]] void fail(lddmm_status s, const std::string &msg);
+void set_last_error(const std::string &msg);
 void check_hip(hipError_t e, const char *what);
 
 // Spectral layout of one real field of n1 x n2 x n3 (internal, never exposed):
@@ -135,6 +136,15 @@ void launch_incstate_step(lddmm_plan *P, const float *min, const float *s, float
 void launch_body_force(lddmm_plan *P, const float *lam, const float *lamN, float scaleN,
                        const float *G, float *b);
 
+// ---- api.hip (sequencing shared with the batched form) ---------------------
+void velocity_state(lddmm_plan *P);
+void gradient_enqueue(lddmm_plan *P, float *g);
+void matvec_impl(lddmm_plan *P, const float *vt, float *hvt);
+void inv_reg(lddmm_plan *P, const float *r, float *s);
+void objective_enqueue(lddmm_plan *P, int sj, int smis, int sreg);
+void pcg_enqueue(lddmm_plan *P, const float *g, int max_it, float *x);
+void gn_trial_enqueue(lddmm_plan *P, int max_pcg, double rtol, float *v0);
+
 // ---- linalg.hip -------------------------------------------------------------
 // FP64 h^3-weighted reductions; result left in P->dscal[slot] (device).
 void dot_async(lddmm_plan *P, const float *a, const float *b, long n, int slot, double scale);
@@ -149,6 +159,30 @@ void fill(lddmm_plan *P, long n, float value, float *out);
 void pcg_update_xr(lddmm_plan *P, long n, float al, const float *p, const float *q, float *x,
                    float *r);
 constexpr int kRedBlocks = 1024;
-constexpr int kNumScalars = 16;
+constexpr int kNumScalars = 32;
+
+// Device scalar slots (P->dscal).  0..4 serve the eager calls; the rest hold
+// the state of the device-resident PCG / Gauss-Newton step, which needs no
+// host round trip and can be captured in a graph.
+enum ScalarSlot {
+    S_GG = 0, S_DOT = 1, S_MIS = 2, S_REG = 3, S_E = 4,
+    S_RR = 5, S_RZ = 6, S_KAPPA = 7, S_RZN = 8, S_R0 = 9, S_ALPHA = 10, S_BETA = 11,
+    S_DONE = 12, S_ITERS = 13, S_FLAGS = 14, S_RTOL = 15, S_REL = 16, S_GNORM = 17,
+    S_G0 = 18, S_GV = 19, S_J0 = 20, S_J1 = 21, S_COPYZ = 22, S_MIS1 = 23, S_REG1 = 24
+};
+
+// device-resident PCG pieces (single-thread scalar kernels and predicated
+// vector updates; see linalg.hip)
+void dev_set_scalar(lddmm_plan *P, int slot, double value);
+void dev_tolerance(lddmm_plan *P, double rtol);
+void dev_pcg_init(lddmm_plan *P);
+void dev_pcg_alpha(lddmm_plan *P);
+void dev_pcg_xr(lddmm_plan *P, long n, const float *p, const float *q, float *x, float *r);
+void dev_copy_if(lddmm_plan *P, long n, const float *z, float *x);
+void dev_pcg_conv(lddmm_plan *P);
+void dev_pcg_beta(lddmm_plan *P);
+void dev_pcg_p(lddmm_plan *P, long n, const float *z, float *p);
+void dev_sum(lddmm_plan *P, int dst, int a, int b);
+void copy_kernel(lddmm_plan *P, long n, const float *x, float *out);
 
 }  // namespace lddmm

@@ -72,6 +72,113 @@ __global__ void k_pcg_xr(long n, float al, const float *__restrict__ p, const fl
     }
 }
 
+// ---- device-resident PCG scalars ----------------------------------------
+__global__ void k_set_scalar(double *d, int slot, double value) { d[slot] = value; }
+
+// gnorm = sqrt(<g,g>); ||g0|| latched on first use; eps_K rule when rtol <= 0
+__global__ void k_tolerance(double *d, double rtol)
+{
+    const double gn = sqrt(d[S_GG]);
+    d[S_GNORM] = gn;
+    if (d[S_G0] == 0.0) d[S_G0] = gn;
+    const double grel = d[S_G0] > 0.0 ? gn / d[S_G0] : 1.0;
+    d[S_RTOL] = rtol > 0.0 ? rtol : fmin(sqrt(grel), 0.5);
+}
+
+__global__ void k_pcg_init(double *d)
+{
+    const double r0 = sqrt(d[S_RR]);
+    d[S_R0] = r0;
+    d[S_DONE] = (r0 == 0.0) ? 1.0 : 0.0;
+    d[S_ITERS] = 0.0;
+    d[S_FLAGS] = 0.0;
+    d[S_REL] = 0.0;
+    d[S_COPYZ] = 0.0;
+    d[S_ALPHA] = 0.0;
+    d[S_BETA] = 0.0;
+}
+
+// after kappa = <p, H p>: alpha, or stop on non-finite / non-positive kappa
+__global__ void k_pcg_alpha(double *d)
+{
+    if (d[S_DONE] != 0.0) {
+        d[S_ALPHA] = 0.0;
+        return;
+    }
+    d[S_ITERS] += 1.0;
+    const double kappa = d[S_KAPPA];
+    if (!isfinite(kappa)) {
+        d[S_FLAGS] = (double)((int)d[S_FLAGS] | 2);
+        d[S_DONE] = 1.0;
+        d[S_ALPHA] = 0.0;
+    } else if (kappa <= 0.0) {
+        d[S_FLAGS] = (double)((int)d[S_FLAGS] | 1);
+        d[S_DONE] = 1.0;
+        d[S_ALPHA] = 0.0;
+        if (d[S_ITERS] == 1.0) d[S_COPYZ] = 1.0;
+    } else {
+        d[S_ALPHA] = d[S_RZ] / kappa;
+    }
+}
+
+__global__ void k_pcg_xr_dev(long n, const double *__restrict__ d, const float *__restrict__ p,
+                             const float *__restrict__ q, float *__restrict__ x, float *__restrict__ r)
+{
+    const float al = (float)d[S_ALPHA];
+    if (al == 0.f) return;
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        x[i] += al * p[i];
+        r[i] -= al * q[i];
+    }
+}
+
+__global__ void k_copy_if(long n, const double *__restrict__ d, const float *__restrict__ z,
+                          float *__restrict__ x)
+{
+    if (d[S_COPYZ] == 0.0) return;
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = z[i];
+}
+
+// after rr = <r, r>: relative residual and the stopping test
+__global__ void k_pcg_conv(double *d)
+{
+    if (d[S_DONE] != 0.0) return;
+    const double rn = sqrt(d[S_RR]);
+    if (!isfinite(rn)) {
+        d[S_FLAGS] = (double)((int)d[S_FLAGS] | 2);
+        d[S_DONE] = 1.0;
+        return;
+    }
+    d[S_REL] = rn / d[S_R0];
+    if (rn <= d[S_RTOL] * d[S_R0]) d[S_DONE] = 1.0;
+}
+
+__global__ void k_pcg_beta(double *d)
+{
+    if (d[S_DONE] != 0.0) return;
+    d[S_BETA] = d[S_RZN] / d[S_RZ];
+    d[S_RZ] = d[S_RZN];
+}
+
+__global__ void k_pcg_p(long n, const double *__restrict__ d, const float *__restrict__ z,
+                        float *__restrict__ p)
+{
+    if (d[S_DONE] != 0.0) return;
+    const float be = (float)d[S_BETA];
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = z[i] + be * p[i];
+}
+
+__global__ void k_sum2(double *d, int dst, int a, int b) { d[dst] = d[a] + d[b]; }
+
+__global__ void k_copy(long n, const float *__restrict__ x, float *__restrict__ out)
+{
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = x[i];
+}
+
 static unsigned vec_blocks(long n)
 {
     long b = (n + 255) / 256;
@@ -130,6 +237,49 @@ void pcg_update_xr(lddmm_plan *P, long n, float al, const float *p, const float 
     Scope s(P, K_VECOP);
     hipLaunchKernelGGL(k_pcg_xr, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, al, p, q, x, r);
     check_hip(hipGetLastError(), "k_pcg_xr");
+}
+
+#define LAUNCH1(kern, ...)                                                                  \
+    do {                                                                                    \
+        Scope s_(P, K_VECOP);                                                               \
+        hipLaunchKernelGGL(kern, dim3(1), dim3(1), 0, P->stream, __VA_ARGS__);              \
+        check_hip(hipGetLastError(), #kern);                                                \
+    } while (0)
+
+void dev_set_scalar(lddmm_plan *P, int slot, double value) { LAUNCH1(k_set_scalar, P->dscal, slot, value); }
+void dev_tolerance(lddmm_plan *P, double rtol) { LAUNCH1(k_tolerance, P->dscal, rtol); }
+void dev_pcg_init(lddmm_plan *P) { LAUNCH1(k_pcg_init, P->dscal); }
+void dev_pcg_alpha(lddmm_plan *P) { LAUNCH1(k_pcg_alpha, P->dscal); }
+void dev_pcg_conv(lddmm_plan *P) { LAUNCH1(k_pcg_conv, P->dscal); }
+void dev_pcg_beta(lddmm_plan *P) { LAUNCH1(k_pcg_beta, P->dscal); }
+void dev_sum(lddmm_plan *P, int dst, int a, int b) { LAUNCH1(k_sum2, P->dscal, dst, a, b); }
+
+void dev_pcg_xr(lddmm_plan *P, long n, const float *p, const float *q, float *x, float *r)
+{
+    Scope s(P, K_VECOP);
+    hipLaunchKernelGGL(k_pcg_xr_dev, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, P->dscal, p, q, x, r);
+    check_hip(hipGetLastError(), "k_pcg_xr_dev");
+}
+
+void dev_copy_if(lddmm_plan *P, long n, const float *z, float *x)
+{
+    Scope s(P, K_VECOP);
+    hipLaunchKernelGGL(k_copy_if, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, P->dscal, z, x);
+    check_hip(hipGetLastError(), "k_copy_if");
+}
+
+void dev_pcg_p(lddmm_plan *P, long n, const float *z, float *p)
+{
+    Scope s(P, K_VECOP);
+    hipLaunchKernelGGL(k_pcg_p, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, P->dscal, z, p);
+    check_hip(hipGetLastError(), "k_pcg_p");
+}
+
+void copy_kernel(lddmm_plan *P, long n, const float *x, float *out)
+{
+    Scope s(P, K_VECOP);
+    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, x, out);
+    check_hip(hipGetLastError(), "k_copy");
 }
 
 }  // namespace lddmm

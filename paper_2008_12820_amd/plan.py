@@ -7,7 +7,7 @@ from . import _lib as L
 
 class Plan:
     def __init__(self, shape, nt, reg=L.REG_H1S, beta=1e-2, leray=False, device=None,
-                 stream=None):
+                 stream=None, transport_only=False):
         self.shape = tuple(int(s) for s in shape)
         self.nt = int(nt)
         self.reg = int(reg)
@@ -17,7 +17,8 @@ class Plan:
         with torch.cuda.device(self.device):
             s = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = s
-        self.cfg = L.make_config(self.shape, self.nt, self.reg, self.beta, self.leray)
+        self.cfg = L.make_config(self.shape, self.nt, self.reg, self.beta, self.leray,
+                                 L.FLAG_TRANSPORT_ONLY if transport_only else 0)
         with torch.cuda.device(self.device):
             self._h = L.lddmm_plan_create(self.cfg, s.cuda_stream)
 
@@ -34,8 +35,9 @@ class Plan:
             pass
 
     @staticmethod
-    def workspace_bytes(shape, nt, reg=L.REG_H1S, beta=1e-2, leray=False):
-        return L.lddmm_workspace_bytes(L.make_config(shape, nt, reg, beta, leray))
+    def workspace_bytes(shape, nt, reg=L.REG_H1S, beta=1e-2, leray=False, transport_only=False):
+        return L.lddmm_workspace_bytes(L.make_config(
+            shape, nt, reg, beta, leray, L.FLAG_TRANSPORT_ONLY if transport_only else 0))
 
     # ---- helpers ----
     def _scalar(self):
@@ -97,6 +99,12 @@ class Plan:
         gv = self._vector() if want_v else None
         L.lddmm_transport_vjp(self._h, ckpt, self._in(v, True), self._in(grad_m1, False), gm0, gv)
         return gm0, gv
+
+    def reg_energy(self, v, want_Av=True):
+        """(1/2 sum (A v).v, A v) -- plain sums, beta not applied."""
+        Av = self._vector() if want_Av else None
+        e = L.lddmm_reg_energy(self._h, self._in(v, True), Av)
+        return e, Av
 
     def fft_r2c(self, f):
         n1, n2, n3 = self.shape
