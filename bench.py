@@ -323,6 +323,8 @@ def main():
     for nt_ in ([4] if args.no_nt8 else [4, 8]):
         log(f"plan {n} nt={nt_}")
         plan = Plan(n, nt_, reg=2, beta=5e-4, leray=True, device=dev)
+        tuning = plan.autotune()
+        log(f"autotuned: {tuning}")
         plan.set_images(m0d, m1d)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -336,7 +338,8 @@ def main():
         steps = args.steps if nt_ == 4 else max(5, args.steps // 2)
         log(f"timing {steps} matvecs nt={nt_}")
         el, kt = time_matvecs(plan, vtd, steps, args.warmup, torch)
-        res_nt[nt_] = dict(elapsed=el, steps=steps, kt=kt, precompute_s=pre, gradient_s=tg)
+        res_nt[nt_] = dict(elapsed=el, steps=steps, kt=kt, precompute_s=pre, gradient_s=tg,
+                           tuning=tuning)
         if nt_ == 4:
             log("newton step, 10 PCG iterations")
             torch.cuda.synchronize()
@@ -408,6 +411,7 @@ def main():
         "gradient_ms": 1e3 * r4["gradient_s"],
         "newton_step_10pcg_ms": 1e3 * r4.get("newton_step_s", float("nan")),
         "newton_info": r4.get("newton_info"),
+        "fft_tiles": r4["tuning"],
     }
     if 8 in res_nt:
         r8 = res_nt[8]

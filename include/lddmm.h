@@ -240,6 +240,16 @@ lddmm_status lddmm_batch_gn_iterate(lddmm_batch *batch, int32_t max_pcg, double 
 
 /* ---- measurement -------------------------------------------------------- */
 
+/* Autotuner: times every candidate tile shape (powers of two up to the LDS
+ * budget) of each FFT kernel of the plan -- x3 rows per block, x1/x2 column
+ * tiles per precision and sub-array, fused x1 operator tiles -- on the
+ * plan's own buffers, keeps the fastest, and caches the choice per device
+ * and grid size for the process and, when the environment variable
+ * LDDMM_TUNE_CACHE names a file, in that file.  Synchronises the stream. */
+lddmm_status lddmm_autotune(lddmm_plan *plan);
+/* NUL-terminated report of the tile shapes in use (len bytes at most). */
+lddmm_status lddmm_tuning(lddmm_plan *plan, char *buf, size_t len);
+
 /* enable != 0: bracket every kernel launch of the plan with HIP events on
  * the plan's stream.  lddmm_get_timing synchronises, then reports the summed
  * event time (ms) and launch count of kernel class id since the last reset

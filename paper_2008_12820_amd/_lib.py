@@ -82,6 +82,8 @@ def lib():
             "lddmm_batch_set_images": (st, [p, P(p), P(p)]),
             "lddmm_batch_set_velocity": (st, [p, P(p)]),
             "lddmm_batch_gn_iterate": (st, [p, i32, d, i32, P(p), P(NewtonInfo)]),
+            "lddmm_autotune": (st, [p]),
+            "lddmm_tuning": (st, [p, ctypes.c_char_p, sz]),
             "lddmm_set_timing": (st, [p, i32]),
             "lddmm_get_timing": (st, [p, i32, P(d), P(ctypes.c_int64)]),
             "lddmm_num_kernels": (i32, []),
@@ -265,6 +267,16 @@ def lddmm_batch_gn_iterate(batch, max_pcg, rtol, use_graph, vs):
     _check(lib().lddmm_batch_gn_iterate(batch, int(max_pcg), float(rtol), int(bool(use_graph)),
                                         _ptr_array(vs), infos), "batch_gn_iterate")
     return [i.as_dict() for i in infos]
+
+
+def lddmm_autotune(plan):
+    _check(lib().lddmm_autotune(plan), "autotune")
+
+
+def lddmm_tuning(plan):
+    buf = ctypes.create_string_buffer(1024)
+    _check(lib().lddmm_tuning(plan, buf, 1024), "tuning")
+    return buf.value.decode()
 
 
 def lddmm_set_timing(plan, enable):

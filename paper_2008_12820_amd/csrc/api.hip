@@ -862,6 +862,28 @@ lddmm_status lddmm_get_timing(lddmm_plan *P, int32_t kernel_id, double *total_ms
     });
 }
 
+lddmm_status lddmm_autotune(lddmm_plan *P)
+{
+    return guard([&] {
+        need(P, "plan");
+        check_hip(hipStreamSynchronize(P->stream), "stream sync");
+        autotune_fft(P);
+    });
+}
+
+lddmm_status lddmm_tuning(lddmm_plan *P, char *buf, size_t len)
+{
+    return guard([&] {
+        need(P, "plan");
+        need(buf, "buf");
+        const std::string r = tuning_report(P);
+        if (len == 0) fail(LDDMM_EINVAL, "len is 0");
+        const size_t n = std::min(len - 1, r.size());
+        std::memcpy(buf, r.data(), n);
+        buf[n] = 0;
+    });
+}
+
 int32_t lddmm_num_kernels(void) { return K_NUM_KERNELS; }
 
 const char *lddmm_kernel_name(int32_t kernel_id) { return kernel_name(kernel_id); }

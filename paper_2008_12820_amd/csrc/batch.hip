@@ -131,6 +131,10 @@ lddmm_status lddmm_batch_create(int32_t B, const lddmm_config *cfgs, int32_t nst
             lddmm_status s = lddmm_plan_create(&cfgs[b], (void *)Bt->streams[b % S], &Bt->plans[b]);
             if (s != LDDMM_OK)
                 fail(s, "member " + std::to_string(b) + ": " + lddmm_last_error());
+            // FFT tiles per grid size (the cache makes repeated sizes free)
+            s = lddmm_autotune(Bt->plans[b]);
+            if (s != LDDMM_OK)
+                fail(s, "member " + std::to_string(b) + " autotune: " + lddmm_last_error());
         }
         *out = Bt;
     });

@@ -27,6 +27,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
 
 namespace lddmm {
 
@@ -706,6 +711,13 @@ RadixPlan make_radix_plan(int L)
     return rp;
 }
 
+static int floor_pow2(long x);
+static int rows_per_block(int m3, size_t csize);
+static int col_tile(int L, size_t bytes_per_elem, int ncols);
+static void col_descs(const FftCtx &F, int axis, struct ColDesc dd[2], int outer[2]);
+static size_t x1_bytes_per_elem(int op);
+static void default_tiles(FftCtx &F);
+
 template <class C>
 static C *upload_twiddles(int L)
 {
@@ -741,6 +753,7 @@ void fft_init(lddmm_plan *P)
     F.tw2d = upload_twiddles<double2>(F.n2);
     F.tw3d = upload_twiddles<double2>(F.m3);
     F.twN3d = upload_twiddles<double2>(F.n3);
+    default_tiles(F);
 }
 
 void fft_free(lddmm_plan *P)
@@ -751,6 +764,19 @@ void fft_free(lddmm_plan *P)
         if (p) (void)hipFree(p);
     F.tw1 = F.tw2 = F.tw3 = F.twN3 = nullptr;
     F.tw1d = F.tw2d = F.tw3d = F.twN3d = nullptr;
+}
+
+// LDS bytes per tile element of each fused x1 kernel
+static size_t x1_bytes_per_elem(int op)
+{
+    switch (op) {
+    case SOP_GRAD: return 2 * 16 + 3 * 8;
+    case SOP_DIV: return 3 * 16;
+    case SOP_LERAY: return 4 * 8;
+    case SOP_ASSEMBLE: return 2 * 16 + 4 * 8;
+    case SOP_REG: return 2 * 16;
+    default: return 2 * 8;
+    }
 }
 
 static int floor_pow2(long x)
@@ -788,6 +814,28 @@ static int col_tile(int L, size_t bytes_per_elem, int ncols)
     return t;
 }
 
+// heuristic tiles: the widest power-of-two tile the LDS budget allows (<= 32)
+static void default_tiles(FftCtx &F)
+{
+    for (int axis = 0; axis < 2; ++axis) {
+        ColDesc dd[2];
+        int outer[2];
+        col_descs(F, axis == 1 ? 1 : 0, dd, outer);
+        const int L = axis == 1 ? F.rp2.L : F.rp1.L;
+        for (int part = 0; part < 2; ++part)
+            for (int dbl = 0; dbl < 2; ++dbl)
+                F.tw_cols[axis][part][dbl] = col_tile(L, 2 * (dbl ? 16 : 8), dd[part].ncols);
+    }
+    ColDesc dd[2];
+    int outer[2];
+    col_descs(F, 0, dd, outer);
+    for (int op = 0; op < 8; ++op)
+        for (int part = 0; part < 2; ++part) F.tw_x1[op][part] = col_tile(F.rp1.L, x1_bytes_per_elem(op), dd[part].ncols);
+    F.twr_r2c[0] = rows_per_block(F.m3, sizeof(float2));
+    F.twr_r2c[1] = rows_per_block(F.m3, sizeof(double2));
+    F.twr_c2r = rows_per_block(F.m3, sizeof(float2));
+}
+
 static void check_lds(size_t bytes, const char *what)
 {
     if (bytes > kLdsBudget) fail(LDDMM_EUNSUPPORTED, std::string(what) + ": LDS tile exceeds the budget");
@@ -797,7 +845,7 @@ void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int slot0, bool dbl)
 {
     FftCtx &F = P->fft;
     const size_t cs = dbl ? sizeof(double2) : sizeof(float2);
-    const int TWR = rows_per_block(F.m3, cs);
+    const int TWR = F.twr_r2c[dbl ? 1 : 0];
     const size_t lds = 2 * cs * TWR * (F.m3 + 1);
     check_lds(lds, "r2c_x3");
     dim3 grid((unsigned)((F.nrow + TWR - 1) / TWR), count);
@@ -814,8 +862,9 @@ void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int slot0, bool dbl)
 void c2r_fields(lddmm_plan *P, int slot0, int count, const RealOut &out, float scale)
 {
     FftCtx &F = P->fft;
-    const int TWR = rows_per_block(F.m3, sizeof(float2));
+    const int TWR = F.twr_c2r;
     const size_t lds = 2 * sizeof(float2) * TWR * (F.m3 + 1);
+    check_lds(lds, "c2r_x3");
     dim3 grid((unsigned)((F.nrow + TWR - 1) / TWR), count);
     Scope s(P, K_C2R_X3);
     hipLaunchKernelGGL(k_c2r_x3, grid, dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes,
@@ -839,7 +888,8 @@ static void col_descs(const FftCtx &F, int axis, ColDesc dd[2], int outer[2])
     }
 }
 
-static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool inverse, bool dbl)
+static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool inverse, bool dbl,
+                      int only_part = -1)
 {
     FftCtx &F = P->fft;
     const RadixPlan &rp = axis == 1 ? F.rp2 : F.rp1;
@@ -848,8 +898,9 @@ static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool invers
     col_descs(F, axis, dd, outer);
     const size_t cs = dbl ? sizeof(double2) : sizeof(float2);
     for (int part = 0; part < 2; ++part) {
+        if (only_part >= 0 && part != only_part) continue;
         const ColDesc &d = dd[part];
-        const int TW = col_tile(rp.L, 2 * cs, d.ncols);
+        const int TW = F.tw_cols[axis == 1 ? 1 : 0][part][dbl ? 1 : 0];
         const size_t lds = 2 * cs * rp.L * TW;
         check_lds(lds, "fft_cols");
         dim3 grid((unsigned)((d.ncols + TW - 1) / TW), outer[part], count);
@@ -933,7 +984,14 @@ static SymCtx sym_ctx(lddmm_plan *P, int leray)
 
 // x1 forward, symbol, x1 inverse for nbatch batches: inputs of batch b at
 // slots in0 + b*nin .. , outputs at out0 + b*nout ..
+static void x1_symbol_parts(lddmm_plan *P, int op, int in0, int out0, int nbatch, int leray, int only_part);
+
 void x1_symbol(lddmm_plan *P, int op, int in0, int out0, int nbatch, int leray)
+{
+    x1_symbol_parts(P, op, in0, out0, nbatch, leray, -1);
+}
+
+static void x1_symbol_parts(lddmm_plan *P, int op, int in0, int out0, int nbatch, int leray, int only_part)
 {
     FftCtx &F = P->fft;
     const RadixPlan &rp = F.rp1;
@@ -943,17 +1001,10 @@ void x1_symbol(lddmm_plan *P, int op, int in0, int out0, int nbatch, int leray)
     int outer[2];
     col_descs(F, 0, dd, outer);
     for (int part = 0; part < 2; ++part) {
+        if (only_part >= 0 && part != only_part) continue;
         const ColDesc &d = dd[part];
-        size_t per;  // LDS bytes per tile element
-        switch (op) {
-        case SOP_GRAD: per = 2 * 16 + 3 * 8; break;
-        case SOP_DIV: per = 3 * 16; break;
-        case SOP_LERAY: per = 4 * 8; break;
-        case SOP_ASSEMBLE: per = 2 * 16 + 4 * 8; break;
-        case SOP_REG: per = 2 * 16; break;
-        default: per = 2 * 8; break;
-        }
-        const int TW = col_tile(L, per, d.ncols);
+        const size_t per = x1_bytes_per_elem(op);  // LDS bytes per tile element
+        const int TW = F.tw_x1[op][part];
         const size_t lds = per * L * TW;
         check_lds(lds, "x1_symbol");
         const int lt = ilog2(TW);
@@ -1036,6 +1087,152 @@ void spectral_apply(lddmm_plan *P, int op, const std::vector<const float *> &in,
             c2r_fields(P, fin + g0, cnt, ro, 1.0f);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: candidate tiles are the powers of two from the LDS-budget
+// maximum down to 1; each is timed with HIP events (one warm-up, three timed
+// launches) on the plan's own buffers and the fastest is kept.
+// ---------------------------------------------------------------------------
+template <class Fn>
+static float time_ms(lddmm_plan *P, Fn &&fn)
+{
+    hipEvent_t a, b;
+    check_hip(hipEventCreate(&a), "hipEventCreate");
+    check_hip(hipEventCreate(&b), "hipEventCreate");
+    fn();
+    check_hip(hipEventRecord(a, P->stream), "hipEventRecord");
+    for (int r = 0; r < 3; ++r) fn();
+    check_hip(hipEventRecord(b, P->stream), "hipEventRecord");
+    check_hip(hipEventSynchronize(b), "hipEventSynchronize");
+    float ms = 0.f;
+    check_hip(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms;
+}
+
+template <class Fn>
+static void tune_one(lddmm_plan *P, int &slot, Fn &&fn)
+{
+    const int top = slot;
+    int best = top;
+    float bt = 1e30f;
+    for (int t = top; t >= 1; t >>= 1) {
+        slot = t;
+        const float ms = time_ms(P, fn);
+        if (ms < bt) {
+            bt = ms;
+            best = t;
+        }
+    }
+    slot = best;
+}
+
+static std::vector<int *> tunables(FftCtx &F)
+{
+    std::vector<int *> v;
+    for (auto &a : F.tw_cols)
+        for (auto &p : a)
+            for (int &x : p) v.push_back(&x);
+    for (auto &o : F.tw_x1)
+        for (int &x : o) v.push_back(&x);
+    v.push_back(&F.twr_r2c[0]);
+    v.push_back(&F.twr_r2c[1]);
+    v.push_back(&F.twr_c2r);
+    return v;
+}
+
+static std::string tune_key(lddmm_plan *P)
+{
+    hipDeviceProp_t prop;
+    check_hip(hipGetDeviceProperties(&prop, P->device), "hipGetDeviceProperties");
+    const FftCtx &F = P->fft;
+    return std::string(prop.gcnArchName) + ":" + std::to_string(F.n1) + "x" + std::to_string(F.n2) +
+           "x" + std::to_string(F.n3);
+}
+
+static std::map<std::string, std::vector<int>> &tune_cache()
+{
+    static std::map<std::string, std::vector<int>> c;
+    return c;
+}
+
+static void load_cache_file()
+{
+    static bool loaded = false;
+    if (loaded) return;
+    loaded = true;
+    const char *path = std::getenv("LDDMM_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        std::istringstream ss(line);
+        std::string key;
+        if (!(ss >> key)) continue;
+        std::vector<int> vals;
+        int x;
+        while (ss >> x) vals.push_back(x);
+        tune_cache()[key] = vals;
+    }
+}
+
+void autotune_fft(lddmm_plan *P)
+{
+    FftCtx &F = P->fft;
+    load_cache_file();
+    const std::string key = tune_key(P);
+    std::vector<int *> tv = tunables(F);
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end() && it->second.size() == tv.size()) {
+        for (size_t i = 0; i < tv.size(); ++i) *tv[i] = it->second[i];
+        F.tuned = 1;
+        return;
+    }
+    const bool timing = P->timing.on;
+    P->timing.on = false;
+    const long N = P->N;
+    RealIn ri{};
+    for (int c = 0; c < 3; ++c) ri.p[c] = P->v + c * N;
+    RealOut ro{};
+    for (int c = 0; c < 3; ++c) ro.p[c] = P->b + c * N;
+    for (int dbl = 0; dbl < 2; ++dbl)
+        tune_one(P, F.twr_r2c[dbl], [&] { r2c_fields(P, ri, 3, 0, dbl != 0); });
+    tune_one(P, F.twr_c2r, [&] { c2r_fields(P, 0, 3, ro, 1.f); });
+    for (int axis = 0; axis < 2; ++axis)
+        for (int part = 0; part < 2; ++part)
+            for (int dbl = 0; dbl < 2; ++dbl)
+                tune_one(P, F.tw_cols[axis][part][dbl],
+                         [&] { cols_pass(P, axis == 1 ? 1 : 0, 0, 3, false, dbl != 0, part); });
+    const int ops[] = {SOP_GRAD, SOP_DIV, SOP_REG, SOP_INVREG, SOP_LERAY, SOP_ASSEMBLE};
+    for (int op : ops)
+        for (int part = 0; part < 2; ++part)
+            tune_one(P, F.tw_x1[op][part], [&] { x1_symbol_parts(P, op, 0, op_nin(op), 1, 1, part); });
+    P->timing.on = timing;
+    F.tuned = 1;
+    std::vector<int> vals;
+    for (int *p : tv) vals.push_back(*p);
+    tune_cache()[key] = vals;
+    if (const char *path = std::getenv("LDDMM_TUNE_CACHE")) {
+        std::ofstream out(path, std::ios::app);
+        out << key;
+        for (int x : vals) out << ' ' << x;
+        out << '\n';
+    }
+}
+
+std::string tuning_report(const lddmm_plan *P)
+{
+    const FftCtx &F = P->fft;
+    std::ostringstream o;
+    o << "tuned=" << F.tuned << " r2c_rows=" << F.twr_r2c[0] << "/" << F.twr_r2c[1]
+      << " c2r_rows=" << F.twr_c2r << " cols_x1=" << F.tw_cols[0][0][0] << "/" << F.tw_cols[0][0][1]
+      << " cols_x2=" << F.tw_cols[1][0][0] << "/" << F.tw_cols[1][0][1]
+      << " x1_grad=" << F.tw_x1[SOP_GRAD][0] << " x1_div=" << F.tw_x1[SOP_DIV][0]
+      << " x1_reg=" << F.tw_x1[SOP_REG][0] << " x1_invreg=" << F.tw_x1[SOP_INVREG][0]
+      << " x1_leray=" << F.tw_x1[SOP_LERAY][0] << " x1_assemble=" << F.tw_x1[SOP_ASSEMBLE][0];
+    return o.str();
 }
 
 void pack_standard(lddmm_plan *P, int slot, float2 *dst)

@@ -33,6 +33,12 @@ struct FftCtx {
     RadixPlan rp1{}, rp2{}, rp3{};
     float2 *tw1 = nullptr, *tw2 = nullptr, *tw3 = nullptr, *twN3 = nullptr;      // device tables
     double2 *tw1d = nullptr, *tw2d = nullptr, *tw3d = nullptr, *twN3d = nullptr;  // FP64 tables
+    // tile shapes (set from LDS-budget heuristics, refined by the autotuner)
+    int tw_cols[2][2][2] = {};  // [axis: 0 = x1, 1 = x2][part: main, Nyquist][FP64]
+    int tw_x1[8][2] = {};       // [spectral op][part]
+    int twr_r2c[2] = {};        // rows per block of the x3 R2C pass [FP64]
+    int twr_c2r = 0;            // rows per block of the x3 C2R pass
+    int tuned = 0;              // 1 once the autotuner has run
 };
 
 // LDS bytes one FFT workgroup may use
@@ -121,6 +127,11 @@ void spectral_apply(lddmm_plan *P, int op, const std::vector<const float *> &in,
                     const std::vector<float *> &out);
 int op_nin(int op);
 int op_nout(int op);
+// time the candidate tile shapes of every FFT kernel of the plan and keep
+// the fastest (results cached per device and shape for the process and, if
+// the environment names one, in a text file)
+void autotune_fft(lddmm_plan *P);
+std::string tuning_report(const lddmm_plan *P);
 // standard half-spectrum [n1][n2][n3/2+1] <-> internal layout
 void pack_standard(lddmm_plan *P, int spec_field, float2 *dst);
 void unpack_standard(lddmm_plan *P, const float2 *srcp, int spec_field);

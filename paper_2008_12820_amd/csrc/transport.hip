@@ -18,6 +18,23 @@ struct Grid3 {
     int N;
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b % 8), each with its own L2.  Renumber them so that each XCD sweeps
+// one contiguous eighth of the grid: neighbouring rows and planes, whose
+// 4x4x4 stencils overlap, then meet in the same L2.  A bijection on the
+// first 8*floor(nb/8) workgroups; the remainder keeps its numbers.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int per = nb >> 3;
+    if (b >= per * 8) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ int point_index()
+{
+    return xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
+}
+
 __device__ __forceinline__ void point_coords(const Grid3 &g, int p, int &i, int &j, int &k)
 {
     k = p % g.n3;
@@ -112,7 +129,7 @@ __global__ __launch_bounds__(kPtThreads) void k_departure(const float *__restric
                                                           float *__restrict__ dXa, Grid3 g, double dt,
                                                           double ih1, double ih2, double ih3)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = point_index();
     if (p >= g.N) return;
     int i, j, k;
     point_coords(g, p, i, j, k);
@@ -140,7 +157,7 @@ __global__ __launch_bounds__(kPtThreads) void k_interp(const float *__restrict__
                                                        const float *__restrict__ disp,
                                                        float *__restrict__ out, Grid3 g, int nf)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = point_index();
     if (p >= g.N) return;
     Stencil<float> s;
     load_stencil(g, p, disp, s);
@@ -154,7 +171,7 @@ __global__ __launch_bounds__(kPtThreads) void k_adj_coef(const float *__restrict
                                                          const float *__restrict__ dXa,
                                                          float *__restrict__ coef, Grid3 g, float dt)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = point_index();
     if (p >= g.N) return;
     Stencil<float> s;
     load_stencil(g, p, dXa, s);
@@ -168,7 +185,7 @@ __global__ __launch_bounds__(kPtThreads) void k_adj_step(const float *__restrict
                                                          const float *__restrict__ coef,
                                                          float *__restrict__ lout, Grid3 g, float scale)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = point_index();
     if (p >= g.N) return;
     Stencil<float> s;
     load_stencil(g, p, dXa, s);
@@ -186,7 +203,7 @@ __global__ __launch_bounds__(kPtThreads) void k_incstate_init(const float *__res
                                                               float *__restrict__ src, Grid3 g,
                                                               int nt, float dt)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = point_index();
     if (p >= g.N) return;
     Stencil<float> s;
     load_stencil(g, p, dX, s);
@@ -216,7 +233,7 @@ __global__ __launch_bounds__(kPtThreads) void k_incstate_step(const float *__res
                                                               float *__restrict__ mout, Grid3 g,
                                                               float dt)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = point_index();
     if (p >= g.N) return;
     Stencil<float> s;
     load_stencil(g, p, dX, s);
@@ -231,7 +248,7 @@ __global__ __launch_bounds__(kPtThreads) void k_body_force(const float *__restri
                                                            float *__restrict__ b, Grid3 g, int nt,
                                                            float dt)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = point_index();
     if (p >= g.N) return;
     const long N = g.N;
     float acc[3] = {0.f, 0.f, 0.f};

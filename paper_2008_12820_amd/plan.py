@@ -141,6 +141,13 @@ class Plan:
         L.lddmm_get_field(self._h, what, j, out)
         return out
 
+    def autotune(self):
+        L.lddmm_autotune(self._h)
+        return L.lddmm_tuning(self._h)
+
+    def tuning(self):
+        return L.lddmm_tuning(self._h)
+
     def set_timing(self, enable):
         L.lddmm_set_timing(self._h, enable)
 

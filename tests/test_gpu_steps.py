@@ -78,3 +78,19 @@ def test_velocity_state_matches_oracle(shape, nt):
         assert rel(to_np(P.get_field(L.FIELD_STATE, j)), ref.get("m", j)) < 1e-6
         assert rel(to_np(P.get_field(L.FIELD_GRAD_STATE, j)), ref.get("G", j)) < 1e-5
     assert rel(to_np(P.get_field(L.FIELD_DIV)), ref.get("delta")) < 1e-5
+
+
+def test_autotune_keeps_results_bitwise():
+    """Tile shapes only change how lines are grouped into workgroups, never
+    the arithmetic of a line: results before and after tuning are identical."""
+    shape = (48, 40, 36)
+    say("autotune")
+    rng = np.random.default_rng(9)
+    v = to_dev(rng.standard_normal((3,) + shape).astype(np.float32))
+    P = Plan(shape, 2, reg=2, beta=1e-3, leray=True)
+    before = [to_np(P.spectral_op(op, v)) for op in (OP_REG, OP_INVREG, OP_LERAY)]
+    rep = P.autotune()
+    assert "tuned=1" in rep
+    after = [to_np(P.spectral_op(op, v)) for op in (OP_REG, OP_INVREG, OP_LERAY)]
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
