@@ -299,6 +299,8 @@ def main():
     ap.add_argument("--cpu-sample", choices=["full", "half"], default="full")
     ap.add_argument("--batched", action="store_true", help="add the 64-member batched run")
     ap.add_argument("--autograd", action="store_true", help="add the 512^3 autograd run")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU's share only (the whole grid on one device); "
@@ -420,6 +422,18 @@ def main():
                       "transport": transport_rate(r8, 8),
                       "matvec_alg_hbm_frac": (136 + 132 * 8) * N / (ms8 * 1e-3) / 1e9 / PEAK_HBM_GBS,
                       "precompute_ms": 1e3 * r8["precompute_s"]}
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        src = torch.empty(1 << 28, device=dev, dtype=torch.float32).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                                   "GBps": 5 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9}
+        del src, dst
     if args.batched:
         out["batched"] = bench_batched(torch, dev)
     if args.autograd:

@@ -56,8 +56,9 @@ __device__ __forceinline__ void lagrange4(T t, T w[4])
 
 // Stencil of one axis: node offsets (already multiplied by the axis stride)
 // and weights for grid index i displaced by d voxels; periodic wrap.
+// Returns the first node index (in [0, n)).
 template <class T>
-__device__ __forceinline__ void axis_stencil(int i, T d, int n, int stride, int o[4], T w[4])
+__device__ __forceinline__ int axis_stencil(int i, T d, int n, unsigned stride, unsigned o[4], T w[4])
 {
     // clamp keeps the integer conversion defined for any input (NaN -> -lim);
     // the modulo below wraps every in-range displacement exactly
@@ -68,17 +69,20 @@ __device__ __forceinline__ void axis_stencil(int i, T d, int n, int stride, int 
     int b = i + (int)fl - 1;
     b %= n;
     if (b < 0) b += n;
+    const int first = b;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        o[q] = b * stride;
+        o[q] = (unsigned)b * stride;
         b = (b + 1 == n) ? 0 : b + 1;
     }
     lagrange4<T>(d - fl, w);
+    return first;
 }
 
 template <class T>
 struct Stencil {
-    int o1[4], o2[4], o3[4];
+    unsigned o1[4], o2[4], o3[4];  // element offsets of the nodes along x1, x2, x3
+    bool contig;                   // x3 nodes consecutive in memory (no wrap)
     T w1[4], w2[4], w3[4];
 };
 
@@ -86,27 +90,45 @@ template <class T>
 __device__ __forceinline__ void make_stencil(const Grid3 &g, int i, int j, int k, T d1, T d2, T d3,
                                              Stencil<T> &s)
 {
-    axis_stencil<T>(i, d1, g.n1, g.n2 * g.n3, s.o1, s.w1);
-    axis_stencil<T>(j, d2, g.n2, g.n3, s.o2, s.w2);
-    axis_stencil<T>(k, d3, g.n3, 1, s.o3, s.w3);
+    axis_stencil<T>(i, d1, g.n1, (unsigned)g.n2 * (unsigned)g.n3, s.o1, s.w1);
+    axis_stencil<T>(j, d2, g.n2, (unsigned)g.n3, s.o2, s.w2);
+    const int b3 = axis_stencil<T>(k, d3, g.n3, 1u, s.o3, s.w3);
+    s.contig = b3 + 3 < g.n3;
 }
 
-// separable evaluation of the tensor-product sum
+// Separable evaluation of the tensor-product sum.  When the four x3 nodes
+// are contiguous (no periodic wrap) their loads come from one row pointer
+// and merge into one 16-byte load; both branches add in the same order.
 template <class T>
 __device__ __forceinline__ T gather(const float *__restrict__ f, const Stencil<T> &s)
 {
     T acc = T(0);
+    if (s.contig) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        T acc2 = T(0);
+        for (int a = 0; a < 4; ++a) {
+            T acc2 = T(0);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const float *row = f + s.o1[a] + s.o2[b];
-            const T r = (T)row[s.o3[0]] * s.w3[0] + (T)row[s.o3[1]] * s.w3[1] +
-                        (T)row[s.o3[2]] * s.w3[2] + (T)row[s.o3[3]] * s.w3[3];
-            acc2 += s.w2[b] * r;
+            for (int b = 0; b < 4; ++b) {
+                const float *row = f + (s.o1[a] + s.o2[b] + s.o3[0]);
+                const T r = (T)row[0] * s.w3[0] + (T)row[1] * s.w3[1] + (T)row[2] * s.w3[2] +
+                            (T)row[3] * s.w3[3];
+                acc2 += s.w2[b] * r;
+            }
+            acc += s.w1[a] * acc2;
         }
-        acc += s.w1[a] * acc2;
+    } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            T acc2 = T(0);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const float *row = f + (s.o1[a] + s.o2[b]);
+                const T r = (T)row[s.o3[0]] * s.w3[0] + (T)row[s.o3[1]] * s.w3[1] +
+                            (T)row[s.o3[2]] * s.w3[2] + (T)row[s.o3[3]] * s.w3[3];
+                acc2 += s.w2[b] * r;
+            }
+            acc += s.w1[a] * acc2;
+        }
     }
     return acc;
 }
@@ -161,6 +183,7 @@ __global__ __launch_bounds__(kPtThreads) void k_interp(const float *__restrict__
     if (p >= g.N) return;
     Stencil<float> s;
     load_stencil(g, p, disp, s);
+#pragma unroll 1
     for (int f = 0; f < nf; ++f) out[(long)f * g.N + p] = gather<float>(in + (long)f * g.N, s);
 }
 
