@@ -138,7 +138,7 @@ __device__ __forceinline__ void load_stencil(const Grid3 &g, int p, const float 
 {
     int i, j, k;
     point_coords(g, p, i, j, k);
-    make_stencil<float>(g, i, j, k, disp[p], disp[g.N + p], disp[2 * g.N + p], s);
+    make_stencil<float>(g, i, j, k, disp[p], disp[(long)g.N + p], disp[2L * g.N + p], s);
 }
 
 // ---------------------------------------------------------------------------
