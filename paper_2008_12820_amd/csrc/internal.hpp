@@ -80,10 +80,12 @@ struct lddmm_plan {
     long slot_bytes = 0;
     int nspec = 0;
     double *red = nullptr;   // reduction partials
+    int *tile_flags = nullptr;  // per gather tile: 1 when its LDS box did not fit
     double *dscal = nullptr; // device scalars
     double *hscal = nullptr; // pinned host mirror
 
     int have_images = 0, have_velocity = 0, have_grad = 0, have_matvec = 0;
+    int tile_big = -1;       // gather tile shape: -1 heuristic, 0 4x4x64, 1 8x8x64
     double g0norm = 0.0;
     lddmm::PlanTiming timing;
 };

@@ -133,14 +133,6 @@ __device__ __forceinline__ T gather(const float *__restrict__ f, const Stencil<T
     return acc;
 }
 
-__device__ __forceinline__ void load_stencil(const Grid3 &g, int p, const float *__restrict__ disp,
-                                             Stencil<float> &s)
-{
-    int i, j, k;
-    point_coords(g, p, i, j, k);
-    make_stencil<float>(g, i, j, k, disp[p], disp[(long)g.N + p], disp[2L * g.N + p], s);
-}
-
 // ---------------------------------------------------------------------------
 // departure points, FP64:  X = x - dt/2 (v(x) + I[v](x - dt v(x)))
 //                          Xa = x + dt/2 (v(x) + I[v](x + dt v(x)))
@@ -174,95 +166,6 @@ __global__ __launch_bounds__(kPtThreads) void k_departure(const float *__restric
     }
 }
 
-// out[f][p] = I[in[f]](x_p + h disp_p) for nf fields (field stride N)
-__global__ __launch_bounds__(kPtThreads) void k_interp(const float *__restrict__ in,
-                                                       const float *__restrict__ disp,
-                                                       float *__restrict__ out, Grid3 g, int nf)
-{
-    const int p = point_index();
-    if (p >= g.N) return;
-    Stencil<float> s;
-    load_stencil(g, p, disp, s);
-#pragma unroll 1
-    for (int f = 0; f < nf; ++f) out[(long)f * g.N + p] = gather<float>(in + (long)f * g.N, s);
-}
-
-// adjoint reaction coefficient: one Heun step of d lam/ds = lam div v along
-// the adjoint characteristic gives lam_j = c * I[lam_{j+1}](Xa) with
-// c = 1 + dt/2 (delta_a + delta (1 + dt delta_a)), delta_a = I[delta](Xa)
-__global__ __launch_bounds__(kPtThreads) void k_adj_coef(const float *__restrict__ delta,
-                                                         const float *__restrict__ dXa,
-                                                         float *__restrict__ coef, Grid3 g, float dt)
-{
-    const int p = point_index();
-    if (p >= g.N) return;
-    Stencil<float> s;
-    load_stencil(g, p, dXa, s);
-    const float da = gather<float>(delta, s);
-    coef[p] = 1.f + 0.5f * dt * (da + delta[p] * (1.f + dt * da));
-}
-
-// lam_out = scale * c * I[lam_in](Xa)
-__global__ __launch_bounds__(kPtThreads) void k_adj_step(const float *__restrict__ lin,
-                                                         const float *__restrict__ dXa,
-                                                         const float *__restrict__ coef,
-                                                         float *__restrict__ lout, Grid3 g, float scale)
-{
-    const int p = point_index();
-    if (p >= g.N) return;
-    Stencil<float> s;
-    load_stencil(g, p, dXa, s);
-    lout[p] = scale * coef[p] * gather<float>(lin, s);
-}
-
-// Incremental state, first step and all sources (eq. incsta along X):
-//   vX = I[v~](X),  s_j = vX . I[G_j](X) + v~ . G_{j+1}   (j = 0..nt-1)
-//   m~_1 = -dt/2 s_0;  s_1..s_{nt-1} stored for the later steps
-__global__ __launch_bounds__(kPtThreads) void k_incstate_init(const float *__restrict__ vt,
-                                                              const float *__restrict__ dX,
-                                                              const float *__restrict__ GX,
-                                                              const float *__restrict__ G,
-                                                              float *__restrict__ mt1,
-                                                              float *__restrict__ src, Grid3 g,
-                                                              int nt, float dt)
-{
-    const int p = point_index();
-    if (p >= g.N) return;
-    Stencil<float> s;
-    load_stencil(g, p, dX, s);
-    const long N = g.N;
-    float vX[3], vp[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        vX[c] = gather<float>(vt + c * N, s);
-        vp[c] = vt[c * N + p];
-    }
-    for (int j = 0; j < nt; ++j) {
-        const float *gx = GX + (long)j * 3 * N;
-        const float *g1 = G + (long)(j + 1) * 3 * N;
-        const float a = vX[0] * gx[p] + vX[1] * gx[N + p] + vX[2] * gx[2 * N + p];
-        const float b = vp[0] * g1[p] + vp[1] * g1[N + p] + vp[2] * g1[2 * N + p];
-        if (j == 0)
-            mt1[p] = -0.5f * dt * (a + b);
-        else
-            src[(long)(j - 1) * N + p] = a + b;
-    }
-}
-
-// m~_{j+1} = I[m~_j](X) - dt/2 s_j
-__global__ __launch_bounds__(kPtThreads) void k_incstate_step(const float *__restrict__ min,
-                                                              const float *__restrict__ dX,
-                                                              const float *__restrict__ s_j,
-                                                              float *__restrict__ mout, Grid3 g,
-                                                              float dt)
-{
-    const int p = point_index();
-    if (p >= g.N) return;
-    Stencil<float> s;
-    load_stencil(g, p, dX, s);
-    mout[p] = gather<float>(min, s) - 0.5f * dt * s_j[p];
-}
-
 // b = dt * sum_j w_j lam_j G_j (trapezoid, w_0 = w_nt = 1/2); lam_nt is read
 // from lamN times scaleN, lam_0..lam_{nt-1} from lam.
 __global__ __launch_bounds__(kPtThreads) void k_body_force(const float *__restrict__ lam,
@@ -287,6 +190,246 @@ __global__ __launch_bounds__(kPtThreads) void k_body_force(const float *__restri
 }
 
 // ---------------------------------------------------------------------------
+// LDS-tiled gathers.  A workgroup of NW wavefronts owns an output tile of
+// T1 x T2 x 64 points (x3 fastest, one wavefront per x3 row segment).  It
+// reduces the stencil extents of its points to one box, stages that box of
+// the source field (periodically wrapped) in LDS with coalesced row loads,
+// and interpolates from LDS, where the nodes never wrap.  A tile whose box
+// does not fit the LDS capacity (a displacement far beyond the halo) is
+// flagged and finished by a second launch with direct global gathers; the
+// decision is per workgroup and on the device.  Both paths add in the same
+// order.
+// ---------------------------------------------------------------------------
+constexpr int kT3 = 64;   // tile extent along x3
+constexpr int kHalo = 4;  // LDS box sized for stencils reaching this far past the tile
+
+template <int T1, int T2>
+struct TileCfg {
+    static constexpr int NW = (T1 * T2 >= 64) ? 8 : 4;  // wavefronts per workgroup
+    static constexpr int PTS = T1 * T2 / NW;            // points per thread
+    static constexpr int NP = T1 * T2 * kT3;            // points per tile
+    static constexpr int CAP = (T1 + 2 * kHalo) * (T2 + 2 * kHalo) * (kT3 + 2 * kHalo);  // box floats
+    // LDS floats: box, the three displacement components and nf-1 partial fields
+    static constexpr int lds_floats(int nf) { return CAP + (3 + nf - 1) * NP; }
+};
+
+__device__ __forceinline__ int wrap1(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+
+__device__ __forceinline__ float clamp_disp(float d)
+{
+    const float lim = 1048576.f;
+    d = d > lim ? lim : d;
+    return d >= -lim ? d : -lim;
+}
+
+// epilogues: which fields are gathered and what is written per point
+struct EpiCopy {  // out = I[src]
+    static constexpr int NF = 1;
+    const float *src;
+    float *dst;
+    __device__ const float *field(int) const { return src; }
+    __device__ void finish(long p, const float *v) const { dst[p] = v[0]; }
+};
+struct EpiAdj {  // out = scale * c * I[src]
+    static constexpr int NF = 1;
+    const float *src, *coef;
+    float *dst;
+    float scale;
+    __device__ const float *field(int) const { return src; }
+    __device__ void finish(long p, const float *v) const { dst[p] = scale * coef[p] * v[0]; }
+};
+struct EpiInc {  // out = I[src] - dt/2 s
+    static constexpr int NF = 1;
+    const float *src, *s;
+    float *dst;
+    float hdt;
+    __device__ const float *field(int) const { return src; }
+    __device__ void finish(long p, const float *v) const { dst[p] = v[0] - hdt * s[p]; }
+};
+struct EpiAdjCoef {  // c = 1 + dt/2 (delta_a + delta (1 + dt delta_a)), delta_a = I[delta](Xa)
+    static constexpr int NF = 1;
+    const float *delta;
+    float *coef;
+    float dt;
+    __device__ const float *field(int) const { return delta; }
+    __device__ void finish(long p, const float *v) const
+    {
+        const float da = v[0];
+        coef[p] = 1.f + 0.5f * dt * (da + delta[p] * (1.f + dt * da));
+    }
+};
+struct EpiVec3 {  // three fields (stride N): out_c = I[src_c]
+    static constexpr int NF = 3;
+    const float *src;
+    float *dst;
+    long N;
+    __device__ const float *field(int f) const { return src + f * N; }
+    __device__ void finish(long p, const float *v) const
+    {
+        dst[p] = v[0];
+        dst[N + p] = v[1];
+        dst[2 * N + p] = v[2];
+    }
+};
+struct EpiIncInit {  // incremental-state sources (see k_incstate_init)
+    static constexpr int NF = 3;
+    const float *vt, *GX, *G;
+    float *mt1, *src;
+    long N;
+    int nt;
+    float dt;
+    __device__ const float *field(int f) const { return vt + f * N; }
+    __device__ void finish(long p, const float *vX) const
+    {
+        const float vp0 = vt[p], vp1 = vt[N + p], vp2 = vt[2 * N + p];
+        for (int j = 0; j < nt; ++j) {
+            const float *gx = GX + (long)j * 3 * N;
+            const float *g1 = G + (long)(j + 1) * 3 * N;
+            const float a = vX[0] * gx[p] + vX[1] * gx[N + p] + vX[2] * gx[2 * N + p];
+            const float b = vp0 * g1[p] + vp1 * g1[N + p] + vp2 * g1[2 * N + p];
+            if (j == 0)
+                mt1[p] = -0.5f * dt * (a + b);
+            else
+                src[(long)(j - 1) * N + p] = a + b;
+        }
+    }
+};
+
+// Tiles whose box does not fit are finished by a second launch with direct
+// global gathers; the tiled kernel leaves a flag per tile for it.
+template <int T1, int T2, class Epi>
+__global__ __launch_bounds__((64 * TileCfg<T1, T2>::NW)) void k_tiled_fixup(Grid3 g,
+                                                                             const float *__restrict__ disp,
+                                                                             Epi epi, int nt1, int nt2, int nt3,
+                                                                             const int *__restrict__ flags)
+{
+    using TC = TileCfg<T1, T2>;
+    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    if (flags[tb] == 0) return;
+    const int grp = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int t3 = tb % nt3, rr = tb / nt3, t2 = rr % nt2, t1 = rr / nt2;
+    const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
+    const long N = g.N;
+    for (int q = 0; q < TC::PTS; ++q) {
+        const int idx = grp + TC::NW * q, i = i0 + idx / T2, j = j0 + idx % T2;
+        if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
+        const long p = ((long)i * g.n2 + j) * g.n3 + k;
+        Stencil<float> s;
+        make_stencil<float>(g, i, j, k, disp[p], disp[N + p], disp[2 * N + p], s);
+        float v[Epi::NF];
+#pragma unroll
+        for (int f = 0; f < Epi::NF; ++f) v[f] = gather<float>(epi.field(f), s);
+        epi.finish(p, v);
+    }
+}
+
+template <int T1, int T2, class Epi>
+__global__ __launch_bounds__((64 * TileCfg<T1, T2>::NW)) void k_tiled(Grid3 g, const float *__restrict__ disp,
+                                                                       Epi epi, int nt1, int nt2, int nt3,
+                                                                       int *__restrict__ flags)
+{
+    using TC = TileCfg<T1, T2>;
+    constexpr int PTS = TC::PTS, NW = TC::NW, NP = TC::NP, NF = Epi::NF;
+    extern __shared__ float lds[];
+    float *box = lds;                 // CAP
+    float *dsh = lds + TC::CAP;       // 3 x NP displacements of the tile's points
+    float *vsh = dsh + 3 * NP;        // (NF-1) x NP gathered values of the earlier fields
+    __shared__ int ext[6];
+    const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int t3 = tb % nt3, rr = tb / nt3, t2 = rr % nt2, t1 = rr / nt2;
+    const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
+    const long N = g.N;
+    if (tid < 6) ext[tid] = tid < 3 ? 0x7fffffff : (int)0x80000000;
+    __syncthreads();
+    // tile entry e = grp + NW q (q < PTS) is point (i0 + e / T2, j0 + e % T2, k);
+    // its LDS slot is e * 64 + lane
+    int lo1 = 0x7fffffff, lo2 = 0x7fffffff, lo3 = 0x7fffffff;
+    int hi1 = (int)0x80000000, hi2 = (int)0x80000000, hi3 = (int)0x80000000;
+#pragma unroll
+    for (int q = 0; q < PTS; ++q) {
+        const int e = grp + NW * q, i = i0 + e / T2, j = j0 + e % T2, slot = e * 64 + lane;
+        float d1 = 0.f, d2 = 0.f, d3 = 0.f;
+        if (i < g.n1 && j < g.n2 && k < g.n3) {
+            const long p = ((long)i * g.n2 + j) * g.n3 + k;
+            d1 = clamp_disp(disp[p]);
+            d2 = clamp_disp(disp[N + p]);
+            d3 = clamp_disp(disp[2 * N + p]);
+            const int b1 = i + (int)floorf(d1) - 1, b2 = j + (int)floorf(d2) - 1, b3 = k + (int)floorf(d3) - 1;
+            lo1 = min(lo1, b1);
+            hi1 = max(hi1, b1 + 3);
+            lo2 = min(lo2, b2);
+            hi2 = max(hi2, b2 + 3);
+            lo3 = min(lo3, b3);
+            hi3 = max(hi3, b3 + 3);
+        }
+        dsh[slot] = d1;
+        dsh[NP + slot] = d2;
+        dsh[2 * NP + slot] = d3;
+    }
+    atomicMin(&ext[0], lo1);
+    atomicMin(&ext[1], lo2);
+    atomicMin(&ext[2], lo3);
+    atomicMax(&ext[3], hi1);
+    atomicMax(&ext[4], hi2);
+    atomicMax(&ext[5], hi3);
+    __syncthreads();
+    const int L1 = ext[0], L2 = ext[1], L3 = ext[2];
+    const int B1 = ext[3] - L1 + 1, B2 = ext[4] - L2 + 1, B3 = ext[5] - L3 + 1;
+    // the box may be wider than the grid (periodic copies repeat); wrap1 needs [-n, 2n)
+    const bool fits = ext[3] >= L1 && (long)B1 * B2 * B3 <= TC::CAP && L1 >= -g.n1 && L2 >= -g.n2 &&
+                      L3 >= -g.n3 && ext[3] < 2 * g.n1 && ext[4] < 2 * g.n2 && ext[5] < 2 * g.n3;
+    if (tid == 0) flags[tb] = fits ? 0 : 1;
+    if (!fits) return;  // uniform over the workgroup; finished by k_tiled_fixup
+    const int S2 = B3, S1 = B2 * B3;  // box strides
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const float *__restrict__ src = epi.field(f);
+        const int rows = B1 * B2;
+        for (int row = grp; row < rows; row += NW) {
+            const int a = row / B2, b = row - a * B2;
+            const float *grow = src + ((long)wrap1(L1 + a, g.n1) * g.n2 + wrap1(L2 + b, g.n2)) * g.n3;
+            for (int c = lane; c < B3; c += 64) box[row * B3 + c] = grow[wrap1(L3 + c, g.n3)];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int q = 0; q < PTS; ++q) {
+            const int e = grp + NW * q, i = i0 + e / T2, j = j0 + e % T2, slot = e * 64 + lane;
+            if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
+            const float d1 = dsh[slot], d2 = dsh[NP + slot], d3 = dsh[2 * NP + slot];
+            const float f1 = floorf(d1), f2 = floorf(d2), f3 = floorf(d3);
+            float w1[4], w2[4], w3[4];
+            lagrange4<float>(d1 - f1, w1);
+            lagrange4<float>(d2 - f2, w2);
+            lagrange4<float>(d3 - f3, w3);
+            const int o = (i + (int)f1 - 1 - L1) * S1 + (j + (int)f2 - 1 - L2) * S2 + (k + (int)f3 - 1 - L3);
+            float acc = 0.f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                float acc2 = 0.f;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const float *row = box + o + a * S1 + b * S2;
+                    const float r = row[0] * w3[0] + row[1] * w3[1] + row[2] * w3[2] + row[3] * w3[3];
+                    acc2 += w2[b] * r;
+                }
+                acc += w1[a] * acc2;
+            }
+            if (f < NF - 1) {
+                vsh[f * NP + slot] = acc;
+            } else {
+                float v[NF];
+#pragma unroll
+                for (int u = 0; u < NF - 1; ++u) v[u] = vsh[u * NP + slot];
+                v[NF - 1] = acc;
+                epi.finish(((long)i * g.n2 + j) * g.n3 + k, v);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 static Grid3 grid_of(const lddmm_plan *P)
@@ -307,44 +450,73 @@ void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa)
     check_hip(hipGetLastError(), "k_departure");
 }
 
+// tile shape: 8 x 8 x 64 on large grids, 4 x 4 x 64 when that leaves too few
+// workgroups to fill the chip
+static bool big_tiles(const lddmm_plan *P)
+{
+    const long n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
+    const long tiles8 = ((n1 + 7) / 8) * ((n2 + 7) / 8) * ((n3 + kT3 - 1) / kT3);
+    return P->tile_big >= 0 ? P->tile_big != 0 : tiles8 >= 2048;
+}
+
+template <int T1, int T2, class Epi>
+static void launch_tiled(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
+{
+    const int n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
+    const int nt1 = (n1 + T1 - 1) / T1, nt2 = (n2 + T2 - 1) / T2, nt3 = (n3 + kT3 - 1) / kT3;
+    const size_t lds = sizeof(float) * TileCfg<T1, T2>::lds_floats(Epi::NF);
+    static bool attr = false;
+    if (!attr) {
+        check_hip(hipFuncSetAttribute((const void *)k_tiled<T1, T2, Epi>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                  "hipFuncSetAttribute");
+        attr = true;
+    }
+    const unsigned ntiles = (unsigned)((long)nt1 * nt2 * nt3);
+    Scope s(P, kid);
+    hipLaunchKernelGGL((k_tiled<T1, T2, Epi>), dim3(ntiles), dim3(64 * TileCfg<T1, T2>::NW), lds, P->stream,
+                       grid_of(P), disp, epi, nt1, nt2, nt3, P->tile_flags);
+    check_hip(hipGetLastError(), "k_tiled");
+    hipLaunchKernelGGL((k_tiled_fixup<T1, T2, Epi>), dim3(ntiles), dim3(64 * TileCfg<T1, T2>::NW), 0,
+                       P->stream, grid_of(P), disp, epi, nt1, nt2, nt3, (const int *)P->tile_flags);
+    check_hip(hipGetLastError(), "k_tiled_fixup");
+}
+
+template <class Epi>
+static void tiled(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
+{
+    if (big_tiles(P))
+        launch_tiled<8, 8>(P, disp, epi, kid);
+    else
+        launch_tiled<4, 4>(P, disp, epi, kid);
+}
+
 void launch_interp(lddmm_plan *P, int nf, const float *fields, const float *disp, float *out, int kid)
 {
-    Scope s(P, kid);
-    hipLaunchKernelGGL(k_interp, blocks_of(P), dim3(kPtThreads), 0, P->stream, fields, disp, out,
-                       grid_of(P), nf);
-    check_hip(hipGetLastError(), "k_interp");
+    const long N = P->N;
+    int f = 0;
+    for (; f + 3 <= nf; f += 3) tiled(P, disp, EpiVec3{fields + f * N, out + f * N, N}, kid);
+    for (; f < nf; ++f) tiled(P, disp, EpiCopy{fields + f * N, out + f * N}, kid);
 }
 
 void launch_adj_coef(lddmm_plan *P)
 {
-    Scope s(P, K_ADJ_COEF);
-    hipLaunchKernelGGL(k_adj_coef, blocks_of(P), dim3(kPtThreads), 0, P->stream, P->delta, P->dXa,
-                       P->coef, grid_of(P), (float)P->dt);
-    check_hip(hipGetLastError(), "k_adj_coef");
+    tiled(P, P->dXa, EpiAdjCoef{P->delta, P->coef, (float)P->dt}, K_ADJ_COEF);
 }
 
 void launch_adj_step(lddmm_plan *P, const float *lin, float *lout, float scale)
 {
-    Scope s(P, K_ADJ_STEP);
-    hipLaunchKernelGGL(k_adj_step, blocks_of(P), dim3(kPtThreads), 0, P->stream, lin, P->dXa,
-                       P->coef, lout, grid_of(P), scale);
-    check_hip(hipGetLastError(), "k_adj_step");
+    tiled(P, P->dXa, EpiAdj{lin, P->coef, lout, scale}, K_ADJ_STEP);
 }
 
 void launch_incstate_init(lddmm_plan *P, const float *vt, float *mt1)
 {
-    Scope s(P, K_INCSTATE_INIT);
-    hipLaunchKernelGGL(k_incstate_init, blocks_of(P), dim3(kPtThreads), 0, P->stream, vt, P->dX,
-                       P->GX, P->G, mt1, P->src, grid_of(P), P->nt, (float)P->dt);
-    check_hip(hipGetLastError(), "k_incstate_init");
+    tiled(P, P->dX, EpiIncInit{vt, P->GX, P->G, mt1, P->src, P->N, P->nt, (float)P->dt}, K_INCSTATE_INIT);
 }
 
 void launch_incstate_step(lddmm_plan *P, const float *min, const float *sj, float *mout)
 {
-    Scope s(P, K_INCSTATE_STEP);
-    hipLaunchKernelGGL(k_incstate_step, blocks_of(P), dim3(kPtThreads), 0, P->stream, min, P->dX,
-                       sj, mout, grid_of(P), (float)P->dt);
-    check_hip(hipGetLastError(), "k_incstate_step");
+    tiled(P, P->dX, EpiInc{min, sj, mout, 0.5f * (float)P->dt}, K_INCSTATE_STEP);
 }
 
 void launch_body_force(lddmm_plan *P, const float *lam, const float *lamN, float scaleN,
