@@ -333,6 +333,8 @@ def main():
         plan.set_velocity(vd)
         torch.cuda.synchronize()
         pre = time.perf_counter() - t0
+        tuning = plan.autotune()  # gather strategy, timed on this velocity's displacements
+        log(f"autotuned: {tuning}")
         t0 = time.perf_counter()
         g, gn = plan.gradient()
         torch.cuda.synchronize()

@@ -83,6 +83,7 @@ def lib():
             "lddmm_batch_set_velocity": (st, [p, P(p)]),
             "lddmm_batch_gn_iterate": (st, [p, i32, d, i32, P(p), P(NewtonInfo)]),
             "lddmm_autotune": (st, [p]),
+            "lddmm_set_gather_mode": (st, [p, i32]),
             "lddmm_tuning": (st, [p, ctypes.c_char_p, sz]),
             "lddmm_set_timing": (st, [p, i32]),
             "lddmm_get_timing": (st, [p, i32, P(d), P(ctypes.c_int64)]),
@@ -271,6 +272,10 @@ def lddmm_batch_gn_iterate(batch, max_pcg, rtol, use_graph, vs):
 
 def lddmm_autotune(plan):
     _check(lib().lddmm_autotune(plan), "autotune")
+
+
+def lddmm_set_gather_mode(plan, mode):
+    _check(lib().lddmm_set_gather_mode(plan, int(mode)), "set_gather_mode")
 
 
 def lddmm_tuning(plan):

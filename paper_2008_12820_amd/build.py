@@ -10,7 +10,7 @@ LIB = os.path.join(HERE, "liblddmm.so")
 SOURCES = ["api.hip", "fft.hip", "transport.hip", "linalg.hip", "batch.hip"]
 ARCH = "gfx950"
 
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-ffp-contract=fast", "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
          "-I" + os.path.join(HERE, "..", "include")]

@@ -870,6 +870,8 @@ lddmm_status lddmm_autotune(lddmm_plan *P)
         need(P, "plan");
         check_hip(hipStreamSynchronize(P->stream), "stream sync");
         autotune_fft(P);
+        // the gather strategy is timed on the real displacement field
+        if (P->have_velocity) autotune_gather(P);
     });
 }
 
@@ -878,11 +880,21 @@ lddmm_status lddmm_tuning(lddmm_plan *P, char *buf, size_t len)
     return guard([&] {
         need(P, "plan");
         need(buf, "buf");
-        const std::string r = tuning_report(P);
+        const std::string r = tuning_report(P) + " gather_mode=" + std::to_string(P->gather_mode) +
+                              (P->gather_tuned ? " (tuned)" : "");
         if (len == 0) fail(LDDMM_EINVAL, "len is 0");
         const size_t n = std::min(len - 1, r.size());
         std::memcpy(buf, r.data(), n);
         buf[n] = 0;
+    });
+}
+
+lddmm_status lddmm_set_gather_mode(lddmm_plan *P, int32_t mode)
+{
+    return guard([&] {
+        need(P, "plan");
+        if (mode < -1 || mode > 2) fail(LDDMM_EINVAL, "mode must be -1, 0, 1 or 2");
+        P->gather_mode = mode;
     });
 }
 

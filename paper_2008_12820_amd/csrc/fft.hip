@@ -239,6 +239,98 @@ __device__ C *lds_fft(C *A, C *B, int TW, int logTW, int LP, const RadixPlan &rp
     return s;
 }
 
+// Compile-time line lengths: the same greedy radix sequence as
+// make_radix_plan, with every pass's stride, butterfly count and twiddle
+// step known at compile time (no runtime integer division in the index math).
+__host__ __device__ constexpr int next_radix(int n)
+{
+    return n % 8 == 0 ? 8 : (n % 4 == 0 ? 4 : (n % 2 == 0 ? 2 : (n % 3 == 0 ? 3 : 5)));
+}
+
+template <int R, int L, int Ns, class C, bool INV, bool CFAST>
+__device__ __forceinline__ void stockham_pass_fixed(const C *__restrict__ src, C *__restrict__ dst, int TW,
+                                                    int logTW, int LP, const C *__restrict__ tw, int tid,
+                                                    int nthr)
+{
+    constexpr int LR = L / R;
+    constexpr int step = L / (Ns * R);
+    const int nb = LR * TW;
+    for (int b = tid; b < nb; b += nthr) {
+        int j, c;
+        if (CFAST) {
+            c = b & (TW - 1);
+            j = b >> logTW;
+        } else {
+            j = b % LR;
+            c = b / LR;
+        }
+        const int jm = j % Ns;
+        C v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int n = j + r * LR;
+            v[r] = src[CFAST ? (n * TW + c) : (c * LP + n)];
+        }
+        if (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const C w = tw[jm * r * step];
+                v[r] = INV ? mulc(v[r], w) : mul(v[r], w);
+            }
+        }
+        dft_small<R, C, INV>(v);
+        const int idxD = (j - jm) * R + jm;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int n = idxD + r * Ns;
+            dst[CFAST ? (n * TW + c) : (c * LP + n)] = v[r];
+        }
+    }
+}
+
+template <bool INV, bool CFAST, class C, int L, int Ns = 1>
+__device__ __forceinline__ C *lds_fft_fixed(C *s, C *d, int TW, int logTW, int LP, const C *__restrict__ tw,
+                                            int tid, int nthr)
+{
+    if constexpr (Ns == L) {
+        return s;
+    } else {
+        constexpr int R = next_radix(L / Ns);
+        stockham_pass_fixed<R, L, Ns, C, INV, CFAST>(s, d, TW, logTW, LP, tw, tid, nthr);
+        __syncthreads();
+        return lds_fft_fixed<INV, CFAST, C, L, Ns * R>(d, s, TW, logTW, LP, tw, tid, nthr);
+    }
+}
+
+// LF > 0: compile-time length LF; LF = 0: the runtime plan
+template <bool INV, bool CFAST, int LF, class C>
+__device__ __forceinline__ C *lds_fft_any(C *A, C *B, int TW, int logTW, int LP, const RadixPlan &rp,
+                                          const C *__restrict__ tw, int tid, int nthr)
+{
+    if constexpr (LF > 0)
+        return lds_fft_fixed<INV, CFAST, C, LF>(A, B, TW, logTW, LP, tw, tid, nthr);
+    else
+        return lds_fft<INV, CFAST, C>(A, B, TW, logTW, LP, rp, tw, tid, nthr);
+}
+
+// runs fn.template operator()<LF>() with LF = L for the compiled lengths, else 0
+template <class Fn>
+static void with_len(int L, Fn &&fn)
+{
+    switch (L) {
+    case 32: fn.template operator()<32>(); break;
+    case 48: fn.template operator()<48>(); break;
+    case 64: fn.template operator()<64>(); break;
+    case 80: fn.template operator()<80>(); break;
+    case 96: fn.template operator()<96>(); break;
+    case 128: fn.template operator()<128>(); break;
+    case 160: fn.template operator()<160>(); break;
+    case 256: fn.template operator()<256>(); break;
+    case 512: fn.template operator()<512>(); break;
+    default: fn.template operator()<0>(); break;
+    }
+}
+
 // first buffer to load into so that a forward transform ends in `home`
 template <class C>
 __device__ __forceinline__ C *load_target(const RadixPlan &rp, C *home, C *other)
@@ -251,9 +343,9 @@ constexpr int kFftThreads = 256;
 // ---------------------------------------------------------------------------
 // x3 pass: real rows -> half spectrum (main + Nyquist plane), computed in R
 // ---------------------------------------------------------------------------
-template <class R>
+template <class R, int LF>
 __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, char *__restrict__ spec,
-                                                        long slot_bytes, int slot0, long nrow, int n3,
+                                                        long slot_bytes, int slot0, long nrow, int n3_rt,
                                                         int TWR, RadixPlan rp,
                                                         const typename CplxOf<R>::type *__restrict__ tw_m3,
                                                         const typename CplxOf<R>::type *__restrict__ tw_n3)
@@ -261,6 +353,7 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, char *__restr
     using C = typename CplxOf<R>::type;
     extern __shared__ char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
+    const int n3 = LF > 0 ? 2 * LF : n3_rt;
     const int m3 = n3 >> 1, LP = m3 + 1;
     C *A = lds, *B = lds + TWR * LP;
     const int f = blockIdx.y;
@@ -274,7 +367,7 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, char *__restr
         Af[(c * LP + (x >> 1)) * 2 + (x & 1)] = row < nrow ? (R)src[row * n3 + x] : R(0);
     }
     __syncthreads();
-    const C *Z = lds_fft<false, false, C>(A, B, TWR, 0, LP, rp, tw_m3, tid, nthr);
+    const C *Z = lds_fft_any<false, false, LF>(A, B, TWR, 0, LP, rp, tw_m3, tid, nthr);
     C *outm = reinterpret_cast<C *>(spec + (long)(slot0 + f) * slot_bytes);
     C *outq = outm + nrow * m3;
     for (int idx = tid; idx < TWR * (m3 + 1); idx += nthr) {
@@ -297,14 +390,16 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, char *__restr
 // ---------------------------------------------------------------------------
 // x3 pass: half spectrum (FP32) -> real rows, times scale
 // ---------------------------------------------------------------------------
+template <int LF>
 __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const char *__restrict__ spec, long slot_bytes,
-                                                        int slot0, RealOut out, long nrow, int n3,
+                                                        int slot0, RealOut out, long nrow, int n3_rt,
                                                         int TWR, RadixPlan rp,
                                                         const float2 *__restrict__ tw_m3,
                                                         const float2 *__restrict__ tw_n3, float scale)
 {
     extern __shared__ char lds_raw[];
     float2 *lds = reinterpret_cast<float2 *>(lds_raw);
+    const int n3 = LF > 0 ? 2 * LF : n3_rt;
     const int m3 = n3 >> 1, LP = m3 + 1;
     float2 *A = lds, *B = lds + TWR * LP;
     const int f = blockIdx.y;
@@ -329,7 +424,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const char *__restrict__
         A[c * LP + k] = add(E, muli(O));
     }
     __syncthreads();
-    const float2 *z = lds_fft<true, false, float2>(A, B, TWR, 0, LP, rp, tw_m3, tid, nthr);
+    const float2 *z = lds_fft_any<true, false, LF>(A, B, TWR, 0, LP, rp, tw_m3, tid, nthr);
     float *__restrict__ dst = out.p[f];
     for (int idx = tid; idx < TWR * m3; idx += nthr) {
         const int c = idx / m3, n = idx - c * m3;
@@ -373,7 +468,7 @@ __device__ __forceinline__ void tile_store(C *__restrict__ dst, const C *src, co
     }
 }
 
-template <bool INV, class R>
+template <bool INV, class R, int LF>
 __global__ __launch_bounds__(kFftThreads) void k_fft_cols(char *__restrict__ spec, long slot_bytes,
                                                           int slot0, ColDesc d, int TW, int logTW,
                                                           RadixPlan rp,
@@ -382,7 +477,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(char *__restrict__ spe
     using C = typename CplxOf<R>::type;
     extern __shared__ char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
-    const int L = rp.L;
+    const int L = LF > 0 ? LF : rp.L;
     C *A = lds, *B = lds + L * TW;
     const int tid = threadIdx.x, nthr = blockDim.x;
     C *base = reinterpret_cast<C *>(spec + (long)(slot0 + blockIdx.z) * slot_bytes) + d.base_off +
@@ -390,7 +485,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(char *__restrict__ spe
     const int col0 = blockIdx.x * TW;
     tile_load(A, base, d, L, TW, logTW, col0, tid, nthr);
     __syncthreads();
-    const C *res = lds_fft<INV, true, C>(A, B, TW, logTW, 0, rp, tw, tid, nthr);
+    const C *res = lds_fft_any<INV, true, LF>(A, B, TW, logTW, 0, rp, tw, tid, nthr);
     tile_store(base, res, d, L, TW, logTW, col0, tid, nthr);
 }
 
@@ -427,7 +522,7 @@ struct ColCtx {  // how a tile position maps to (l2, l3)
 // per-field real symbol, forward and inverse in R
 enum { SYM_REG = 0, SYM_INVREG = 1, SYM_IDENT = 2 };
 
-template <class R, int SYM>
+template <class R, int SYM, int LF>
 __global__ __launch_bounds__(kFftThreads) void k_x1_scalar(char *__restrict__ spec, long slot_bytes,
                                                            int in0, int out0, ColDesc d, int nyq,
                                                            int TW, int logTW, RadixPlan rp,
@@ -437,7 +532,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_scalar(char *__restrict__ sp
     using C = typename CplxOf<R>::type;
     extern __shared__ char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
-    const int L = rp.L, tile = L * TW;
+    const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     C *A = lds, *B = lds + tile;
     const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
     const long off = d.base_off + (long)blockIdx.y * d.ostride;
@@ -445,7 +540,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_scalar(char *__restrict__ sp
     float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + blockIdx.z) * slot_bytes) + off;
     tile_load(load_target(rp, A, B), src, d, L, TW, logTW, col0, tid, nthr);
     __syncthreads();
-    lds_fft<false, true, C>(load_target(rp, A, B), load_target(rp, B, A), TW, logTW, 0, rp, tw, tid, nthr);
+    lds_fft_any<false, true, LF>(load_target(rp, A, B), load_target(rp, B, A), TW, logTW, 0, rp, tw, tid, nthr);
     const ColCtx cc{nyq};
     for (int idx = tid; idx < tile; idx += nthr) {
         const int n = idx >> logTW, c = idx & (TW - 1);
@@ -461,7 +556,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_scalar(char *__restrict__ sp
         A[idx] = scl(A[idx], (R)f);
     }
     __syncthreads();
-    const C *res = lds_fft<true, true, C>(A, B, TW, logTW, 0, rp, tw, tid, nthr);
+    const C *res = lds_fft_any<true, true, LF>(A, B, TW, logTW, 0, rp, tw, tid, nthr);
     for (int idx = tid; idx < tile; idx += nthr) {
         const int n = idx >> logTW, c = idx & (TW - 1);
         const int col = col0 + c;
@@ -470,13 +565,14 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_scalar(char *__restrict__ sp
 }
 
 // grad: one FP64 input field -> three FP32 output fields
+template <int LF>
 __global__ __launch_bounds__(kFftThreads) void k_x1_grad(char *__restrict__ spec, long slot_bytes, int in0,
                                                          int out0, ColDesc d, int nyq, int TW, int logTW,
                                                          RadixPlan rp, const double2 *__restrict__ twd,
                                                          const float2 *__restrict__ twf, SymCtx sc)
 {
     extern __shared__ char lds_raw[];
-    const int L = rp.L, tile = L * TW;
+    const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile;
     float2 *O = reinterpret_cast<float2 *>(WB + tile);  // three float2 tiles
     float2 *S = reinterpret_cast<float2 *>(WA);         // float scratch once WA/WB are free
@@ -485,7 +581,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_grad(char *__restrict__ spec
     const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(in0 + blockIdx.z) * slot_bytes) + off;
     tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
     __syncthreads();
-    lds_fft<false, true, double2>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
+    lds_fft_any<false, true, LF>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
     const ColCtx cc{nyq};
     for (int idx = tid; idx < tile; idx += nthr) {
         const int n = idx >> logTW, c = idx & (TW - 1);
@@ -498,7 +594,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_grad(char *__restrict__ spec
     }
     __syncthreads();
     for (int q = 0; q < 3; ++q) {
-        const float2 *res = lds_fft<true, true, float2>(O + q * tile, S, TW, logTW, 0, rp, twf, tid, nthr);
+        const float2 *res = lds_fft_any<true, true, LF>(O + q * tile, S, TW, logTW, 0, rp, twf, tid, nthr);
         float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + 3 * blockIdx.z + q) * slot_bytes) + off;
         tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
@@ -506,13 +602,14 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_grad(char *__restrict__ spec
 }
 
 // div: three FP64 input fields -> one FP32 output field (FP64 accumulation)
+template <int LF>
 __global__ __launch_bounds__(kFftThreads) void k_x1_div(char *__restrict__ spec, long slot_bytes, int in0,
                                                         int out0, ColDesc d, int nyq, int TW, int logTW,
                                                         RadixPlan rp, const double2 *__restrict__ twd,
                                                         const float2 *__restrict__ twf, SymCtx sc)
 {
     extern __shared__ char lds_raw[];
-    const int L = rp.L, tile = L * TW;
+    const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile, *ACC = WB + tile;
     const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
     const long off = d.base_off + (long)blockIdx.y * d.ostride;
@@ -521,7 +618,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_div(char *__restrict__ spec,
         const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(in0 + 3 * blockIdx.z + q) * slot_bytes) + off;
         tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
-        lds_fft<false, true, double2>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
+        lds_fft_any<false, true, LF>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
         for (int idx = tid; idx < tile; idx += nthr) {
             const int n = idx >> logTW, c = idx & (TW - 1);
             int l2, l3;
@@ -535,7 +632,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_div(char *__restrict__ spec,
     float2 *FA = reinterpret_cast<float2 *>(WA), *FB = FA + tile;
     for (int idx = tid; idx < tile; idx += nthr) FA[idx] = to_f2(ACC[idx]);
     __syncthreads();
-    const float2 *res = lds_fft<true, true, float2>(FA, FB, TW, logTW, 0, rp, twf, tid, nthr);
+    const float2 *res = lds_fft_any<true, true, LF>(FA, FB, TW, logTW, 0, rp, twf, tid, nthr);
     float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + blockIdx.z) * slot_bytes) + off;
     tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
 }
@@ -550,13 +647,14 @@ __device__ __forceinline__ void leray_coef(const SymCtx &sc, int n, int l2, int 
 }
 
 // Leray projection: three FP32 fields in and out
+template <int LF>
 __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spec, long slot_bytes, int in0,
                                                           int out0, ColDesc d, int nyq, int TW, int logTW,
                                                           RadixPlan rp, const float2 *__restrict__ twf,
                                                           SymCtx sc)
 {
     extern __shared__ char lds_raw[];
-    const int L = rp.L, tile = L * TW;
+    const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     float2 *T = reinterpret_cast<float2 *>(lds_raw);  // three field tiles, then scratch
     float2 *S = T + 3 * tile;
     const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
@@ -566,7 +664,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
         float2 *home = T + q * tile;
         tile_load(load_target(rp, home, S), src, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
-        lds_fft<false, true, float2>(load_target(rp, home, S), load_target(rp, S, home), TW, logTW, 0, rp, twf, tid, nthr);
+        lds_fft_any<false, true, LF>(load_target(rp, home, S), load_target(rp, S, home), TW, logTW, 0, rp, twf, tid, nthr);
     }
     const ColCtx cc{nyq};
     for (int idx = tid; idx < tile; idx += nthr) {
@@ -585,7 +683,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
     }
     __syncthreads();
     for (int q = 0; q < 3; ++q) {
-        const float2 *res = lds_fft<true, true, float2>(T + q * tile, S, TW, logTW, 0, rp, twf, tid, nthr);
+        const float2 *res = lds_fft_any<true, true, LF>(T + q * tile, S, TW, logTW, 0, rp, twf, tid, nthr);
         float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + 3 * blockIdx.z + q) * slot_bytes) + off;
         tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
@@ -595,6 +693,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
 // Assembly beta A w + K b: w three FP64 fields, b three FP32 fields, out three
 // FP32 fields.  K = Leray if sc.leray.  The b components stream through one
 // working tile; the Leray correction accumulates s = k.b / |k|^2.
+template <int LF>
 __global__ __launch_bounds__(kFftThreads) void k_x1_assemble(char *__restrict__ spec, long slot_bytes,
                                                              int w0, int b0, int out0, ColDesc d, int nyq,
                                                              int TW, int logTW, RadixPlan rp,
@@ -602,7 +701,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_assemble(char *__restrict__ 
                                                              const float2 *__restrict__ twf, SymCtx sc)
 {
     extern __shared__ char lds_raw[];
-    const int L = rp.L, tile = L * TW;
+    const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile;
     float2 *FA = reinterpret_cast<float2 *>(WA), *FB = FA + tile;  // float view of the working pair
     float2 *O = reinterpret_cast<float2 *>(WB + tile);             // three output tiles
@@ -614,7 +713,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_assemble(char *__restrict__ 
         const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(w0 + q) * slot_bytes) + off;
         tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
-        lds_fft<false, true, double2>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
+        lds_fft_any<false, true, LF>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
         for (int idx = tid; idx < tile; idx += nthr) {
             const int n = idx >> logTW, c = idx & (TW - 1);
             int l2, l3;
@@ -627,7 +726,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_assemble(char *__restrict__ 
         const float2 *src = reinterpret_cast<const float2 *>(spec + (long)(b0 + q) * slot_bytes) + off;
         tile_load(load_target(rp, FA, FB), src, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
-        lds_fft<false, true, float2>(load_target(rp, FA, FB), load_target(rp, FB, FA), TW, logTW, 0, rp, twf, tid, nthr);
+        lds_fft_any<false, true, LF>(load_target(rp, FA, FB), load_target(rp, FB, FA), TW, logTW, 0, rp, twf, tid, nthr);
         for (int idx = tid; idx < tile; idx += nthr) {
             const float2 bq = FA[idx];
             const float s = (float)sc.scale;
@@ -658,7 +757,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_assemble(char *__restrict__ 
         __syncthreads();
     }
     for (int q = 0; q < 3; ++q) {
-        const float2 *res = lds_fft<true, true, float2>(O + q * tile, FA, TW, logTW, 0, rp, twf, tid, nthr);
+        const float2 *res = lds_fft_any<true, true, LF>(O + q * tile, FA, TW, logTW, 0, rp, twf, tid, nthr);
         float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + q) * slot_bytes) + off;
         tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
@@ -850,12 +949,14 @@ void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int slot0, bool dbl)
     check_lds(lds, "r2c_x3");
     dim3 grid((unsigned)((F.nrow + TWR - 1) / TWR), count);
     Scope s(P, K_R2C_X3);
-    if (dbl)
-        hipLaunchKernelGGL(k_r2c_x3<double>, grid, dim3(kFftThreads), lds, P->stream, in, P->spec,
-                           P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3d, F.twN3d);
-    else
-        hipLaunchKernelGGL(k_r2c_x3<float>, grid, dim3(kFftThreads), lds, P->stream, in, P->spec,
-                           P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3);
+    with_len(F.m3, [&]<int LF>() {
+        if (dbl)
+            hipLaunchKernelGGL((k_r2c_x3<double, LF>), grid, dim3(kFftThreads), lds, P->stream, in, P->spec,
+                               P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3d, F.twN3d);
+        else
+            hipLaunchKernelGGL((k_r2c_x3<float, LF>), grid, dim3(kFftThreads), lds, P->stream, in, P->spec,
+                               P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3);
+    });
     check_hip(hipGetLastError(), "k_r2c_x3");
 }
 
@@ -867,8 +968,10 @@ void c2r_fields(lddmm_plan *P, int slot0, int count, const RealOut &out, float s
     check_lds(lds, "c2r_x3");
     dim3 grid((unsigned)((F.nrow + TWR - 1) / TWR), count);
     Scope s(P, K_C2R_X3);
-    hipLaunchKernelGGL(k_c2r_x3, grid, dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes,
-                       slot0, out, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3, scale);
+    with_len(F.m3, [&]<int LF>() {
+        hipLaunchKernelGGL((k_c2r_x3<LF>), grid, dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes,
+                           slot0, out, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3, scale);
+    });
     check_hip(hipGetLastError(), "k_c2r_x3");
 }
 
@@ -906,23 +1009,25 @@ static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool invers
         dim3 grid((unsigned)((d.ncols + TW - 1) / TW), outer[part], count);
         Scope s(P, K_FFT_COLS);
         const int lt = ilog2(TW);
-        if (dbl) {
-            const double2 *tw = axis == 1 ? F.tw2d : F.tw1d;
-            if (inverse)
-                hipLaunchKernelGGL((k_fft_cols<true, double>), grid, dim3(kFftThreads), lds, P->stream,
-                                   P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
-            else
-                hipLaunchKernelGGL((k_fft_cols<false, double>), grid, dim3(kFftThreads), lds, P->stream,
-                                   P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
-        } else {
-            const float2 *tw = axis == 1 ? F.tw2 : F.tw1;
-            if (inverse)
-                hipLaunchKernelGGL((k_fft_cols<true, float>), grid, dim3(kFftThreads), lds, P->stream,
-                                   P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
-            else
-                hipLaunchKernelGGL((k_fft_cols<false, float>), grid, dim3(kFftThreads), lds, P->stream,
-                                   P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
-        }
+        with_len(rp.L, [&]<int LF>() {
+            if (dbl) {
+                const double2 *tw = axis == 1 ? F.tw2d : F.tw1d;
+                if (inverse)
+                    hipLaunchKernelGGL((k_fft_cols<true, double, LF>), grid, dim3(kFftThreads), lds, P->stream,
+                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+                else
+                    hipLaunchKernelGGL((k_fft_cols<false, double, LF>), grid, dim3(kFftThreads), lds, P->stream,
+                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+            } else {
+                const float2 *tw = axis == 1 ? F.tw2 : F.tw1;
+                if (inverse)
+                    hipLaunchKernelGGL((k_fft_cols<true, float, LF>), grid, dim3(kFftThreads), lds, P->stream,
+                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+                else
+                    hipLaunchKernelGGL((k_fft_cols<false, float, LF>), grid, dim3(kFftThreads), lds, P->stream,
+                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+            }
+        });
         check_hip(hipGetLastError(), "k_fft_cols");
     }
 }
@@ -1010,42 +1115,46 @@ static void x1_symbol_parts(lddmm_plan *P, int op, int in0, int out0, int nbatch
         const int lt = ilog2(TW);
         const unsigned gx = (unsigned)((d.ncols + TW - 1) / TW);
         Scope s(P, K_SPECTRAL_X1);
-        switch (op) {
-        case SOP_GRAD:
-            hipLaunchKernelGGL(k_x1_grad, dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds, P->stream,
-                               P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d, F.tw1, sc);
-            break;
-        case SOP_DIV:
-            hipLaunchKernelGGL(k_x1_div, dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds, P->stream,
-                               P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d, F.tw1, sc);
-            break;
-        case SOP_LERAY:
-            hipLaunchKernelGGL(k_x1_leray, dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds, P->stream,
-                               P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1, sc);
-            break;
-        case SOP_ASSEMBLE:
-            for (int b = 0; b < nbatch; ++b)
-                hipLaunchKernelGGL(k_x1_assemble, dim3(gx, outer[part], 1), dim3(kFftThreads), lds, P->stream,
-                                   P->spec, P->slot_bytes, in0 + 6 * b, in0 + 6 * b + 3, out0 + 3 * b, d, part,
-                                   TW, lt, rp, F.tw1d, F.tw1, sc);
-            break;
-        case SOP_REG:  // three independent fields per batch
-            hipLaunchKernelGGL((k_x1_scalar<double, SYM_REG>), dim3(gx, outer[part], 3 * nbatch),
-                               dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part,
-                               TW, lt, rp, F.tw1d, sc);
-            break;
-        case SOP_INVREG:
-            hipLaunchKernelGGL((k_x1_scalar<float, SYM_INVREG>), dim3(gx, outer[part], 3 * nbatch),
-                               dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part,
-                               TW, lt, rp, F.tw1, sc);
-            break;
-        case SOP_IDENT:
-            hipLaunchKernelGGL((k_x1_scalar<float, SYM_IDENT>), dim3(gx, outer[part], nbatch),
-                               dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part,
-                               TW, lt, rp, F.tw1, sc);
-            break;
-        default: fail(LDDMM_EINVAL, "unknown spectral operator");
-        }
+        with_len(L, [&]<int LF>() {
+            switch (op) {
+            case SOP_GRAD:
+                hipLaunchKernelGGL((k_x1_grad<LF>), dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds,
+                                   P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d,
+                                   F.tw1, sc);
+                break;
+            case SOP_DIV:
+                hipLaunchKernelGGL((k_x1_div<LF>), dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds,
+                                   P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d,
+                                   F.tw1, sc);
+                break;
+            case SOP_LERAY:
+                hipLaunchKernelGGL((k_x1_leray<LF>), dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds,
+                                   P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1, sc);
+                break;
+            case SOP_ASSEMBLE:
+                for (int b = 0; b < nbatch; ++b)
+                    hipLaunchKernelGGL((k_x1_assemble<LF>), dim3(gx, outer[part], 1), dim3(kFftThreads), lds,
+                                       P->stream, P->spec, P->slot_bytes, in0 + 6 * b, in0 + 6 * b + 3,
+                                       out0 + 3 * b, d, part, TW, lt, rp, F.tw1d, F.tw1, sc);
+                break;
+            case SOP_REG:  // three independent fields per batch
+                hipLaunchKernelGGL((k_x1_scalar<double, SYM_REG, LF>), dim3(gx, outer[part], 3 * nbatch),
+                                   dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
+                                   part, TW, lt, rp, F.tw1d, sc);
+                break;
+            case SOP_INVREG:
+                hipLaunchKernelGGL((k_x1_scalar<float, SYM_INVREG, LF>), dim3(gx, outer[part], 3 * nbatch),
+                                   dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
+                                   part, TW, lt, rp, F.tw1, sc);
+                break;
+            case SOP_IDENT:
+                hipLaunchKernelGGL((k_x1_scalar<float, SYM_IDENT, LF>), dim3(gx, outer[part], nbatch),
+                                   dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
+                                   part, TW, lt, rp, F.tw1, sc);
+                break;
+            default: fail(LDDMM_EINVAL, "unknown spectral operator");
+            }
+        });
         check_hip(hipGetLastError(), "x1_symbol");
     }
 }

@@ -85,7 +85,9 @@ struct lddmm_plan {
     double *hscal = nullptr; // pinned host mirror
 
     int have_images = 0, have_velocity = 0, have_grad = 0, have_matvec = 0;
-    int tile_big = -1;       // gather tile shape: -1 heuristic, 0 4x4x64, 1 8x8x64
+    int gather_mode = -1;    // 0 direct, 1 tiled 4x4x64, 2 tiled 8x8x64, -1 heuristic
+    int gather_tuned = 0;
+    float gather_ms[1] = {0.f};
     double g0norm = 0.0;
     lddmm::PlanTiming timing;
 };
@@ -140,6 +142,7 @@ void unpack_standard(lddmm_plan *P, const float2 *srcp, int spec_field);
 
 // ---- transport.hip ----------------------------------------------------------
 void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa);
+void autotune_gather(lddmm_plan *P);
 void launch_interp(lddmm_plan *P, int nf, const float *fields, const float *disp, float *out,
                    int kid);
 void launch_adj_coef(lddmm_plan *P);

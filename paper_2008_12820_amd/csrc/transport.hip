@@ -367,12 +367,23 @@ __global__ __launch_bounds__((64 * TileCfg<T1, T2>::NW)) void k_tiled(Grid3 g, c
         dsh[NP + slot] = d2;
         dsh[2 * NP + slot] = d3;
     }
-    atomicMin(&ext[0], lo1);
-    atomicMin(&ext[1], lo2);
-    atomicMin(&ext[2], lo3);
-    atomicMax(&ext[3], hi1);
-    atomicMax(&ext[4], hi2);
-    atomicMax(&ext[5], hi3);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {  // wavefront reduction, then one atomic per wave
+        lo1 = min(lo1, __shfl_xor(lo1, off));
+        lo2 = min(lo2, __shfl_xor(lo2, off));
+        lo3 = min(lo3, __shfl_xor(lo3, off));
+        hi1 = max(hi1, __shfl_xor(hi1, off));
+        hi2 = max(hi2, __shfl_xor(hi2, off));
+        hi3 = max(hi3, __shfl_xor(hi3, off));
+    }
+    if (lane == 0) {
+        atomicMin(&ext[0], lo1);
+        atomicMin(&ext[1], lo2);
+        atomicMin(&ext[2], lo3);
+        atomicMax(&ext[3], hi1);
+        atomicMax(&ext[4], hi2);
+        atomicMax(&ext[5], hi3);
+    }
     __syncthreads();
     const int L1 = ext[0], L2 = ext[1], L3 = ext[2];
     const int B1 = ext[3] - L1 + 1, B2 = ext[4] - L2 + 1, B3 = ext[5] - L3 + 1;
@@ -429,6 +440,23 @@ __global__ __launch_bounds__((64 * TileCfg<T1, T2>::NW)) void k_tiled(Grid3 g, c
     }
 }
 
+// direct gathers, one thread per point, stencil loads from L1/L2
+template <class Epi>
+__global__ __launch_bounds__(kPtThreads) void k_direct(Grid3 g, const float *__restrict__ disp, Epi epi)
+{
+    const int p = point_index();
+    if (p >= g.N) return;
+    int i, j, k;
+    point_coords(g, p, i, j, k);
+    const long N = g.N;
+    Stencil<float> s;
+    make_stencil<float>(g, i, j, k, disp[p], disp[N + p], disp[2 * N + p], s);
+    float v[Epi::NF];
+#pragma unroll
+    for (int f = 0; f < Epi::NF; ++f) v[f] = gather<float>(epi.field(f), s);
+    epi.finish(p, v);
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -450,13 +478,15 @@ void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa)
     check_hip(hipGetLastError(), "k_departure");
 }
 
-// tile shape: 8 x 8 x 64 on large grids, 4 x 4 x 64 when that leaves too few
+// gather strategy: P->gather_mode 0 direct, 1 tiled 4x4x64, 2 tiled 8x8x64;
+// -1 before tuning: tiled, 8x8 on large grids, 4x4 when that leaves too few
 // workgroups to fill the chip
-static bool big_tiles(const lddmm_plan *P)
+static int gather_mode(const lddmm_plan *P)
 {
+    if (P->gather_mode >= 0) return P->gather_mode;
     const long n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
     const long tiles8 = ((n1 + 7) / 8) * ((n2 + 7) / 8) * ((n3 + kT3 - 1) / kT3);
-    return P->tile_big >= 0 ? P->tile_big != 0 : tiles8 >= 2048;
+    return tiles8 >= 2048 ? 2 : 1;
 }
 
 template <int T1, int T2, class Epi>
@@ -485,10 +515,49 @@ static void launch_tiled(lddmm_plan *P, const float *disp, const Epi &epi, int k
 template <class Epi>
 static void tiled(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
 {
-    if (big_tiles(P))
-        launch_tiled<8, 8>(P, disp, epi, kid);
-    else
-        launch_tiled<4, 4>(P, disp, epi, kid);
+    switch (gather_mode(P)) {
+    case 0: {
+        Scope s(P, kid);
+        hipLaunchKernelGGL((k_direct<Epi>), blocks_of(P), dim3(kPtThreads), 0, P->stream, grid_of(P), disp, epi);
+        check_hip(hipGetLastError(), "k_direct");
+        break;
+    }
+    case 1: launch_tiled<4, 4>(P, disp, epi, kid); break;
+    default: launch_tiled<8, 8>(P, disp, epi, kid); break;
+    }
+}
+
+// time the three gather strategies on the plan's adjoint displacement field
+// (one adjoint step into scratch) and keep the fastest
+void autotune_gather(lddmm_plan *P)
+{
+    const int keep = P->gather_mode;
+    float best = 1e30f;
+    int bm = 2;
+    const float *src = P->lam;
+    float *dst = P->lam + P->N;
+    for (int m = 0; m < 3; ++m) {
+        P->gather_mode = m;
+        hipEvent_t a, b;
+        check_hip(hipEventCreate(&a), "hipEventCreate");
+        check_hip(hipEventCreate(&b), "hipEventCreate");
+        tiled(P, P->dXa, EpiAdj{src, P->coef, dst, 1.f}, K_ADJ_STEP);
+        check_hip(hipEventRecord(a, P->stream), "hipEventRecord");
+        for (int r = 0; r < 3; ++r) tiled(P, P->dXa, EpiAdj{src, P->coef, dst, 1.f}, K_ADJ_STEP);
+        check_hip(hipEventRecord(b, P->stream), "hipEventRecord");
+        check_hip(hipEventSynchronize(b), "hipEventSynchronize");
+        float ms = 0.f;
+        check_hip(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        if (ms < best) {
+            best = ms;
+            bm = m;
+        }
+    }
+    P->gather_mode = keep >= 0 ? keep : bm;
+    P->gather_tuned = 1;
+    P->gather_ms[0] = best;
 }
 
 void launch_interp(lddmm_plan *P, int nf, const float *fields, const float *disp, float *out, int kid)

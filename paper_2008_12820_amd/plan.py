@@ -145,6 +145,9 @@ class Plan:
         L.lddmm_autotune(self._h)
         return L.lddmm_tuning(self._h)
 
+    def set_gather_mode(self, mode):
+        L.lddmm_set_gather_mode(self._h, mode)
+
     def tuning(self):
         return L.lddmm_tuning(self._h)
 

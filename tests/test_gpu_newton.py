@@ -136,3 +136,22 @@ def test_negative_curvature_is_reported():
     P.set_velocity(to_dev(v))
     vt, info = P.newton_step(3, 0.0, allow_notconv=True)
     assert info["status"] == ENOTCONV and info["flags"] & 2
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (40, 36, 96)])
+def test_gather_strategies_agree(shape):
+    """Direct and LDS-tiled gathers (both tile shapes) add in the same order:
+    the matvec is the same for every strategy and matches the oracle."""
+    say(f"gather strategies {shape}")
+    nt = 3
+    m0, m1, vtrue, v, ref = problem(shape, nt, 2, 1e-3, disp=3.0)
+    P = _plan(shape, nt, 2, 1e-3, False, m0, m1, v)
+    vt = incremental(shape, 1300)
+    ref_hv = ref.matvec(synth.f64(vt))
+    outs = []
+    for mode in (0, 1, 2):
+        P.set_gather_mode(mode)
+        P.set_velocity(to_dev(v))
+        outs.append(to_np(P.hessian_matvec(to_dev(vt))))
+        assert rel(outs[-1], ref_hv) < 1e-5, mode
+    assert rel(outs[0], outs[1]) < 1e-6 and rel(outs[0], outs[2]) < 1e-6
