@@ -30,6 +30,7 @@
 #include <cstdlib>
 #include <fstream>
 #include <map>
+#include <set>
 #include <sstream>
 #include <string>
 
@@ -339,6 +340,23 @@ __device__ __forceinline__ C *load_target(const RadixPlan &rp, C *home, C *other
 }
 
 constexpr int kFftThreads = 256;
+
+// Launch with dynamic LDS; above 64 KB the kernel's limit is raised (once
+// per kernel) to kLdsMax.
+static void allow_big_lds(const void *k)
+{
+    static std::set<const void *> done;
+    if (done.count(k)) return;
+    check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax),
+              "hipFuncSetAttribute");
+    done.insert(k);
+}
+
+#define FFT_LAUNCH(kern, grid, lds, stream, ...)                                   \
+    do {                                                                           \
+        if ((lds) > 65536) allow_big_lds((const void *)(kern));                     \
+        hipLaunchKernelGGL(kern, grid, dim3(kFftThreads), lds, stream, __VA_ARGS__); \
+    } while (0)
 
 // ---------------------------------------------------------------------------
 // x3 pass: real rows -> half spectrum (main + Nyquist plane), computed in R
@@ -811,8 +829,8 @@ RadixPlan make_radix_plan(int L)
 }
 
 static int floor_pow2(long x);
-static int rows_per_block(int m3, size_t csize);
-static int col_tile(int L, size_t bytes_per_elem, int ncols);
+static int rows_per_block(int m3, size_t csize, size_t budget);
+static int col_tile(int L, size_t bytes_per_elem, int ncols, size_t budget);
 static void col_descs(const FftCtx &F, int axis, struct ColDesc dd[2], int outer[2]);
 static size_t x1_bytes_per_elem(int op);
 static void default_tiles(FftCtx &F);
@@ -893,18 +911,18 @@ static int ilog2(int x)
 }
 
 // rows per block of the x3 passes: two buffers of TWR*(m3+1) complex values
-static int rows_per_block(int m3, size_t csize)
+static int rows_per_block(int m3, size_t csize, size_t budget)
 {
-    long cap = (long)(kLdsBudget / (2 * csize * (m3 + 1)));
+    long cap = (long)(budget / (2 * csize * (m3 + 1)));
     int t = floor_pow2(cap < 1 ? 1 : cap);
     return t > 32 ? 32 : t;
 }
 
 // columns per tile when each column needs `bytes_per_elem` bytes of LDS per
 // line element (summed over all tiles the kernel holds)
-static int col_tile(int L, size_t bytes_per_elem, int ncols)
+static int col_tile(int L, size_t bytes_per_elem, int ncols, size_t budget)
 {
-    long cap = (long)(kLdsBudget / (bytes_per_elem * (size_t)L));
+    long cap = (long)(budget / (bytes_per_elem * (size_t)L));
     int t = floor_pow2(cap < 1 ? 1 : cap);
     if (t > 32) t = 32;
     int nc = floor_pow2(ncols);
@@ -923,21 +941,22 @@ static void default_tiles(FftCtx &F)
         const int L = axis == 1 ? F.rp2.L : F.rp1.L;
         for (int part = 0; part < 2; ++part)
             for (int dbl = 0; dbl < 2; ++dbl)
-                F.tw_cols[axis][part][dbl] = col_tile(L, 2 * (dbl ? 16 : 8), dd[part].ncols);
+                F.tw_cols[axis][part][dbl] = col_tile(L, 2 * (dbl ? 16 : 8), dd[part].ncols, kLdsBudget);
     }
     ColDesc dd[2];
     int outer[2];
     col_descs(F, 0, dd, outer);
     for (int op = 0; op < 8; ++op)
-        for (int part = 0; part < 2; ++part) F.tw_x1[op][part] = col_tile(F.rp1.L, x1_bytes_per_elem(op), dd[part].ncols);
-    F.twr_r2c[0] = rows_per_block(F.m3, sizeof(float2));
-    F.twr_r2c[1] = rows_per_block(F.m3, sizeof(double2));
-    F.twr_c2r = rows_per_block(F.m3, sizeof(float2));
+        for (int part = 0; part < 2; ++part)
+            F.tw_x1[op][part] = col_tile(F.rp1.L, x1_bytes_per_elem(op), dd[part].ncols, kLdsBudget);
+    F.twr_r2c[0] = rows_per_block(F.m3, sizeof(float2), kLdsBudget);
+    F.twr_r2c[1] = rows_per_block(F.m3, sizeof(double2), kLdsBudget);
+    F.twr_c2r = rows_per_block(F.m3, sizeof(float2), kLdsBudget);
 }
 
 static void check_lds(size_t bytes, const char *what)
 {
-    if (bytes > kLdsBudget) fail(LDDMM_EUNSUPPORTED, std::string(what) + ": LDS tile exceeds the budget");
+    if (bytes > kLdsMax) fail(LDDMM_EUNSUPPORTED, std::string(what) + ": LDS tile exceeds the budget");
 }
 
 void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int slot0, bool dbl)
@@ -951,10 +970,10 @@ void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int slot0, bool dbl)
     Scope s(P, K_R2C_X3);
     with_len(F.m3, [&]<int LF>() {
         if (dbl)
-            hipLaunchKernelGGL((k_r2c_x3<double, LF>), grid, dim3(kFftThreads), lds, P->stream, in, P->spec,
+            FFT_LAUNCH((k_r2c_x3<double, LF>), grid, lds, P->stream, in, P->spec,
                                P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3d, F.twN3d);
         else
-            hipLaunchKernelGGL((k_r2c_x3<float, LF>), grid, dim3(kFftThreads), lds, P->stream, in, P->spec,
+            FFT_LAUNCH((k_r2c_x3<float, LF>), grid, lds, P->stream, in, P->spec,
                                P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3);
     });
     check_hip(hipGetLastError(), "k_r2c_x3");
@@ -969,7 +988,7 @@ void c2r_fields(lddmm_plan *P, int slot0, int count, const RealOut &out, float s
     dim3 grid((unsigned)((F.nrow + TWR - 1) / TWR), count);
     Scope s(P, K_C2R_X3);
     with_len(F.m3, [&]<int LF>() {
-        hipLaunchKernelGGL((k_c2r_x3<LF>), grid, dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes,
+        FFT_LAUNCH((k_c2r_x3<LF>), grid, lds, P->stream, P->spec, P->slot_bytes,
                            slot0, out, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3, scale);
     });
     check_hip(hipGetLastError(), "k_c2r_x3");
@@ -1013,18 +1032,18 @@ static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool invers
             if (dbl) {
                 const double2 *tw = axis == 1 ? F.tw2d : F.tw1d;
                 if (inverse)
-                    hipLaunchKernelGGL((k_fft_cols<true, double, LF>), grid, dim3(kFftThreads), lds, P->stream,
+                    FFT_LAUNCH((k_fft_cols<true, double, LF>), grid, lds, P->stream,
                                        P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
                 else
-                    hipLaunchKernelGGL((k_fft_cols<false, double, LF>), grid, dim3(kFftThreads), lds, P->stream,
+                    FFT_LAUNCH((k_fft_cols<false, double, LF>), grid, lds, P->stream,
                                        P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
             } else {
                 const float2 *tw = axis == 1 ? F.tw2 : F.tw1;
                 if (inverse)
-                    hipLaunchKernelGGL((k_fft_cols<true, float, LF>), grid, dim3(kFftThreads), lds, P->stream,
+                    FFT_LAUNCH((k_fft_cols<true, float, LF>), grid, lds, P->stream,
                                        P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
                 else
-                    hipLaunchKernelGGL((k_fft_cols<false, float, LF>), grid, dim3(kFftThreads), lds, P->stream,
+                    FFT_LAUNCH((k_fft_cols<false, float, LF>), grid, lds, P->stream,
                                        P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
             }
         });
@@ -1118,38 +1137,31 @@ static void x1_symbol_parts(lddmm_plan *P, int op, int in0, int out0, int nbatch
         with_len(L, [&]<int LF>() {
             switch (op) {
             case SOP_GRAD:
-                hipLaunchKernelGGL((k_x1_grad<LF>), dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds,
-                                   P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d,
+                FFT_LAUNCH((k_x1_grad<LF>), dim3(gx, outer[part], nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d,
                                    F.tw1, sc);
                 break;
             case SOP_DIV:
-                hipLaunchKernelGGL((k_x1_div<LF>), dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds,
-                                   P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d,
+                FFT_LAUNCH((k_x1_div<LF>), dim3(gx, outer[part], nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d,
                                    F.tw1, sc);
                 break;
             case SOP_LERAY:
-                hipLaunchKernelGGL((k_x1_leray<LF>), dim3(gx, outer[part], nbatch), dim3(kFftThreads), lds,
-                                   P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1, sc);
+                FFT_LAUNCH((k_x1_leray<LF>), dim3(gx, outer[part], nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1, sc);
                 break;
             case SOP_ASSEMBLE:
                 for (int b = 0; b < nbatch; ++b)
-                    hipLaunchKernelGGL((k_x1_assemble<LF>), dim3(gx, outer[part], 1), dim3(kFftThreads), lds,
-                                       P->stream, P->spec, P->slot_bytes, in0 + 6 * b, in0 + 6 * b + 3,
+                    FFT_LAUNCH((k_x1_assemble<LF>), dim3(gx, outer[part], 1), lds, P->stream, P->spec, P->slot_bytes, in0 + 6 * b, in0 + 6 * b + 3,
                                        out0 + 3 * b, d, part, TW, lt, rp, F.tw1d, F.tw1, sc);
                 break;
             case SOP_REG:  // three independent fields per batch
-                hipLaunchKernelGGL((k_x1_scalar<double, SYM_REG, LF>), dim3(gx, outer[part], 3 * nbatch),
-                                   dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
+                FFT_LAUNCH((k_x1_scalar<double, SYM_REG, LF>), dim3(gx, outer[part], 3 * nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
                                    part, TW, lt, rp, F.tw1d, sc);
                 break;
             case SOP_INVREG:
-                hipLaunchKernelGGL((k_x1_scalar<float, SYM_INVREG, LF>), dim3(gx, outer[part], 3 * nbatch),
-                                   dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
+                FFT_LAUNCH((k_x1_scalar<float, SYM_INVREG, LF>), dim3(gx, outer[part], 3 * nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
                                    part, TW, lt, rp, F.tw1, sc);
                 break;
             case SOP_IDENT:
-                hipLaunchKernelGGL((k_x1_scalar<float, SYM_IDENT, LF>), dim3(gx, outer[part], nbatch),
-                                   dim3(kFftThreads), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
+                FFT_LAUNCH((k_x1_scalar<float, SYM_IDENT, LF>), dim3(gx, outer[part], nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
                                    part, TW, lt, rp, F.tw1, sc);
                 break;
             default: fail(LDDMM_EINVAL, "unknown spectral operator");
@@ -1222,9 +1234,8 @@ static float time_ms(lddmm_plan *P, Fn &&fn)
 }
 
 template <class Fn>
-static void tune_one(lddmm_plan *P, int &slot, Fn &&fn)
+static void tune_one(lddmm_plan *P, int &slot, int top, Fn &&fn)
 {
-    const int top = slot;
     int best = top;
     float bt = 1e30f;
     for (int t = top; t >= 1; t >>= 1) {
@@ -1307,17 +1318,27 @@ void autotune_fft(lddmm_plan *P)
     RealOut ro{};
     for (int c = 0; c < 3; ++c) ro.p[c] = P->b + c * N;
     for (int dbl = 0; dbl < 2; ++dbl)
-        tune_one(P, F.twr_r2c[dbl], [&] { r2c_fields(P, ri, 3, 0, dbl != 0); });
-    tune_one(P, F.twr_c2r, [&] { c2r_fields(P, 0, 3, ro, 1.f); });
-    for (int axis = 0; axis < 2; ++axis)
+        tune_one(P, F.twr_r2c[dbl], rows_per_block(F.m3, dbl ? sizeof(double2) : sizeof(float2), kLdsMax),
+                 [&] { r2c_fields(P, ri, 3, 0, dbl != 0); });
+    tune_one(P, F.twr_c2r, rows_per_block(F.m3, sizeof(float2), kLdsMax), [&] { c2r_fields(P, 0, 3, ro, 1.f); });
+    for (int axis = 0; axis < 2; ++axis) {
+        ColDesc dd[2];
+        int outer[2];
+        col_descs(F, axis == 1 ? 1 : 0, dd, outer);
+        const int L = axis == 1 ? F.rp2.L : F.rp1.L;
         for (int part = 0; part < 2; ++part)
             for (int dbl = 0; dbl < 2; ++dbl)
-                tune_one(P, F.tw_cols[axis][part][dbl],
+                tune_one(P, F.tw_cols[axis][part][dbl], col_tile(L, 2 * (dbl ? 16 : 8), dd[part].ncols, kLdsMax),
                          [&] { cols_pass(P, axis == 1 ? 1 : 0, 0, 3, false, dbl != 0, part); });
+    }
+    ColDesc d1[2];
+    int o1[2];
+    col_descs(F, 0, d1, o1);
     const int ops[] = {SOP_GRAD, SOP_DIV, SOP_REG, SOP_INVREG, SOP_LERAY, SOP_ASSEMBLE};
     for (int op : ops)
         for (int part = 0; part < 2; ++part)
-            tune_one(P, F.tw_x1[op][part], [&] { x1_symbol_parts(P, op, 0, op_nin(op), 1, 1, part); });
+            tune_one(P, F.tw_x1[op][part], col_tile(F.rp1.L, x1_bytes_per_elem(op), d1[part].ncols, kLdsMax),
+                     [&] { x1_symbol_parts(P, op, 0, op_nin(op), 1, 1, part); });
     P->timing.on = timing;
     F.tuned = 1;
     std::vector<int> vals;

@@ -41,8 +41,11 @@ struct FftCtx {
     int tuned = 0;              // 1 once the autotuner has run
 };
 
-// LDS bytes one FFT workgroup may use
+// LDS bytes of one FFT workgroup: the default tiles stay within kLdsBudget
+// (several workgroups per CU); the autotuner may go up to kLdsMax (the
+// 160 KB a gfx950 workgroup can address)
 constexpr size_t kLdsBudget = 64 * 1024;
+constexpr size_t kLdsMax = 160 * 1024;
 
 struct PlanTiming {
     bool on = false;
