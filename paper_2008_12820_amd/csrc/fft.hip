@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, char *__restr
     const int f = blockIdx.y;
     const float *__restrict__ src = in.p[f];
     const long row0 = (long)blockIdx.x * TWR;
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x, nthr = kFftThreads;
     R *Af = reinterpret_cast<R *>(A);
     for (int idx = tid; idx < TWR * n3; idx += nthr) {
         const int c = idx / n3, x = idx - c * n3;
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const char *__restrict__
     float2 *A = lds, *B = lds + TWR * LP;
     const int f = blockIdx.y;
     const long row0 = (long)blockIdx.x * TWR;
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x, nthr = kFftThreads;
     const float2 *inm = reinterpret_cast<const float2 *>(spec + (long)(slot0 + f) * slot_bytes);
     const float2 *inq = inm + nrow * m3;
     for (int idx = tid; idx < TWR * (m3 + 1); idx += nthr) {
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(char *__restrict__ spe
     C *lds = reinterpret_cast<C *>(lds_raw);
     const int L = LF > 0 ? LF : rp.L;
     C *A = lds, *B = lds + L * TW;
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x, nthr = kFftThreads;
     C *base = reinterpret_cast<C *>(spec + (long)(slot0 + blockIdx.z) * slot_bytes) + d.base_off +
               (long)blockIdx.y * d.ostride;
     const int col0 = blockIdx.x * TW;
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_scalar(char *__restrict__ sp
     C *lds = reinterpret_cast<C *>(lds_raw);
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     C *A = lds, *B = lds + tile;
-    const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
+    const int tid = threadIdx.x, nthr = kFftThreads, col0 = blockIdx.x * TW;
     const long off = d.base_off + (long)blockIdx.y * d.ostride;
     const C *src = reinterpret_cast<const C *>(spec + (long)(in0 + blockIdx.z) * slot_bytes) + off;
     float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + blockIdx.z) * slot_bytes) + off;
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_grad(char *__restrict__ spec
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile;
     float2 *O = reinterpret_cast<float2 *>(WB + tile);  // three float2 tiles
     float2 *S = reinterpret_cast<float2 *>(WA);         // float scratch once WA/WB are free
-    const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
+    const int tid = threadIdx.x, nthr = kFftThreads, col0 = blockIdx.x * TW;
     const long off = d.base_off + (long)blockIdx.y * d.ostride;
     const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(in0 + blockIdx.z) * slot_bytes) + off;
     tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
@@ -629,7 +629,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_div(char *__restrict__ spec,
     extern __shared__ char lds_raw[];
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile, *ACC = WB + tile;
-    const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
+    const int tid = threadIdx.x, nthr = kFftThreads, col0 = blockIdx.x * TW;
     const long off = d.base_off + (long)blockIdx.y * d.ostride;
     const ColCtx cc{nyq};
     for (int q = 0; q < 3; ++q) {
@@ -675,7 +675,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     float2 *T = reinterpret_cast<float2 *>(lds_raw);  // three field tiles, then scratch
     float2 *S = T + 3 * tile;
-    const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
+    const int tid = threadIdx.x, nthr = kFftThreads, col0 = blockIdx.x * TW;
     const long off = d.base_off + (long)blockIdx.y * d.ostride;
     for (int q = 0; q < 3; ++q) {
         const float2 *src = reinterpret_cast<const float2 *>(spec + (long)(in0 + 3 * blockIdx.z + q) * slot_bytes) + off;
@@ -724,7 +724,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_assemble(char *__restrict__ 
     float2 *FA = reinterpret_cast<float2 *>(WA), *FB = FA + tile;  // float view of the working pair
     float2 *O = reinterpret_cast<float2 *>(WB + tile);             // three output tiles
     float2 *Sd = O + 3 * tile;                                     // Leray accumulator
-    const int tid = threadIdx.x, nthr = blockDim.x, col0 = blockIdx.x * TW;
+    const int tid = threadIdx.x, nthr = kFftThreads, col0 = blockIdx.x * TW;
     const long off = d.base_off + (long)blockIdx.y * d.ostride;
     const ColCtx cc{nyq};
     for (int q = 0; q < 3; ++q) {

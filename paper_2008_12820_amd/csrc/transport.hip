@@ -13,10 +13,24 @@ namespace lddmm {
 
 constexpr int kPtThreads = 256;
 
+// Division of a point index by n3 and n2 with one multiply-high: for
+// 0 <= p < 2^31 and sh = ceil(log2 d), mag = floor(2^(31+sh)/d) + 1,
+// floor(p/d) = (p*mag) >> (31+sh) exactly (Granlund and Montgomery, "Division
+// by invariant integers using multiplication", 1994, Theorem 4.2 with N = 31).
+struct Divider {
+    unsigned mag, sh;  // sh >= 1 (d >= 2)
+};
+
 struct Grid3 {
     int n1, n2, n3;
     int N;
+    Divider by3, by2;
 };
+
+__device__ __forceinline__ unsigned divide(unsigned p, Divider d)
+{
+    return __umulhi(p, d.mag) >> (d.sh - 1);
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
 // XCD b % 8), each with its own L2.  Renumber them so that each XCD sweeps
@@ -32,15 +46,16 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 
 __device__ __forceinline__ int point_index()
 {
-    return xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
+    return xcd_block((int)blockIdx.x, (int)gridDim.x) * kPtThreads + (int)threadIdx.x;
 }
 
 __device__ __forceinline__ void point_coords(const Grid3 &g, int p, int &i, int &j, int &k)
 {
-    k = p % g.n3;
-    const int r = p / g.n3;
-    j = r % g.n2;
-    i = r / g.n2;
+    const unsigned r = divide((unsigned)p, g.by3);
+    k = p - (int)r * g.n3;
+    const unsigned q = divide(r, g.by2);
+    j = (int)r - (int)q * g.n2;
+    i = (int)q;
 }
 
 // Lagrange basis on the nodes -1, 0, 1, 2 at t in [0,1)
@@ -67,8 +82,13 @@ __device__ __forceinline__ int axis_stencil(int i, T d, int n, unsigned stride, 
     d = d >= -lim ? d : -lim;
     const T fl = floor(d);
     int b = i + (int)fl - 1;
-    b %= n;
-    if (b < 0) b += n;
+    if ((unsigned)(b + n) < (unsigned)(3 * n)) {  // |displacement| below n: one wrap
+        b = b < 0 ? b + n : b;
+        b = b >= n ? b - n : b;
+    } else {
+        b %= n;
+        if (b < 0) b += n;
+    }
     const int first = b;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -460,9 +480,17 @@ __global__ __launch_bounds__(kPtThreads) void k_direct(Grid3 g, const float *__r
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+static Divider divider(int d)
+{
+    unsigned sh = 0;
+    while ((1u << sh) < (unsigned)d) ++sh;
+    const unsigned long long mag = ((1ull << (31 + sh)) / (unsigned)d) + 1;
+    return Divider{(unsigned)mag, sh};
+}
+
 static Grid3 grid_of(const lddmm_plan *P)
 {
-    return Grid3{P->cfg.n[0], P->cfg.n[1], P->cfg.n[2], (int)P->N};
+    return Grid3{P->cfg.n[0], P->cfg.n[1], P->cfg.n[2], (int)P->N, divider(P->cfg.n[2]), divider(P->cfg.n[1])};
 }
 
 static dim3 blocks_of(const lddmm_plan *P)
