@@ -458,11 +458,28 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const char *__restrict__
 // ---------------------------------------------------------------------------
 struct ColDesc {
     long base_off;  // offset of the sub-array (main: 0, Nyquist plane: nrow*m3), in elements
-    long ostride;   // stride between outer indices (blockIdx.y)
+    long ostride;   // stride between outer indices
     long nstride;   // stride along the transformed line
     long cstride;   // stride between columns
     int ncols;      // columns per outer index
 };
+
+// Position of a column-pass workgroup.  Workgroups go round-robin to the 8
+// XCDs (linear id mod 8); renumbering the (x, y) plane of the grid gives each
+// XCD a contiguous run of column tiles, so the narrow column segments of
+// neighbouring tiles, which share 128-byte lines, meet in one L2.
+struct TilePos {
+    int x, y;
+};
+
+__device__ __forceinline__ TilePos tile_pos()
+{
+    const int gx = (int)gridDim.x, tot = gx * (int)gridDim.y;
+    int lin = (int)blockIdx.x + gx * (int)blockIdx.y;
+    const int per = tot >> 3;
+    if (lin < per * 8) lin = (lin & 7) * per + (lin >> 3);
+    return TilePos{lin % gx, lin / gx};
+}
 
 template <class C>
 __device__ __forceinline__ void tile_load(C *dst, const C *__restrict__ src, const ColDesc &d, int L,
@@ -498,9 +515,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(char *__restrict__ spe
     const int L = LF > 0 ? LF : rp.L;
     C *A = lds, *B = lds + L * TW;
     const int tid = threadIdx.x, nthr = kFftThreads;
+    const TilePos tp = tile_pos();
     C *base = reinterpret_cast<C *>(spec + (long)(slot0 + blockIdx.z) * slot_bytes) + d.base_off +
-              (long)blockIdx.y * d.ostride;
-    const int col0 = blockIdx.x * TW;
+              (long)tp.y * d.ostride;
+    const int col0 = tp.x * TW;
     tile_load(A, base, d, L, TW, logTW, col0, tid, nthr);
     __syncthreads();
     const C *res = lds_fft_any<INV, true, LF>(A, B, TW, logTW, 0, rp, tw, tid, nthr);
@@ -529,10 +547,11 @@ __device__ __forceinline__ double reg_symbol(const SymCtx &s, int l1, int l2, in
 }
 
 struct ColCtx {  // how a tile position maps to (l2, l3)
-    int nyq;     // 0: main array (columns are k3, blockIdx.y is k2); 1: Nyquist plane
+    int nyq;     // 0: main array (columns are k3, the outer index is k2); 1: Nyquist plane
+    int outer;   // outer index of the tile
     __device__ __forceinline__ void l23(const SymCtx &s, int col, int &l2, int &l3) const
     {
-        l2 = nyq ? col : (int)blockIdx.y;
+        l2 = nyq ? col : outer;
         l3 = nyq ? (s.n3 >> 1) : col;
     }
 };
@@ -552,14 +571,15 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_scalar(char *__restrict__ sp
     C *lds = reinterpret_cast<C *>(lds_raw);
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     C *A = lds, *B = lds + tile;
-    const int tid = threadIdx.x, nthr = kFftThreads, col0 = blockIdx.x * TW;
-    const long off = d.base_off + (long)blockIdx.y * d.ostride;
+    const TilePos tp = tile_pos();
+    const int tid = threadIdx.x, nthr = kFftThreads, col0 = tp.x * TW;
+    const long off = d.base_off + (long)tp.y * d.ostride;
     const C *src = reinterpret_cast<const C *>(spec + (long)(in0 + blockIdx.z) * slot_bytes) + off;
     float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + blockIdx.z) * slot_bytes) + off;
     tile_load(load_target(rp, A, B), src, d, L, TW, logTW, col0, tid, nthr);
     __syncthreads();
     lds_fft_any<false, true, LF>(load_target(rp, A, B), load_target(rp, B, A), TW, logTW, 0, rp, tw, tid, nthr);
-    const ColCtx cc{nyq};
+    const ColCtx cc{nyq, tp.y};
     for (int idx = tid; idx < tile; idx += nthr) {
         const int n = idx >> logTW, c = idx & (TW - 1);
         int l2, l3;
@@ -594,13 +614,14 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_grad(char *__restrict__ spec
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile;
     float2 *O = reinterpret_cast<float2 *>(WB + tile);  // three float2 tiles
     float2 *S = reinterpret_cast<float2 *>(WA);         // float scratch once WA/WB are free
-    const int tid = threadIdx.x, nthr = kFftThreads, col0 = blockIdx.x * TW;
-    const long off = d.base_off + (long)blockIdx.y * d.ostride;
+    const TilePos tp = tile_pos();
+    const int tid = threadIdx.x, nthr = kFftThreads, col0 = tp.x * TW;
+    const long off = d.base_off + (long)tp.y * d.ostride;
     const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(in0 + blockIdx.z) * slot_bytes) + off;
     tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
     __syncthreads();
     lds_fft_any<false, true, LF>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
-    const ColCtx cc{nyq};
+    const ColCtx cc{nyq, tp.y};
     for (int idx = tid; idx < tile; idx += nthr) {
         const int n = idx >> logTW, c = idx & (TW - 1);
         int l2, l3;
@@ -629,9 +650,10 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_div(char *__restrict__ spec,
     extern __shared__ char lds_raw[];
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile, *ACC = WB + tile;
-    const int tid = threadIdx.x, nthr = kFftThreads, col0 = blockIdx.x * TW;
-    const long off = d.base_off + (long)blockIdx.y * d.ostride;
-    const ColCtx cc{nyq};
+    const TilePos tp = tile_pos();
+    const int tid = threadIdx.x, nthr = kFftThreads, col0 = tp.x * TW;
+    const long off = d.base_off + (long)tp.y * d.ostride;
+    const ColCtx cc{nyq, tp.y};
     for (int q = 0; q < 3; ++q) {
         const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(in0 + 3 * blockIdx.z + q) * slot_bytes) + off;
         tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
@@ -675,8 +697,9 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     float2 *T = reinterpret_cast<float2 *>(lds_raw);  // three field tiles, then scratch
     float2 *S = T + 3 * tile;
-    const int tid = threadIdx.x, nthr = kFftThreads, col0 = blockIdx.x * TW;
-    const long off = d.base_off + (long)blockIdx.y * d.ostride;
+    const TilePos tp = tile_pos();
+    const int tid = threadIdx.x, nthr = kFftThreads, col0 = tp.x * TW;
+    const long off = d.base_off + (long)tp.y * d.ostride;
     for (int q = 0; q < 3; ++q) {
         const float2 *src = reinterpret_cast<const float2 *>(spec + (long)(in0 + 3 * blockIdx.z + q) * slot_bytes) + off;
         float2 *home = T + q * tile;
@@ -684,7 +707,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
         __syncthreads();
         lds_fft_any<false, true, LF>(load_target(rp, home, S), load_target(rp, S, home), TW, logTW, 0, rp, twf, tid, nthr);
     }
-    const ColCtx cc{nyq};
+    const ColCtx cc{nyq, tp.y};
     for (int idx = tid; idx < tile; idx += nthr) {
         const int n = idx >> logTW, c = idx & (TW - 1);
         int l2, l3;
@@ -724,9 +747,10 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_assemble(char *__restrict__ 
     float2 *FA = reinterpret_cast<float2 *>(WA), *FB = FA + tile;  // float view of the working pair
     float2 *O = reinterpret_cast<float2 *>(WB + tile);             // three output tiles
     float2 *Sd = O + 3 * tile;                                     // Leray accumulator
-    const int tid = threadIdx.x, nthr = kFftThreads, col0 = blockIdx.x * TW;
-    const long off = d.base_off + (long)blockIdx.y * d.ostride;
-    const ColCtx cc{nyq};
+    const TilePos tp = tile_pos();
+    const int tid = threadIdx.x, nthr = kFftThreads, col0 = tp.x * TW;
+    const long off = d.base_off + (long)tp.y * d.ostride;
+    const ColCtx cc{nyq, tp.y};
     for (int q = 0; q < 3; ++q) {
         const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(w0 + q) * slot_bytes) + off;
         tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
