@@ -249,8 +249,11 @@ lddmm_status lddmm_batch_gn_iterate(lddmm_batch *batch, int32_t max_pcg, double 
 lddmm_status lddmm_autotune(lddmm_plan *plan);
 /* Override the gather strategy of the interpolation kernels: 0 direct
  * (one thread per point, stencil loads through L1/L2), 1 and 2 LDS-staged
- * tiles of 4x4x64 and 8x8x64 points, -1 the default heuristic.  lddmm_autotune
- * picks among 0..2 by timing once the plan has a velocity. */
+ * boxes for tiles of 2x4x64 and 4x4x64 points (points whose stencil leaves
+ * the box load from global memory), -1 the default heuristic.  Every
+ * strategy computes the same tensor-product sum in the same order.
+ * lddmm_autotune picks among 0..2 by timing once the plan has a velocity.
+ * EINVAL for a mode outside -1..2. */
 lddmm_status lddmm_set_gather_mode(lddmm_plan *plan, int32_t mode);
 /* NUL-terminated report of the tile shapes in use (len bytes at most). */
 lddmm_status lddmm_tuning(lddmm_plan *plan, char *buf, size_t len);

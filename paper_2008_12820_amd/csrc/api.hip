@@ -146,7 +146,6 @@ static Layout make_layout(const lddmm_config *cfg)
     L.add(spectral_slots(cfg) * 2 * spec);  // 22 spec (slots sized for FP64)
     L.add(sizeof(double) * kRedBlocks);     // 23 red
     L.add(sizeof(double) * kNumScalars);    // 24 dscal
-    L.add(sizeof(int) * (N / 16 + 64));     // 25 gather tile flags (>= number of 4x4x64 tiles)
     return L;
 }
 
@@ -491,7 +490,6 @@ lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan
         P->slot_bytes = (long)sizeof(double2) * cfg->n[0] * cfg->n[1] * (cfg->n[2] / 2 + 1);
         P->red = (double *)(a + L.off[23]);
         P->dscal = (double *)(a + L.off[24]);
-        P->tile_flags = (int *)(a + L.off[25]);
         check_hip(hipHostMalloc((void **)&P->hscal, sizeof(double) * kNumScalars, hipHostMallocDefault),
                   "hipHostMalloc");
         fft_init(P);

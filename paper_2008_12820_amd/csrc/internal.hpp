@@ -83,12 +83,11 @@ struct lddmm_plan {
     long slot_bytes = 0;
     int nspec = 0;
     double *red = nullptr;   // reduction partials
-    int *tile_flags = nullptr;  // per gather tile: 1 when its LDS box did not fit
     double *dscal = nullptr; // device scalars
     double *hscal = nullptr; // pinned host mirror
 
     int have_images = 0, have_velocity = 0, have_grad = 0, have_matvec = 0;
-    int gather_mode = -1;    // 0 direct, 1 tiled 4x4x64, 2 tiled 8x8x64, -1 heuristic
+    int gather_mode = -1;    // 0 direct, 1 box tiles 2x4x64, 2 box tiles 4x4x64, -1 heuristic
     int gather_tuned = 0;
     float gather_ms[1] = {0.f};
     double g0norm = 0.0;

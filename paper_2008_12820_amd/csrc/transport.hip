@@ -210,30 +210,37 @@ __global__ __launch_bounds__(kPtThreads) void k_body_force(const float *__restri
 }
 
 // ---------------------------------------------------------------------------
-// LDS-tiled gathers.  A workgroup of NW wavefronts owns an output tile of
-// T1 x T2 x 64 points (x3 fastest, one wavefront per x3 row segment).  It
-// reduces the stencil extents of its points to one box, stages that box of
-// the source field (periodically wrapped) in LDS with coalesced row loads,
-// and interpolates from LDS, where the nodes never wrap.  A tile whose box
-// does not fit the LDS capacity (a displacement far beyond the halo) is
-// flagged and finished by a second launch with direct global gathers; the
-// decision is per workgroup and on the device.  Both paths add in the same
-// order.
+// Box gathers.  A 256-thread workgroup owns an output tile of T1 x T2 rows of
+// 64 x3 points; wavefront w takes the rows w, w + 4, ... (PPT points per
+// thread).  The workgroup reduces the stencil extents of its points and
+// stages that box of every source field, periodically wrapped, in LDS with
+// coalesced row loads; the stencils are then read from LDS, where nodes never
+// wrap.  The box capacity is fixed, (T1+3+H) x (T2+3+H) rows of kPad3 floats:
+// a point whose stencil is not inside the staged box (displacements varying
+// across the tile by more than H voxels along x1 or x2, or by more than
+// kPad3 - 67 along x3) gathers from global memory instead.
 // ---------------------------------------------------------------------------
-constexpr int kT3 = 64;   // tile extent along x3
-constexpr int kHalo = 4;  // LDS box sized for stencils reaching this far past the tile
+constexpr int kT3 = 64;    // tile extent along x3 (one wavefront)
+constexpr int kBoxH = 1;   // tolerated spread of floor(d) across the tile, x1 and x2
+constexpr int kPad3 = 72;  // box row pitch along x3 (floats)
 
 template <int T1, int T2>
-struct TileCfg {
-    static constexpr int NW = (T1 * T2 >= 64) ? 8 : 4;  // wavefronts per workgroup
-    static constexpr int PTS = T1 * T2 / NW;            // points per thread
-    static constexpr int NP = T1 * T2 * kT3;            // points per tile
-    static constexpr int CAP = (T1 + 2 * kHalo) * (T2 + 2 * kHalo) * (kT3 + 2 * kHalo);  // box floats
-    // LDS floats: box, the three displacement components and nf-1 partial fields
-    static constexpr int lds_floats(int nf) { return CAP + (3 + nf - 1) * NP; }
+struct BoxCfg {
+    static constexpr int PPT = T1 * T2 / 4;  // points per thread
+    static constexpr int BR1 = T1 + 3 + kBoxH, BR2 = T2 + 3 + kBoxH;
+    static constexpr int CAP = BR1 * BR2 * kPad3;  // floats per field
 };
 
-__device__ __forceinline__ int wrap1(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+// periodic wrap of any index: one step for [-n, 2n), a modulo beyond
+__device__ __forceinline__ int wrapg(int x, int n)
+{
+    if ((unsigned)(x + n) < (unsigned)(3 * n)) {
+        x = x < 0 ? x + n : x;
+        return x >= n ? x - n : x;
+    }
+    x %= n;
+    return x < 0 ? x + n : x;
+}
 
 __device__ __forceinline__ float clamp_disp(float d)
 {
@@ -315,80 +322,43 @@ struct EpiIncInit {  // incremental-state sources (see k_incstate_init)
     }
 };
 
-// Tiles whose box does not fit are finished by a second launch with direct
-// global gathers; the tiled kernel leaves a flag per tile for it.
 template <int T1, int T2, class Epi>
-__global__ __launch_bounds__((64 * TileCfg<T1, T2>::NW)) void k_tiled_fixup(Grid3 g,
-                                                                             const float *__restrict__ disp,
-                                                                             Epi epi, int nt1, int nt2, int nt3,
-                                                                             const int *__restrict__ flags)
+__global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ disp, Epi epi, int nt2, int nt3)
 {
-    using TC = TileCfg<T1, T2>;
-    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    if (flags[tb] == 0) return;
-    const int grp = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int t3 = tb % nt3, rr = tb / nt3, t2 = rr % nt2, t1 = rr / nt2;
-    const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
-    const long N = g.N;
-    for (int q = 0; q < TC::PTS; ++q) {
-        const int idx = grp + TC::NW * q, i = i0 + idx / T2, j = j0 + idx % T2;
-        if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
-        const long p = ((long)i * g.n2 + j) * g.n3 + k;
-        Stencil<float> s;
-        make_stencil<float>(g, i, j, k, disp[p], disp[N + p], disp[2 * N + p], s);
-        float v[Epi::NF];
-#pragma unroll
-        for (int f = 0; f < Epi::NF; ++f) v[f] = gather<float>(epi.field(f), s);
-        epi.finish(p, v);
-    }
-}
-
-template <int T1, int T2, class Epi>
-__global__ __launch_bounds__((64 * TileCfg<T1, T2>::NW)) void k_tiled(Grid3 g, const float *__restrict__ disp,
-                                                                       Epi epi, int nt1, int nt2, int nt3,
-                                                                       int *__restrict__ flags)
-{
-    using TC = TileCfg<T1, T2>;
-    constexpr int PTS = TC::PTS, NW = TC::NW, NP = TC::NP, NF = Epi::NF;
-    extern __shared__ float lds[];
-    float *box = lds;                 // CAP
-    float *dsh = lds + TC::CAP;       // 3 x NP displacements of the tile's points
-    float *vsh = dsh + 3 * NP;        // (NF-1) x NP gathered values of the earlier fields
-    __shared__ int ext[6];
-    const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+    using BC = BoxCfg<T1, T2>;
+    constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, CAP = BC::CAP, NF = Epi::NF;
+    constexpr int S1 = BR2 * kPad3;  // box stride along x1 (x2: kPad3)
+    extern __shared__ float box[];   // NF x CAP
+    __shared__ int red[4][6];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int t3 = tb % nt3, rr = tb / nt3, t2 = rr % nt2, t1 = rr / nt2;
     const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
     const long N = g.N;
-    if (tid < 6) ext[tid] = tid < 3 ? 0x7fffffff : (int)0x80000000;
-    __syncthreads();
-    // tile entry e = grp + NW q (q < PTS) is point (i0 + e / T2, j0 + e % T2, k);
-    // its LDS slot is e * 64 + lane
+    float d1[PPT], d2[PPT], d3[PPT];
     int lo1 = 0x7fffffff, lo2 = 0x7fffffff, lo3 = 0x7fffffff;
     int hi1 = (int)0x80000000, hi2 = (int)0x80000000, hi3 = (int)0x80000000;
 #pragma unroll
-    for (int q = 0; q < PTS; ++q) {
-        const int e = grp + NW * q, i = i0 + e / T2, j = j0 + e % T2, slot = e * 64 + lane;
-        float d1 = 0.f, d2 = 0.f, d3 = 0.f;
+    for (int q = 0; q < PPT; ++q) {
+        const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+        d1[q] = d2[q] = d3[q] = 0.f;
         if (i < g.n1 && j < g.n2 && k < g.n3) {
             const long p = ((long)i * g.n2 + j) * g.n3 + k;
-            d1 = clamp_disp(disp[p]);
-            d2 = clamp_disp(disp[N + p]);
-            d3 = clamp_disp(disp[2 * N + p]);
-            const int b1 = i + (int)floorf(d1) - 1, b2 = j + (int)floorf(d2) - 1, b3 = k + (int)floorf(d3) - 1;
+            d1[q] = clamp_disp(disp[p]);
+            d2[q] = clamp_disp(disp[N + p]);
+            d3[q] = clamp_disp(disp[2 * N + p]);
+            const int b1 = i + (int)floorf(d1[q]) - 1, b2 = j + (int)floorf(d2[q]) - 1,
+                      b3 = k + (int)floorf(d3[q]) - 1;
             lo1 = min(lo1, b1);
-            hi1 = max(hi1, b1 + 3);
+            hi1 = max(hi1, b1);
             lo2 = min(lo2, b2);
-            hi2 = max(hi2, b2 + 3);
+            hi2 = max(hi2, b2);
             lo3 = min(lo3, b3);
-            hi3 = max(hi3, b3 + 3);
+            hi3 = max(hi3, b3);
         }
-        dsh[slot] = d1;
-        dsh[NP + slot] = d2;
-        dsh[2 * NP + slot] = d3;
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {  // wavefront reduction, then one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
         lo1 = min(lo1, __shfl_xor(lo1, off));
         lo2 = min(lo2, __shfl_xor(lo2, off));
         lo3 = min(lo3, __shfl_xor(lo3, off));
@@ -397,66 +367,88 @@ __global__ __launch_bounds__((64 * TileCfg<T1, T2>::NW)) void k_tiled(Grid3 g, c
         hi3 = max(hi3, __shfl_xor(hi3, off));
     }
     if (lane == 0) {
-        atomicMin(&ext[0], lo1);
-        atomicMin(&ext[1], lo2);
-        atomicMin(&ext[2], lo3);
-        atomicMax(&ext[3], hi1);
-        atomicMax(&ext[4], hi2);
-        atomicMax(&ext[5], hi3);
+        red[w][0] = lo1;
+        red[w][1] = lo2;
+        red[w][2] = lo3;
+        red[w][3] = hi1;
+        red[w][4] = hi2;
+        red[w][5] = hi3;
     }
     __syncthreads();
-    const int L1 = ext[0], L2 = ext[1], L3 = ext[2];
-    const int B1 = ext[3] - L1 + 1, B2 = ext[4] - L2 + 1, B3 = ext[5] - L3 + 1;
-    // the box may be wider than the grid (periodic copies repeat); wrap1 needs [-n, 2n)
-    const bool fits = ext[3] >= L1 && (long)B1 * B2 * B3 <= TC::CAP && L1 >= -g.n1 && L2 >= -g.n2 &&
-                      L3 >= -g.n3 && ext[3] < 2 * g.n1 && ext[4] < 2 * g.n2 && ext[5] < 2 * g.n3;
-    if (tid == 0) flags[tb] = fits ? 0 : 1;
-    if (!fits) return;  // uniform over the workgroup; finished by k_tiled_fixup
-    const int S2 = B3, S1 = B2 * B3;  // box strides
+    const int L1 = min(min(red[0][0], red[1][0]), min(red[2][0], red[3][0]));
+    const int L2 = min(min(red[0][1], red[1][1]), min(red[2][1], red[3][1]));
+    const int L3 = min(min(red[0][2], red[1][2]), min(red[2][2], red[3][2]));
+    const int H1 = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3]));
+    const int H2 = max(max(red[0][4], red[1][4]), max(red[2][4], red[3][4]));
+    const int H3 = max(max(red[0][5], red[1][5]), max(red[2][5], red[3][5]));
+    if (L1 > H1) return;  // no point of the tile is inside the grid (uniform)
+    // staged extents: the stencil box, cut to the capacity (64-bit: a clamped
+    // displacement spans up to 2^21 nodes)
+    const int B1 = (int)min((long)H1 + 4 - L1, (long)BR1);
+    const int B2 = (int)min((long)H2 + 4 - L2, (long)BR2);
+    const int B3 = (int)min((long)H3 + 4 - L3, (long)kPad3);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const float *__restrict__ src = epi.field(f);
-        const int rows = B1 * B2;
-        for (int row = grp; row < rows; row += NW) {
-            const int a = row / B2, b = row - a * B2;
-            const float *grow = src + ((long)wrap1(L1 + a, g.n1) * g.n2 + wrap1(L2 + b, g.n2)) * g.n3;
-            for (int c = lane; c < B3; c += 64) box[row * B3 + c] = grow[wrap1(L3 + c, g.n3)];
+        float *bx = box + f * CAP;
+        for (int e = tid; e < CAP; e += 256) {
+            const int r = e / kPad3, c = e - r * kPad3, a = r / BR2, b = r - a * BR2;
+            if (a < B1 && b < B2 && c < B3)
+                bx[e] = src[((long)wrapg(L1 + a, g.n1) * g.n2 + wrapg(L2 + b, g.n2)) * g.n3 + wrapg(L3 + c, g.n3)];
         }
-        __syncthreads();
-#pragma unroll 1
-        for (int q = 0; q < PTS; ++q) {
-            const int e = grp + NW * q, i = i0 + e / T2, j = j0 + e % T2, slot = e * 64 + lane;
-            if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
-            const float d1 = dsh[slot], d2 = dsh[NP + slot], d3 = dsh[2 * NP + slot];
-            const float f1 = floorf(d1), f2 = floorf(d2), f3 = floorf(d3);
-            float w1[4], w2[4], w3[4];
-            lagrange4<float>(d1 - f1, w1);
-            lagrange4<float>(d2 - f2, w2);
-            lagrange4<float>(d3 - f3, w3);
-            const int o = (i + (int)f1 - 1 - L1) * S1 + (j + (int)f2 - 1 - L2) * S2 + (k + (int)f3 - 1 - L3);
-            float acc = 0.f;
+    }
+    __syncthreads();
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                float acc2 = 0.f;
+    for (int q = 0; q < PPT; ++q) {
+        const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+        if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
+        const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
+        float w1[4], w2[4], w3[4];
+        lagrange4<float>(d1[q] - f1, w1);
+        lagrange4<float>(d2[q] - f2, w2);
+        lagrange4<float>(d3[q] - f3, w3);
+        const int b1 = i + (int)f1 - 1, b2 = j + (int)f2 - 1, b3 = k + (int)f3 - 1;
+        const int o1 = b1 - L1, o2 = b2 - L2, o3 = b3 - L3;  // >= 0 by the reduction
+        float v[NF];
+        if (o1 <= B1 - 4 && o2 <= B2 - 4 && o3 <= B3 - 4) {
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const float *row = box + o + a * S1 + b * S2;
-                    const float r = row[0] * w3[0] + row[1] * w3[1] + row[2] * w3[2] + row[3] * w3[3];
-                    acc2 += w2[b] * r;
+            for (int f = 0; f < NF; ++f) {
+                const float *bx = box + f * CAP + o1 * S1 + o2 * kPad3 + o3;
+                float acc = 0.f;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    float acc2 = 0.f;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const float *row = bx + a * S1 + b * kPad3;
+                        const float r = row[0] * w3[0] + row[1] * w3[1] + row[2] * w3[2] + row[3] * w3[3];
+                        acc2 += w2[b] * r;
+                    }
+                    acc += w1[a] * acc2;
                 }
-                acc += w1[a] * acc2;
+                v[f] = acc;
             }
-            if (f < NF - 1) {
-                vsh[f * NP + slot] = acc;
-            } else {
-                float v[NF];
-#pragma unroll
-                for (int u = 0; u < NF - 1; ++u) v[u] = vsh[u * NP + slot];
-                v[NF - 1] = acc;
-                epi.finish(((long)i * g.n2 + j) * g.n3 + k, v);
+        } else {  // stencil outside the staged box: global loads, wrapped per node
+#pragma unroll 1
+            for (int f = 0; f < NF; ++f) {
+                const float *__restrict__ src = epi.field(f);
+                float acc = 0.f;
+#pragma unroll 1
+                for (int a = 0; a < 4; ++a) {
+                    const long ra = (long)wrapg(b1 + a, g.n1) * g.n2;
+                    float acc2 = 0.f;
+                    for (int b = 0; b < 4; ++b) {
+                        const float *row = src + (ra + wrapg(b2 + b, g.n2)) * g.n3;
+                        const float r = row[wrapg(b3, g.n3)] * w3[0] + row[wrapg(b3 + 1, g.n3)] * w3[1] +
+                                        row[wrapg(b3 + 2, g.n3)] * w3[2] + row[wrapg(b3 + 3, g.n3)] * w3[3];
+                        acc2 += w2[b] * r;
+                    }
+                    acc += w1[a] * acc2;
+                }
+                v[f] = acc;
             }
         }
-        __syncthreads();
+        epi.finish(((long)i * g.n2 + j) * g.n3 + k, v);
     }
 }
 
@@ -506,38 +498,29 @@ void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa)
     check_hip(hipGetLastError(), "k_departure");
 }
 
-// gather strategy: P->gather_mode 0 direct, 1 tiled 4x4x64, 2 tiled 8x8x64;
-// -1 before tuning: tiled, 8x8 on large grids, 4x4 when that leaves too few
-// workgroups to fill the chip
+// gather strategy: P->gather_mode 0 direct, 1 box tiles 2x4x64, 2 box tiles
+// 4x4x64; -1 before tuning: 4x4 tiles when they leave enough workgroups to
+// fill the chip, else 2x4
 static int gather_mode(const lddmm_plan *P)
 {
     if (P->gather_mode >= 0) return P->gather_mode;
     const long n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
-    const long tiles8 = ((n1 + 7) / 8) * ((n2 + 7) / 8) * ((n3 + kT3 - 1) / kT3);
-    return tiles8 >= 2048 ? 2 : 1;
+    const long tiles = ((n1 + 3) / 4) * ((n2 + 3) / 4) * ((n3 + kT3 - 1) / kT3);
+    return tiles >= 4096 ? 2 : 1;
 }
 
 template <int T1, int T2, class Epi>
-static void launch_tiled(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
+static void launch_box(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
 {
     const int n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
     const int nt1 = (n1 + T1 - 1) / T1, nt2 = (n2 + T2 - 1) / T2, nt3 = (n3 + kT3 - 1) / kT3;
-    const size_t lds = sizeof(float) * TileCfg<T1, T2>::lds_floats(Epi::NF);
-    static bool attr = false;
-    if (!attr) {
-        check_hip(hipFuncSetAttribute((const void *)k_tiled<T1, T2, Epi>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
-                  "hipFuncSetAttribute");
-        attr = true;
-    }
+    const size_t lds = sizeof(float) * BoxCfg<T1, T2>::CAP * Epi::NF;
+    static_assert(sizeof(float) * BoxCfg<4, 4>::CAP * 3 <= 64 * 1024, "box exceeds the default LDS limit");
     const unsigned ntiles = (unsigned)((long)nt1 * nt2 * nt3);
     Scope s(P, kid);
-    hipLaunchKernelGGL((k_tiled<T1, T2, Epi>), dim3(ntiles), dim3(64 * TileCfg<T1, T2>::NW), lds, P->stream,
-                       grid_of(P), disp, epi, nt1, nt2, nt3, P->tile_flags);
-    check_hip(hipGetLastError(), "k_tiled");
-    hipLaunchKernelGGL((k_tiled_fixup<T1, T2, Epi>), dim3(ntiles), dim3(64 * TileCfg<T1, T2>::NW), 0,
-                       P->stream, grid_of(P), disp, epi, nt1, nt2, nt3, (const int *)P->tile_flags);
-    check_hip(hipGetLastError(), "k_tiled_fixup");
+    hipLaunchKernelGGL((k_box<T1, T2, Epi>), dim3(ntiles), dim3(256), lds, P->stream, grid_of(P), disp, epi, nt2,
+                       nt3);
+    check_hip(hipGetLastError(), "k_box");
 }
 
 template <class Epi>
@@ -550,8 +533,8 @@ static void tiled(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
         check_hip(hipGetLastError(), "k_direct");
         break;
     }
-    case 1: launch_tiled<4, 4>(P, disp, epi, kid); break;
-    default: launch_tiled<8, 8>(P, disp, epi, kid); break;
+    case 1: launch_box<2, 4>(P, disp, epi, kid); break;
+    default: launch_box<4, 4>(P, disp, epi, kid); break;
     }
 }
 

@@ -54,14 +54,29 @@ def test_interp_matches_oracle(shape):
     f = rng.standard_normal((2,) + shape).astype(np.float32)
     disp = rng.uniform(-7.5, 7.5, (3,) + shape).astype(np.float32)
     disp[:, 0, 0, 0] = [shape[0] + 0.25, -shape[1] - 0.5, 2 * shape[2] - 0.1]  # beyond one period
+    # second half of the grid: a smooth displacement, so that the LDS-staged
+    # strategies take their box path there and the global fallback elsewhere
+    half = shape[0] // 2
+    xs = np.arange(shape[0])[half:, None, None] * (2 * np.pi / shape[0])
+    ys = np.arange(shape[1])[None, :, None] * (2 * np.pi / shape[1])
+    zs = np.arange(shape[2])[None, None, :] * (2 * np.pi / shape[2])
+    disp[0, half:] = 2.3 * np.sin(ys + zs)
+    disp[1, half:] = -1.7 * np.cos(xs + zs)
+    disp[2, half:] = 3.1 * np.sin(xs + ys) + 0.5
     P = Plan(shape, 1)
-    got = to_np(P.interp(to_dev(f), to_dev(disp)))
     x = oracle.grid_points(shape)
     h = np.array([2 * np.pi / n for n in shape]).reshape(3, 1, 1, 1)
     y = (x + h * synth.f64(disp)).reshape(3, -1)
     ref = oracle.interp(synth.f64(f), y).reshape((2,) + shape)
-    assert rel(got, ref) < 1e-6
-    assert np.abs(got - ref).max() < 1e-5
+    outs = []
+    for mode in (-1, 0, 1, 2):  # default, direct, box tiles 2x4x64 and 4x4x64
+        P.set_gather_mode(mode)
+        got = to_np(P.interp(to_dev(f), to_dev(disp)))
+        assert rel(got, ref) < 1e-6, mode
+        assert np.abs(got - ref).max() < 1e-5, mode
+        outs.append(got)
+    for got in outs[2:]:
+        assert rel(got, outs[1]) < 1e-6
 
 
 @pytest.mark.parametrize("shape,nt", [((16, 16, 16), 4), ((24, 20, 30), 3), ((32, 32, 32), 4)])
