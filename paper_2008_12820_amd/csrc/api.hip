@@ -27,7 +27,7 @@ const char *kernel_name(int id)
     static const char *names[K_NUM_KERNELS] = {
         "r2c_x3", "fft_cols", "x1_symbol", "c2r_x3", "departure", "state_step", "gather_vec",
         "adj_coef", "adj_step", "incstate_init", "incstate_step", "body_force", "dot", "vecop",
-        "pack"};
+        "pack", "inc_sources"};
     return (id >= 0 && id < K_NUM_KERNELS) ? names[id] : "unknown";
 }
 

@@ -209,6 +209,37 @@ __global__ __launch_bounds__(kPtThreads) void k_body_force(const float *__restri
     for (int c = 0; c < 3; ++c) b[c * N + p] = dt * acc[c];
 }
 
+// Incremental-state sources from the increment vt and its values vX at the
+// departure points: s_j = vX . I[G_j](X) + vt . G_{j+1}; m~_1 = -dt/2 s_0 and
+// s_1 .. s_{nt-1} are stored.  Four points per thread (16-byte accesses).
+__global__ __launch_bounds__(kPtThreads) void k_inc_sources(const float4 *__restrict__ vt,
+                                                            const float4 *__restrict__ vX,
+                                                            const float4 *__restrict__ GX,
+                                                            const float4 *__restrict__ G,
+                                                            float4 *__restrict__ mt1, float4 *__restrict__ src,
+                                                            long N4, int nt, float hdt)
+{
+    const long p = (long)xcd_block((int)blockIdx.x, (int)gridDim.x) * kPtThreads + threadIdx.x;
+    if (p >= N4) return;
+    const float4 v0 = vt[p], v1 = vt[N4 + p], v2 = vt[2 * N4 + p];
+    const float4 x0 = vX[p], x1 = vX[N4 + p], x2 = vX[2 * N4 + p];
+    for (int j = 0; j < nt; ++j) {
+        const float4 *gx = GX + (long)j * 3 * N4;
+        const float4 *g1 = G + (long)(j + 1) * 3 * N4;
+        const float4 a0 = gx[p], a1 = gx[N4 + p], a2 = gx[2 * N4 + p];
+        const float4 b0 = g1[p], b1 = g1[N4 + p], b2 = g1[2 * N4 + p];
+        float4 s;
+        s.x = (x0.x * a0.x + x1.x * a1.x + x2.x * a2.x) + (v0.x * b0.x + v1.x * b1.x + v2.x * b2.x);
+        s.y = (x0.y * a0.y + x1.y * a1.y + x2.y * a2.y) + (v0.y * b0.y + v1.y * b1.y + v2.y * b2.y);
+        s.z = (x0.z * a0.z + x1.z * a1.z + x2.z * a2.z) + (v0.z * b0.z + v1.z * b1.z + v2.z * b2.z);
+        s.w = (x0.w * a0.w + x1.w * a1.w + x2.w * a2.w) + (v0.w * b0.w + v1.w * b1.w + v2.w * b2.w);
+        if (j == 0)
+            mt1[p] = make_float4(-hdt * s.x, -hdt * s.y, -hdt * s.z, -hdt * s.w);
+        else
+            src[(long)(j - 1) * N4 + p] = s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Box gathers.  A 256-thread workgroup owns an output tile of T1 x T2 rows of
 // 64 x3 points; wavefront w takes the rows w, w + 4, ... (PPT points per
@@ -298,30 +329,6 @@ struct EpiVec3 {  // three fields (stride N): out_c = I[src_c]
         dst[2 * N + p] = v[2];
     }
 };
-struct EpiIncInit {  // incremental-state sources (see k_incstate_init)
-    static constexpr int NF = 3;
-    const float *vt, *GX, *G;
-    float *mt1, *src;
-    long N;
-    int nt;
-    float dt;
-    __device__ const float *field(int f) const { return vt + f * N; }
-    __device__ void finish(long p, const float *vX) const
-    {
-        const float vp0 = vt[p], vp1 = vt[N + p], vp2 = vt[2 * N + p];
-        for (int j = 0; j < nt; ++j) {
-            const float *gx = GX + (long)j * 3 * N;
-            const float *g1 = G + (long)(j + 1) * 3 * N;
-            const float a = vX[0] * gx[p] + vX[1] * gx[N + p] + vX[2] * gx[2 * N + p];
-            const float b = vp0 * g1[p] + vp1 * g1[N + p] + vp2 * g1[2 * N + p];
-            if (j == 0)
-                mt1[p] = -0.5f * dt * (a + b);
-            else
-                src[(long)(j - 1) * N + p] = a + b;
-        }
-    }
-};
-
 template <int T1, int T2, class Epi>
 __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ disp, Epi epi, int nt2, int nt3)
 {
@@ -387,14 +394,38 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
     const int B1 = (int)min((long)H1 + 4 - L1, (long)BR1);
     const int B2 = (int)min((long)H2 + 4 - L2, (long)BR2);
     const int B3 = (int)min((long)H3 + 4 - L3, (long)kPad3);
+    // Staging: wavefront w loads the box rows r = w, w + 4, ... (row r is
+    // (a, b) = (r / BR2, r % BR2)); a row's source pointer is uniform over the
+    // wavefront, so its wrap and address arithmetic run on the scalar unit.
+    // The x3 wrap of a lane's two columns is the same for every row.
+    constexpr int RPW = (BR1 * BR2 + 3) / 4;  // rows per wavefront
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const int c1 = lane + 64;
+    const bool has0 = lane < B3, has1 = c1 < B3;
+    const unsigned k0 = (unsigned)wrapg(L3 + lane, g.n3), k1 = (unsigned)wrapg(L3 + c1, g.n3);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const float *__restrict__ src = epi.field(f);
         float *bx = box + f * CAP;
-        for (int e = tid; e < CAP; e += 256) {
-            const int r = e / kPad3, c = e - r * kPad3, a = r / BR2, b = r - a * BR2;
-            if (a < B1 && b < B2 && c < B3)
-                bx[e] = src[((long)wrapg(L1 + a, g.n1) * g.n2 + wrapg(L2 + b, g.n2)) * g.n3 + wrapg(L3 + c, g.n3)];
+        float r0[RPW], r1[RPW];
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int r = wu + 4 * q, a = r / BR2, b = r - a * BR2;
+            r0[q] = r1[q] = 0.f;
+            if (a < B1 && b < B2) {
+                const float *grow = src + ((long)wrapg(L1 + a, g.n1) * g.n2 + wrapg(L2 + b, g.n2)) * g.n3;
+                if (has0) r0[q] = grow[k0];
+                if (has1) r1[q] = grow[k1];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int r = wu + 4 * q, a = r / BR2, b = r - a * BR2;
+            if (a < B1 && b < B2) {
+                float *brow = bx + r * kPad3;
+                if (has0) brow[lane] = r0[q];
+                if (has1) brow[c1] = r1[q];
+            }
         }
     }
     __syncthreads();
@@ -589,9 +620,18 @@ void launch_adj_step(lddmm_plan *P, const float *lin, float *lout, float scale)
     tiled(P, P->dXa, EpiAdj{lin, P->coef, lout, scale}, K_ADJ_STEP);
 }
 
+// vX = vt(X) is staged in the body-force buffer, which the matvec writes
+// only later
 void launch_incstate_init(lddmm_plan *P, const float *vt, float *mt1)
 {
-    tiled(P, P->dX, EpiIncInit{vt, P->GX, P->G, mt1, P->src, P->N, P->nt, (float)P->dt}, K_INCSTATE_INIT);
+    const long N = P->N, N4 = N / 4;
+    float *vX = P->b;
+    tiled(P, P->dX, EpiVec3{vt, vX, N}, K_INCSTATE_INIT);
+    Scope s(P, K_INC_SOURCES);
+    hipLaunchKernelGGL(k_inc_sources, dim3((unsigned)((N4 + kPtThreads - 1) / kPtThreads)), dim3(kPtThreads), 0,
+                       P->stream, (const float4 *)vt, (const float4 *)vX, (const float4 *)P->GX,
+                       (const float4 *)P->G, (float4 *)mt1, (float4 *)P->src, N4, P->nt, 0.5f * (float)P->dt);
+    check_hip(hipGetLastError(), "k_inc_sources");
 }
 
 void launch_incstate_step(lddmm_plan *P, const float *min, const float *sj, float *mout)
