@@ -33,6 +33,7 @@
 #include <set>
 #include <sstream>
 #include <string>
+#include <type_traits>
 
 namespace lddmm {
 
@@ -164,6 +165,147 @@ __device__ __forceinline__ void dft_small(C *v)
     else if constexpr (R == 8) dft8<C, INV>(v);
     else if constexpr (R == 3) dft3<C, INV>(v);
     else dft5<C, INV>(v);
+}
+
+// 16-point DFT in registers, natural order in and out: DFT4 over the four
+// stride-4 subsequences, twiddles W16^(n1 k2), DFT4 across, 4x4 transpose
+template <class C, bool INV>
+__device__ __forceinline__ void dft16(C *v)
+{
+    using R = typename RealOf<C>::type;
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) dft4<C, INV>(v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]);
+    // Y[n1][k2] sits at v[n1 + 4 k2]; W16^m = cos(pi m / 8) + sg i sin(pi m / 8)
+    const R c1 = R(0.92387953251128675613), s1 = R(0.38268343236508977173), h = R(0.70710678118654752440);
+    const R sg = INV ? R(1) : R(-1);
+    v[5] = mul(v[5], mk<C>(c1, sg * s1));     // m = 1
+    v[9] = mul(v[9], mk<C>(h, sg * h));       // m = 2
+    v[13] = mul(v[13], mk<C>(s1, sg * c1));   // m = 3
+    v[6] = mul(v[6], mk<C>(h, sg * h));       // m = 2
+    v[10] = mul_mi<C, INV>(v[10]);            // m = 4
+    v[14] = mul(v[14], mk<C>(-h, sg * h));    // m = 6
+    v[7] = mul(v[7], mk<C>(s1, sg * c1));     // m = 3
+    v[11] = mul(v[11], mk<C>(-h, sg * h));    // m = 6
+    v[15] = mul(v[15], mk<C>(-c1, -sg * s1)); // m = 9
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) dft4<C, INV>(v[4 * k2], v[4 * k2 + 1], v[4 * k2 + 2], v[4 * k2 + 3]);
+    C t[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) t[4 * k1 + k2] = v[4 * k2 + k1];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = t[i];
+}
+
+template <int R, class C, bool INV>
+__device__ __forceinline__ void dft_reg(C *v)
+{
+    if constexpr (R == 16) dft16<C, INV>(v);
+    else dft_small<R, C, INV>(v);
+}
+
+// ---------------------------------------------------------------------------
+// Register line FFTs for the column passes.  A 256-thread workgroup owns TW
+// adjacent columns of lines of L = R1 * R2 points.  Stage 1: a task (c, s)
+// loads the stride-R2 subsequence n = s + R2 m of column c into registers,
+// takes its DFT_R1 and multiplies by W_L^(s k1); one LDS exchange; stage 2:
+// a task (c, k1) takes the DFT_R2 over s and holds X[k1 + R1 k2], k2 < R2.
+// The inverse runs the two stages the other way round from that register
+// layout, so a pointwise symbol can be applied in between with no exchange.
+// ---------------------------------------------------------------------------
+template <int L>
+struct RegPlan {
+    static constexpr bool ok = false;
+    static constexpr int R1 = 1, R2 = 1, TW = 1;
+};
+template <>
+struct RegPlan<64> {
+    static constexpr bool ok = true;
+    static constexpr int R1 = 8, R2 = 8, TW = 32;
+};
+template <>
+struct RegPlan<128> {
+    static constexpr bool ok = true;
+    static constexpr int R1 = 16, R2 = 8, TW = 32;
+};
+template <>
+struct RegPlan<256> {
+    static constexpr bool ok = true;
+    static constexpr int R1 = 16, R2 = 16, TW = 16;
+};
+
+template <int L>
+struct RegShape {
+    using P = RegPlan<L>;
+    static constexpr int R1 = P::R1, R2 = P::R2, TW = P::TW;
+    static constexpr int T1 = TW * R2 / 256;  // stage-1 tasks per thread
+    static constexpr int T2 = TW * R1 / 256;  // stage-2 tasks per thread
+    static constexpr int PITCH = R2 * TW + 1; // exchange row per k1 (+1 against bank conflicts)
+    static constexpr int XCH = R1 * PITCH;    // exchange buffer, complex values
+    static_assert(T1 * 256 == TW * R2 && T2 * 256 == TW * R1, "tasks must fill the workgroup");
+};
+
+// load(n, c) returns element n of column c of the tile (zero past the last
+// column); on return out[u][k2] = X[k1 + R1 k2] of task u (c, k1).
+template <int L, bool INV, class C, class LoadF>
+__device__ __forceinline__ void reg_fft(LoadF &&load, C *X, C (&out)[RegShape<L>::T2][RegShape<L>::R2],
+                                        const C *__restrict__ tw)
+{
+    using S = RegShape<L>;
+    constexpr int R1 = S::R1, R2 = S::R2, TW = S::TW, PITCH = S::PITCH;
+    __syncthreads();  // X may still be read by a previous transform
+#pragma unroll
+    for (int u = 0; u < S::T1; ++u) {
+        const int task = (int)threadIdx.x + 256 * u, c = task % TW, s = task / TW;
+        C v[R1];
+#pragma unroll
+        for (int m = 0; m < R1; ++m) v[m] = load(s + R2 * m, c);
+        dft_reg<R1, C, INV>(v);
+#pragma unroll
+        for (int k1 = 1; k1 < R1; ++k1) v[k1] = INV ? mulc(v[k1], tw[s * k1]) : mul(v[k1], tw[s * k1]);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) X[k1 * PITCH + s * TW + c] = v[k1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < S::T2; ++u) {
+        const int task = (int)threadIdx.x + 256 * u, c = task % TW, k1 = task / TW;
+#pragma unroll
+        for (int s = 0; s < R2; ++s) out[u][s] = X[k1 * PITCH + s * TW + c];
+        dft_reg<R2, C, INV>(out[u]);
+    }
+}
+
+// inverse from the register layout reg_fft leaves (in is overwritten):
+// store(n, c, value) for every element of the tile.
+template <int L, class C, class StoreF>
+__device__ __forceinline__ void reg_ifft(C (&in)[RegShape<L>::T2][RegShape<L>::R2], C *X, StoreF &&store,
+                                         const C *__restrict__ tw)
+{
+    using S = RegShape<L>;
+    constexpr int R1 = S::R1, R2 = S::R2, TW = S::TW, PITCH = S::PITCH;
+    __syncthreads();  // X may still be read by a previous transform
+#pragma unroll
+    for (int u = 0; u < S::T2; ++u) {
+        const int task = (int)threadIdx.x + 256 * u, c = task % TW, k1 = task / TW;
+        dft_reg<R2, C, true>(in[u]);
+#pragma unroll
+        for (int na = 1; na < R2; ++na) in[u][na] = mulc(in[u][na], tw[na * k1]);
+#pragma unroll
+        for (int na = 0; na < R2; ++na) X[k1 * PITCH + na * TW + c] = in[u][na];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < S::T1; ++u) {
+        const int task = (int)threadIdx.x + 256 * u, c = task % TW, na = task / TW;
+        C v[R1];
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) v[k1] = X[k1 * PITCH + na * TW + c];
+        dft_reg<R1, C, true>(v);
+#pragma unroll
+        for (int nb = 0; nb < R1; ++nb) store(na + R2 * nb, c, v[nb]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -526,6 +668,197 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(char *__restrict__ spe
 }
 
 // ---------------------------------------------------------------------------
+// Register Stockham passes for the fused x1 operators: eight values per
+// thread, radix <= 8.  A task (c, j) is butterfly j of column c; pass p
+// (radix R, Ns = product of the earlier radices) reads elements j + r L/R,
+// multiplies by W_{Ns R}^((j mod Ns) r), takes the DFT_R and writes elements
+// (j - j mod Ns) R + j mod Ns + r Ns; the first pass reads the tile from
+// global memory, the passes exchange through LDS.  After the last forward
+// pass a thread holds X[j + r L/R_P], which is exactly the input of the
+// first pass of the inverse run with the radices in reverse order, so a
+// pointwise symbol is applied in registers between the two.
+// ---------------------------------------------------------------------------
+template <int L>
+struct StPlan {
+    static constexpr bool ok = false;
+    static constexpr int NP = 1, TW = 1, NT = 256;
+    static constexpr int radix(int) { return 1; }
+};
+template <>
+struct StPlan<64> {
+    static constexpr bool ok = true;
+    static constexpr int NP = 2, TW = 32, NT = 256;
+    static constexpr int radix(int p) { return p == 0 ? 8 : 8; }
+};
+template <>
+struct StPlan<128> {
+    static constexpr bool ok = true;
+    static constexpr int NP = 3, TW = 16, NT = 256;
+    static constexpr int radix(int p) { return p == 0 ? 8 : 4; }
+};
+template <>
+struct StPlan<256> {
+    static constexpr bool ok = true;
+    static constexpr int NP = 3, TW = 16, NT = 512;
+    static constexpr int radix(int p) { return p < 2 ? 8 : 4; }
+};
+template <>
+struct StPlan<512> {
+    static constexpr bool ok = true;
+    static constexpr int NP = 3, TW = 8, NT = 512;
+    static constexpr int radix(int) { return 8; }
+};
+
+template <int L>
+struct StShape {
+    using P = StPlan<L>;
+    static constexpr int TW = P::TW, NT = P::NT, NP = P::NP;
+    static constexpr int RL = P::radix(NP - 1);  // radix of the last forward pass
+    static constexpr int NTL = 8 / RL;           // butterflies a thread holds after it
+    static constexpr int PITCH = TW + 1;         // LDS row pitch (complex values)
+    static constexpr int XCH = L * PITCH;        // exchange buffer (complex values)
+    static_assert(NT * 8 == TW * L, "eight values per thread");
+};
+
+// one pass over registers v (8 values: task t, element r at v[t R + r])
+template <int L, int R, int NS, bool INV, class C>
+__device__ __forceinline__ void st_butterflies(C *v, const C *__restrict__ tw)
+{
+    using S = StShape<L>;
+#pragma unroll
+    for (int t = 0; t < 8 / R; ++t) {
+        const int j = ((int)threadIdx.x + S::NT * t) / S::TW;
+        if constexpr (NS > 1) {
+            const int jm = j & (NS - 1);
+            constexpr int step = L / (NS * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const C w = tw[jm * r * step];
+                v[t * R + r] = INV ? mulc(v[t * R + r], w) : mul(v[t * R + r], w);
+            }
+        }
+        dft_small<R, C, INV>(v + t * R);
+    }
+}
+
+// element rows written by a pass (Ns = NS, radix R) for task t, value r
+template <int L, int R, int NS>
+__device__ __forceinline__ int st_out_row(int t, int r)
+{
+    using S = StShape<L>;
+    const int j = ((int)threadIdx.x + S::NT * t) / S::TW, jm = j & (NS - 1);
+    return (j - jm) * R + jm + r * NS;
+}
+
+template <int L, int R>
+__device__ __forceinline__ int st_in_row(int t, int r)
+{
+    using S = StShape<L>;
+    return ((int)threadIdx.x + S::NT * t) / S::TW + r * (L / R);
+}
+
+__device__ __forceinline__ int st_col(int t, int NT, int TW) { return ((int)threadIdx.x + NT * t) % TW; }
+
+// passes P0.. of a transform whose input already sits in v (as pass P0
+// reads it); the radices are taken in forward order (FWD) or reversed;
+// intermediate results go through X; the final pass leaves its outputs in v
+template <int L, bool FWD, bool INV, int P0, int NS, class C>
+__device__ __forceinline__ void st_run(C *v, C *X, const C *__restrict__ tw)
+{
+    using S = StShape<L>;
+    constexpr int R = FWD ? S::P::radix(P0) : S::P::radix(S::NP - 1 - P0);
+    st_butterflies<L, R, NS, INV>(v, tw);
+    if constexpr (P0 + 1 < S::NP) {
+        constexpr int R2 = FWD ? S::P::radix(P0 + 1) : S::P::radix(S::NP - 2 - P0);
+        __syncthreads();  // X free
+#pragma unroll
+        for (int t = 0; t < 8 / R; ++t)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                X[st_out_row<L, R, NS>(t, r) * S::PITCH + st_col(t, S::NT, S::TW)] = v[t * R + r];
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 8 / R2; ++t)
+#pragma unroll
+            for (int r = 0; r < R2; ++r)
+                v[t * R2 + r] = X[st_in_row<L, R2>(t, r) * S::PITCH + st_col(t, S::NT, S::TW)];
+        st_run<L, FWD, INV, P0 + 1, NS * R>(v, X, tw);
+    }
+}
+
+// forward transform: load(n, c) -> v holds X[j + r L/R_P] (task t at v[t R_P + r])
+template <int L, class C, class LoadF>
+__device__ __forceinline__ void st_fwd(LoadF &&load, C *v, C *X, const C *__restrict__ tw)
+{
+    using S = StShape<L>;
+    constexpr int R = S::P::radix(0);
+#pragma unroll
+    for (int t = 0; t < 8 / R; ++t)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[t * R + r] = load(st_in_row<L, R>(t, r), st_col(t, S::NT, S::TW));
+    st_run<L, true, false, 0, 1>(v, X, tw);
+}
+
+// spectral index (x1 wavenumber index) of held value i after st_fwd
+template <int L>
+__device__ __forceinline__ int st_held_index(int i)
+{
+    using S = StShape<L>;
+    return st_in_row<L, S::RL>(i / S::RL, i % S::RL);
+}
+template <int L>
+__device__ __forceinline__ int st_held_col(int i)
+{
+    using S = StShape<L>;
+    return st_col(i / S::RL, S::NT, S::TW);
+}
+
+// inverse transform from the layout st_fwd leaves (v is overwritten):
+// store(n, c, value) for every element of the tile
+template <int L, class C, class StoreF>
+__device__ __forceinline__ void st_inv(C *v, C *X, StoreF &&store, const C *__restrict__ tw)
+{
+    using S = StShape<L>;
+    st_run<L, false, true, 0, 1>(v, X, tw);
+    constexpr int R = S::P::radix(0);  // the inverse ends with the first forward radix
+    constexpr int NS = L / R;
+#pragma unroll
+    for (int t = 0; t < 8 / R; ++t)
+#pragma unroll
+        for (int r = 0; r < R; ++r) store(st_out_row<L, R, NS>(t, r), st_col(t, S::NT, S::TW), v[t * R + r]);
+}
+
+// Column pass with register line FFTs (lengths with a RegPlan)
+template <bool INV, class R, int L>
+__global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long slot_bytes, int slot0, ColDesc d,
+                                                  const typename CplxOf<R>::type *__restrict__ tw)
+{
+    using C = typename CplxOf<R>::type;
+    using S = RegShape<L>;
+    extern __shared__ char lds_raw[];
+    C *X = reinterpret_cast<C *>(lds_raw);
+    const TilePos tp = tile_pos();
+    C *base = reinterpret_cast<C *>(spec + (long)(slot0 + blockIdx.z) * slot_bytes) + d.base_off +
+              (long)tp.y * d.ostride;
+    const int col0 = tp.x * S::TW;
+    C out[S::T2][S::R2];
+    reg_fft<L, INV>(
+        [&](int n, int c) {
+            const int col = col0 + c;
+            return col < d.ncols ? base[n * d.nstride + col * d.cstride] : mk<C>(0, 0);
+        },
+        X, out, tw);
+#pragma unroll
+    for (int u = 0; u < S::T2; ++u) {
+        const int task = (int)threadIdx.x + 256 * u, c = task % S::TW, k1 = task / S::TW;
+        const int col = col0 + c;
+        if (col < d.ncols)
+#pragma unroll
+            for (int k2 = 0; k2 < S::R2; ++k2) base[(k1 + S::R1 * k2) * d.nstride + col * d.cstride] = out[u][k2];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Spectral symbols.  (l1, l2, l3) index a spectral point, l3 in [0, n3/2].
 // ---------------------------------------------------------------------------
 struct SymCtx {
@@ -686,6 +1019,14 @@ __device__ __forceinline__ void leray_coef(const SymCtx &sc, int n, int l2, int 
     ikk = kk > 0.0 ? 1.0 / kk : 0.0;
 }
 
+// 1 / |k~|^2 in FP32 (0 where k~ = 0); |k~|^2 is an exact integer
+__device__ __forceinline__ float leray_ikk(const SymCtx &sc, int n, int l2, int l3)
+{
+    const float k1 = (float)wn_odd(n, sc.n1), k2 = (float)wn_odd(l2, sc.n2), k3 = (float)wn_odd(l3, sc.n3);
+    const float kk = k1 * k1 + k2 * k2 + k3 * k3;
+    return kk > 0.f ? 1.f / kk : 0.f;
+}
+
 // Leray projection: three FP32 fields in and out
 template <int LF>
 __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spec, long slot_bytes, int in0,
@@ -728,6 +1069,194 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
         float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + 3 * blockIdx.z + q) * slot_bytes) + off;
         tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused x1 operators with register line FFTs: forward x1 transform of the
+// input fields, the symbol applied to the spectra each thread holds, inverse
+// x1 transform of the outputs; the same arithmetic, in the same order and
+// precision, as the LDS kernels above.  blockIdx.z is the batch index.
+// ---------------------------------------------------------------------------
+template <int OP, int L>
+__global__ __launch_bounds__(StPlan<L>::NT) void k_x1_reg(char *__restrict__ spec, long slot_bytes, int in0,
+                                                         int out0, ColDesc d, int nyq,
+                                                         const double2 *__restrict__ twd,
+                                                         const float2 *__restrict__ twf, SymCtx sc)
+{
+    using S = StShape<L>;
+    constexpr int TW = S::TW;
+    extern __shared__ char lds_raw[];
+    double2 *XD = reinterpret_cast<double2 *>(lds_raw);
+    float2 *XF = reinterpret_cast<float2 *>(lds_raw);
+    const TilePos tp = tile_pos();
+    const int col0 = tp.x * TW, z = (int)blockIdx.z;
+    const long off = d.base_off + (long)tp.y * d.ostride;
+    const ColCtx cc{nyq, tp.y};
+    auto load_d = [&](int slot) {
+        const double2 *src = reinterpret_cast<const double2 *>(spec + (long)slot * slot_bytes) + off;
+        return [=](int n, int c) {
+            const int col = col0 + c;
+            return col < d.ncols ? src[n * d.nstride + col * d.cstride] : mk<double2>(0, 0);
+        };
+    };
+    auto load_f = [&](int slot) {
+        const float2 *src = reinterpret_cast<const float2 *>(spec + (long)slot * slot_bytes) + off;
+        return [=](int n, int c) {
+            const int col = col0 + c;
+            return col < d.ncols ? src[n * d.nstride + col * d.cstride] : mk<float2>(0, 0);
+        };
+    };
+    auto store = [&](int slot) {
+        float2 *dst = reinterpret_cast<float2 *>(spec + (long)slot * slot_bytes) + off;
+        return [=](int n, int c, auto v) {
+            const int col = col0 + c;
+            if (col < d.ncols) dst[n * d.nstride + col * d.cstride] = to_f2(v);
+        };
+    };
+    // spectral position of held value i: x1 index n(i), columns give (l2, l3)
+    auto pos = [&](int i, int &n, int &l2, int &l3) {
+        n = st_held_index<L>(i);
+        cc.l23(sc, col0 + st_held_col<L>(i), l2, l3);
+    };
+    if constexpr (OP == SOP_GRAD) {  // one FP64 field -> three FP32 fields
+        double2 f[8];
+        st_fwd<L>(load_d(in0 + z), f, XD, twd);
+#pragma unroll 1
+        for (int q = 0; q < 3; ++q) {
+            float2 o[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                int n, l2, l3;
+                pos(i, n, l2, l3);
+                const double kq = q == 0 ? wn_odd(n, sc.n1) : (q == 1 ? wn_odd(l2, sc.n2) : wn_odd(l3, sc.n3));
+                o[i] = to_f2(muli(scl(scl(f[i], sc.scale), kq)));
+            }
+            __syncthreads();  // the exchange buffer is reused
+            st_inv<L>(o, XF, store(out0 + 3 * z + q), twf);
+        }
+    } else if constexpr (OP == SOP_DIV) {  // three FP64 fields -> one FP32 field
+        double2 acc[8];
+#pragma unroll 1
+        for (int q = 0; q < 3; ++q) {
+            double2 f[8];
+            if (q > 0) __syncthreads();
+            st_fwd<L>(load_d(in0 + 3 * z + q), f, XD, twd);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                int n, l2, l3;
+                pos(i, n, l2, l3);
+                const double kq = q == 0 ? wn_odd(n, sc.n1) : (q == 1 ? wn_odd(l2, sc.n2) : wn_odd(l3, sc.n3));
+                const double2 t = muli(scl(f[i], kq * sc.scale));
+                acc[i] = q == 0 ? t : add(acc[i], t);
+            }
+        }
+        float2 o[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = to_f2(acc[i]);
+        __syncthreads();
+        st_inv<L>(o, XF, store(out0 + z), twf);
+    } else if constexpr (OP == SOP_LERAY) {  // three FP32 fields in and out
+        float2 w[3][8];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (q > 0) __syncthreads();
+            st_fwd<L>(load_f(in0 + 3 * z + q), w[q], XF, twf);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            int n, l2, l3;
+            pos(i, n, l2, l3);
+            double k[3], ikk;
+            leray_coef(sc, n, l2, l3, k, ikk);
+            const float2 a = w[0][i], b = w[1][i], c = w[2][i];
+            const double sx = (k[0] * a.x + k[1] * b.x + k[2] * c.x) * ikk;
+            const double sy = (k[0] * a.y + k[1] * b.y + k[2] * c.y) * ikk;
+            const float2 in3[3] = {a, b, c};
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                w[q][i] = make_float2((float)((in3[q].x - k[q] * sx) * sc.scale),
+                                      (float)((in3[q].y - k[q] * sy) * sc.scale));
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            __syncthreads();
+            st_inv<L>(w[q], XF, store(out0 + 3 * z + q), twf);
+        }
+    } else if constexpr (OP == SOP_ASSEMBLE) {  // w: 3 FP64, b: 3 FP32 -> 3 FP32
+        // o_q = (K b)_q + beta A w_q: the b part first (the Leray accumulator
+        // needs all three components), then the w components one at a time
+        const int w0 = in0 + 6 * z, b0 = w0 + 3, o0 = out0 + 3 * z;
+        float2 o[3][8], sd[8];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (q > 0) __syncthreads();
+            st_fwd<L>(load_f(b0 + q), o[q], XF, twf);
+            if (sc.leray) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    int n, l2, l3;
+                    pos(i, n, l2, l3);
+                    const float kq = (float)(q == 0 ? wn_odd(n, sc.n1) : (q == 1 ? wn_odd(l2, sc.n2) : wn_odd(l3, sc.n3)));
+                    const float t = kq * leray_ikk(sc, n, l2, l3);
+                    const float2 tb = mk<float2>(o[q][i].x * t, o[q][i].y * t);
+                    sd[i] = q == 0 ? tb : add(sd[i], tb);
+                }
+            }
+        }
+        const float fs = (float)sc.scale;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            int n, l2, l3;
+            pos(i, n, l2, l3);
+            const float k[3] = {(float)wn_odd(n, sc.n1), (float)wn_odd(l2, sc.n2), (float)wn_odd(l3, sc.n3)};
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                float2 v = o[q][i];
+                if (sc.leray) v = sub(v, mk<float2>(sd[i].x * k[q], sd[i].y * k[q]));
+                o[q][i] = scl(v, fs);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double2 f[8];
+            __syncthreads();
+            st_fwd<L>(load_d(w0 + q), f, XD, twd);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                int n, l2, l3;
+                pos(i, n, l2, l3);
+                o[q][i] = add(o[q][i], to_f2(scl(f[i], sc.beta * reg_symbol(sc, n, l2, l3) * sc.scale)));
+            }
+            __syncthreads();
+            st_inv<L>(o[q], XF, store(o0 + q), twf);
+        }
+    } else {  // scalar symbols: REG (FP64), INVREG and IDENT (FP32)
+        using C = typename std::conditional<OP == SOP_REG, double2, float2>::type;
+        using R = typename RealOf<C>::type;
+        C f[8];
+        if constexpr (OP == SOP_REG)
+            st_fwd<L>(load_d(in0 + z), f, XD, twd);
+        else
+            st_fwd<L>(load_f(in0 + z), f, XF, twf);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            int n, l2, l3;
+            pos(i, n, l2, l3);
+            double fac = sc.scale;
+            if (OP == SOP_REG) {
+                fac *= reg_symbol(sc, n, l2, l3);
+            } else if (OP == SOP_INVREG) {
+                const double a = reg_symbol(sc, n, l2, l3);
+                fac *= (a == 0.0) ? 1.0 / sc.beta : 1.0 / (sc.beta * a);
+            }
+            f[i] = scl(f[i], (R)fac);
+        }
+        __syncthreads();
+        if constexpr (OP == SOP_REG)
+            st_inv<L>(f, XD, store(out0 + z), twd);
+        else
+            st_inv<L>(f, XF, store(out0 + z), twf);
     }
 }
 
@@ -1046,11 +1575,42 @@ static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool invers
     for (int part = 0; part < 2; ++part) {
         if (only_part >= 0 && part != only_part) continue;
         const ColDesc &d = dd[part];
+        Scope s(P, K_FFT_COLS);
+        bool done = false;
+        with_len(rp.L, [&]<int LF>() {
+            if constexpr (RegPlan<LF>::ok) {
+                using RS = RegShape<LF>;
+                dim3 grid((unsigned)((d.ncols + RS::TW - 1) / RS::TW), outer[part], count);
+                const size_t lds = cs * RS::XCH;
+                check_lds(lds, "fft_cols");
+                if (dbl) {
+                    const double2 *tw = axis == 1 ? F.tw2d : F.tw1d;
+                    if (inverse)
+                        FFT_LAUNCH((k_cols_reg<true, double, LF>), grid, lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, d, tw);
+                    else
+                        FFT_LAUNCH((k_cols_reg<false, double, LF>), grid, lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, d, tw);
+                } else {
+                    const float2 *tw = axis == 1 ? F.tw2 : F.tw1;
+                    if (inverse)
+                        FFT_LAUNCH((k_cols_reg<true, float, LF>), grid, lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, d, tw);
+                    else
+                        FFT_LAUNCH((k_cols_reg<false, float, LF>), grid, lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, d, tw);
+                }
+                done = true;
+            }
+        });
+        if (done) {
+            check_hip(hipGetLastError(), "k_cols_reg");
+            continue;
+        }
         const int TW = F.tw_cols[axis == 1 ? 1 : 0][part][dbl ? 1 : 0];
         const size_t lds = 2 * cs * rp.L * TW;
         check_lds(lds, "fft_cols");
         dim3 grid((unsigned)((d.ncols + TW - 1) / TW), outer[part], count);
-        Scope s(P, K_FFT_COLS);
         const int lt = ilog2(TW);
         with_len(rp.L, [&]<int LF>() {
             if (dbl) {
@@ -1151,6 +1711,40 @@ static void x1_symbol_parts(lddmm_plan *P, int op, int in0, int out0, int nbatch
     for (int part = 0; part < 2; ++part) {
         if (only_part >= 0 && part != only_part) continue;
         const ColDesc &d = dd[part];
+        bool done = false;
+        with_len(L, [&]<int LF>() {
+            if constexpr (StPlan<LF>::ok) {
+                using RS = StShape<LF>;
+                const bool fp64x = op == SOP_GRAD || op == SOP_DIV || op == SOP_ASSEMBLE || op == SOP_REG;
+                const size_t lds = (fp64x ? sizeof(double2) : sizeof(float2)) * RS::XCH;
+                check_lds(lds, "x1_symbol");
+                const int nz = (op == SOP_REG || op == SOP_INVREG) ? 3 * nbatch : nbatch;
+                const dim3 grid((unsigned)((d.ncols + RS::TW - 1) / RS::TW), outer[part], nz);
+                Scope s(P, K_SPECTRAL_X1);
+#define X1R(OPV)                                                                                           \
+    do {                                                                                                   \
+        if (lds > 65536) allow_big_lds((const void *)(k_x1_reg<OPV, LF>));                                 \
+        hipLaunchKernelGGL((k_x1_reg<OPV, LF>), grid, dim3(RS::NT), lds, P->stream, P->spec, P->slot_bytes, \
+                           in0, out0, d, part, F.tw1d, F.tw1, sc);                                         \
+    } while (0)
+                switch (op) {
+                case SOP_GRAD: X1R(SOP_GRAD); break;
+                case SOP_DIV: X1R(SOP_DIV); break;
+                case SOP_LERAY: X1R(SOP_LERAY); break;
+                case SOP_ASSEMBLE: X1R(SOP_ASSEMBLE); break;
+                case SOP_REG: X1R(SOP_REG); break;
+                case SOP_INVREG: X1R(SOP_INVREG); break;
+                case SOP_IDENT: X1R(SOP_IDENT); break;
+                default: fail(LDDMM_EINVAL, "unknown spectral operator");
+                }
+#undef X1R
+                done = true;
+            }
+        });
+        if (done) {
+            check_hip(hipGetLastError(), "k_x1_reg");
+            continue;
+        }
         const size_t per = x1_bytes_per_elem(op);  // LDS bytes per tile element
         const int TW = F.tw_x1[op][part];
         const size_t lds = per * L * TW;
