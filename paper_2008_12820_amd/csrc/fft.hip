@@ -501,6 +501,216 @@ static void allow_big_lds(const void *k)
     } while (0)
 
 // ---------------------------------------------------------------------------
+// Register Stockham passes along x3 rows (the R2C / C2R passes): a 256-thread
+// workgroup owns RB rows of M = n3/2 complex points, eight values per
+// thread; task (row, j) with the butterfly index j fastest, so the global
+// accesses of one element r of a pass are contiguous along the row.
+// ---------------------------------------------------------------------------
+template <int M>
+struct RowPlan {
+    static constexpr bool ok = false;
+    static constexpr int NP = 1, RB = 1;
+    static constexpr int radix(int) { return 1; }
+};
+template <>
+struct RowPlan<64> {
+    static constexpr bool ok = true;
+    static constexpr int NP = 2, RB = 32;
+    static constexpr int radix(int) { return 8; }
+};
+template <>
+struct RowPlan<128> {
+    static constexpr bool ok = true;
+    static constexpr int NP = 3, RB = 16;
+    static constexpr int radix(int p) { return p == 0 ? 8 : 4; }
+};
+template <>
+struct RowPlan<256> {
+    static constexpr bool ok = true;
+    static constexpr int NP = 3, RB = 8;
+    static constexpr int radix(int p) { return p < 2 ? 8 : 4; }
+};
+template <>
+struct RowPlan<512> {
+    static constexpr bool ok = true;
+    static constexpr int NP = 3, RB = 4;
+    static constexpr int radix(int) { return 8; }
+};
+
+template <int M>
+struct RowShape {
+    using P = RowPlan<M>;
+    static constexpr int RB = P::RB, NP = P::NP;
+    static constexpr int RPITCH = M + 1;     // LDS row pitch (complex values)
+    static constexpr int XCH = RB * RPITCH;  // exchange buffer (complex values)
+    static_assert(RB * M == 8 * 256, "eight values per thread");
+};
+
+template <int M, int R>
+__device__ __forceinline__ int rw_line(int t)
+{
+    return ((int)threadIdx.x + 256 * t) / (M / R);
+}
+template <int M, int R>
+__device__ __forceinline__ int rw_but(int t)
+{
+    return ((int)threadIdx.x + 256 * t) % (M / R);
+}
+
+template <int M, int R, int NS, bool INV, class C>
+__device__ __forceinline__ void rw_butterflies(C *v, const C *__restrict__ tw)
+{
+#pragma unroll
+    for (int t = 0; t < 8 / R; ++t) {
+        if constexpr (NS > 1) {
+            const int jm = rw_but<M, R>(t) & (NS - 1);
+            constexpr int step = M / (NS * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const C w = tw[jm * r * step];
+                v[t * R + r] = INV ? mulc(v[t * R + r], w) : mul(v[t * R + r], w);
+            }
+        }
+        dft_small<R, C, INV>(v + t * R);
+    }
+}
+
+template <int M, int R, int NS>
+__device__ __forceinline__ int rw_out_elem(int t, int r)
+{
+    const int j = rw_but<M, R>(t), jm = j & (NS - 1);
+    return (j - jm) * R + jm + r * NS;
+}
+
+// passes P0.. in forward (FWD) or reversed radix order, input in v as pass
+// P0 reads it; the final pass leaves its outputs in v
+template <int M, bool FWD, bool INV, int P0, int NS, class C>
+__device__ __forceinline__ void rw_run(C *v, C *X, const C *__restrict__ tw)
+{
+    using S = RowShape<M>;
+    constexpr int R = FWD ? S::P::radix(P0) : S::P::radix(S::NP - 1 - P0);
+    rw_butterflies<M, R, NS, INV>(v, tw);
+    if constexpr (P0 + 1 < S::NP) {
+        constexpr int R2 = FWD ? S::P::radix(P0 + 1) : S::P::radix(S::NP - 2 - P0);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 8 / R; ++t)
+#pragma unroll
+            for (int r = 0; r < R; ++r) X[rw_line<M, R>(t) * S::RPITCH + rw_out_elem<M, R, NS>(t, r)] = v[t * R + r];
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 8 / R2; ++t)
+#pragma unroll
+            for (int r = 0; r < R2; ++r)
+                v[t * R2 + r] = X[rw_line<M, R2>(t) * S::RPITCH + rw_but<M, R2>(t) + r * (M / R2)];
+        rw_run<M, FWD, INV, P0 + 1, NS * R>(v, X, tw);
+    }
+}
+
+// R2C rows with register passes: n3 = 2M real values per row
+template <class R, int M>
+__global__ __launch_bounds__(256) void k_r2c_reg(RealIn in, char *__restrict__ spec, long slot_bytes, int slot0,
+                                                 long nrow, const typename CplxOf<R>::type *__restrict__ tw_m,
+                                                 const typename CplxOf<R>::type *__restrict__ tw_n)
+{
+    using C = typename CplxOf<R>::type;
+    using S = RowShape<M>;
+    constexpr int R0 = S::P::radix(0), RL = S::P::radix(S::NP - 1);
+    extern __shared__ char lds_raw[];
+    C *X = reinterpret_cast<C *>(lds_raw);
+    const int f = blockIdx.y;
+    const float2 *__restrict__ src = reinterpret_cast<const float2 *>(in.p[f]);
+    const long row0 = (long)blockIdx.x * S::RB;
+    C v[8];
+#pragma unroll
+    for (int t = 0; t < 8 / R0; ++t) {
+        const long row = row0 + rw_line<M, R0>(t);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int e = rw_but<M, R0>(t) + r * (M / R0);
+            const float2 z = row < nrow ? src[row * M + e] : make_float2(0.f, 0.f);
+            v[t * R0 + r] = mk<C>((R)z.x, (R)z.y);
+        }
+    }
+    rw_run<M, true, false, 0, 1>(v, X, tw_m);
+    // Z to LDS (natural order), then the pairs (k, M - k) give the half spectrum
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 8 / RL; ++t)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) X[rw_line<M, RL>(t) * S::RPITCH + rw_out_elem<M, RL, M / RL>(t, r)] = v[t * RL + r];
+    __syncthreads();
+    C *outm = reinterpret_cast<C *>(spec + (long)(slot0 + f) * slot_bytes);
+    C *outq = outm + nrow * M;
+    for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += 256) {
+        const int c = idx / (M + 1), k = idx - c * (M + 1);
+        const long row = row0 + c;
+        if (row >= nrow) continue;
+        const C zk = X[c * S::RPITCH + (k == M ? 0 : k)];
+        const C zc = conj_(X[c * S::RPITCH + (k == 0 ? 0 : M - k)]);
+        const C E = scl(add(zk, zc), R(0.5));
+        const C D = scl(sub(zk, zc), R(0.5));
+        const C O = mk<C>(D.y, -D.x);  // D / i
+        const C Xk = add(E, mul(tw_n[k], O));
+        if (k < M)
+            outm[row * M + k] = Xk;
+        else
+            outq[row] = Xk;
+    }
+}
+
+// C2R rows with register passes (FP32), times scale
+template <int M>
+__global__ __launch_bounds__(256) void k_c2r_reg(const char *__restrict__ spec, long slot_bytes, int slot0,
+                                                 RealOut out, long nrow, const float2 *__restrict__ tw_m,
+                                                 const float2 *__restrict__ tw_n, float scale)
+{
+    using S = RowShape<M>;
+    constexpr int RA = S::P::radix(S::NP - 1), R1 = S::P::radix(0);  // first and last inverse radices
+    extern __shared__ char lds_raw[];
+    float2 *X = reinterpret_cast<float2 *>(lds_raw);
+    const int f = blockIdx.y;
+    const long row0 = (long)blockIdx.x * S::RB;
+    const float2 *inm = reinterpret_cast<const float2 *>(spec + (long)(slot0 + f) * slot_bytes);
+    const float2 *inq = inm + nrow * M;
+    for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += 256) {
+        const int c = idx / (M + 1), k = idx - c * (M + 1);
+        const long row = row0 + c;
+        float2 Xv = make_float2(0.f, 0.f);
+        if (row < nrow) Xv = (k < M) ? inm[row * M + k] : inq[row];
+        X[c * S::RPITCH + k] = Xv;
+    }
+    __syncthreads();
+    float2 v[8];
+#pragma unroll
+    for (int t = 0; t < 8 / RA; ++t) {
+        const int c = rw_line<M, RA>(t);
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            const int k = rw_but<M, RA>(t) + r * (M / RA);
+            const float2 Xk = X[c * S::RPITCH + k];
+            const float2 Xc = conj_(X[c * S::RPITCH + M - k]);
+            const float2 E = add(Xk, Xc);
+            const float2 O = mulc(sub(Xk, Xc), tw_n[k]);  // * exp(+2 pi i k / n3)
+            v[t * RA + r] = add(E, muli(O));
+        }
+    }
+    rw_run<M, false, true, 0, 1>(v, X, tw_m);
+    float *__restrict__ dst = out.p[f];
+#pragma unroll
+    for (int t = 0; t < 8 / R1; ++t) {
+        const long row = row0 + rw_line<M, R1>(t);
+        if (row >= nrow) continue;
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int e = rw_out_elem<M, R1, M / R1>(t, r);
+            const float2 z = v[t * R1 + r];
+            *reinterpret_cast<float2 *>(dst + row * 2 * M + 2 * e) = make_float2(z.x * scale, z.y * scale);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // x3 pass: real rows -> half spectrum (main + Nyquist plane), computed in R
 // ---------------------------------------------------------------------------
 template <class R, int LF>
@@ -1521,6 +1731,26 @@ void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int slot0, bool dbl)
     check_lds(lds, "r2c_x3");
     dim3 grid((unsigned)((F.nrow + TWR - 1) / TWR), count);
     Scope s(P, K_R2C_X3);
+    bool done = false;
+    with_len(F.m3, [&]<int LF>() {
+        if constexpr (RowPlan<LF>::ok) {
+            using RS = RowShape<LF>;
+            const size_t ldsr = cs * RS::XCH;
+            check_lds(ldsr, "r2c_x3");
+            const dim3 gr((unsigned)((F.nrow + RS::RB - 1) / RS::RB), count);
+            if (dbl)
+                FFT_LAUNCH((k_r2c_reg<double, LF>), gr, ldsr, P->stream, in, P->spec, P->slot_bytes, slot0, F.nrow,
+                           F.tw3d, F.twN3d);
+            else
+                FFT_LAUNCH((k_r2c_reg<float, LF>), gr, ldsr, P->stream, in, P->spec, P->slot_bytes, slot0, F.nrow,
+                           F.tw3, F.twN3);
+            done = true;
+        }
+    });
+    if (done) {
+        check_hip(hipGetLastError(), "k_r2c_reg");
+        return;
+    }
     with_len(F.m3, [&]<int LF>() {
         if (dbl)
             FFT_LAUNCH((k_r2c_x3<double, LF>), grid, lds, P->stream, in, P->spec,
@@ -1540,6 +1770,22 @@ void c2r_fields(lddmm_plan *P, int slot0, int count, const RealOut &out, float s
     check_lds(lds, "c2r_x3");
     dim3 grid((unsigned)((F.nrow + TWR - 1) / TWR), count);
     Scope s(P, K_C2R_X3);
+    bool done = false;
+    with_len(F.m3, [&]<int LF>() {
+        if constexpr (RowPlan<LF>::ok) {
+            using RS = RowShape<LF>;
+            const size_t ldsr = sizeof(float2) * RS::XCH;
+            check_lds(ldsr, "c2r_x3");
+            const dim3 gr((unsigned)((F.nrow + RS::RB - 1) / RS::RB), count);
+            FFT_LAUNCH((k_c2r_reg<LF>), gr, ldsr, P->stream, P->spec, P->slot_bytes, slot0, out, F.nrow, F.tw3, F.twN3,
+                       scale);
+            done = true;
+        }
+    });
+    if (done) {
+        check_hip(hipGetLastError(), "k_c2r_reg");
+        return;
+    }
     with_len(F.m3, [&]<int LF>() {
         FFT_LAUNCH((k_c2r_x3<LF>), grid, lds, P->stream, P->spec, P->slot_bytes,
                            slot0, out, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3, scale);
