@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
     using BC = BoxCfg<T1, T2>;
     constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, CAP = BC::CAP, NF = Epi::NF;
     constexpr int S1 = BR2 * kPad3;  // box stride along x1 (x2: kPad3)
-    extern __shared__ float box[];   // NF x CAP
+    extern __shared__ float box[];   // CAP floats
     __shared__ int red[4][6];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
@@ -397,16 +397,17 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
     // Staging: wavefront w loads the box rows r = w, w + 4, ... (row r is
     // (a, b) = (r / BR2, r % BR2)); a row's source pointer is uniform over the
     // wavefront, so its wrap and address arithmetic run on the scalar unit.
-    // The x3 wrap of a lane's two columns is the same for every row.
+    // The x3 wrap of a lane's two columns is the same for every row.  Fields
+    // go through the one box in turn.
     constexpr int RPW = (BR1 * BR2 + 3) / 4;  // rows per wavefront
     const int wu = __builtin_amdgcn_readfirstlane(w);
     const int c1 = lane + 64;
     const bool has0 = lane < B3, has1 = c1 < B3;
     const unsigned k0 = (unsigned)wrapg(L3 + lane, g.n3), k1 = (unsigned)wrapg(L3 + c1, g.n3);
+    float val[PPT][NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const float *__restrict__ src = epi.field(f);
-        float *bx = box + f * CAP;
         float r0[RPW], r1[RPW];
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
@@ -418,52 +419,48 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
                 if (has1) r1[q] = grow[k1];
             }
         }
+        if (f > 0) __syncthreads();  // the previous field's stencils are read
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int r = wu + 4 * q, a = r / BR2, b = r - a * BR2;
             if (a < B1 && b < B2) {
-                float *brow = bx + r * kPad3;
+                float *brow = box + r * kPad3;
                 if (has0) brow[lane] = r0[q];
                 if (has1) brow[c1] = r1[q];
             }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
-        if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
-        const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
-        float w1[4], w2[4], w3[4];
-        lagrange4<float>(d1[q] - f1, w1);
-        lagrange4<float>(d2[q] - f2, w2);
-        lagrange4<float>(d3[q] - f3, w3);
-        const int b1 = i + (int)f1 - 1, b2 = j + (int)f2 - 1, b3 = k + (int)f3 - 1;
-        const int o1 = b1 - L1, o2 = b2 - L2, o3 = b3 - L3;  // >= 0 by the reduction
-        float v[NF];
-        if (o1 <= B1 - 4 && o2 <= B2 - 4 && o3 <= B3 - 4) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const float *bx = box + f * CAP + o1 * S1 + o2 * kPad3 + o3;
-                float acc = 0.f;
+        for (int q = 0; q < PPT; ++q) {
+            const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+            val[q][f] = 0.f;
+            if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
+            const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
+            float w1[4], w2[4], w3[4];
+            lagrange4<float>(d1[q] - f1, w1);
+            lagrange4<float>(d2[q] - f2, w2);
+            lagrange4<float>(d3[q] - f3, w3);
+            const int b1 = i + (int)f1 - 1, b2 = j + (int)f2 - 1, b3 = k + (int)f3 - 1;
+            const int o1 = b1 - L1, o2 = b2 - L2, o3 = b3 - L3;  // >= 0 by the reduction
+            float acc = 0.f;
+            if (o1 <= B1 - 4 && o2 <= B2 - 4 && o3 <= B3 - 4) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
+                    // one base address per x1 plane: the row reads of the
+                    // plane then fit the LDS instruction's offset field
+                    int pa = (o1 + a) * S1 + o2 * kPad3 + o3;
+                    asm("" : "+v"(pa));
+                    const float *pl = box + pa;
                     float acc2 = 0.f;
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
-                        const float *row = bx + a * S1 + b * kPad3;
+                        const float *row = pl + b * kPad3;
                         const float r = row[0] * w3[0] + row[1] * w3[1] + row[2] * w3[2] + row[3] * w3[3];
-                        acc2 += w2[b] * r;
+                        acc2 = b == 0 ? w2[0] * r : acc2 + w2[b] * r;
                     }
-                    acc += w1[a] * acc2;
+                    acc = a == 0 ? w1[0] * acc2 : acc + w1[a] * acc2;
                 }
-                v[f] = acc;
-            }
-        } else {  // stencil outside the staged box: global loads, wrapped per node
-#pragma unroll 1
-            for (int f = 0; f < NF; ++f) {
-                const float *__restrict__ src = epi.field(f);
-                float acc = 0.f;
+            } else {  // stencil outside the staged box: global loads, wrapped per node
 #pragma unroll 1
                 for (int a = 0; a < 4; ++a) {
                     const long ra = (long)wrapg(b1 + a, g.n1) * g.n2;
@@ -472,14 +469,18 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
                         const float *row = src + (ra + wrapg(b2 + b, g.n2)) * g.n3;
                         const float r = row[wrapg(b3, g.n3)] * w3[0] + row[wrapg(b3 + 1, g.n3)] * w3[1] +
                                         row[wrapg(b3 + 2, g.n3)] * w3[2] + row[wrapg(b3 + 3, g.n3)] * w3[3];
-                        acc2 += w2[b] * r;
+                        acc2 = b == 0 ? w2[0] * r : acc2 + w2[b] * r;
                     }
-                    acc += w1[a] * acc2;
+                    acc = a == 0 ? w1[0] * acc2 : acc + w1[a] * acc2;
                 }
-                v[f] = acc;
             }
+            val[q][f] = acc;
         }
-        epi.finish(((long)i * g.n2 + j) * g.n3 + k, v);
+    }
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+        if (i < g.n1 && j < g.n2 && k < g.n3) epi.finish(((long)i * g.n2 + j) * g.n3 + k, val[q]);
     }
 }
 
@@ -545,8 +546,8 @@ static void launch_box(lddmm_plan *P, const float *disp, const Epi &epi, int kid
 {
     const int n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
     const int nt1 = (n1 + T1 - 1) / T1, nt2 = (n2 + T2 - 1) / T2, nt3 = (n3 + kT3 - 1) / kT3;
-    const size_t lds = sizeof(float) * BoxCfg<T1, T2>::CAP * Epi::NF;
-    static_assert(sizeof(float) * BoxCfg<4, 4>::CAP * 3 <= 64 * 1024, "box exceeds the default LDS limit");
+    const size_t lds = sizeof(float) * BoxCfg<T1, T2>::CAP;
+    static_assert(sizeof(float) * BoxCfg<4, 4>::CAP <= 64 * 1024, "box exceeds the default LDS limit");
     const unsigned ntiles = (unsigned)((long)nt1 * nt2 * nt3);
     Scope s(P, kid);
     hipLaunchKernelGGL((k_box<T1, T2, Epi>), dim3(ntiles), dim3(256), lds, P->stream, grid_of(P), disp, epi, nt2,
