@@ -238,6 +238,39 @@ def bench_batched(torch, dev):
     }
 
 
+def fft_comparison(torch, dev, n):
+    """One forward 3D R2C of an n^3 FP32 field: the hand-written FFT (x3, x2
+    and x1 passes plus the repack into the standard half-spectrum layout)
+    against torch.fft.rfftn (rocFFT through hipFFT), both timed with events
+    on the current stream; context only, not part of the metric."""
+    from paper_2008_12820_amd import Plan
+    P = Plan(n, 1, reg=2, beta=1e-3, device=dev, transport_only=True)
+    x = torch.randn(n, device=dev, dtype=torch.float32)
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ours = timed(lambda: P.fft_r2c(x))
+    try:
+        ref = timed(lambda: torch.fft.rfftn(x))
+        y1, y2 = P.fft_r2c(x), torch.fft.rfftn(x)
+        agree = float(torch.linalg.vector_norm(y1 - y2) / torch.linalg.vector_norm(y2))
+    except Exception as e:  # no hipFFT in this torch build
+        log(f"rocFFT comparison unavailable: {e}")
+        ref, agree = None, None
+    P.close()
+    return {"grid": list(n), "fft_r2c_ms": ours, "rocfft_rfftn_ms": ref, "rel_l2_vs_rocfft": agree}
+
+
 def bench_autograd(torch, dev, n=512, nt=8):
     """TransportMap forward + backward at 512^3, N_t = 8, with the loss
     0.5 ||m(1) - m1||^2 + beta H2(v), beta = 1e-4, against the plain reduced
@@ -439,6 +472,7 @@ def main():
         out["copy_calibration"] = {"bytes_read": 1 << 30, "bytes_written": 1 << 30,
                                    "GBps": 5 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9}
         del src, dst
+    out["fft_vs_rocfft"] = fft_comparison(torch, dev, n)
     if args.batched:
         out["batched"] = bench_batched(torch, dev)
     if args.autograd:

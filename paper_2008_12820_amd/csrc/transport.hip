@@ -116,9 +116,25 @@ __device__ __forceinline__ void make_stencil(const Grid3 &g, int i, int j, int k
     s.contig = b3 + 3 < g.n3;
 }
 
-// Separable evaluation of the tensor-product sum.  When the four x3 nodes
-// are contiguous (no periodic wrap) their loads come from one row pointer
-// and merge into one 16-byte load; both branches add in the same order.
+// Separable evaluation of the tensor-product sum, with one rounding sequence
+// shared by every gather strategy: each stencil row is contracted along x3
+// by explicit fused multiply-adds, rows along x2, then planes along x1.
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <class T>
+__device__ __forceinline__ T row3(T f0, T f1, T f2, T f3, const T w[4])
+{
+    return fma_(f3, w[3], fma_(f2, w[2], fma_(f1, w[1], f0 * w[0])));
+}
+template <class T>
+__device__ __forceinline__ T accum(int i, const T w[4], T r, T acc)
+{
+    return i == 0 ? w[0] * r : fma_(w[i], r, acc);
+}
+
+// When the four x3 nodes are contiguous (no periodic wrap) their loads come
+// from one row pointer and merge into one 16-byte load.
 template <class T>
 __device__ __forceinline__ T gather(const float *__restrict__ f, const Stencil<T> &s)
 {
@@ -130,11 +146,9 @@ __device__ __forceinline__ T gather(const float *__restrict__ f, const Stencil<T
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const float *row = f + (s.o1[a] + s.o2[b] + s.o3[0]);
-                const T r = (T)row[0] * s.w3[0] + (T)row[1] * s.w3[1] + (T)row[2] * s.w3[2] +
-                            (T)row[3] * s.w3[3];
-                acc2 += s.w2[b] * r;
+                acc2 = accum<T>(b, s.w2, row3<T>((T)row[0], (T)row[1], (T)row[2], (T)row[3], s.w3), acc2);
             }
-            acc += s.w1[a] * acc2;
+            acc = accum<T>(a, s.w1, acc2, acc);
         }
     } else {
 #pragma unroll
@@ -143,11 +157,11 @@ __device__ __forceinline__ T gather(const float *__restrict__ f, const Stencil<T
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const float *row = f + (s.o1[a] + s.o2[b]);
-                const T r = (T)row[s.o3[0]] * s.w3[0] + (T)row[s.o3[1]] * s.w3[1] +
-                            (T)row[s.o3[2]] * s.w3[2] + (T)row[s.o3[3]] * s.w3[3];
-                acc2 += s.w2[b] * r;
+                acc2 = accum<T>(b, s.w2,
+                                row3<T>((T)row[s.o3[0]], (T)row[s.o3[1]], (T)row[s.o3[2]], (T)row[s.o3[3]], s.w3),
+                                acc2);
             }
-            acc += s.w1[a] * acc2;
+            acc = accum<T>(a, s.w1, acc2, acc);
         }
     }
     return acc;
@@ -455,10 +469,9 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
                         const float *row = pl + b * kPad3;
-                        const float r = row[0] * w3[0] + row[1] * w3[1] + row[2] * w3[2] + row[3] * w3[3];
-                        acc2 = b == 0 ? w2[0] * r : acc2 + w2[b] * r;
+                        acc2 = accum<float>(b, w2, row3<float>(row[0], row[1], row[2], row[3], w3), acc2);
                     }
-                    acc = a == 0 ? w1[0] * acc2 : acc + w1[a] * acc2;
+                    acc = accum<float>(a, w1, acc2, acc);
                 }
             } else {  // stencil outside the staged box: global loads, wrapped per node
 #pragma unroll 1
@@ -467,11 +480,12 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
                     float acc2 = 0.f;
                     for (int b = 0; b < 4; ++b) {
                         const float *row = src + (ra + wrapg(b2 + b, g.n2)) * g.n3;
-                        const float r = row[wrapg(b3, g.n3)] * w3[0] + row[wrapg(b3 + 1, g.n3)] * w3[1] +
-                                        row[wrapg(b3 + 2, g.n3)] * w3[2] + row[wrapg(b3 + 3, g.n3)] * w3[3];
-                        acc2 = b == 0 ? w2[0] * r : acc2 + w2[b] * r;
+                        acc2 = accum<float>(b, w2,
+                                            row3<float>(row[wrapg(b3, g.n3)], row[wrapg(b3 + 1, g.n3)],
+                                                        row[wrapg(b3 + 2, g.n3)], row[wrapg(b3 + 3, g.n3)], w3),
+                                            acc2);
                     }
-                    acc = a == 0 ? w1[0] * acc2 : acc + w1[a] * acc2;
+                    acc = accum<float>(a, w1, acc2, acc);
                 }
             }
             val[q][f] = acc;
