@@ -541,10 +541,15 @@ template <int M>
 struct RowShape {
     using P = RowPlan<M>;
     static constexpr int RB = P::RB, NP = P::NP;
-    static constexpr int RPITCH = M + 1;     // LDS row pitch (complex values)
-    static constexpr int XCH = RB * RPITCH;  // exchange buffer (complex values)
+    static constexpr int RPITCH = M + M / 8 + 1;  // LDS row pitch (complex values)
+    static constexpr int XCH = RB * RPITCH;       // exchange buffer (complex values)
     static_assert(RB * M == 8 * 256, "eight values per thread");
 };
+
+// LDS slot of row element e: one pad value after every eight, so that the
+// stride-R writes of a pass (lanes j, j + 1 write elements R j + r) spread
+// over the banks
+__device__ __forceinline__ int rw_slot(int e) { return e + (e >> 3); }
 
 template <int M, int R>
 __device__ __forceinline__ int rw_line(int t)
@@ -596,13 +601,14 @@ __device__ __forceinline__ void rw_run(C *v, C *X, const C *__restrict__ tw)
 #pragma unroll
         for (int t = 0; t < 8 / R; ++t)
 #pragma unroll
-            for (int r = 0; r < R; ++r) X[rw_line<M, R>(t) * S::RPITCH + rw_out_elem<M, R, NS>(t, r)] = v[t * R + r];
+            for (int r = 0; r < R; ++r)
+                X[rw_line<M, R>(t) * S::RPITCH + rw_slot(rw_out_elem<M, R, NS>(t, r))] = v[t * R + r];
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 8 / R2; ++t)
 #pragma unroll
             for (int r = 0; r < R2; ++r)
-                v[t * R2 + r] = X[rw_line<M, R2>(t) * S::RPITCH + rw_but<M, R2>(t) + r * (M / R2)];
+                v[t * R2 + r] = X[rw_line<M, R2>(t) * S::RPITCH + rw_slot(rw_but<M, R2>(t) + r * (M / R2))];
         rw_run<M, FWD, INV, P0 + 1, NS * R>(v, X, tw);
     }
 }
@@ -638,7 +644,8 @@ __global__ __launch_bounds__(256) void k_r2c_reg(RealIn in, char *__restrict__ s
 #pragma unroll
     for (int t = 0; t < 8 / RL; ++t)
 #pragma unroll
-        for (int r = 0; r < RL; ++r) X[rw_line<M, RL>(t) * S::RPITCH + rw_out_elem<M, RL, M / RL>(t, r)] = v[t * RL + r];
+        for (int r = 0; r < RL; ++r)
+            X[rw_line<M, RL>(t) * S::RPITCH + rw_slot(rw_out_elem<M, RL, M / RL>(t, r))] = v[t * RL + r];
     __syncthreads();
     C *outm = reinterpret_cast<C *>(spec + (long)(slot0 + f) * slot_bytes);
     C *outq = outm + nrow * M;
@@ -646,8 +653,8 @@ __global__ __launch_bounds__(256) void k_r2c_reg(RealIn in, char *__restrict__ s
         const int c = idx / (M + 1), k = idx - c * (M + 1);
         const long row = row0 + c;
         if (row >= nrow) continue;
-        const C zk = X[c * S::RPITCH + (k == M ? 0 : k)];
-        const C zc = conj_(X[c * S::RPITCH + (k == 0 ? 0 : M - k)]);
+        const C zk = X[c * S::RPITCH + rw_slot(k == M ? 0 : k)];
+        const C zc = conj_(X[c * S::RPITCH + rw_slot(k == 0 ? 0 : M - k)]);
         const C E = scl(add(zk, zc), R(0.5));
         const C D = scl(sub(zk, zc), R(0.5));
         const C O = mk<C>(D.y, -D.x);  // D / i
@@ -678,7 +685,7 @@ __global__ __launch_bounds__(256) void k_c2r_reg(const char *__restrict__ spec, 
         const long row = row0 + c;
         float2 Xv = make_float2(0.f, 0.f);
         if (row < nrow) Xv = (k < M) ? inm[row * M + k] : inq[row];
-        X[c * S::RPITCH + k] = Xv;
+        X[c * S::RPITCH + rw_slot(k)] = Xv;
     }
     __syncthreads();
     float2 v[8];
@@ -688,8 +695,8 @@ __global__ __launch_bounds__(256) void k_c2r_reg(const char *__restrict__ spec, 
 #pragma unroll
         for (int r = 0; r < RA; ++r) {
             const int k = rw_but<M, RA>(t) + r * (M / RA);
-            const float2 Xk = X[c * S::RPITCH + k];
-            const float2 Xc = conj_(X[c * S::RPITCH + M - k]);
+            const float2 Xk = X[c * S::RPITCH + rw_slot(k)];
+            const float2 Xc = conj_(X[c * S::RPITCH + rw_slot(M - k)]);
             const float2 E = add(Xk, Xc);
             const float2 O = mulc(sub(Xk, Xc), tw_n[k]);  // * exp(+2 pi i k / n3)
             v[t * RA + r] = add(E, muli(O));
@@ -888,41 +895,43 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(char *__restrict__ spe
 // first pass of the inverse run with the radices in reverse order, so a
 // pointwise symbol is applied in registers between the two.
 // ---------------------------------------------------------------------------
+// TWA and TWB: the two column-tile widths (threads = TW L / 8) the
+// autotuner chooses between
 template <int L>
 struct StPlan {
     static constexpr bool ok = false;
-    static constexpr int NP = 1, TW = 1, NT = 256;
+    static constexpr int NP = 1, TWA = 1, TWB = 1;
     static constexpr int radix(int) { return 1; }
 };
 template <>
 struct StPlan<64> {
     static constexpr bool ok = true;
-    static constexpr int NP = 2, TW = 32, NT = 256;
-    static constexpr int radix(int p) { return p == 0 ? 8 : 8; }
+    static constexpr int NP = 2, TWA = 32, TWB = 16;
+    static constexpr int radix(int) { return 8; }
 };
 template <>
 struct StPlan<128> {
     static constexpr bool ok = true;
-    static constexpr int NP = 3, TW = 16, NT = 256;
+    static constexpr int NP = 3, TWA = 16, TWB = 8;
     static constexpr int radix(int p) { return p == 0 ? 8 : 4; }
 };
 template <>
 struct StPlan<256> {
     static constexpr bool ok = true;
-    static constexpr int NP = 3, TW = 16, NT = 512;
+    static constexpr int NP = 3, TWA = 16, TWB = 8;
     static constexpr int radix(int p) { return p < 2 ? 8 : 4; }
 };
 template <>
 struct StPlan<512> {
     static constexpr bool ok = true;
-    static constexpr int NP = 3, TW = 8, NT = 512;
+    static constexpr int NP = 3, TWA = 8, TWB = 4;
     static constexpr int radix(int) { return 8; }
 };
 
-template <int L>
+template <int L, int TW_>
 struct StShape {
     using P = StPlan<L>;
-    static constexpr int TW = P::TW, NT = P::NT, NP = P::NP;
+    static constexpr int TW = TW_, NT = TW_ * L / 8, NP = P::NP;
     static constexpr int RL = P::radix(NP - 1);  // radix of the last forward pass
     static constexpr int NTL = 8 / RL;           // butterflies a thread holds after it
     static constexpr int PITCH = TW + 1;         // LDS row pitch (complex values)
@@ -931,10 +940,10 @@ struct StShape {
 };
 
 // one pass over registers v (8 values: task t, element r at v[t R + r])
-template <int L, int R, int NS, bool INV, class C>
+template <int L, int TW, int R, int NS, bool INV, class C>
 __device__ __forceinline__ void st_butterflies(C *v, const C *__restrict__ tw)
 {
-    using S = StShape<L>;
+    using S = StShape<L, TW>;
 #pragma unroll
     for (int t = 0; t < 8 / R; ++t) {
         const int j = ((int)threadIdx.x + S::NT * t) / S::TW;
@@ -952,18 +961,18 @@ __device__ __forceinline__ void st_butterflies(C *v, const C *__restrict__ tw)
 }
 
 // element rows written by a pass (Ns = NS, radix R) for task t, value r
-template <int L, int R, int NS>
+template <int L, int TW, int R, int NS>
 __device__ __forceinline__ int st_out_row(int t, int r)
 {
-    using S = StShape<L>;
+    using S = StShape<L, TW>;
     const int j = ((int)threadIdx.x + S::NT * t) / S::TW, jm = j & (NS - 1);
     return (j - jm) * R + jm + r * NS;
 }
 
-template <int L, int R>
+template <int L, int TW, int R>
 __device__ __forceinline__ int st_in_row(int t, int r)
 {
-    using S = StShape<L>;
+    using S = StShape<L, TW>;
     return ((int)threadIdx.x + S::NT * t) / S::TW + r * (L / R);
 }
 
@@ -972,12 +981,12 @@ __device__ __forceinline__ int st_col(int t, int NT, int TW) { return ((int)thre
 // passes P0.. of a transform whose input already sits in v (as pass P0
 // reads it); the radices are taken in forward order (FWD) or reversed;
 // intermediate results go through X; the final pass leaves its outputs in v
-template <int L, bool FWD, bool INV, int P0, int NS, class C>
+template <int L, int TW, bool FWD, bool INV, int P0, int NS, class C>
 __device__ __forceinline__ void st_run(C *v, C *X, const C *__restrict__ tw)
 {
-    using S = StShape<L>;
+    using S = StShape<L, TW>;
     constexpr int R = FWD ? S::P::radix(P0) : S::P::radix(S::NP - 1 - P0);
-    st_butterflies<L, R, NS, INV>(v, tw);
+    st_butterflies<L, TW, R, NS, INV>(v, tw);
     if constexpr (P0 + 1 < S::NP) {
         constexpr int R2 = FWD ? S::P::radix(P0 + 1) : S::P::radix(S::NP - 2 - P0);
         __syncthreads();  // X free
@@ -985,57 +994,57 @@ __device__ __forceinline__ void st_run(C *v, C *X, const C *__restrict__ tw)
         for (int t = 0; t < 8 / R; ++t)
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                X[st_out_row<L, R, NS>(t, r) * S::PITCH + st_col(t, S::NT, S::TW)] = v[t * R + r];
+                X[st_out_row<L, TW, R, NS>(t, r) * S::PITCH + st_col(t, S::NT, S::TW)] = v[t * R + r];
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 8 / R2; ++t)
 #pragma unroll
             for (int r = 0; r < R2; ++r)
-                v[t * R2 + r] = X[st_in_row<L, R2>(t, r) * S::PITCH + st_col(t, S::NT, S::TW)];
-        st_run<L, FWD, INV, P0 + 1, NS * R>(v, X, tw);
+                v[t * R2 + r] = X[st_in_row<L, TW, R2>(t, r) * S::PITCH + st_col(t, S::NT, S::TW)];
+        st_run<L, TW, FWD, INV, P0 + 1, NS * R>(v, X, tw);
     }
 }
 
 // forward transform: load(n, c) -> v holds X[j + r L/R_P] (task t at v[t R_P + r])
-template <int L, class C, class LoadF>
+template <int L, int TW, class C, class LoadF>
 __device__ __forceinline__ void st_fwd(LoadF &&load, C *v, C *X, const C *__restrict__ tw)
 {
-    using S = StShape<L>;
+    using S = StShape<L, TW>;
     constexpr int R = S::P::radix(0);
 #pragma unroll
     for (int t = 0; t < 8 / R; ++t)
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[t * R + r] = load(st_in_row<L, R>(t, r), st_col(t, S::NT, S::TW));
-    st_run<L, true, false, 0, 1>(v, X, tw);
+        for (int r = 0; r < R; ++r) v[t * R + r] = load(st_in_row<L, TW, R>(t, r), st_col(t, S::NT, S::TW));
+    st_run<L, TW, true, false, 0, 1>(v, X, tw);
 }
 
 // spectral index (x1 wavenumber index) of held value i after st_fwd
-template <int L>
+template <int L, int TW>
 __device__ __forceinline__ int st_held_index(int i)
 {
-    using S = StShape<L>;
-    return st_in_row<L, S::RL>(i / S::RL, i % S::RL);
+    using S = StShape<L, TW>;
+    return st_in_row<L, TW, S::RL>(i / S::RL, i % S::RL);
 }
-template <int L>
+template <int L, int TW>
 __device__ __forceinline__ int st_held_col(int i)
 {
-    using S = StShape<L>;
+    using S = StShape<L, TW>;
     return st_col(i / S::RL, S::NT, S::TW);
 }
 
 // inverse transform from the layout st_fwd leaves (v is overwritten):
 // store(n, c, value) for every element of the tile
-template <int L, class C, class StoreF>
+template <int L, int TW, class C, class StoreF>
 __device__ __forceinline__ void st_inv(C *v, C *X, StoreF &&store, const C *__restrict__ tw)
 {
-    using S = StShape<L>;
-    st_run<L, false, true, 0, 1>(v, X, tw);
+    using S = StShape<L, TW>;
+    st_run<L, TW, false, true, 0, 1>(v, X, tw);
     constexpr int R = S::P::radix(0);  // the inverse ends with the first forward radix
     constexpr int NS = L / R;
 #pragma unroll
     for (int t = 0; t < 8 / R; ++t)
 #pragma unroll
-        for (int r = 0; r < R; ++r) store(st_out_row<L, R, NS>(t, r), st_col(t, S::NT, S::TW), v[t * R + r]);
+        for (int r = 0; r < R; ++r) store(st_out_row<L, TW, R, NS>(t, r), st_col(t, S::NT, S::TW), v[t * R + r]);
 }
 
 // Column pass with register line FFTs (lengths with a RegPlan)
@@ -1288,14 +1297,13 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
 // x1 transform of the outputs; the same arithmetic, in the same order and
 // precision, as the LDS kernels above.  blockIdx.z is the batch index.
 // ---------------------------------------------------------------------------
-template <int OP, int L>
-__global__ __launch_bounds__(StPlan<L>::NT) void k_x1_reg(char *__restrict__ spec, long slot_bytes, int in0,
+template <int OP, int L, int TW>
+__global__ __launch_bounds__(TW * L / 8) void k_x1_reg(char *__restrict__ spec, long slot_bytes, int in0,
                                                          int out0, ColDesc d, int nyq,
                                                          const double2 *__restrict__ twd,
                                                          const float2 *__restrict__ twf, SymCtx sc)
 {
-    using S = StShape<L>;
-    constexpr int TW = S::TW;
+    using S = StShape<L, TW>;
     extern __shared__ char lds_raw[];
     double2 *XD = reinterpret_cast<double2 *>(lds_raw);
     float2 *XF = reinterpret_cast<float2 *>(lds_raw);
@@ -1326,12 +1334,12 @@ __global__ __launch_bounds__(StPlan<L>::NT) void k_x1_reg(char *__restrict__ spe
     };
     // spectral position of held value i: x1 index n(i), columns give (l2, l3)
     auto pos = [&](int i, int &n, int &l2, int &l3) {
-        n = st_held_index<L>(i);
-        cc.l23(sc, col0 + st_held_col<L>(i), l2, l3);
+        n = st_held_index<L, TW>(i);
+        cc.l23(sc, col0 + st_held_col<L, TW>(i), l2, l3);
     };
     if constexpr (OP == SOP_GRAD) {  // one FP64 field -> three FP32 fields
         double2 f[8];
-        st_fwd<L>(load_d(in0 + z), f, XD, twd);
+        st_fwd<L, TW>(load_d(in0 + z), f, XD, twd);
 #pragma unroll 1
         for (int q = 0; q < 3; ++q) {
             float2 o[8];
@@ -1343,7 +1351,7 @@ __global__ __launch_bounds__(StPlan<L>::NT) void k_x1_reg(char *__restrict__ spe
                 o[i] = to_f2(muli(scl(scl(f[i], sc.scale), kq)));
             }
             __syncthreads();  // the exchange buffer is reused
-            st_inv<L>(o, XF, store(out0 + 3 * z + q), twf);
+            st_inv<L, TW>(o, XF, store(out0 + 3 * z + q), twf);
         }
     } else if constexpr (OP == SOP_DIV) {  // three FP64 fields -> one FP32 field
         double2 acc[8];
@@ -1351,7 +1359,7 @@ __global__ __launch_bounds__(StPlan<L>::NT) void k_x1_reg(char *__restrict__ spe
         for (int q = 0; q < 3; ++q) {
             double2 f[8];
             if (q > 0) __syncthreads();
-            st_fwd<L>(load_d(in0 + 3 * z + q), f, XD, twd);
+            st_fwd<L, TW>(load_d(in0 + 3 * z + q), f, XD, twd);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 int n, l2, l3;
@@ -1365,13 +1373,13 @@ __global__ __launch_bounds__(StPlan<L>::NT) void k_x1_reg(char *__restrict__ spe
 #pragma unroll
         for (int i = 0; i < 8; ++i) o[i] = to_f2(acc[i]);
         __syncthreads();
-        st_inv<L>(o, XF, store(out0 + z), twf);
+        st_inv<L, TW>(o, XF, store(out0 + z), twf);
     } else if constexpr (OP == SOP_LERAY) {  // three FP32 fields in and out
         float2 w[3][8];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             if (q > 0) __syncthreads();
-            st_fwd<L>(load_f(in0 + 3 * z + q), w[q], XF, twf);
+            st_fwd<L, TW>(load_f(in0 + 3 * z + q), w[q], XF, twf);
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -1391,7 +1399,7 @@ __global__ __launch_bounds__(StPlan<L>::NT) void k_x1_reg(char *__restrict__ spe
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             __syncthreads();
-            st_inv<L>(w[q], XF, store(out0 + 3 * z + q), twf);
+            st_inv<L, TW>(w[q], XF, store(out0 + 3 * z + q), twf);
         }
     } else if constexpr (OP == SOP_ASSEMBLE) {  // w: 3 FP64, b: 3 FP32 -> 3 FP32
         // o_q = (K b)_q + beta A w_q: the b part first (the Leray accumulator
@@ -1401,7 +1409,7 @@ __global__ __launch_bounds__(StPlan<L>::NT) void k_x1_reg(char *__restrict__ spe
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             if (q > 0) __syncthreads();
-            st_fwd<L>(load_f(b0 + q), o[q], XF, twf);
+            st_fwd<L, TW>(load_f(b0 + q), o[q], XF, twf);
             if (sc.leray) {
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
@@ -1431,7 +1439,7 @@ __global__ __launch_bounds__(StPlan<L>::NT) void k_x1_reg(char *__restrict__ spe
         for (int q = 0; q < 3; ++q) {
             double2 f[8];
             __syncthreads();
-            st_fwd<L>(load_d(w0 + q), f, XD, twd);
+            st_fwd<L, TW>(load_d(w0 + q), f, XD, twd);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 int n, l2, l3;
@@ -1439,16 +1447,16 @@ __global__ __launch_bounds__(StPlan<L>::NT) void k_x1_reg(char *__restrict__ spe
                 o[q][i] = add(o[q][i], to_f2(scl(f[i], sc.beta * reg_symbol(sc, n, l2, l3) * sc.scale)));
             }
             __syncthreads();
-            st_inv<L>(o[q], XF, store(o0 + q), twf);
+            st_inv<L, TW>(o[q], XF, store(o0 + q), twf);
         }
     } else {  // scalar symbols: REG (FP64), INVREG and IDENT (FP32)
         using C = typename std::conditional<OP == SOP_REG, double2, float2>::type;
         using R = typename RealOf<C>::type;
         C f[8];
         if constexpr (OP == SOP_REG)
-            st_fwd<L>(load_d(in0 + z), f, XD, twd);
+            st_fwd<L, TW>(load_d(in0 + z), f, XD, twd);
         else
-            st_fwd<L>(load_f(in0 + z), f, XF, twf);
+            st_fwd<L, TW>(load_f(in0 + z), f, XF, twf);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             int n, l2, l3;
@@ -1464,9 +1472,9 @@ __global__ __launch_bounds__(StPlan<L>::NT) void k_x1_reg(char *__restrict__ spe
         }
         __syncthreads();
         if constexpr (OP == SOP_REG)
-            st_inv<L>(f, XD, store(out0 + z), twd);
+            st_inv<L, TW>(f, XD, store(out0 + z), twd);
         else
-            st_inv<L>(f, XF, store(out0 + z), twf);
+            st_inv<L, TW>(f, XF, store(out0 + z), twf);
     }
 }
 
@@ -1938,6 +1946,37 @@ static SymCtx sym_ctx(lddmm_plan *P, int leray)
 
 // x1 forward, symbol, x1 inverse for nbatch batches: inputs of batch b at
 // slots in0 + b*nin .. , outputs at out0 + b*nout ..
+template <int LF, int TW>
+static void x1_reg_launch(lddmm_plan *P, int op, int in0, int out0, const ColDesc &d, int part, int outer,
+                          int nbatch, const SymCtx &sc)
+{
+    FftCtx &F = P->fft;
+    using RS = StShape<LF, TW>;
+    const bool fp64x = op == SOP_GRAD || op == SOP_DIV || op == SOP_ASSEMBLE || op == SOP_REG;
+    const size_t lds = (fp64x ? sizeof(double2) : sizeof(float2)) * RS::XCH;
+    check_lds(lds, "x1_symbol");
+    const int nz = (op == SOP_REG || op == SOP_INVREG) ? 3 * nbatch : nbatch;
+    const dim3 grid((unsigned)((d.ncols + TW - 1) / TW), outer, nz);
+    Scope s(P, K_SPECTRAL_X1);
+#define X1R(OPV)                                                                                         \
+    do {                                                                                                 \
+        if (lds > 65536) allow_big_lds((const void *)(k_x1_reg<OPV, LF, TW>));                           \
+        hipLaunchKernelGGL((k_x1_reg<OPV, LF, TW>), grid, dim3(RS::NT), lds, P->stream, P->spec,         \
+                           P->slot_bytes, in0, out0, d, part, F.tw1d, F.tw1, sc);                        \
+    } while (0)
+    switch (op) {
+    case SOP_GRAD: X1R(SOP_GRAD); break;
+    case SOP_DIV: X1R(SOP_DIV); break;
+    case SOP_LERAY: X1R(SOP_LERAY); break;
+    case SOP_ASSEMBLE: X1R(SOP_ASSEMBLE); break;
+    case SOP_REG: X1R(SOP_REG); break;
+    case SOP_INVREG: X1R(SOP_INVREG); break;
+    case SOP_IDENT: X1R(SOP_IDENT); break;
+    default: fail(LDDMM_EINVAL, "unknown spectral operator");
+    }
+#undef X1R
+}
+
 static void x1_symbol_parts(lddmm_plan *P, int op, int in0, int out0, int nbatch, int leray, int only_part);
 
 void x1_symbol(lddmm_plan *P, int op, int in0, int out0, int nbatch, int leray)
@@ -1960,30 +1999,12 @@ static void x1_symbol_parts(lddmm_plan *P, int op, int in0, int out0, int nbatch
         bool done = false;
         with_len(L, [&]<int LF>() {
             if constexpr (StPlan<LF>::ok) {
-                using RS = StShape<LF>;
-                const bool fp64x = op == SOP_GRAD || op == SOP_DIV || op == SOP_ASSEMBLE || op == SOP_REG;
-                const size_t lds = (fp64x ? sizeof(double2) : sizeof(float2)) * RS::XCH;
-                check_lds(lds, "x1_symbol");
-                const int nz = (op == SOP_REG || op == SOP_INVREG) ? 3 * nbatch : nbatch;
-                const dim3 grid((unsigned)((d.ncols + RS::TW - 1) / RS::TW), outer[part], nz);
-                Scope s(P, K_SPECTRAL_X1);
-#define X1R(OPV)                                                                                           \
-    do {                                                                                                   \
-        if (lds > 65536) allow_big_lds((const void *)(k_x1_reg<OPV, LF>));                                 \
-        hipLaunchKernelGGL((k_x1_reg<OPV, LF>), grid, dim3(RS::NT), lds, P->stream, P->spec, P->slot_bytes, \
-                           in0, out0, d, part, F.tw1d, F.tw1, sc);                                         \
-    } while (0)
-                switch (op) {
-                case SOP_GRAD: X1R(SOP_GRAD); break;
-                case SOP_DIV: X1R(SOP_DIV); break;
-                case SOP_LERAY: X1R(SOP_LERAY); break;
-                case SOP_ASSEMBLE: X1R(SOP_ASSEMBLE); break;
-                case SOP_REG: X1R(SOP_REG); break;
-                case SOP_INVREG: X1R(SOP_INVREG); break;
-                case SOP_IDENT: X1R(SOP_IDENT); break;
-                default: fail(LDDMM_EINVAL, "unknown spectral operator");
-                }
-#undef X1R
+                using SP = StPlan<LF>;
+                const bool wide = F.tw_x1[op][part] >= SP::TWA;
+                if (wide)
+                    x1_reg_launch<LF, SP::TWA>(P, op, in0, out0, d, part, outer[part], nbatch, sc);
+                else
+                    x1_reg_launch<LF, SP::TWB>(P, op, in0, out0, d, part, outer[part], nbatch, sc);
                 done = true;
             }
         });
@@ -2098,11 +2119,11 @@ static float time_ms(lddmm_plan *P, Fn &&fn)
 }
 
 template <class Fn>
-static void tune_one(lddmm_plan *P, int &slot, int top, Fn &&fn)
+static void tune_one(lddmm_plan *P, int &slot, int top, Fn &&fn, int bottom = 1)
 {
     int best = top;
     float bt = 1e30f;
-    for (int t = top; t >= 1; t >>= 1) {
+    for (int t = top; t >= bottom; t >>= 1) {
         slot = t;
         const float ms = time_ms(P, fn);
         if (ms < bt) {
@@ -2199,10 +2220,22 @@ void autotune_fft(lddmm_plan *P)
     int o1[2];
     col_descs(F, 0, d1, o1);
     const int ops[] = {SOP_GRAD, SOP_DIV, SOP_REG, SOP_INVREG, SOP_LERAY, SOP_ASSEMBLE};
+    int twa = 0, twb = 0;  // register-pass tile widths, when the x1 length has them
+    with_len(F.rp1.L, [&]<int LF>() {
+        if constexpr (StPlan<LF>::ok) {
+            twa = StPlan<LF>::TWA;
+            twb = StPlan<LF>::TWB;
+        }
+    });
     for (int op : ops)
-        for (int part = 0; part < 2; ++part)
-            tune_one(P, F.tw_x1[op][part], col_tile(F.rp1.L, x1_bytes_per_elem(op), d1[part].ncols, kLdsMax),
-                     [&] { x1_symbol_parts(P, op, 0, op_nin(op), 1, 1, part); });
+        for (int part = 0; part < 2; ++part) {
+            auto run = [&] { x1_symbol_parts(P, op, 0, op_nin(op), 1, 1, part); };
+            if (twa > 0)
+                tune_one(P, F.tw_x1[op][part], twa, run, twb);
+            else
+                tune_one(P, F.tw_x1[op][part],
+                         col_tile(F.rp1.L, x1_bytes_per_elem(op), d1[part].ncols, kLdsMax), run);
+        }
     P->timing.on = timing;
     F.tuned = 1;
     std::vector<int> vals;
