@@ -501,49 +501,49 @@ static void allow_big_lds(const void *k)
     } while (0)
 
 // ---------------------------------------------------------------------------
-// Register Stockham passes along x3 rows (the R2C / C2R passes): a 256-thread
-// workgroup owns RB rows of M = n3/2 complex points, eight values per
-// thread; task (row, j) with the butterfly index j fastest, so the global
-// accesses of one element r of a pass are contiguous along the row.
+// Register Stockham passes along x3 rows (the R2C / C2R passes): a workgroup
+// of RB M / 8 threads owns RB rows of M = n3/2 complex points, eight values
+// per thread; task (row, j) with the butterfly index j fastest, so the
+// global accesses of one element r of a pass are contiguous along the row.
+// RBA and RBB: the two row counts the autotuner chooses between.
 // ---------------------------------------------------------------------------
 template <int M>
 struct RowPlan {
     static constexpr bool ok = false;
-    static constexpr int NP = 1, RB = 1;
+    static constexpr int NP = 1, RBA = 1, RBB = 1;
     static constexpr int radix(int) { return 1; }
 };
 template <>
 struct RowPlan<64> {
     static constexpr bool ok = true;
-    static constexpr int NP = 2, RB = 32;
+    static constexpr int NP = 2, RBA = 32, RBB = 16;
     static constexpr int radix(int) { return 8; }
 };
 template <>
 struct RowPlan<128> {
     static constexpr bool ok = true;
-    static constexpr int NP = 3, RB = 16;
+    static constexpr int NP = 3, RBA = 16, RBB = 8;
     static constexpr int radix(int p) { return p == 0 ? 8 : 4; }
 };
 template <>
 struct RowPlan<256> {
     static constexpr bool ok = true;
-    static constexpr int NP = 3, RB = 8;
+    static constexpr int NP = 3, RBA = 8, RBB = 4;
     static constexpr int radix(int p) { return p < 2 ? 8 : 4; }
 };
 template <>
 struct RowPlan<512> {
     static constexpr bool ok = true;
-    static constexpr int NP = 3, RB = 4;
+    static constexpr int NP = 3, RBA = 4, RBB = 2;
     static constexpr int radix(int) { return 8; }
 };
 
-template <int M>
+template <int M, int RB_>
 struct RowShape {
     using P = RowPlan<M>;
-    static constexpr int RB = P::RB, NP = P::NP;
+    static constexpr int RB = RB_, NP = P::NP, NT = RB_ * M / 8;
     static constexpr int RPITCH = M + M / 8 + 1;  // LDS row pitch (complex values)
     static constexpr int XCH = RB * RPITCH;       // exchange buffer (complex values)
-    static_assert(RB * M == 8 * 256, "eight values per thread");
 };
 
 // LDS slot of row element e: one pad value after every eight, so that the
@@ -551,24 +551,24 @@ struct RowShape {
 // over the banks
 __device__ __forceinline__ int rw_slot(int e) { return e + (e >> 3); }
 
-template <int M, int R>
+template <int M, int RB, int R>
 __device__ __forceinline__ int rw_line(int t)
 {
-    return ((int)threadIdx.x + 256 * t) / (M / R);
+    return ((int)threadIdx.x + RowShape<M, RB>::NT * t) / (M / R);
 }
-template <int M, int R>
+template <int M, int RB, int R>
 __device__ __forceinline__ int rw_but(int t)
 {
-    return ((int)threadIdx.x + 256 * t) % (M / R);
+    return ((int)threadIdx.x + RowShape<M, RB>::NT * t) % (M / R);
 }
 
-template <int M, int R, int NS, bool INV, class C>
+template <int M, int RB, int R, int NS, bool INV, class C>
 __device__ __forceinline__ void rw_butterflies(C *v, const C *__restrict__ tw)
 {
 #pragma unroll
     for (int t = 0; t < 8 / R; ++t) {
         if constexpr (NS > 1) {
-            const int jm = rw_but<M, R>(t) & (NS - 1);
+            const int jm = rw_but<M, RB, R>(t) & (NS - 1);
             constexpr int step = M / (NS * R);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
@@ -580,21 +580,21 @@ __device__ __forceinline__ void rw_butterflies(C *v, const C *__restrict__ tw)
     }
 }
 
-template <int M, int R, int NS>
+template <int M, int RB, int R, int NS>
 __device__ __forceinline__ int rw_out_elem(int t, int r)
 {
-    const int j = rw_but<M, R>(t), jm = j & (NS - 1);
+    const int j = rw_but<M, RB, R>(t), jm = j & (NS - 1);
     return (j - jm) * R + jm + r * NS;
 }
 
 // passes P0.. in forward (FWD) or reversed radix order, input in v as pass
 // P0 reads it; the final pass leaves its outputs in v
-template <int M, bool FWD, bool INV, int P0, int NS, class C>
+template <int M, int RB, bool FWD, bool INV, int P0, int NS, class C>
 __device__ __forceinline__ void rw_run(C *v, C *X, const C *__restrict__ tw)
 {
-    using S = RowShape<M>;
+    using S = RowShape<M, RB>;
     constexpr int R = FWD ? S::P::radix(P0) : S::P::radix(S::NP - 1 - P0);
-    rw_butterflies<M, R, NS, INV>(v, tw);
+    rw_butterflies<M, RB, R, NS, INV>(v, tw);
     if constexpr (P0 + 1 < S::NP) {
         constexpr int R2 = FWD ? S::P::radix(P0 + 1) : S::P::radix(S::NP - 2 - P0);
         __syncthreads();
@@ -602,25 +602,25 @@ __device__ __forceinline__ void rw_run(C *v, C *X, const C *__restrict__ tw)
         for (int t = 0; t < 8 / R; ++t)
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                X[rw_line<M, R>(t) * S::RPITCH + rw_slot(rw_out_elem<M, R, NS>(t, r))] = v[t * R + r];
+                X[rw_line<M, RB, R>(t) * S::RPITCH + rw_slot(rw_out_elem<M, RB, R, NS>(t, r))] = v[t * R + r];
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 8 / R2; ++t)
 #pragma unroll
             for (int r = 0; r < R2; ++r)
-                v[t * R2 + r] = X[rw_line<M, R2>(t) * S::RPITCH + rw_slot(rw_but<M, R2>(t) + r * (M / R2))];
-        rw_run<M, FWD, INV, P0 + 1, NS * R>(v, X, tw);
+                v[t * R2 + r] = X[rw_line<M, RB, R2>(t) * S::RPITCH + rw_slot(rw_but<M, RB, R2>(t) + r * (M / R2))];
+        rw_run<M, RB, FWD, INV, P0 + 1, NS * R>(v, X, tw);
     }
 }
 
 // R2C rows with register passes: n3 = 2M real values per row
-template <class R, int M>
-__global__ __launch_bounds__(256) void k_r2c_reg(RealIn in, char *__restrict__ spec, long slot_bytes, int slot0,
+template <class R, int M, int RB>
+__global__ __launch_bounds__(RB * M / 8) void k_r2c_reg(RealIn in, char *__restrict__ spec, long slot_bytes, int slot0,
                                                  long nrow, const typename CplxOf<R>::type *__restrict__ tw_m,
                                                  const typename CplxOf<R>::type *__restrict__ tw_n)
 {
     using C = typename CplxOf<R>::type;
-    using S = RowShape<M>;
+    using S = RowShape<M, RB>;
     constexpr int R0 = S::P::radix(0), RL = S::P::radix(S::NP - 1);
     extern __shared__ char lds_raw[];
     C *X = reinterpret_cast<C *>(lds_raw);
@@ -630,26 +630,26 @@ __global__ __launch_bounds__(256) void k_r2c_reg(RealIn in, char *__restrict__ s
     C v[8];
 #pragma unroll
     for (int t = 0; t < 8 / R0; ++t) {
-        const long row = row0 + rw_line<M, R0>(t);
+        const long row = row0 + rw_line<M, RB, R0>(t);
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-            const int e = rw_but<M, R0>(t) + r * (M / R0);
+            const int e = rw_but<M, RB, R0>(t) + r * (M / R0);
             const float2 z = row < nrow ? src[row * M + e] : make_float2(0.f, 0.f);
             v[t * R0 + r] = mk<C>((R)z.x, (R)z.y);
         }
     }
-    rw_run<M, true, false, 0, 1>(v, X, tw_m);
+    rw_run<M, RB, true, false, 0, 1>(v, X, tw_m);
     // Z to LDS (natural order), then the pairs (k, M - k) give the half spectrum
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < 8 / RL; ++t)
 #pragma unroll
         for (int r = 0; r < RL; ++r)
-            X[rw_line<M, RL>(t) * S::RPITCH + rw_slot(rw_out_elem<M, RL, M / RL>(t, r))] = v[t * RL + r];
+            X[rw_line<M, RB, RL>(t) * S::RPITCH + rw_slot(rw_out_elem<M, RB, RL, M / RL>(t, r))] = v[t * RL + r];
     __syncthreads();
     C *outm = reinterpret_cast<C *>(spec + (long)(slot0 + f) * slot_bytes);
     C *outq = outm + nrow * M;
-    for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += 256) {
+    for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += S::NT) {
         const int c = idx / (M + 1), k = idx - c * (M + 1);
         const long row = row0 + c;
         if (row >= nrow) continue;
@@ -667,12 +667,12 @@ __global__ __launch_bounds__(256) void k_r2c_reg(RealIn in, char *__restrict__ s
 }
 
 // C2R rows with register passes (FP32), times scale
-template <int M>
-__global__ __launch_bounds__(256) void k_c2r_reg(const char *__restrict__ spec, long slot_bytes, int slot0,
+template <int M, int RB>
+__global__ __launch_bounds__(RB * M / 8) void k_c2r_reg(const char *__restrict__ spec, long slot_bytes, int slot0,
                                                  RealOut out, long nrow, const float2 *__restrict__ tw_m,
                                                  const float2 *__restrict__ tw_n, float scale)
 {
-    using S = RowShape<M>;
+    using S = RowShape<M, RB>;
     constexpr int RA = S::P::radix(S::NP - 1), R1 = S::P::radix(0);  // first and last inverse radices
     extern __shared__ char lds_raw[];
     float2 *X = reinterpret_cast<float2 *>(lds_raw);
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(256) void k_c2r_reg(const char *__restrict__ spec, 
     const long row0 = (long)blockIdx.x * S::RB;
     const float2 *inm = reinterpret_cast<const float2 *>(spec + (long)(slot0 + f) * slot_bytes);
     const float2 *inq = inm + nrow * M;
-    for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += 256) {
+    for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += S::NT) {
         const int c = idx / (M + 1), k = idx - c * (M + 1);
         const long row = row0 + c;
         float2 Xv = make_float2(0.f, 0.f);
@@ -691,10 +691,10 @@ __global__ __launch_bounds__(256) void k_c2r_reg(const char *__restrict__ spec, 
     float2 v[8];
 #pragma unroll
     for (int t = 0; t < 8 / RA; ++t) {
-        const int c = rw_line<M, RA>(t);
+        const int c = rw_line<M, RB, RA>(t);
 #pragma unroll
         for (int r = 0; r < RA; ++r) {
-            const int k = rw_but<M, RA>(t) + r * (M / RA);
+            const int k = rw_but<M, RB, RA>(t) + r * (M / RA);
             const float2 Xk = X[c * S::RPITCH + rw_slot(k)];
             const float2 Xc = conj_(X[c * S::RPITCH + rw_slot(M - k)]);
             const float2 E = add(Xk, Xc);
@@ -702,15 +702,15 @@ __global__ __launch_bounds__(256) void k_c2r_reg(const char *__restrict__ spec, 
             v[t * RA + r] = add(E, muli(O));
         }
     }
-    rw_run<M, false, true, 0, 1>(v, X, tw_m);
+    rw_run<M, RB, false, true, 0, 1>(v, X, tw_m);
     float *__restrict__ dst = out.p[f];
 #pragma unroll
     for (int t = 0; t < 8 / R1; ++t) {
-        const long row = row0 + rw_line<M, R1>(t);
+        const long row = row0 + rw_line<M, RB, R1>(t);
         if (row >= nrow) continue;
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
-            const int e = rw_out_elem<M, R1, M / R1>(t, r);
+            const int e = rw_out_elem<M, RB, R1, M / R1>(t, r);
             const float2 z = v[t * R1 + r];
             *reinterpret_cast<float2 *>(dst + row * 2 * M + 2 * e) = make_float2(z.x * scale, z.y * scale);
         }
@@ -1742,16 +1742,26 @@ void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int slot0, bool dbl)
     bool done = false;
     with_len(F.m3, [&]<int LF>() {
         if constexpr (RowPlan<LF>::ok) {
-            using RS = RowShape<LF>;
-            const size_t ldsr = cs * RS::XCH;
-            check_lds(ldsr, "r2c_x3");
-            const dim3 gr((unsigned)((F.nrow + RS::RB - 1) / RS::RB), count);
-            if (dbl)
-                FFT_LAUNCH((k_r2c_reg<double, LF>), gr, ldsr, P->stream, in, P->spec, P->slot_bytes, slot0, F.nrow,
-                           F.tw3d, F.twN3d);
+            auto go = [&]<int RB>() {
+                using RS = RowShape<LF, RB>;
+                const size_t ldsr = cs * RS::XCH;
+                check_lds(ldsr, "r2c_x3");
+                const dim3 gr((unsigned)((F.nrow + RB - 1) / RB), count);
+                const dim3 blk(RS::NT);
+                if (dbl) {
+                    if (ldsr > 65536) allow_big_lds((const void *)(k_r2c_reg<double, LF, RB>));
+                    hipLaunchKernelGGL((k_r2c_reg<double, LF, RB>), gr, blk, ldsr, P->stream, in, P->spec,
+                                       P->slot_bytes, slot0, F.nrow, F.tw3d, F.twN3d);
+                } else {
+                    if (ldsr > 65536) allow_big_lds((const void *)(k_r2c_reg<float, LF, RB>));
+                    hipLaunchKernelGGL((k_r2c_reg<float, LF, RB>), gr, blk, ldsr, P->stream, in, P->spec,
+                                       P->slot_bytes, slot0, F.nrow, F.tw3, F.twN3);
+                }
+            };
+            if (TWR >= RowPlan<LF>::RBA)
+                go.template operator()<RowPlan<LF>::RBA>();
             else
-                FFT_LAUNCH((k_r2c_reg<float, LF>), gr, ldsr, P->stream, in, P->spec, P->slot_bytes, slot0, F.nrow,
-                           F.tw3, F.twN3);
+                go.template operator()<RowPlan<LF>::RBB>();
             done = true;
         }
     });
@@ -1781,12 +1791,19 @@ void c2r_fields(lddmm_plan *P, int slot0, int count, const RealOut &out, float s
     bool done = false;
     with_len(F.m3, [&]<int LF>() {
         if constexpr (RowPlan<LF>::ok) {
-            using RS = RowShape<LF>;
-            const size_t ldsr = sizeof(float2) * RS::XCH;
-            check_lds(ldsr, "c2r_x3");
-            const dim3 gr((unsigned)((F.nrow + RS::RB - 1) / RS::RB), count);
-            FFT_LAUNCH((k_c2r_reg<LF>), gr, ldsr, P->stream, P->spec, P->slot_bytes, slot0, out, F.nrow, F.tw3, F.twN3,
-                       scale);
+            auto go = [&]<int RB>() {
+                using RS = RowShape<LF, RB>;
+                const size_t ldsr = sizeof(float2) * RS::XCH;
+                check_lds(ldsr, "c2r_x3");
+                const dim3 gr((unsigned)((F.nrow + RB - 1) / RB), count);
+                if (ldsr > 65536) allow_big_lds((const void *)(k_c2r_reg<LF, RB>));
+                hipLaunchKernelGGL((k_c2r_reg<LF, RB>), gr, dim3(RS::NT), ldsr, P->stream, P->spec, P->slot_bytes,
+                                   slot0, out, F.nrow, F.tw3, F.twN3, scale);
+            };
+            if (TWR >= RowPlan<LF>::RBA)
+                go.template operator()<RowPlan<LF>::RBA>();
+            else
+                go.template operator()<RowPlan<LF>::RBB>();
             done = true;
         }
     });
@@ -2202,10 +2219,27 @@ void autotune_fft(lddmm_plan *P)
     for (int c = 0; c < 3; ++c) ri.p[c] = P->v + c * N;
     RealOut ro{};
     for (int c = 0; c < 3; ++c) ro.p[c] = P->b + c * N;
-    for (int dbl = 0; dbl < 2; ++dbl)
-        tune_one(P, F.twr_r2c[dbl], rows_per_block(F.m3, dbl ? sizeof(double2) : sizeof(float2), kLdsMax),
-                 [&] { r2c_fields(P, ri, 3, 0, dbl != 0); });
-    tune_one(P, F.twr_c2r, rows_per_block(F.m3, sizeof(float2), kLdsMax), [&] { c2r_fields(P, 0, 3, ro, 1.f); });
+    int rba = 0, rbb = 0;  // register row-pass candidates, when n3/2 has a plan
+    with_len(F.m3, [&]<int LF>() {
+        if constexpr (RowPlan<LF>::ok) {
+            rba = RowPlan<LF>::RBA;
+            rbb = RowPlan<LF>::RBB;
+        }
+    });
+    for (int dbl = 0; dbl < 2; ++dbl) {
+        auto run = [&] { r2c_fields(P, ri, 3, 0, dbl != 0); };
+        if (rba > 0)
+            tune_one(P, F.twr_r2c[dbl], rba, run, rbb);
+        else
+            tune_one(P, F.twr_r2c[dbl], rows_per_block(F.m3, dbl ? sizeof(double2) : sizeof(float2), kLdsMax), run);
+    }
+    {
+        auto run = [&] { c2r_fields(P, 0, 3, ro, 1.f); };
+        if (rba > 0)
+            tune_one(P, F.twr_c2r, rba, run, rbb);
+        else
+            tune_one(P, F.twr_c2r, rows_per_block(F.m3, sizeof(float2), kLdsMax), run);
+    }
     for (int axis = 0; axis < 2; ++axis) {
         ColDesc dd[2];
         int outer[2];
