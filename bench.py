@@ -182,6 +182,8 @@ def bench_batched(torch, dev):
     log(f"batched: generating {len(sizes)} members")
     m0s, m1s = [], []
     for b, s in enumerate(shapes):
+        if b % 16 == 0:
+            log(f"batched: member {b}")
         seed = 4000 + 10 * b
         m0 = torch.from_numpy(synth.f32(synth.blob_image(s, 40, seed))).to(dev)
         vt = torch.from_numpy(synth.f32(synth.bandlimited_vector(s, 6, seed + 1, max_disp=4.0))).to(dev)

@@ -58,17 +58,15 @@ __device__ __forceinline__ void point_coords(const Grid3 &g, int p, int &i, int 
     i = (int)q;
 }
 
-// Lagrange basis on the nodes -1, 0, 1, 2 at t in [0,1), from the shared
-// products t (t - 1) and (t + 1)(t - 2) = t (t - 1) - 2
+// Lagrange basis on the nodes -1, 0, 1, 2 at t in [0,1)
 template <class T>
 __device__ __forceinline__ void lagrange4(T t, T w[4])
 {
-    const T tm1 = t - T(1), tm2 = t - T(2);
-    const T a = t * tm1, b = a - T(2);
-    w[0] = a * (tm2 * T(-1.0 / 6.0));
-    w[1] = b * (tm1 * T(0.5));
-    w[2] = b * (t * T(-0.5));
-    w[3] = a * (t * T(1.0 / 6.0) + T(1.0 / 6.0));
+    const T tm1 = t - T(1), tm2 = t - T(2), tp1 = t + T(1);
+    w[0] = -t * tm1 * tm2 * T(1.0 / 6.0);
+    w[1] = tp1 * tm1 * tm2 * T(0.5);
+    w[2] = -tp1 * t * tm2 * T(0.5);
+    w[3] = tp1 * t * tm1 * T(1.0 / 6.0);
 }
 
 // Stencil of one axis: node offsets (already multiplied by the axis stride)
@@ -355,35 +353,29 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
     __shared__ int red[4][6];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int u3 = tb % nt3, rr = tb / nt3, u2 = rr % nt2, u1 = rr / nt2;
-    const int i0 = u1 * T1, j0 = u2 * T2, k = u3 * kT3 + lane;
+    const int t3 = tb % nt3, rr = tb / nt3, t2 = rr % nt2, t1 = rr / nt2;
+    const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
     const long N = g.N;
-    // per point: fractional offsets f and first stencil nodes b (unwrapped)
-    float f1[PPT], f2[PPT], f3[PPT];
-    int b1[PPT], b2[PPT], b3[PPT];
+    float d1[PPT], d2[PPT], d3[PPT];
     int lo1 = 0x7fffffff, lo2 = 0x7fffffff, lo3 = 0x7fffffff;
     int hi1 = (int)0x80000000, hi2 = (int)0x80000000, hi3 = (int)0x80000000;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
-        f1[q] = f2[q] = f3[q] = 0.f;
-        b1[q] = b2[q] = b3[q] = 0;
+        d1[q] = d2[q] = d3[q] = 0.f;
         if (i < g.n1 && j < g.n2 && k < g.n3) {
             const long p = ((long)i * g.n2 + j) * g.n3 + k;
-            const float d1 = clamp_disp(disp[p]), d2 = clamp_disp(disp[N + p]), d3 = clamp_disp(disp[2 * N + p]);
-            const float l1 = floorf(d1), l2 = floorf(d2), l3 = floorf(d3);
-            f1[q] = d1 - l1;
-            f2[q] = d2 - l2;
-            f3[q] = d3 - l3;
-            b1[q] = i + (int)l1 - 1;
-            b2[q] = j + (int)l2 - 1;
-            b3[q] = k + (int)l3 - 1;
-            lo1 = min(lo1, b1[q]);
-            hi1 = max(hi1, b1[q]);
-            lo2 = min(lo2, b2[q]);
-            hi2 = max(hi2, b2[q]);
-            lo3 = min(lo3, b3[q]);
-            hi3 = max(hi3, b3[q]);
+            d1[q] = clamp_disp(disp[p]);
+            d2[q] = clamp_disp(disp[N + p]);
+            d3[q] = clamp_disp(disp[2 * N + p]);
+            const int b1 = i + (int)floorf(d1[q]) - 1, b2 = j + (int)floorf(d2[q]) - 1,
+                      b3 = k + (int)floorf(d3[q]) - 1;
+            lo1 = min(lo1, b1);
+            hi1 = max(hi1, b1);
+            lo2 = min(lo2, b2);
+            hi2 = max(hi2, b2);
+            lo3 = min(lo3, b3);
+            hi3 = max(hi3, b3);
         }
     }
 #pragma unroll
@@ -457,11 +449,13 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
             const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
             val[q][f] = 0.f;
             if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
+            const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
             float w1[4], w2[4], w3[4];
-            lagrange4<float>(f1[q], w1);
-            lagrange4<float>(f2[q], w2);
-            lagrange4<float>(f3[q], w3);
-            const int o1 = b1[q] - L1, o2 = b2[q] - L2, o3 = b3[q] - L3;  // >= 0 by the reduction
+            lagrange4<float>(d1[q] - f1, w1);
+            lagrange4<float>(d2[q] - f2, w2);
+            lagrange4<float>(d3[q] - f3, w3);
+            const int b1 = i + (int)f1 - 1, b2 = j + (int)f2 - 1, b3 = k + (int)f3 - 1;
+            const int o1 = b1 - L1, o2 = b2 - L2, o3 = b3 - L3;  // >= 0 by the reduction
             float acc = 0.f;
             if (o1 <= B1 - 4 && o2 <= B2 - 4 && o3 <= B3 - 4) {
 #pragma unroll
@@ -482,14 +476,13 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
             } else {  // stencil outside the staged box: global loads, wrapped per node
 #pragma unroll 1
                 for (int a = 0; a < 4; ++a) {
-                    const long ra = (long)wrapg(b1[q] + a, g.n1) * g.n2;
+                    const long ra = (long)wrapg(b1 + a, g.n1) * g.n2;
                     float acc2 = 0.f;
                     for (int b = 0; b < 4; ++b) {
-                        const float *row = src + (ra + wrapg(b2[q] + b, g.n2)) * g.n3;
-                        const int c = b3[q];
+                        const float *row = src + (ra + wrapg(b2 + b, g.n2)) * g.n3;
                         acc2 = accum<float>(b, w2,
-                                            row3<float>(row[wrapg(c, g.n3)], row[wrapg(c + 1, g.n3)],
-                                                        row[wrapg(c + 2, g.n3)], row[wrapg(c + 3, g.n3)], w3),
+                                            row3<float>(row[wrapg(b3, g.n3)], row[wrapg(b3 + 1, g.n3)],
+                                                        row[wrapg(b3 + 2, g.n3)], row[wrapg(b3 + 3, g.n3)], w3),
                                             acc2);
                     }
                     acc = accum<float>(a, w1, acc2, acc);

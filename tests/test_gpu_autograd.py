@@ -32,7 +32,9 @@ def test_autograd_matches_oracle_gradient(shape, nt):
     assert rel(to_np(mt), mref) < 1e-6
     # total dL/dv = beta A v - B(T(m(1) - m1)) = reduced gradient with K = I, plain sums
     g_ref = ref.gradient()
-    assert rel(to_np(vd.grad), g_ref) < 1e-5
+    eg = rel(to_np(vd.grad), g_ref)
+    say(f"  dL/dv rel {eg:.2e}")
+    assert eg < 1e-5
     # dL/dm0 = lam_0 of the adjoint sweep with final value m(1) - m1
     gm0_ref, _ = ref.transport_vjp(synth.f64(m0), mref - synth.f64(m1))
     assert rel(to_np(m0d.grad), gm0_ref) < 1e-5
