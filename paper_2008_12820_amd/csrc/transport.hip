@@ -201,42 +201,64 @@ __global__ __launch_bounds__(kPtThreads) void k_departure(const float *__restric
 }
 
 // b = dt * sum_j w_j lam_j G_j (trapezoid, w_0 = w_nt = 1/2); lam_nt is read
-// from lamN times scaleN, lam_0..lam_{nt-1} from lam.
-__global__ __launch_bounds__(kPtThreads) void k_body_force(const float *__restrict__ lam,
-                                                           const float *__restrict__ lamN, float scaleN,
-                                                           const float *__restrict__ G,
-                                                           float *__restrict__ b, Grid3 g, int nt,
-                                                           float dt)
+// from lamN times scaleN, lam_0..lam_{nt-1} from lam.  Four points per thread
+// (16-byte accesses); NTC > 0 fixes nt at compile time so that every load of
+// the sum is in flight at once.
+__device__ __forceinline__ float4 f4fma(float a, float4 x, float4 y)
 {
-    const int p = point_index();
-    if (p >= g.N) return;
-    const long N = g.N;
-    float acc[3] = {0.f, 0.f, 0.f};
+    return make_float4(a * x.x + y.x, a * x.y + y.y, a * x.z + y.z, a * x.w + y.w);
+}
+__device__ __forceinline__ float4 f4mul(float4 x, float4 y)
+{
+    return make_float4(x.x * y.x, x.y * y.y, x.z * y.z, x.w * y.w);
+}
+__device__ __forceinline__ float4 f4scl(float a, float4 x) { return make_float4(a * x.x, a * x.y, a * x.z, a * x.w); }
+__device__ __forceinline__ float4 f4add(float4 x, float4 y)
+{
+    return make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+}
+
+template <int NTC>
+__global__ __launch_bounds__(kPtThreads) void k_body_force(const float4 *__restrict__ lam,
+                                                           const float4 *__restrict__ lamN, float scaleN,
+                                                           const float4 *__restrict__ G, float4 *__restrict__ b,
+                                                           long N4, int nt_rt, float dt)
+{
+    const int nt = NTC > 0 ? NTC : nt_rt;
+    const long p = (long)xcd_block((int)blockIdx.x, (int)gridDim.x) * kPtThreads + threadIdx.x;
+    if (p >= N4) return;
+    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0, a2 = a0;
+#pragma unroll
     for (int j = 0; j <= nt; ++j) {
         const float w = (j == 0 || j == nt) ? 0.5f : 1.f;
-        const float l = (j == nt ? scaleN * lamN[p] : lam[(long)j * N + p]) * w;
-        const float *gj = G + (long)j * 3 * N;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] += l * gj[c * N + p];
+        const float4 l = j == nt ? f4scl(scaleN * w, lamN[p]) : f4scl(w, lam[(long)j * N4 + p]);
+        const float4 *gj = G + (long)j * 3 * N4;
+        a0 = f4add(a0, f4mul(l, gj[p]));
+        a1 = f4add(a1, f4mul(l, gj[N4 + p]));
+        a2 = f4add(a2, f4mul(l, gj[2 * N4 + p]));
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) b[c * N + p] = dt * acc[c];
+    b[p] = f4scl(dt, a0);
+    b[N4 + p] = f4scl(dt, a1);
+    b[2 * N4 + p] = f4scl(dt, a2);
 }
 
 // Incremental-state sources from the increment vt and its values vX at the
 // departure points: s_j = vX . I[G_j](X) + vt . G_{j+1}; m~_1 = -dt/2 s_0 and
 // s_1 .. s_{nt-1} are stored.  Four points per thread (16-byte accesses).
+template <int NTC>
 __global__ __launch_bounds__(kPtThreads) void k_inc_sources(const float4 *__restrict__ vt,
                                                             const float4 *__restrict__ vX,
                                                             const float4 *__restrict__ GX,
                                                             const float4 *__restrict__ G,
                                                             float4 *__restrict__ mt1, float4 *__restrict__ src,
-                                                            long N4, int nt, float hdt)
+                                                            long N4, int nt_rt, float hdt)
 {
+    const int nt = NTC > 0 ? NTC : nt_rt;
     const long p = (long)xcd_block((int)blockIdx.x, (int)gridDim.x) * kPtThreads + threadIdx.x;
     if (p >= N4) return;
     const float4 v0 = vt[p], v1 = vt[N4 + p], v2 = vt[2 * N4 + p];
     const float4 x0 = vX[p], x1 = vX[N4 + p], x2 = vX[2 * N4 + p];
+#pragma unroll
     for (int j = 0; j < nt; ++j) {
         const float4 *gx = GX + (long)j * 3 * N4;
         const float4 *g1 = G + (long)(j + 1) * 3 * N4;
@@ -643,9 +665,17 @@ void launch_incstate_init(lddmm_plan *P, const float *vt, float *mt1)
     float *vX = P->b;
     tiled(P, P->dX, EpiVec3{vt, vX, N}, K_INCSTATE_INIT);
     Scope s(P, K_INC_SOURCES);
-    hipLaunchKernelGGL(k_inc_sources, dim3((unsigned)((N4 + kPtThreads - 1) / kPtThreads)), dim3(kPtThreads), 0,
-                       P->stream, (const float4 *)vt, (const float4 *)vX, (const float4 *)P->GX,
-                       (const float4 *)P->G, (float4 *)mt1, (float4 *)P->src, N4, P->nt, 0.5f * (float)P->dt);
+    const dim3 grid((unsigned)((N4 + kPtThreads - 1) / kPtThreads));
+#define INC_SRC(NTC)                                                                                         \
+    hipLaunchKernelGGL((k_inc_sources<NTC>), grid, dim3(kPtThreads), 0, P->stream, (const float4 *)vt,       \
+                       (const float4 *)vX, (const float4 *)P->GX, (const float4 *)P->G, (float4 *)mt1,       \
+                       (float4 *)P->src, N4, P->nt, 0.5f * (float)P->dt)
+    switch (P->nt) {
+    case 4: INC_SRC(4); break;
+    case 8: INC_SRC(8); break;
+    default: INC_SRC(0); break;
+    }
+#undef INC_SRC
     check_hip(hipGetLastError(), "k_inc_sources");
 }
 
@@ -658,8 +688,17 @@ void launch_body_force(lddmm_plan *P, const float *lam, const float *lamN, float
                        const float *G, float *b)
 {
     Scope s(P, K_BODY_FORCE);
-    hipLaunchKernelGGL(k_body_force, blocks_of(P), dim3(kPtThreads), 0, P->stream, lam, lamN,
-                       scaleN, G, b, grid_of(P), P->nt, (float)P->dt);
+    const long N4 = P->N / 4;
+    const dim3 grid((unsigned)((N4 + kPtThreads - 1) / kPtThreads));
+#define BODY(NTC)                                                                                              \
+    hipLaunchKernelGGL((k_body_force<NTC>), grid, dim3(kPtThreads), 0, P->stream, (const float4 *)lam,          \
+                       (const float4 *)lamN, scaleN, (const float4 *)G, (float4 *)b, N4, P->nt, (float)P->dt)
+    switch (P->nt) {
+    case 4: BODY(4); break;
+    case 8: BODY(8); break;
+    default: BODY(0); break;
+    }
+#undef BODY
     check_hip(hipGetLastError(), "k_body_force");
 }
 
