@@ -146,6 +146,7 @@ static Layout make_layout(const lddmm_config *cfg)
     L.add(spectral_slots(cfg) * 2 * spec);  // 22 spec (slots sized for FP64)
     L.add(sizeof(double) * kRedBlocks);     // 23 red
     L.add(sizeof(double) * kNumScalars);    // 24 dscal
+    L.add(2 * tile_boxes_bytes(cfg->n));     // 25 stencil extents per gather tile (dX, dXa)
     return L;
 }
 
@@ -490,6 +491,7 @@ lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan
         P->slot_bytes = (long)sizeof(double2) * cfg->n[0] * cfg->n[1] * (cfg->n[2] / 2 + 1);
         P->red = (double *)(a + L.off[23]);
         P->dscal = (double *)(a + L.off[24]);
+        assign_tile_boxes(P, a + L.off[25]);
         check_hip(hipHostMalloc((void **)&P->hscal, sizeof(double) * kNumScalars, hipHostMallocDefault),
                   "hipHostMalloc");
         fft_init(P);

@@ -87,6 +87,8 @@ struct lddmm_plan {
     double *hscal = nullptr; // pinned host mirror
 
     int have_images = 0, have_velocity = 0, have_grad = 0, have_matvec = 0;
+    void *boxes[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // stencil extents per tile: [dX, dXa][2x4, 4x4]
+    int boxes_valid = 0;
     int gather_mode = -1;    // 0 direct, 1 box tiles 2x4x64, 2 box tiles 4x4x64, -1 heuristic
     int gather_tuned = 0;
     float gather_ms[1] = {0.f};
@@ -144,6 +146,9 @@ void unpack_standard(lddmm_plan *P, const float2 *srcp, int spec_field);
 
 // ---- transport.hip ----------------------------------------------------------
 void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa);
+size_t tile_boxes_bytes(const int n[3]);                // per displacement field
+void assign_tile_boxes(lddmm_plan *P, char *base);      // 2 * tile_boxes_bytes at base
+void launch_tile_boxes(lddmm_plan *P);
 void autotune_gather(lddmm_plan *P);
 void launch_interp(lddmm_plan *P, int nf, const float *fields, const float *disp, float *out,
                    int kid);

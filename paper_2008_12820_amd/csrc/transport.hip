@@ -365,33 +365,25 @@ struct EpiVec3 {  // three fields (stride N): out_c = I[src_c]
         dst[2 * N + p] = v[2];
     }
 };
-template <int T1, int T2, class Epi>
-__global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ disp, Epi epi, int nt2, int nt3)
+// Stencil extents of one tile: the smallest first node (L) and the largest
+// (H) along each axis over the tile's grid points, reduced over the
+// workgroup; L1 > H1 when no point of the tile is inside the grid.
+template <int T1, int T2>
+__device__ __forceinline__ void tile_extents(const Grid3 &g, const float *__restrict__ disp, int i0, int j0, int k,
+                                             int w, int lane, int (*red)[6], int L[3], int H[3])
 {
     using BC = BoxCfg<T1, T2>;
-    constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, CAP = BC::CAP, NF = Epi::NF;
-    constexpr int S1 = BR2 * kPad3;  // box stride along x1 (x2: kPad3)
-    extern __shared__ float box[];   // CAP floats
-    __shared__ int red[4][6];
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int t3 = tb % nt3, rr = tb / nt3, t2 = rr % nt2, t1 = rr / nt2;
-    const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
     const long N = g.N;
-    float d1[PPT], d2[PPT], d3[PPT];
     int lo1 = 0x7fffffff, lo2 = 0x7fffffff, lo3 = 0x7fffffff;
     int hi1 = (int)0x80000000, hi2 = (int)0x80000000, hi3 = (int)0x80000000;
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
+    for (int q = 0; q < BC::PPT; ++q) {
         const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
-        d1[q] = d2[q] = d3[q] = 0.f;
         if (i < g.n1 && j < g.n2 && k < g.n3) {
             const long p = ((long)i * g.n2 + j) * g.n3 + k;
-            d1[q] = clamp_disp(disp[p]);
-            d2[q] = clamp_disp(disp[N + p]);
-            d3[q] = clamp_disp(disp[2 * N + p]);
-            const int b1 = i + (int)floorf(d1[q]) - 1, b2 = j + (int)floorf(d2[q]) - 1,
-                      b3 = k + (int)floorf(d3[q]) - 1;
+            const int b1 = i + (int)floorf(clamp_disp(disp[p])) - 1;
+            const int b2 = j + (int)floorf(clamp_disp(disp[N + p])) - 1;
+            const int b3 = k + (int)floorf(clamp_disp(disp[2 * N + p])) - 1;
             lo1 = min(lo1, b1);
             hi1 = max(hi1, b1);
             lo2 = min(lo2, b2);
@@ -418,13 +410,83 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
         red[w][5] = hi3;
     }
     __syncthreads();
-    const int L1 = min(min(red[0][0], red[1][0]), min(red[2][0], red[3][0]));
-    const int L2 = min(min(red[0][1], red[1][1]), min(red[2][1], red[3][1]));
-    const int L3 = min(min(red[0][2], red[1][2]), min(red[2][2], red[3][2]));
-    const int H1 = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3]));
-    const int H2 = max(max(red[0][4], red[1][4]), max(red[2][4], red[3][4]));
-    const int H3 = max(max(red[0][5], red[1][5]), max(red[2][5], red[3][5]));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        L[a] = min(min(red[0][a], red[1][a]), min(red[2][a], red[3][a]));
+        H[a] = max(max(red[0][a + 3], red[1][a + 3]), max(red[2][a + 3], red[3][a + 3]));
+    }
+}
+
+// Per-tile stencil extents of a displacement field, computed once per
+// velocity: the matvec's gathers read them instead of reducing again, so a
+// workgroup starts staging its box at once.  Entry t: L[3], H[3] of tile t
+// (in the numbering of the gather kernel, before the XCD renumbering).
+struct TileBox {
+    int L[3], H[3], pad[2];
+};
+
+template <int T1, int T2>
+__global__ __launch_bounds__(256) void k_tile_boxes(Grid3 g, const float *__restrict__ disp, TileBox *__restrict__ out,
+                                                    int nt2, int nt3)
+{
+    __shared__ int red[4][6];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int tb = (int)blockIdx.x;
+    const int u3 = tb % nt3, rr = tb / nt3, u2 = rr % nt2, u1 = rr / nt2;
+    int L[3], H[3];
+    tile_extents<T1, T2>(g, disp, u1 * T1, u2 * T2, u3 * kT3 + lane, w, lane, red, L, H);
+    if (tid == 0) {
+        TileBox b;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            b.L[a] = L[a];
+            b.H[a] = H[a];
+        }
+        b.pad[0] = b.pad[1] = 0;
+        out[tb] = b;
+    }
+}
+
+// boxes != nullptr: the extents come from k_tile_boxes for this displacement field
+template <int T1, int T2, class Epi>
+__global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ disp, Epi epi, int nt2, int nt3,
+                                             const TileBox *__restrict__ boxes)
+{
+    using BC = BoxCfg<T1, T2>;
+    constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, CAP = BC::CAP, NF = Epi::NF;
+    constexpr int S1 = BR2 * kPad3;  // box stride along x1 (x2: kPad3)
+    extern __shared__ float box[];   // CAP floats
+    __shared__ int red[4][6];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int t3 = tb % nt3, rr = tb / nt3, t2 = rr % nt2, t1 = rr / nt2;
+    const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
+    const long N = g.N;
+    int Lx[3], Hx[3];
+    if (boxes) {
+        const TileBox tbx = boxes[tb];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Lx[a] = tbx.L[a];
+            Hx[a] = tbx.H[a];
+        }
+    } else {
+        tile_extents<T1, T2>(g, disp, i0, j0, k, w, lane, red, Lx, Hx);
+    }
+    const int L1 = Lx[0], L2 = Lx[1], L3 = Lx[2], H1 = Hx[0], H2 = Hx[1], H3 = Hx[2];
     if (L1 > H1) return;  // no point of the tile is inside the grid (uniform)
+    float d1[PPT], d2[PPT], d3[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+        d1[q] = d2[q] = d3[q] = 0.f;
+        if (i < g.n1 && j < g.n2 && k < g.n3) {
+            const long p = ((long)i * g.n2 + j) * g.n3 + k;
+            d1[q] = clamp_disp(disp[p]);
+            d2[q] = clamp_disp(disp[N + p]);
+            d3[q] = clamp_disp(disp[2 * N + p]);
+        }
+    }
     // staged extents: the stencil box, cut to the capacity (64-bit: a clamped
     // displacement spans up to 2^21 nodes)
     const int B1 = (int)min((long)H1 + 4 - L1, (long)BR1);
@@ -564,6 +626,7 @@ void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa)
     hipLaunchKernelGGL(k_departure, blocks_of(P), dim3(kPtThreads), 0, P->stream, v, dX, dXa,
                        grid_of(P), P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2]);
     check_hip(hipGetLastError(), "k_departure");
+    if (dX == P->dX && dXa == P->dXa) launch_tile_boxes(P);
 }
 
 // gather strategy: P->gather_mode 0 direct, 1 box tiles 2x4x64, 2 box tiles
@@ -577,18 +640,76 @@ static int gather_mode(const lddmm_plan *P)
     return tiles >= 4096 ? 2 : 1;
 }
 
+template <int T1, int T2>
+static unsigned tiles_of(const lddmm_plan *P, int &nt2, int &nt3)
+{
+    const int n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
+    const int nt1 = (n1 + T1 - 1) / T1;
+    nt2 = (n2 + T2 - 1) / T2;
+    nt3 = (n3 + kT3 - 1) / kT3;
+    return (unsigned)((long)nt1 * nt2 * nt3);
+}
+
+// the extents table of a displacement field for tiles T1 x T2, when the plan
+// holds one for that field (its own departure points)
+template <int T1, int T2>
+static const TileBox *boxes_for(const lddmm_plan *P, const float *disp)
+{
+    const int shape = (T1 == 4 && T2 == 4) ? 1 : 0;
+    if (!P->boxes_valid) return nullptr;
+    if (disp == P->dX) return (const TileBox *)P->boxes[0][shape];
+    if (disp == P->dXa) return (const TileBox *)P->boxes[1][shape];
+    return nullptr;
+}
+
 template <int T1, int T2, class Epi>
 static void launch_box(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
 {
-    const int n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
-    const int nt1 = (n1 + T1 - 1) / T1, nt2 = (n2 + T2 - 1) / T2, nt3 = (n3 + kT3 - 1) / kT3;
+    int nt2, nt3;
+    const unsigned ntiles = tiles_of<T1, T2>(P, nt2, nt3);
     const size_t lds = sizeof(float) * BoxCfg<T1, T2>::CAP;
     static_assert(sizeof(float) * BoxCfg<4, 4>::CAP <= 64 * 1024, "box exceeds the default LDS limit");
-    const unsigned ntiles = (unsigned)((long)nt1 * nt2 * nt3);
     Scope s(P, kid);
     hipLaunchKernelGGL((k_box<T1, T2, Epi>), dim3(ntiles), dim3(256), lds, P->stream, grid_of(P), disp, epi, nt2,
-                       nt3);
+                       nt3, boxes_for<T1, T2>(P, disp));
     check_hip(hipGetLastError(), "k_box");
+}
+
+// extents tables of the plan's two displacement fields for both tile shapes
+size_t tile_boxes_bytes(const int n[3])
+{
+    auto cnt = [&](int T1, int T2) {
+        return (size_t)((n[0] + T1 - 1) / T1) * ((n[1] + T2 - 1) / T2) * ((n[2] + kT3 - 1) / kT3);
+    };
+    return sizeof(TileBox) * (cnt(2, 4) + cnt(4, 4));
+}
+
+void assign_tile_boxes(lddmm_plan *P, char *base)
+{
+    int nt2, nt3;
+    const size_t n24 = tiles_of<2, 4>(P, nt2, nt3), per = tile_boxes_bytes(P->cfg.n);
+    for (int f = 0; f < 2; ++f) {
+        P->boxes[f][0] = base + f * per;
+        P->boxes[f][1] = base + f * per + sizeof(TileBox) * n24;
+    }
+    P->boxes_valid = 0;
+}
+
+void launch_tile_boxes(lddmm_plan *P)
+{
+    if (!P->boxes[0][0]) return;
+    int nt2, nt3;
+    for (int f = 0; f < 2; ++f) {
+        const float *disp = f == 0 ? P->dX : P->dXa;
+        unsigned nb = tiles_of<2, 4>(P, nt2, nt3);
+        hipLaunchKernelGGL((k_tile_boxes<2, 4>), dim3(nb), dim3(256), 0, P->stream, grid_of(P), disp,
+                           (TileBox *)P->boxes[f][0], nt2, nt3);
+        nb = tiles_of<4, 4>(P, nt2, nt3);
+        hipLaunchKernelGGL((k_tile_boxes<4, 4>), dim3(nb), dim3(256), 0, P->stream, grid_of(P), disp,
+                           (TileBox *)P->boxes[f][1], nt2, nt3);
+    }
+    check_hip(hipGetLastError(), "k_tile_boxes");
+    P->boxes_valid = 1;
 }
 
 template <class Epi>
