@@ -881,6 +881,7 @@ lddmm_status lddmm_tuning(lddmm_plan *P, char *buf, size_t len)
         need(P, "plan");
         need(buf, "buf");
         const std::string r = tuning_report(P) + " gather_mode=" + std::to_string(P->gather_mode) +
+                              "/" + std::to_string(P->gather_mode3) +
                               (P->gather_tuned ? " (tuned)" : "");
         if (len == 0) fail(LDDMM_EINVAL, "len is 0");
         const size_t n = std::min(len - 1, r.size());
@@ -895,6 +896,7 @@ lddmm_status lddmm_set_gather_mode(lddmm_plan *P, int32_t mode)
         need(P, "plan");
         if (mode < -1 || mode > 2) fail(LDDMM_EINVAL, "mode must be -1, 0, 1 or 2");
         P->gather_mode = mode;
+        P->gather_mode3 = -1;
     });
 }
 

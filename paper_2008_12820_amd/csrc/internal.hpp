@@ -90,6 +90,7 @@ struct lddmm_plan {
     void *boxes[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // stencil extents per tile: [dX, dXa][2x4, 4x4]
     int boxes_valid = 0;
     int gather_mode = -1;    // 0 direct, 1 box tiles 2x4x64, 2 box tiles 4x4x64, -1 heuristic
+    int gather_mode3 = -1;   // the same for three-field gathers; -1: follow gather_mode
     int gather_tuned = 0;
     float gather_ms[1] = {0.f};
     double g0norm = 0.0;

@@ -715,7 +715,8 @@ void launch_tile_boxes(lddmm_plan *P)
 template <class Epi>
 static void tiled(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
 {
-    switch (gather_mode(P)) {
+    const int mode = (Epi::NF > 1 && P->gather_mode3 >= 0) ? P->gather_mode3 : gather_mode(P);
+    switch (mode) {
     case 0: {
         Scope s(P, kid);
         hipLaunchKernelGGL((k_direct<Epi>), blocks_of(P), dim3(kPtThreads), 0, P->stream, grid_of(P), disp, epi);
@@ -756,8 +757,34 @@ void autotune_gather(lddmm_plan *P)
         }
     }
     P->gather_mode = keep >= 0 ? keep : bm;
-    P->gather_tuned = 1;
     P->gather_ms[0] = best;
+    // three-field gathers (more registers per point) are tuned on their own,
+    // on the velocity into the body-force scratch buffer
+    if (keep < 0 && P->v && P->b) {
+        float best3 = 1e30f;
+        int bm3 = P->gather_mode;
+        for (int m = 0; m < 3; ++m) {
+            P->gather_mode3 = m;
+            hipEvent_t a, b;
+            check_hip(hipEventCreate(&a), "hipEventCreate");
+            check_hip(hipEventCreate(&b), "hipEventCreate");
+            tiled(P, P->dX, EpiVec3{P->v, P->b, P->N}, K_INCSTATE_INIT);
+            check_hip(hipEventRecord(a, P->stream), "hipEventRecord");
+            for (int r = 0; r < 3; ++r) tiled(P, P->dX, EpiVec3{P->v, P->b, P->N}, K_INCSTATE_INIT);
+            check_hip(hipEventRecord(b, P->stream), "hipEventRecord");
+            check_hip(hipEventSynchronize(b), "hipEventSynchronize");
+            float ms = 0.f;
+            check_hip(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            if (ms < best3) {
+                best3 = ms;
+                bm3 = m;
+            }
+        }
+        P->gather_mode3 = bm3;
+    }
+    P->gather_tuned = 1;
 }
 
 void launch_interp(lddmm_plan *P, int nf, const float *fields, const float *disp, float *out, int kid)
