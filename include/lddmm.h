@@ -250,10 +250,13 @@ lddmm_status lddmm_autotune(lddmm_plan *plan);
 /* Override the gather strategy of the interpolation kernels: 0 direct
  * (one thread per point, stencil loads through L1/L2), 1 and 2 LDS-staged
  * boxes for tiles of 2x4x64 and 4x4x64 points (points whose stencil leaves
- * the box load from global memory), -1 the default heuristic.  Every
- * strategy computes the same tensor-product sum in the same order.
- * lddmm_autotune picks among 0..2 by timing once the plan has a velocity.
- * EINVAL for a mode outside -1..2. */
+ * the box load from global memory), 3 and 4 the same tiles walked by a
+ * resident grid of workgroups that stage the next tile's box while they
+ * interpolate the current one (one-field gathers at the plan's own
+ * departure points; other gathers take 1 or 2), -1 the default heuristic.
+ * Every strategy computes the same tensor-product sum in the same order.
+ * lddmm_autotune picks among 0..4 by timing once the plan has a velocity.
+ * EINVAL for a mode outside -1..4. */
 lddmm_status lddmm_set_gather_mode(lddmm_plan *plan, int32_t mode);
 /* NUL-terminated report of the tile shapes in use (len bytes at most). */
 lddmm_status lddmm_tuning(lddmm_plan *plan, char *buf, size_t len);

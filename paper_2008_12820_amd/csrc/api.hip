@@ -894,7 +894,7 @@ lddmm_status lddmm_set_gather_mode(lddmm_plan *P, int32_t mode)
 {
     return guard([&] {
         need(P, "plan");
-        if (mode < -1 || mode > 2) fail(LDDMM_EINVAL, "mode must be -1, 0, 1 or 2");
+        if (mode < -1 || mode > 4) fail(LDDMM_EINVAL, "mode must be -1 .. 4");
         P->gather_mode = mode;
         P->gather_mode3 = -1;
     });

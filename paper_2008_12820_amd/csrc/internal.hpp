@@ -89,9 +89,10 @@ struct lddmm_plan {
     int have_images = 0, have_velocity = 0, have_grad = 0, have_matvec = 0;
     void *boxes[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // stencil extents per tile: [dX, dXa][2x4, 4x4]
     int boxes_valid = 0;
-    int gather_mode = -1;    // 0 direct, 1 box tiles 2x4x64, 2 box tiles 4x4x64, -1 heuristic
+    int gather_mode = -1;    // 0 direct, 1/2 box tiles 2x4x64/4x4x64, 3/4 the same pipelined, -1 heuristic
     int gather_mode3 = -1;   // the same for three-field gathers; -1: follow gather_mode
     int gather_tuned = 0;
+    int pipe_grid[2] = {0, 0};  // workgroups of the pipelined gathers [2x4, 4x4] (0: not yet sized)
     float gather_ms[1] = {0.f};
     double g0norm = 0.0;
     lddmm::PlanTiming timing;

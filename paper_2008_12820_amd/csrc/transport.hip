@@ -582,6 +582,162 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
     }
 }
 
+// Persistent, software-pipelined box gathers (one field, extents table
+// required): a fixed grid of workgroups walks the tiles, each XCD a
+// contiguous run of them; while a workgroup interpolates tile k from one LDS
+// box, the global loads of tile k+1's box are already in flight into
+// registers and land in the other box, so the staging latency hides behind
+// the arithmetic.  Same stencil sums, bitwise, as k_box.
+template <int T1, int T2, class Epi>
+__global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restrict__ disp, Epi epi, int nt2,
+                                                  int nt3, const TileBox *__restrict__ boxes, int ntiles)
+{
+    static_assert(Epi::NF == 1, "one field");
+    using BC = BoxCfg<T1, T2>;
+    constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, CAP = BC::CAP;
+    constexpr int S1 = BR2 * kPad3;
+    constexpr int RPW = (BR1 * BR2 + 3) / 4;
+    extern __shared__ float boxes2[];  // 2 x CAP floats
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const long N = g.N;
+    const float *__restrict__ src = epi.field(0);
+    // tiles of this workgroup: XCD x = blockIdx % 8 owns tiles [x T / 8, (x+1) T / 8)
+    const int G = (int)gridDim.x, per = (ntiles + 7) / 8;
+    const int xcd = (int)blockIdx.x & 7, slot = (int)blockIdx.x >> 3, gx = (G + 7 - xcd) / 8;
+    const int tbeg = xcd * per, tend = min(ntiles, tbeg + per);
+    auto tile_at = [&](int kk) { return tbeg + slot + kk * gx; };
+    float r0[RPW], r1[RPW];
+    // Issue the staging loads of tile t (extents from the table) into r0/r1.
+    // Every load is issued, from a valid wrapped address (rows outside the
+    // box re-read the box's first row, columns past it the lane's first
+    // column): straight-line code lets the compiler wait for this tile's
+    // displacements without waiting for these loads.
+    auto fetch = [&](int t) {
+        const TileBox tbx = boxes[t];
+        const bool live = tbx.L[0] <= tbx.H[0];
+        const int L1 = live ? tbx.L[0] : 0, L2 = live ? tbx.L[1] : 0, L3 = live ? tbx.L[2] : 0;
+        const int B1 = live ? (int)min((long)tbx.H[0] + 4 - L1, (long)BR1) : 0;
+        const int B2 = live ? (int)min((long)tbx.H[1] + 4 - L2, (long)BR2) : 0;
+        const int B3 = live ? (int)min((long)tbx.H[2] + 4 - L3, (long)kPad3) : 0;
+        const unsigned k0 = (unsigned)wrapg(L3 + lane, g.n3);
+        const unsigned k1 = lane + 64 < B3 ? (unsigned)wrapg(L3 + lane + 64, g.n3) : k0;
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int r = wu + 4 * q, a0 = r / BR2, b0 = r - a0 * BR2;
+            const bool in = a0 < B1 && b0 < B2;
+            const int a = in ? a0 : 0, b = in ? b0 : 0;
+            const float *grow = src + ((long)wrapg(L1 + a, g.n1) * g.n2 + wrapg(L2 + b, g.n2)) * g.n3;
+            r0[q] = grow[k0];
+            r1[q] = grow[k1];
+        }
+    };
+    auto deposit = [&](float *bx) {
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int r = wu + 4 * q;
+            if (r < BR1 * BR2) {
+                float *brow = bx + r * kPad3;
+                brow[lane] = r0[q];
+                if (lane + 64 < kPad3) brow[lane + 64] = r1[q];
+            }
+        }
+    };
+    if (tile_at(0) >= tend) return;  // uniform over the workgroup
+    fetch(tile_at(0));
+    deposit(boxes2);
+    __syncthreads();
+    for (int kk = 0;; ++kk) {
+        const int t = tile_at(kk), tn = tile_at(kk + 1);
+        const bool more = tn < tend;
+        const int t3 = t % nt3, rr = t / nt3, t2 = rr % nt2, t1 = rr / nt2;
+        const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
+        // this tile's displacements first: the wait for them must not wait
+        // for the next tile's staging loads, issued after them
+        // (straight-line loads: points outside the grid read point 0 and are
+        // skipped below)
+        float d1[PPT], d2[PPT], d3[PPT];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+            const long p = (i < g.n1 && j < g.n2 && k < g.n3) ? ((long)i * g.n2 + j) * g.n3 + k : 0;
+            d1[q] = disp[p];
+            d2[q] = disp[N + p];
+            d3[q] = disp[2 * N + p];
+        }
+        const TileBox tbx = boxes[t];
+        fetch(more ? tn : t);  // the last tile re-reads its own box, unused
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            d1[q] = clamp_disp(d1[q]);
+            d2[q] = clamp_disp(d2[q]);
+            d3[q] = clamp_disp(d3[q]);
+        }
+        const float *cur = boxes2 + (kk & 1) * CAP;
+        const int L1 = tbx.L[0], L2 = tbx.L[1], L3 = tbx.L[2];
+        const int B1 = (int)min((long)tbx.H[0] + 4 - L1, (long)BR1);
+        const int B2 = (int)min((long)tbx.H[1] + 4 - L2, (long)BR2);
+        const int B3 = (int)min((long)tbx.H[2] + 4 - L3, (long)kPad3);
+        float val[PPT];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+            val[q] = 0.f;
+            if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
+            const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
+            float w1[4], w2[4], w3[4];
+            lagrange4<float>(d1[q] - f1, w1);
+            lagrange4<float>(d2[q] - f2, w2);
+            lagrange4<float>(d3[q] - f3, w3);
+            const int b1 = i + (int)f1 - 1, b2 = j + (int)f2 - 1, b3 = k + (int)f3 - 1;
+            const int o1 = b1 - L1, o2 = b2 - L2, o3 = b3 - L3;
+            float acc = 0.f;
+            if (o1 <= B1 - 4 && o2 <= B2 - 4 && o3 <= B3 - 4) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    int pa = (o1 + a) * S1 + o2 * kPad3 + o3;
+                    asm("" : "+v"(pa));
+                    const float *pl = cur + pa;
+                    float acc2 = 0.f;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const float *row = pl + b * kPad3;
+                        acc2 = accum<float>(b, w2, row3<float>(row[0], row[1], row[2], row[3], w3), acc2);
+                    }
+                    acc = accum<float>(a, w1, acc2, acc);
+                }
+            } else {
+#pragma unroll 1
+                for (int a = 0; a < 4; ++a) {
+                    const long ra = (long)wrapg(b1 + a, g.n1) * g.n2;
+                    float acc2 = 0.f;
+                    for (int b = 0; b < 4; ++b) {
+                        const float *row = src + (ra + wrapg(b2 + b, g.n2)) * g.n3;
+                        acc2 = accum<float>(b, w2,
+                                            row3<float>(row[wrapg(b3, g.n3)], row[wrapg(b3 + 1, g.n3)],
+                                                        row[wrapg(b3 + 2, g.n3)], row[wrapg(b3 + 3, g.n3)], w3),
+                                            acc2);
+                    }
+                    acc = accum<float>(a, w1, acc2, acc);
+                }
+            }
+            val[q] = acc;
+        }
+        // the next box lands in the other buffer, last read two tiles ago
+        if (more) deposit(boxes2 + ((kk + 1) & 1) * CAP);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+            if (i < g.n1 && j < g.n2 && k < g.n3) {
+                float v[1] = {val[q]};
+                epi.finish(((long)i * g.n2 + j) * g.n3 + k, v);
+            }
+        }
+        if (!more) break;  // uniform
+        __syncthreads();
+    }
+}
+
 // direct gathers, one thread per point, stencil loads from L1/L2
 template <class Epi>
 __global__ __launch_bounds__(kPtThreads) void k_direct(Grid3 g, const float *__restrict__ disp, Epi epi)
@@ -630,8 +786,10 @@ void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa)
 }
 
 // gather strategy: P->gather_mode 0 direct, 1 box tiles 2x4x64, 2 box tiles
-// 4x4x64; -1 before tuning: 4x4 tiles when they leave enough workgroups to
-// fill the chip, else 2x4
+// 4x4x64, 3 and 4 the same tiles walked by persistent pipelined workgroups
+// (one-field gathers at the plan's own departure points; others take 1 or
+// 2); -1 before tuning: 4x4 tiles when they leave enough workgroups to fill
+// the chip, else 2x4
 static int gather_mode(const lddmm_plan *P)
 {
     if (P->gather_mode >= 0) return P->gather_mode;
@@ -673,6 +831,50 @@ static void launch_box(lddmm_plan *P, const float *disp, const Epi &epi, int kid
     hipLaunchKernelGGL((k_box<T1, T2, Epi>), dim3(ntiles), dim3(256), lds, P->stream, grid_of(P), disp, epi, nt2,
                        nt3, boxes_for<T1, T2>(P, disp));
     check_hip(hipGetLastError(), "k_box");
+}
+
+// Pipelined gathers: as many workgroups as stay resident on the device at
+// once (a multiple of the 8 XCDs), at most one per tile; the plain box
+// kernel where no extents table exists.
+template <int T1, int T2, class Epi>
+static void launch_box_pipe1(lddmm_plan *P, const float *disp, const Epi &epi, int kid);
+
+template <int T1, int T2, class Epi>
+static void launch_box_pipe(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
+{
+    if constexpr (Epi::NF != 1) {
+        launch_box<T1, T2>(P, disp, epi, kid);
+    } else {
+        launch_box_pipe1<T1, T2>(P, disp, epi, kid);
+    }
+}
+
+template <int T1, int T2, class Epi>
+static void launch_box_pipe1(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
+{
+    const TileBox *bx = boxes_for<T1, T2>(P, disp);
+    if (!bx) {
+        launch_box<T1, T2>(P, disp, epi, kid);
+        return;
+    }
+    int nt2, nt3;
+    const unsigned ntiles = tiles_of<T1, T2>(P, nt2, nt3);
+    const size_t lds = 2 * sizeof(float) * BoxCfg<T1, T2>::CAP;
+    static_assert(2 * sizeof(float) * BoxCfg<4, 4>::CAP <= 64 * 1024, "boxes exceed the default LDS limit");
+    int &grid = P->pipe_grid[(T1 == 4 && T2 == 4) ? 1 : 0];
+    if (grid == 0) {
+        int per_cu = 0, cus = 0;
+        check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_box_pipe<T1, T2, EpiAdj>, 256, lds),
+                  "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device),
+                  "hipDeviceGetAttribute");
+        grid = std::max(8, (std::max(per_cu, 1) * cus) / 8 * 8);
+    }
+    const unsigned nb = std::min((unsigned)grid, ntiles);
+    Scope s(P, kid);
+    hipLaunchKernelGGL((k_box_pipe<T1, T2, Epi>), dim3(nb), dim3(256), lds, P->stream, grid_of(P), disp, epi, nt2,
+                       nt3, bx, (int)ntiles);
+    check_hip(hipGetLastError(), "k_box_pipe");
 }
 
 // extents tables of the plan's two displacement fields for both tile shapes
@@ -724,12 +926,14 @@ static void tiled(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
         break;
     }
     case 1: launch_box<2, 4>(P, disp, epi, kid); break;
-    default: launch_box<4, 4>(P, disp, epi, kid); break;
+    case 2: launch_box<4, 4>(P, disp, epi, kid); break;
+    case 3: launch_box_pipe<2, 4>(P, disp, epi, kid); break;
+    default: launch_box_pipe<4, 4>(P, disp, epi, kid); break;
     }
 }
 
-// time the three gather strategies on the plan's adjoint displacement field
-// (one adjoint step into scratch) and keep the fastest
+// time the gather strategies on the plan's adjoint displacement field (one
+// adjoint step into scratch) and keep the fastest
 void autotune_gather(lddmm_plan *P)
 {
     const int keep = P->gather_mode;
@@ -737,7 +941,7 @@ void autotune_gather(lddmm_plan *P)
     int bm = 2;
     const float *src = P->lam;
     float *dst = P->lam + P->N;
-    for (int m = 0; m < 3; ++m) {
+    for (int m = 0; m < 5; ++m) {
         P->gather_mode = m;
         hipEvent_t a, b;
         check_hip(hipEventCreate(&a), "hipEventCreate");

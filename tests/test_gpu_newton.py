@@ -144,9 +144,10 @@ def test_negative_curvature_is_reported():
 
 @pytest.mark.parametrize("shape", [(32, 32, 32), (40, 36, 96)])
 def test_gather_strategies_agree(shape):
-    """Direct and LDS-staged box gathers (both tile shapes) form the stencil
-    sum with the same fused multiply-adds in the same order: the matvec is
-    bitwise the same for every strategy and matches the oracle."""
+    """Direct, LDS-staged box gathers (both tile shapes) and their pipelined
+    persistent forms compute the stencil sum with the same fused multiply-adds
+    in the same order: the matvec is bitwise the same for every strategy and
+    matches the oracle."""
     say(f"gather strategies {shape}")
     nt = 3
     m0, m1, vtrue, v, ref = problem(shape, nt, 2, 1e-3, disp=3.0)
@@ -154,9 +155,35 @@ def test_gather_strategies_agree(shape):
     vt = incremental(shape, 1300)
     ref_hv = ref.matvec(synth.f64(vt))
     outs = []
-    for mode in (0, 1, 2):
+    for mode in (0, 1, 2, 3, 4):
         P.set_gather_mode(mode)
         P.set_velocity(to_dev(v))
         outs.append(to_np(P.hessian_matvec(to_dev(vt))))
         assert rel(outs[-1], ref_hv) < 1e-5, mode
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    for got in outs[1:]:
+        assert np.array_equal(got, outs[0])
+
+
+def test_pipelined_gathers_walk_many_tiles():
+    """A grid with more tiles than resident workgroups (2250 tiles of 2x4x64,
+    1150 of 4x4x64, ragged along every axis and unequal over the eight
+    per-XCD ranges): every workgroup of the pipelined gathers walks several
+    tiles through its two LDS boxes.  Gradient and matvec are bitwise those of
+    the one-tile-per-workgroup box gathers."""
+    shape, nt = (90, 100, 120), 3
+    say(f"pipelined gathers {shape}")
+    m0 = synth.f32(synth.blob_image(shape, 40, 2100))
+    m1 = synth.f32(synth.blob_image(shape, 40, 2101))
+    v = synth.f32(synth.bandlimited_vector(shape, 4, 2102, max_disp=4.0))
+    P = _plan(shape, nt, 2, 1e-3, True, m0, m1, v)
+    vt = incremental(shape, 1301)
+    res = {}
+    for mode in (1, 2, 3, 4):
+        P.set_gather_mode(mode)
+        P.set_velocity(to_dev(v))
+        g, _ = P.gradient()
+        res[mode] = (to_np(g), to_np(P.hessian_matvec(to_dev(vt))))
+    for a, b in ((1, 3), (2, 4), (1, 2)):
+        assert np.array_equal(res[a][0], res[b][0]), (a, b)
+        assert np.array_equal(res[a][1], res[b][1]), (a, b)
+    assert np.isfinite(res[3][1]).all() and np.abs(res[3][1]).max() > 0
