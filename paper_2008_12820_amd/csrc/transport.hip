@@ -309,11 +309,12 @@ __device__ __forceinline__ int wrapg(int x, int n)
     return x < 0 ? x + n : x;
 }
 
+// displacements clamped to +-2^20 voxels (NaN to the lower bound), so that
+// every index derived from them stays a finite int
 __device__ __forceinline__ float clamp_disp(float d)
 {
     const float lim = 1048576.f;
-    d = d > lim ? lim : d;
-    return d >= -lim ? d : -lim;
+    return fminf(fmaxf(d, -lim), lim);
 }
 
 // epilogues: which fields are gathered and what is written per point
@@ -430,7 +431,10 @@ __global__ __launch_bounds__(256) void k_tile_boxes(Grid3 g, const float *__rest
                                                     int nt2, int nt3)
 {
     __shared__ int red[4][6];
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the wavefront index, wave-uniform: the compiler keeps what derives from
+    // it (the rows of a point, their bounds and base addresses) in scalars
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tb = (int)blockIdx.x;
     const int u3 = tb % nt3, rr = tb / nt3, u2 = rr % nt2, u1 = rr / nt2;
     int L[3], H[3];
@@ -457,7 +461,10 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
     constexpr int S1 = BR2 * kPad3;  // box stride along x1 (x2: kPad3)
     extern __shared__ float box[];   // CAP floats
     __shared__ int red[4][6];
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the wavefront index, wave-uniform: the compiler keeps what derives from
+    // it (the rows of a point, their bounds and base addresses) in scalars
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int t3 = tb % nt3, rr = tb / nt3, t2 = rr % nt2, t1 = rr / nt2;
     const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
@@ -498,7 +505,7 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
     // The x3 wrap of a lane's two columns is the same for every row.  Fields
     // go through the one box in turn.
     constexpr int RPW = (BR1 * BR2 + 3) / 4;  // rows per wavefront
-    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const int wu = w;
     const int c1 = lane + 64;
     const bool has0 = lane < B3, has1 = c1 < B3;
     const unsigned k0 = (unsigned)wrapg(L3 + lane, g.n3), k1 = (unsigned)wrapg(L3 + c1, g.n3);
@@ -546,7 +553,7 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
                 for (int a = 0; a < 4; ++a) {
                     // one base address per x1 plane: the row reads of the
                     // plane then fit the LDS instruction's offset field
-                    int pa = (o1 + a) * S1 + o2 * kPad3 + o3;
+                    int pa = (int)(__umul24((unsigned)(o1 + a), S1) + __umul24((unsigned)o2, kPad3)) + o3;  // 24-bit: full rate
                     asm("" : "+v"(pa));
                     const float *pl = box + pa;
                     float acc2 = 0.f;
@@ -598,8 +605,11 @@ __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restri
     constexpr int S1 = BR2 * kPad3;
     constexpr int RPW = (BR1 * BR2 + 3) / 4;
     extern __shared__ float boxes2[];  // 2 x CAP floats
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the wavefront index, wave-uniform: the compiler keeps what derives from
+    // it (the rows of a point, their bounds and base addresses) in scalars
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wu = w;
     const long N = g.N;
     const float *__restrict__ src = epi.field(0);
     // tiles of this workgroup: XCD x = blockIdx % 8 owns tiles [x T / 8, (x+1) T / 8)
@@ -695,7 +705,7 @@ __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restri
             if (o1 <= B1 - 4 && o2 <= B2 - 4 && o3 <= B3 - 4) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
-                    int pa = (o1 + a) * S1 + o2 * kPad3 + o3;
+                    int pa = (int)(__umul24((unsigned)(o1 + a), S1) + __umul24((unsigned)o2, kPad3)) + o3;  // 24-bit: full rate
                     asm("" : "+v"(pa));
                     const float *pl = cur + pa;
                     float acc2 = 0.f;
