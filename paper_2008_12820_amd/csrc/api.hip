@@ -27,7 +27,7 @@ const char *kernel_name(int id)
     static const char *names[K_NUM_KERNELS] = {
         "r2c_x3", "fft_cols", "x1_symbol", "c2r_x3", "departure", "state_step", "gather_vec",
         "adj_coef", "adj_step", "incstate_init", "incstate_step", "body_force", "dot", "vecop",
-        "pack", "inc_sources"};
+        "pack", "adj_body"};
     return (id >= 0 && id < K_NUM_KERNELS) ? names[id] : "unknown";
 }
 
@@ -244,8 +244,8 @@ void gradient_enqueue(lddmm_plan *P, float *g)
     const int nt = P->nt;
     float *lam = P->lam;
     axpby(P, N, 1.f, P->m1, -1.f, P->m + (long)nt * N, lam + (long)nt * N);
-    for (int j = nt - 1; j >= 0; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
-    launch_body_force(P, lam, lam + (long)nt * N, 1.f, P->G, P->b);
+    for (int j = nt - 1; j >= 1; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
+    launch_adj_body(P, lam + N, 1.f, lam, lam, lam + (long)nt * N, 1.f);
     assemble(P, P->v, P->b, g);
     dot_async(P, g, g, 3 * N, S_GG, P->h3);
     P->have_grad = 1;
@@ -272,9 +272,13 @@ void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
         launch_incstate_step(P, mt[(j - 1) & 1], P->src + (long)(j - 1) * N, mt[j & 1]);
     const float *mtN = mt[(nt - 1) & 1];
     float *lam = P->lam;
-    launch_adj_step(P, mtN, lam + (long)(nt - 1) * N, -1.f);
-    for (int j = nt - 2; j >= 0; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
-    launch_body_force(P, lam, mtN, -1.f, P->G, P->b);
+    if (nt == 1) {
+        launch_adj_body(P, mtN, -1.f, lam, lam, mtN, -1.f);
+    } else {
+        launch_adj_step(P, mtN, lam + (long)(nt - 1) * N, -1.f);
+        for (int j = nt - 2; j >= 1; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
+        launch_adj_body(P, lam + N, 1.f, lam, lam, mtN, -1.f);
+    }
     assemble(P, vt, P->b, hvt);
     P->have_matvec = 1;
 }

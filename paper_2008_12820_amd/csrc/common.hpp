@@ -59,7 +59,7 @@ enum KernelId : int {
     K_DOT,
     K_VECOP,
     K_PACK,
-    K_INC_SOURCES,
+    K_ADJ_BODY,
     K_NUM_KERNELS
 };
 const char *kernel_name(int id);

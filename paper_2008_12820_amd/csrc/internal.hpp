@@ -158,6 +158,9 @@ void launch_adj_coef(lddmm_plan *P);
 void launch_adj_step(lddmm_plan *P, const float *lin, float *lout, float scale);
 void launch_incstate_init(lddmm_plan *P, const float *vt, float *mt1);
 void launch_incstate_step(lddmm_plan *P, const float *min, const float *s, float *mout);
+// last adjoint step into lam0 fused with the body force into P->b
+void launch_adj_body(lddmm_plan *P, const float *lin, float scale, float *lam0, const float *lam,
+                     const float *lamN, float scaleN);
 void launch_body_force(lddmm_plan *P, const float *lam, const float *lamN, float scaleN,
                        const float *G, float *b);
 

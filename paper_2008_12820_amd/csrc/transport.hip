@@ -245,36 +245,6 @@ __global__ __launch_bounds__(kPtThreads) void k_body_force(const float4 *__restr
 // Incremental-state sources from the increment vt and its values vX at the
 // departure points: s_j = vX . I[G_j](X) + vt . G_{j+1}; m~_1 = -dt/2 s_0 and
 // s_1 .. s_{nt-1} are stored.  Four points per thread (16-byte accesses).
-template <int NTC>
-__global__ __launch_bounds__(kPtThreads) void k_inc_sources(const float4 *__restrict__ vt,
-                                                            const float4 *__restrict__ vX,
-                                                            const float4 *__restrict__ GX,
-                                                            const float4 *__restrict__ G,
-                                                            float4 *__restrict__ mt1, float4 *__restrict__ src,
-                                                            long N4, int nt_rt, float hdt)
-{
-    const int nt = NTC > 0 ? NTC : nt_rt;
-    const long p = (long)xcd_block((int)blockIdx.x, (int)gridDim.x) * kPtThreads + threadIdx.x;
-    if (p >= N4) return;
-    const float4 v0 = vt[p], v1 = vt[N4 + p], v2 = vt[2 * N4 + p];
-    const float4 x0 = vX[p], x1 = vX[N4 + p], x2 = vX[2 * N4 + p];
-#pragma unroll
-    for (int j = 0; j < nt; ++j) {
-        const float4 *gx = GX + (long)j * 3 * N4;
-        const float4 *g1 = G + (long)(j + 1) * 3 * N4;
-        const float4 a0 = gx[p], a1 = gx[N4 + p], a2 = gx[2 * N4 + p];
-        const float4 b0 = g1[p], b1 = g1[N4 + p], b2 = g1[2 * N4 + p];
-        float4 s;
-        s.x = (x0.x * a0.x + x1.x * a1.x + x2.x * a2.x) + (v0.x * b0.x + v1.x * b1.x + v2.x * b2.x);
-        s.y = (x0.y * a0.y + x1.y * a1.y + x2.y * a2.y) + (v0.y * b0.y + v1.y * b1.y + v2.y * b2.y);
-        s.z = (x0.z * a0.z + x1.z * a1.z + x2.z * a2.z) + (v0.z * b0.z + v1.z * b1.z + v2.z * b2.z);
-        s.w = (x0.w * a0.w + x1.w * a1.w + x2.w * a2.w) + (v0.w * b0.w + v1.w * b1.w + v2.w * b2.w);
-        if (j == 0)
-            mt1[p] = make_float4(-hdt * s.x, -hdt * s.y, -hdt * s.z, -hdt * s.w);
-        else
-            src[(long)(j - 1) * N4 + p] = s;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Box gathers.  A 256-thread workgroup owns an output tile of T1 x T2 rows of
@@ -366,6 +336,79 @@ struct EpiVec3 {  // three fields (stride N): out_c = I[src_c]
         dst[2 * N + p] = v[2];
     }
 };
+// Incremental-state start (eq. incsta, Heun along the characteristics, with
+// m~_0 = 0): the gather gives v~(X) (three fields); with the per-velocity
+// I[grad m_j](X) and grad m_{j+1} the epilogue forms every step's source
+//   s_j = v~(X) . I[grad m_j](X) + v~ . grad m_{j+1},   j = 0 .. N_t - 1,
+// writes m~_1 = -dt/2 s_0 and keeps s_1 .. s_{N_t-1} for the later steps.
+template <int NTC>
+struct EpiIncSrc {
+    static constexpr int NF = 3;
+    const float *vt;        // v~ (stride N): gathered and read pointwise
+    const float *GX, *G;    // I[grad m_j](X) and grad m_j, three fields per j
+    float *mt1, *src;       // m~_1; s_j at src + (j - 1) N
+    long N;
+    int nt_rt;
+    float hdt;
+    __device__ const float *field(int f) const { return vt + f * N; }
+    __device__ void finish(long p, const float *x) const
+    {
+        const int nt = NTC > 0 ? NTC : nt_rt;
+        const float v0 = vt[p], v1 = vt[N + p], v2 = vt[2 * N + p];
+#pragma unroll
+        for (int j = 0; j < nt; ++j) {
+            const float *gx = GX + (long)j * 3 * N, *g1 = G + (long)(j + 1) * 3 * N;
+            const float s = (x[0] * gx[p] + x[1] * gx[N + p] + x[2] * gx[2 * N + p]) +
+                            (v0 * g1[p] + v1 * g1[N + p] + v2 * g1[2 * N + p]);
+            if (j == 0)
+                mt1[p] = -hdt * s;
+            else
+                src[(long)(j - 1) * N + p] = s;
+        }
+    }
+};
+
+// Last adjoint step (eq. adj-transport, incadj) fused with the body force:
+// lam_0 = scale c I[lam_1](Xa), then the trapezoid in time
+//   b = dt sum_j w_j lam_j grad m_j,  w_0 = w_{N_t} = 1/2, else 1,
+// with lam_0 from the gather, lam_1 .. lam_{N_t-1} from the sweep and
+// lam_{N_t} = scaleN lamN.
+template <int NTC>
+struct EpiAdjBody {
+    static constexpr int NF = 1;
+    const float *src, *coef;
+    float *lam0;            // lam_0 out
+    float scale;
+    const float *lam;       // lam_j at lam + j N, 1 <= j < N_t
+    const float *lamN;
+    float scaleN;
+    const float *G;         // grad m_j, three fields per j
+    float *b;               // body force, three fields
+    long N;
+    int nt_rt;
+    float dt;
+    __device__ const float *field(int) const { return src; }
+    __device__ void finish(long p, const float *v) const
+    {
+        const int nt = NTC > 0 ? NTC : nt_rt;
+        const float l0 = scale * coef[p] * v[0];
+        lam0[p] = l0;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+        for (int j = 0; j <= nt; ++j) {
+            const float w = (j == 0 || j == nt) ? 0.5f : 1.f;
+            const float l = j == 0 ? w * l0 : (j == nt ? (scaleN * w) * lamN[p] : w * lam[(long)j * N + p]);
+            const float *gj = G + (long)j * 3 * N;
+            a0 += l * gj[p];
+            a1 += l * gj[N + p];
+            a2 += l * gj[2 * N + p];
+        }
+        b[p] = dt * a0;
+        b[N + p] = dt * a1;
+        b[2 * N + p] = dt * a2;
+    }
+};
+
 // Stencil extents of one tile: the smallest first node (L) and the largest
 // (H) along each axis over the tile's grid points, reduced over the
 // workgroup; L1 > H1 when no point of the tile is inside the grid.
@@ -973,8 +1016,9 @@ void autotune_gather(lddmm_plan *P)
     P->gather_mode = keep >= 0 ? keep : bm;
     P->gather_ms[0] = best;
     // three-field gathers (more registers per point) are tuned on their own,
-    // on the velocity into the body-force scratch buffer
-    if (keep < 0 && P->v && P->b) {
+    // on the incremental-state start with the velocity for v~ (its outputs
+    // are matvec scratch)
+    if (keep < 0 && P->v && P->GX && P->mt && P->src) {
         float best3 = 1e30f;
         int bm3 = P->gather_mode;
         for (int m = 0; m < 3; ++m) {
@@ -982,9 +1026,9 @@ void autotune_gather(lddmm_plan *P)
             hipEvent_t a, b;
             check_hip(hipEventCreate(&a), "hipEventCreate");
             check_hip(hipEventCreate(&b), "hipEventCreate");
-            tiled(P, P->dX, EpiVec3{P->v, P->b, P->N}, K_INCSTATE_INIT);
+            launch_incstate_init(P, P->v, P->mt);
             check_hip(hipEventRecord(a, P->stream), "hipEventRecord");
-            for (int r = 0; r < 3; ++r) tiled(P, P->dX, EpiVec3{P->v, P->b, P->N}, K_INCSTATE_INIT);
+            for (int r = 0; r < 3; ++r) launch_incstate_init(P, P->v, P->mt);
             check_hip(hipEventRecord(b, P->stream), "hipEventRecord");
             check_hip(hipEventSynchronize(b), "hipEventSynchronize");
             float ms = 0.f;
@@ -1019,26 +1063,29 @@ void launch_adj_step(lddmm_plan *P, const float *lin, float *lout, float scale)
     tiled(P, P->dXa, EpiAdj{lin, P->coef, lout, scale}, K_ADJ_STEP);
 }
 
-// vX = vt(X) is staged in the body-force buffer, which the matvec writes
-// only later
 void launch_incstate_init(lddmm_plan *P, const float *vt, float *mt1)
 {
-    const long N = P->N, N4 = N / 4;
-    float *vX = P->b;
-    tiled(P, P->dX, EpiVec3{vt, vX, N}, K_INCSTATE_INIT);
-    Scope s(P, K_INC_SOURCES);
-    const dim3 grid((unsigned)((N4 + kPtThreads - 1) / kPtThreads));
-#define INC_SRC(NTC)                                                                                         \
-    hipLaunchKernelGGL((k_inc_sources<NTC>), grid, dim3(kPtThreads), 0, P->stream, (const float4 *)vt,       \
-                       (const float4 *)vX, (const float4 *)P->GX, (const float4 *)P->G, (float4 *)mt1,       \
-                       (float4 *)P->src, N4, P->nt, 0.5f * (float)P->dt)
+    const float hdt = 0.5f * (float)P->dt;
     switch (P->nt) {
-    case 4: INC_SRC(4); break;
-    case 8: INC_SRC(8); break;
-    default: INC_SRC(0); break;
+    case 4: tiled(P, P->dX, EpiIncSrc<4>{vt, P->GX, P->G, mt1, P->src, P->N, 4, hdt}, K_INCSTATE_INIT); break;
+    case 8: tiled(P, P->dX, EpiIncSrc<8>{vt, P->GX, P->G, mt1, P->src, P->N, 8, hdt}, K_INCSTATE_INIT); break;
+    default: tiled(P, P->dX, EpiIncSrc<0>{vt, P->GX, P->G, mt1, P->src, P->N, P->nt, hdt}, K_INCSTATE_INIT); break;
     }
-#undef INC_SRC
-    check_hip(hipGetLastError(), "k_inc_sources");
+}
+
+void launch_adj_body(lddmm_plan *P, const float *lin, float scale, float *lam0, const float *lam,
+                     const float *lamN, float scaleN)
+{
+    const float dt = (float)P->dt;
+#define ADJ_BODY(NTC, NT)                                                                                 \
+    tiled(P, P->dXa, EpiAdjBody<NTC>{lin, P->coef, lam0, scale, lam, lamN, scaleN, P->G, P->b, P->N, NT, dt}, \
+          K_ADJ_BODY)
+    switch (P->nt) {
+    case 4: ADJ_BODY(4, 4); break;
+    case 8: ADJ_BODY(8, 8); break;
+    default: ADJ_BODY(0, P->nt); break;
+    }
+#undef ADJ_BODY
 }
 
 void launch_incstate_step(lddmm_plan *P, const float *min, const float *sj, float *mout)
