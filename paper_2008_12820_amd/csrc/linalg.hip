@@ -8,20 +8,39 @@ constexpr int kRedThreads = 256;
 
 // mode 0: sum a*b;  mode 1: sum (a-b)^2
 template <int MODE>
+__device__ __forceinline__ double red_term(float x, float y)
+{
+    if (MODE == 0) return (double)x * (double)y;
+    const double d = (double)x - (double)y;
+    return d * d;
+}
+
+// Partial sums per workgroup over a fixed grid, in a fixed order: the result
+// is bitwise reproducible.  vec: 16-byte accesses over the first n/4 groups of
+// four, the n % 4 tail by the first threads of workgroup 0.
+template <int MODE>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const float *__restrict__ a,
                                                                 const float *__restrict__ b, long n,
-                                                                double *__restrict__ partial)
+                                                                int vec, double *__restrict__ partial)
 {
     __shared__ double sh[kRedThreads];
     double acc = 0.0;
     const long stride = (long)gridDim.x * blockDim.x;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        if (MODE == 0) {
-            acc += (double)a[i] * (double)b[i];
-        } else {
-            const double d = (double)a[i] - (double)b[i];
-            acc += d * d;
+    const long i0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (vec) {
+        const long n4 = n >> 2;
+        const float4 *a4 = (const float4 *)a, *b4 = (const float4 *)b;
+        for (long i = i0; i < n4; i += stride) {
+            const float4 x = a4[i], y = b4[i];
+            acc += (red_term<MODE>(x.x, y.x) + red_term<MODE>(x.y, y.y)) +
+                   (red_term<MODE>(x.z, y.z) + red_term<MODE>(x.w, y.w));
         }
+        if (blockIdx.x == 0 && (long)threadIdx.x < (n & 3)) {
+            const long t = (n4 << 2) + threadIdx.x;
+            acc += red_term<MODE>(a[t], b[t]);
+        }
+    } else {
+        for (long i = i0; i < n; i += stride) acc += red_term<MODE>(a[i], b[i]);
     }
     sh[threadIdx.x] = acc;
     __syncthreads();
@@ -48,28 +67,86 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double *__re
     if (threadIdx.x == 0) *out = scale * sh[0];
 }
 
-__global__ void k_axpby(long n, float a, const float *__restrict__ x, float b,
+// Elementwise updates: with vec set (every pointer 16-byte aligned) thread t
+// handles the groups of four t, t + stride, ... with 16-byte accesses and the
+// n % 4 tail elements go to the first threads; otherwise one element each.
+template <class F4, class F1>
+__device__ __forceinline__ void ew_loop(long n, int vec, F4 body4, F1 body1)
+{
+    const long stride = (long)gridDim.x * blockDim.x;
+    const long i0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (vec) {
+        const long n4 = n >> 2;
+        for (long i = i0; i < n4; i += stride) body4(i);
+        if (i0 < (n & 3)) body1((n4 << 2) + i0);
+    } else {
+        for (long i = i0; i < n; i += stride) body1(i);
+    }
+}
+
+// The updates round as written with explicit fused multiply-adds, the same in
+// the 16-byte and the one-element paths and in the host- and device-scalar
+// forms of the PCG loop (z + beta p, x + alpha p, r - alpha q: one rounding).
+__device__ __forceinline__ float axpby1(float a, float x, float b, float y) { return __builtin_fmaf(b, y, a * x); }
+
+__device__ __forceinline__ float4 f4axpby(float a, float4 x, float b, float4 y)
+{
+    return make_float4(axpby1(a, x.x, b, y.x), axpby1(a, x.y, b, y.y), axpby1(a, x.z, b, y.z),
+                       axpby1(a, x.w, b, y.w));
+}
+
+__global__ void k_axpby(long n, int vec, float a, const float *__restrict__ x, float b,
                         const float *__restrict__ y, float *__restrict__ out)
 {
-    const long stride = (long)gridDim.x * blockDim.x;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        out[i] = y ? a * x[i] + b * y[i] : a * x[i];
+    if (y) {
+        ew_loop(
+            n, vec,
+            [&](long i) { ((float4 *)out)[i] = f4axpby(a, ((const float4 *)x)[i], b, ((const float4 *)y)[i]); },
+            [&](long i) { out[i] = axpby1(a, x[i], b, y[i]); });
+    } else {
+        ew_loop(
+            n, vec,
+            [&](long i) {
+                const float4 v = ((const float4 *)x)[i];
+                ((float4 *)out)[i] = make_float4(a * v.x, a * v.y, a * v.z, a * v.w);
+            },
+            [&](long i) { out[i] = a * x[i]; });
+    }
 }
 
-__global__ void k_fill(long n, float value, float *__restrict__ out)
+__global__ void k_fill(long n, int vec, float value, float *__restrict__ out)
 {
-    const long stride = (long)gridDim.x * blockDim.x;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = value;
+    ew_loop(
+        n, vec, [&](long i) { ((float4 *)out)[i] = make_float4(value, value, value, value); },
+        [&](long i) { out[i] = value; });
 }
 
-__global__ void k_pcg_xr(long n, float al, const float *__restrict__ p, const float *__restrict__ q,
+// x += al p, r -= al q
+__device__ __forceinline__ void xr_update(long n, int vec, float al, const float *__restrict__ p,
+                                          const float *__restrict__ q, float *__restrict__ x,
+                                          float *__restrict__ r)
+{
+    ew_loop(
+        n, vec,
+        [&](long i) {
+            float4 *x4 = (float4 *)x + i, *r4 = (float4 *)r + i;
+            const float4 pv = ((const float4 *)p)[i], qv = ((const float4 *)q)[i];
+            const float4 xv = *x4, rv = *r4;
+            *x4 = make_float4(__builtin_fmaf(al, pv.x, xv.x), __builtin_fmaf(al, pv.y, xv.y),
+                              __builtin_fmaf(al, pv.z, xv.z), __builtin_fmaf(al, pv.w, xv.w));
+            *r4 = make_float4(__builtin_fmaf(-al, qv.x, rv.x), __builtin_fmaf(-al, qv.y, rv.y),
+                              __builtin_fmaf(-al, qv.z, rv.z), __builtin_fmaf(-al, qv.w, rv.w));
+        },
+        [&](long i) {
+            x[i] = __builtin_fmaf(al, p[i], x[i]);
+            r[i] = __builtin_fmaf(-al, q[i], r[i]);
+        });
+}
+
+__global__ void k_pcg_xr(long n, int vec, float al, const float *__restrict__ p, const float *__restrict__ q,
                          float *__restrict__ x, float *__restrict__ r)
 {
-    const long stride = (long)gridDim.x * blockDim.x;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        x[i] += al * p[i];
-        r[i] -= al * q[i];
-    }
+    xr_update(n, vec, al, p, q, x, r);
 }
 
 // ---- device-resident PCG scalars ----------------------------------------
@@ -121,24 +198,20 @@ __global__ void k_pcg_alpha(double *d)
     }
 }
 
-__global__ void k_pcg_xr_dev(long n, const double *__restrict__ d, const float *__restrict__ p,
+__global__ void k_pcg_xr_dev(long n, int vec, const double *__restrict__ d, const float *__restrict__ p,
                              const float *__restrict__ q, float *__restrict__ x, float *__restrict__ r)
 {
     const float al = (float)d[S_ALPHA];
     if (al == 0.f) return;
-    const long stride = (long)gridDim.x * blockDim.x;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        x[i] += al * p[i];
-        r[i] -= al * q[i];
-    }
+    xr_update(n, vec, al, p, q, x, r);
 }
 
-__global__ void k_copy_if(long n, const double *__restrict__ d, const float *__restrict__ z,
+__global__ void k_copy_if(long n, int vec, const double *__restrict__ d, const float *__restrict__ z,
                           float *__restrict__ x)
 {
     if (d[S_COPYZ] == 0.0) return;
-    const long stride = (long)gridDim.x * blockDim.x;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = z[i];
+    ew_loop(
+        n, vec, [&](long i) { ((float4 *)x)[i] = ((const float4 *)z)[i]; }, [&](long i) { x[i] = z[i]; });
 }
 
 // after rr = <r, r>: relative residual and the stopping test
@@ -162,25 +235,43 @@ __global__ void k_pcg_beta(double *d)
     d[S_RZ] = d[S_RZN];
 }
 
-__global__ void k_pcg_p(long n, const double *__restrict__ d, const float *__restrict__ z,
+__global__ void k_pcg_p(long n, int vec, const double *__restrict__ d, const float *__restrict__ z,
                         float *__restrict__ p)
 {
     if (d[S_DONE] != 0.0) return;
     const float be = (float)d[S_BETA];
-    const long stride = (long)gridDim.x * blockDim.x;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = z[i] + be * p[i];
+    ew_loop(
+        n, vec,
+        [&](long i) {
+            const float4 zv = ((const float4 *)z)[i];
+            float4 *p4 = (float4 *)p + i;
+            const float4 pv = *p4;
+            *p4 = make_float4(__builtin_fmaf(be, pv.x, zv.x), __builtin_fmaf(be, pv.y, zv.y),
+                              __builtin_fmaf(be, pv.z, zv.z), __builtin_fmaf(be, pv.w, zv.w));
+        },
+        [&](long i) { p[i] = __builtin_fmaf(be, p[i], z[i]); });
 }
 
 __global__ void k_sum2(double *d, int dst, int a, int b) { d[dst] = d[a] + d[b]; }
 
-__global__ void k_copy(long n, const float *__restrict__ x, float *__restrict__ out)
+__global__ void k_copy(long n, int vec, const float *__restrict__ x, float *__restrict__ out)
 {
-    const long stride = (long)gridDim.x * blockDim.x;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = x[i];
+    ew_loop(
+        n, vec, [&](long i) { ((float4 *)out)[i] = ((const float4 *)x)[i]; }, [&](long i) { out[i] = x[i]; });
 }
 
-static unsigned vec_blocks(long n)
+// 16-byte accesses when every pointer is 16-byte aligned
+static int vec_ok(std::initializer_list<const void *> ptrs)
 {
+    for (const void *q : ptrs)
+        if (q && ((uintptr_t)q & 15)) return 0;
+    return 1;
+}
+
+// workgroups of 256 for n elements (n / 4 groups when vec), at most 8192
+static unsigned vec_blocks(long n, int vec = 0)
+{
+    if (vec) n = (n + 3) / 4;
     long b = (n + 255) / 256;
     if (b > 8192) b = 8192;
     if (b < 1) b = 1;
@@ -191,7 +282,7 @@ void dot_async(lddmm_plan *P, const float *a, const float *b, long n, int slot, 
 {
     Scope s(P, K_DOT);
     hipLaunchKernelGGL(k_reduce_partial<0>, dim3(kRedBlocks), dim3(kRedThreads), 0, P->stream, a, b,
-                       n, P->red);
+                       n, vec_ok({a, b}), P->red);
     check_hip(hipGetLastError(), "k_reduce_partial");
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, P->stream, P->red, kRedBlocks,
                        P->dscal + slot, scale);
@@ -202,7 +293,7 @@ void sqdiff_async(lddmm_plan *P, const float *a, const float *b, long n, int slo
 {
     Scope s(P, K_DOT);
     hipLaunchKernelGGL(k_reduce_partial<1>, dim3(kRedBlocks), dim3(kRedThreads), 0, P->stream, a, b,
-                       n, P->red);
+                       n, vec_ok({a, b}), P->red);
     check_hip(hipGetLastError(), "k_reduce_partial");
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, P->stream, P->red, kRedBlocks,
                        P->dscal + slot, scale);
@@ -221,21 +312,24 @@ double fetch_scalar(lddmm_plan *P, int slot)
 void axpby(lddmm_plan *P, long n, float a, const float *x, float b, const float *y, float *out)
 {
     Scope s(P, K_VECOP);
-    hipLaunchKernelGGL(k_axpby, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, a, x, b, y, out);
+    const int vec = vec_ok({x, y, out});
+    hipLaunchKernelGGL(k_axpby, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, a, x, b, y, out);
     check_hip(hipGetLastError(), "k_axpby");
 }
 
 void fill(lddmm_plan *P, long n, float value, float *out)
 {
     Scope s(P, K_VECOP);
-    hipLaunchKernelGGL(k_fill, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, value, out);
+    const int vec = vec_ok({out});
+    hipLaunchKernelGGL(k_fill, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, value, out);
     check_hip(hipGetLastError(), "k_fill");
 }
 
 void pcg_update_xr(lddmm_plan *P, long n, float al, const float *p, const float *q, float *x, float *r)
 {
     Scope s(P, K_VECOP);
-    hipLaunchKernelGGL(k_pcg_xr, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, al, p, q, x, r);
+    const int vec = vec_ok({p, q, x, r});
+    hipLaunchKernelGGL(k_pcg_xr, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, al, p, q, x, r);
     check_hip(hipGetLastError(), "k_pcg_xr");
 }
 
@@ -257,28 +351,33 @@ void dev_sum(lddmm_plan *P, int dst, int a, int b) { LAUNCH1(k_sum2, P->dscal, d
 void dev_pcg_xr(lddmm_plan *P, long n, const float *p, const float *q, float *x, float *r)
 {
     Scope s(P, K_VECOP);
-    hipLaunchKernelGGL(k_pcg_xr_dev, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, P->dscal, p, q, x, r);
+    const int vec = vec_ok({p, q, x, r});
+    hipLaunchKernelGGL(k_pcg_xr_dev, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, P->dscal, p, q, x,
+                       r);
     check_hip(hipGetLastError(), "k_pcg_xr_dev");
 }
 
 void dev_copy_if(lddmm_plan *P, long n, const float *z, float *x)
 {
     Scope s(P, K_VECOP);
-    hipLaunchKernelGGL(k_copy_if, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, P->dscal, z, x);
+    const int vec = vec_ok({z, x});
+    hipLaunchKernelGGL(k_copy_if, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, P->dscal, z, x);
     check_hip(hipGetLastError(), "k_copy_if");
 }
 
 void dev_pcg_p(lddmm_plan *P, long n, const float *z, float *p)
 {
     Scope s(P, K_VECOP);
-    hipLaunchKernelGGL(k_pcg_p, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, P->dscal, z, p);
+    const int vec = vec_ok({z, p});
+    hipLaunchKernelGGL(k_pcg_p, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, P->dscal, z, p);
     check_hip(hipGetLastError(), "k_pcg_p");
 }
 
 void copy_kernel(lddmm_plan *P, long n, const float *x, float *out)
 {
     Scope s(P, K_VECOP);
-    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n)), dim3(256), 0, P->stream, n, x, out);
+    const int vec = vec_ok({x, out});
+    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, x, out);
     check_hip(hipGetLastError(), "k_copy");
 }
 
