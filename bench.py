@@ -341,6 +341,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-nt8", action="store_true")
+    ap.add_argument("--overlap", action="store_true",
+                    help="overlap the assembly's forward transform with the transport sweeps "
+                         "(per-kernel timings then share the device)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", choices=["full", "half"], default="full")
     ap.add_argument("--batched", action="store_true", help="add the 64-member batched run")
@@ -380,6 +383,7 @@ def main():
         torch.cuda.synchronize()
         pre = time.perf_counter() - t0
         tuning = plan.autotune()  # gather strategy, timed on this velocity's displacements
+        plan.set_overlap(args.overlap)
         log(f"autotuned: {tuning}")
         t0 = time.perf_counter()
         g, gn = plan.gradient()
@@ -464,6 +468,7 @@ def main():
         "newton_step_10pcg_ms": 1e3 * r4.get("newton_step_s", float("nan")),
         "newton_info": r4.get("newton_info"),
         "fft_tiles": r4["tuning"],
+        "overlap": bool(args.overlap),
     }
     if 8 in res_nt:
         r8 = res_nt[8]

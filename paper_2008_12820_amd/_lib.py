@@ -84,6 +84,7 @@ def lib():
             "lddmm_batch_gn_iterate": (st, [p, i32, d, i32, P(p), P(NewtonInfo)]),
             "lddmm_autotune": (st, [p]),
             "lddmm_set_gather_mode": (st, [p, i32]),
+            "lddmm_set_overlap": (st, [p, i32]),
             "lddmm_tuning": (st, [p, ctypes.c_char_p, sz]),
             "lddmm_set_timing": (st, [p, i32]),
             "lddmm_get_timing": (st, [p, i32, P(d), P(ctypes.c_int64)]),
@@ -276,6 +277,10 @@ def lddmm_autotune(plan):
 
 def lddmm_set_gather_mode(plan, mode):
     _check(lib().lddmm_set_gather_mode(plan, int(mode)), "set_gather_mode")
+
+
+def lddmm_set_overlap(plan, enable):
+    _check(lib().lddmm_set_overlap(plan, int(bool(enable))), "set_overlap")
 
 
 def lddmm_tuning(plan):

@@ -154,6 +154,12 @@ static void plan_free(lddmm_plan *P)
 {
     if (!P) return;
     fft_free(P);
+    if (P->side) {
+        (void)hipStreamSynchronize(P->side);
+        (void)hipStreamDestroy(P->side);
+    }
+    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     if (P->arena) (void)hipFree(P->arena);
     if (P->hscal) (void)hipHostFree(P->hscal);
     for (auto &pr : P->timing.pool) {
@@ -230,11 +236,44 @@ void velocity_state(lddmm_plan *P)
     P->have_matvec = 0;
 }
 
-static void assemble(lddmm_plan *P, const float *w, const float *b, float *out)
+// The assembly beta A w + K b needs the forward transform of w, which depends
+// on the input alone: with overlap on and outside stream capture it is started
+// on the side stream (forked from the plan's stream) while the transport
+// sweeps run, and the assembly joins it.  Otherwise everything stays on the
+// plan's stream.
+static bool assemble_prefetch(lddmm_plan *P, const float *w)
+{
+    if (!P->overlap) return false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    check_hip(hipStreamIsCapturing(P->stream, &cs), "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) return false;
+    if (!P->side) {  // created on first use, default priority
+        check_hip(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+        check_hip(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming), "hipEventCreateWithFlags");
+        check_hip(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming), "hipEventCreateWithFlags");
+    }
+    const long N = P->N;
+    check_hip(hipEventRecord(P->ev_fork, P->stream), "hipEventRecord");
+    check_hip(hipStreamWaitEvent(P->side, P->ev_fork, 0), "hipStreamWaitEvent");
+    hipStream_t main = P->stream;
+    P->stream = P->side;
+    try {
+        spectral_forward(P, SOP_ASSEMBLE, {w, w + N, w + 2 * N}, 3);
+    } catch (...) {
+        P->stream = main;
+        throw;
+    }
+    P->stream = main;
+    check_hip(hipEventRecord(P->ev_join, P->side), "hipEventRecord");
+    return true;
+}
+
+static void assemble(lddmm_plan *P, const float *w, const float *b, float *out, bool w_started = false)
 {
     const long N = P->N;
+    if (w_started) check_hip(hipStreamWaitEvent(P->stream, P->ev_join, 0), "hipStreamWaitEvent");
     spectral_apply(P, SOP_ASSEMBLE, {w, w + N, w + 2 * N, b, b + N, b + 2 * N},
-                   {out, out + N, out + 2 * N});
+                   {out, out + N, out + 2 * N}, w_started ? 3 : 0);
 }
 
 // g and <g,g> (slot S_GG), no host synchronisation
@@ -243,10 +282,11 @@ void gradient_enqueue(lddmm_plan *P, float *g)
     const long N = P->N;
     const int nt = P->nt;
     float *lam = P->lam;
+    const bool started = assemble_prefetch(P, P->v);
     axpby(P, N, 1.f, P->m1, -1.f, P->m + (long)nt * N, lam + (long)nt * N);
     for (int j = nt - 1; j >= 1; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
     launch_adj_body(P, lam + N, 1.f, lam, lam, lam + (long)nt * N, 1.f);
-    assemble(P, P->v, P->b, g);
+    assemble(P, P->v, P->b, g, started);
     dot_async(P, g, g, 3 * N, S_GG, P->h3);
     P->have_grad = 1;
 }
@@ -267,6 +307,7 @@ void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
     const long N = P->N;
     const int nt = P->nt;
     float *mt[2] = {P->mt, P->mt + N};
+    const bool started = assemble_prefetch(P, vt);
     launch_incstate_init(P, vt, mt[0]);
     for (int j = 1; j < nt; ++j)
         launch_incstate_step(P, mt[(j - 1) & 1], P->src + (long)(j - 1) * N, mt[j & 1]);
@@ -279,7 +320,7 @@ void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
         for (int j = nt - 2; j >= 1; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
         launch_adj_body(P, lam + N, 1.f, lam, lam, mtN, -1.f);
     }
-    assemble(P, vt, P->b, hvt);
+    assemble(P, vt, P->b, hvt, started);
     P->have_matvec = 1;
 }
 
@@ -891,6 +932,15 @@ lddmm_status lddmm_tuning(lddmm_plan *P, char *buf, size_t len)
         const size_t n = std::min(len - 1, r.size());
         std::memcpy(buf, r.data(), n);
         buf[n] = 0;
+    });
+}
+
+lddmm_status lddmm_set_overlap(lddmm_plan *P, int32_t enable)
+{
+    return guard([&] {
+        need(P, "plan");
+        if (enable != 0 && enable != 1) fail(LDDMM_EINVAL, "enable must be 0 or 1");
+        P->overlap = enable;
     });
 }
 

@@ -2076,31 +2076,44 @@ static void x1_symbol_parts(lddmm_plan *P, int op, int in0, int out0, int nbatch
 // Apply a spectral operator to real fields.  The real inputs are grouped in
 // batches of op_nin(op) fields; batches are processed in chunks that fit the
 // plan's spectral scratch (input slots followed by output slots).
+// forward x3 and x2 passes of inputs [f0, fin) of one chunk into slots
+// f0 .., grouped by precision (consecutive runs of at most eight)
+static void forward_passes(lddmm_plan *P, int op, const float *const *in, int nin, int f0, int fin)
+{
+    while (f0 < fin) {
+        const bool dbl = input_is_fp64(op, f0 % nin);
+        int f1 = f0 + 1;
+        while (f1 < fin && f1 - f0 < 8 && input_is_fp64(op, f1 % nin) == dbl) ++f1;
+        RealIn ri{};
+        for (int i = f0; i < f1; ++i) ri.p[i - f0] = in[i];
+        r2c_fields(P, ri, f1 - f0, f0, dbl);
+        x2_pass(P, f0, f1 - f0, false, dbl);
+        f0 = f1;
+    }
+}
+
+void spectral_forward(lddmm_plan *P, int op, const std::vector<const float *> &in, int count)
+{
+    if (count > op_nin(op) || count > (int)in.size() || P->nspec < op_nin(op) + op_nout(op))
+        fail(LDDMM_EINVAL, "spectral_forward: bad field count");
+    forward_passes(P, op, in.data(), op_nin(op), 0, count);
+}
+
 void spectral_apply(lddmm_plan *P, int op, const std::vector<const float *> &in,
-                    const std::vector<float *> &out)
+                    const std::vector<float *> &out, int fwd_done)
 {
     const int nin = op_nin(op), nout = op_nout(op);
     const int nbatch = (int)in.size() / nin;
     if ((int)in.size() != nbatch * nin || (int)out.size() != nbatch * nout)
         fail(LDDMM_EINVAL, "spectral_apply: field count mismatch");
+    if (fwd_done && nbatch != 1) fail(LDDMM_EINVAL, "spectral_apply: forward passes done for one field set only");
     const int per = nin + nout;
     const int chunk = P->nspec / per;
     if (chunk < 1) fail(LDDMM_EINVAL, "spectral scratch too small");
     for (int b0 = 0; b0 < nbatch; b0 += chunk) {
         const int nb = std::min(chunk, nbatch - b0);
         const int fin = nb * nin, fout = nb * nout;
-        // forward x3 and x2 passes, grouped by precision (consecutive runs)
-        int f0 = 0;
-        while (f0 < fin) {
-            const bool dbl = input_is_fp64(op, f0 % nin);
-            int f1 = f0 + 1;
-            while (f1 < fin && f1 - f0 < 8 && input_is_fp64(op, f1 % nin) == dbl) ++f1;
-            RealIn ri{};
-            for (int i = f0; i < f1; ++i) ri.p[i - f0] = in[(size_t)b0 * nin + i];
-            r2c_fields(P, ri, f1 - f0, f0, dbl);
-            x2_pass(P, f0, f1 - f0, false, dbl);
-            f0 = f1;
-        }
+        forward_passes(P, op, in.data() + (size_t)b0 * nin, nin, fwd_done, fin);
         x1_symbol(P, op, 0, fin, nb, P->cfg.leray);
         x2_pass(P, fin, fout, true, false);
         for (int g0 = 0; g0 < fout; g0 += 8) {

@@ -59,6 +59,11 @@ struct PlanTiming {
 struct lddmm_plan {
     lddmm_config cfg{};
     hipStream_t stream = nullptr;
+    // side stream and fork/join events: the forward transform of an input that
+    // only the final assembly needs runs beside the transport sweeps
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int overlap = 0;  // lddmm_set_overlap
     int device = 0;
     long N = 0;
     int nt = 0;
@@ -132,9 +137,14 @@ enum SpecOp { SOP_GRAD = 1, SOP_DIV, SOP_REG, SOP_INVREG, SOP_LERAY, SOP_ASSEMBL
 // x1 forward, pointwise symbol, x1 inverse in one pass: batches of the op's
 // input fields at spec_in + b*nin, outputs at spec_out + b*nout.
 void x1_symbol(lddmm_plan *P, int op, int spec_in, int spec_out, int nbatch, int leray);
-// whole operator on real fields (in: nbatch*nin fields, out: nbatch*nout)
+// whole operator on real fields (in: nbatch*nin fields, out: nbatch*nout);
+// fwd_done > 0 (one field set only): the forward passes of the first fwd_done
+// inputs were already run by spectral_forward
 void spectral_apply(lddmm_plan *P, int op, const std::vector<const float *> &in,
-                    const std::vector<float *> &out);
+                    const std::vector<float *> &out, int fwd_done = 0);
+// forward x3 and x2 passes of the first count inputs of one field set, into
+// the slots spectral_apply uses for them
+void spectral_forward(lddmm_plan *P, int op, const std::vector<const float *> &in, int count);
 int op_nin(int op);
 int op_nout(int op);
 // time the candidate tile shapes of every FFT kernel of the plan and keep

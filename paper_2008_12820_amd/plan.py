@@ -148,6 +148,9 @@ class Plan:
     def set_gather_mode(self, mode):
         L.lddmm_set_gather_mode(self._h, mode)
 
+    def set_overlap(self, enable):
+        L.lddmm_set_overlap(self._h, enable)
+
     def tuning(self):
         return L.lddmm_tuning(self._h)
 
