@@ -49,6 +49,10 @@ def lib():
             "or_ctx_get": (None, [p, i, i, p]),
             "or_ctx_pcg": (i, [p, p, i, d, p, p]),
             "or_ctx_gn_iterate": (i, [p, i, d, p, p]),
+            "or_ctx_h0_apply": (None, [p, p, p]),
+            "or_ctx_invh0": (i, [p, p, d, i, p]),
+            "or_ctx_pcg_pc": (i, [p, p, i, d, i, d, i, p, p]),
+            "or_ctx_gn_iterate_pc": (i, [p, i, d, i, d, i, p, p]),
             "or_ctx_transport": (None, [p, p, p]),
             "or_ctx_transport_vjp": (None, [p, p, p, p, p]),
         }
@@ -231,7 +235,35 @@ class Problem:
         h = np.array([2 * np.pi / n for n in self.shape]).reshape(3, 1, 1, 1)
         return (X - x) / h
 
-    def pcg(self, rhs, max_it, rtol):
+    def h0_apply(self, s):
+        """H0 s = beta0 A s + grad m(1) (grad m(1) . s), beta0 = max(beta, 5e-2)
+        (Section 2 "Preconditioning", eq. h0-pc)."""
+        a, pa = _c(s)
+        out = np.empty((3,) + self.shape)
+        lib().or_ctx_h0_apply(self._ctx, pa, out.ctypes.data_as(ctypes.c_void_p))
+        return out
+
+    def invh0(self, r, tol, max_it):
+        """Inner PCG solve of H0 s = r (Algorithm "PC"); returns (s, iterations)."""
+        a, pa = _c(r)
+        out = np.empty((3,) + self.shape)
+        it = lib().or_ctx_invh0(self._ctx, pa, float(tol), int(max_it),
+                                out.ctypes.data_as(ctypes.c_void_p))
+        return out, int(it)
+
+    def pcg(self, rhs, max_it, rtol, pc="inva", eps_h0=1e-3, max_inner=50):
+        if pc != "inva":
+            a, pa = _c(rhs)
+            x = np.empty((3,) + self.shape)
+            info = np.empty(5)
+            lib().or_ctx_pcg_pc(self._ctx, pa, int(max_it), float(rtol), {"invh0": 1}[pc],
+                                float(eps_h0), int(max_inner), x.ctypes.data_as(ctypes.c_void_p),
+                                info.ctypes.data_as(ctypes.c_void_p))
+            return x, {"iters": int(info[0]), "rel_res": float(info[1]), "flags": int(info[2]),
+                       "r0": float(info[3]), "inner": int(info[4])}
+        return self._pcg_inva(rhs, max_it, rtol)
+
+    def _pcg_inva(self, rhs, max_it, rtol):
         a, pa = _c(rhs)
         x = np.empty((3,) + self.shape)
         info = np.empty(4)
@@ -240,14 +272,15 @@ class Problem:
         return x, {"iters": int(info[0]), "rel_res": float(info[1]), "flags": int(info[2]),
                    "r0": float(info[3])}
 
-    def gn_iterate(self, max_pcg, rtol):
+    def gn_iterate(self, max_pcg, rtol, pc="inva", eps_h0=1e-3, max_inner=50):
         v = np.empty((3,) + self.shape)
-        info = np.empty(8)
-        lib().or_ctx_gn_iterate(self._ctx, int(max_pcg), float(rtol),
-                                v.ctypes.data_as(ctypes.c_void_p),
-                                info.ctypes.data_as(ctypes.c_void_p))
+        info = np.empty(9)
+        lib().or_ctx_gn_iterate_pc(self._ctx, int(max_pcg), float(rtol),
+                                   {"inva": 0, "invh0": 1}[pc], float(eps_h0), int(max_inner),
+                                   v.ctypes.data_as(ctypes.c_void_p),
+                                   info.ctypes.data_as(ctypes.c_void_p))
         keys = ["pcg_iters", "rel_res", "flags", "alpha", "J_before", "J_after", "gnorm_rel",
-                "gnorm"]
+                "gnorm", "inner_iters"]
         d = dict(zip(keys, info.tolist()))
         d["pcg_iters"] = int(d["pcg_iters"])
         d["flags"] = int(d["flags"])

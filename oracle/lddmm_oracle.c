@@ -25,7 +25,10 @@
  *   trapezoid rule in time for the body force;
  *   first-order spectral symbols use the Nyquist-zeroed wavenumber;
  *   (beta A)^{-1} takes 1/beta on the zero mode;
- *   h^3-weighted inner products; Armijo with c1 = 1e-4, halving, 10 tries.
+ *   h^3-weighted inner products; Armijo with c1 = 1e-4, halving, 10 tries;
+ *   InvH0: H0 without the Leray projector (as printed), beta0 = max(beta,
+ *   5e-2) in H0 and in its inner preconditioner, inner start (beta0 A)^{-1} r,
+ *   inner stop relative to ||r||, tolerance eps_H0 times the outer tolerance.
  */
 #include <complex.h>
 #include <math.h>
@@ -662,16 +665,99 @@ void or_ctx_get(const or_ctx *c, int what, int j, double *out)
 /* PCG and Gauss-Newton (eq. iter, Algorithm "GNK", preconditioner InvA)    */
 /* ------------------------------------------------------------------------ */
 
-/* Preconditioned CG for H x = rhs with M^{-1} = (beta A)^{-1}, x0 = 0.
+/* ------------------------------------------------------------------------ */
+/* Zero-velocity Hessian preconditioner InvH0 (Section 2 "Preconditioning", */
+/* eq. h0-pc, Algorithm "PC", first function)                               */
+/* ------------------------------------------------------------------------ */
+
+/* beta inside H0: the problem's beta, bounded below by 5e-2 */
+static double h0_beta(const or_ctx *c) { return c->beta < 5e-2 ? 5e-2 : c->beta; }
+
+/* out = H0 s = beta0 A s + grad m (grad m . s) with m the deformed template
+ * m(1) = m_{N_t} at the current velocity (the paper refreshes m0 in H0 with
+ * the template transported by the current iterate) and beta0 = h0_beta. */
+void or_ctx_h0_apply(const or_ctx *c, const double *s, double *out)
+{
+    long N = c->N;
+    const double *G = c->G + (long)c->nt * 3 * N;
+    double b0 = h0_beta(c);
+    or_reg_apply(s, out, 3, c->n[0], c->n[1], c->n[2], c->reg);
+    for (long p = 0; p < N; p++) {
+        double gs = G[p] * s[p] + G[N + p] * s[N + p] + G[2 * N + p] * s[2 * N + p];
+        for (int d = 0; d < 3; d++) out[d * N + p] = b0 * out[d * N + p] + G[d * N + p] * gs;
+    }
+}
+
+/* s ~= H0^{-1} r: PCG on H0 s = r, preconditioned by (beta0 A)^{-1}, started
+ * from s = (beta0 A)^{-1} r; stops when ||r - H0 s|| <= tol ||r|| (the
+ * unweighted L2 norm, as the outer PCG), after max_it iterations, or when
+ * <p, H0 p> <= 0.  Returns the iterations taken. */
+int or_ctx_invh0(const or_ctx *c, const double *r, double tol, int max_it, double *s)
+{
+    long M = 3 * c->N;
+    double h3 = c->h3, b0 = h0_beta(c);
+    double *ri = malloc(sizeof(double) * M);
+    double *zi = malloc(sizeof(double) * M);
+    double *pi = malloc(sizeof(double) * M);
+    double *qi = malloc(sizeof(double) * M);
+    or_reg_inverse(r, s, 3, c->n[0], c->n[1], c->n[2], c->reg, b0);
+    double rn0 = sqrt(or_inner(r, r, M, h3));
+    int it = 0;
+    if (rn0 > 0.0) {
+        or_ctx_h0_apply(c, s, qi);
+        for (long i = 0; i < M; i++) ri[i] = r[i] - qi[i];
+        double rn = sqrt(or_inner(ri, ri, M, h3));
+        if (rn > tol * rn0) {
+            or_reg_inverse(ri, zi, 3, c->n[0], c->n[1], c->n[2], c->reg, b0);
+            memcpy(pi, zi, sizeof(double) * M);
+            double rz = or_inner(ri, zi, M, h3);
+            while (it < max_it) {
+                or_ctx_h0_apply(c, pi, qi);
+                it++;
+                double kappa = or_inner(pi, qi, M, h3);
+                if (!(kappa > 0.0)) break;
+                double alpha = rz / kappa;
+                for (long i = 0; i < M; i++) {
+                    s[i] += alpha * pi[i];
+                    ri[i] -= alpha * qi[i];
+                }
+                rn = sqrt(or_inner(ri, ri, M, h3));
+                if (rn <= tol * rn0) break;
+                or_reg_inverse(ri, zi, 3, c->n[0], c->n[1], c->n[2], c->reg, b0);
+                double rz_new = or_inner(ri, zi, M, h3);
+                double bet = rz_new / rz;
+                rz = rz_new;
+                for (long i = 0; i < M; i++) pi[i] = zi[i] + bet * pi[i];
+            }
+        }
+    }
+    free(ri); free(zi); free(pi); free(qi);
+    return it;
+}
+
+/* the preconditioner M^{-1}: pc 0 = InvA, (beta A)^{-1}; pc 1 = InvH0 with
+ * the inner tolerance tol_h0 and at most max_inner inner iterations.
+ * Returns the inner iterations. */
+static int precondition(const or_ctx *c, const double *r, double *z, int pc, double tol_h0,
+                        int max_inner)
+{
+    if (pc == 1) return or_ctx_invh0(c, r, tol_h0, max_inner, z);
+    or_reg_inverse(r, z, 3, c->n[0], c->n[1], c->n[2], c->reg, c->beta);
+    return 0;
+}
+
+/* Preconditioned CG for H x = rhs, x0 = 0, M^{-1} from precondition() (InvA
+ * or InvH0 with the inner tolerance eps_h0 * rtol, Algorithm "PC").
  * Stops when ||r|| <= rtol ||r0||, after max_it matvecs, or when
  * <p, H p> <= 0 (then the current x; at the first iteration M^{-1} r0).
  * info: [0] iterations (matvecs), [1] ||r||/||r0||, [2] flags
- * (1 negative curvature, 2 non-finite), [3] ||r0||.  Returns flags. */
-int or_ctx_pcg(const or_ctx *c, const double *rhs, int max_it, double rtol, double *x,
-               double *info)
+ * (1 negative curvature, 2 non-finite), [3] ||r0||, [4] inner iterations of
+ * the preconditioner (summed).  Returns flags. */
+int or_ctx_pcg_pc(const or_ctx *c, const double *rhs, int max_it, double rtol, int pc,
+                  double eps_h0, int max_inner, double *x, double *info)
 {
     long M = 3 * c->N;
-    double h3 = c->h3;
+    double h3 = c->h3, tol_h0 = eps_h0 * rtol;
     double *r = malloc(sizeof(double) * M);
     double *z = malloc(sizeof(double) * M);
     double *p = malloc(sizeof(double) * M);
@@ -681,16 +767,16 @@ int or_ctx_pcg(const or_ctx *c, const double *rhs, int max_it, double rtol, doub
         r[i] = rhs[i];
     }
     double r0 = sqrt(or_inner(r, r, M, h3));
-    or_reg_inverse(r, z, 3, c->n[0], c->n[1], c->n[2], c->reg, c->beta);
-    memcpy(p, z, sizeof(double) * M);
-    double rz = or_inner(r, z, M, h3);
-    int it = 0, flags = 0;
+    int it = 0, flags = 0, inner = 0;
     double rn = r0;
     if (r0 == 0.0) {
-        info[0] = 0; info[1] = 0.0; info[2] = 0; info[3] = 0.0;
+        info[0] = 0; info[1] = 0.0; info[2] = 0; info[3] = 0.0; info[4] = 0;
         free(r); free(z); free(p); free(q);
         return 0;
     }
+    inner += precondition(c, r, z, pc, tol_h0, max_inner);
+    memcpy(p, z, sizeof(double) * M);
+    double rz = or_inner(r, z, M, h3);
     while (it < max_it) {
         or_ctx_matvec(c, p, q);
         it++;
@@ -701,7 +787,7 @@ int or_ctx_pcg(const or_ctx *c, const double *rhs, int max_it, double rtol, doub
         }
         if (kappa <= 0.0) {
             flags |= 1;
-            if (it == 1) or_reg_inverse(r, x, 3, c->n[0], c->n[1], c->n[2], c->reg, c->beta);
+            if (it == 1) memcpy(x, z, sizeof(double) * M);  /* z = M^{-1} r0 */
             break;
         }
         double alpha = rz / kappa;
@@ -711,7 +797,7 @@ int or_ctx_pcg(const or_ctx *c, const double *rhs, int max_it, double rtol, doub
         }
         rn = sqrt(or_inner(r, r, M, h3));
         if (rn <= rtol * r0) break;
-        or_reg_inverse(r, z, 3, c->n[0], c->n[1], c->n[2], c->reg, c->beta);
+        inner += precondition(c, r, z, pc, tol_h0, max_inner);
         double rz_new = or_inner(r, z, M, h3);
         double bet = rz_new / rz;
         rz = rz_new;
@@ -721,7 +807,18 @@ int or_ctx_pcg(const or_ctx *c, const double *rhs, int max_it, double rtol, doub
     info[1] = rn / r0;
     info[2] = flags;
     info[3] = r0;
+    info[4] = inner;
     free(r); free(z); free(p); free(q);
+    return flags;
+}
+
+/* PCG with M^{-1} = (beta A)^{-1} (preconditioner InvA); info [0..3] */
+int or_ctx_pcg(const or_ctx *c, const double *rhs, int max_it, double rtol, double *x,
+               double *info)
+{
+    double inf5[5];
+    int flags = or_ctx_pcg_pc(c, rhs, max_it, rtol, 0, 0.0, 0, x, inf5);
+    for (int k = 0; k < 4; k++) info[k] = inf5[k];
     return flags;
 }
 
@@ -732,8 +829,9 @@ int or_ctx_pcg(const or_ctx *c, const double *rhs, int max_it, double rtol, doub
  * then v <- v + alpha v~ and the context is refreshed.
  * v_out receives the new velocity.  info: [0] pcg its, [1] rel res, [2] flags,
  * [3] alpha (0 if the search failed), [4] J before, [5] J after,
- * [6] ||g||/||g0||, [7] ||g||. */
-int or_ctx_gn_iterate(or_ctx *c, int max_pcg, double rtol, double *v_out, double *info)
+ * [6] ||g||/||g0||, [7] ||g||, [8] inner preconditioner iterations. */
+int or_ctx_gn_iterate_pc(or_ctx *c, int max_pcg, double rtol, int pc, double eps_h0, int max_inner,
+                         double *v_out, double *info)
 {
     long M = 3 * c->N;
     double *g = malloc(sizeof(double) * M);
@@ -749,8 +847,8 @@ int or_ctx_gn_iterate(or_ctx *c, int max_pcg, double rtol, double *v_out, double
     or_ctx_objective(c, J0);
     double tol = rtol > 0.0 ? rtol : fmin(sqrt(grel), 0.5);
     for (long i = 0; i < M; i++) mg[i] = -g[i];
-    double pinfo[4];
-    int flags = or_ctx_pcg(c, mg, max_pcg, tol, vt, pinfo);
+    double pinfo[5];
+    int flags = or_ctx_pcg_pc(c, mg, max_pcg, tol, pc, eps_h0, max_inner, vt, pinfo);
     double gv = or_inner(g, vt, M, c->h3);
     double alpha = 1.0, Jn[3] = {J0[0], J0[1], J0[2]};
     int ok = 0;
@@ -779,7 +877,17 @@ int or_ctx_gn_iterate(or_ctx *c, int max_pcg, double rtol, double *v_out, double
     info[5] = Jn[0];
     info[6] = grel;
     info[7] = gnorm;
+    info[8] = pinfo[4];
     free(g); free(mg); free(vt); free(v0); free(vn);
+    return flags;
+}
+
+/* the Gauss-Newton iteration with PCG preconditioned by InvA; info [0..7] */
+int or_ctx_gn_iterate(or_ctx *c, int max_pcg, double rtol, double *v_out, double *info)
+{
+    double inf9[9];
+    int flags = or_ctx_gn_iterate_pc(c, max_pcg, rtol, 0, 0.0, 0, v_out, inf9);
+    for (int k = 0; k < 8; k++) info[k] = inf9[k];
     return flags;
 }
 
