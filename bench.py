@@ -402,6 +402,19 @@ def main():
             torch.cuda.synchronize()
             res_nt[nt_]["newton_step_s"] = time.perf_counter() - t0
             res_nt[nt_]["newton_info"] = {k: info[k] for k in ("pcg_iters", "rel_res", "gnorm")}
+            # Newton step to a fixed relative residual with each preconditioner
+            pcs = {}
+            for kind in ("inva", "invh0"):
+                plan.set_preconditioner(kind, eps_h0=1e-3, max_inner=50)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, inf = plan.newton_step(100, 1e-2)
+                torch.cuda.synchronize()
+                pcs[kind] = {"ms": 1e3 * (time.perf_counter() - t0), "pcg_iters": inf["pcg_iters"],
+                             "inner_iters": inf["inner_iters"], "rel_res": inf["rel_res"]}
+                log(f"newton step rtol 1e-2, {kind}: {pcs[kind]}")
+            plan.set_preconditioner("inva")
+            res_nt[nt_]["newton_preconditioners"] = pcs
         plan.close()
         del plan
         torch.cuda.empty_cache()
@@ -467,6 +480,7 @@ def main():
         "gradient_ms": 1e3 * r4["gradient_s"],
         "newton_step_10pcg_ms": 1e3 * r4.get("newton_step_s", float("nan")),
         "newton_info": r4.get("newton_info"),
+        "newton_rtol_1e-2": r4.get("newton_preconditioners"),
         "fft_tiles": r4["tuning"],
         "overlap": bool(args.overlap),
     }

@@ -82,6 +82,8 @@ typedef struct lddmm_newton_info {
     double J_after;     /* objective at the accepted velocity */
     double gnorm;       /* ||g|| at the start of the step */
     double gnorm_rel;   /* ||g|| / ||g0||, g0 the first gradient after set_images */
+    int32_t inner_iters;  /* H0 applications inside the InvH0 preconditioner (0 for InvA) */
+    int32_t reserved;
 } lddmm_newton_info;
 
 typedef struct lddmm_plan lddmm_plan;
@@ -247,6 +249,25 @@ lddmm_status lddmm_batch_gn_iterate(lddmm_batch *batch, int32_t max_pcg, double 
  * and grid size for the process and, when the environment variable
  * LDDMM_TUNE_CACHE names a file, in that file.  Synchronises the stream. */
 lddmm_status lddmm_autotune(lddmm_plan *plan);
+/* Preconditioner of the PCG in lddmm_newton_step and lddmm_gn_iterate
+ * (Section 2 "Preconditioning"): kind 0 = InvA, (beta A)^{-1} (the default);
+ * kind 1 = InvH0, an inner PCG solve of eq. h0-pc,
+ *   (beta0 A + grad m (x) grad m) s = r,  beta0 = max(beta, 5e-2),
+ * with m the deformed template m(1) at the current velocity, preconditioned
+ * by (beta0 A)^{-1}, started from (beta0 A)^{-1} r, stopped at
+ * ||r - H0 s|| <= eps_h0 * eps_K * ||r|| (eps_K the outer tolerance) or after
+ * max_inner iterations (Algorithm "PC", first variant).  InvH0 allocates four
+ * more 3N-float vectors on first use.  EINVAL for kind outside 0..1, eps_h0
+ * not in (0, 1) or max_inner < 1.  The batched iteration supports InvA only. */
+lddmm_status lddmm_set_preconditioner(lddmm_plan *plan, int32_t kind, double eps_h0, int32_t max_inner);
+/* out = H0 s (eq. h0-pc, the operator above); 3N floats each.  ESTATE before
+ * a velocity is set. */
+lddmm_status lddmm_apply_h0(lddmm_plan *plan, const float *s, float *out);
+/* s ~= H0^{-1} r by the inner PCG above with relative tolerance tol (>= 0; 0
+ * runs exactly max_inner iterations unless the residual vanishes) and at most
+ * max_inner >= 0 iterations; *iters (may be NULL) receives the iterations. */
+lddmm_status lddmm_apply_invh0(lddmm_plan *plan, const float *r, double tol, int32_t max_inner, float *s,
+                               int32_t *iters);
 /* Override the gather strategy of the interpolation kernels: 0 direct
  * (one thread per point, stencil loads through L1/L2), 1 and 2 LDS-staged
  * boxes for tiles of 2x4x64 and 4x4x64 points (points whose stencil leaves

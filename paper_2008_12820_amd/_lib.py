@@ -31,10 +31,11 @@ class NewtonInfo(ctypes.Structure):
     _fields_ = [("pcg_iters", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("rel_res", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("J_before", ctypes.c_double), ("J_after", ctypes.c_double),
-                ("gnorm", ctypes.c_double), ("gnorm_rel", ctypes.c_double)]
+                ("gnorm", ctypes.c_double), ("gnorm_rel", ctypes.c_double),
+                ("inner_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class LddmmError(RuntimeError):
@@ -66,6 +67,9 @@ def lib():
             "lddmm_gradient": (st, [p, p, P(d)]),
             "lddmm_hessian_matvec": (st, [p, p, p]),
             "lddmm_apply_inv_reg": (st, [p, p, p]),
+            "lddmm_set_preconditioner": (st, [p, i32, d, i32]),
+            "lddmm_apply_h0": (st, [p, p, p]),
+            "lddmm_apply_invh0": (st, [p, p, d, i32, p, P(i32)]),
             "lddmm_newton_step": (st, [p, i32, d, p, P(NewtonInfo)]),
             "lddmm_gn_iterate": (st, [p, i32, d, p, P(NewtonInfo)]),
             "lddmm_transport_forward": (st, [p, p, p, p, p]),
@@ -179,6 +183,22 @@ def lddmm_hessian_matvec(plan, vt, hvt):
 
 def lddmm_apply_inv_reg(plan, r, s):
     _check(lib().lddmm_apply_inv_reg(plan, _ptr(r), _ptr(s)), "apply_inv_reg")
+
+
+def lddmm_set_preconditioner(plan, kind, eps_h0=1e-3, max_inner=50):
+    _check(lib().lddmm_set_preconditioner(plan, int(kind), float(eps_h0), int(max_inner)),
+           "set_preconditioner")
+
+
+def lddmm_apply_h0(plan, s, out):
+    _check(lib().lddmm_apply_h0(plan, _ptr(s), _ptr(out)), "apply_h0")
+
+
+def lddmm_apply_invh0(plan, r, tol, max_inner, s):
+    it = ctypes.c_int32(0)
+    _check(lib().lddmm_apply_invh0(plan, _ptr(r), float(tol), int(max_inner), _ptr(s), ctypes.byref(it)),
+           "apply_invh0")
+    return it.value
 
 
 def lddmm_newton_step(plan, max_pcg, rtol, vt_out, allow_notconv=False):

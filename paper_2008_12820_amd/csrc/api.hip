@@ -160,6 +160,7 @@ static void plan_free(lddmm_plan *P)
     }
     if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
     if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+    if (P->h0buf) (void)hipFree(P->h0buf);
     if (P->arena) (void)hipFree(P->arena);
     if (P->hscal) (void)hipHostFree(P->hscal);
     for (auto &pr : P->timing.pool) {
@@ -336,6 +337,87 @@ static double dot_now(lddmm_plan *P, const float *a, const float *b, long n)
     return fetch_scalar(P, 1);
 }
 
+// ---- zero-velocity Hessian preconditioner InvH0 (Section 2 "Preconditioning",
+// eq. h0-pc, Algorithm "PC") ---------------------------------------------------
+
+static double h0_beta(const lddmm_plan *P) { return P->cfg.beta < 5e-2 ? 5e-2 : P->cfg.beta; }
+
+// out = H0 s = beta0 A s + grad m(1) (grad m(1) . s), with grad m(1) the stored
+// gradient of the template transported by the current velocity
+static void h0_apply(lddmm_plan *P, const float *s, float *out)
+{
+    const long N = P->N;
+    spectral_apply(P, SOP_REG, {s, s + N, s + 2 * N}, {out, out + N, out + 2 * N});
+    h0_point(P, s, P->G + (long)P->nt * 3 * N, out, (float)h0_beta(P));
+}
+
+// (beta0 A)^{-1} r: the InvA symbol with beta0 for the duration of the scope
+struct Beta0Scope {
+    lddmm_plan *P;
+    explicit Beta0Scope(lddmm_plan *p) : P(p) { P->beta_sym = h0_beta(P); }
+    ~Beta0Scope() { P->beta_sym = 0.0; }
+};
+
+static float *h0_vectors(lddmm_plan *P)
+{
+    if (!P->h0buf) {
+        const size_t bytes = sizeof(float) * 4 * 3 * (size_t)P->N;
+        hipError_t e = hipMalloc((void **)&P->h0buf, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            P->h0buf = nullptr;
+            fail(LDDMM_ENOMEM, "InvH0 vectors of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+        }
+    }
+    return P->h0buf;
+}
+
+// s ~= H0^{-1} r: PCG on H0 s = r preconditioned by (beta0 A)^{-1}, from
+// s = (beta0 A)^{-1} r, until ||r - H0 s|| <= tol ||r||, max_it iterations or
+// <p, H0 p> <= 0.  Returns the iterations (H0 applications after the start).
+static int invh0_impl(lddmm_plan *P, const float *r, float *s, double tol, int max_it)
+{
+    const long M = 3 * P->N;
+    float *w = h0_vectors(P);
+    float *ri = w, *zi = w + M, *pi = w + 2 * M, *qi = w + 3 * M;
+    Beta0Scope b0(P);
+    inv_reg(P, r, s);
+    const double rn0 = std::sqrt(dot_now(P, r, r, M));
+    if (rn0 == 0.0) return 0;
+    h0_apply(P, s, qi);
+    axpby(P, M, 1.f, r, -1.f, qi, ri);
+    double rn = std::sqrt(dot_now(P, ri, ri, M));
+    if (rn <= tol * rn0) return 0;
+    inv_reg(P, ri, zi);
+    copy_dev(P, pi, zi, M);
+    double rz = dot_now(P, ri, zi, M);
+    int it = 0;
+    while (it < max_it) {
+        h0_apply(P, pi, qi);
+        ++it;
+        const double kappa = dot_now(P, pi, qi, M);
+        if (!(kappa > 0.0)) break;
+        pcg_update_xr(P, M, (float)(rz / kappa), pi, qi, s, ri);
+        rn = std::sqrt(dot_now(P, ri, ri, M));
+        if (rn <= tol * rn0) break;
+        inv_reg(P, ri, zi);
+        const double rz_new = dot_now(P, ri, zi, M);
+        const double be = rz_new / rz;
+        rz = rz_new;
+        axpby(P, M, 1.f, zi, (float)be, pi, pi);
+    }
+    return it;
+}
+
+// the preconditioner M^{-1} r of the outer PCG (tol_outer: its eps_K);
+// returns the inner iterations
+static int precondition(lddmm_plan *P, const float *r, float *z, double tol_outer)
+{
+    if (P->pc_kind == 1) return invh0_impl(P, r, z, P->pc_eps_h0 * tol_outer, P->pc_max_inner);
+    inv_reg(P, r, z);
+    return 0;
+}
+
 // Preconditioned CG on H x = rhs, x0 = 0, M^{-1} = (beta A)^{-1}.
 static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, float *x,
                     lddmm_newton_info &info)
@@ -349,8 +431,9 @@ static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, fl
     double rn = r0;
     info.pcg_iters = 0;
     info.rel_res = 0.0;
+    info.inner_iters = 0;
     if (r0 == 0.0) return 0;
-    inv_reg(P, r, z);
+    info.inner_iters += precondition(P, r, z, rtol);
     copy_dev(P, p, z, M);
     double rz = dot_now(P, r, z, M);
     while (it < max_it) {
@@ -374,7 +457,7 @@ static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, fl
             break;
         }
         if (rn <= rtol * r0) break;
-        inv_reg(P, r, z);
+        info.inner_iters += precondition(P, r, z, rtol);
         const double rz_new = dot_now(P, r, z, M);
         const double be = rz_new / rz;
         rz = rz_new;
@@ -932,6 +1015,46 @@ lddmm_status lddmm_tuning(lddmm_plan *P, char *buf, size_t len)
         const size_t n = std::min(len - 1, r.size());
         std::memcpy(buf, r.data(), n);
         buf[n] = 0;
+    });
+}
+
+lddmm_status lddmm_set_preconditioner(lddmm_plan *P, int32_t kind, double eps_h0, int32_t max_inner)
+{
+    return guard([&] {
+        need(P, "plan");
+        if (kind < 0 || kind > 1) fail(LDDMM_EINVAL, "kind must be 0 (InvA) or 1 (InvH0)");
+        if (!(eps_h0 > 0.0 && eps_h0 < 1.0)) fail(LDDMM_EINVAL, "eps_h0 must lie in (0, 1)");
+        if (max_inner < 1) fail(LDDMM_EINVAL, "max_inner must be >= 1");
+        P->pc_kind = kind;
+        P->pc_eps_h0 = eps_h0;
+        P->pc_max_inner = max_inner;
+    });
+}
+
+lddmm_status lddmm_apply_h0(lddmm_plan *P, const float *s, float *out)
+{
+    return guard([&] {
+        need(P, "plan");
+        need_dev(s, "s");
+        need_dev(out, "out");
+        need_full(P);
+        need_velocity(P);
+        h0_apply(P, s, out);
+    });
+}
+
+lddmm_status lddmm_apply_invh0(lddmm_plan *P, const float *r, double tol, int32_t max_inner, float *s,
+                               int32_t *iters)
+{
+    return guard([&] {
+        need(P, "plan");
+        need_dev(r, "r");
+        need_dev(s, "s");
+        if (!(tol >= 0.0) || max_inner < 0) fail(LDDMM_EINVAL, "tol must be >= 0 and max_inner >= 0");
+        need_full(P);
+        need_velocity(P);
+        const int it = invh0_impl(P, r, s, tol, max_inner);
+        if (iters) *iters = it;
     });
 }
 

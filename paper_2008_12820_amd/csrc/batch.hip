@@ -197,6 +197,8 @@ lddmm_status lddmm_batch_gn_iterate(lddmm_batch *Bt, int32_t max_pcg, double rto
             if (!P->have_images || !P->have_velocity)
                 fail(LDDMM_ESTATE, "member " + std::to_string(b) + " has no velocity state");
             if (!v_inout[b] || (uintptr_t)v_inout[b] % 16) fail(LDDMM_EINVAL, "v_inout entry NULL or misaligned");
+            if (P->pc_kind != 0)
+                fail(LDDMM_EUNSUPPORTED, "member " + std::to_string(b) + ": the batched iteration runs InvA only");
         }
         check_hip(hipDeviceSynchronize(), "device sync");
         // phase 1: every member's iteration up to the first Armijo trial

@@ -1955,7 +1955,7 @@ static SymCtx sym_ctx(lddmm_plan *P, int leray)
     sc.n2 = F.n2;
     sc.n3 = F.n3;
     sc.scale = 1.0 / ((double)F.n1 * F.n2 * F.n3);
-    sc.beta = P->cfg.beta;
+    sc.beta = P->beta_sym > 0.0 ? P->beta_sym : P->cfg.beta;
     sc.reg = P->cfg.reg;
     sc.leray = leray;
     return sc;

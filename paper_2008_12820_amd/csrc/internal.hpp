@@ -64,6 +64,11 @@ struct lddmm_plan {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int overlap = 0;  // lddmm_set_overlap
+    // preconditioner (lddmm_set_preconditioner): 0 InvA, 1 InvH0
+    int pc_kind = 0, pc_max_inner = 50;
+    double pc_eps_h0 = 1e-3;
+    float *h0buf = nullptr;   // InvH0 inner PCG vectors r, z, p, q (4 x 3N), on first use
+    double beta_sym = 0.0;    // > 0: beta of the (beta A)^{-1} symbol instead of cfg.beta
     int device = 0;
     long N = 0;
     int nt = 0;
@@ -169,6 +174,7 @@ void launch_adj_step(lddmm_plan *P, const float *lin, float *lout, float scale);
 void launch_incstate_init(lddmm_plan *P, const float *vt, float *mt1);
 void launch_incstate_step(lddmm_plan *P, const float *min, const float *s, float *mout);
 // last adjoint step into lam0 fused with the body force into P->b
+void h0_point(lddmm_plan *P, const float *s, const float *G, float *out, float beta0);
 void launch_adj_body(lddmm_plan *P, const float *lin, float scale, float *lam0, const float *lam,
                      const float *lamN, float scaleN);
 void launch_body_force(lddmm_plan *P, const float *lam, const float *lamN, float scaleN,

@@ -149,6 +149,37 @@ __global__ void k_pcg_xr(long n, int vec, float al, const float *__restrict__ p,
     xr_update(n, vec, al, p, q, x, r);
 }
 
+// H0 s = beta0 A s + G (G . s) (eq. h0-pc): on entry out holds A s; three
+// fields each, stride n
+__global__ void k_h0_point(long n, int vec, float beta0, const float *__restrict__ s,
+                           const float *__restrict__ G, float *__restrict__ out)
+{
+    ew_loop(
+        n, vec,
+        [&](long i) {
+            const float4 s0 = ((const float4 *)s)[i], s1 = ((const float4 *)(s + n))[i],
+                         s2 = ((const float4 *)(s + 2 * n))[i];
+            const float4 g0 = ((const float4 *)G)[i], g1 = ((const float4 *)(G + n))[i],
+                         g2 = ((const float4 *)(G + 2 * n))[i];
+            float4 *o0 = (float4 *)out + i, *o1 = (float4 *)(out + n) + i, *o2 = (float4 *)(out + 2 * n) + i;
+            const float4 d = make_float4(g0.x * s0.x + g1.x * s1.x + g2.x * s2.x, g0.y * s0.y + g1.y * s1.y + g2.y * s2.y,
+                                         g0.z * s0.z + g1.z * s1.z + g2.z * s2.z, g0.w * s0.w + g1.w * s1.w + g2.w * s2.w);
+            const float4 a0 = *o0, a1 = *o1, a2 = *o2;
+            *o0 = make_float4(beta0 * a0.x + g0.x * d.x, beta0 * a0.y + g0.y * d.y, beta0 * a0.z + g0.z * d.z,
+                              beta0 * a0.w + g0.w * d.w);
+            *o1 = make_float4(beta0 * a1.x + g1.x * d.x, beta0 * a1.y + g1.y * d.y, beta0 * a1.z + g1.z * d.z,
+                              beta0 * a1.w + g1.w * d.w);
+            *o2 = make_float4(beta0 * a2.x + g2.x * d.x, beta0 * a2.y + g2.y * d.y, beta0 * a2.z + g2.z * d.z,
+                              beta0 * a2.w + g2.w * d.w);
+        },
+        [&](long i) {
+            const float d = G[i] * s[i] + G[n + i] * s[n + i] + G[2 * n + i] * s[2 * n + i];
+            out[i] = beta0 * out[i] + G[i] * d;
+            out[n + i] = beta0 * out[n + i] + G[n + i] * d;
+            out[2 * n + i] = beta0 * out[2 * n + i] + G[2 * n + i] * d;
+        });
+}
+
 // ---- device-resident PCG scalars ----------------------------------------
 __global__ void k_set_scalar(double *d, int slot, double value) { d[slot] = value; }
 
@@ -371,6 +402,15 @@ void dev_pcg_p(lddmm_plan *P, long n, const float *z, float *p)
     const int vec = vec_ok({z, p});
     hipLaunchKernelGGL(k_pcg_p, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, P->dscal, z, p);
     check_hip(hipGetLastError(), "k_pcg_p");
+}
+
+void h0_point(lddmm_plan *P, const float *s, const float *G, float *out, float beta0)
+{
+    Scope sc(P, K_VECOP);
+    const long n = P->N;
+    const int vec = vec_ok({s, s + n, G, G + n, out, out + n});
+    hipLaunchKernelGGL(k_h0_point, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, beta0, s, G, out);
+    check_hip(hipGetLastError(), "k_h0_point");
 }
 
 void copy_kernel(lddmm_plan *P, long n, const float *x, float *out)

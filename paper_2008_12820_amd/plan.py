@@ -79,6 +79,20 @@ class Plan:
         L.lddmm_apply_inv_reg(self._h, self._in(r, True), s)
         return s
 
+    def set_preconditioner(self, kind, eps_h0=1e-3, max_inner=50):
+        """kind "inva" ((beta A)^-1) or "invh0" (inner PCG on eq. h0-pc)"""
+        L.lddmm_set_preconditioner(self._h, {"inva": 0, "invh0": 1}[kind], eps_h0, max_inner)
+
+    def apply_h0(self, s, out=None):
+        o = out if out is not None else self._vector()
+        L.lddmm_apply_h0(self._h, self._in(s, True), o)
+        return o
+
+    def apply_invh0(self, r, tol, max_inner, out=None):
+        s = out if out is not None else self._vector()
+        it = L.lddmm_apply_invh0(self._h, self._in(r, True), tol, max_inner, s)
+        return s, it
+
     def newton_step(self, max_pcg, rtol=0.0, out=None, allow_notconv=False):
         vt = out if out is not None else self._vector()
         st, info = L.lddmm_newton_step(self._h, max_pcg, rtol, vt, allow_notconv)

@@ -1,0 +1,112 @@
+"""GPU parity of the zero-velocity Hessian preconditioner InvH0 (Section 2
+"Preconditioning", eq. h0-pc, Algorithm "PC") against the FP64 oracle: the H0
+operator, the inner PCG solve at a fixed iteration count and at a tolerance,
+and a Newton step whose PCG uses it; argument checks."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import DEV, incremental, problem, rel, say, to_dev, to_np
+from paper_2008_12820_amd import LddmmError, Plan
+from paper_2008_12820_amd import _lib as L
+from paper_2008_12820_amd.batch import Batch
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(shape=(24, 20, 30), nt=3, reg=2, beta=1e-3, leray=False, disp=2.0):
+    m0, m1, vtrue, v, ref = problem(shape, nt, reg, beta, leray, disp=disp, nblobs=10)
+    P = Plan(shape, nt, reg=reg, beta=beta, leray=leray)
+    P.set_images(to_dev(m0), to_dev(m1))
+    P.set_velocity(to_dev(v))
+    return P, ref
+
+
+@pytest.mark.parametrize("beta,reg", [(1e-3, 2), (0.2, 1)])
+def test_h0_apply_matches_oracle(beta, reg):
+    say(f"H0 apply beta {beta} reg {reg}")
+    P, ref = _setup(beta=beta, reg=reg)
+    s = incremental(P.shape, 1500)
+    e = rel(to_np(P.apply_h0(to_dev(s))), ref.h0_apply(synth.f64(s)))
+    say(f"H0 rel {e:.2e}")
+    assert e < 1e-5
+
+
+def test_inner_solve_matches_oracle():
+    say("InvH0 inner solve")
+    P, ref = _setup()
+    r = incremental(P.shape, 1501)
+    s, it = P.apply_invh0(to_dev(r), 0.0, 6)
+    s_ref, it_ref = ref.invh0(synth.f64(r), 0.0, 6)
+    assert it == it_ref == 6
+    e = rel(to_np(s), s_ref)
+    say(f"6 inner iterations: rel {e:.2e}")
+    assert e < 1e-4
+    # to a tolerance: the same stopping rule, so the same iteration within one.
+    # The true FP64 residual of the FP32 iterate carries the FP32 rounding of s
+    # times ||H0|| ~ beta0 |k_max|^4 (1.1e4 here): about 1.3e-3 of ||r|| on top
+    # of the tolerance, which is what FP32 vectors can attain.
+    s, it = P.apply_invh0(to_dev(r), 1e-3, 100)
+    s_ref, it_ref = ref.invh0(synth.f64(r), 1e-3, 100)
+    assert abs(it - it_ref) <= 1 and it > 0
+    rr = synth.f64(r)
+    res = np.linalg.norm(rr - ref.h0_apply(synth.f64(to_np(s)))) / np.linalg.norm(rr)
+    res_ref = np.linalg.norm(rr - ref.h0_apply(s_ref)) / np.linalg.norm(rr)
+    say(f"tolerance 1e-3: {it} vs {it_ref} iterations, residual {res:.2e} vs {res_ref:.2e}")
+    assert res_ref <= 1e-3 and res <= 1e-3 + 1.5e-3, res
+
+
+def test_newton_step_with_invh0_matches_oracle_pcg():
+    say("Newton step, PCG with InvH0")
+    P, ref = _setup(shape=(32, 32, 32), nt=4, reg=2, beta=5e-4)
+    P.set_preconditioner("invh0", eps_h0=1e-3, max_inner=8)
+    vt, info = P.newton_step(4, 1e-12)  # fixed outer count; the inner tolerance 1e-15 leaves 8 each
+    vt_ref, pinfo = ref.pcg(-ref.gradient(), 4, 1e-12, pc="invh0", eps_h0=1e-3, max_inner=8)
+    assert info["pcg_iters"] == pinfo["iters"] == 4
+    assert info["inner_iters"] == pinfo["inner"] == 5 * 8
+    e = rel(to_np(vt), vt_ref)
+    say(f"newton step rel {e:.2e}")
+    assert e < 1e-4
+    # InvA again on the same plan
+    P.set_preconditioner("inva")
+    vt2, info2 = P.newton_step(4, 1e-12)
+    vt2_ref, _ = ref.pcg(-ref.gradient(), 4, 1e-12)
+    assert info2["inner_iters"] == 0 and rel(to_np(vt2), vt2_ref) < 1e-4
+
+
+def test_invh0_cuts_outer_iterations():
+    say("InvH0 vs InvA outer iterations")
+    P, _ = _setup(shape=(32, 32, 32), nt=4, reg=2, beta=5e-4, disp=3.0)
+    _, ia = P.newton_step(200, 1e-3)
+    P.set_preconditioner("invh0", eps_h0=1e-3, max_inner=50)
+    _, ih = P.newton_step(200, 1e-3)
+    say(f"outer: InvA {ia['pcg_iters']}, InvH0 {ih['pcg_iters']} (+{ih['inner_iters']} inner)")
+    assert ih["pcg_iters"] < ia["pcg_iters"]
+    assert ih["rel_res"] <= 1e-3 and ia["rel_res"] <= 1e-3
+
+
+def test_preconditioner_arguments():
+    P, _ = _setup(shape=(16, 16, 16), nt=2)
+    for args in [(2, 1e-3, 10), (1, 0.0, 10), (1, 1.0, 10), (1, 1e-3, 0), (-1, 1e-3, 10)]:
+        with pytest.raises(LddmmError) as e:
+            L.lddmm_set_preconditioner(P._h, *args)
+        assert e.value.status == L.EINVAL
+    s = to_dev(incremental(P.shape, 1502))
+    with pytest.raises(LddmmError) as e:
+        L.lddmm_apply_invh0(P._h, s, -1.0, 5, P._vector())
+    assert e.value.status == L.EINVAL
+
+
+def test_batch_rejects_invh0():
+    shapes = [(16, 16, 16), (16, 16, 16)]
+    Bt = Batch(shapes, 2, reg=2, beta=1e-3, nstreams=2)
+    m0 = [to_dev(synth.f32(synth.blob_image(s, 4, 1510 + b))) for b, s in enumerate(shapes)]
+    Bt.set_images(m0, m0)
+    vb = [to_dev(np.zeros((3,) + s, np.float32)) for s in shapes]
+    Bt.set_velocity(vb)
+    L.lddmm_set_preconditioner(L.lddmm_batch_plan(Bt._h, 1), 1, 1e-3, 10)
+    with pytest.raises(LddmmError) as e:
+        Bt.gn_iterate(vb, 2, 0.0)
+    assert e.value.status == L.EUNSUPPORTED
+    Bt.close()
