@@ -50,6 +50,9 @@ def lib():
             "or_ctx_pcg": (i, [p, p, i, d, p, p]),
             "or_ctx_gn_iterate": (i, [p, i, d, p, p]),
             "or_ctx_h0_apply": (None, [p, p, p]),
+            "or_restrict": (None, [p, p, i, i, i, i]),
+            "or_prolong": (None, [p, p, i, i, i, i]),
+            "or_ctx_2linvh0": (i, [p, p, d, i, p]),
             "or_ctx_invh0": (i, [p, p, d, i, p]),
             "or_ctx_pcg_pc": (i, [p, p, i, d, i, d, i, p, p]),
             "or_ctx_gn_iterate_pc": (i, [p, i, d, i, d, i, p, p]),
@@ -144,6 +147,27 @@ def departure(v, nt):
     lib().or_departure(pv, *v.shape[1:], int(nt), X.ctypes.data_as(ctypes.c_void_p),
                        Xa.ctypes.data_as(ctypes.c_void_p))
     return X, Xa
+
+
+def restrict(f):
+    """Spectral restriction of a field (or [3] stack) to half the resolution
+    (Algorithm "PC", Restrict): coarse Nyquist modes dropped."""
+    a, pa = _c(f)
+    vec = a.ndim == 4
+    shape = a.shape[1:] if vec else a.shape
+    out = np.empty(((3,) if vec else ()) + tuple(n // 2 for n in shape))
+    lib().or_restrict(pa, out.ctypes.data_as(ctypes.c_void_p), 3 if vec else 1, *shape)
+    return out
+
+
+def prolong(f):
+    """Spectral prolongation (zero padding) to twice the resolution (Prolong)."""
+    a, pa = _c(f)
+    vec = a.ndim == 4
+    shape = a.shape[1:] if vec else a.shape
+    out = np.empty(((3,) if vec else ()) + tuple(2 * n for n in shape))
+    lib().or_prolong(pa, out.ctypes.data_as(ctypes.c_void_p), 3 if vec else 1, *shape)
+    return out
 
 
 def grid_points(shape):
@@ -251,12 +275,20 @@ class Problem:
                                 out.ctypes.data_as(ctypes.c_void_p))
         return out, int(it)
 
+    def two_level_invh0(self, r, tol, max_it):
+        """2LInvH0 (Algorithm "PC", second function); returns (s, coarse iterations)."""
+        a, pa = _c(r)
+        out = np.empty((3,) + self.shape)
+        it = lib().or_ctx_2linvh0(self._ctx, pa, float(tol), int(max_it),
+                                  out.ctypes.data_as(ctypes.c_void_p))
+        return out, int(it)
+
     def pcg(self, rhs, max_it, rtol, pc="inva", eps_h0=1e-3, max_inner=50):
         if pc != "inva":
             a, pa = _c(rhs)
             x = np.empty((3,) + self.shape)
             info = np.empty(5)
-            lib().or_ctx_pcg_pc(self._ctx, pa, int(max_it), float(rtol), {"invh0": 1}[pc],
+            lib().or_ctx_pcg_pc(self._ctx, pa, int(max_it), float(rtol), {"invh0": 1, "2linvh0": 2}[pc],
                                 float(eps_h0), int(max_inner), x.ctypes.data_as(ctypes.c_void_p),
                                 info.ctypes.data_as(ctypes.c_void_p))
             return x, {"iters": int(info[0]), "rel_res": float(info[1]), "flags": int(info[2]),
@@ -276,7 +308,8 @@ class Problem:
         v = np.empty((3,) + self.shape)
         info = np.empty(9)
         lib().or_ctx_gn_iterate_pc(self._ctx, int(max_pcg), float(rtol),
-                                   {"inva": 0, "invh0": 1}[pc], float(eps_h0), int(max_inner),
+                                   {"inva": 0, "invh0": 1, "2linvh0": 2}[pc], float(eps_h0),
+                                   int(max_inner),
                                    v.ctypes.data_as(ctypes.c_void_p),
                                    info.ctypes.data_as(ctypes.c_void_p))
         keys = ["pcg_iters", "rel_res", "flags", "alpha", "J_before", "J_after", "gnorm_rel",

@@ -676,43 +676,50 @@ static double h0_beta(const or_ctx *c) { return c->beta < 5e-2 ? 5e-2 : c->beta;
 /* out = H0 s = beta0 A s + grad m (grad m . s) with m the deformed template
  * m(1) = m_{N_t} at the current velocity (the paper refreshes m0 in H0 with
  * the template transported by the current iterate) and beta0 = h0_beta. */
-void or_ctx_h0_apply(const or_ctx *c, const double *s, double *out)
+/* out = beta0 A s + G (G . s) on an n[0] x n[1] x n[2] grid */
+static void h0_apply_grid(const double *G, const int n[3], int reg, double b0, const double *s,
+                          double *out)
 {
-    long N = c->N;
-    const double *G = c->G + (long)c->nt * 3 * N;
-    double b0 = h0_beta(c);
-    or_reg_apply(s, out, 3, c->n[0], c->n[1], c->n[2], c->reg);
+    long N = (long)n[0] * n[1] * n[2];
+    or_reg_apply(s, out, 3, n[0], n[1], n[2], reg);
     for (long p = 0; p < N; p++) {
         double gs = G[p] * s[p] + G[N + p] * s[N + p] + G[2 * N + p] * s[2 * N + p];
         for (int d = 0; d < 3; d++) out[d * N + p] = b0 * out[d * N + p] + G[d * N + p] * gs;
     }
 }
 
+void or_ctx_h0_apply(const or_ctx *c, const double *s, double *out)
+{
+    h0_apply_grid(c->G + (long)c->nt * 3 * c->N, c->n, c->reg, h0_beta(c), s, out);
+}
+
 /* s ~= H0^{-1} r: PCG on H0 s = r, preconditioned by (beta0 A)^{-1}, started
  * from s = (beta0 A)^{-1} r; stops when ||r - H0 s|| <= tol ||r|| (the
  * unweighted L2 norm, as the outer PCG), after max_it iterations, or when
  * <p, H0 p> <= 0.  Returns the iterations taken. */
-int or_ctx_invh0(const or_ctx *c, const double *r, double tol, int max_it, double *s)
+/* PCG on H0 s = r over an n-grid (G its grad m, cell volume h3), from the
+ * start s0 given in s, preconditioned by (beta0 A)^{-1}; the stopping rule of
+ * or_ctx_invh0.  Returns the iterations. */
+static int h0_pcg_grid(const double *G, const int n[3], int reg, double b0, double h3,
+                       const double *r, double tol, int max_it, double *s)
 {
-    long M = 3 * c->N;
-    double h3 = c->h3, b0 = h0_beta(c);
+    long M = 3L * n[0] * n[1] * n[2];
     double *ri = malloc(sizeof(double) * M);
     double *zi = malloc(sizeof(double) * M);
     double *pi = malloc(sizeof(double) * M);
     double *qi = malloc(sizeof(double) * M);
-    or_reg_inverse(r, s, 3, c->n[0], c->n[1], c->n[2], c->reg, b0);
     double rn0 = sqrt(or_inner(r, r, M, h3));
     int it = 0;
     if (rn0 > 0.0) {
-        or_ctx_h0_apply(c, s, qi);
+        h0_apply_grid(G, n, reg, b0, s, qi);
         for (long i = 0; i < M; i++) ri[i] = r[i] - qi[i];
         double rn = sqrt(or_inner(ri, ri, M, h3));
         if (rn > tol * rn0) {
-            or_reg_inverse(ri, zi, 3, c->n[0], c->n[1], c->n[2], c->reg, b0);
+            or_reg_inverse(ri, zi, 3, n[0], n[1], n[2], reg, b0);
             memcpy(pi, zi, sizeof(double) * M);
             double rz = or_inner(ri, zi, M, h3);
             while (it < max_it) {
-                or_ctx_h0_apply(c, pi, qi);
+                h0_apply_grid(G, n, reg, b0, pi, qi);
                 it++;
                 double kappa = or_inner(pi, qi, M, h3);
                 if (!(kappa > 0.0)) break;
@@ -723,7 +730,7 @@ int or_ctx_invh0(const or_ctx *c, const double *r, double tol, int max_it, doubl
                 }
                 rn = sqrt(or_inner(ri, ri, M, h3));
                 if (rn <= tol * rn0) break;
-                or_reg_inverse(ri, zi, 3, c->n[0], c->n[1], c->n[2], c->reg, b0);
+                or_reg_inverse(ri, zi, 3, n[0], n[1], n[2], reg, b0);
                 double rz_new = or_inner(ri, zi, M, h3);
                 double bet = rz_new / rz;
                 rz = rz_new;
@@ -735,13 +742,110 @@ int or_ctx_invh0(const or_ctx *c, const double *r, double tol, int max_it, doubl
     return it;
 }
 
-/* the preconditioner M^{-1}: pc 0 = InvA, (beta A)^{-1}; pc 1 = InvH0 with
- * the inner tolerance tol_h0 and at most max_inner inner iterations.
+int or_ctx_invh0(const or_ctx *c, const double *r, double tol, int max_it, double *s)
+{
+    double b0 = h0_beta(c);
+    or_reg_inverse(r, s, 3, c->n[0], c->n[1], c->n[2], c->reg, b0);
+    return h0_pcg_grid(c->G + (long)c->nt * 3 * c->N, c->n, c->reg, b0, c->h3, r, tol, max_it, s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Two-level variant 2LInvH0 (Section 2 "Preconditioning", Algorithm "PC", */
+/* second function): H0 inverted on a grid of half the resolution.          */
+/* ------------------------------------------------------------------------ */
+
+/* Spectral restriction of ncomp fields from the fine grid nf to the coarse
+ * grid nc = nf/2: the coarse field keeps the fine Fourier coefficients of
+ * the wavenumbers |k_d| < nc_d/2 (the coarse Nyquist modes are dropped), so a
+ * band-limited field restricts to its samples on the coarse grid. */
+void or_restrict(const double *f, double *out, int ncomp, int n1, int n2, int n3)
+{
+    int nf[3] = {n1, n2, n3}, nc[3] = {n1 / 2, n2 / 2, n3 / 2};
+    long Nf = (long)n1 * n2 * n3, Nc = (long)nc[0] * nc[1] * nc[2];
+    for (int c = 0; c < ncomp; c++) {
+        cplx *F = forward_real(f + c * Nf, nf);
+        cplx *C = malloc(sizeof(cplx) * (size_t)Nc);
+        for (long q = 0; q < Nc; q++) {
+            int l[3], lf[3], keep = 1;
+            spectral_index(q, nc, l);
+            for (int d = 0; d < 3; d++) {
+                int k = (int)wavenumber(l[d], nc[d]);
+                if (2 * abs(k) == nc[d]) keep = 0;
+                lf[d] = (k + nf[d]) % nf[d];
+            }
+            C[q] = keep ? F[((long)lf[0] * nf[1] + lf[1]) * nf[2] + lf[2]] * ((double)Nc / (double)Nf) : 0.0;
+        }
+        inverse_real(C, out + c * Nc, nc);
+        free(C);
+        free(F);
+    }
+}
+
+/* Spectral prolongation (zero padding) of ncomp coarse fields on nc to the
+ * fine grid 2 nc: the coarse coefficients of |k_d| < nc_d/2 move to the same
+ * wavenumbers of the fine spectrum, every other fine coefficient is zero. */
+void or_prolong(const double *f, double *out, int ncomp, int n1c, int n2c, int n3c)
+{
+    int nc[3] = {n1c, n2c, n3c}, nf[3] = {2 * n1c, 2 * n2c, 2 * n3c};
+    long Nc = (long)n1c * n2c * n3c, Nf = 8 * Nc;
+    for (int c = 0; c < ncomp; c++) {
+        cplx *C = forward_real(f + c * Nc, nc);
+        cplx *F = calloc((size_t)Nf, sizeof(cplx));
+        for (long q = 0; q < Nc; q++) {
+            int l[3], lf[3], keep = 1;
+            spectral_index(q, nc, l);
+            for (int d = 0; d < 3; d++) {
+                int k = (int)wavenumber(l[d], nc[d]);
+                if (2 * abs(k) == nc[d]) keep = 0;
+                lf[d] = (k + nf[d]) % nf[d];
+            }
+            if (keep) F[((long)lf[0] * nf[1] + lf[1]) * nf[2] + lf[2]] = C[q] * ((double)Nf / (double)Nc);
+        }
+        inverse_real(F, out + c * Nf, nf);
+        free(F);
+        free(C);
+    }
+}
+
+/* s ~= 2LInvH0(r), the steps of Algorithm "PC" (second function):
+ *   s_f = (beta0 A)^{-1} r;  s_c = Restrict(s_f);
+ *   s_c <- PCG on H0_c s_c = Restrict(r) from s_c, preconditioned by
+ *          (beta0 A_c)^{-1}, H0_c built from Restrict(grad m(1)), relative
+ *          tolerance tol, at most max_it iterations;
+ *   s_f = Prolong(s_c) + HighPass(s_f),  HighPass(f) = f - Prolong(Restrict(f)).
+ * The fine grid must halve to a valid grid.  Returns the coarse iterations. */
+int or_ctx_2linvh0(const or_ctx *c, const double *r, double tol, int max_it, double *s)
+{
+    int nc[3] = {c->n[0] / 2, c->n[1] / 2, c->n[2] / 2};
+    long Mf = 3 * c->N, Mc = 3L * nc[0] * nc[1] * nc[2];
+    double b0 = h0_beta(c), h3c = 8.0 * c->h3;
+    double *sc = malloc(sizeof(double) * Mc);
+    double *rc = malloc(sizeof(double) * Mc);
+    double *Gc = malloc(sizeof(double) * Mc);
+    double *lo = malloc(sizeof(double) * Mf);
+    or_reg_inverse(r, s, 3, c->n[0], c->n[1], c->n[2], c->reg, b0);
+    or_restrict(s, sc, 3, c->n[0], c->n[1], c->n[2]);
+    or_restrict(r, rc, 3, c->n[0], c->n[1], c->n[2]);
+    or_restrict(c->G + (long)c->nt * 3 * c->N, Gc, 3, c->n[0], c->n[1], c->n[2]);
+    /* the high-pass part of s_f: s_f - Prolong(Restrict(s_f)) */
+    or_prolong(sc, lo, 3, nc[0], nc[1], nc[2]);
+    for (long i = 0; i < Mf; i++) s[i] -= lo[i];
+    int it = h0_pcg_grid(Gc, nc, c->reg, b0, h3c, rc, tol, max_it, sc);
+    or_prolong(sc, lo, 3, nc[0], nc[1], nc[2]);
+    for (long i = 0; i < Mf; i++) s[i] += lo[i];
+    free(sc); free(rc); free(Gc); free(lo);
+    return it;
+}
+
+/* the preconditioner M^{-1}: pc 0 = InvA, (beta A)^{-1}; pc 1 = InvH0, pc 2
+ * = 2LInvH0, with the inner tolerance tol_h0 and at most max_inner inner
+ * iterations.
  * Returns the inner iterations. */
 static int precondition(const or_ctx *c, const double *r, double *z, int pc, double tol_h0,
                         int max_inner)
 {
     if (pc == 1) return or_ctx_invh0(c, r, tol_h0, max_inner, z);
+    if (pc == 2) return or_ctx_2linvh0(c, r, tol_h0, max_inner, z);
     or_reg_inverse(r, z, 3, c->n[0], c->n[1], c->n[2], c->reg, c->beta);
     return 0;
 }

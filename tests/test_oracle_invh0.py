@@ -5,7 +5,10 @@ form, against the Gauss-Newton matvec at v = 0, against a construction with
 numpy's FFT at a nonzero velocity; the inner solve against a dense solve and
 its exact reduction to (beta0 A)^{-1} for a constant template; the outer PCG
 with InvH0 against the Krylov-optimal iterates of the H0^{-1}-preconditioned
-system."""
+system.  The two-level variant 2LInvH0: spectral restriction and prolongation
+against band-limited samples and a numpy construction, its reduction to
+(beta0 A)^{-1} for a constant template, and the whole step (restrict, dense
+coarse solve, prolong, high-pass) rebuilt with numpy."""
 import numpy as np
 import pytest
 
@@ -181,3 +184,126 @@ def test_invh0_needs_fewer_outer_iterations_than_inva():
     _, ih = P.pcg(-g, 200, 1e-3, pc="invh0", eps_h0=1e-3, max_inner=200)
     assert ih["iters"] < ia["iters"], (ih, ia)
     assert ih["rel_res"] <= 1e-3 and ia["rel_res"] <= 1e-3
+
+
+# ---- two-level variant 2LInvH0 (Algorithm "PC", second function) ------------
+
+
+def _np_restrict(f):
+    """numpy: fine Fourier coefficients of |k_d| < n_d/4 onto the half grid"""
+    shape = f.shape
+    nc = [n // 2 for n in shape]
+    F = np.fft.fftn(f)
+    kc = [np.fft.fftfreq(m, 1.0 / m).astype(int) for m in nc]
+    idx = np.ix_(*[k % n for k, n in zip(kc, shape)])
+    mask = np.ones(nc)
+    for d in range(3):
+        sl = [None, None, None]
+        sl[d] = slice(None)
+        mask = mask * (2 * np.abs(kc[d]) != nc[d])[tuple(sl)]
+    return np.fft.ifftn(F[idx] * mask * (np.prod(nc) / np.prod(shape))).real
+
+
+def _np_prolong(g):
+    shape = [2 * n for n in g.shape]
+    G = np.fft.fftn(g)
+    kc = [np.fft.fftfreq(m, 1.0 / m).astype(int) for m in g.shape]
+    mask = np.ones(g.shape)
+    for d in range(3):
+        sl = [None, None, None]
+        sl[d] = slice(None)
+        mask = mask * (2 * np.abs(kc[d]) != g.shape[d])[tuple(sl)]
+    F = np.zeros(shape, complex)
+    F[np.ix_(*[k % n for k, n in zip(kc, shape)])] = G * mask * (np.prod(shape) / np.prod(g.shape))
+    return np.fft.ifftn(F).real
+
+
+def test_restrict_and_prolong_sample_band_limited_fields():
+    shape = (16, 12, 20)
+    x = _grid(shape)
+    f = np.sin(x[0] + 2 * x[2]) + 0.3 * np.cos(2 * x[1] - x[0]) + 0.2  # |k_d| < n_d/4
+    xc = _grid(tuple(n // 2 for n in shape))
+    fc = np.sin(xc[0] + 2 * xc[2]) + 0.3 * np.cos(2 * xc[1] - xc[0]) + 0.2
+    assert np.abs(oracle.restrict(f) - fc).max() < 1e-13
+    assert np.abs(oracle.prolong(fc) - f).max() < 1e-13
+    assert np.abs(oracle.restrict(oracle.prolong(fc)) - fc).max() < 1e-13
+    v = np.stack([f, 2 * f, -f])
+    assert np.abs(oracle.restrict(v) - np.stack([fc, 2 * fc, -fc])).max() < 1e-13
+
+
+def test_high_pass_partition():
+    """P R is the projector on |k_d| < n_d/4: idempotent, and f - P R f keeps no
+    such mode (numpy FFT); the oracle's R and P equal the numpy construction."""
+    shape = (16, 16, 12)
+    rng = np.random.default_rng(760)
+    f = rng.standard_normal(shape)
+    lo = oracle.prolong(oracle.restrict(f))
+    assert np.abs(oracle.prolong(oracle.restrict(lo)) - lo).max() < 1e-12
+    F = np.fft.fftn(f - lo)
+    k = np.meshgrid(*[np.fft.fftfreq(n, 1.0 / n) for n in shape], indexing="ij")
+    low = (np.abs(k[0]) < 4) & (np.abs(k[1]) < 4) & (np.abs(k[2]) < 3)
+    assert np.abs(F[low]).max() < 1e-10
+    assert np.abs(oracle.restrict(f) - _np_restrict(f)).max() < 1e-12
+    g = rng.standard_normal((8, 8, 6))
+    assert np.abs(oracle.prolong(g) - _np_prolong(g)).max() < 1e-12
+
+
+def test_two_level_is_inva_for_a_constant_template():
+    shape = (16, 16, 16)
+    P = oracle.Problem(shape, 2, reg=2, beta=1e-3)
+    P.set_images(np.full(shape, 0.3), np.full(shape, 0.7))
+    P.set_velocity(synth.bandlimited_vector(shape, 2, 770, max_disp=1.0))
+    r = synth.bandlimited_vector(shape, 3, 771)
+    s, it = P.two_level_invh0(r, 1e-10, 100)
+    assert it == 0
+    assert np.abs(s - oracle.reg_inverse(r, 2, 5e-2)).max() < 1e-12 * np.abs(s).max()
+
+
+def test_two_level_matches_numpy_construction():
+    """16^3 fine, 8^3 coarse: restriction, dense coarse H0 solve, prolongation
+    and high-pass all by numpy, against the oracle run to convergence."""
+    shape = (16, 16, 16)
+    nt, beta, reg = 2, 1e-2, 1
+    m0 = synth.sin2_template(shape, 3, 780)
+    P = oracle.Problem(shape, nt, reg=reg, beta=beta)
+    P.set_images(m0, m0)
+    P.set_velocity(synth.bandlimited_vector(shape, 2, 781, max_disp=1.0))
+    r = synth.bandlimited_vector(shape, 4, 782)
+    G1 = P.get("G", nt)
+    Gc = np.stack([_np_restrict(g) for g in G1])
+    rc = np.stack([_np_restrict(c) for c in r])
+    cshape = Gc.shape[1:]
+    n3 = 3 * int(np.prod(cshape))
+    H0c = _dense(lambda e: _h0_numpy(e.reshape((3,) + cshape), Gc, beta, reg).ravel(), n3)
+    sc = np.linalg.solve(H0c, rc.ravel()).reshape((3,) + cshape)
+    sf = _reg_inverse_numpy(r, reg, max(beta, 5e-2))
+    hp = sf - np.stack([_np_prolong(_np_restrict(c)) for c in sf])
+    want = np.stack([_np_prolong(c) for c in sc]) + hp
+    s, it = P.two_level_invh0(r, 1e-13, 500)
+    assert 0 < it < 500
+    assert rel_l2(s, want) < 1e-9
+
+
+def _reg_inverse_numpy(s, reg, beta):
+    shape = s.shape[1:]
+    k = np.meshgrid(*[np.fft.fftfreq(n, 1.0 / n) for n in shape], indexing="ij")
+    a = (k[0] ** 2 + k[1] ** 2 + k[2] ** 2) ** reg
+    inv = np.where(a == 0, 1.0 / beta, 1.0 / (beta * np.where(a == 0, 1.0, a)))
+    return np.stack([np.fft.ifftn(inv * np.fft.fftn(c)).real for c in s])
+
+
+def test_pcg_with_two_level_converges():
+    shape = (32, 32, 32)
+    m0 = synth.blob_image(shape, 10, 790)
+    vtrue = synth.bandlimited_vector(shape, 3, 791, max_disp=2.0)
+    P = oracle.Problem(shape, 2, reg=2, beta=1e-3)
+    P.set_images(m0, m0)
+    P.set_velocity(vtrue)
+    m1 = P.transport(m0)[-1]
+    P.set_images(m0, m1)
+    P.set_velocity(0.5 * vtrue)
+    g = P.gradient()
+    _, ia = P.pcg(-g, 200, 1e-2)
+    _, i2 = P.pcg(-g, 200, 1e-2, pc="2linvh0", eps_h0=1e-3, max_inner=200)
+    assert i2["rel_res"] <= 1e-2 and i2["inner"] > 0
+    assert i2["iters"] <= ia["iters"], (i2, ia)
