@@ -404,7 +404,7 @@ def main():
             res_nt[nt_]["newton_info"] = {k: info[k] for k in ("pcg_iters", "rel_res", "gnorm")}
             # Newton step to a fixed relative residual with each preconditioner
             pcs = {}
-            for kind in ("inva", "invh0"):
+            for kind in ("inva", "invh0", "2linvh0"):
                 plan.set_preconditioner(kind, eps_h0=1e-3, max_inner=50)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()

@@ -250,15 +250,18 @@ lddmm_status lddmm_batch_gn_iterate(lddmm_batch *batch, int32_t max_pcg, double 
  * LDDMM_TUNE_CACHE names a file, in that file.  Synchronises the stream. */
 lddmm_status lddmm_autotune(lddmm_plan *plan);
 /* Preconditioner of the PCG in lddmm_newton_step and lddmm_gn_iterate
- * (Section 2 "Preconditioning"): kind 0 = InvA, (beta A)^{-1} (the default);
- * kind 1 = InvH0, an inner PCG solve of eq. h0-pc,
- *   (beta0 A + grad m (x) grad m) s = r,  beta0 = max(beta, 5e-2),
- * with m the deformed template m(1) at the current velocity, preconditioned
- * by (beta0 A)^{-1}, started from (beta0 A)^{-1} r, stopped at
- * ||r - H0 s|| <= eps_h0 * eps_K * ||r|| (eps_K the outer tolerance) or after
- * max_inner iterations (Algorithm "PC", first variant).  InvH0 allocates four
- * more 3N-float vectors on first use.  EINVAL for kind outside 0..1, eps_h0
- * not in (0, 1) or max_inner < 1.  The batched iteration supports InvA only. */
+ * (Section 2 "Preconditioning", Algorithm "PC"):
+ *   kind 0 = InvA, (beta A)^{-1} (the default);
+ *   kind 1 = InvH0, an inner PCG solve of eq. h0-pc,
+ *     (beta0 A + grad m (x) grad m) s = r,  beta0 = max(beta, 5e-2),
+ *   with m the deformed template m(1) at the current velocity,
+ *   preconditioned by (beta0 A)^{-1}, started from (beta0 A)^{-1} r, stopped
+ *   at ||r - H0 s|| <= eps_h0 * eps_K * ||r|| (eps_K the outer tolerance) or
+ *   after max_inner iterations; four more 3N-float vectors on first use;
+ *   kind 2 = 2LInvH0, the same solve on the grid of half the resolution
+ *   (lddmm_apply_2linvh0 below); every n_d divisible by 4 and at least 16.
+ * EINVAL for kind outside 0..2, eps_h0 not in (0, 1), max_inner < 1, or a
+ * grid kind 2 cannot halve.  The batched iteration supports InvA only. */
 lddmm_status lddmm_set_preconditioner(lddmm_plan *plan, int32_t kind, double eps_h0, int32_t max_inner);
 /* out = H0 s (eq. h0-pc, the operator above); 3N floats each.  ESTATE before
  * a velocity is set. */
@@ -268,6 +271,16 @@ lddmm_status lddmm_apply_h0(lddmm_plan *plan, const float *s, float *out);
  * max_inner >= 0 iterations; *iters (may be NULL) receives the iterations. */
 lddmm_status lddmm_apply_invh0(lddmm_plan *plan, const float *r, double tol, int32_t max_inner, float *s,
                                int32_t *iters);
+/* s ~= 2LInvH0(r) (Algorithm "PC", second function): s_f = (beta0 A)^{-1} r;
+ * the H0 system restricted to the half grid (Fourier coefficients of
+ * |k_d| < n_d/4, the coarse Nyquist modes dropped; grad m(1) restricted the
+ * same way) solved by the inner PCG from the restricted s_f with tolerance
+ * tol and at most max_inner iterations; s = Prolong(s_c) + s_f -
+ * Prolong(Restrict(s_f)).  The half-grid plan (about 1/8 of the workspace) is
+ * created on first use.  EINVAL unless every n_d is divisible by 4 and at
+ * least 16; *iters (may be NULL) receives the coarse iterations. */
+lddmm_status lddmm_apply_2linvh0(lddmm_plan *plan, const float *r, double tol, int32_t max_inner, float *s,
+                                 int32_t *iters);
 /* Override the gather strategy of the interpolation kernels: 0 direct
  * (one thread per point, stencil loads through L1/L2), 1 and 2 LDS-staged
  * boxes for tiles of 2x4x64 and 4x4x64 points (points whose stencil leaves

@@ -70,6 +70,7 @@ def lib():
             "lddmm_set_preconditioner": (st, [p, i32, d, i32]),
             "lddmm_apply_h0": (st, [p, p, p]),
             "lddmm_apply_invh0": (st, [p, p, d, i32, p, P(i32)]),
+            "lddmm_apply_2linvh0": (st, [p, p, d, i32, p, P(i32)]),
             "lddmm_newton_step": (st, [p, i32, d, p, P(NewtonInfo)]),
             "lddmm_gn_iterate": (st, [p, i32, d, p, P(NewtonInfo)]),
             "lddmm_transport_forward": (st, [p, p, p, p, p]),
@@ -198,6 +199,13 @@ def lddmm_apply_invh0(plan, r, tol, max_inner, s):
     it = ctypes.c_int32(0)
     _check(lib().lddmm_apply_invh0(plan, _ptr(r), float(tol), int(max_inner), _ptr(s), ctypes.byref(it)),
            "apply_invh0")
+    return it.value
+
+
+def lddmm_apply_2linvh0(plan, r, tol, max_inner, s):
+    it = ctypes.c_int32(0)
+    _check(lib().lddmm_apply_2linvh0(plan, _ptr(r), float(tol), int(max_inner), _ptr(s), ctypes.byref(it)),
+           "apply_2linvh0")
     return it.value
 
 

@@ -161,6 +161,7 @@ static void plan_free(lddmm_plan *P)
     if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
     if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     if (P->h0buf) (void)hipFree(P->h0buf);
+    if (P->coarse) (void)lddmm_plan_destroy(P->coarse);
     if (P->arena) (void)hipFree(P->arena);
     if (P->hscal) (void)hipHostFree(P->hscal);
     for (auto &pr : P->timing.pool) {
@@ -218,6 +219,7 @@ void velocity_state(lddmm_plan *P)
 {
     const long N = P->N;
     const int nt = P->nt;
+    ++P->vel_gen;
     launch_departure(P, P->v, P->dX, P->dXa);
     copy_dev(P, P->m, P->m0, N);
     for (int j = 0; j < nt; ++j)
@@ -409,11 +411,83 @@ static int invh0_impl(lddmm_plan *P, const float *r, float *s, double tol, int m
     return it;
 }
 
+// ---- two-level variant 2LInvH0 (Algorithm "PC", second function) ---------
+
+static bool halves(const lddmm_config &c)
+{
+    for (int d = 0; d < 3; ++d)
+        if (c.n[d] % 4 != 0 || c.n[d] < 16) return false;
+    return true;
+}
+
+static lddmm_plan *coarse_plan(lddmm_plan *P)
+{
+    if (!P->coarse) {
+        lddmm_config c = P->cfg;
+        for (int d = 0; d < 3; ++d) c.n[d] = P->cfg.n[d] / 2;
+        lddmm_plan *C = nullptr;
+        const lddmm_status st = lddmm_plan_create(&c, (void *)P->stream, &C);
+        if (st != LDDMM_OK) fail(st, std::string("half-grid plan: ") + lddmm_last_error());
+        P->coarse = C;
+    }
+    return P->coarse;
+}
+
+// three fields: out (grid of C) = Restrict / Prolong of in (grid of F), by
+// FP32 transforms on both plans and spectral resampling in between
+static void resample3(lddmm_plan *F, const float *in, lddmm_plan *C, float *out)
+{
+    RealIn ri{};
+    for (int c = 0; c < 3; ++c) ri.p[c] = in + c * F->N;
+    r2c_fields(F, ri, 3, 0, false);
+    x2_pass(F, 0, 3, false, false);
+    x1_pass(F, 0, 3, false, false);
+    spectral_resample(F, 0, C, 0, 3);
+    x1_pass(C, 0, 3, true, false);
+    x2_pass(C, 0, 3, true, false);
+    RealOut ro{};
+    for (int c = 0; c < 3; ++c) ro.p[c] = out + c * C->N;
+    c2r_fields(C, 0, 3, ro, (float)(1.0 / (double)C->N));
+}
+
+// s ~= 2LInvH0(r).  The paper's steps s_f = (b0 A)^{-1} r, s_c = R s_f, coarse
+// PCG on H0_c s_c = R r from s_c, s_f = P s_c + (s_f - P R s_f) are run as
+// s_f = (b0 A)^{-1} r + P (s_c - s_c0) with s_c0 = (b0 A_c)^{-1} R r, the same
+// coarse start: R and (b0 A)^{-1} commute (the same symbol at every kept
+// wavenumber), so R s_f = s_c0 and one fine restriction is saved.  The coarse
+// plan holds R grad m(1) in its grad m_{N_t} slot, refreshed per velocity.
+static int twolevel_impl(lddmm_plan *P, const float *r, float *s, double tol, int max_it)
+{
+    lddmm_plan *C = coarse_plan(P);
+    const long M = 3 * P->N, Mc = 3 * C->N;
+    if (P->coarse_gen != P->vel_gen) {
+        resample3(P, P->G + (long)P->nt * 3 * P->N, C, C->G + (long)C->nt * 3 * C->N);
+        P->coarse_gen = P->vel_gen;
+    }
+    float *rc = C->pr, *sc = C->px, *sc0 = C->pz;  // the half-grid plan runs no PCG of its own
+    float *tmp = h0_vectors(P);
+    {
+        Beta0Scope b0(P);
+        inv_reg(P, r, s);
+    }
+    resample3(P, r, C, rc);
+    {
+        Beta0Scope b0(C);
+        inv_reg(C, rc, sc0);
+    }
+    const int it = invh0_impl(C, rc, sc, tol, max_it);
+    axpby(C, Mc, 1.f, sc, -1.f, sc0, sc);
+    resample3(C, sc, P, tmp);
+    axpby(P, M, 1.f, s, 1.f, tmp, s);
+    return it;
+}
+
 // the preconditioner M^{-1} r of the outer PCG (tol_outer: its eps_K);
 // returns the inner iterations
 static int precondition(lddmm_plan *P, const float *r, float *z, double tol_outer)
 {
     if (P->pc_kind == 1) return invh0_impl(P, r, z, P->pc_eps_h0 * tol_outer, P->pc_max_inner);
+    if (P->pc_kind == 2) return twolevel_impl(P, r, z, P->pc_eps_h0 * tol_outer, P->pc_max_inner);
     inv_reg(P, r, z);
     return 0;
 }
@@ -1022,7 +1096,9 @@ lddmm_status lddmm_set_preconditioner(lddmm_plan *P, int32_t kind, double eps_h0
 {
     return guard([&] {
         need(P, "plan");
-        if (kind < 0 || kind > 1) fail(LDDMM_EINVAL, "kind must be 0 (InvA) or 1 (InvH0)");
+        if (kind < 0 || kind > 2) fail(LDDMM_EINVAL, "kind must be 0 (InvA), 1 (InvH0) or 2 (2LInvH0)");
+        if (kind == 2 && !halves(P->cfg))
+            fail(LDDMM_EINVAL, "2LInvH0 needs every grid size divisible by 4 and at least 16");
         if (!(eps_h0 > 0.0 && eps_h0 < 1.0)) fail(LDDMM_EINVAL, "eps_h0 must lie in (0, 1)");
         if (max_inner < 1) fail(LDDMM_EINVAL, "max_inner must be >= 1");
         P->pc_kind = kind;
@@ -1054,6 +1130,22 @@ lddmm_status lddmm_apply_invh0(lddmm_plan *P, const float *r, double tol, int32_
         need_full(P);
         need_velocity(P);
         const int it = invh0_impl(P, r, s, tol, max_inner);
+        if (iters) *iters = it;
+    });
+}
+
+lddmm_status lddmm_apply_2linvh0(lddmm_plan *P, const float *r, double tol, int32_t max_inner, float *s,
+                                 int32_t *iters)
+{
+    return guard([&] {
+        need(P, "plan");
+        need_dev(r, "r");
+        need_dev(s, "s");
+        if (!(tol >= 0.0) || max_inner < 0) fail(LDDMM_EINVAL, "tol must be >= 0 and max_inner >= 0");
+        if (!halves(P->cfg)) fail(LDDMM_EINVAL, "2LInvH0 needs every grid size divisible by 4 and at least 16");
+        need_full(P);
+        need_velocity(P);
+        const int it = twolevel_impl(P, r, s, tol, max_inner);
         if (iters) *iters = it;
     });
 }

@@ -2309,6 +2309,53 @@ std::string tuning_report(const lddmm_plan *P)
     return o.str();
 }
 
+// Spectral resampling between a grid and its half (two-level preconditioner):
+// FP32 spectra in the private layout (main [n1][n2][n3/2], then the Nyquist
+// plane).  Every destination coefficient of wavenumber k takes the source
+// coefficient of the same k times scale when |k_d| < nc_d/2 on every axis of
+// the coarse grid nc (coarse Nyquist modes dropped), else zero.
+__global__ void k_resample(const float2 *__restrict__ src, int s1, int s2, int sm3, float2 *__restrict__ dst,
+                           int d1, int d2, int dm3, int c1, int c2, int cm3, float scale)
+{
+    const long nrow = (long)d1 * d2, total = nrow * (dm3 + 1);
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        long row;
+        int k;
+        if (i < nrow * dm3) {
+            row = i / dm3;
+            k = (int)(i - row * dm3);
+        } else {
+            row = i - nrow * dm3;
+            k = dm3;
+        }
+        const int l1 = (int)(row / d2), l2 = (int)(row - (long)l1 * d2);
+        const int k1 = 2 * l1 <= d1 ? l1 : l1 - d1, k2 = 2 * l2 <= d2 ? l2 : l2 - d2;
+        float2 v = make_float2(0.f, 0.f);
+        if (2 * abs(k1) < c1 && 2 * abs(k2) < c2 && k < cm3) {
+            const int m1 = k1 < 0 ? k1 + s1 : k1, m2 = k2 < 0 ? k2 + s2 : k2;
+            const float2 u = src[((long)m1 * s2 + m2) * sm3 + k];  // k < cm3 <= sm3: main array
+            v = make_float2(scale * u.x, scale * u.y);
+        }
+        dst[i < nrow * dm3 ? row * dm3 + k : nrow * dm3 + row] = v;
+    }
+}
+
+void spectral_resample(lddmm_plan *S, int s0, lddmm_plan *D, int d0, int count)
+{
+    const FftCtx &FS = S->fft, &FD = D->fft;
+    const bool down = FD.n1 < FS.n1;
+    const FftCtx &FC = down ? FD : FS;  // the coarse grid
+    const float scale = (float)((double)FD.n1 * FD.n2 * FD.n3 / ((double)FS.n1 * FS.n2 * FS.n3));
+    Scope sc(D, K_PACK);
+    for (int f = 0; f < count; ++f) {
+        const float2 *src = reinterpret_cast<const float2 *>(S->spec + (long)(s0 + f) * S->slot_bytes);
+        float2 *dst = reinterpret_cast<float2 *>(D->spec + (long)(d0 + f) * D->slot_bytes);
+        hipLaunchKernelGGL(k_resample, dim3(1024), dim3(256), 0, D->stream, src, FS.n1, FS.n2, FS.m3, dst, FD.n1,
+                           FD.n2, FD.m3, FC.n1, FC.n2, FC.m3, scale);
+    }
+    check_hip(hipGetLastError(), "k_resample");
+}
+
 void pack_standard(lddmm_plan *P, int slot, float2 *dst)
 {
     FftCtx &F = P->fft;

@@ -68,6 +68,9 @@ struct lddmm_plan {
     int pc_kind = 0, pc_max_inner = 50;
     double pc_eps_h0 = 1e-3;
     float *h0buf = nullptr;   // InvH0 inner PCG vectors r, z, p, q (4 x 3N), on first use
+    lddmm_plan *coarse = nullptr;  // 2LInvH0: the plan of the half grid, on first use
+    unsigned long vel_gen = 0;     // velocity states computed (grad m(1) generations)
+    unsigned long coarse_gen = 0;  // vel_gen whose restricted grad m(1) the coarse plan holds
     double beta_sym = 0.0;    // > 0: beta of the (beta A)^{-1} symbol instead of cfg.beta
     int device = 0;
     long N = 0;
@@ -147,6 +150,10 @@ void x1_symbol(lddmm_plan *P, int op, int spec_in, int spec_out, int nbatch, int
 // inputs were already run by spectral_forward
 void spectral_apply(lddmm_plan *P, int op, const std::vector<const float *> &in,
                     const std::vector<float *> &out, int fwd_done = 0);
+// FP32 spectra of slots [s0, s0+count) of plan S resampled into slots
+// [d0, ..) of plan D, a grid of half or twice the size (restriction /
+// prolongation by truncation / zero padding of the Fourier coefficients)
+void spectral_resample(lddmm_plan *S, int s0, lddmm_plan *D, int d0, int count);
 // forward x3 and x2 passes of the first count inputs of one field set, into
 // the slots spectral_apply uses for them
 void spectral_forward(lddmm_plan *P, int op, const std::vector<const float *> &in, int count);

@@ -80,8 +80,9 @@ class Plan:
         return s
 
     def set_preconditioner(self, kind, eps_h0=1e-3, max_inner=50):
-        """kind "inva" ((beta A)^-1) or "invh0" (inner PCG on eq. h0-pc)"""
-        L.lddmm_set_preconditioner(self._h, {"inva": 0, "invh0": 1}[kind], eps_h0, max_inner)
+        """kind "inva" ((beta A)^-1), "invh0" (inner PCG on eq. h0-pc) or
+        "2linvh0" (the same on the half grid)"""
+        L.lddmm_set_preconditioner(self._h, {"inva": 0, "invh0": 1, "2linvh0": 2}[kind], eps_h0, max_inner)
 
     def apply_h0(self, s, out=None):
         o = out if out is not None else self._vector()
@@ -91,6 +92,11 @@ class Plan:
     def apply_invh0(self, r, tol, max_inner, out=None):
         s = out if out is not None else self._vector()
         it = L.lddmm_apply_invh0(self._h, self._in(r, True), tol, max_inner, s)
+        return s, it
+
+    def apply_2linvh0(self, r, tol, max_inner, out=None):
+        s = out if out is not None else self._vector()
+        it = L.lddmm_apply_2linvh0(self._h, self._in(r, True), tol, max_inner, s)
         return s, it
 
     def newton_step(self, max_pcg, rtol=0.0, out=None, allow_notconv=False):

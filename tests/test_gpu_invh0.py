@@ -1,7 +1,8 @@
-"""GPU parity of the zero-velocity Hessian preconditioner InvH0 (Section 2
-"Preconditioning", eq. h0-pc, Algorithm "PC") against the FP64 oracle: the H0
-operator, the inner PCG solve at a fixed iteration count and at a tolerance,
-and a Newton step whose PCG uses it; argument checks."""
+"""GPU parity of the zero-velocity Hessian preconditioners InvH0 and 2LInvH0
+(Section 2 "Preconditioning", eq. h0-pc, Algorithm "PC") against the FP64
+oracle: the H0 operator, the inner PCG solve at a fixed iteration count and at
+a tolerance, the two-level step, Newton steps whose PCG uses them; argument
+checks."""
 import numpy as np
 import pytest
 
@@ -88,7 +89,7 @@ def test_invh0_cuts_outer_iterations():
 
 def test_preconditioner_arguments():
     P, _ = _setup(shape=(16, 16, 16), nt=2)
-    for args in [(2, 1e-3, 10), (1, 0.0, 10), (1, 1.0, 10), (1, 1e-3, 0), (-1, 1e-3, 10)]:
+    for args in [(3, 1e-3, 10), (1, 0.0, 10), (1, 1.0, 10), (1, 1e-3, 0), (-1, 1e-3, 10)]:
         with pytest.raises(LddmmError) as e:
             L.lddmm_set_preconditioner(P._h, *args)
         assert e.value.status == L.EINVAL
@@ -110,3 +111,45 @@ def test_batch_rejects_invh0():
         Bt.gn_iterate(vb, 2, 0.0)
     assert e.value.status == L.EUNSUPPORTED
     Bt.close()
+
+
+def test_two_level_matches_oracle():
+    say("2LInvH0 step")
+    P, ref = _setup(shape=(32, 24, 40), nt=3, reg=2, beta=1e-3)
+    r = incremental(P.shape, 1520)
+    s, it = P.apply_2linvh0(to_dev(r), 0.0, 6)
+    s_ref, it_ref = ref.two_level_invh0(synth.f64(r), 0.0, 6)
+    assert it == it_ref == 6
+    e = rel(to_np(s), s_ref)
+    say(f"2L, 6 coarse iterations: rel {e:.2e}")
+    assert e < 1e-4
+    # the coarse restriction of grad m(1) follows a new velocity
+    v2 = to_dev(synth.f32(0.5 * synth.bandlimited_vector(P.shape, 3, 1521, max_disp=2.0)))
+    P.set_velocity(v2)
+    ref.set_velocity(synth.f64(to_np(v2)))
+    s, _ = P.apply_2linvh0(to_dev(r), 0.0, 6)
+    s_ref, _ = ref.two_level_invh0(synth.f64(r), 0.0, 6)
+    assert rel(to_np(s), s_ref) < 1e-4
+
+
+def test_newton_step_with_two_level_matches_oracle_pcg():
+    say("Newton step, PCG with 2LInvH0")
+    P, ref = _setup(shape=(32, 32, 32), nt=4, reg=2, beta=5e-4)
+    P.set_preconditioner("2linvh0", eps_h0=1e-3, max_inner=8)
+    vt, info = P.newton_step(4, 1e-12)
+    vt_ref, pinfo = ref.pcg(-ref.gradient(), 4, 1e-12, pc="2linvh0", eps_h0=1e-3, max_inner=8)
+    assert info["pcg_iters"] == pinfo["iters"] == 4
+    assert info["inner_iters"] == pinfo["inner"] == 5 * 8
+    e = rel(to_np(vt), vt_ref)
+    say(f"newton step (2L) rel {e:.2e}")
+    assert e < 1e-4
+
+
+def test_two_level_needs_a_halving_grid():
+    P, _ = _setup(shape=(24, 20, 30), nt=2)
+    with pytest.raises(LddmmError) as e:
+        P.set_preconditioner("2linvh0")
+    assert e.value.status == L.EINVAL
+    with pytest.raises(LddmmError) as e:
+        P.apply_2linvh0(to_dev(incremental(P.shape, 1530)), 0.0, 2)
+    assert e.value.status == L.EINVAL
