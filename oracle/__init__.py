@@ -51,6 +51,9 @@ def lib():
             "or_ctx_gn_iterate": (i, [p, i, d, p, p]),
             "or_ctx_h0_apply": (None, [p, p, p]),
             "or_restrict": (None, [p, p, i, i, i, i]),
+            "or_fd8_grad": (None, [p, p, i, i, i]),
+            "or_fd8_div": (None, [p, p, i, i, i]),
+            "or_ctx_set_fd8": (None, [p, i]),
             "or_prolong": (None, [p, p, i, i, i, i]),
             "or_ctx_2linvh0": (i, [p, p, d, i, p]),
             "or_ctx_invh0": (i, [p, p, d, i, p]),
@@ -149,6 +152,22 @@ def departure(v, nt):
     return X, Xa
 
 
+def fd8_grad(f):
+    """Eighth-order central-difference gradient (periodic), [3] stack out."""
+    a, pa = _c(f)
+    out = np.empty((3,) + a.shape)
+    lib().or_fd8_grad(pa, out.ctypes.data_as(ctypes.c_void_p), *a.shape)
+    return out
+
+
+def fd8_div(v):
+    """Eighth-order central-difference divergence of a [3] stack."""
+    a, pa = _c(v)
+    out = np.empty(a.shape[1:])
+    lib().or_fd8_div(pa, out.ctypes.data_as(ctypes.c_void_p), *a.shape[1:])
+    return out
+
+
 def restrict(f):
     """Spectral restriction of a field (or [3] stack) to half the resolution
     (Algorithm "PC", Restrict): coarse Nyquist modes dropped."""
@@ -185,7 +204,7 @@ def inner(a, b, h3):
 class Problem:
     """One registration problem: grid, N_t, regularisation, images, velocity."""
 
-    def __init__(self, shape, nt, reg=1, beta=1e-2, leray=False):
+    def __init__(self, shape, nt, reg=1, beta=1e-2, leray=False, fd8=False):
         self.shape = tuple(int(s) for s in shape)
         self.nt = int(nt)
         self.reg = int(reg)
@@ -195,6 +214,8 @@ class Problem:
         self.h3 = float(np.prod([2 * np.pi / n for n in self.shape]))
         self._ctx = lib().or_ctx_create(*self.shape, self.nt, self.reg, self.beta,
                                         int(self.leray))
+        self.fd8 = bool(fd8)
+        lib().or_ctx_set_fd8(self._ctx, int(self.fd8))
 
     def __del__(self):
         if getattr(self, "_ctx", None) and _lib is not None:

@@ -28,7 +28,9 @@
  *   h^3-weighted inner products; Armijo with c1 = 1e-4, halving, 10 tries;
  *   InvH0: H0 without the Leray projector (as printed), beta0 = max(beta,
  *   5e-2) in H0 and in its inner preconditioner, inner start (beta0 A)^{-1} r,
- *   inner stop relative to ||r||, tolerance eps_H0 times the outer tolerance.
+ *   inner stop relative to ||r||, tolerance eps_H0 times the outer tolerance;
+ *   FD8: the standard eighth-order central stencil (coefficients 4/5, -1/5,
+ *   4/105, -1/280), used for every first derivative when selected.
  */
 #include <complex.h>
 #include <math.h>
@@ -242,6 +244,54 @@ void or_spectral_div(const double *v, double *out, int n1, int n2, int n3)
     free(S);
 }
 
+/* Eighth-order central differences for first derivatives (Section 3.2, the
+ * FD kernel that replaces the spectral gradient and divergence): on a
+ * periodic axis of spacing h,
+ *   df/dx ~= (1/h) sum_{j=1..4} c_j (f(x + j h) - f(x - j h)),
+ *   c = (4/5, -1/5, 4/105, -1/280),
+ * the unique antisymmetric 9-point stencil exact for polynomials of degree 8. */
+static const double fd8_c[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+
+static double fd8_axis(const double *f, const int n[3], int i, int j, int k, int d)
+{
+    double s = 0.0, h = 2.0 * OR_PI / n[d];
+    for (int q = 1; q <= 4; q++) {
+        int ip = i, jp = j, kp = k, im = i, jm = j, km = k;
+        if (d == 0) { ip = (i + q) % n[0]; im = (i - q + n[0]) % n[0]; }
+        if (d == 1) { jp = (j + q) % n[1]; jm = (j - q + n[1]) % n[1]; }
+        if (d == 2) { kp = (k + q) % n[2]; km = (k - q + n[2]) % n[2]; }
+        s += fd8_c[q - 1] * (f[((long)ip * n[1] + jp) * n[2] + kp] - f[((long)im * n[1] + jm) * n[2] + km]);
+    }
+    return s / h;
+}
+
+void or_fd8_grad(const double *f, double *g, int n1, int n2, int n3)
+{
+    int n[3] = {n1, n2, n3};
+    long N = (long)n1 * n2 * n3;
+#pragma omp parallel for
+    for (int i = 0; i < n1; i++)
+        for (int j = 0; j < n2; j++)
+            for (int k = 0; k < n3; k++) {
+                long p = ((long)i * n2 + j) * n3 + k;
+                for (int d = 0; d < 3; d++) g[d * N + p] = fd8_axis(f, n, i, j, k, d);
+            }
+}
+
+void or_fd8_div(const double *v, double *out, int n1, int n2, int n3)
+{
+    int n[3] = {n1, n2, n3};
+    long N = (long)n1 * n2 * n3;
+#pragma omp parallel for
+    for (int i = 0; i < n1; i++)
+        for (int j = 0; j < n2; j++)
+            for (int k = 0; k < n3; k++) {
+                long p = ((long)i * n2 + j) * n3 + k;
+                out[p] = fd8_axis(v, n, i, j, k, 0) + fd8_axis(v + N, n, i, j, k, 1) +
+                         fd8_axis(v + 2 * N, n, i, j, k, 2);
+            }
+}
+
 /* out_c = A v_c for each component (ncomp = 1 or 3) */
 void or_reg_apply(const double *v, double *out, int ncomp, int n1, int n2, int n3, int reg)
 {
@@ -422,7 +472,28 @@ typedef struct {
     double *delta_a;      /* div v at Xa */
     int have_images, have_velocity;
     double g0norm;        /* norm of the first gradient after set_images */
+    int fd8;              /* first derivatives: 0 spectral, 1 eighth-order FD */
 } or_ctx;
+
+/* grad of a scalar and div of a vector field with the context's scheme */
+static void ctx_grad(const or_ctx *c, const double *f, double *g)
+{
+    if (c->fd8)
+        or_fd8_grad(f, g, c->n[0], c->n[1], c->n[2]);
+    else
+        or_spectral_grad(f, g, c->n[0], c->n[1], c->n[2]);
+}
+
+static void ctx_div(const or_ctx *c, const double *v, double *out)
+{
+    if (c->fd8)
+        or_fd8_div(v, out, c->n[0], c->n[1], c->n[2]);
+    else
+        or_spectral_div(v, out, c->n[0], c->n[1], c->n[2]);
+}
+
+/* choose the first-derivative scheme; takes effect at the next velocity */
+void or_ctx_set_fd8(or_ctx *c, int on) { c->fd8 = on ? 1 : 0; }
 
 or_ctx *or_ctx_create(int n1, int n2, int n3, int nt, int reg, double beta, int leray)
 {
@@ -497,9 +568,8 @@ void or_ctx_set_velocity(or_ctx *c, const double *v)
     memcpy(c->v, v, sizeof(double) * 3 * N);
     or_departure(c->v, c->n[0], c->n[1], c->n[2], c->nt, c->X, c->Xa);
     solve_state(c, c->m0, c->m);
-    for (int j = 0; j <= c->nt; j++)
-        or_spectral_grad(c->m + j * N, c->G + (long)j * 3 * N, c->n[0], c->n[1], c->n[2]);
-    or_spectral_div(c->v, c->delta, c->n[0], c->n[1], c->n[2]);
+    for (int j = 0; j <= c->nt; j++) ctx_grad(c, c->m + j * N, c->G + (long)j * 3 * N);
+    ctx_div(c, c->v, c->delta);
     or_interp(c->delta, 1, c->n[0], c->n[1], c->n[2], c->Xa, N, c->delta_a);
     c->have_velocity = 1;
 }
@@ -1017,8 +1087,7 @@ void or_ctx_transport_vjp(const or_ctx *c, const double *m0, const double *gout,
     tmp.m = malloc(sizeof(double) * (nt + 1) * N);
     tmp.G = malloc(sizeof(double) * (nt + 1) * 3 * N);
     solve_state(&tmp, m0, tmp.m);
-    for (int j = 0; j <= nt; j++)
-        or_spectral_grad(tmp.m + j * N, tmp.G + (long)j * 3 * N, c->n[0], c->n[1], c->n[2]);
+    for (int j = 0; j <= nt; j++) ctx_grad(c, tmp.m + j * N, tmp.G + (long)j * 3 * N);
     double *lam = malloc(sizeof(double) * (nt + 1) * N);
     or_ctx_adjoint(&tmp, gout, lam);
     memcpy(grad_m0, lam, sizeof(double) * N);
