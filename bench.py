@@ -415,6 +415,32 @@ def main():
                 log(f"newton step rtol 1e-2, {kind}: {pcs[kind]}")
             plan.set_preconditioner("inva")
             res_nt[nt_]["newton_preconditioners"] = pcs
+            # the eighth-order FD first derivatives (Section 3.2) in a second plan:
+            # per-velocity precompute, derivative kernel time, scheme difference
+            g_spec, _ = plan.gradient()
+            g_spec = g_spec.clone()
+            fplan = Plan(n, nt_, reg=2, beta=5e-4, leray=True, device=dev, fd8=True)
+            fplan.autotune()
+            fplan.set_images(m0d, m1d)
+            fplan.set_velocity(vd)
+            torch.cuda.synchronize()
+            fplan.set_timing(True)
+            t0 = time.perf_counter()
+            fplan.set_velocity(vd)
+            torch.cuda.synchronize()
+            pre_fd8 = time.perf_counter() - t0
+            kt8 = fplan.timing()
+            g_fd8, _ = fplan.gradient()
+            res_nt[nt_]["fd8"] = {
+                "precompute_ms": 1e3 * pre_fd8,
+                "fd8_kernel_ms_per_velocity": kt8.get("fd8", (0, 0))[0],
+                "fd8_launches_per_velocity": kt8.get("fd8", (0, 0))[1],
+                "gradient_rel_diff_vs_spectral": float(
+                    torch.linalg.vector_norm(g_fd8 - g_spec) / torch.linalg.vector_norm(g_spec)),
+            }
+            log(f"fd8: {res_nt[nt_]['fd8']}")
+            fplan.close()
+            del fplan
         plan.close()
         del plan
         torch.cuda.empty_cache()
@@ -481,6 +507,7 @@ def main():
         "newton_step_10pcg_ms": 1e3 * r4.get("newton_step_s", float("nan")),
         "newton_info": r4.get("newton_info"),
         "newton_rtol_1e-2": r4.get("newton_preconditioners"),
+        "fd8": r4.get("fd8"),
         "fft_tiles": r4["tuning"],
         "overlap": bool(args.overlap),
     }

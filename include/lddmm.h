@@ -61,7 +61,12 @@ enum {
     /* Allocate only what the transport map, its VJP, the spectral operators
      * and lddmm_reg_energy need; the Newton-path calls then return
      * LDDMM_EUNSUPPORTED.  (Roughly half the workspace.) */
-    LDDMM_FLAG_TRANSPORT_ONLY = 1
+    LDDMM_FLAG_TRANSPORT_ONLY = 1,
+    /* First derivatives (grad m_j, div v, and those of the transport VJP) by
+     * the eighth-order central finite-difference stencil of Section 3.2,
+     * coefficients 4/5, -1/5, 4/105, -1/280 over +-1..4 points, instead of
+     * spectrally.  A, (beta A)^{-1} and the Leray projection stay spectral. */
+    LDDMM_FLAG_FD8 = 2
 };
 
 typedef struct lddmm_config {

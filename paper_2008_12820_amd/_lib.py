@@ -20,6 +20,7 @@ FIELD_DISP, FIELD_DISP_ADJ, FIELD_STATE, FIELD_GRAD_STATE, FIELD_DIV, FIELD_INC_
 
 
 FLAG_TRANSPORT_ONLY = 1
+FLAG_FD8 = 2
 
 
 class Config(ctypes.Structure):

@@ -27,7 +27,7 @@ const char *kernel_name(int id)
     static const char *names[K_NUM_KERNELS] = {
         "r2c_x3", "fft_cols", "x1_symbol", "c2r_x3", "departure", "state_step", "gather_vec",
         "adj_coef", "adj_step", "incstate_init", "incstate_step", "body_force", "dot", "vecop",
-        "pack", "adj_body"};
+        "pack", "adj_body", "fd8"};
     return (id >= 0 && id < K_NUM_KERNELS) ? names[id] : "unknown";
 }
 
@@ -91,7 +91,7 @@ static void validate(const lddmm_config *cfg)
         fail(LDDMM_EINVAL, "reg must be LDDMM_REG_H1S or LDDMM_REG_H2S");
     if (!(std::isfinite(cfg->beta) && cfg->beta > 0.0)) fail(LDDMM_EINVAL, "beta must be finite and > 0");
     if (cfg->leray != 0 && cfg->leray != 1) fail(LDDMM_EINVAL, "leray must be 0 or 1");
-    if (cfg->flags & ~LDDMM_FLAG_TRANSPORT_ONLY) fail(LDDMM_EINVAL, "unknown bits in flags");
+    if (cfg->flags & ~(LDDMM_FLAG_TRANSPORT_ONLY | LDDMM_FLAG_FD8)) fail(LDDMM_EINVAL, "unknown bits in flags");
 }
 
 // Sub-allocation plan of the arena, in bytes, each piece 256-byte aligned.
@@ -215,6 +215,26 @@ static void zero_dev(lddmm_plan *P, float *dst, long count)
 // ---------------------------------------------------------------------------
 // operators
 // ---------------------------------------------------------------------------
+// first derivatives with the plan's scheme: spectral, or the FD8 stencil
+// (LDDMM_FLAG_FD8); gradients: three outputs per input
+static void gradients(lddmm_plan *P, const std::vector<const float *> &in, const std::vector<float *> &out)
+{
+    if (!(P->cfg.flags & LDDMM_FLAG_FD8)) {
+        spectral_apply(P, SOP_GRAD, in, out);
+        return;
+    }
+    for (size_t f = 0; f < in.size(); ++f) launch_fd8_grad(P, in[f], out[3 * f], out[3 * f + 1], out[3 * f + 2]);
+}
+
+static void divergence(lddmm_plan *P, const float *v, float *out)
+{
+    const long N = P->N;
+    if (P->cfg.flags & LDDMM_FLAG_FD8)
+        launch_fd8_div(P, v, out);
+    else
+        spectral_apply(P, SOP_DIV, {v, v + N, v + 2 * N}, {out});
+}
+
 void velocity_state(lddmm_plan *P)
 {
     const long N = P->N;
@@ -230,9 +250,9 @@ void velocity_state(lddmm_plan *P)
         in.push_back(P->m + (long)j * N);
         for (int c = 0; c < 3; ++c) out.push_back(P->G + ((long)j * 3 + c) * N);
     }
-    spectral_apply(P, SOP_GRAD, in, out);
+    gradients(P, in, out);
     launch_interp(P, 3 * nt, P->G, P->dX, P->GX, K_GATHER_VEC);
-    spectral_apply(P, SOP_DIV, {P->v, P->v + N, P->v + 2 * N}, {P->delta});
+    divergence(P, P->v, P->delta);
     launch_adj_coef(P);
     P->have_velocity = 1;
     P->have_grad = 0;
@@ -896,7 +916,7 @@ lddmm_status lddmm_transport_vjp(lddmm_plan *P, const float *ckpt, const float *
         copy_dev(P, P->v, v, 3 * N);
         P->have_velocity = 0;
         launch_departure(P, P->v, P->dX, P->dXa);
-        spectral_apply(P, SOP_DIV, {P->v, P->v + N, P->v + 2 * N}, {P->delta});
+        divergence(P, P->v, P->delta);
         launch_adj_coef(P);
         float *lam = P->lam;
         copy_dev(P, lam + (long)nt * N, grad_m1, N);
@@ -909,7 +929,7 @@ lddmm_status lddmm_transport_vjp(lddmm_plan *P, const float *ckpt, const float *
                 in.push_back(ckpt + (long)j * N);
                 for (int c = 0; c < 3; ++c) out.push_back(P->G + ((long)j * 3 + c) * N);
             }
-            spectral_apply(P, SOP_GRAD, in, out);
+            gradients(P, in, out);
             launch_body_force(P, lam, lam + (long)nt * N, 1.f, P->G, P->b);
             axpby(P, 3 * N, -1.f, P->b, 0.f, nullptr, grad_v);
         }

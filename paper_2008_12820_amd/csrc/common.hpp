@@ -60,6 +60,7 @@ enum KernelId : int {
     K_VECOP,
     K_PACK,
     K_ADJ_BODY,
+    K_FD8,
     K_NUM_KERNELS
 };
 const char *kernel_name(int id);

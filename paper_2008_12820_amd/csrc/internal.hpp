@@ -182,6 +182,10 @@ void launch_incstate_init(lddmm_plan *P, const float *vt, float *mt1);
 void launch_incstate_step(lddmm_plan *P, const float *min, const float *s, float *mout);
 // last adjoint step into lam0 fused with the body force into P->b
 void h0_point(lddmm_plan *P, const float *s, const float *G, float *out, float beta0);
+// eighth-order central differences (Section 3.2): grad f into g1, g2, g3;
+// div of v (three fields, stride N) into out
+void launch_fd8_grad(lddmm_plan *P, const float *f, float *g1, float *g2, float *g3);
+void launch_fd8_div(lddmm_plan *P, const float *v, float *out);
 void launch_adj_body(lddmm_plan *P, const float *lin, float scale, float *lam0, const float *lam,
                      const float *lamN, float scaleN);
 void launch_body_force(lddmm_plan *P, const float *lam, const float *lamN, float scaleN,

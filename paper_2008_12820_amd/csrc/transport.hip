@@ -808,6 +808,76 @@ __global__ __launch_bounds__(kPtThreads) void k_direct(Grid3 g, const float *__r
     epi.finish(p, v);
 }
 
+// Eighth-order central first derivatives on the periodic grid (Section 3.2,
+// the FD kernel replacing the spectral gradient and divergence):
+//   df/dx ~= (1/h) sum_{q=1..4} c_q (f(x + q h) - f(x - q h)),
+//   c = (4/5, -1/5, 4/105, -1/280).
+// A workgroup covers 64 x3 points of 4 x2 rows of one x1 plane; the x3
+// neighbours share cache lines, the x2 and x1 ones come through L2.
+__device__ __forceinline__ float fd8_sum(float p1, float m1, float p2, float m2, float p3, float m3, float p4,
+                                         float m4)
+{
+    float s = 0.8f * (p1 - m1);
+    s = __builtin_fmaf(-0.2f, p2 - m2, s);
+    s = __builtin_fmaf(0.038095238095238095f, p3 - m3, s);
+    return __builtin_fmaf(-0.0035714285714285713f, p4 - m4, s);
+}
+
+__device__ __forceinline__ int wrap_up(int x, int n) { return x >= n ? x - n : x; }
+__device__ __forceinline__ int wrap_dn(int x, int n) { return x < 0 ? x + n : x; }
+
+// derivative along axis AX (0: x1, 1: x2, 2: x3) of f at (i, j, k)
+template <int AX>
+__device__ __forceinline__ float fd8_at(const float *__restrict__ f, int n1, int n2, int n3, int i, int j, int k)
+{
+    float p[4], m[4];
+#pragma unroll
+    for (int q = 1; q <= 4; ++q) {
+        int ip = i, im = i, jp = j, jm = j, kp = k, km = k;
+        if (AX == 0) {
+            ip = wrap_up(i + q, n1);
+            im = wrap_dn(i - q, n1);
+        } else if (AX == 1) {
+            jp = wrap_up(j + q, n2);
+            jm = wrap_dn(j - q, n2);
+        } else {
+            kp = wrap_up(k + q, n3);
+            km = wrap_dn(k - q, n3);
+        }
+        p[q - 1] = f[((long)ip * n2 + jp) * n3 + kp];
+        m[q - 1] = f[((long)im * n2 + jm) * n3 + km];
+    }
+    return fd8_sum(p[0], m[0], p[1], m[1], p[2], m[2], p[3], m[3]);
+}
+
+__global__ __launch_bounds__(256) void k_fd8_grad(const float *__restrict__ f, float *__restrict__ g1,
+                                                  float *__restrict__ g2, float *__restrict__ g3, int n1, int n2,
+                                                  int n3, float ih1, float ih2, float ih3)
+{
+    const int nkt = (n3 + 63) / 64;
+    const int kt = (int)blockIdx.x % nkt, jt = (int)blockIdx.x / nkt, i = (int)blockIdx.y;
+    const int k = kt * 64 + (int)(threadIdx.x & 63), j = jt * 4 + (int)(threadIdx.x >> 6);
+    if (k >= n3 || j >= n2) return;
+    const long p = ((long)i * n2 + j) * n3 + k;
+    g1[p] = ih1 * fd8_at<0>(f, n1, n2, n3, i, j, k);
+    g2[p] = ih2 * fd8_at<1>(f, n1, n2, n3, i, j, k);
+    g3[p] = ih3 * fd8_at<2>(f, n1, n2, n3, i, j, k);
+}
+
+__global__ __launch_bounds__(256) void k_fd8_div(const float *__restrict__ v, float *__restrict__ out, int n1,
+                                                 int n2, int n3, long N, float ih1, float ih2, float ih3)
+{
+    const int nkt = (n3 + 63) / 64;
+    const int kt = (int)blockIdx.x % nkt, jt = (int)blockIdx.x / nkt, i = (int)blockIdx.y;
+    const int k = kt * 64 + (int)(threadIdx.x & 63), j = jt * 4 + (int)(threadIdx.x >> 6);
+    if (k >= n3 || j >= n2) return;
+    const long p = ((long)i * n2 + j) * n3 + k;
+    const float d1 = ih1 * fd8_at<0>(v, n1, n2, n3, i, j, k);
+    const float d2 = ih2 * fd8_at<1>(v + N, n1, n2, n3, i, j, k);
+    const float d3 = ih3 * fd8_at<2>(v + 2 * N, n1, n2, n3, i, j, k);
+    out[p] = (d1 + d2) + d3;
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -827,6 +897,28 @@ static Grid3 grid_of(const lddmm_plan *P)
 static dim3 blocks_of(const lddmm_plan *P)
 {
     return dim3((unsigned)((P->N + kPtThreads - 1) / kPtThreads));
+}
+
+static dim3 fd8_grid(const lddmm_plan *P)
+{
+    const int n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
+    return dim3((unsigned)(((n3 + 63) / 64) * ((n2 + 3) / 4)), (unsigned)n1);
+}
+
+void launch_fd8_grad(lddmm_plan *P, const float *f, float *g1, float *g2, float *g3)
+{
+    Scope s(P, K_FD8);
+    hipLaunchKernelGGL(k_fd8_grad, fd8_grid(P), dim3(256), 0, P->stream, f, g1, g2, g3, P->cfg.n[0], P->cfg.n[1],
+                       P->cfg.n[2], (float)(1.0 / P->h[0]), (float)(1.0 / P->h[1]), (float)(1.0 / P->h[2]));
+    check_hip(hipGetLastError(), "k_fd8_grad");
+}
+
+void launch_fd8_div(lddmm_plan *P, const float *v, float *out)
+{
+    Scope s(P, K_FD8);
+    hipLaunchKernelGGL(k_fd8_div, fd8_grid(P), dim3(256), 0, P->stream, v, out, P->cfg.n[0], P->cfg.n[1],
+                       P->cfg.n[2], P->N, (float)(1.0 / P->h[0]), (float)(1.0 / P->h[1]), (float)(1.0 / P->h[2]));
+    check_hip(hipGetLastError(), "k_fd8_div");
 }
 
 void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa)

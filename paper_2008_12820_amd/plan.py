@@ -7,7 +7,7 @@ from . import _lib as L
 
 class Plan:
     def __init__(self, shape, nt, reg=L.REG_H1S, beta=1e-2, leray=False, device=None,
-                 stream=None, transport_only=False):
+                 stream=None, transport_only=False, fd8=False):
         self.shape = tuple(int(s) for s in shape)
         self.nt = int(nt)
         self.reg = int(reg)
@@ -18,7 +18,8 @@ class Plan:
             s = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = s
         self.cfg = L.make_config(self.shape, self.nt, self.reg, self.beta, self.leray,
-                                 L.FLAG_TRANSPORT_ONLY if transport_only else 0)
+                                 (L.FLAG_TRANSPORT_ONLY if transport_only else 0) |
+                                 (L.FLAG_FD8 if fd8 else 0))
         with torch.cuda.device(self.device):
             self._h = L.lddmm_plan_create(self.cfg, s.cuda_stream)
 

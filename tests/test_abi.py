@@ -76,3 +76,12 @@ def test_null_pointers_and_status_strings():
     assert L.lib().lddmm_set_images(None, None, None) == L.EINVAL
     assert L.lib().lddmm_num_kernels() > 10
     assert L.lddmm_kernel_name(0) == "r2c_x3"
+
+
+def test_config_flags():
+    """FD8 and transport-only are the known flag bits; any other bit is rejected."""
+    out = ctypes.c_size_t()
+    for flags, want in ((L.FLAG_FD8, L.OK), (L.FLAG_FD8 | L.FLAG_TRANSPORT_ONLY, L.OK), (4, L.EINVAL),
+                        (8 | L.FLAG_FD8, L.EINVAL)):
+        cfg = L.make_config((16, 16, 16), 2, 2, 1e-2, flags=flags)
+        assert L.lib().lddmm_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == want, flags
