@@ -54,6 +54,9 @@ def lib():
             "or_fd8_grad": (None, [p, p, i, i, i]),
             "or_fd8_div": (None, [p, p, i, i, i]),
             "or_ctx_set_fd8": (None, [p, i]),
+            "or_interp_linear": (None, [p, i, i, i, i, p, l, p]),
+            "or_ctx_set_ip_order": (None, [p, i]),
+            "or_ctx_set_beta": (None, [p, d]),
             "or_prolong": (None, [p, p, i, i, i, i]),
             "or_ctx_2linvh0": (i, [p, p, d, i, p]),
             "or_ctx_invh0": (i, [p, p, d, i, p]),
@@ -129,17 +132,21 @@ def leray(v):
     return out
 
 
-def interp(fields, y):
-    """fields: [nf][n1][n2][n3] (or one [n1][n2][n3]); y: [3][nq] physical
-    coordinates.  Returns [nf][nq] (or [nq])."""
+def _interp_generic(fields, y, fn):
     single = fields.ndim == 3
     f = fields[None] if single else fields
     f, pf = _c(f)
     y, py = _c(y)
     nq = y.shape[1]
     out = np.empty((f.shape[0], nq))
-    lib().or_interp(pf, f.shape[0], *f.shape[1:], py, nq, out.ctypes.data_as(ctypes.c_void_p))
+    fn(pf, f.shape[0], *f.shape[1:], py, nq, out.ctypes.data_as(ctypes.c_void_p))
     return out[0] if single else out
+
+
+def interp(fields, y):
+    """fields: [nf][n1][n2][n3] (or one [n1][n2][n3]); y: [3][nq] physical
+    coordinates.  Returns [nf][nq] (or [nq])."""
+    return _interp_generic(fields, y, lib().or_interp)
 
 
 def departure(v, nt):
@@ -166,6 +173,11 @@ def fd8_div(v):
     out = np.empty(a.shape[1:])
     lib().or_fd8_div(pa, out.ctypes.data_as(ctypes.c_void_p), *a.shape[1:])
     return out
+
+
+def interp_linear(fields, y):
+    """Trilinear interpolation (d = 1), arguments as interp."""
+    return _interp_generic(fields, y, lib().or_interp_linear)
 
 
 def restrict(f):
@@ -204,7 +216,7 @@ def inner(a, b, h3):
 class Problem:
     """One registration problem: grid, N_t, regularisation, images, velocity."""
 
-    def __init__(self, shape, nt, reg=1, beta=1e-2, leray=False, fd8=False):
+    def __init__(self, shape, nt, reg=1, beta=1e-2, leray=False, fd8=False, ip=3):
         self.shape = tuple(int(s) for s in shape)
         self.nt = int(nt)
         self.reg = int(reg)
@@ -216,6 +228,53 @@ class Problem:
                                         int(self.leray))
         self.fd8 = bool(fd8)
         lib().or_ctx_set_fd8(self._ctx, int(self.fd8))
+        self.ip = 1 if ip == 1 else 3
+        lib().or_ctx_set_ip_order(self._ctx, self.ip)
+
+    def set_beta(self, beta):
+        """new regularisation weight; the next gradient is the new ||g0||"""
+        self.beta = float(beta)
+        lib().or_ctx_set_beta(self._ctx, self.beta)
+
+    def gn_solve(self, v0, beta_target, eps_n=5e-2, max_gn=10, max_pcg=50, rtol=0.0,
+                 continuation=True, pc="2linvh0", eps_h0=1e-3, max_inner=50, pc_switch=0.5):
+        """Gauss-Newton-Krylov driver (Algorithm "GNK") with beta-continuation
+        (Section 2 "Preconditioning", last paragraph): beta = 1, 1e-1, ...
+        while above beta_target, then beta_target; per stage, Gauss-Newton
+        iterations from the previous stage's velocity until ||g|| <= eps_n ||g0||
+        (g0 the stage's first gradient), max_gn iterations or a failed line
+        search; InvA while beta > pc_switch, else pc.  Returns (v, report)."""
+        betas = []
+        if continuation:
+            b = 1.0
+            while b > beta_target * (1 + 1e-12):
+                betas.append(b)
+                b /= 10.0
+        betas.append(float(beta_target))
+        v = np.array(v0, dtype=np.float64)
+        rep = {"stages": 0, "gn_iters": 0, "pcg_iters": 0, "inner_iters": 0}
+        self.set_velocity(v)
+        for beta in betas:
+            self.set_beta(beta)
+            kind = "inva" if beta > pc_switch else pc
+            rep["stages"] += 1
+            g0 = None
+            for _ in range(max_gn):
+                g = self.gradient()
+                gn = np.sqrt(inner(g, g, self.h3))
+                g0 = gn if g0 is None else g0
+                if gn <= eps_n * g0:
+                    break
+                v, info = self.gn_iterate(max_pcg, rtol, pc=kind, eps_h0=eps_h0, max_inner=max_inner)
+                rep["gn_iters"] += 1
+                rep["pcg_iters"] += info["pcg_iters"]
+                rep["inner_iters"] += int(info["inner_iters"])
+                if info["alpha"] == 0.0:
+                    break
+        g = self.gradient()
+        rep["J"] = self.objective()[0]
+        rep["gnorm_rel"] = float(np.sqrt(inner(g, g, self.h3)) / g0) if g0 else 0.0
+        return v, rep
 
     def __del__(self):
         if getattr(self, "_ctx", None) and _lib is not None:

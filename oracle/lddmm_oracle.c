@@ -30,7 +30,9 @@
  *   5e-2) in H0 and in its inner preconditioner, inner start (beta0 A)^{-1} r,
  *   inner stop relative to ||r||, tolerance eps_H0 times the outer tolerance;
  *   FD8: the standard eighth-order central stencil (coefficients 4/5, -1/5,
- *   4/105, -1/280), used for every first derivative when selected.
+ *   4/105, -1/280), used for every first derivative when selected;
+ *   trilinear interpolation, when selected, everywhere the cubic one is used
+ *   (departure predictor included).
  */
 #include <complex.h>
 #include <math.h>
@@ -412,6 +414,48 @@ void or_interp(const double *fields, int nf, int n1, int n2, int n3,
     }
 }
 
+/* The same with first-order (trilinear) Lagrange interpolation, d = 1 in
+ * the formula of Section 3.1: nodes floor(u) and floor(u)+1, weights 1-t, t. */
+void or_interp_linear(const double *fields, int nf, int n1, int n2, int n3,
+                      const double *y, long nq, double *out)
+{
+    int n[3] = {n1, n2, n3};
+    long N = (long)n1 * n2 * n3;
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < nq; q++) {
+        double w[3][2];
+        long idx[3][2];
+        for (int d = 0; d < 3; d++) {
+            double h = 2.0 * OR_PI / n[d];
+            double u = y[d * nq + q] / h;
+            double b = floor(u);
+            w[d][0] = 1.0 - (u - b);
+            w[d][1] = u - b;
+            for (int r = 0; r < 2; r++) idx[d][r] = wrap_index((long)b + r, n[d]);
+        }
+        for (int f = 0; f < nf; f++) {
+            const double *F = fields + (long)f * N;
+            double s = 0.0;
+            for (int a = 0; a < 2; a++)
+                for (int b = 0; b < 2; b++)
+                    for (int c = 0; c < 2; c++)
+                        s += F[(idx[0][a] * n2 + idx[1][b]) * n3 + idx[2][c]] *
+                             w[0][a] * w[1][b] * w[2][c];
+            out[(long)f * nq + q] = s;
+        }
+    }
+}
+
+/* order 3 (cubic, the default) or 1 (trilinear) */
+static void interp_order(int order, const double *fields, int nf, const int n[3], const double *y, long nq,
+                         double *out)
+{
+    if (order == 1)
+        or_interp_linear(fields, nf, n[0], n[1], n[2], y, nq, out);
+    else
+        or_interp(fields, nf, n[0], n[1], n[2], y, nq, out);
+}
+
 /* physical coordinates of all grid points, component-major */
 static double *grid_points(const int n[3])
 {
@@ -432,7 +476,17 @@ static double *grid_points(const int n[3])
 
 /* X  = x - dt/2 (v(x) + v(x - dt v(x)))   (state and incremental state)
  * Xa = x + dt/2 (v(x) + v(x + dt v(x)))   (adjoints: transport along -v) */
+static void departure_order(int order, const double *v, int n1, int n2, int n3, int nt, double *X,
+                            double *Xa);
+
 void or_departure(const double *v, int n1, int n2, int n3, int nt, double *X, double *Xa)
+{
+    departure_order(3, v, n1, n2, n3, nt, X, Xa);
+}
+
+/* the departure points with the interpolation of the given order at the predictor */
+static void departure_order(int order, const double *v, int n1, int n2, int n3, int nt, double *X,
+                            double *Xa)
 {
     int n[3] = {n1, n2, n3};
     long N = (long)n1 * n2 * n3;
@@ -444,7 +498,7 @@ void or_departure(const double *v, int n1, int n2, int n3, int nt, double *X, do
         double s = dir == 0 ? -1.0 : 1.0;
         double *out = dir == 0 ? X : Xa;
         for (long i = 0; i < 3 * N; i++) y[i] = x[i] + s * dt * v[i];
-        or_interp(v, 3, n1, n2, n3, y, N, vy);
+        interp_order(order, v, 3, n, y, N, vy);
         for (long i = 0; i < 3 * N; i++) out[i] = x[i] + s * 0.5 * dt * (v[i] + vy[i]);
     }
     free(vy);
@@ -473,7 +527,24 @@ typedef struct {
     int have_images, have_velocity;
     double g0norm;        /* norm of the first gradient after set_images */
     int fd8;              /* first derivatives: 0 spectral, 1 eighth-order FD */
+    int ip;               /* interpolation order: 3 cubic (default), 1 trilinear */
 } or_ctx;
+
+static void ctx_interp(const or_ctx *c, const double *fields, int nf, const double *y, double *out)
+{
+    interp_order(c->ip, fields, nf, c->n, y, c->N, out);
+}
+
+/* interpolation order 3 or 1; takes effect at the next velocity */
+void or_ctx_set_ip_order(or_ctx *c, int order) { c->ip = order == 1 ? 1 : 3; }
+
+/* the regularisation weight (for beta-continuation); the velocity state does
+ * not depend on it */
+void or_ctx_set_beta(or_ctx *c, double beta)
+{
+    c->beta = beta;
+    c->g0norm = 0.0;  /* a new beta starts a new Newton solve: ||g||_rel from its first gradient */
+}
 
 /* grad of a scalar and div of a vector field with the context's scheme */
 static void ctx_grad(const or_ctx *c, const double *f, double *g)
@@ -506,6 +577,7 @@ or_ctx *or_ctx_create(int n1, int n2, int n3, int nt, int reg, double beta, int 
     c->reg = reg;
     c->beta = beta;
     c->leray = leray;
+    c->ip = 3;
     c->h3 = (2.0 * OR_PI / n1) * (2.0 * OR_PI / n2) * (2.0 * OR_PI / n3);
     long N = c->N;
     c->m0 = malloc(sizeof(double) * N);
@@ -549,7 +621,7 @@ static void solve_state(const or_ctx *c, const double *m0, double *m)
     long N = c->N;
     memcpy(m, m0, sizeof(double) * N);
     for (int j = 0; j < c->nt; j++)
-        or_interp(m + j * N, 1, c->n[0], c->n[1], c->n[2], c->X, N, m + (j + 1) * N);
+        ctx_interp(c, m + j * N, 1, c->X, m + (j + 1) * N);
 }
 
 void or_ctx_set_images(or_ctx *c, const double *m0, const double *m1)
@@ -566,11 +638,11 @@ void or_ctx_set_velocity(or_ctx *c, const double *v)
 {
     long N = c->N;
     memcpy(c->v, v, sizeof(double) * 3 * N);
-    or_departure(c->v, c->n[0], c->n[1], c->n[2], c->nt, c->X, c->Xa);
+    departure_order(c->ip, c->v, c->n[0], c->n[1], c->n[2], c->nt, c->X, c->Xa);
     solve_state(c, c->m0, c->m);
     for (int j = 0; j <= c->nt; j++) ctx_grad(c, c->m + j * N, c->G + (long)j * 3 * N);
     ctx_div(c, c->v, c->delta);
-    or_interp(c->delta, 1, c->n[0], c->n[1], c->n[2], c->Xa, N, c->delta_a);
+    ctx_interp(c, c->delta, 1, c->Xa, c->delta_a);
     c->have_velocity = 1;
 }
 
@@ -586,7 +658,7 @@ void or_ctx_adjoint(const or_ctx *c, const double *phi, double *lam)
     memcpy(lam + (long)c->nt * N, phi, sizeof(double) * N);
     double *l = malloc(sizeof(double) * N);
     for (int j = c->nt - 1; j >= 0; j--) {
-        or_interp(lam + (long)(j + 1) * N, 1, c->n[0], c->n[1], c->n[2], c->Xa, N, l);
+        ctx_interp(c, lam + (long)(j + 1) * N, 1, c->Xa, l);
         for (long p = 0; p < N; p++) {
             double r0 = l[p] * c->delta_a[p];
             double ls = l[p] + dt * r0;
@@ -671,13 +743,13 @@ void or_ctx_inc_state(const or_ctx *c, const double *vt, double *mt)
     long N = c->N;
     double dt = 1.0 / c->nt;
     double *vtX = malloc(sizeof(double) * 3 * N);
-    or_interp(vt, 3, c->n[0], c->n[1], c->n[2], c->X, N, vtX);
+    ctx_interp(c, vt, 3, c->X, vtX);
     double *GX = malloc(sizeof(double) * 3 * N);
     double *mX = malloc(sizeof(double) * N);
     for (long p = 0; p < N; p++) mt[p] = 0.0;
     for (int j = 0; j < c->nt; j++) {
-        or_interp(mt + (long)j * N, 1, c->n[0], c->n[1], c->n[2], c->X, N, mX);
-        or_interp(c->G + (long)j * 3 * N, 3, c->n[0], c->n[1], c->n[2], c->X, N, GX);
+        ctx_interp(c, mt + (long)j * N, 1, c->X, mX);
+        ctx_interp(c, c->G + (long)j * 3 * N, 3, c->X, GX);
         const double *G1 = c->G + (long)(j + 1) * 3 * N;
         for (long p = 0; p < N; p++) {
             double s0 = 0.0, s1 = 0.0;
