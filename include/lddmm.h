@@ -66,7 +66,11 @@ enum {
      * the eighth-order central finite-difference stencil of Section 3.2,
      * coefficients 4/5, -1/5, 4/105, -1/280 over +-1..4 points, instead of
      * spectrally.  A, (beta A)^{-1} and the Leray projection stay spectral. */
-    LDDMM_FLAG_FD8 = 2
+    LDDMM_FLAG_FD8 = 2,
+    /* First-order (trilinear) Lagrange interpolation, d = 1 in the formula
+     * of Section 3.1, in every semi-Lagrangian step and the departure
+     * predictor, instead of the cubic one (the paper's tuned runs use it). */
+    LDDMM_FLAG_LINEAR_IP = 4
 };
 
 typedef struct lddmm_config {
@@ -254,6 +258,47 @@ lddmm_status lddmm_batch_gn_iterate(lddmm_batch *batch, int32_t max_pcg, double 
  * and grid size for the process and, when the environment variable
  * LDDMM_TUNE_CACHE names a file, in that file.  Synchronises the stream. */
 lddmm_status lddmm_autotune(lddmm_plan *plan);
+/* Change the regularisation weight beta (finite, > 0), e.g. for a
+ * beta-continuation; the velocity state stays valid (it does not depend on
+ * beta) and the stored ||g0|| is cleared, so the next gradient sets it.
+ * EINVAL for a bad beta. */
+lddmm_status lddmm_set_beta(lddmm_plan *plan, double beta);
+
+/* Options of lddmm_gn_solve (Algorithm "GNK" with the beta-continuation of
+ * Section 2 "Preconditioning", last paragraph). */
+typedef struct lddmm_solve_opts {
+    double beta_target;    /* final beta, > 0 */
+    double eps_n;          /* a stage stops at ||g|| <= eps_n ||g0|| (the paper: 5e-2); 0 never */
+    double rtol;           /* PCG tolerance; <= 0: eps_K = min(sqrt(||g||/||g0||), 0.5) */
+    double eps_h0;         /* inner tolerance factor of InvH0 / 2LInvH0, in (0, 1) */
+    double pc_switch;      /* InvA while beta > pc_switch (the paper: 0.5) */
+    int32_t max_gn;        /* Gauss-Newton iterations per stage, >= 0 */
+    int32_t max_pcg;       /* PCG iterations per Newton step, >= 0 */
+    int32_t max_inner;     /* inner iterations per preconditioner application, >= 1 */
+    int32_t continuation;  /* 1: beta = 1, 1e-1, ... while above beta_target, then beta_target */
+    int32_t pc_kind;       /* preconditioner below pc_switch: 0 InvA, 1 InvH0, 2 2LInvH0 */
+    int32_t reserved;
+} lddmm_solve_opts;
+
+typedef struct lddmm_solve_report {
+    int32_t stages;       /* beta values solved for */
+    int32_t gn_iters;     /* Newton steps taken over all stages */
+    int32_t pcg_iters;    /* Hessian matvecs spent in PCG */
+    int32_t inner_iters;  /* H0 applications inside the preconditioners */
+    double J;             /* final objective (at beta_target) */
+    double gnorm_rel;     /* final ||g|| / ||g0|| of the last stage */
+} lddmm_solve_report;
+
+/* Gauss-Newton-Krylov solve from the velocity in v_inout (3N, overwritten
+ * with the result): per beta stage, Gauss-Newton iterations (lddmm_gn_iterate
+ * semantics, the stage's first gradient as ||g0||) until ||g|| <= eps_n
+ * ||g0||, max_gn steps or a failed line search, each stage starting from the
+ * previous one's velocity; the plan's own preconditioner setting is restored
+ * afterwards and its beta is left at beta_target.  ESTATE before
+ * set_images; EINVAL for options out of range. */
+lddmm_status lddmm_gn_solve(lddmm_plan *plan, const lddmm_solve_opts *opts, float *v_inout,
+                            lddmm_solve_report *report);
+
 /* Preconditioner of the PCG in lddmm_newton_step and lddmm_gn_iterate
  * (Section 2 "Preconditioning", Algorithm "PC"):
  *   kind 0 = InvA, (beta A)^{-1} (the default);

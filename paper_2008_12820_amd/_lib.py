@@ -21,6 +21,7 @@ FIELD_DISP, FIELD_DISP_ADJ, FIELD_STATE, FIELD_GRAD_STATE, FIELD_DIV, FIELD_INC_
 
 FLAG_TRANSPORT_ONLY = 1
 FLAG_FD8 = 2
+FLAG_LINEAR_IP = 4
 
 
 class Config(ctypes.Structure):
@@ -37,6 +38,21 @@ class NewtonInfo(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("beta_target", ctypes.c_double), ("eps_n", ctypes.c_double), ("rtol", ctypes.c_double),
+                ("eps_h0", ctypes.c_double), ("pc_switch", ctypes.c_double), ("max_gn", ctypes.c_int32),
+                ("max_pcg", ctypes.c_int32), ("max_inner", ctypes.c_int32), ("continuation", ctypes.c_int32),
+                ("pc_kind", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("stages", ctypes.c_int32), ("gn_iters", ctypes.c_int32), ("pcg_iters", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int32), ("J", ctypes.c_double), ("gnorm_rel", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class LddmmError(RuntimeError):
@@ -69,6 +85,8 @@ def lib():
             "lddmm_hessian_matvec": (st, [p, p, p]),
             "lddmm_apply_inv_reg": (st, [p, p, p]),
             "lddmm_set_preconditioner": (st, [p, i32, d, i32]),
+            "lddmm_set_beta": (st, [p, d]),
+            "lddmm_gn_solve": (st, [p, P(SolveOpts), p, P(SolveReport)]),
             "lddmm_apply_h0": (st, [p, p, p]),
             "lddmm_apply_invh0": (st, [p, p, d, i32, p, P(i32)]),
             "lddmm_apply_2linvh0": (st, [p, p, d, i32, p, P(i32)]),
@@ -185,6 +203,20 @@ def lddmm_hessian_matvec(plan, vt, hvt):
 
 def lddmm_apply_inv_reg(plan, r, s):
     _check(lib().lddmm_apply_inv_reg(plan, _ptr(r), _ptr(s)), "apply_inv_reg")
+
+
+def lddmm_set_beta(plan, beta):
+    _check(lib().lddmm_set_beta(plan, float(beta)), "set_beta")
+
+
+def lddmm_gn_solve(plan, v_inout, beta_target, eps_n=5e-2, rtol=0.0, eps_h0=1e-3, pc_switch=0.5, max_gn=10,
+                   max_pcg=50, max_inner=50, continuation=True, pc_kind=2):
+    o = SolveOpts(beta_target=float(beta_target), eps_n=float(eps_n), rtol=float(rtol), eps_h0=float(eps_h0),
+                  pc_switch=float(pc_switch), max_gn=int(max_gn), max_pcg=int(max_pcg), max_inner=int(max_inner),
+                  continuation=int(bool(continuation)), pc_kind=int(pc_kind), reserved=0)
+    rep = SolveReport()
+    _check(lib().lddmm_gn_solve(plan, ctypes.byref(o), _ptr(v_inout), ctypes.byref(rep)), "gn_solve")
+    return rep.as_dict()
 
 
 def lddmm_set_preconditioner(plan, kind, eps_h0=1e-3, max_inner=50):

@@ -91,7 +91,8 @@ static void validate(const lddmm_config *cfg)
         fail(LDDMM_EINVAL, "reg must be LDDMM_REG_H1S or LDDMM_REG_H2S");
     if (!(std::isfinite(cfg->beta) && cfg->beta > 0.0)) fail(LDDMM_EINVAL, "beta must be finite and > 0");
     if (cfg->leray != 0 && cfg->leray != 1) fail(LDDMM_EINVAL, "leray must be 0 or 1");
-    if (cfg->flags & ~(LDDMM_FLAG_TRANSPORT_ONLY | LDDMM_FLAG_FD8)) fail(LDDMM_EINVAL, "unknown bits in flags");
+    if (cfg->flags & ~(LDDMM_FLAG_TRANSPORT_ONLY | LDDMM_FLAG_FD8 | LDDMM_FLAG_LINEAR_IP))
+        fail(LDDMM_EINVAL, "unknown bits in flags");
 }
 
 // Sub-allocation plan of the arena, in bytes, each piece 256-byte aligned.
@@ -830,6 +831,66 @@ lddmm_status lddmm_newton_step(lddmm_plan *P, int32_t max_pcg, double rtol, floa
     return st;
 }
 
+}  // extern "C"
+
+namespace lddmm {
+
+// One Gauss-Newton iteration at the plan's velocity (Algorithm "GNK"): g, J,
+// eps_K, PCG on H v~ = -g, Armijo (c1 = 1e-4, halving, 10 trials), state
+// refresh.  With eps_n > 0 it returns false without a step when the
+// gradient already meets ||g|| <= eps_n ||g0||.
+static bool gn_iterate_impl(lddmm_plan *P, int max_pcg, double rtol, double eps_n, lddmm_newton_info &loc)
+{
+    const long M = 3 * P->N;
+    const double gn = gradient_impl(P, P->g);
+    loc.gnorm = gn;
+    loc.gnorm_rel = P->g0norm > 0 ? gn / P->g0norm : 1.0;
+    if (eps_n > 0.0 && gn <= eps_n * P->g0norm) return false;
+    double J0, mis, rg;
+    objective_impl(P, J0, mis, rg);
+    loc.J_before = J0;
+    const double tol = tolerance(P, rtol, gn);
+    axpby(P, M, -1.f, P->g, 0.f, nullptr, P->tmp3);
+    const int flags = pcg_impl(P, P->tmp3, max_pcg, tol, P->vt, loc);
+    const double gv = dot_now(P, P->g, P->vt, M);
+    float *v0 = P->pq, *vn = P->pp;  // PCG scratch is free now
+    copy_dev(P, v0, P->v, M);
+    double alpha = 1.0, Jn = J0;
+    bool ok = false;
+    for (int tries = 0; tries < 10; ++tries) {
+        axpby(P, M, 1.f, v0, (float)alpha, P->vt, vn);
+        copy_dev(P, P->v, vn, M);
+        velocity_state(P);
+        objective_impl(P, Jn, mis, rg);
+        if (Jn <= J0 + 1e-4 * alpha * gv) {
+            ok = true;
+            break;
+        }
+        alpha *= 0.5;
+    }
+    if (!ok) {
+        copy_dev(P, P->v, v0, M);
+        velocity_state(P);
+        alpha = 0.0;
+        Jn = J0;
+    }
+    loc.alpha = alpha;
+    loc.J_after = Jn;
+    loc.flags = flags;
+    return true;
+}
+
+static void set_beta_impl(lddmm_plan *P, double beta)
+{
+    P->cfg.beta = beta;
+    P->g0norm = 0.0;
+    dev_set_scalar(P, S_G0, 0.0);
+}
+
+}  // namespace lddmm
+
+extern "C" {
+
 lddmm_status lddmm_gn_iterate(lddmm_plan *P, int32_t max_pcg, double rtol, float *v_inout,
                               lddmm_newton_info *info)
 {
@@ -839,45 +900,81 @@ lddmm_status lddmm_gn_iterate(lddmm_plan *P, int32_t max_pcg, double rtol, float
         need_dev(v_inout, "v_inout");
         if (max_pcg < 0) fail(LDDMM_EINVAL, "max_pcg must be >= 0");
         need_velocity(P);
-        const long M = 3 * P->N;
-        const double gn = gradient_impl(P, P->g);
-        loc.gnorm = gn;
-        loc.gnorm_rel = P->g0norm > 0 ? gn / P->g0norm : 1.0;
-        double J0, mis, rg;
-        objective_impl(P, J0, mis, rg);
-        loc.J_before = J0;
-        const double tol = tolerance(P, rtol, gn);
-        axpby(P, M, -1.f, P->g, 0.f, nullptr, P->tmp3);
-        const int flags = pcg_impl(P, P->tmp3, max_pcg, tol, P->vt, loc);
-        const double gv = dot_now(P, P->g, P->vt, M);
-        float *v0 = P->pq, *vn = P->pp;  // PCG scratch is free now
-        copy_dev(P, v0, P->v, M);
-        double alpha = 1.0, Jn = J0;
-        bool ok = false;
-        for (int tries = 0; tries < 10; ++tries) {
-            axpby(P, M, 1.f, v0, (float)alpha, P->vt, vn);
-            copy_dev(P, P->v, vn, M);
-            velocity_state(P);
-            objective_impl(P, Jn, mis, rg);
-            if (Jn <= J0 + 1e-4 * alpha * gv) {
-                ok = true;
-                break;
-            }
-            alpha *= 0.5;
-        }
-        if (!ok) {
-            copy_dev(P, P->v, v0, M);
-            velocity_state(P);
-            alpha = 0.0;
-            Jn = J0;
-        }
-        copy_dev(P, v_inout, P->v, M);
+        gn_iterate_impl(P, max_pcg, rtol, 0.0, loc);
+        copy_dev(P, v_inout, P->v, 3 * P->N);
         check_hip(hipStreamSynchronize(P->stream), "stream sync");
-        loc.alpha = alpha;
-        loc.J_after = Jn;
-        loc.flags = flags;
     });
     if (info) *info = loc;
+    return st;
+}
+
+lddmm_status lddmm_set_beta(lddmm_plan *P, double beta)
+{
+    return guard([&] {
+        need(P, "plan");
+        if (!(beta > 0.0) || !std::isfinite(beta)) fail(LDDMM_EINVAL, "beta must be finite and > 0");
+        set_beta_impl(P, beta);
+    });
+}
+
+lddmm_status lddmm_gn_solve(lddmm_plan *P, const lddmm_solve_opts *o, float *v_inout, lddmm_solve_report *report)
+{
+    lddmm_solve_report rep{};
+    lddmm_status st = guard([&] {
+        need(P, "plan");
+        need(o, "opts");
+        need_dev(v_inout, "v_inout");
+        need_full(P);
+        if (!P->have_images) fail(LDDMM_ESTATE, "set_images first");
+        if (!(o->beta_target > 0.0) || !std::isfinite(o->beta_target)) fail(LDDMM_EINVAL, "beta_target must be > 0");
+        if (o->max_gn < 0 || o->max_pcg < 0 || o->max_inner < 1 || o->pc_kind < 0 || o->pc_kind > 2 ||
+            !(o->eps_h0 > 0.0 && o->eps_h0 < 1.0) || !(o->eps_n >= 0.0))
+            fail(LDDMM_EINVAL, "solve options out of range");
+        if (o->pc_kind == 2 && !halves(P->cfg)) fail(LDDMM_EINVAL, "2LInvH0 needs a grid that halves");
+        std::vector<double> betas;
+        if (o->continuation)
+            for (double b = 1.0; b > o->beta_target * (1 + 1e-12); b /= 10.0) betas.push_back(b);
+        betas.push_back(o->beta_target);
+        const int keep_kind = P->pc_kind, keep_inner = P->pc_max_inner;
+        const double keep_eps = P->pc_eps_h0;
+        const long M = 3 * P->N;
+        copy_dev(P, P->v, v_inout, M);
+        velocity_state(P);
+        P->have_velocity = 1;
+        try {
+            for (double b : betas) {
+                set_beta_impl(P, b);
+                P->pc_kind = b > o->pc_switch ? 0 : o->pc_kind;
+                P->pc_eps_h0 = o->eps_h0;
+                P->pc_max_inner = o->max_inner;
+                ++rep.stages;
+                for (int it = 0; it < o->max_gn; ++it) {
+                    lddmm_newton_info loc{};
+                    if (!gn_iterate_impl(P, o->max_pcg, o->rtol, o->eps_n, loc)) break;
+                    ++rep.gn_iters;
+                    rep.pcg_iters += loc.pcg_iters;
+                    rep.inner_iters += loc.inner_iters;
+                    if (loc.alpha == 0.0) break;
+                }
+            }
+        } catch (...) {
+            P->pc_kind = keep_kind;
+            P->pc_eps_h0 = keep_eps;
+            P->pc_max_inner = keep_inner;
+            throw;
+        }
+        P->pc_kind = keep_kind;
+        P->pc_eps_h0 = keep_eps;
+        P->pc_max_inner = keep_inner;
+        const double gn = gradient_impl(P, P->g);
+        rep.gnorm_rel = P->g0norm > 0 ? gn / P->g0norm : 1.0;
+        double J, mis, rg;
+        objective_impl(P, J, mis, rg);
+        rep.J = J;
+        copy_dev(P, v_inout, P->v, M);
+        check_hip(hipStreamSynchronize(P->stream), "stream sync");
+    });
+    if (report) *report = rep;
     return st;
 }
 

@@ -167,11 +167,70 @@ __device__ __forceinline__ T gather(const float *__restrict__ f, const Stencil<T
     return acc;
 }
 
+// First-order (trilinear) interpolation, d = 1 in the Section 3.1 formula:
+// nodes floor(u) and floor(u) + 1 per axis, weights 1 - t and t.
+template <class T>
+struct Stencil2 {
+    unsigned o1[2], o2[2], o3[2];
+    T w1[2], w2[2], w3[2];
+};
+
+template <class T>
+__device__ __forceinline__ void axis_stencil2(int i, T d, int n, unsigned stride, unsigned o[2], T w[2])
+{
+    const T lim = (T)1048576;
+    d = d > lim ? lim : d;
+    d = d >= -lim ? d : -lim;
+    const T fl = floor(d);
+    int b = i + (int)fl;
+    if ((unsigned)(b + n) < (unsigned)(3 * n)) {
+        b = b < 0 ? b + n : b;
+        b = b >= n ? b - n : b;
+    } else {
+        b %= n;
+        if (b < 0) b += n;
+    }
+    o[0] = (unsigned)b * stride;
+    o[1] = (unsigned)(b + 1 == n ? 0 : b + 1) * stride;
+    const T t = d - fl;
+    w[0] = T(1) - t;
+    w[1] = t;
+}
+
+template <class T>
+__device__ __forceinline__ void make_stencil2(const Grid3 &g, int i, int j, int k, T d1, T d2, T d3,
+                                              Stencil2<T> &s)
+{
+    axis_stencil2<T>(i, d1, g.n1, (unsigned)g.n2 * (unsigned)g.n3, s.o1, s.w1);
+    axis_stencil2<T>(j, d2, g.n2, (unsigned)g.n3, s.o2, s.w2);
+    axis_stencil2<T>(k, d3, g.n3, 1u, s.o3, s.w3);
+}
+
+// x3 pairs, then x2, then x1, with explicit fused multiply-adds
+template <class T>
+__device__ __forceinline__ T gather2(const float *__restrict__ f, const Stencil2<T> &s)
+{
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        T acc2 = T(0);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const float *row = f + (s.o1[a] + s.o2[b]);
+            const T r = fma_((T)row[s.o3[1]], s.w3[1], (T)row[s.o3[0]] * s.w3[0]);
+            acc2 = b == 0 ? s.w2[0] * r : fma_(s.w2[1], r, acc2);
+        }
+        acc = a == 0 ? s.w1[0] * acc2 : fma_(s.w1[1], acc2, acc);
+    }
+    return acc;
+}
+
 // ---------------------------------------------------------------------------
 // departure points, FP64:  X = x - dt/2 (v(x) + I[v](x - dt v(x)))
 //                          Xa = x + dt/2 (v(x) + I[v](x + dt v(x)))
 // stored as displacements in voxels
 // ---------------------------------------------------------------------------
+template <int ORDER>
 __global__ __launch_bounds__(kPtThreads) void k_departure(const float *__restrict__ v,
                                                           float *__restrict__ dX,
                                                           float *__restrict__ dXa, Grid3 g, double dt,
@@ -188,14 +247,25 @@ __global__ __launch_bounds__(kPtThreads) void k_departure(const float *__restric
 #pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
         const double sgn = dir == 0 ? -1.0 : 1.0;
-        Stencil<double> s;
-        make_stencil<double>(g, i, j, k, sgn * dt * vx[0] * ih[0], sgn * dt * vx[1] * ih[1],
-                             sgn * dt * vx[2] * ih[2], s);
         float *out = dir == 0 ? dX : dXa;
+        if constexpr (ORDER == 1) {
+            Stencil2<double> s;
+            make_stencil2<double>(g, i, j, k, sgn * dt * vx[0] * ih[0], sgn * dt * vx[1] * ih[1],
+                                  sgn * dt * vx[2] * ih[2], s);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double vi = gather<double>(v + (long)c * g.N, s);
-            out[(long)c * g.N + p] = (float)(sgn * 0.5 * dt * (vx[c] + vi) * ih[c]);
+            for (int c = 0; c < 3; ++c) {
+                const double vi = gather2<double>(v + (long)c * g.N, s);
+                out[(long)c * g.N + p] = (float)(sgn * 0.5 * dt * (vx[c] + vi) * ih[c]);
+            }
+        } else {
+            Stencil<double> s;
+            make_stencil<double>(g, i, j, k, sgn * dt * vx[0] * ih[0], sgn * dt * vx[1] * ih[1],
+                                 sgn * dt * vx[2] * ih[2], s);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double vi = gather<double>(v + (long)c * g.N, s);
+                out[(long)c * g.N + p] = (float)(sgn * 0.5 * dt * (vx[c] + vi) * ih[c]);
+            }
         }
     }
 }
@@ -808,6 +878,23 @@ __global__ __launch_bounds__(kPtThreads) void k_direct(Grid3 g, const float *__r
     epi.finish(p, v);
 }
 
+// trilinear gathers (LDDMM_FLAG_LINEAR_IP): eight nodes per point from L1/L2
+template <class Epi>
+__global__ __launch_bounds__(kPtThreads) void k_direct_lin(Grid3 g, const float *__restrict__ disp, Epi epi)
+{
+    const int p = point_index();
+    if (p >= g.N) return;
+    int i, j, k;
+    point_coords(g, p, i, j, k);
+    const long N = g.N;
+    Stencil2<float> s;
+    make_stencil2<float>(g, i, j, k, disp[p], disp[N + p], disp[2 * N + p], s);
+    float v[Epi::NF];
+#pragma unroll
+    for (int f = 0; f < Epi::NF; ++f) v[f] = gather2<float>(epi.field(f), s);
+    epi.finish(p, v);
+}
+
 // Eighth-order central first derivatives on the periodic grid (Section 3.2,
 // the FD kernel replacing the spectral gradient and divergence):
 //   df/dx ~= (1/h) sum_{q=1..4} c_q (f(x + q h) - f(x - q h)),
@@ -921,10 +1008,18 @@ void launch_fd8_div(lddmm_plan *P, const float *v, float *out)
     check_hip(hipGetLastError(), "k_fd8_div");
 }
 
+static bool linear_ip(const lddmm_plan *P) { return (P->cfg.flags & LDDMM_FLAG_LINEAR_IP) != 0; }
+
 void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa)
 {
     Scope s(P, K_DEPARTURE);
-    hipLaunchKernelGGL(k_departure, blocks_of(P), dim3(kPtThreads), 0, P->stream, v, dX, dXa,
+    if (linear_ip(P)) {
+        hipLaunchKernelGGL(k_departure<1>, blocks_of(P), dim3(kPtThreads), 0, P->stream, v, dX, dXa, grid_of(P),
+                           P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2]);
+        check_hip(hipGetLastError(), "k_departure");
+        return;  // the trilinear gathers stage no boxes
+    }
+    hipLaunchKernelGGL(k_departure<3>, blocks_of(P), dim3(kPtThreads), 0, P->stream, v, dX, dXa,
                        grid_of(P), P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2]);
     check_hip(hipGetLastError(), "k_departure");
     if (dX == P->dX && dXa == P->dXa) launch_tile_boxes(P);
@@ -1062,6 +1157,12 @@ void launch_tile_boxes(lddmm_plan *P)
 template <class Epi>
 static void tiled(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
 {
+    if (linear_ip(P)) {
+        Scope s(P, kid);
+        hipLaunchKernelGGL((k_direct_lin<Epi>), blocks_of(P), dim3(kPtThreads), 0, P->stream, grid_of(P), disp, epi);
+        check_hip(hipGetLastError(), "k_direct_lin");
+        return;
+    }
     const int mode = (Epi::NF > 1 && P->gather_mode3 >= 0) ? P->gather_mode3 : gather_mode(P);
     switch (mode) {
     case 0: {

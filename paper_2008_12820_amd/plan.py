@@ -7,7 +7,7 @@ from . import _lib as L
 
 class Plan:
     def __init__(self, shape, nt, reg=L.REG_H1S, beta=1e-2, leray=False, device=None,
-                 stream=None, transport_only=False, fd8=False):
+                 stream=None, transport_only=False, fd8=False, linear_ip=False):
         self.shape = tuple(int(s) for s in shape)
         self.nt = int(nt)
         self.reg = int(reg)
@@ -19,7 +19,8 @@ class Plan:
         self.stream = s
         self.cfg = L.make_config(self.shape, self.nt, self.reg, self.beta, self.leray,
                                  (L.FLAG_TRANSPORT_ONLY if transport_only else 0) |
-                                 (L.FLAG_FD8 if fd8 else 0))
+                                 (L.FLAG_FD8 if fd8 else 0) |
+                                 (L.FLAG_LINEAR_IP if linear_ip else 0))
         with torch.cuda.device(self.device):
             self._h = L.lddmm_plan_create(self.cfg, s.cuda_stream)
 
@@ -84,6 +85,20 @@ class Plan:
         """kind "inva" ((beta A)^-1), "invh0" (inner PCG on eq. h0-pc) or
         "2linvh0" (the same on the half grid)"""
         L.lddmm_set_preconditioner(self._h, {"inva": 0, "invh0": 1, "2linvh0": 2}[kind], eps_h0, max_inner)
+
+    def set_beta(self, beta):
+        L.lddmm_set_beta(self._h, beta)
+        self.beta = float(beta)
+
+    def gn_solve(self, v, beta_target, eps_n=5e-2, max_gn=10, max_pcg=50, rtol=0.0, continuation=True,
+                 pc="2linvh0", eps_h0=1e-3, max_inner=50, pc_switch=0.5):
+        """Gauss-Newton-Krylov solve with beta-continuation (lddmm_gn_solve);
+        v (initial velocity) is overwritten with the result; returns the report."""
+        rep = L.lddmm_gn_solve(self._h, v, beta_target, eps_n=eps_n, rtol=rtol, eps_h0=eps_h0,
+                               pc_switch=pc_switch, max_gn=max_gn, max_pcg=max_pcg, max_inner=max_inner,
+                               continuation=continuation, pc_kind={"inva": 0, "invh0": 1, "2linvh0": 2}[pc])
+        self.beta = float(beta_target)
+        return rep
 
     def apply_h0(self, s, out=None):
         o = out if out is not None else self._vector()

@@ -79,9 +79,10 @@ def test_null_pointers_and_status_strings():
 
 
 def test_config_flags():
-    """FD8 and transport-only are the known flag bits; any other bit is rejected."""
+    """FD8, trilinear interpolation and transport-only are the known flag bits;
+    any other bit is rejected."""
     out = ctypes.c_size_t()
-    for flags, want in ((L.FLAG_FD8, L.OK), (L.FLAG_FD8 | L.FLAG_TRANSPORT_ONLY, L.OK), (4, L.EINVAL),
-                        (8 | L.FLAG_FD8, L.EINVAL)):
+    for flags, want in ((L.FLAG_FD8, L.OK), (L.FLAG_FD8 | L.FLAG_TRANSPORT_ONLY, L.OK),
+                        (L.FLAG_LINEAR_IP | L.FLAG_FD8, L.OK), (8, L.EINVAL), (16 | L.FLAG_FD8, L.EINVAL)):
         cfg = L.make_config((16, 16, 16), 2, 2, 1e-2, flags=flags)
         assert L.lib().lddmm_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == want, flags
