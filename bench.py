@@ -334,6 +334,39 @@ def bench_autograd(torch, dev, n=512, nt=8):
             "torch_peak_GB": torch_peak / 1e9, "rel_l2_autograd_vs_plain_gradient": rel}
 
 
+def bench_syn(torch, dev, n):
+    """The paper's SYN problem (Section 4) as in its scaling table: 5 Gauss-
+    Newton iterations of 10 PCG steps, InvA, beta = 1e-3, N_t = 4, trilinear
+    interpolation, FD first derivatives; m1 = the template transported by the
+    SYN velocity.  Time of the whole solve from v = 0."""
+    import synth
+    from paper_2008_12820_amd import Plan
+
+    log(f"SYN workload {n}")
+    m0, vsyn = synth.syn_problem(n)
+    m0d = torch.from_numpy(synth.f32(m0)).to(dev)
+    vd = torch.from_numpy(synth.f32(vsyn)).to(dev)
+    P = Plan(n, 4, reg=2, beta=1e-3, device=dev, linear_ip=True, fd8=True)
+    P.autotune()
+    m1d = P.transport_forward(m0d, vd)
+    P.set_images(m0d, m1d)
+    v = torch.zeros_like(vd)
+    kw = dict(eps_n=0.0, max_gn=5, max_pcg=10, rtol=1e-12, continuation=False, pc="inva")
+    P.gn_solve(v.clone(), 1e-3, **{**kw, "max_gn": 1, "max_pcg": 2})  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = P.gn_solve(v, 1e-3, **kw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    mis = P.objective()[1]
+    P.set_velocity(torch.zeros_like(vd))
+    mis0 = P.objective()[1]
+    P.close()
+    return {"grid": list(n), "gn_iters": rep["gn_iters"], "pcg_iters": rep["pcg_iters"], "seconds": el,
+            "relative_mismatch": mis / mis0, "gnorm_rel": rep["gnorm_rel"],
+            "paper_v100_1gpu_seconds": 3.32 if n == (256, 256, 256) else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,6 +564,7 @@ def main():
                                    "GBps": 5 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9}
         del src, dst
     out["fft_vs_rocfft"] = fft_comparison(torch, dev, n)
+    out["syn_workload"] = bench_syn(torch, dev, n)
     if args.batched:
         out["batched"] = bench_batched(torch, dev)
     if args.autograd:
