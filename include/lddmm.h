@@ -359,6 +359,9 @@ lddmm_status lddmm_tuning(lddmm_plan *plan, char *buf, size_t len);
  * event time (ms) and launch count of kernel class id since the last reset
  * (lddmm_set_timing resets).  Ids 0 .. lddmm_num_kernels()-1. */
 lddmm_status lddmm_set_timing(lddmm_plan *plan, int32_t enable);
+/* The same for the launches of one kernel class only (two events per launch
+ * of that class, none elsewhere); lddmm_set_timing(plan, 0) turns it off. */
+lddmm_status lddmm_set_timing_only(lddmm_plan *plan, int32_t kernel_id);
 lddmm_status lddmm_get_timing(lddmm_plan *plan, int32_t kernel_id, double *total_ms,
                               int64_t *launches);
 int32_t lddmm_num_kernels(void);

@@ -86,6 +86,7 @@ def lib():
             "lddmm_apply_inv_reg": (st, [p, p, p]),
             "lddmm_set_preconditioner": (st, [p, i32, d, i32]),
             "lddmm_set_beta": (st, [p, d]),
+            "lddmm_set_timing_only": (st, [p, i32]),
             "lddmm_gn_solve": (st, [p, P(SolveOpts), p, P(SolveReport)]),
             "lddmm_apply_h0": (st, [p, p, p]),
             "lddmm_apply_invh0": (st, [p, p, d, i32, p, P(i32)]),
@@ -352,6 +353,10 @@ def lddmm_tuning(plan):
 
 def lddmm_set_timing(plan, enable):
     _check(lib().lddmm_set_timing(plan, int(bool(enable))), "set_timing")
+
+
+def lddmm_set_timing_only(plan, kernel_id):
+    _check(lib().lddmm_set_timing_only(plan, int(kernel_id)), "set_timing_only")
 
 
 def lddmm_get_timing(plan, kernel_id):

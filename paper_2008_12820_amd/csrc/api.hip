@@ -34,7 +34,7 @@ const char *kernel_name(int id)
 Scope::Scope(lddmm_plan *p, int k) : P(p), kid(k)
 {
     PlanTiming &T = P->timing;
-    if (!T.on) return;
+    if (!T.on || (T.only >= 0 && T.only != k)) return;
     if (T.used == T.pool.size()) {
         hipEvent_t a, b;
         check_hip(hipEventCreate(&a), "hipEventCreate");
@@ -1158,6 +1158,19 @@ lddmm_status lddmm_set_timing(lddmm_plan *P, int32_t enable)
         need(P, "plan");
         check_hip(hipStreamSynchronize(P->stream), "stream sync");
         P->timing.on = enable != 0;
+        P->timing.only = -1;
+        P->timing.used = 0;
+    });
+}
+
+lddmm_status lddmm_set_timing_only(lddmm_plan *P, int32_t kernel_id)
+{
+    return guard([&] {
+        need(P, "plan");
+        if (kernel_id < 0 || kernel_id >= K_NUM_KERNELS) fail(LDDMM_EINVAL, "kernel id out of range");
+        check_hip(hipStreamSynchronize(P->stream), "stream sync");
+        P->timing.on = true;
+        P->timing.only = kernel_id;
         P->timing.used = 0;
     });
 }

@@ -49,6 +49,7 @@ constexpr size_t kLdsMax = 160 * 1024;
 
 struct PlanTiming {
     bool on = false;
+    int only = -1;  // >= 0: bracket only launches of this kernel class
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
     std::vector<int> kid;  // kernel class of each used pair
     size_t used = 0;

@@ -190,8 +190,14 @@ class Plan:
     def tuning(self):
         return L.lddmm_tuning(self._h)
 
-    def set_timing(self, enable):
-        L.lddmm_set_timing(self._h, enable)
+    def set_timing(self, enable, only=None):
+        """enable per-kernel HIP-event timing; only: a kernel class name to
+        bracket alone (the other launches stay unbracketed)"""
+        if enable and only is not None:
+            ids = {L.lddmm_kernel_name(k): k for k in range(L.lddmm_num_kernels())}
+            L.lddmm_set_timing_only(self._h, ids[only])
+        else:
+            L.lddmm_set_timing(self._h, enable)
 
     def timing(self):
         """{kernel name: (total ms, launches)} since the last set_timing."""
