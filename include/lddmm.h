@@ -342,14 +342,16 @@ lddmm_status lddmm_apply_2linvh0(lddmm_plan *plan, const float *r, double tol, i
  * lddmm_autotune picks among 0..4 by timing once the plan has a velocity.
  * EINVAL for a mode outside -1..4. */
 lddmm_status lddmm_set_gather_mode(lddmm_plan *plan, int32_t mode);
-/* Overlap (enable = 1) or serialise (0, the default) the forward transform of
- * the assembly's first operand -- the incremental velocity in a Hessian
- * matvec (eq. matvec), the velocity in a reduced gradient (eq. reducedgrad) --
- * with the transport sweeps: it depends on the input alone, so it runs on a
- * side stream of the plan (created on first use, default priority) forked
- * from and joined back into the plan's stream.  Results are bitwise the same
- * either way; calls made under stream capture always serialise.  Kernels of
- * the two streams then share the device, so per-kernel timings overlap. */
+/* Overlap (enable = 1, the default) or serialise (0) the forward transform
+ * of the assembly's first operand -- the incremental velocity in a Hessian
+ * matvec (eq. matvec), the velocity in a reduced gradient (eq.
+ * reducedgrad) -- with the transport sweeps: it depends on the input alone,
+ * so it runs on a side stream of the plan (created on first use, default
+ * priority), forked from the plan's stream after the incremental-state start
+ * (matvec) or at the start (gradient) and joined back before the assembly.
+ * Results are bitwise the same either way; calls made under stream capture
+ * always serialise.  Kernels of the two streams then share the device, so
+ * per-kernel timings of the overlapped sweeps include that sharing. */
 lddmm_status lddmm_set_overlap(lddmm_plan *plan, int32_t enable);
 /* NUL-terminated report of the tile shapes in use (len bytes at most). */
 lddmm_status lddmm_tuning(lddmm_plan *plan, char *buf, size_t len);

@@ -331,8 +331,10 @@ void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
     const long N = P->N;
     const int nt = P->nt;
     float *mt[2] = {P->mt, P->mt + N};
-    const bool started = assemble_prefetch(P, vt);
     launch_incstate_init(P, vt, mt[0]);
+    // forked after the start gather, which streams at full bandwidth: the
+    // transform then shares the device with the issue-bound gather steps
+    const bool started = assemble_prefetch(P, vt);
     for (int j = 1; j < nt; ++j)
         launch_incstate_step(P, mt[(j - 1) & 1], P->src + (long)(j - 1) * N, mt[j & 1]);
     const float *mtN = mt[(nt - 1) & 1];

@@ -64,7 +64,7 @@ struct lddmm_plan {
     // only the final assembly needs runs beside the transport sweeps
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    int overlap = 0;  // lddmm_set_overlap
+    int overlap = 1;  // lddmm_set_overlap (on by default)
     // preconditioner (lddmm_set_preconditioner): 0 InvA, 1 InvH0
     int pc_kind = 0, pc_max_inner = 50;
     double pc_eps_h0 = 1e-3;
