@@ -1215,7 +1215,7 @@ lddmm_status lddmm_tuning(lddmm_plan *P, char *buf, size_t len)
         need(P, "plan");
         need(buf, "buf");
         const std::string r = tuning_report(P) + " gather_mode=" + std::to_string(P->gather_mode) +
-                              "/" + std::to_string(P->gather_mode3) +
+                              "/" + std::to_string(P->gather_mode3) + " departure_mode=" + std::to_string(P->departure_mode) +
                               (P->gather_tuned ? " (tuned)" : "");
         if (len == 0) fail(LDDMM_EINVAL, "len is 0");
         const size_t n = std::min(len - 1, r.size());
@@ -1298,6 +1298,7 @@ lddmm_status lddmm_set_gather_mode(lddmm_plan *P, int32_t mode)
         if (mode < -1 || mode > 4) fail(LDDMM_EINVAL, "mode must be -1 .. 4");
         P->gather_mode = mode;
         P->gather_mode3 = -1;
+        P->departure_mode = mode < 0 ? -1 : mode == 0 ? 0 : (mode & 1) ? 1 : 2;
     });
 }
 

@@ -105,6 +105,7 @@ struct lddmm_plan {
     int boxes_valid = 0;
     int gather_mode = -1;    // 0 direct, 1/2 box tiles 2x4x64/4x4x64, 3/4 the same pipelined, -1 heuristic
     int gather_mode3 = -1;   // the same for three-field gathers; -1: follow gather_mode
+    int departure_mode = -1; // 0 direct, 1/2 box tiles 2x4x64/4x4x64, -1 the gather strategy's tiles
     int gather_tuned = 0;
     int pipe_grid[2] = {0, 0};  // workgroups of the pipelined gathers [2x4, 4x4] (0: not yet sized)
     float gather_ms[1] = {0.f};

@@ -702,6 +702,168 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
     }
 }
 
+// Departure points through an LDS box (cubic interpolation): per direction
+// the tile's predictor stencils at x -+ dt v(x) are reduced to their extents,
+// the three velocity components are staged through the box in turn and the
+// FP64 contraction runs from LDS in the order of gather<double>, so X and Xa
+// are bitwise those of k_departure<3>.  Stencils outside the box gather from
+// global memory.  Nothing per point stays in registers across
+// the component and point loops; v(x) is read again where it is needed.
+__device__ __forceinline__ double predictor_disp(const float *__restrict__ v, long N, long p, int c, double sdt,
+                                                 double ihc)
+{
+    // the clamped displacement of axis_stencil<double>
+    double d = sdt * (double)v[(long)c * N + p] * ihc;
+    const double lim = 1048576.0;
+    d = d > lim ? lim : d;
+    return d >= -lim ? d : -lim;
+}
+
+template <int T1, int T2>
+__global__ __launch_bounds__(256) void k_departure_box(const float *__restrict__ v, float *__restrict__ dX,
+                                                       float *__restrict__ dXa, Grid3 g, int nt2, int nt3, double dt,
+                                                       double ih1, double ih2, double ih3)
+{
+    using BC = BoxCfg<T1, T2>;
+    constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2;
+    constexpr int S1 = BR2 * kPad3;
+    constexpr int RPW = (BR1 * BR2 + 3) / 4;
+    extern __shared__ float box[];
+    __shared__ int red[4][6];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int t3 = tb % nt3, rr = tb / nt3, t2 = rr % nt2, t1 = rr / nt2;
+    const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
+    const long N = g.N;
+    const double ih[3] = {ih1, ih2, ih3};
+#pragma unroll 1
+    for (int dir = 0; dir < 2; ++dir) {
+        const double sgn = dir == 0 ? -1.0 : 1.0;
+        float *__restrict__ out = dir == 0 ? dX : dXa;
+        const double sdt = sgn * dt;
+        int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
+        int hi[3] = {(int)0x80000000, (int)0x80000000, (int)0x80000000};
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+            if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
+            const long p = ((long)i * g.n2 + j) * g.n3 + k;
+            const int ijk[3] = {i, j, k};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int b = ijk[c] + (int)floor(predictor_disp(v, N, p, c, sdt, ih[c])) - 1;
+                lo[c] = min(lo[c], b);
+                hi[c] = max(hi[c], b);
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = min(lo[c], __shfl_xor(lo[c], off));
+                hi[c] = max(hi[c], __shfl_xor(hi[c], off));
+            }
+        if (dir > 0) __syncthreads();  // the first direction's box and extents are read
+        if (lane == 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                red[w][c] = lo[c];
+                red[w][c + 3] = hi[c];
+            }
+        __syncthreads();
+        int L[3], H[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            L[c] = min(min(red[0][c], red[1][c]), min(red[2][c], red[3][c]));
+            H[c] = max(max(red[0][c + 3], red[1][c + 3]), max(red[2][c + 3], red[3][c + 3]));
+        }
+        if (L[0] > H[0]) return;  // no point of the tile inside the grid (uniform)
+        const int B1 = (int)min((long)H[0] + 4 - L[0], (long)BR1);
+        const int B2 = (int)min((long)H[1] + 4 - L[1], (long)BR2);
+        const int B3 = (int)min((long)H[2] + 4 - L[2], (long)kPad3);
+        const bool has0 = lane < B3, has1 = lane + 64 < B3;
+        const unsigned k0 = (unsigned)wrapg(L[2] + lane, g.n3), k1 = (unsigned)wrapg(L[2] + lane + 64, g.n3);
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
+            const float *__restrict__ src = v + (long)c * N;
+            const double ihc = c == 0 ? ih1 : c == 1 ? ih2 : ih3;
+            float r0[RPW], r1[RPW];
+#pragma unroll
+            for (int q = 0; q < RPW; ++q) {
+                const int r = w + 4 * q, a = r / BR2, b = r - a * BR2;
+                r0[q] = r1[q] = 0.f;
+                if (a < B1 && b < B2) {
+                    const float *grow = src + ((long)wrapg(L[0] + a, g.n1) * g.n2 + wrapg(L[1] + b, g.n2)) * g.n3;
+                    if (has0) r0[q] = grow[k0];
+                    if (has1) r1[q] = grow[k1];
+                }
+            }
+            if (c > 0) __syncthreads();  // the previous component's stencils are read
+#pragma unroll
+            for (int q = 0; q < RPW; ++q) {
+                const int r = w + 4 * q, a = r / BR2, b = r - a * BR2;
+                if (a < B1 && b < B2) {
+                    float *brow = box + r * kPad3;
+                    if (has0) brow[lane] = r0[q];
+                    if (has1) brow[lane + 64] = r1[q];
+                }
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int q = 0; q < PPT; ++q) {
+                const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+                if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
+                const long p = ((long)i * g.n2 + j) * g.n3 + k;
+                const double d1 = predictor_disp(v, N, p, 0, sdt, ih1), d2 = predictor_disp(v, N, p, 1, sdt, ih2),
+                             d3 = predictor_disp(v, N, p, 2, sdt, ih3);
+                const double f1 = floor(d1), f2 = floor(d2), f3 = floor(d3);
+                double w1[4], w2[4], w3[4];
+                lagrange4<double>(d1 - f1, w1);
+                lagrange4<double>(d2 - f2, w2);
+                lagrange4<double>(d3 - f3, w3);
+                const int b1 = i + (int)f1 - 1, b2 = j + (int)f2 - 1, b3 = k + (int)f3 - 1;
+                const int o1 = b1 - L[0], o2 = b2 - L[1], o3 = b3 - L[2];
+                double acc = 0.0;
+                if (o1 <= B1 - 4 && o2 <= B2 - 4 && o3 <= B3 - 4) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const float *pl = box + (o1 + a) * S1 + o2 * kPad3 + o3;
+                        double acc2 = 0.0;
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const float *row = pl + b * kPad3;
+                            acc2 = accum<double>(
+                                b, w2,
+                                row3<double>((double)row[0], (double)row[1], (double)row[2], (double)row[3], w3),
+                                acc2);
+                        }
+                        acc = accum<double>(a, w1, acc2, acc);
+                    }
+                } else {  // from global memory, wrapped per node
+#pragma unroll 1
+                    for (int a = 0; a < 4; ++a) {
+                        const long ra = (long)wrapg(b1 + a, g.n1) * g.n2;
+                        double acc2 = 0.0;
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const float *row = src + (ra + wrapg(b2 + b, g.n2)) * g.n3;
+                            acc2 = accum<double>(b, w2,
+                                                 row3<double>((double)row[wrapg(b3, g.n3)],
+                                                              (double)row[wrapg(b3 + 1, g.n3)],
+                                                              (double)row[wrapg(b3 + 2, g.n3)],
+                                                              (double)row[wrapg(b3 + 3, g.n3)], w3),
+                                                 acc2);
+                        }
+                        acc = accum<double>(a, w1, acc2, acc);
+                    }
+                }
+                out[(long)c * N + p] = (float)(sgn * 0.5 * dt * ((double)src[p] + acc) * ihc);
+            }
+        }
+    }
+}
+
 // Persistent, software-pipelined box gathers (one field, extents table
 // required): a fixed grid of workgroups walks the tiles, each XCD a
 // contiguous run of them; while a workgroup interpolates tile k from one LDS
@@ -1010,6 +1172,30 @@ void launch_fd8_div(lddmm_plan *P, const float *v, float *out)
 
 static bool linear_ip(const lddmm_plan *P) { return (P->cfg.flags & LDDMM_FLAG_LINEAR_IP) != 0; }
 
+static int gather_mode(const lddmm_plan *P);
+template <int T1, int T2>
+static unsigned tiles_of(const lddmm_plan *P, int &nt2, int &nt3);
+
+// departure strategy: P->departure_mode 0 direct, 1 box tiles 2x4x64, 2 box
+// tiles 4x4x64; -1 the tile shape of the gather strategy
+static int departure_mode(const lddmm_plan *P)
+{
+    if (P->departure_mode >= 0) return P->departure_mode;
+    const int m = gather_mode(P);
+    return m == 0 ? 0 : (m == 1 || m == 3) ? 1 : 2;
+}
+
+template <int T1, int T2>
+static void launch_departure_box(lddmm_plan *P, const float *v, float *dX, float *dXa)
+{
+    int nt2, nt3;
+    const unsigned ntiles = tiles_of<T1, T2>(P, nt2, nt3);
+    const size_t lds = sizeof(float) * BoxCfg<T1, T2>::CAP;
+    hipLaunchKernelGGL((k_departure_box<T1, T2>), dim3(ntiles), dim3(256), lds, P->stream, v, dX, dXa, grid_of(P),
+                       nt2, nt3, P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2]);
+    check_hip(hipGetLastError(), "k_departure_box");
+}
+
 void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa)
 {
     Scope s(P, K_DEPARTURE);
@@ -1019,9 +1205,15 @@ void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa)
         check_hip(hipGetLastError(), "k_departure");
         return;  // the trilinear gathers stage no boxes
     }
-    hipLaunchKernelGGL(k_departure<3>, blocks_of(P), dim3(kPtThreads), 0, P->stream, v, dX, dXa,
-                       grid_of(P), P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2]);
-    check_hip(hipGetLastError(), "k_departure");
+    switch (departure_mode(P)) {
+    case 0:
+        hipLaunchKernelGGL(k_departure<3>, blocks_of(P), dim3(kPtThreads), 0, P->stream, v, dX, dXa, grid_of(P),
+                           P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2]);
+        check_hip(hipGetLastError(), "k_departure");
+        break;
+    case 1: launch_departure_box<2, 4>(P, v, dX, dXa); break;
+    default: launch_departure_box<4, 4>(P, v, dX, dXa); break;
+    }
     if (dX == P->dX && dXa == P->dXa) launch_tile_boxes(P);
 }
 
@@ -1234,6 +1426,32 @@ void autotune_gather(lddmm_plan *P)
             }
         }
         P->gather_mode3 = bm3;
+    }
+    // departure points (bitwise the same under every strategy, so the plan's
+    // own fields are recomputed in place)
+    if (P->departure_mode < 0 && P->v && P->dX && P->dXa) {
+        float bestd = 1e30f;
+        int bd = 2;
+        for (int m = 0; m < 3; ++m) {
+            P->departure_mode = m;
+            hipEvent_t a, b;
+            check_hip(hipEventCreate(&a), "hipEventCreate");
+            check_hip(hipEventCreate(&b), "hipEventCreate");
+            launch_departure(P, P->v, P->dX, P->dXa);
+            check_hip(hipEventRecord(a, P->stream), "hipEventRecord");
+            for (int r = 0; r < 3; ++r) launch_departure(P, P->v, P->dX, P->dXa);
+            check_hip(hipEventRecord(b, P->stream), "hipEventRecord");
+            check_hip(hipEventSynchronize(b), "hipEventSynchronize");
+            float ms = 0.f;
+            check_hip(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            if (ms < bestd) {
+                bestd = ms;
+                bd = m;
+            }
+        }
+        P->departure_mode = bd;
     }
     P->gather_tuned = 1;
 }
