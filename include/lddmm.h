@@ -338,8 +338,11 @@ lddmm_status lddmm_apply_2linvh0(lddmm_plan *plan, const float *r, double tol, i
  * resident grid of workgroups that stage the next tile's box while they
  * interpolate the current one (one-field gathers at the plan's own
  * departure points; other gathers take 1 or 2), -1 the default heuristic.
- * Every strategy computes the same tensor-product sum in the same order.
- * lddmm_autotune picks among 0..4 by timing once the plan has a velocity.
+ * The FP64 departure-point kernel follows the tile shape (0 direct, 1 and
+ * 3 boxes of 2x4x64, 2 and 4 boxes of 4x4x64).  Every strategy computes
+ * the same tensor-product sum in the same order, so results are bitwise
+ * equal.  lddmm_autotune picks among 0..4 (and the departure strategy on
+ * its own) by timing once the plan has a velocity.
  * EINVAL for a mode outside -1..4. */
 lddmm_status lddmm_set_gather_mode(lddmm_plan *plan, int32_t mode);
 /* Overlap (enable = 1, the default) or serialise (0) the forward transform
