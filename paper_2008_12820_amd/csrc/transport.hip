@@ -349,6 +349,18 @@ __device__ __forceinline__ int wrapg(int x, int n)
     return x < 0 ? x + n : x;
 }
 
+// Direct global-to-LDS load of one dword per active lane: lane l's value
+// lands at lds + l (the row base is wave-uniform), with no register round
+// trip; completion is tracked by the vector-memory counter, so a wait on it
+// precedes the barrier that publishes the box.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+__device__ __forceinline__ void load_to_lds(const float *g, float *lds)
+{
+    __builtin_amdgcn_global_load_lds((glb_void_t *)const_cast<float *>(g), (lds_void_t *)lds, 4, 0, 0);
+}
+__device__ __forceinline__ void wait_lds_loads() { __builtin_amdgcn_s_waitcnt(0); }
+
 // displacements clamped to +-2^20 voxels (NaN to the lower bound), so that
 // every index derived from them stays a finite int
 __device__ __forceinline__ float clamp_disp(float d)
@@ -626,27 +638,18 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const float *__restrict__ src = epi.field(f);
-        float r0[RPW], r1[RPW];
-#pragma unroll
-        for (int q = 0; q < RPW; ++q) {
-            const int r = wu + 4 * q, a = r / BR2, b = r - a * BR2;
-            r0[q] = r1[q] = 0.f;
-            if (a < B1 && b < B2) {
-                const float *grow = src + ((long)wrapg(L1 + a, g.n1) * g.n2 + wrapg(L2 + b, g.n2)) * g.n3;
-                if (has0) r0[q] = grow[k0];
-                if (has1) r1[q] = grow[k1];
-            }
-        }
         if (f > 0) __syncthreads();  // the previous field's stencils are read
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int r = wu + 4 * q, a = r / BR2, b = r - a * BR2;
             if (a < B1 && b < B2) {
+                const float *grow = src + ((long)wrapg(L1 + a, g.n1) * g.n2 + wrapg(L2 + b, g.n2)) * g.n3;
                 float *brow = box + r * kPad3;
-                if (has0) brow[lane] = r0[q];
-                if (has1) brow[c1] = r1[q];
+                if (has0) load_to_lds(grow + k0, brow);
+                if (has1) load_to_lds(grow + k1, brow + 64);
             }
         }
+        wait_lds_loads();
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
@@ -788,27 +791,18 @@ __global__ __launch_bounds__(256) void k_departure_box(const float *__restrict__
         for (int c = 0; c < 3; ++c) {
             const float *__restrict__ src = v + (long)c * N;
             const double ihc = c == 0 ? ih1 : c == 1 ? ih2 : ih3;
-            float r0[RPW], r1[RPW];
-#pragma unroll
-            for (int q = 0; q < RPW; ++q) {
-                const int r = w + 4 * q, a = r / BR2, b = r - a * BR2;
-                r0[q] = r1[q] = 0.f;
-                if (a < B1 && b < B2) {
-                    const float *grow = src + ((long)wrapg(L[0] + a, g.n1) * g.n2 + wrapg(L[1] + b, g.n2)) * g.n3;
-                    if (has0) r0[q] = grow[k0];
-                    if (has1) r1[q] = grow[k1];
-                }
-            }
             if (c > 0) __syncthreads();  // the previous component's stencils are read
 #pragma unroll
             for (int q = 0; q < RPW; ++q) {
                 const int r = w + 4 * q, a = r / BR2, b = r - a * BR2;
                 if (a < B1 && b < B2) {
+                    const float *grow = src + ((long)wrapg(L[0] + a, g.n1) * g.n2 + wrapg(L[1] + b, g.n2)) * g.n3;
                     float *brow = box + r * kPad3;
-                    if (has0) brow[lane] = r0[q];
-                    if (has1) brow[lane + 64] = r1[q];
+                    if (has0) load_to_lds(grow + k0, brow);
+                    if (has1) load_to_lds(grow + k1, brow + 64);
                 }
             }
+            wait_lds_loads();
             __syncthreads();
 #pragma unroll 1
             for (int q = 0; q < PPT; ++q) {
@@ -866,10 +860,10 @@ __global__ __launch_bounds__(256) void k_departure_box(const float *__restrict__
 
 // Persistent, software-pipelined box gathers (one field, extents table
 // required): a fixed grid of workgroups walks the tiles, each XCD a
-// contiguous run of them; while a workgroup interpolates tile k from one LDS
-// box, the global loads of tile k+1's box are already in flight into
-// registers and land in the other box, so the staging latency hides behind
-// the arithmetic.  Same stencil sums, bitwise, as k_box.
+// contiguous run of them.  While a workgroup interpolates tile k from one
+// LDS box, tile k+1's box rows are already in flight straight into the other
+// box (global-to-LDS loads, no registers) together with its displacements;
+// one wait and one barrier per tile.  Same stencil sums, bitwise, as k_box.
 template <int T1, int T2, class Epi>
 __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restrict__ disp, Epi epi, int nt2,
                                                   int nt3, const TileBox *__restrict__ boxes, int ntiles)
@@ -884,7 +878,6 @@ __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restri
     // the wavefront index, wave-uniform: the compiler keeps what derives from
     // it (the rows of a point, their bounds and base addresses) in scalars
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wu = w;
     const long N = g.N;
     const float *__restrict__ src = epi.field(0);
     // tiles of this workgroup: XCD x = blockIdx % 8 owns tiles [x T / 8, (x+1) T / 8)
@@ -892,72 +885,64 @@ __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restri
     const int xcd = (int)blockIdx.x & 7, slot = (int)blockIdx.x >> 3, gx = (G + 7 - xcd) / 8;
     const int tbeg = xcd * per, tend = min(ntiles, tbeg + per);
     auto tile_at = [&](int kk) { return tbeg + slot + kk * gx; };
-    float r0[RPW], r1[RPW];
-    // Issue the staging loads of tile t (extents from the table) into r0/r1.
-    // Every load is issued, from a valid wrapped address (rows outside the
-    // box re-read the box's first row, columns past it the lane's first
-    // column): straight-line code lets the compiler wait for this tile's
-    // displacements without waiting for these loads.
-    auto fetch = [&](int t) {
+    // issue the box rows of tile t into bx (wavefront w: rows w, w + 4, ...)
+    auto fetch_to = [&](int t, float *bx) {
         const TileBox tbx = boxes[t];
-        const bool live = tbx.L[0] <= tbx.H[0];
-        const int L1 = live ? tbx.L[0] : 0, L2 = live ? tbx.L[1] : 0, L3 = live ? tbx.L[2] : 0;
-        const int B1 = live ? (int)min((long)tbx.H[0] + 4 - L1, (long)BR1) : 0;
-        const int B2 = live ? (int)min((long)tbx.H[1] + 4 - L2, (long)BR2) : 0;
-        const int B3 = live ? (int)min((long)tbx.H[2] + 4 - L3, (long)kPad3) : 0;
-        const unsigned k0 = (unsigned)wrapg(L3 + lane, g.n3);
-        const unsigned k1 = lane + 64 < B3 ? (unsigned)wrapg(L3 + lane + 64, g.n3) : k0;
+        if (tbx.L[0] > tbx.H[0]) return;  // no point of the tile inside the grid
+        const int L1 = tbx.L[0], L2 = tbx.L[1], L3 = tbx.L[2];
+        const int B1 = (int)min((long)tbx.H[0] + 4 - L1, (long)BR1);
+        const int B2 = (int)min((long)tbx.H[1] + 4 - L2, (long)BR2);
+        const int B3 = (int)min((long)tbx.H[2] + 4 - L3, (long)kPad3);
+        const unsigned k0 = (unsigned)wrapg(L3 + lane, g.n3), k1 = (unsigned)wrapg(L3 + lane + 64, g.n3);
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
-            const int r = wu + 4 * q, a0 = r / BR2, b0 = r - a0 * BR2;
-            const bool in = a0 < B1 && b0 < B2;
-            const int a = in ? a0 : 0, b = in ? b0 : 0;
-            const float *grow = src + ((long)wrapg(L1 + a, g.n1) * g.n2 + wrapg(L2 + b, g.n2)) * g.n3;
-            r0[q] = grow[k0];
-            r1[q] = grow[k1];
-        }
-    };
-    auto deposit = [&](float *bx) {
-#pragma unroll
-        for (int q = 0; q < RPW; ++q) {
-            const int r = wu + 4 * q;
-            if (r < BR1 * BR2) {
+            const int r = w + 4 * q, a = r / BR2, b = r - a * BR2;
+            if (a < B1 && b < B2) {
+                const float *grow = src + ((long)wrapg(L1 + a, g.n1) * g.n2 + wrapg(L2 + b, g.n2)) * g.n3;
                 float *brow = bx + r * kPad3;
-                brow[lane] = r0[q];
-                if (lane + 64 < kPad3) brow[lane + 64] = r1[q];
+                if (lane < B3) load_to_lds(grow + k0, brow);
+                if (lane + 64 < B3) load_to_lds(grow + k1, brow + 64);
             }
         }
     };
+    // the displacements of tile t's points (points outside the grid read point 0)
+    auto load_disp = [&](int t, float *e1, float *e2, float *e3) {
+        const int t3 = t % nt3, rr = t / nt3, t2 = rr % nt2, t1 = rr / nt2;
+        const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+            const long p = (i < g.n1 && j < g.n2 && k < g.n3) ? ((long)i * g.n2 + j) * g.n3 + k : 0;
+            e1[q] = disp[p];
+            e2[q] = disp[N + p];
+            e3[q] = disp[2 * N + p];
+        }
+    };
     if (tile_at(0) >= tend) return;  // uniform over the workgroup
-    fetch(tile_at(0));
-    deposit(boxes2);
+    float d1[PPT], d2[PPT], d3[PPT];
+    fetch_to(tile_at(0), boxes2);
+    load_disp(tile_at(0), d1, d2, d3);
+    wait_lds_loads();
     __syncthreads();
     for (int kk = 0;; ++kk) {
         const int t = tile_at(kk), tn = tile_at(kk + 1);
         const bool more = tn < tend;
         const int t3 = t % nt3, rr = t / nt3, t2 = rr % nt2, t1 = rr / nt2;
         const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
-        // this tile's displacements first: the wait for them must not wait
-        // for the next tile's staging loads, issued after them
-        // (straight-line loads: points outside the grid read point 0 and are
-        // skipped below)
-        float d1[PPT], d2[PPT], d3[PPT];
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-            const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
-            const long p = (i < g.n1 && j < g.n2 && k < g.n3) ? ((long)i * g.n2 + j) * g.n3 + k : 0;
-            d1[q] = disp[p];
-            d2[q] = disp[N + p];
-            d3[q] = disp[2 * N + p];
+        // the next tile's box goes to the buffer last read two tiles ago (every
+        // wave has passed the barrier that ended that tile)
+        float n1[PPT], n2[PPT], n3[PPT];
+        if (more) {
+            fetch_to(tn, boxes2 + ((kk + 1) & 1) * CAP);
+            load_disp(tn, n1, n2, n3);
         }
-        const TileBox tbx = boxes[t];
-        fetch(more ? tn : t);  // the last tile re-reads its own box, unused
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             d1[q] = clamp_disp(d1[q]);
             d2[q] = clamp_disp(d2[q]);
             d3[q] = clamp_disp(d3[q]);
         }
+        const TileBox tbx = boxes[t];
         const float *cur = boxes2 + (kk & 1) * CAP;
         const int L1 = tbx.L[0], L2 = tbx.L[1], L3 = tbx.L[2];
         const int B1 = (int)min((long)tbx.H[0] + 4 - L1, (long)BR1);
@@ -1008,8 +993,6 @@ __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restri
             }
             val[q] = acc;
         }
-        // the next box lands in the other buffer, last read two tiles ago
-        if (more) deposit(boxes2 + ((kk + 1) & 1) * CAP);
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
@@ -1019,7 +1002,14 @@ __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restri
             }
         }
         if (!more) break;  // uniform
+        wait_lds_loads();
         __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            d1[q] = n1[q];
+            d2[q] = n2[q];
+            d3[q] = n3[q];
+        }
     }
 }
 
