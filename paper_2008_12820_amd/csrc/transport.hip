@@ -369,49 +369,72 @@ __device__ __forceinline__ float clamp_disp(float d)
     return fminf(fmaxf(d, -lim), lim);
 }
 
-// epilogues: which fields are gathered and what is written per point
+// Epilogues: which fields are gathered and what is written per point.  Each
+// splits its work into load(p), every pointwise input, and store(p, v, in):
+// the gather kernels issue the loads of all of a thread's points before the
+// first store, since a load placed after a store to another array cannot be
+// moved above it (the arrays may alias as far as the compiler knows) and
+// would cost one memory round trip per point and step.
+struct NoIn {
+};
 struct EpiCopy {  // out = I[src]
     static constexpr int NF = 1;
+    using In = NoIn;
     const float *src;
     float *dst;
     __device__ const float *field(int) const { return src; }
-    __device__ void finish(long p, const float *v) const { dst[p] = v[0]; }
+    __device__ In load(long) const { return {}; }
+    __device__ void store(long p, const float *v, const In &) const { dst[p] = v[0]; }
 };
 struct EpiAdj {  // out = scale * c * I[src]
     static constexpr int NF = 1;
+    struct In {
+        float c;
+    };
     const float *src, *coef;
     float *dst;
     float scale;
     __device__ const float *field(int) const { return src; }
-    __device__ void finish(long p, const float *v) const { dst[p] = scale * coef[p] * v[0]; }
+    __device__ In load(long p) const { return {coef[p]}; }
+    __device__ void store(long p, const float *v, const In &in) const { dst[p] = scale * in.c * v[0]; }
 };
 struct EpiInc {  // out = I[src] - dt/2 s
     static constexpr int NF = 1;
+    struct In {
+        float s;
+    };
     const float *src, *s;
     float *dst;
     float hdt;
     __device__ const float *field(int) const { return src; }
-    __device__ void finish(long p, const float *v) const { dst[p] = v[0] - hdt * s[p]; }
+    __device__ In load(long p) const { return {s[p]}; }
+    __device__ void store(long p, const float *v, const In &in) const { dst[p] = v[0] - hdt * in.s; }
 };
 struct EpiAdjCoef {  // c = 1 + dt/2 (delta_a + delta (1 + dt delta_a)), delta_a = I[delta](Xa)
     static constexpr int NF = 1;
+    struct In {
+        float d;
+    };
     const float *delta;
     float *coef;
     float dt;
     __device__ const float *field(int) const { return delta; }
-    __device__ void finish(long p, const float *v) const
+    __device__ In load(long p) const { return {delta[p]}; }
+    __device__ void store(long p, const float *v, const In &in) const
     {
         const float da = v[0];
-        coef[p] = 1.f + 0.5f * dt * (da + delta[p] * (1.f + dt * da));
+        coef[p] = 1.f + 0.5f * dt * (da + in.d * (1.f + dt * da));
     }
 };
 struct EpiVec3 {  // three fields (stride N): out_c = I[src_c]
     static constexpr int NF = 3;
+    using In = NoIn;
     const float *src;
     float *dst;
     long N;
     __device__ const float *field(int f) const { return src + f * N; }
-    __device__ void finish(long p, const float *v) const
+    __device__ In load(long) const { return {}; }
+    __device__ void store(long p, const float *v, const In &) const
     {
         dst[p] = v[0];
         dst[N + p] = v[1];
@@ -423,9 +446,14 @@ struct EpiVec3 {  // three fields (stride N): out_c = I[src_c]
 // I[grad m_j](X) and grad m_{j+1} the epilogue forms every step's source
 //   s_j = v~(X) . I[grad m_j](X) + v~ . grad m_{j+1},   j = 0 .. N_t - 1,
 // writes m~_1 = -dt/2 s_0 and keeps s_1 .. s_{N_t-1} for the later steps.
+// With N_t fixed at compile time (NTC > 0) all 6 N_t + 3 inputs are loaded
+// before the first store.
 template <int NTC>
 struct EpiIncSrc {
     static constexpr int NF = 3;
+    struct In {
+        float v[3], gx[NTC > 0 ? NTC : 1][3], g1[NTC > 0 ? NTC : 1][3];
+    };
     const float *vt;        // v~ (stride N): gathered and read pointwise
     const float *GX, *G;    // I[grad m_j](X) and grad m_j, three fields per j
     float *mt1, *src;       // m~_1; s_j at src + (j - 1) N
@@ -433,20 +461,44 @@ struct EpiIncSrc {
     int nt_rt;
     float hdt;
     __device__ const float *field(int f) const { return vt + f * N; }
-    __device__ void finish(long p, const float *x) const
+    __device__ In load(long p) const
     {
-        const int nt = NTC > 0 ? NTC : nt_rt;
-        const float v0 = vt[p], v1 = vt[N + p], v2 = vt[2 * N + p];
+        In in;
 #pragma unroll
-        for (int j = 0; j < nt; ++j) {
-            const float *gx = GX + (long)j * 3 * N, *g1 = G + (long)(j + 1) * 3 * N;
-            const float s = (x[0] * gx[p] + x[1] * gx[N + p] + x[2] * gx[2 * N + p]) +
-                            (v0 * g1[p] + v1 * g1[N + p] + v2 * g1[2 * N + p]);
-            if (j == 0)
-                mt1[p] = -hdt * s;
-            else
-                src[(long)(j - 1) * N + p] = s;
+        for (int c = 0; c < 3; ++c) in.v[c] = vt[c * N + p];
+        if constexpr (NTC > 0) {
+#pragma unroll
+            for (int j = 0; j < NTC; ++j)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    in.gx[j][c] = GX[((long)j * 3 + c) * N + p];
+                    in.g1[j][c] = G[((long)(j + 1) * 3 + c) * N + p];
+                }
         }
+        return in;
+    }
+    __device__ void store(long p, const float *x, const In &in) const
+    {
+        const float v0 = in.v[0], v1 = in.v[1], v2 = in.v[2];
+        if constexpr (NTC > 0) {
+#pragma unroll
+            for (int j = 0; j < NTC; ++j)
+                put(p, j, (x[0] * in.gx[j][0] + x[1] * in.gx[j][1] + x[2] * in.gx[j][2]) +
+                              (v0 * in.g1[j][0] + v1 * in.g1[j][1] + v2 * in.g1[j][2]));
+        } else {
+            for (int j = 0; j < nt_rt; ++j) {
+                const float *gx = GX + (long)j * 3 * N, *g1 = G + (long)(j + 1) * 3 * N;
+                put(p, j, (x[0] * gx[p] + x[1] * gx[N + p] + x[2] * gx[2 * N + p]) +
+                              (v0 * g1[p] + v1 * g1[N + p] + v2 * g1[2 * N + p]));
+            }
+        }
+    }
+    __device__ void put(long p, int j, float s) const
+    {
+        if (j == 0)
+            mt1[p] = -hdt * s;
+        else
+            src[(long)(j - 1) * N + p] = s;
     }
 };
 
@@ -454,10 +506,14 @@ struct EpiIncSrc {
 // lam_0 = scale c I[lam_1](Xa), then the trapezoid in time
 //   b = dt sum_j w_j lam_j grad m_j,  w_0 = w_{N_t} = 1/2, else 1,
 // with lam_0 from the gather, lam_1 .. lam_{N_t-1} from the sweep and
-// lam_{N_t} = scaleN lamN.
+// lam_{N_t} = scaleN lamN.  With N_t fixed at compile time (NTC > 0) all
+// inputs are loaded before the first store.
 template <int NTC>
 struct EpiAdjBody {
     static constexpr int NF = 1;
+    struct In {
+        float c, lam[NTC > 0 ? NTC : 1], g[NTC > 0 ? NTC + 1 : 1][3];  // lam[j-1] = lam_j, j = 1 .. N_t
+    };
     const float *src, *coef;
     float *lam0;            // lam_0 out
     float scale;
@@ -470,26 +526,79 @@ struct EpiAdjBody {
     int nt_rt;
     float dt;
     __device__ const float *field(int) const { return src; }
-    __device__ void finish(long p, const float *v) const
+    __device__ In load(long p) const
     {
-        const int nt = NTC > 0 ? NTC : nt_rt;
-        const float l0 = scale * coef[p] * v[0];
+        In in;
+        in.c = coef[p];
+        if constexpr (NTC > 0) {
+#pragma unroll
+            for (int j = 1; j <= NTC; ++j) in.lam[j - 1] = j == NTC ? lamN[p] : lam[(long)j * N + p];
+#pragma unroll
+            for (int j = 0; j <= NTC; ++j)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) in.g[j][c] = G[((long)j * 3 + c) * N + p];
+        }
+        return in;
+    }
+    __device__ void store(long p, const float *v, const In &in) const
+    {
+        const float l0 = scale * in.c * v[0];
         lam0[p] = l0;
         float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        if constexpr (NTC > 0) {
 #pragma unroll
-        for (int j = 0; j <= nt; ++j) {
-            const float w = (j == 0 || j == nt) ? 0.5f : 1.f;
-            const float l = j == 0 ? w * l0 : (j == nt ? (scaleN * w) * lamN[p] : w * lam[(long)j * N + p]);
-            const float *gj = G + (long)j * 3 * N;
-            a0 += l * gj[p];
-            a1 += l * gj[N + p];
-            a2 += l * gj[2 * N + p];
+            for (int j = 0; j <= NTC; ++j) {
+                const float w = (j == 0 || j == NTC) ? 0.5f : 1.f;
+                const float l = j == 0 ? w * l0 : (j == NTC ? (scaleN * w) * in.lam[j - 1] : w * in.lam[j - 1]);
+                a0 += l * in.g[j][0];
+                a1 += l * in.g[j][1];
+                a2 += l * in.g[j][2];
+            }
+        } else {
+            const int nt = nt_rt;
+            for (int j = 0; j <= nt; ++j) {
+                const float w = (j == 0 || j == nt) ? 0.5f : 1.f;
+                const float l = j == 0 ? w * l0 : (j == nt ? (scaleN * w) * lamN[p] : w * lam[(long)j * N + p]);
+                const float *gj = G + (long)j * 3 * N;
+                a0 += l * gj[p];
+                a1 += l * gj[N + p];
+                a2 += l * gj[2 * N + p];
+            }
         }
         b[p] = dt * a0;
         b[N + p] = dt * a1;
         b[2 * N + p] = dt * a2;
     }
 };
+
+// one point's epilogue, its loads first
+template <class Epi>
+__device__ __forceinline__ void epi_finish(const Epi &epi, long p, const float *v)
+{
+    const typename Epi::In in = epi.load(p);
+    epi.store(p, v, in);
+}
+
+// the epilogues of a thread's PPT points of a tile: small inputs are loaded
+// for every point before the first store (out-of-grid points load point 0
+// and store nothing); large ones (the fused kernels) point by point
+template <int PPT, class Epi>
+__device__ __forceinline__ void epi_finish_tile(const Epi &epi, const long (&pp)[PPT], const bool (&ok)[PPT],
+                                                const float (*val)[Epi::NF])
+{
+    if constexpr (sizeof(typename Epi::In) <= 8 * sizeof(float)) {
+        typename Epi::In in[PPT];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) in[q] = epi.load(ok[q] ? pp[q] : 0);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+            if (ok[q]) epi.store(pp[q], val[q], in[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+            if (ok[q]) epi_finish(epi, pp[q], val[q]);
+    }
+}
 
 // Stencil extents of one tile: the smallest first node (L) and the largest
 // (H) along each axis over the tile's grid points, reduced over the
@@ -698,11 +807,15 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
             val[q][f] = acc;
         }
     }
+    long pp[PPT];
+    bool ok[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
-        if (i < g.n1 && j < g.n2 && k < g.n3) epi.finish(((long)i * g.n2 + j) * g.n3 + k, val[q]);
+        ok[q] = i < g.n1 && j < g.n2 && k < g.n3;
+        pp[q] = ((long)i * g.n2 + j) * g.n3 + k;
     }
+    epi_finish_tile<PPT>(epi, pp, ok, val);
 }
 
 // Departure points through an LDS box (cubic interpolation): per direction
@@ -993,13 +1106,18 @@ __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restri
             }
             val[q] = acc;
         }
+        {
+            long pp[PPT];
+            bool ok[PPT];
+            float vv[PPT][1];
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-            const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
-            if (i < g.n1 && j < g.n2 && k < g.n3) {
-                float v[1] = {val[q]};
-                epi.finish(((long)i * g.n2 + j) * g.n3 + k, v);
+            for (int q = 0; q < PPT; ++q) {
+                const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+                ok[q] = i < g.n1 && j < g.n2 && k < g.n3;
+                pp[q] = ((long)i * g.n2 + j) * g.n3 + k;
+                vv[q][0] = val[q];
             }
+            epi_finish_tile<PPT>(epi, pp, ok, vv);
         }
         if (!more) break;  // uniform
         wait_lds_loads();
@@ -1027,7 +1145,7 @@ __global__ __launch_bounds__(kPtThreads) void k_direct(Grid3 g, const float *__r
     float v[Epi::NF];
 #pragma unroll
     for (int f = 0; f < Epi::NF; ++f) v[f] = gather<float>(epi.field(f), s);
-    epi.finish(p, v);
+    epi_finish(epi, p, v);
 }
 
 // trilinear gathers (LDDMM_FLAG_LINEAR_IP): eight nodes per point from L1/L2
@@ -1044,7 +1162,7 @@ __global__ __launch_bounds__(kPtThreads) void k_direct_lin(Grid3 g, const float 
     float v[Epi::NF];
 #pragma unroll
     for (int f = 0; f < Epi::NF; ++f) v[f] = gather2<float>(epi.field(f), s);
-    epi.finish(p, v);
+    epi_finish(epi, p, v);
 }
 
 // Eighth-order central first derivatives on the periodic grid (Section 3.2,
