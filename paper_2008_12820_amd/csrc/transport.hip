@@ -579,24 +579,27 @@ __device__ __forceinline__ void epi_finish(const Epi &epi, long p, const float *
     epi.store(p, v, in);
 }
 
-// the epilogues of a thread's PPT points of a tile: small inputs are loaded
-// for every point before the first store (out-of-grid points load point 0
-// and store nothing); large ones (the fused kernels) point by point
+// the epilogues of a thread's PPT points of a tile, in groups: a group's
+// loads are all issued before its first store (out-of-grid points load
+// point 0 and store nothing)
 template <int PPT, class Epi>
 __device__ __forceinline__ void epi_finish_tile(const Epi &epi, const long (&pp)[PPT], const bool (&ok)[PPT],
                                                 const float (*val)[Epi::NF])
 {
-    if constexpr (sizeof(typename Epi::In) <= 8 * sizeof(float)) {
-        typename Epi::In in[PPT];
+    // points per group: their inputs together within 64 floats for two points
+    // per thread, 32 for four (the contraction's registers set the kernel's
+    // peak there)
+    constexpr int SZ = (int)(sizeof(typename Epi::In) / sizeof(float)), BUD = PPT <= 2 ? 64 : 32;
+    constexpr int GRP = SZ * PPT <= BUD ? PPT : (BUD / SZ > 1 ? BUD / SZ : 1);
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) in[q] = epi.load(ok[q] ? pp[q] : 0);
+    for (int q0 = 0; q0 < PPT; q0 += GRP) {
+        typename Epi::In in[GRP];
 #pragma unroll
-        for (int q = 0; q < PPT; ++q)
-            if (ok[q]) epi.store(pp[q], val[q], in[q]);
-    } else {
+        for (int u = 0; u < GRP; ++u)
+            if (q0 + u < PPT) in[u] = epi.load(ok[q0 + u] ? pp[q0 + u] : 0);
 #pragma unroll
-        for (int q = 0; q < PPT; ++q)
-            if (ok[q]) epi_finish(epi, pp[q], val[q]);
+        for (int u = 0; u < GRP; ++u)
+            if (q0 + u < PPT && ok[q0 + u]) epi.store(pp[q0 + u], val[q0 + u], in[u]);
     }
 }
 
