@@ -20,6 +20,7 @@ CASES = [
     ((24, 20, 30), 3, 2, 1e-3, False),   # ragged, radix 3 and 5
     ((48, 40, 36), 2, 1, 5e-2, True),
     ((16, 16, 16), 1, 2, 1e-2, False),   # a single time step
+    ((24, 20, 30), 8, 2, 1e-3, True),    # N_t = 8: the other fused-epilogue instantiation
 ]
 
 
