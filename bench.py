@@ -392,7 +392,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU's share only (the whole grid on one device); "
-              "runs on more than one GPU are not part of this build", file=sys.stderr)
+              "runs on more than one GPU are not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -48,7 +48,7 @@ typedef enum lddmm_status {
     LDDMM_EDEVICE = 3,      /* a HIP runtime error (detail in lddmm_last_error) */
     LDDMM_ESTATE = 4,       /* call out of order (e.g. gradient before set_velocity) */
     LDDMM_ENOTCONV = 5,     /* PCG met non-positive curvature or a non-finite value */
-    LDDMM_EUNSUPPORTED = 6  /* valid request this build does not implement */
+    LDDMM_EUNSUPPORTED = 6  /* valid request the library does not implement */
 } lddmm_status;
 
 /* Regularisation operator A (Section 1.1: H1 seminorm by default, A the
