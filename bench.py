@@ -136,6 +136,29 @@ def time_matvecs(plan, vts_dev, steps, warmup, torch, only=None):
     return t1 - t0, kt
 
 
+def bench_leray_off(torch, dev, n, m0d, m1d, vd, vtd, steps, warmup):
+    """The same matvec with the Leray projection off (K = I): the assembly is
+    pointwise in b, A v~ runs wholly beside the transport sweeps."""
+    from paper_2008_12820_amd import Plan
+    log("matvec, Leray projection off")
+    plan = Plan(n, 4, reg=2, beta=5e-4, leray=False, device=dev)
+    plan.autotune()
+    plan.set_images(m0d, m1d)
+    plan.set_velocity(vd)
+    plan.autotune()
+    out = torch.empty_like(vtd[0])
+    for i in range(warmup):
+        plan.hessian_matvec(vtd[i % len(vtd)], out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        plan.hessian_matvec(vtd[i % len(vtd)], out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    plan.close()
+    return {"matvecs_per_s": steps / el, "ms_per_matvec": 1e3 * el / steps, "nt": 4, "leray": False}
+
+
 def dominant_class(kt, n, nt):
     return max((k for k in kt if kernel_bytes(k, n, nt) is not None), key=lambda k: kt[k][0])
 
@@ -590,6 +613,7 @@ def main():
         out["copy_calibration"] = {"bytes_read": 1 << 30, "bytes_written": 1 << 30,
                                    "GBps": 5 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9}
         del src, dst
+    out["leray_off"] = bench_leray_off(torch, dev, n, m0d, m1d, vd, vtd, args.steps, args.warmup)
     out["fft_vs_rocfft"] = fft_comparison(torch, dev, n)
     out["syn_workload"] = bench_syn(torch, dev, n)
     if args.batched:

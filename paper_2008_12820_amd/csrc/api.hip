@@ -260,12 +260,19 @@ void velocity_state(lddmm_plan *P)
     P->have_matvec = 0;
 }
 
+// Without the Leray projection K = I, so the assembly is pointwise in b:
+// out = beta (A w) + b.  A w (the FP64 forward chain of the regularisation
+// operator) is written straight into out, which never aliases w, and b is
+// not transformed at all.
+static bool assemble_pointwise(const lddmm_plan *P) { return !P->cfg.leray; }
+
 // The assembly beta A w + K b needs the forward transform of w, which depends
 // on the input alone: with overlap on and outside stream capture it is started
 // on the side stream (forked from the plan's stream) while the transport
-// sweeps run, and the assembly joins it.  Otherwise everything stays on the
-// plan's stream.
-static bool assemble_prefetch(lddmm_plan *P, const float *w)
+// sweeps run, and the assembly joins it; without the Leray projection the
+// side stream computes the whole of A w into out.  Otherwise everything stays
+// on the plan's stream.
+static bool assemble_prefetch(lddmm_plan *P, const float *w, float *out)
 {
     if (!P->overlap) return false;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -282,7 +289,10 @@ static bool assemble_prefetch(lddmm_plan *P, const float *w)
     hipStream_t main = P->stream;
     P->stream = P->side;
     try {
-        spectral_forward(P, SOP_ASSEMBLE, {w, w + N, w + 2 * N}, 3);
+        if (assemble_pointwise(P))
+            spectral_apply(P, SOP_REG, {w, w + N, w + 2 * N}, {out, out + N, out + 2 * N});
+        else
+            spectral_forward(P, SOP_ASSEMBLE, {w, w + N, w + 2 * N}, 3);
     } catch (...) {
         P->stream = main;
         throw;
@@ -296,6 +306,12 @@ static void assemble(lddmm_plan *P, const float *w, const float *b, float *out, 
 {
     const long N = P->N;
     if (w_started) check_hip(hipStreamWaitEvent(P->stream, P->ev_join, 0), "hipStreamWaitEvent");
+    if (assemble_pointwise(P)) {
+        if (!w_started) spectral_apply(P, SOP_REG, {w, w + N, w + 2 * N}, {out, out + N, out + 2 * N});
+        const double beta = P->beta_sym > 0.0 ? P->beta_sym : P->cfg.beta;  // the symbol's beta
+        axpby(P, 3 * N, (float)beta, out, 1.f, b, out);
+        return;
+    }
     spectral_apply(P, SOP_ASSEMBLE, {w, w + N, w + 2 * N, b, b + N, b + 2 * N},
                    {out, out + N, out + 2 * N}, w_started ? 3 : 0);
 }
@@ -306,7 +322,7 @@ void gradient_enqueue(lddmm_plan *P, float *g)
     const long N = P->N;
     const int nt = P->nt;
     float *lam = P->lam;
-    const bool started = assemble_prefetch(P, P->v);
+    const bool started = assemble_prefetch(P, P->v, g);
     axpby(P, N, 1.f, P->m1, -1.f, P->m + (long)nt * N, lam + (long)nt * N);
     for (int j = nt - 1; j >= 1; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
     launch_adj_body(P, lam + N, 1.f, lam, lam, lam + (long)nt * N, 1.f);
@@ -334,7 +350,7 @@ void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
     launch_incstate_init(P, vt, mt[0]);
     // forked after the start gather, which streams at full bandwidth: the
     // transform then shares the device with the issue-bound gather steps
-    const bool started = assemble_prefetch(P, vt);
+    const bool started = assemble_prefetch(P, vt, hvt);
     for (int j = 1; j < nt; ++j)
         launch_incstate_step(P, mt[(j - 1) & 1], P->src + (long)(j - 1) * N, mt[j & 1]);
     const float *mtN = mt[(nt - 1) & 1];
