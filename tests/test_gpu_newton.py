@@ -87,14 +87,16 @@ def test_inv_reg_and_newton_step_match_oracle_pcg():
     assert abs(info["rel_res"] - pinfo["rel_res"]) < 1e-3 * max(pinfo["rel_res"], 1e-3)
 
 
-def test_overlapped_assembly_is_bitwise_the_same():
+@pytest.mark.parametrize("leray", [True, False])
+def test_overlapped_assembly_is_bitwise_the_same(leray):
     """With overlap on, the forward transform of the assembly's first operand
-    runs on the plan's side stream beside the transport sweeps; gradient and
-    matvec keep every bit, call after call."""
+    (without the Leray projection: the whole of A v) runs on the plan's side
+    stream beside the transport sweeps; gradient and matvec keep every bit,
+    call after call."""
     shape, nt = (32, 24, 40), 3
-    say("overlap on/off")
+    say(f"overlap on/off, leray {leray}")
     m0, m1, vtrue, v, _ = problem(shape, nt, 2, 1e-3, disp=2.0)
-    P = _plan(shape, nt, 2, 1e-3, True, m0, m1, v)
+    P = _plan(shape, nt, 2, 1e-3, leray, m0, m1, v)
     vt = to_dev(incremental(shape, 1400))
     g0, _ = P.gradient()
     h0 = P.hessian_matvec(vt)
