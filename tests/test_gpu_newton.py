@@ -21,6 +21,7 @@ CASES = [
     ((48, 40, 36), 2, 1, 5e-2, True),
     ((16, 16, 16), 1, 2, 1e-2, False),   # a single time step
     ((24, 20, 30), 8, 2, 1e-3, True),    # N_t = 8: the other fused-epilogue instantiation
+    ((64, 20, 24), 2, 2, 1e-3, True),    # x1 length with a register pass, Leray on
 ]
 
 
@@ -93,7 +94,7 @@ def test_overlapped_assembly_is_bitwise_the_same(leray):
     (without the Leray projection: the whole of A v) runs on the plan's side
     stream beside the transport sweeps; gradient and matvec keep every bit,
     call after call."""
-    shape, nt = (32, 24, 40), 3
+    shape, nt = (64, 24, 40), 3  # n1 = 64: the register-pass assembly
     say(f"overlap on/off, leray {leray}")
     m0, m1, vtrue, v, _ = problem(shape, nt, 2, 1e-3, disp=2.0)
     P = _plan(shape, nt, 2, 1e-3, leray, m0, m1, v)
