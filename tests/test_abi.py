@@ -86,3 +86,39 @@ def test_config_flags():
                         (L.FLAG_LINEAR_IP | L.FLAG_FD8, L.OK), (8, L.EINVAL), (16 | L.FLAG_FD8, L.EINVAL)):
         cfg = L.make_config((16, 16, 16), 2, 2, 1e-2, flags=flags)
         assert L.lib().lddmm_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == want, flags
+
+
+def test_missing_library_fails_loudly():
+    """No fallback: without liblddmm.so the binding raises instead of
+    computing anything on the host."""
+    import subprocess
+    import sys
+    code = ("import paper_2008_12820_amd._lib as L\n"
+            "L.LIB_PATH = '/nonexistent/liblddmm.so'\n"
+            "L._lib = None\n"
+            "try:\n"
+            "    L.lib()\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n"
+            "else:\n"
+            "    raise SystemExit('no error')\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert r.returncode == 0, r.stderr
+    assert "raised" in r.stdout and "missing" in r.stdout
+
+
+def test_product_sources_never_use_the_oracle():
+    """The oracle is test infrastructure: nothing in the package (Python
+    binding or HIP sources) imports, loads or includes it."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_2008_12820_amd")
+    for dirpath, _, files in os.walk(pkg):
+        if "_build" in dirpath or "__pycache__" in dirpath:
+            continue
+        for f in files:
+            if not f.endswith((".py", ".hip", ".hpp", ".h", ".c")):
+                continue
+            text = open(os.path.join(dirpath, f), encoding="utf-8").read()
+            for bad in ("import oracle", "from oracle", "liboracle", "lddmm_oracle"):
+                assert bad not in text, (f, bad)
