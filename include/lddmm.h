@@ -149,6 +149,14 @@ lddmm_status lddmm_apply_inv_reg(lddmm_plan *plan, const float *r, float *s);
 lddmm_status lddmm_newton_step(lddmm_plan *plan, int32_t max_pcg, double rtol, float *vt_out,
                                lddmm_newton_info *info);
 
+/* Residual history of the last PCG of lddmm_newton_step / lddmm_gn_iterate
+ * (Algorithm "GNK", the Krylov solve of eq. "iter"): rel_res[k] (host, len
+ * entries at most) = ||r|| / ||r0|| after iteration k + 1 (the value before
+ * it when that iteration stopped at the curvature test); *count (host, may
+ * be NULL) = the iterations recorded (the first 4096 of a solve).  Copies
+ * min(len, count) entries; EINVAL for len < 0 or rel_res NULL with len > 0. */
+lddmm_status lddmm_pcg_history(lddmm_plan *plan, double *rel_res, int32_t len, int32_t *count);
+
 /* One Gauss-Newton iteration (Algorithm "GNK"): gradient, PCG step as in
  * lddmm_newton_step, Armijo line search (alpha = 1, accept
  * J(v + a v~) <= J(v) + 1e-4 a <g, v~>, else halve, at most 10 tries), then
@@ -213,10 +221,21 @@ lddmm_status lddmm_interp(lddmm_plan *plan, int32_t nfields, const float *fields
  * LDDMM_FIELD_STATE (m_j, N), LDDMM_FIELD_GRAD_STATE (grad m_j, 3N),
  * LDDMM_FIELD_DIV (div v, N), LDDMM_FIELD_INC_STATE (m~(1) of the last
  * matvec, N), LDDMM_FIELD_ADJOINT (lam_j of the last gradient, N).
+ * LDDMM_FIELD_PCG_R, _PCG_Z, _PCG_P (3N each): the residual r, the
+ * preconditioned residual z = M^{-1} r and the search direction p that the
+ * last PCG of lddmm_newton_step / lddmm_gn_iterate left (after k iterations
+ * without a stop: r_k, z_k and p_k = z_k + beta_k p_{k-1}, the state from
+ * which iteration k + 1 starts; Algorithm "GNK" solves eq. "iter" with it);
+ * unspecified before the first Newton step.
+ * After lddmm_transport_forward or lddmm_transport_vjp (e.g. on a
+ * transport-only plan) the displacements are available, and after a VJP
+ * also div v, the adjoint lam_j of that sweep (final value grad_m1) and, when
+ * grad_v was asked for, grad m_j of the checkpoints.
  * ESTATE when the array has not been computed. */
 enum { LDDMM_FIELD_DISP = 1, LDDMM_FIELD_DISP_ADJ = 2, LDDMM_FIELD_STATE = 3,
        LDDMM_FIELD_GRAD_STATE = 4, LDDMM_FIELD_DIV = 5, LDDMM_FIELD_INC_STATE = 6,
-       LDDMM_FIELD_ADJOINT = 7 };
+       LDDMM_FIELD_ADJOINT = 7, LDDMM_FIELD_PCG_R = 8, LDDMM_FIELD_PCG_Z = 9,
+       LDDMM_FIELD_PCG_P = 10 };
 lddmm_status lddmm_get_field(lddmm_plan *plan, int32_t what, int32_t j, float *out);
 
 /* ---- batched form --------------------------------------------------------- */

@@ -35,6 +35,7 @@ def lib():
             "or_leray": (None, [p, p, i, i, i]),
             "or_interp": (None, [p, i, i, i, i, p, l, p]),
             "or_departure": (None, [p, i, i, i, i, p, p]),
+            "or_departure_points": (None, [p, i, i, i, i, p, l, p, p]),
             "or_inner": (d, [p, p, l, d]),
             "or_ctx_create": (p, [i, i, i, i, i, d, i]),
             "or_ctx_destroy": (None, [p]),
@@ -61,6 +62,7 @@ def lib():
             "or_ctx_2linvh0": (i, [p, p, d, i, p]),
             "or_ctx_invh0": (i, [p, p, d, i, p]),
             "or_ctx_pcg_pc": (i, [p, p, i, d, i, d, i, p, p]),
+            "or_ctx_pcg_hist": (i, [p, p, i, d, i, d, i, p, p, p]),
             "or_ctx_gn_iterate_pc": (i, [p, i, d, i, d, i, p, p]),
             "or_ctx_transport": (None, [p, p, p]),
             "or_ctx_transport_vjp": (None, [p, p, p, p, p]),
@@ -156,6 +158,19 @@ def departure(v, nt):
     Xa = np.empty(v.shape)
     lib().or_departure(pv, *v.shape[1:], int(nt), X.ctypes.data_as(ctypes.c_void_p),
                        Xa.ctypes.data_as(ctypes.c_void_p))
+    return X, Xa
+
+
+def departure_points(v, nt, idx):
+    """Departure points X, Xa at the grid points idx ([3][nq] integer
+    indices) only: [3][nq] physical coordinates each."""
+    v, pv = _c(v)
+    ii = np.ascontiguousarray(idx, dtype=np.int64)
+    nq = ii.shape[1]
+    X = np.empty((3, nq))
+    Xa = np.empty((3, nq))
+    lib().or_departure_points(pv, *v.shape[1:], int(nt), ii.ctypes.data_as(ctypes.c_void_p), nq,
+                              X.ctypes.data_as(ctypes.c_void_p), Xa.ctypes.data_as(ctypes.c_void_p))
     return X, Xa
 
 
@@ -374,6 +389,21 @@ class Problem:
             return x, {"iters": int(info[0]), "rel_res": float(info[1]), "flags": int(info[2]),
                        "r0": float(info[3]), "inner": int(info[4])}
         return self._pcg_inva(rhs, max_it, rtol)
+
+    def pcg_history(self, rhs, max_it, rtol, pc="inva", eps_h0=1e-3, max_inner=50):
+        """PCG as pcg(), plus the relative residual ||r_k|| / ||r0|| after each
+        iteration; returns (x, info, history[iterations])."""
+        a, pa = _c(rhs)
+        x = np.empty((3,) + self.shape)
+        info = np.empty(5)
+        hist = np.zeros(max(int(max_it), 1))
+        lib().or_ctx_pcg_hist(self._ctx, pa, int(max_it), float(rtol),
+                              {"inva": 0, "invh0": 1, "2linvh0": 2}[pc], float(eps_h0), int(max_inner),
+                              x.ctypes.data_as(ctypes.c_void_p), info.ctypes.data_as(ctypes.c_void_p),
+                              hist.ctypes.data_as(ctypes.c_void_p))
+        d = {"iters": int(info[0]), "rel_res": float(info[1]), "flags": int(info[2]),
+             "r0": float(info[3]), "inner": int(info[4])}
+        return x, d, hist[:d["iters"]]
 
     def _pcg_inva(self, rhs, max_it, rtol):
         a, pa = _c(rhs)

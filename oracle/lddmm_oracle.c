@@ -506,6 +506,39 @@ static void departure_order(int order, const double *v, int n1, int n2, int n3, 
     free(x);
 }
 
+/* The same two departure points (cubic predictor) at nq chosen grid points
+ * only, given by their indices idx[3][nq]: for checks at grid sizes where the
+ * whole field would take too long.  X, Xa: [3][nq]. */
+void or_departure_points(const double *v, int n1, int n2, int n3, int nt, const long *idx, long nq,
+                         double *X, double *Xa)
+{
+    int n[3] = {n1, n2, n3};
+    long N = (long)n1 * n2 * n3;
+    double dt = 1.0 / nt;
+    double *x = malloc(sizeof(double) * 3 * (size_t)nq);
+    double *vx = malloc(sizeof(double) * 3 * (size_t)nq);
+    double *y = malloc(sizeof(double) * 3 * (size_t)nq);
+    double *vy = malloc(sizeof(double) * 3 * (size_t)nq);
+    for (long q = 0; q < nq; q++) {
+        long p = (idx[q] * n2 + idx[nq + q]) * n3 + idx[2 * nq + q];
+        for (int d = 0; d < 3; d++) {
+            x[d * nq + q] = idx[d * nq + q] * (2.0 * OR_PI / n[d]);
+            vx[d * nq + q] = v[d * N + p];
+        }
+    }
+    for (int dir = 0; dir < 2; dir++) {
+        double s = dir == 0 ? -1.0 : 1.0;
+        double *out = dir == 0 ? X : Xa;
+        for (long i = 0; i < 3 * nq; i++) y[i] = x[i] + s * dt * vx[i];
+        or_interp(v, 3, n1, n2, n3, y, nq, vy);
+        for (long i = 0; i < 3 * nq; i++) out[i] = x[i] + s * 0.5 * dt * (vx[i] + vy[i]);
+    }
+    free(vy);
+    free(y);
+    free(vx);
+    free(x);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Problem context                                                          */
 /* ------------------------------------------------------------------------ */
@@ -998,9 +1031,11 @@ static int precondition(const or_ctx *c, const double *r, double *z, int pc, dou
  * <p, H p> <= 0 (then the current x; at the first iteration M^{-1} r0).
  * info: [0] iterations (matvecs), [1] ||r||/||r0||, [2] flags
  * (1 negative curvature, 2 non-finite), [3] ||r0||, [4] inner iterations of
- * the preconditioner (summed).  Returns flags. */
-int or_ctx_pcg_pc(const or_ctx *c, const double *rhs, int max_it, double rtol, int pc,
-                  double eps_h0, int max_inner, double *x, double *info)
+ * the preconditioner (summed).  hist (may be NULL, max_it entries): after
+ * iteration k + 1, hist[k] = ||r|| / ||r0|| (the current value when the
+ * iteration stopped at the curvature test).  Returns flags. */
+int or_ctx_pcg_hist(const or_ctx *c, const double *rhs, int max_it, double rtol, int pc,
+                    double eps_h0, int max_inner, double *x, double *info, double *hist)
 {
     long M = 3 * c->N;
     double h3 = c->h3, tol_h0 = eps_h0 * rtol;
@@ -1026,6 +1061,7 @@ int or_ctx_pcg_pc(const or_ctx *c, const double *rhs, int max_it, double rtol, i
     while (it < max_it) {
         or_ctx_matvec(c, p, q);
         it++;
+        if (hist) hist[it - 1] = rn / r0;
         double kappa = or_inner(p, q, M, h3);
         if (!isfinite(kappa)) {
             flags |= 2;
@@ -1042,6 +1078,7 @@ int or_ctx_pcg_pc(const or_ctx *c, const double *rhs, int max_it, double rtol, i
             r[i] -= alpha * q[i];
         }
         rn = sqrt(or_inner(r, r, M, h3));
+        if (hist) hist[it - 1] = rn / r0;
         if (rn <= rtol * r0) break;
         inner += precondition(c, r, z, pc, tol_h0, max_inner);
         double rz_new = or_inner(r, z, M, h3);
@@ -1056,6 +1093,12 @@ int or_ctx_pcg_pc(const or_ctx *c, const double *rhs, int max_it, double rtol, i
     info[4] = inner;
     free(r); free(z); free(p); free(q);
     return flags;
+}
+
+int or_ctx_pcg_pc(const or_ctx *c, const double *rhs, int max_it, double rtol, int pc,
+                  double eps_h0, int max_inner, double *x, double *info)
+{
+    return or_ctx_pcg_hist(c, rhs, max_it, rtol, pc, eps_h0, max_inner, x, info, NULL);
 }
 
 /* PCG with M^{-1} = (beta A)^{-1} (preconditioner InvA); info [0..3] */

@@ -16,7 +16,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOTCONV, EUNSUPPORTED = range(7)
 REG_H1S, REG_H2S = 1, 2
 OP_GRAD, OP_DIV, OP_REG, OP_INVREG, OP_LERAY = 1, 2, 3, 4, 5
 FIELD_DISP, FIELD_DISP_ADJ, FIELD_STATE, FIELD_GRAD_STATE, FIELD_DIV, FIELD_INC_STATE, \
-    FIELD_ADJOINT = 1, 2, 3, 4, 5, 6, 7
+    FIELD_ADJOINT, FIELD_PCG_R, FIELD_PCG_Z, FIELD_PCG_P = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
 
 
 FLAG_TRANSPORT_ONLY = 1
@@ -93,6 +93,7 @@ def lib():
             "lddmm_apply_2linvh0": (st, [p, p, d, i32, p, P(i32)]),
             "lddmm_newton_step": (st, [p, i32, d, p, P(NewtonInfo)]),
             "lddmm_gn_iterate": (st, [p, i32, d, p, P(NewtonInfo)]),
+            "lddmm_pcg_history": (st, [p, P(d), i32, P(i32)]),
             "lddmm_transport_forward": (st, [p, p, p, p, p]),
             "lddmm_transport_vjp": (st, [p, p, p, p, p, p]),
             "lddmm_reg_energy": (st, [p, p, p, P(d)]),
@@ -249,6 +250,14 @@ def lddmm_newton_step(plan, max_pcg, rtol, vt_out, allow_notconv=False):
     if not (allow_notconv and st == ENOTCONV):
         _check(st, "newton_step")
     return st, info.as_dict()
+
+
+def lddmm_pcg_history(plan, maxlen=4096):
+    """||r_k|| / ||r0|| after each iteration of the last PCG (a list)"""
+    buf = (ctypes.c_double * max(int(maxlen), 1))()
+    cnt = ctypes.c_int32(0)
+    _check(lib().lddmm_pcg_history(plan, buf, int(maxlen), ctypes.byref(cnt)), "pcg_history")
+    return [buf[k] for k in range(min(cnt.value, int(maxlen)))]
 
 
 def lddmm_gn_iterate(plan, max_pcg, rtol, v_inout):

@@ -148,6 +148,7 @@ static Layout make_layout(const lddmm_config *cfg)
     L.add(sizeof(double) * kRedBlocks);     // 23 red
     L.add(sizeof(double) * kNumScalars);    // 24 dscal
     L.add(2 * tile_boxes_bytes(cfg->n));     // 25 stencil extents per gather tile (dX, dXa)
+    L.add(sizeof(double) * kHistMax);       // 26 PCG residual history
     return L;
 }
 
@@ -165,6 +166,8 @@ static void plan_free(lddmm_plan *P)
     if (P->coarse) (void)lddmm_plan_destroy(P->coarse);
     if (P->arena) (void)hipFree(P->arena);
     if (P->hscal) (void)hipHostFree(P->hscal);
+    for (hipEvent_t e : P->ev_poll)
+        if (e) (void)hipEventDestroy(e);
     for (auto &pr : P->timing.pool) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
@@ -258,6 +261,8 @@ void velocity_state(lddmm_plan *P)
     P->have_velocity = 1;
     P->have_grad = 0;
     P->have_matvec = 0;
+    P->have_disp = 1;
+    P->have_vjp = 0;
 }
 
 // Without the Leray projection K = I, so the assembly is pointwise in b:
@@ -498,6 +503,9 @@ static void resample3(lddmm_plan *F, const float *in, lddmm_plan *C, float *out)
 static int twolevel_impl(lddmm_plan *P, const float *r, float *s, double tol, int max_it)
 {
     lddmm_plan *C = coarse_plan(P);
+    // the half-grid H0 and (beta0 A_c)^{-1} take the fine plan's beta0: the
+    // identity R (beta0 A)^{-1} = (beta0 A_c)^{-1} R used below needs one beta0
+    C->cfg.beta = P->cfg.beta;
     const long M = 3 * P->N, Mc = 3 * C->N;
     if (P->coarse_gen != P->vel_gen) {
         resample3(P, P->G + (long)P->nt * 3 * P->N, C, C->G + (long)C->nt * 3 * C->N);
@@ -531,10 +539,72 @@ static int precondition(lddmm_plan *P, const float *r, float *z, double tol_oute
     return 0;
 }
 
-// Preconditioned CG on H x = rhs, x0 = 0, M^{-1} = (beta A)^{-1}.
+// PCG with M^{-1} = (beta A)^{-1} and every scalar on the device (the
+// kernels of pcg_enqueue): iteration k is enqueued before the host reads the
+// stop flag of iteration k - 1, so the stream never drains between
+// iterations; after a stop the one iteration already queued is predicated
+// off (its matvec runs, its updates do not), which gives the early exit of
+// the host loop with the same arithmetic.
+static int pcg_device(lddmm_plan *P, const float *rhs, int max_it, double rtol, float *x,
+                      lddmm_newton_info &info)
+{
+    const long M = 3 * P->N;
+    float *r = P->pr, *z = P->pz, *p = P->pp, *q = P->pq;
+    for (hipEvent_t &e : P->ev_poll)
+        if (!e) check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
+    double *poll = P->hscal + kNumScalars;
+    dev_set_scalar(P, S_RTOL, rtol);
+    copy_kernel(P, M, rhs, r);
+    fill(P, M, 0.f, x);
+    dot_async(P, r, r, M, S_RR, P->h3);
+    dev_pcg_init(P);
+    inv_reg(P, r, z);
+    copy_kernel(P, M, z, p);
+    dot_async(P, r, z, M, S_RZ, P->h3);
+    for (int it = 0; it < max_it; ++it) {
+        matvec_impl(P, p, q);
+        dot_async(P, p, q, M, S_KAPPA, P->h3);
+        dev_pcg_alpha(P);
+        dev_pcg_xr(P, M, p, q, x, r);
+        dev_copy_if(P, M, z, x);
+        dot_async(P, r, r, M, S_RR, P->h3);
+        dev_pcg_conv(P);
+        if (it < kHistMax) dev_store_scalar(P, S_REL, P->hist + it);
+        inv_reg(P, r, z);
+        dot_async(P, r, z, M, S_RZN, P->h3);
+        dev_pcg_beta(P);
+        dev_pcg_p(P, M, z, p);
+        check_hip(hipMemcpyAsync(poll + (it & 1), P->dscal + S_DONE, sizeof(double), hipMemcpyDeviceToHost,
+                                 P->stream),
+                  "stop flag copy");
+        check_hip(hipEventRecord(P->ev_poll[it & 1], P->stream), "hipEventRecord");
+        if (it >= 1) {
+            check_hip(hipEventSynchronize(P->ev_poll[(it - 1) & 1]), "hipEventSynchronize");
+            if (poll[(it - 1) & 1] != 0.0) break;  // iteration it is queued, predicated off
+        }
+    }
+    check_hip(hipMemcpyAsync(P->hscal, P->dscal, sizeof(double) * kNumScalars, hipMemcpyDeviceToHost, P->stream),
+              "scalar copy");
+    check_hip(hipStreamSynchronize(P->stream), "stream sync");
+    const double *h = P->hscal;
+    info.pcg_iters = (int)h[S_ITERS];
+    info.rel_res = h[S_REL];
+    info.inner_iters = 0;
+    info.flags = (int)h[S_FLAGS];
+    P->pcg_hist.assign(std::min(info.pcg_iters, kHistMax), 0.0);
+    if (!P->pcg_hist.empty())
+        check_hip(hipMemcpy(P->pcg_hist.data(), P->hist, sizeof(double) * P->pcg_hist.size(), hipMemcpyDeviceToHost),
+                  "history copy");
+    return info.flags;
+}
+
+// Preconditioned CG on H x = rhs, x0 = 0, M^{-1} = (beta A)^{-1} (device
+// resident) or the InvH0 / 2LInvH0 inner solve (host loop).
 static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, float *x,
                     lddmm_newton_info &info)
 {
+    if (P->pc_kind == 0) return pcg_device(P, rhs, max_it, rtol, x, info);
+    P->pcg_hist.clear();
     const long M = 3 * P->N;
     float *r = P->pr, *z = P->pz, *p = P->pp, *q = P->pq;
     copy_dev(P, r, rhs, M);
@@ -555,20 +625,25 @@ static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, fl
         const double kappa = dot_now(P, p, q, M);
         if (!std::isfinite(kappa)) {
             flags |= 2;
+            P->pcg_hist.push_back(rn / r0);
             break;
         }
         if (kappa <= 0.0) {
             flags |= 1;
             if (it == 1) copy_dev(P, x, z, M);
+            P->pcg_hist.push_back(rn / r0);
             break;
         }
         const double al = rz / kappa;
         pcg_update_xr(P, M, (float)al, p, q, x, r);
-        rn = std::sqrt(dot_now(P, r, r, M));
-        if (!std::isfinite(rn)) {
+        const double rn_new = std::sqrt(dot_now(P, r, r, M));
+        if (!std::isfinite(rn_new)) {
             flags |= 2;
+            P->pcg_hist.push_back(rn / r0);
             break;
         }
+        rn = rn_new;
+        P->pcg_hist.push_back(rn / r0);
         if (rn <= rtol * r0) break;
         info.inner_iters += precondition(P, r, z, rtol);
         const double rz_new = dot_now(P, r, z, M);
@@ -733,7 +808,8 @@ lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan
         P->red = (double *)(a + L.off[23]);
         P->dscal = (double *)(a + L.off[24]);
         assign_tile_boxes(P, a + L.off[25]);
-        check_hip(hipHostMalloc((void **)&P->hscal, sizeof(double) * kNumScalars, hipHostMallocDefault),
+        P->hist = (double *)(a + L.off[26]);
+        check_hip(hipHostMalloc((void **)&P->hscal, sizeof(double) * (kNumScalars + 2), hipHostMallocDefault),
                   "hipHostMalloc");
         fft_init(P);
         *plan = P;
@@ -901,8 +977,10 @@ static bool gn_iterate_impl(lddmm_plan *P, int max_pcg, double rtol, double eps_
 static void set_beta_impl(lddmm_plan *P, double beta)
 {
     P->cfg.beta = beta;
+    if (P->coarse) P->coarse->cfg.beta = beta;
     P->g0norm = 0.0;
     dev_set_scalar(P, S_G0, 0.0);
+    ++P->enqueue_gen;  // beta is an argument of the enqueued kernels
 }
 
 }  // namespace lddmm
@@ -1007,7 +1085,9 @@ lddmm_status lddmm_transport_forward(lddmm_plan *P, const float *m0, const float
         const long N = P->N;
         copy_dev(P, P->v, v, 3 * N);
         P->have_velocity = 0;
+        P->have_vjp = 0;
         launch_departure(P, P->v, P->dX, P->dXa);
+        P->have_disp = 1;
         float *buf = ckpt ? ckpt : P->m;
         copy_dev(P, buf, m0, N);
         for (int j = 0; j < P->nt; ++j)
@@ -1030,7 +1110,9 @@ lddmm_status lddmm_transport_vjp(lddmm_plan *P, const float *ckpt, const float *
         const int nt = P->nt;
         copy_dev(P, P->v, v, 3 * N);
         P->have_velocity = 0;
+        P->have_vjp = 0;
         launch_departure(P, P->v, P->dX, P->dXa);
+        P->have_disp = 1;
         divergence(P, P->v, P->delta);
         launch_adj_coef(P);
         float *lam = P->lam;
@@ -1048,6 +1130,7 @@ lddmm_status lddmm_transport_vjp(lddmm_plan *P, const float *ckpt, const float *
             launch_body_force(P, lam, lam + (long)nt * N, 1.f, P->G, P->b);
             axpby(P, 3 * N, -1.f, P->b, 0.f, nullptr, grad_v);
         }
+        P->have_vjp = grad_v ? 2 : 1;  // 2: the checkpoint gradients are held too
     });
 }
 
@@ -1142,26 +1225,42 @@ lddmm_status lddmm_get_field(lddmm_plan *P, int32_t what, int32_t j, float *out)
         const long N = P->N;
         const int nt = P->nt;
         auto need_v = [&] { need_velocity(P); };
+        // after a transport-map call the departure points, the divergence and,
+        // after a VJP, the adjoint sweep and the checkpoint gradients are held
+        const bool tmap = !P->have_velocity && P->have_disp;
         switch (what) {
-        case LDDMM_FIELD_DISP: need_v(); copy_dev(P, out, P->dX, 3 * N); break;
-        case LDDMM_FIELD_DISP_ADJ: need_v(); copy_dev(P, out, P->dXa, 3 * N); break;
+        case LDDMM_FIELD_DISP:
+            if (!tmap) need_v();
+            copy_dev(P, out, P->dX, 3 * N);
+            break;
+        case LDDMM_FIELD_DISP_ADJ:
+            if (!tmap) need_v();
+            copy_dev(P, out, P->dXa, 3 * N);
+            break;
         case LDDMM_FIELD_STATE:
             need_v();
             if (j < 0 || j > nt) fail(LDDMM_EINVAL, "j out of range");
             copy_dev(P, out, P->m + (long)j * N, N);
             break;
         case LDDMM_FIELD_GRAD_STATE:
-            need_v();
+            if (!(tmap && P->have_vjp == 2)) need_v();
             if (j < 0 || j > nt) fail(LDDMM_EINVAL, "j out of range");
             copy_dev(P, out, P->G + (long)j * 3 * N, 3 * N);
             break;
-        case LDDMM_FIELD_DIV: need_v(); copy_dev(P, out, P->delta, N); break;
+        case LDDMM_FIELD_DIV:
+            if (!(tmap && P->have_vjp)) need_v();
+            copy_dev(P, out, P->delta, N);
+            break;
         case LDDMM_FIELD_INC_STATE:
             if (!P->have_matvec) fail(LDDMM_ESTATE, "no matvec has been computed");
             copy_dev(P, out, P->mt + (long)((nt - 1) & 1) * N, N);
             break;
+        case LDDMM_FIELD_PCG_R: copy_dev(P, out, P->pr, 3 * N); break;
+        case LDDMM_FIELD_PCG_Z: copy_dev(P, out, P->pz, 3 * N); break;
+        case LDDMM_FIELD_PCG_P: copy_dev(P, out, P->pp, 3 * N); break;
         case LDDMM_FIELD_ADJOINT:
-            if (!P->have_grad && !P->have_matvec) fail(LDDMM_ESTATE, "no adjoint has been computed");
+            if (!P->have_grad && !P->have_matvec && !(tmap && P->have_vjp))
+                fail(LDDMM_ESTATE, "no adjoint has been computed");
             if (j < 0 || j > nt) fail(LDDMM_EINVAL, "j out of range");
             copy_dev(P, out, P->lam + (long)j * N, N);
             break;
@@ -1222,6 +1321,7 @@ lddmm_status lddmm_autotune(lddmm_plan *P)
         autotune_fft(P);
         // the gather strategy is timed on the real displacement field
         if (P->have_velocity) autotune_gather(P);
+        ++P->enqueue_gen;
     });
 }
 
@@ -1252,6 +1352,7 @@ lddmm_status lddmm_set_preconditioner(lddmm_plan *P, int32_t kind, double eps_h0
         P->pc_kind = kind;
         P->pc_eps_h0 = eps_h0;
         P->pc_max_inner = max_inner;
+        ++P->enqueue_gen;
     });
 }
 
@@ -1315,6 +1416,19 @@ lddmm_status lddmm_set_gather_mode(lddmm_plan *P, int32_t mode)
         P->gather_mode = mode;
         P->gather_mode3 = -1;
         P->departure_mode = mode < 0 ? -1 : mode == 0 ? 0 : (mode & 1) ? 1 : 2;
+        ++P->enqueue_gen;
+    });
+}
+
+lddmm_status lddmm_pcg_history(lddmm_plan *P, double *rel_res, int32_t len, int32_t *count)
+{
+    return guard([&] {
+        need(P, "plan");
+        if (len < 0) fail(LDDMM_EINVAL, "len must be >= 0");
+        if (len > 0) need(rel_res, "rel_res");
+        const int n = (int)P->pcg_hist.size();
+        for (int k = 0; k < std::min(n, (int)len); ++k) rel_res[k] = P->pcg_hist[k];
+        if (count) *count = n;
     });
 }
 

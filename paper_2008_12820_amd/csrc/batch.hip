@@ -19,6 +19,7 @@ struct MemberGraph {
     hipGraphExec_t exec = nullptr;
     int max_pcg = -1;
     double rtol = 0.0;
+    unsigned long gen = 0;  // the plan's enqueue generation at capture
 };
 
 }  // namespace lddmm
@@ -74,7 +75,9 @@ static void capture_member(lddmm_batch *Bt, int b, int max_pcg, double rtol)
 {
     lddmm_plan *P = Bt->plans[b];
     MemberGraph &G = Bt->graphs[b];
-    if (G.exec && G.max_pcg == max_pcg && G.rtol == rtol) return;
+    // kernel arguments such as beta are baked into the graph: recapture when
+    // the plan's enqueue generation moved since the capture
+    if (G.exec && G.max_pcg == max_pcg && G.rtol == rtol && G.gen == P->enqueue_gen) return;
     if (G.exec) {
         check_hip(hipGraphExecDestroy(G.exec), "hipGraphExecDestroy");
         G.exec = nullptr;
@@ -99,6 +102,7 @@ static void capture_member(lddmm_batch *Bt, int b, int max_pcg, double rtol)
     check_hip(e, "hipGraphInstantiate");
     G.max_pcg = max_pcg;
     G.rtol = rtol;
+    G.gen = P->enqueue_gen;
 }
 
 }  // namespace lddmm

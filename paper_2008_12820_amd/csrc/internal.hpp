@@ -97,10 +97,16 @@ struct lddmm_plan {
     long slot_bytes = 0;
     int nspec = 0;
     double *red = nullptr;   // reduction partials
+    double *hist = nullptr;  // ||r_k|| / ||r0|| per PCG iteration (device, kHistMax)
+    std::vector<double> pcg_hist;  // the last PCG's history (host)
     double *dscal = nullptr; // device scalars
-    double *hscal = nullptr; // pinned host mirror
+    double *hscal = nullptr; // pinned host mirror (kNumScalars, then a 2-slot poll ring)
+    hipEvent_t ev_poll[2] = {nullptr, nullptr};  // the device-resident PCG's lagged stop test
 
     int have_images = 0, have_velocity = 0, have_grad = 0, have_matvec = 0;
+    // transport map calls: departure points (forward or VJP), and the adjoint
+    // sweep and checkpoint gradients of the last VJP
+    int have_disp = 0, have_vjp = 0;
     void *boxes[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // stencil extents per tile: [dX, dXa][2x4, 4x4]
     int boxes_valid = 0;
     int gather_mode = -1;    // 0 direct, 1/2 box tiles 2x4x64/4x4x64, 3/4 the same pipelined, -1 heuristic
@@ -110,6 +116,10 @@ struct lddmm_plan {
     int pipe_grid[2] = {0, 0};  // workgroups of the pipelined gathers [2x4, 4x4] (0: not yet sized)
     float gather_ms[1] = {0.f};
     double g0norm = 0.0;
+    // bumped by every setter that changes the arguments or the choice of the
+    // kernels a call enqueues (beta, tile shapes, gather strategy, ...), so
+    // that a captured graph of an older generation is not replayed
+    unsigned long enqueue_gen = 0;
     lddmm::PlanTiming timing;
 };
 
@@ -217,6 +227,7 @@ void pcg_update_xr(lddmm_plan *P, long n, float al, const float *p, const float 
                    float *r);
 constexpr int kRedBlocks = 1024;
 constexpr int kNumScalars = 32;
+constexpr int kHistMax = 4096;  // PCG iterations whose residual is recorded
 
 // Device scalar slots (P->dscal).  0..4 serve the eager calls; the rest hold
 // the state of the device-resident PCG / Gauss-Newton step, which needs no
@@ -240,6 +251,8 @@ void dev_pcg_conv(lddmm_plan *P);
 void dev_pcg_beta(lddmm_plan *P);
 void dev_pcg_p(lddmm_plan *P, long n, const float *z, float *p);
 void dev_sum(lddmm_plan *P, int dst, int a, int b);
+// dst[0] = dscal[slot] (device to device, a kernel: capturable)
+void dev_store_scalar(lddmm_plan *P, int slot, double *dst);
 void copy_kernel(lddmm_plan *P, long n, const float *x, float *out);
 
 }  // namespace lddmm

@@ -200,7 +200,7 @@ __global__ void k_pcg_init(double *d)
     d[S_DONE] = (r0 == 0.0) ? 1.0 : 0.0;
     d[S_ITERS] = 0.0;
     d[S_FLAGS] = 0.0;
-    d[S_REL] = 0.0;
+    d[S_REL] = (r0 == 0.0) ? 0.0 : 1.0;  // ||r|| / ||r0|| before the first iteration
     d[S_COPYZ] = 0.0;
     d[S_ALPHA] = 0.0;
     d[S_BETA] = 0.0;
@@ -284,6 +284,7 @@ __global__ void k_pcg_p(long n, int vec, const double *__restrict__ d, const flo
 }
 
 __global__ void k_sum2(double *d, int dst, int a, int b) { d[dst] = d[a] + d[b]; }
+__global__ void k_store_scalar(const double *d, int slot, double *dst) { dst[0] = d[slot]; }
 
 __global__ void k_copy(long n, int vec, const float *__restrict__ x, float *__restrict__ out)
 {
@@ -378,6 +379,7 @@ void dev_pcg_alpha(lddmm_plan *P) { LAUNCH1(k_pcg_alpha, P->dscal); }
 void dev_pcg_conv(lddmm_plan *P) { LAUNCH1(k_pcg_conv, P->dscal); }
 void dev_pcg_beta(lddmm_plan *P) { LAUNCH1(k_pcg_beta, P->dscal); }
 void dev_sum(lddmm_plan *P, int dst, int a, int b) { LAUNCH1(k_sum2, P->dscal, dst, a, b); }
+void dev_store_scalar(lddmm_plan *P, int slot, double *dst) { LAUNCH1(k_store_scalar, P->dscal, slot, dst); }
 
 void dev_pcg_xr(lddmm_plan *P, long n, const float *p, const float *q, float *x, float *r)
 {

@@ -121,6 +121,10 @@ class Plan:
         info["status"] = st
         return vt, info
 
+    def pcg_history(self):
+        """relative residuals ||r_k|| / ||r0|| of the last PCG solve"""
+        return L.lddmm_pcg_history(self._h)
+
     def gn_iterate(self, v, max_pcg, rtol=0.0):
         """v (updated in place) must equal the plan's current velocity."""
         return L.lddmm_gn_iterate(self._h, max_pcg, rtol, v)
@@ -172,7 +176,8 @@ class Plan:
         return out[0] if single else out
 
     def get_field(self, what, j=0):
-        vec = what in (L.FIELD_DISP, L.FIELD_DISP_ADJ, L.FIELD_GRAD_STATE)
+        vec = what in (L.FIELD_DISP, L.FIELD_DISP_ADJ, L.FIELD_GRAD_STATE, L.FIELD_PCG_R, L.FIELD_PCG_Z,
+                       L.FIELD_PCG_P)
         out = self._vector() if vec else self._scalar()
         L.lddmm_get_field(self._h, what, j, out)
         return out

@@ -9,6 +9,7 @@ import oracle
 import synth
 from gpu_util import DEV, rel, say, to_dev, to_np
 from paper_2008_12820_amd import Plan
+from paper_2008_12820_amd import _lib as L
 from paper_2008_12820_amd.batch import Batch
 
 pytestmark = pytest.mark.gpu
@@ -63,4 +64,42 @@ def test_batch_matches_plain_gn(use_graph):
     for it in range(2):
         v_ref, rinfo = ref.gn_iterate(6, 0.0)
     assert rel(to_np(vb[3]), v_ref) < 1e-4
+    Bt.close()
+
+
+def test_batch_graph_follows_set_beta():
+    """A member's captured iteration is recaptured after a beta change (beta
+    is an argument of the captured kernels): the batch still equals the
+    plain lddmm_gn_iterate at the new beta."""
+    say("batch graph after set_beta")
+    sizes = [16, 20]
+    mem = [_member(n, 5100 + 10 * b) for b, n in enumerate(sizes)]
+    shapes = [(n, n, n) for n in sizes]
+    Bt = Batch(shapes, NT, reg=2, beta=BETA, nstreams=2)
+    m0s = [to_dev(m[0]) for m in mem]
+    m1s = [to_dev(m[1]) for m in mem]
+    vb = [torch.zeros((3,) + s, device=DEV) for s in shapes]
+    Bt.set_images(m0s, m1s)
+    Bt.set_velocity(vb)
+    plans, vp = [], []
+    for b, s in enumerate(shapes):
+        P = Plan(s, NT, reg=2, beta=BETA)
+        P.set_images(m0s[b], m1s[b])
+        v = torch.zeros((3,) + s, device=DEV)
+        P.set_velocity(v)
+        plans.append(P)
+        vp.append(v)
+    for it, beta in enumerate((BETA, 20 * BETA)):
+        if it:
+            for b, P in enumerate(plans):
+                P.set_beta(beta)
+                L.lddmm_set_beta(L.lddmm_batch_plan(Bt._h, b), beta)
+        infos = Bt.gn_iterate(vb, 4, 0.0, use_graph=True)
+        for b, P in enumerate(plans):
+            pinfo = P.gn_iterate(vp[b], 4, 0.0)
+            assert infos[b]["pcg_iters"] == pinfo["pcg_iters"], (it, b)
+            assert infos[b]["alpha"] == pinfo["alpha"], (it, b)
+            e = rel(to_np(vb[b]), to_np(vp[b]))
+            say(f"  iteration {it} beta {beta} member {b}: rel {e:.2e}")
+            assert e < 1e-6, (it, b)
     Bt.close()

@@ -153,3 +153,23 @@ def test_two_level_needs_a_halving_grid():
     with pytest.raises(LddmmError) as e:
         P.apply_2linvh0(to_dev(incremental(P.shape, 1530)), 0.0, 2)
     assert e.value.status == L.EINVAL
+
+
+def test_two_level_after_set_beta_matches_oracle():
+    """The half-grid H0 and (beta0 A_c)^{-1} follow a beta change of the fine
+    plan: the coarse plan, created at beta = 0.2 (beta0 = 0.2), must use
+    beta0 = 5e-2 after set_beta(1e-3), as the fine (beta0 A)^{-1} does."""
+    say("2LInvH0 after set_beta")
+    P, ref = _setup(shape=(32, 24, 40), nt=3, reg=2, beta=0.2)
+    r = incremental(P.shape, 1540)
+    s, _ = P.apply_2linvh0(to_dev(r), 0.0, 6)  # creates the half-grid plan at beta 0.2
+    s_ref, _ = ref.two_level_invh0(synth.f64(r), 0.0, 6)
+    e0 = rel(to_np(s), s_ref)
+    P.set_beta(1e-3)
+    ref.set_beta(1e-3)
+    s, it = P.apply_2linvh0(to_dev(r), 0.0, 6)
+    s_ref, it_ref = ref.two_level_invh0(synth.f64(r), 0.0, 6)
+    e1 = rel(to_np(s), s_ref)
+    say(f"2L beta 0.2: rel {e0:.2e}; after set_beta(1e-3): rel {e1:.2e}")
+    assert it == it_ref == 6
+    assert e0 < 1e-5 and e1 < 1e-5

@@ -177,3 +177,15 @@ def test_adjoint_conserves_integral():
     for _ in range(4):
         l = oracle.interp(l, Xa).reshape(shape)
     assert abs(l.sum() - s_end) > 20 * abs(s0 - s_end)
+
+
+def test_departure_points_at_chosen_points_equal_the_whole_field():
+    """the point-wise departure evaluation is the whole-grid one restricted"""
+    shape, nt = (16, 12, 20), 3
+    v = synth.bandlimited_vector(shape, 3, 910, max_disp=2.5)
+    X, Xa = oracle.departure(v, nt)
+    rng = np.random.default_rng(911)
+    idx = np.stack([rng.integers(0, n, 200) for n in shape])
+    Xp, Xap = oracle.departure_points(v, nt, idx)
+    assert np.array_equal(Xp, X[:, idx[0], idx[1], idx[2]])
+    assert np.array_equal(Xap, Xa[:, idx[0], idx[1], idx[2]])
