@@ -63,7 +63,9 @@ def test_batch_matches_plain_gn(use_graph):
     ref = mem[3][2]
     for it in range(2):
         v_ref, rinfo = ref.gn_iterate(6, 0.0)
-    assert rel(to_np(vb[3]), v_ref) < 1e-4
+    e = rel(to_np(vb[3]), v_ref)
+    say(f"  member 3 after two GN iterations vs oracle: rel {e:.2e}")
+    assert e < 1e-5
     Bt.close()
 
 

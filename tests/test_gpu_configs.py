@@ -59,7 +59,7 @@ def _pcg_step_check(P, ref, k):
     r_or = r - alpha * q
     z_or = oracle.reg_inverse(r_or, ref.reg, ref.beta)
     p_or = z_or + (oracle.inner(r_or, z_or, ref.h3) / rz) * p
-    return rel(xk, x_or), rel(rk, r_or), rel(pk, p_or)
+    return rel(xk, x_or), rel(rk, r_or), rel(pk, p_or), rk
 
 
 @pytest.mark.timeout(900)
@@ -81,8 +81,10 @@ def test_config2_128_gauss_newton(leray):
     say(f"  v = 0: gradient rel {eg:.2e}, matvec rel {eh:.2e}")
     assert eg < 1e-5 and eh < 1e-5
     # every PCG iteration on its own, from the GPU's state
+    rnorm = {0: np.linalg.norm(to_np(g))}
     for k in (1, 2, 5, 10):
-        ex, er, ep = _pcg_step_check(P, ref, k)
+        ex, er, ep, rk = _pcg_step_check(P, ref, k)
+        rnorm[k] = np.linalg.norm(rk)
         say(f"  PCG iteration {k} from the GPU state: x {ex:.2e}, r {er:.2e}, p {ep:.2e}")
         assert ex < 1e-5 and er < 1e-5 and ep < 1e-5, k
     # the whole first Newton step and its residual history
@@ -91,9 +93,19 @@ def test_config2_128_gauss_newton(leray):
     vt_ref, rinfo, hist_ref = ref.pcg_history(-ref.gradient(), 10, 1e-30)
     e10 = rel(to_np(vt10), vt_ref)
     dh = max(abs(a - b) / b for a, b in zip(hist, hist_ref))
-    say(f"  10-iteration step rel {e10:.2e}; history {['%.4e' % h for h in hist]}; max rel diff {dh:.2e}")
+    say(f"  10-iteration step rel {e10:.2e}; history {['%.4e' % h for h in hist]}; "
+        f"oracle {['%.4e' % h for h in hist_ref]}; max rel diff {dh:.2e}")
     assert info["pcg_iters"] == rinfo["iters"] == 10 and len(hist) == 10
-    assert e10 < 1e-5 and dh < 1e-5
+    assert e10 < 1e-5
+    # the history is ||r_k|| / ||r_0|| of the GPU's own residuals
+    for k in (1, 2, 5, 10):
+        assert abs(hist[k - 1] - rnorm[k] / rnorm[0]) <= 1e-6 * hist[k - 1], k
+    # Against the FP64 history the recursion amplifies round-off: a white
+    # error of 1e-7 ||z|| (an FP32 transform's) in each preconditioned
+    # residual z moves the FP64 history of this problem by 6.8e-3 (and x by
+    # 3.4e-7), since the next matvec multiplies the high-|k| part of p by
+    # beta |k|^4; rounding only the stored vectors to FP32 moves it by 7e-4.
+    assert dh < 2e-2
     # one Gauss-Newton iteration, then the gradient and a matvec at the new
     # velocity on both sides (the oracle takes the GPU's velocity)
     v = to_dev(zero)
@@ -104,10 +116,17 @@ def test_config2_128_gauss_newton(leray):
     J, _, _ = ref.objective()
     assert abs(gi["J_after"] - J) <= 1e-5 * J
     g, _ = P.gradient()
-    eg = rel(to_np(g), ref.gradient())
+    g_ref = ref.gradient()
+    eg = rel(to_np(g), g_ref)
     eh = rel(to_np(P.hessian_matvec(to_dev(vt))), ref.matvec(synth.f64(vt)))
-    say(f"  after one GN iteration: gradient rel {eg:.2e}, matvec rel {eh:.2e}")
-    assert eg < 1e-5 and eh < 1e-5
+    # g = beta A v + K b: the FP32 rounding of each term is relative to that
+    # term, so where the two cancel (here, after a Newton step) the relative
+    # error of g grows by c_g = (||beta A v|| + ||K b||) / ||g|| (1 at v = 0)
+    bav = 5e-4 * oracle.reg_apply(synth.f64(to_np(v)), 2)
+    c_g = (np.linalg.norm(bav) + np.linalg.norm(g_ref - bav)) / np.linalg.norm(g_ref)
+    say(f"  after one GN iteration: gradient rel {eg:.2e} (c_g {c_g:.2f}, bar {1e-5 * c_g:.2e}), "
+        f"matvec rel {eh:.2e}")
+    assert eg < 1e-5 * c_g and eh < 1e-5
     P.close()
 
 

@@ -95,8 +95,8 @@ def test_gn_solve_matches_oracle():
         assert rep[k] == rep_ref[k], k
     e = rel(to_np(v), v_ref)
     say(f"final velocity rel {e:.2e}")
-    assert e < 1e-3
-    assert abs(rep["J"] - rep_ref["J"]) <= 1e-4 * abs(rep_ref["J"])
+    assert e < 1e-5
+    assert abs(rep["J"] - rep_ref["J"]) <= 1e-5 * abs(rep_ref["J"])
 
 
 def test_gn_solve_arguments():

@@ -43,7 +43,7 @@ def test_inner_solve_matches_oracle():
     assert it == it_ref == 6
     e = rel(to_np(s), s_ref)
     say(f"6 inner iterations: rel {e:.2e}")
-    assert e < 1e-4
+    assert e < 1e-5
     # to a tolerance: the same stopping rule, so the same iteration within one.
     # The true FP64 residual of the FP32 iterate carries the FP32 rounding of s
     # times ||H0|| ~ beta0 |k_max|^4 (1.1e4 here): about 1.3e-3 of ||r|| on top
@@ -68,12 +68,14 @@ def test_newton_step_with_invh0_matches_oracle_pcg():
     assert info["inner_iters"] == pinfo["inner"] == 5 * 8
     e = rel(to_np(vt), vt_ref)
     say(f"newton step rel {e:.2e}")
-    assert e < 1e-4
+    assert e < 1e-5
     # InvA again on the same plan
     P.set_preconditioner("inva")
     vt2, info2 = P.newton_step(4, 1e-12)
     vt2_ref, _ = ref.pcg(-ref.gradient(), 4, 1e-12)
-    assert info2["inner_iters"] == 0 and rel(to_np(vt2), vt2_ref) < 1e-4
+    e2 = rel(to_np(vt2), vt2_ref)
+    say(f"newton step, InvA again: rel {e2:.2e}")
+    assert info2["inner_iters"] == 0 and e2 < 1e-5
 
 
 def test_invh0_cuts_outer_iterations():
@@ -122,14 +124,16 @@ def test_two_level_matches_oracle():
     assert it == it_ref == 6
     e = rel(to_np(s), s_ref)
     say(f"2L, 6 coarse iterations: rel {e:.2e}")
-    assert e < 1e-4
+    assert e < 1e-5
     # the coarse restriction of grad m(1) follows a new velocity
     v2 = to_dev(synth.f32(0.5 * synth.bandlimited_vector(P.shape, 3, 1521, max_disp=2.0)))
     P.set_velocity(v2)
     ref.set_velocity(synth.f64(to_np(v2)))
     s, _ = P.apply_2linvh0(to_dev(r), 0.0, 6)
     s_ref, _ = ref.two_level_invh0(synth.f64(r), 0.0, 6)
-    assert rel(to_np(s), s_ref) < 1e-4
+    e = rel(to_np(s), s_ref)
+    say(f"2L after a new velocity: rel {e:.2e}")
+    assert e < 1e-5
 
 
 def test_newton_step_with_two_level_matches_oracle_pcg():
@@ -142,7 +146,7 @@ def test_newton_step_with_two_level_matches_oracle_pcg():
     assert info["inner_iters"] == pinfo["inner"] == 5 * 8
     e = rel(to_np(vt), vt_ref)
     say(f"newton step (2L) rel {e:.2e}")
-    assert e < 1e-4
+    assert e < 1e-5
 
 
 def test_two_level_needs_a_halving_grid():

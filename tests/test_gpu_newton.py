@@ -84,7 +84,9 @@ def test_inv_reg_and_newton_step_match_oracle_pcg():
     g_ref = ref.gradient()
     vt_ref, pinfo = ref.pcg(-g_ref, 10, 1e-12)
     assert info["pcg_iters"] == pinfo["iters"] == 10
-    assert rel(to_np(vt), vt_ref) < 1e-4
+    e = rel(to_np(vt), vt_ref)
+    say(f"  10-iteration Newton step rel {e:.2e}, rel_res {info['rel_res']:.6e} vs {pinfo['rel_res']:.6e}")
+    assert e < 1e-5
     assert abs(info["rel_res"] - pinfo["rel_res"]) < 1e-3 * max(pinfo["rel_res"], 1e-3)
 
 
@@ -121,7 +123,9 @@ def test_gn_iterate_matches_oracle():
     v_ref, rinfo = ref.gn_iterate(5, 0.0)
     assert info["alpha"] == rinfo["alpha"] and info["alpha"] > 0
     assert abs(info["J_after"] - rinfo["J_after"]) / rinfo["J_after"] < 1e-5
-    assert rel(to_np(vd), v_ref) < 1e-4
+    e = rel(to_np(vd), v_ref)
+    say(f"  GN iterate velocity rel {e:.2e}")
+    assert e < 1e-5
     assert abs(P.objective()[0] - info["J_after"]) <= 1e-6 * info["J_after"]
 
 
