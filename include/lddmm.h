@@ -182,6 +182,25 @@ lddmm_status lddmm_transport_forward(lddmm_plan *plan, const float *m0, const fl
 lddmm_status lddmm_transport_vjp(lddmm_plan *plan, const float *ckpt, const float *v,
                                  const float *grad_m1, float *grad_m0, float *grad_v);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the transport
+ * map of lddmm_transport_forward without a plan.  cfg gives the grid, N_t
+ * and the interpolation order (LDDMM_FLAG_LINEAR_IP; the other flags, reg,
+ * leray and beta are validated but not used); stream is a hipStream_t
+ * (NULL = the null stream) on the current device.  Writes m(1) to m1_out (N)
+ * and, when ckpt is not NULL, every m_j to ckpt ((N_t+1) N); m0, v, m1_out,
+ * ckpt are caller-owned device arrays, m0 and m1_out distinct.  Results are
+ * bitwise those of lddmm_transport_forward.  Nothing is allocated: the
+ * departure displacements and a state buffer (7N floats) live in a static
+ * device array of 56 MiB that each GPU the library runs on holds until the
+ * process ends, so at most 2^21 grid points (128^3): EINVAL beyond that.
+ * Every call on a GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (other streams or threads) race, so serialise them.  Asynchronous
+ * on the stream; the array is written before it is read, nothing needs
+ * clearing. */
+lddmm_status lddmm_transport_forward_static(const lddmm_config *cfg, void *stream, const float *m0,
+                                            const float *v, float *m1_out, float *ckpt);
+
 /* Regularisation energy E = 1/2 sum_x (A v) . v (plain sum over the grid, no
  * h^3; beta not applied) and, when Av is not NULL, A v (3N) -- the beta/2
  * reg(v) term of eq. "problem" up to the factors beta h^3, and its gradient

@@ -96,6 +96,7 @@ def lib():
             "lddmm_pcg_history": (st, [p, P(d), i32, P(i32)]),
             "lddmm_transport_forward": (st, [p, p, p, p, p]),
             "lddmm_transport_vjp": (st, [p, p, p, p, p, p]),
+            "lddmm_transport_forward_static": (st, [P(Config), p, p, p, p, p]),
             "lddmm_reg_energy": (st, [p, p, p, P(d)]),
             "lddmm_fft_r2c": (st, [p, p, p]),
             "lddmm_fft_c2r": (st, [p, p, p]),
@@ -270,6 +271,11 @@ def lddmm_gn_iterate(plan, max_pcg, rtol, v_inout):
 def lddmm_transport_forward(plan, m0, v, m1_out, ckpt=None):
     _check(lib().lddmm_transport_forward(plan, _ptr(m0), _ptr(v), _ptr(m1_out), _ptr(ckpt)),
            "transport_forward")
+
+
+def lddmm_transport_forward_static(cfg, stream, m0, v, m1_out, ckpt=None):
+    _check(lib().lddmm_transport_forward_static(ctypes.byref(cfg), ctypes.c_void_p(stream), _ptr(m0), _ptr(v),
+                                                _ptr(m1_out), _ptr(ckpt)), "transport_forward_static")
 
 
 def lddmm_transport_vjp(plan, ckpt, v, grad_m1, grad_m0=None, grad_v=None):

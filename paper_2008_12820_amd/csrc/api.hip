@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -1451,5 +1452,89 @@ const char *lddmm_status_string(lddmm_status s)
 }
 
 const char *lddmm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Transport map without device allocation (lddmm_transport_forward_static).
+// The departure displacements and the state ping-pong live in one
+// file-scope device array, one copy per GPU for the life of the process; its
+// device address is looked up once per device and kept.  The host-side
+// array name is not a device address, so only the looked-up pointer is
+// handed to kernels.
+// ---------------------------------------------------------------------------
+namespace lddmm {
+
+constexpr long kStaticMaxPoints = 1L << 21;  // 128^3 grid points
+constexpr long kStaticFloats = 7 * kStaticMaxPoints;  // dX, dXa (3N each), one state buffer (N)
+static __device__ __align__(256) float scratch[kStaticFloats];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's copy of the array (looked up on first use, with that
+// device current)
+static float *static_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) fail(LDDMM_EDEVICE, "device index " + std::to_string(dev) + " out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr) fail(LDDMM_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = (float *)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace lddmm
+
+extern "C" {
+
+lddmm_status lddmm_transport_forward_static(const lddmm_config *cfg, void *stream, const float *m0, const float *v,
+                                            float *m1_out, float *ckpt)
+{
+    return guard([&] {
+        validate(cfg);
+        need_dev(m0, "m0");
+        need_dev(v, "v");
+        need_dev(m1_out, "m1_out");
+        need_dev(ckpt, "ckpt", true);
+        if (m0 == m1_out) fail(LDDMM_EINVAL, "m0 and m1_out must be distinct arrays");
+        const long N = (long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+        if (N > kStaticMaxPoints)
+            fail(LDDMM_EINVAL, "lddmm_transport_forward_static: " + std::to_string(N) + " grid points exceed its " +
+                                   std::to_string(kStaticMaxPoints) + "-point maximum (use lddmm_transport_forward)");
+        // a plan record on the host only: no workspace, no tile-extents tables
+        // (the gathers reduce their extents themselves), timing off
+        lddmm_plan T;
+        T.cfg = *cfg;
+        T.stream = (hipStream_t)stream;
+        check_hip(hipGetDevice(&T.device), "hipGetDevice");
+        T.N = N;
+        T.nt = cfg->nt;
+        for (int d = 0; d < 3; ++d) T.h[d] = 2.0 * M_PI / cfg->n[d];
+        T.h3 = T.h[0] * T.h[1] * T.h[2];
+        T.dt = 1.0 / cfg->nt;
+        float *s = static_scratch(T.device);
+        float *dX = s, *dXa = s + 3 * N, *buf = s + 6 * N;
+        launch_departure(&T, v, dX, dXa);
+        if (ckpt) {
+            copy_kernel(&T, N, m0, ckpt);
+            for (int j = 0; j < T.nt; ++j)
+                launch_interp(&T, 1, ckpt + (long)j * N, dX, ckpt + (long)(j + 1) * N, K_STATE_STEP);
+            copy_kernel(&T, N, ckpt + (long)T.nt * N, m1_out);
+        } else {
+            // m_j alternates between buf and m1_out so that the last step writes m1_out
+            const float *cur = m0;
+            for (int j = 0; j < T.nt; ++j) {
+                float *dst = ((T.nt - 1 - j) % 2 == 0) ? m1_out : buf;
+                launch_interp(&T, 1, cur, dX, dst, K_STATE_STEP);
+                cur = dst;
+            }
+        }
+    });
+}
 
 }  // extern "C"
