@@ -40,7 +40,8 @@ def kernel_bytes(cls, n, nt):
     input and output once.  Leray on (assembly: 6 fields in, 3 out)."""
     n1, n2, n3 = n
     N = n1 * n2 * n3
-    S = n1 * n2 * (n3 // 2 + 1) * 8  # one half-spectrum field
+    S = n1 * n2 * (n3 // 2 + 1) * 8  # one FP32 half-spectrum field (complex64)
+    D = 2 * S                        # the same in FP64 (the forward chain of v~)
     return {
         # incremental-state start: dX 12 + v~ 12 (gathered and read pointwise,
         # counted once) + I[G_j](X) 12 nt + G_{j+1} 12 nt; writes m~_1 and
@@ -55,9 +56,12 @@ def kernel_bytes(cls, n, nt):
         "adj_body": (16 * nt + 44) * N,
         # (transport VJP only) lam_j (nt+1) + G_j 3 (nt+1) + b 3
         "body_force": (16 * (nt + 1) + 12) * N,
-        "r2c_x3": 6 * (4 * N + S),
-        "fft_cols": (6 + 3) * 2 * S,
-        "x1_symbol": (6 + 3) * S,
+        # x3 R2C of v~ (FP32 in, FP64 out) and of b~ (FP32 in and out)
+        "r2c_x3": 3 * (4 * N + D) + 3 * (4 * N + S),
+        # x2 forward of v~ (FP64) and b~ (FP32), x2 inverse of the result (FP32)
+        "fft_cols": 3 * 2 * D + 3 * 2 * S + 3 * 2 * S,
+        # fused x1 forward (v~ FP64, b~ FP32), symbol, x1 inverse (FP32 out)
+        "x1_symbol": 3 * D + 3 * S + 3 * S,
         "c2r_x3": 3 * (S + 4 * N),
     }.get(cls)
 
@@ -136,6 +140,57 @@ def time_matvecs(plan, vts_dev, steps, warmup, torch, only=None):
     return t1 - t0, kt
 
 
+def matvec_spread(plan, vts_dev, steps, torch):
+    """Each of `steps` matvecs bracketed by HIP events on the plan's stream
+    (a pass of its own after the timed region): median, minimum and mean ms."""
+    import numpy as np
+    out = torch.empty_like(vts_dev[0])
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    plan.hessian_matvec(vts_dev[0], out)
+    torch.cuda.synchronize()
+    for i in range(steps):
+        ev[i][0].record()
+        plan.hessian_matvec(vts_dev[i % len(vts_dev)], out)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"median_ms": float(np.median(t)), "min_ms": float(t.min()), "mean_ms": float(t.mean()),
+            "max_ms": float(t.max()), "matvecs": steps}
+
+
+def bench_config2(torch, dev):
+    """The 128^3 Gauss-Newton problem (40-blob template, its image under a
+    divergence-free band-limited velocity |k| <= 6 of about 4 voxels, H2
+    beta = 5e-4, N_t = 4): one Newton step of exactly 10 PCG iterations with
+    (beta A)^{-1} from v = 0, on the GPU (warm, mean of three).  Returns the
+    GPU figures and the inputs for the oracle's run of the same step."""
+    import synth
+    from paper_2008_12820_amd import Plan
+    n = (128, 128, 128)
+    m0 = synth.f32(synth.blob_image(n, 40, 2000))
+    vtrue = synth.f32(synth.bandlimited_vector(n, 6, 2001, max_disp=4.0, divfree=True))
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    T = Plan(n, 4, reg=2, beta=5e-4, device=dev, transport_only=True)
+    m1 = T.transport_forward(to(m0), to(vtrue))
+    T.close()
+    P = Plan(n, 4, reg=2, beta=5e-4, device=dev)
+    P.autotune()
+    P.set_images(to(m0), m1)
+    zero = torch.zeros((3,) + n, device=dev)
+    P.set_velocity(zero)
+    P.autotune()
+    P.newton_step(10, 1e-30)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        _, info = P.newton_step(10, 1e-30)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / 3
+    m1h = m1.cpu().numpy()
+    P.close()
+    return {"grid": list(n), "pcg_iters": info["pcg_iters"], "newton_step_ms": 1e3 * el}, (m0, m1h)
+
+
 def bench_leray_off(torch, dev, n, m0d, m1d, vd, vtd, steps, warmup):
     """The same matvec with the Leray projection off (K = I): the assembly is
     pointwise in b, A v~ runs wholly beside the transport sweeps."""
@@ -163,6 +218,54 @@ def dominant_class(kt, n, nt):
     return max((k for k in kt if kernel_bytes(k, n, nt) is not None), key=lambda k: kt[k][0])
 
 
+# the oracle's 128^3 matvec on one thread, in a child process (the OpenMP
+# thread count is fixed at the runtime's start); prints the seconds
+_ONE_THREAD = r"""
+import sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import oracle, synth
+n = (128, 128, 128)
+m0 = synth.f32(synth.blob_image(n, 40, 3000))
+m1 = synth.f32(synth.blob_image(n, 40, 3002))
+v = synth.f32(0.5 * synth.bandlimited_vector(n, 8, 3001, max_disp=3.0))
+vt = synth.f32(synth.unit_rms(synth.bandlimited_vector(n, 8, 3100)))
+P = oracle.Problem(n, 4, reg=2, beta=5e-4, leray=True)
+P.set_images(synth.f64(m0), synth.f64(m1))
+P.set_velocity(synth.f64(v))
+t0 = time.perf_counter()
+P.matvec(synth.f64(vt))
+print(time.perf_counter() - t0)
+"""
+
+
+def oracle_one_thread():
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ONE_THREAD, ROOT], env=env, capture_output=True, text=True,
+                       timeout=600)
+    if r.returncode != 0:
+        log(f"one-thread oracle run failed: {r.stderr[-400:]}")
+        return None
+    return float(r.stdout.strip().splitlines()[-1])
+
+
+def oracle_config2(m0, m1):
+    """the oracle's Newton step (10 PCG iterations, InvA, from v = 0) on the
+    128^3 problem of bench_config2, with the precompute and gradient"""
+    import numpy as np
+    import oracle
+    import synth
+    n = m0.shape
+    P = oracle.Problem(n, 4, reg=2, beta=5e-4)
+    P.set_images(synth.f64(m0), synth.f64(m1))
+    t0 = time.perf_counter()
+    P.set_velocity(np.zeros((3,) + n))
+    g = P.gradient()
+    P.pcg(-g, 10, 1e-30)
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(n, nt, m0, m1, v, vt, sample):
     import numpy as np
     import oracle
@@ -176,8 +279,10 @@ def cpu_baseline(n, nt, m0, m1, v, vt, sample):
         v, vt = v[(slice(None),) + sl], vt[(slice(None),) + sl]
     P = oracle.Problem(shape, nt, reg=2, beta=5e-4, leray=True)
     P.set_images(synth.f64(m0), synth.f64(m1))
-    log(f"oracle precompute {shape} (untimed)")
+    log(f"oracle precompute {shape} (timed apart)")
+    t0 = time.perf_counter()
     P.set_velocity(synth.f64(v))
+    t_pre = time.perf_counter() - t0
     log("oracle matvec (timed)")
     t0 = time.perf_counter()
     P.matvec(synth.f64(vt))
@@ -201,6 +306,7 @@ def cpu_baseline(n, nt, m0, m1, v, vt, sample):
                    f"precompute untimed), {dt:.2f} s" +
                    ("" if sample == "full" else "; scaled by the point-count ratio to 256^3")),
         "seconds": dt,
+        "precompute_seconds": t_pre,
         "cpu_model": cpu,
     }
 
@@ -408,8 +514,10 @@ def main():
                     help="serialise the assembly's forward transform with the transport sweeps")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", choices=["full", "half"], default="full")
-    ap.add_argument("--batched", action="store_true", help="add the 64-member batched run")
-    ap.add_argument("--autograd", action="store_true", help="add the 512^3 autograd run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-member batched run")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the 512^3 autograd run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the matvec lines (no Leray-off, FFT, SYN, 128^3 Newton, batched, autograd)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -468,8 +576,10 @@ def main():
         plan.set_overlap(not args.no_overlap)
         log(f"timing {steps} matvecs nt={nt_} (events on {dom_}, overlap {not args.no_overlap})")
         el, kt_dom = time_matvecs(plan, vtd, steps, args.warmup, torch, only=dom_)
+        spread = matvec_spread(plan, vtd, steps, torch)
+        log(f"per-matvec events nt={nt_}: {spread}")
         res_nt[nt_] = dict(elapsed=el, steps=steps, kt=kt, prof_steps=prof_steps, kt_dom=kt_dom, dom=dom_,
-                           precompute_s=pre,
+                           precompute_s=pre, spread=spread,
                            gradient_s=tg, tuning=tuning)
         if nt_ == 4:
             log("newton step, 10 PCG iterations")
@@ -562,6 +672,9 @@ def main():
     def matvec_alg_bytes(nt_):  # whole-matvec algorithmic bytes (Leray on): the classes' sum
         return sum(kernel_bytes(k, n, nt_) for k in MATVEC_CLASSES)
 
+    def survey_bytes(nt_):  # the unfused step count, (136 + 132 N_t) B per grid point (Leray on)
+        return (136 + 132 * nt_) * N
+
     out = {
         "metric": "Hessian matvecs/s and transport grid-pts/s at 256^3 FP32; % HBM roofline",
         "value": value,
@@ -583,7 +696,11 @@ def main():
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": t_dom_ms / launches},
         "transport": transport_rate(r4, 4),
+        "matvec_alg_bytes_per_pt": matvec_alg_bytes(nt) / N,
         "matvec_alg_hbm_frac": matvec_alg_bytes(nt) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "matvec_unfused_bytes_per_pt": survey_bytes(nt) / N,
+        "matvec_unfused_hbm_frac": survey_bytes(nt) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "matvec_events": r4["spread"],
         "kernels": kernels,
         "precompute_ms": 1e3 * r4["precompute_s"],
         "gradient_ms": 1e3 * r4["gradient_s"],
@@ -600,6 +717,8 @@ def main():
         out["nt8"] = {"matvecs_per_s": r8["steps"] / r8["elapsed"], "ms_per_matvec": ms8,
                       "transport": transport_rate(r8, 8),
                       "matvec_alg_hbm_frac": matvec_alg_bytes(8) / (ms8 * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                      "matvec_unfused_hbm_frac": survey_bytes(8) / (ms8 * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                      "matvec_events": r8["spread"],
                       "precompute_ms": 1e3 * r8["precompute_s"]}
     if args.copy_calibration:
         # a plain copy of known size: 1 GiB read + 1 GiB written per launch
@@ -613,16 +732,31 @@ def main():
         out["copy_calibration"] = {"bytes_read": 1 << 30, "bytes_written": 1 << 30,
                                    "GBps": 5 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9}
         del src, dst
-    out["leray_off"] = bench_leray_off(torch, dev, n, m0d, m1d, vd, vtd, args.steps, args.warmup)
-    out["fft_vs_rocfft"] = fft_comparison(torch, dev, n)
-    out["syn_workload"] = bench_syn(torch, dev, n)
-    if args.batched:
-        out["batched"] = bench_batched(torch, dev)
-    if args.autograd:
-        out["autograd"] = bench_autograd(torch, dev)
+    c2_inputs = None
+    if not args.no_extras:
+        out["leray_off"] = bench_leray_off(torch, dev, n, m0d, m1d, vd, vtd, args.steps, args.warmup)
+        out["fft_vs_rocfft"] = fft_comparison(torch, dev, n)
+        out["syn_workload"] = bench_syn(torch, dev, n)
+        log("128^3 Newton step (10 PCG)")
+        out["newton_128"], c2_inputs = bench_config2(torch, dev)
+        if not args.no_batched:
+            out["batched"] = bench_batched(torch, dev)
+            log(f"batched: {out['batched']}")
+        if not args.no_autograd:
+            out["autograd"] = bench_autograd(torch, dev)
+            log(f"autograd: {out['autograd']}")
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle)")
         out["cpu_baseline"] = cpu_baseline(n, nt, m0, m1, v, vts[0], args.cpu_sample)
+        out["cpu_baseline"]["precompute_vs_gpu"] = out["cpu_baseline"]["precompute_seconds"] / (
+            out["precompute_ms"] * 1e-3)
+        if not args.no_extras:
+            log("oracle: one thread, one matvec at 128^3")
+            out["cpu_baseline"]["one_thread_128_matvec_s"] = oracle_one_thread()
+            log("oracle: 128^3 Newton step")
+            t_or = oracle_config2(*c2_inputs)
+            out["newton_128"]["oracle_s"] = t_or
+            out["newton_128"]["oracle_cores"] = out["cpu_baseline"]["cores"]
     else:
         out["cpu_baseline"] = None
     out["host"] = platform.node()

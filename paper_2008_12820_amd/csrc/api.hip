@@ -147,7 +147,7 @@ static Layout make_layout(const lddmm_config *cfg)
     for (int i = 0; i < 6; ++i) L.add(full * 3 * f);  // 16..21 pcg x r z p q vt
     L.add(spectral_slots(cfg) * 2 * spec);  // 22 spec (slots sized for FP64)
     L.add(sizeof(double) * kRedBlocks);     // 23 red
-    L.add(sizeof(double) * kNumScalars);    // 24 dscal
+    L.add(sizeof(double) * 2 * kNumScalars);  // 24 dscal (two banks)
     L.add(2 * tile_boxes_bytes(cfg->n));     // 25 stencil extents per gather tile (dX, dXa)
     L.add(sizeof(double) * kHistMax);       // 26 PCG residual history
     return L;
@@ -168,6 +168,8 @@ static void plan_free(lddmm_plan *P)
     if (P->arena) (void)hipFree(P->arena);
     if (P->hscal) (void)hipHostFree(P->hscal);
     for (hipEvent_t e : P->ev_poll)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : P->ev_inner)
         if (e) (void)hipEventDestroy(e);
     for (auto &pr : P->timing.pool) {
         (void)hipEventDestroy(pr.first);
@@ -419,41 +421,86 @@ static float *h0_vectors(lddmm_plan *P)
     return P->h0buf;
 }
 
+// The stop test of a device-resident PCG loop: iteration k has been
+// enqueued; the host reads the stop flag (slot S_DONE of the current bank)
+// that iteration k - 1 left, through a pinned copy and an event, so the
+// stream holds one iteration ahead and never drains.  An iteration queued
+// after the stop is predicated off on the device.  Returns true on a stop.
+struct StopPoll {
+    lddmm_plan *P;
+    hipEvent_t *ev;
+    double *host;
+    StopPoll(lddmm_plan *p, hipEvent_t *events, double *pinned) : P(p), ev(events), host(pinned)
+    {
+        for (int i = 0; i < 2; ++i)
+            if (!ev[i]) check_hip(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming), "hipEventCreateWithFlags");
+    }
+    bool after(int it)
+    {
+        check_hip(hipMemcpyAsync(host + (it & 1), scalars(P) + S_DONE, sizeof(double), hipMemcpyDeviceToHost,
+                                 P->stream),
+                  "stop flag copy");
+        check_hip(hipEventRecord(ev[it & 1], P->stream), "hipEventRecord");
+        if (it < 1) return false;
+        check_hip(hipEventSynchronize(ev[(it - 1) & 1]), "hipEventSynchronize");
+        return host[(it - 1) & 1] != 0.0;
+    }
+};
+
+struct BankScope {
+    lddmm_plan *P;
+    int keep;
+    BankScope(lddmm_plan *p, int b) : P(p), keep(p->bank) { P->bank = b; }
+    ~BankScope() { P->bank = keep; }
+};
+
 // s ~= H0^{-1} r: PCG on H0 s = r preconditioned by (beta0 A)^{-1}, from
 // s = (beta0 A)^{-1} r, until ||r - H0 s|| <= tol ||r||, max_it iterations or
-// <p, H0 p> <= 0.  Returns the iterations (H0 applications after the start).
-static int invh0_impl(lddmm_plan *P, const float *r, float *s, double tol, int max_it)
+// <p, H0 p> <= 0; every scalar on the device (bank 1 of P), the stop test
+// lagged by one iteration.  outer (may be NULL): the bank-0 scalars of the
+// outer PCG this solve preconditions; the solve then does nothing once that
+// PCG has stopped and adds its iterations to the outer S_INNER.
+static void invh0_dev(lddmm_plan *P, const float *r, float *s, double tol, int max_it, double *outer)
 {
     const long M = 3 * P->N;
     float *w = h0_vectors(P);
     float *ri = w, *zi = w + M, *pi = w + 2 * M, *qi = w + 3 * M;
     Beta0Scope b0(P);
+    BankScope bk(P, 1);
+    StopPoll poll(P, P->ev_inner, P->hscal + kNumScalars + 2);
+    dev_set_scalar(P, S_RTOL, tol);
+    dot_async(P, r, r, M, S_RR, P->h3);
+    dev_pcg_init(P);  // S_R0 = ||r||; stopped when r = 0
+    if (outer) dev_inner_link(P, outer);
     inv_reg(P, r, s);
-    const double rn0 = std::sqrt(dot_now(P, r, r, M));
-    if (rn0 == 0.0) return 0;
     h0_apply(P, s, qi);
     axpby(P, M, 1.f, r, -1.f, qi, ri);
-    double rn = std::sqrt(dot_now(P, ri, ri, M));
-    if (rn <= tol * rn0) return 0;
+    dot_async(P, ri, ri, M, S_RR, P->h3);
+    dev_pcg_conv(P);  // the start may already meet the tolerance
     inv_reg(P, ri, zi);
-    copy_dev(P, pi, zi, M);
-    double rz = dot_now(P, ri, zi, M);
-    int it = 0;
-    while (it < max_it) {
+    copy_kernel(P, M, zi, pi);
+    dot_async(P, ri, zi, M, S_RZ, P->h3);
+    for (int it = 0; it < max_it; ++it) {
         h0_apply(P, pi, qi);
-        ++it;
-        const double kappa = dot_now(P, pi, qi, M);
-        if (!(kappa > 0.0)) break;
-        pcg_update_xr(P, M, (float)(rz / kappa), pi, qi, s, ri);
-        rn = std::sqrt(dot_now(P, ri, ri, M));
-        if (rn <= tol * rn0) break;
+        dot_async(P, pi, qi, M, S_KAPPA, P->h3);
+        dev_pcg_alpha(P);
+        dev_pcg_xr(P, M, pi, qi, s, ri);
+        dot_async(P, ri, ri, M, S_RR, P->h3);
+        dev_pcg_conv(P);
         inv_reg(P, ri, zi);
-        const double rz_new = dot_now(P, ri, zi, M);
-        const double be = rz_new / rz;
-        rz = rz_new;
-        axpby(P, M, 1.f, zi, (float)be, pi, pi);
+        dot_async(P, ri, zi, M, S_RZN, P->h3);
+        dev_pcg_beta(P);
+        dev_pcg_p(P, M, zi, pi);
+        if (poll.after(it)) break;
     }
-    return it;
+    if (outer) dev_inner_accum(P, outer);
+}
+
+// iterations of the last invh0_dev on P (synchronises the stream)
+static int inner_iterations(lddmm_plan *P)
+{
+    BankScope bk(P, 1);
+    return (int)fetch_scalar(P, S_ITERS);
 }
 
 // ---- two-level variant 2LInvH0 (Algorithm "PC", second function) ---------
@@ -501,7 +548,7 @@ static void resample3(lddmm_plan *F, const float *in, lddmm_plan *C, float *out)
 // coarse start: R and (b0 A)^{-1} commute (the same symbol at every kept
 // wavenumber), so R s_f = s_c0 and one fine restriction is saved.  The coarse
 // plan holds R grad m(1) in its grad m_{N_t} slot, refreshed per velocity.
-static int twolevel_impl(lddmm_plan *P, const float *r, float *s, double tol, int max_it)
+static void twolevel_dev(lddmm_plan *P, const float *r, float *s, double tol, int max_it, double *outer)
 {
     lddmm_plan *C = coarse_plan(P);
     // the half-grid H0 and (beta0 A_c)^{-1} take the fine plan's beta0: the
@@ -523,43 +570,42 @@ static int twolevel_impl(lddmm_plan *P, const float *r, float *s, double tol, in
         Beta0Scope b0(C);
         inv_reg(C, rc, sc0);
     }
-    const int it = invh0_impl(C, rc, sc, tol, max_it);
+    invh0_dev(C, rc, sc, tol, max_it, outer);
     axpby(C, Mc, 1.f, sc, -1.f, sc0, sc);
     resample3(C, sc, P, tmp);
     axpby(P, M, 1.f, s, 1.f, tmp, s);
-    return it;
 }
 
-// the preconditioner M^{-1} r of the outer PCG (tol_outer: its eps_K);
-// returns the inner iterations
-static int precondition(lddmm_plan *P, const float *r, float *z, double tol_outer)
+// the preconditioner M^{-1} r of the outer PCG (tol_outer: its tolerance);
+// InvH0 and 2LInvH0 add their inner iterations to the outer S_INNER
+static void precondition(lddmm_plan *P, const float *r, float *z, double tol_outer)
 {
-    if (P->pc_kind == 1) return invh0_impl(P, r, z, P->pc_eps_h0 * tol_outer, P->pc_max_inner);
-    if (P->pc_kind == 2) return twolevel_impl(P, r, z, P->pc_eps_h0 * tol_outer, P->pc_max_inner);
-    inv_reg(P, r, z);
-    return 0;
+    if (P->pc_kind == 1)
+        invh0_dev(P, r, z, P->pc_eps_h0 * tol_outer, P->pc_max_inner, P->dscal);
+    else if (P->pc_kind == 2)
+        twolevel_dev(P, r, z, P->pc_eps_h0 * tol_outer, P->pc_max_inner, P->dscal);
+    else
+        inv_reg(P, r, z);
 }
 
-// PCG with M^{-1} = (beta A)^{-1} and every scalar on the device (the
-// kernels of pcg_enqueue): iteration k is enqueued before the host reads the
-// stop flag of iteration k - 1, so the stream never drains between
-// iterations; after a stop the one iteration already queued is predicated
-// off (its matvec runs, its updates do not), which gives the early exit of
-// the host loop with the same arithmetic.
-static int pcg_device(lddmm_plan *P, const float *rhs, int max_it, double rtol, float *x,
-                      lddmm_newton_info &info)
+// Preconditioned CG on H x = rhs, x0 = 0, M^{-1} = (beta A)^{-1} or the InvH0
+// / 2LInvH0 inner solve, every scalar on the device (bank 0): iteration k is
+// enqueued before the host reads the stop flag of iteration k - 1, so the
+// stream never drains between iterations; after a stop the one iteration
+// already queued is predicated off (its matvec runs, its updates do not),
+// which gives the early exit of a host loop with the same arithmetic.
+static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, float *x,
+                    lddmm_newton_info &info)
 {
     const long M = 3 * P->N;
     float *r = P->pr, *z = P->pz, *p = P->pp, *q = P->pq;
-    for (hipEvent_t &e : P->ev_poll)
-        if (!e) check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
-    double *poll = P->hscal + kNumScalars;
+    StopPoll poll(P, P->ev_poll, P->hscal + kNumScalars);
     dev_set_scalar(P, S_RTOL, rtol);
     copy_kernel(P, M, rhs, r);
     fill(P, M, 0.f, x);
     dot_async(P, r, r, M, S_RR, P->h3);
     dev_pcg_init(P);
-    inv_reg(P, r, z);
+    precondition(P, r, z, rtol);
     copy_kernel(P, M, z, p);
     dot_async(P, r, z, M, S_RZ, P->h3);
     for (int it = 0; it < max_it; ++it) {
@@ -571,18 +617,11 @@ static int pcg_device(lddmm_plan *P, const float *rhs, int max_it, double rtol, 
         dot_async(P, r, r, M, S_RR, P->h3);
         dev_pcg_conv(P);
         if (it < kHistMax) dev_store_scalar(P, S_REL, P->hist + it);
-        inv_reg(P, r, z);
+        precondition(P, r, z, rtol);
         dot_async(P, r, z, M, S_RZN, P->h3);
         dev_pcg_beta(P);
         dev_pcg_p(P, M, z, p);
-        check_hip(hipMemcpyAsync(poll + (it & 1), P->dscal + S_DONE, sizeof(double), hipMemcpyDeviceToHost,
-                                 P->stream),
-                  "stop flag copy");
-        check_hip(hipEventRecord(P->ev_poll[it & 1], P->stream), "hipEventRecord");
-        if (it >= 1) {
-            check_hip(hipEventSynchronize(P->ev_poll[(it - 1) & 1]), "hipEventSynchronize");
-            if (poll[(it - 1) & 1] != 0.0) break;  // iteration it is queued, predicated off
-        }
+        if (poll.after(it)) break;  // iteration it is queued, predicated off
     }
     check_hip(hipMemcpyAsync(P->hscal, P->dscal, sizeof(double) * kNumScalars, hipMemcpyDeviceToHost, P->stream),
               "scalar copy");
@@ -590,72 +629,13 @@ static int pcg_device(lddmm_plan *P, const float *rhs, int max_it, double rtol, 
     const double *h = P->hscal;
     info.pcg_iters = (int)h[S_ITERS];
     info.rel_res = h[S_REL];
-    info.inner_iters = 0;
+    info.inner_iters = (int)h[S_INNER];
     info.flags = (int)h[S_FLAGS];
     P->pcg_hist.assign(std::min(info.pcg_iters, kHistMax), 0.0);
     if (!P->pcg_hist.empty())
         check_hip(hipMemcpy(P->pcg_hist.data(), P->hist, sizeof(double) * P->pcg_hist.size(), hipMemcpyDeviceToHost),
                   "history copy");
     return info.flags;
-}
-
-// Preconditioned CG on H x = rhs, x0 = 0, M^{-1} = (beta A)^{-1} (device
-// resident) or the InvH0 / 2LInvH0 inner solve (host loop).
-static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, float *x,
-                    lddmm_newton_info &info)
-{
-    if (P->pc_kind == 0) return pcg_device(P, rhs, max_it, rtol, x, info);
-    P->pcg_hist.clear();
-    const long M = 3 * P->N;
-    float *r = P->pr, *z = P->pz, *p = P->pp, *q = P->pq;
-    copy_dev(P, r, rhs, M);
-    zero_dev(P, x, M);
-    const double r0 = std::sqrt(dot_now(P, r, r, M));
-    int it = 0, flags = 0;
-    double rn = r0;
-    info.pcg_iters = 0;
-    info.rel_res = 0.0;
-    info.inner_iters = 0;
-    if (r0 == 0.0) return 0;
-    info.inner_iters += precondition(P, r, z, rtol);
-    copy_dev(P, p, z, M);
-    double rz = dot_now(P, r, z, M);
-    while (it < max_it) {
-        matvec_impl(P, p, q);
-        ++it;
-        const double kappa = dot_now(P, p, q, M);
-        if (!std::isfinite(kappa)) {
-            flags |= 2;
-            P->pcg_hist.push_back(rn / r0);
-            break;
-        }
-        if (kappa <= 0.0) {
-            flags |= 1;
-            if (it == 1) copy_dev(P, x, z, M);
-            P->pcg_hist.push_back(rn / r0);
-            break;
-        }
-        const double al = rz / kappa;
-        pcg_update_xr(P, M, (float)al, p, q, x, r);
-        const double rn_new = std::sqrt(dot_now(P, r, r, M));
-        if (!std::isfinite(rn_new)) {
-            flags |= 2;
-            P->pcg_hist.push_back(rn / r0);
-            break;
-        }
-        rn = rn_new;
-        P->pcg_hist.push_back(rn / r0);
-        if (rn <= rtol * r0) break;
-        info.inner_iters += precondition(P, r, z, rtol);
-        const double rz_new = dot_now(P, r, z, M);
-        const double be = rz_new / rz;
-        rz = rz_new;
-        axpby(P, M, 1.f, z, (float)be, p, p);
-    }
-    info.pcg_iters = it;
-    info.rel_res = rn / r0;
-    info.flags = flags;
-    return flags;
 }
 
 // J into slot sj, its parts into smis and sreg; no host synchronisation
@@ -810,7 +790,7 @@ lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan
         P->dscal = (double *)(a + L.off[24]);
         assign_tile_boxes(P, a + L.off[25]);
         P->hist = (double *)(a + L.off[26]);
-        check_hip(hipHostMalloc((void **)&P->hscal, sizeof(double) * (kNumScalars + 2), hipHostMallocDefault),
+        check_hip(hipHostMalloc((void **)&P->hscal, sizeof(double) * (kNumScalars + 4), hipHostMallocDefault),
                   "hipHostMalloc");
         fft_init(P);
         *plan = P;
@@ -1379,7 +1359,8 @@ lddmm_status lddmm_apply_invh0(lddmm_plan *P, const float *r, double tol, int32_
         if (!(tol >= 0.0) || max_inner < 0) fail(LDDMM_EINVAL, "tol must be >= 0 and max_inner >= 0");
         need_full(P);
         need_velocity(P);
-        const int it = invh0_impl(P, r, s, tol, max_inner);
+        invh0_dev(P, r, s, tol, max_inner, nullptr);
+        const int it = inner_iterations(P);
         if (iters) *iters = it;
     });
 }
@@ -1395,7 +1376,8 @@ lddmm_status lddmm_apply_2linvh0(lddmm_plan *P, const float *r, double tol, int3
         if (!halves(P->cfg)) fail(LDDMM_EINVAL, "2LInvH0 needs every grid size divisible by 4 and at least 16");
         need_full(P);
         need_velocity(P);
-        const int it = twolevel_impl(P, r, s, tol, max_inner);
+        twolevel_dev(P, r, s, tol, max_inner, nullptr);
+        const int it = inner_iterations(coarse_plan(P));
         if (iters) *iters = it;
     });
 }

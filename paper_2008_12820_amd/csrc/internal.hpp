@@ -99,9 +99,11 @@ struct lddmm_plan {
     double *red = nullptr;   // reduction partials
     double *hist = nullptr;  // ||r_k|| / ||r0|| per PCG iteration (device, kHistMax)
     std::vector<double> pcg_hist;  // the last PCG's history (host)
-    double *dscal = nullptr; // device scalars
-    double *hscal = nullptr; // pinned host mirror (kNumScalars, then a 2-slot poll ring)
-    hipEvent_t ev_poll[2] = {nullptr, nullptr};  // the device-resident PCG's lagged stop test
+    double *dscal = nullptr; // device scalars, two banks of kNumScalars (see ScalarSlot)
+    int bank = 0;            // the bank the scalar kernels and reductions use
+    double *hscal = nullptr; // pinned host mirror (kNumScalars, then the 2-slot poll rings of the PCG and the inner PCG)
+    hipEvent_t ev_poll[2] = {nullptr, nullptr};   // the device-resident PCG's lagged stop test
+    hipEvent_t ev_inner[2] = {nullptr, nullptr};  // the same for the InvH0 inner PCG
 
     int have_images = 0, have_velocity = 0, have_grad = 0, have_matvec = 0;
     // transport map calls: departure points (forward or VJP), and the adjoint
@@ -236,8 +238,13 @@ enum ScalarSlot {
     S_GG = 0, S_DOT = 1, S_MIS = 2, S_REG = 3, S_E = 4,
     S_RR = 5, S_RZ = 6, S_KAPPA = 7, S_RZN = 8, S_R0 = 9, S_ALPHA = 10, S_BETA = 11,
     S_DONE = 12, S_ITERS = 13, S_FLAGS = 14, S_RTOL = 15, S_REL = 16, S_GNORM = 17,
-    S_G0 = 18, S_GV = 19, S_J0 = 20, S_J1 = 21, S_COPYZ = 22, S_MIS1 = 23, S_REG1 = 24
+    S_G0 = 18, S_GV = 19, S_J0 = 20, S_J1 = 21, S_COPYZ = 22, S_MIS1 = 23, S_REG1 = 24,
+    S_INNER = 25  // inner iterations of the InvH0 / 2LInvH0 preconditioner summed over a PCG
 };
+// Two banks of kNumScalars slots: bank 0 holds the outer PCG / Gauss-Newton
+// state, bank 1 the inner PCG of the H0 preconditioner.  The scalar kernels
+// and reductions work on the plan's current bank.
+inline double *scalars(lddmm_plan *P) { return P->dscal + P->bank * kNumScalars; }
 
 // device-resident PCG pieces (single-thread scalar kernels and predicated
 // vector updates; see linalg.hip)
@@ -253,6 +260,10 @@ void dev_pcg_p(lddmm_plan *P, long n, const float *z, float *p);
 void dev_sum(lddmm_plan *P, int dst, int a, int b);
 // dst[0] = dscal[slot] (device to device, a kernel: capturable)
 void dev_store_scalar(lddmm_plan *P, int slot, double *dst);
+// the inner PCG (current bank) counts as stopped when the outer one (bank-0
+// scalars outer) has stopped; and adds its iterations to outer[S_INNER]
+void dev_inner_link(lddmm_plan *P, double *outer);
+void dev_inner_accum(lddmm_plan *P, double *outer);
 void copy_kernel(lddmm_plan *P, long n, const float *x, float *out);
 
 }  // namespace lddmm

@@ -201,6 +201,7 @@ __global__ void k_pcg_init(double *d)
     d[S_ITERS] = 0.0;
     d[S_FLAGS] = 0.0;
     d[S_REL] = (r0 == 0.0) ? 0.0 : 1.0;  // ||r|| / ||r0|| before the first iteration
+    d[S_INNER] = 0.0;
     d[S_COPYZ] = 0.0;
     d[S_ALPHA] = 0.0;
     d[S_BETA] = 0.0;
@@ -284,6 +285,14 @@ __global__ void k_pcg_p(long n, int vec, const double *__restrict__ d, const flo
 }
 
 __global__ void k_sum2(double *d, int dst, int a, int b) { d[dst] = d[a] + d[b]; }
+__global__ void k_inner_link(double *inner, const double *outer)
+{
+    if (outer[S_DONE] != 0.0) inner[S_DONE] = 1.0;
+}
+__global__ void k_inner_accum(const double *inner, double *outer)
+{
+    if (outer[S_DONE] == 0.0) outer[S_INNER] += inner[S_ITERS];
+}
 __global__ void k_store_scalar(const double *d, int slot, double *dst) { dst[0] = d[slot]; }
 
 __global__ void k_copy(long n, int vec, const float *__restrict__ x, float *__restrict__ out)
@@ -317,7 +326,7 @@ void dot_async(lddmm_plan *P, const float *a, const float *b, long n, int slot, 
                        n, vec_ok({a, b}), P->red);
     check_hip(hipGetLastError(), "k_reduce_partial");
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, P->stream, P->red, kRedBlocks,
-                       P->dscal + slot, scale);
+                       scalars(P) + slot, scale);
     check_hip(hipGetLastError(), "k_reduce_final");
 }
 
@@ -328,13 +337,13 @@ void sqdiff_async(lddmm_plan *P, const float *a, const float *b, long n, int slo
                        n, vec_ok({a, b}), P->red);
     check_hip(hipGetLastError(), "k_reduce_partial");
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, P->stream, P->red, kRedBlocks,
-                       P->dscal + slot, scale);
+                       scalars(P) + slot, scale);
     check_hip(hipGetLastError(), "k_reduce_final");
 }
 
 double fetch_scalar(lddmm_plan *P, int slot)
 {
-    check_hip(hipMemcpyAsync(P->hscal + slot, P->dscal + slot, sizeof(double), hipMemcpyDeviceToHost,
+    check_hip(hipMemcpyAsync(P->hscal + slot, scalars(P) + slot, sizeof(double), hipMemcpyDeviceToHost,
                              P->stream),
               "scalar copy");
     check_hip(hipStreamSynchronize(P->stream), "stream sync");
@@ -372,20 +381,22 @@ void pcg_update_xr(lddmm_plan *P, long n, float al, const float *p, const float 
         check_hip(hipGetLastError(), #kern);                                                \
     } while (0)
 
-void dev_set_scalar(lddmm_plan *P, int slot, double value) { LAUNCH1(k_set_scalar, P->dscal, slot, value); }
-void dev_tolerance(lddmm_plan *P, double rtol) { LAUNCH1(k_tolerance, P->dscal, rtol); }
-void dev_pcg_init(lddmm_plan *P) { LAUNCH1(k_pcg_init, P->dscal); }
-void dev_pcg_alpha(lddmm_plan *P) { LAUNCH1(k_pcg_alpha, P->dscal); }
-void dev_pcg_conv(lddmm_plan *P) { LAUNCH1(k_pcg_conv, P->dscal); }
-void dev_pcg_beta(lddmm_plan *P) { LAUNCH1(k_pcg_beta, P->dscal); }
-void dev_sum(lddmm_plan *P, int dst, int a, int b) { LAUNCH1(k_sum2, P->dscal, dst, a, b); }
-void dev_store_scalar(lddmm_plan *P, int slot, double *dst) { LAUNCH1(k_store_scalar, P->dscal, slot, dst); }
+void dev_set_scalar(lddmm_plan *P, int slot, double value) { LAUNCH1(k_set_scalar, scalars(P), slot, value); }
+void dev_tolerance(lddmm_plan *P, double rtol) { LAUNCH1(k_tolerance, scalars(P), rtol); }
+void dev_pcg_init(lddmm_plan *P) { LAUNCH1(k_pcg_init, scalars(P)); }
+void dev_pcg_alpha(lddmm_plan *P) { LAUNCH1(k_pcg_alpha, scalars(P)); }
+void dev_pcg_conv(lddmm_plan *P) { LAUNCH1(k_pcg_conv, scalars(P)); }
+void dev_pcg_beta(lddmm_plan *P) { LAUNCH1(k_pcg_beta, scalars(P)); }
+void dev_sum(lddmm_plan *P, int dst, int a, int b) { LAUNCH1(k_sum2, scalars(P), dst, a, b); }
+void dev_store_scalar(lddmm_plan *P, int slot, double *dst) { LAUNCH1(k_store_scalar, scalars(P), slot, dst); }
+void dev_inner_link(lddmm_plan *P, double *outer) { LAUNCH1(k_inner_link, scalars(P), outer); }
+void dev_inner_accum(lddmm_plan *P, double *outer) { LAUNCH1(k_inner_accum, scalars(P), outer); }
 
 void dev_pcg_xr(lddmm_plan *P, long n, const float *p, const float *q, float *x, float *r)
 {
     Scope s(P, K_VECOP);
     const int vec = vec_ok({p, q, x, r});
-    hipLaunchKernelGGL(k_pcg_xr_dev, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, P->dscal, p, q, x,
+    hipLaunchKernelGGL(k_pcg_xr_dev, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, scalars(P), p, q, x,
                        r);
     check_hip(hipGetLastError(), "k_pcg_xr_dev");
 }
@@ -394,7 +405,7 @@ void dev_copy_if(lddmm_plan *P, long n, const float *z, float *x)
 {
     Scope s(P, K_VECOP);
     const int vec = vec_ok({z, x});
-    hipLaunchKernelGGL(k_copy_if, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, P->dscal, z, x);
+    hipLaunchKernelGGL(k_copy_if, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, scalars(P), z, x);
     check_hip(hipGetLastError(), "k_copy_if");
 }
 
@@ -402,7 +413,7 @@ void dev_pcg_p(lddmm_plan *P, long n, const float *z, float *p)
 {
     Scope s(P, K_VECOP);
     const int vec = vec_ok({z, p});
-    hipLaunchKernelGGL(k_pcg_p, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, P->dscal, z, p);
+    hipLaunchKernelGGL(k_pcg_p, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, scalars(P), z, p);
     check_hip(hipGetLastError(), "k_pcg_p");
 }
 

@@ -158,8 +158,51 @@ def test_state_errors():
 
 
 def test_negative_curvature_is_reported():
-    """A zero template makes H = beta A; a huge negative beta is rejected at
-    plan creation, so instead feed a non-finite velocity: PCG reports it."""
+    """With the Leray projection the matvec is beta A v~ + P b~, and for a
+    first search direction p = (beta A)^{-1}(-g) that is mostly curl free
+    (P removes that part from b~ but not from beta A p), <p, H p> can be
+    negative: here v is a gradient field, m1 the template transported by
+    1.001 v, beta = 1e-4.  The oracle's first curvature is negative (cosine
+    about -0.14, far beyond FP32 round-off); the GPU PCG must stop with flag 1
+    and return M^{-1} r0, as the oracle does."""
+    shape, nt, beta = (16, 16, 16), 2, 1e-4
+    say("non-positive curvature")
+    m0 = synth.f32(synth.blob_image(shape, 4, 7001))
+    phi = synth.bandlimited_vector(shape, 2, 7201, max_disp=1.0)[0]
+    v = oracle.spectral_grad(phi)
+    v = synth.f32(v / np.abs(v).max() * (2 * np.pi / 16))
+    ref = oracle.Problem(shape, nt, reg=1, beta=beta, leray=True)
+    ref.set_images(synth.f64(m0), synth.f64(m0))
+    ref.set_velocity(1.001 * synth.f64(v))
+    m1 = synth.f32(ref.transport(synth.f64(m0))[-1])
+    ref.set_images(synth.f64(m0), synth.f64(m1))
+    ref.set_velocity(synth.f64(v))
+    g_ref = ref.gradient()
+    p = oracle.reg_inverse(-g_ref, 1, beta)
+    hp = ref.matvec(p)
+    cos = oracle.inner(p, hp, ref.h3) / np.sqrt(oracle.inner(p, p, ref.h3) * oracle.inner(hp, hp, ref.h3))
+    x_ref, rinfo = ref.pcg(-g_ref, 5, 1e-12)
+    say(f"  oracle: first curvature cosine {cos:.3f}, flags {rinfo['flags']}, iterations {rinfo['iters']}")
+    assert cos < -0.1 and rinfo["flags"] == 1 and rinfo["iters"] == 1
+    P = _plan(shape, nt, 1, beta, True, m0, m1, v)
+    vt, info = P.newton_step(5, 1e-12, allow_notconv=True)
+    g, _ = P.gradient()
+    own = to_np(P.apply_inv_reg(-g))
+    e_own = rel(to_np(vt), own)
+    e = rel(to_np(vt), x_ref)
+    # the residual m1 - m(1) is 1e-3 of the image here, so the FP32 rounding
+    # of m(1) alone moves g (and M^{-1} r0) by about 6e-5 relative
+    mN = ref.transport(synth.f64(m0))[-1]
+    c_r = np.linalg.norm(mN) / np.linalg.norm(synth.f64(m1) - mN)
+    say(f"  GPU: status {info['status']}, flags {info['flags']}, iterations {info['pcg_iters']}, "
+        f"vs its own M^-1 r0 {e_own:.2e}, vs the oracle's {e:.2e} (||m(1)|| / ||m1 - m(1)|| = {c_r:.0f})")
+    assert info["status"] == ENOTCONV and info["flags"] == 1 and info["pcg_iters"] == 1
+    assert e_own < 1e-6
+    assert e < 1e-7 * c_r
+
+
+def test_non_finite_value_is_reported():
+    """A non-finite velocity: PCG reports flag 2."""
     shape = (16, 16, 16)
     m0 = np.zeros(shape, np.float32)
     P = Plan(shape, 2, beta=1e-2)
@@ -216,3 +259,23 @@ def test_pipelined_gathers_walk_many_tiles():
         assert np.array_equal(res[a][0], res[b][0]), (a, b)
         assert np.array_equal(res[a][1], res[b][1]), (a, b)
     assert np.isfinite(res[3][1]).all() and np.abs(res[3][1]).max() > 0
+
+
+def test_workspace_beyond_device_memory_is_enomem():
+    """A plan whose workspace cannot fit in HBM (1024^3, N_t = 256: about
+    10 TB) fails with ENOMEM and leaves the device usable."""
+    cfg = L.make_config((1024, 1024, 1024), 256, L.REG_H2S, 1e-3)
+    need = L.lddmm_workspace_bytes(cfg)
+    free, total = torch.cuda.mem_get_info(DEV)
+    say(f"ENOMEM: workspace {need / 1e12:.1f} TB, device {total / 1e9:.0f} GB")
+    assert need > total
+    with pytest.raises(LddmmError) as e:
+        L.lddmm_plan_create(cfg, torch.cuda.current_stream(DEV).cuda_stream)
+    assert e.value.status == L.ENOMEM
+    # the device still works: a small plan runs a matvec
+    shape = (16, 16, 16)
+    m0, m1, vtrue, v, ref = problem(shape, 2, 1, 1e-2)
+    P = _plan(shape, 2, 1, 1e-2, False, m0, m1, v)
+    vt = incremental(shape, 1600)
+    assert rel(to_np(P.hessian_matvec(to_dev(vt))), ref.matvec(synth.f64(vt))) < 1e-5
+    P.close()
