@@ -361,6 +361,40 @@ __device__ __forceinline__ void load_to_lds(const float *g, float *lds)
 }
 __device__ __forceinline__ void wait_lds_loads() { __builtin_amdgcn_s_waitcnt(0); }
 
+// Stage the periodic box [L1, L1 + B1) x [L2, L2 + B2) x [L3, L3 + B3) of src
+// into LDS rows of kPad3 floats, row (a, b) at box + (a BR2 + b) kPad3.  With
+// BR2 = 8 rows per x1 plane, wavefront w stages the x2 rows w and w + 4 of
+// every plane: their offsets are wrapped once and a plane's offset advances by
+// one wrapped step, so a row costs the scalar unit one 64-bit add.  Lane l
+// loads the columns k0 = wrap(L3 + l) and k1 = wrap(L3 + l + 64) (has0, has1:
+// inside the box).
+template <int BR1, int BR2>
+__device__ __forceinline__ void stage_box(const float *__restrict__ src, const Grid3 &g, int L1, int L2, int B1,
+                                          int B2, int w, unsigned k0, unsigned k1, bool has0, bool has1, float *box)
+{
+    static_assert(BR2 == 8, "four wavefronts stage two x2 rows of each plane");
+    const long n23 = (long)g.n2 * g.n3;
+    const long ob0 = (long)wrapg(L2 + w, g.n2) * g.n3, ob1 = (long)wrapg(L2 + w + 4, g.n2) * g.n3;
+    const bool hb0 = w < B2, hb1 = w + 4 < B2;
+    int ia = wrapg(L1, g.n1);
+#pragma unroll
+    for (int a = 0; a < BR1; ++a) {
+        if (a < B1) {
+            const float *plane = src + (long)ia * n23;
+            float *brow = box + (a * BR2 + w) * kPad3;
+            if (hb0) {
+                if (has0) load_to_lds(plane + ob0 + k0, brow);
+                if (has1) load_to_lds(plane + ob0 + k1, brow + 64);
+            }
+            if (hb1) {
+                if (has0) load_to_lds(plane + ob1 + k0, brow + 4 * kPad3);
+                if (has1) load_to_lds(plane + ob1 + k1, brow + 4 * kPad3 + 64);
+            }
+        }
+        ia = ia + 1 == g.n1 ? 0 : ia + 1;
+    }
+}
+
 // displacements clamped to +-2^20 voxels (NaN to the lower bound), so that
 // every index derived from them stays a finite int
 __device__ __forceinline__ float clamp_disp(float d)
@@ -694,7 +728,7 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
                                              const TileBox *__restrict__ boxes)
 {
     using BC = BoxCfg<T1, T2>;
-    constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, CAP = BC::CAP, NF = Epi::NF;
+    constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, NF = Epi::NF;
     constexpr int S1 = BR2 * kPad3;  // box stride along x1 (x2: kPad3)
     extern __shared__ float box[];   // CAP floats
     __shared__ int red[4][6];
@@ -723,60 +757,56 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
-        d1[q] = d2[q] = d3[q] = 0.f;
-        if (i < g.n1 && j < g.n2 && k < g.n3) {
-            const long p = ((long)i * g.n2 + j) * g.n3 + k;
-            d1[q] = clamp_disp(disp[p]);
-            d2[q] = clamp_disp(disp[N + p]);
-            d3[q] = clamp_disp(disp[2 * N + p]);
-        }
+        // points outside the grid (ragged tiles) read point 0 and use d = 0;
+        // their sums are formed (wrapped, valid) and never stored, so no
+        // lane of the contraction branches on them
+        const bool in = i < g.n1 && j < g.n2 && k < g.n3;
+        const long p = in ? ((long)i * g.n2 + j) * g.n3 + k : 0;
+        const float e1 = clamp_disp(disp[p]), e2 = clamp_disp(disp[N + p]), e3 = clamp_disp(disp[2 * N + p]);
+        d1[q] = in ? e1 : 0.f;
+        d2[q] = in ? e2 : 0.f;
+        d3[q] = in ? e3 : 0.f;
     }
     // staged extents: the stencil box, cut to the capacity (64-bit: a clamped
     // displacement spans up to 2^21 nodes)
     const int B1 = (int)min((long)H1 + 4 - L1, (long)BR1);
     const int B2 = (int)min((long)H2 + 4 - L2, (long)BR2);
     const int B3 = (int)min((long)H3 + 4 - L3, (long)kPad3);
-    // Staging: wavefront w loads the box rows r = w, w + 4, ... (row r is
-    // (a, b) = (r / BR2, r % BR2)); a row's source pointer is uniform over the
-    // wavefront, so its wrap and address arithmetic run on the scalar unit.
-    // The x3 wrap of a lane's two columns is the same for every row.  Fields
-    // go through the one box in turn.
-    constexpr int RPW = (BR1 * BR2 + 3) / 4;  // rows per wavefront
-    const int wu = w;
-    const int c1 = lane + 64;
-    const bool has0 = lane < B3, has1 = c1 < B3;
-    const unsigned k0 = (unsigned)wrapg(L3 + lane, g.n3), k1 = (unsigned)wrapg(L3 + c1, g.n3);
+    // Staging (stage_box): a row's source pointer is uniform over the
+    // wavefront, so its address arithmetic runs on the scalar unit; the x3
+    // wrap of a lane's two columns is the same for every row.  Fields go
+    // through the one box in turn.
+    const bool has0 = lane < B3, has1 = lane + 64 < B3;
+    const unsigned k0 = (unsigned)wrapg(L3 + lane, g.n3), k1 = (unsigned)wrapg(L3 + lane + 64, g.n3);
     float val[PPT][NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const float *__restrict__ src = epi.field(f);
         if (f > 0) __syncthreads();  // the previous field's stencils are read
-#pragma unroll
-        for (int q = 0; q < RPW; ++q) {
-            const int r = wu + 4 * q, a = r / BR2, b = r - a * BR2;
-            if (a < B1 && b < B2) {
-                const float *grow = src + ((long)wrapg(L1 + a, g.n1) * g.n2 + wrapg(L2 + b, g.n2)) * g.n3;
-                float *brow = box + r * kPad3;
-                if (has0) load_to_lds(grow + k0, brow);
-                if (has1) load_to_lds(grow + k1, brow + 64);
-            }
-        }
+        stage_box<BR1, BR2>(src, g, L1, L2, B1, B2, w, k0, k1, has0, has1, box);
         wait_lds_loads();
         __syncthreads();
+        if constexpr (NF > 1) {
+            // weights and indices are formed again per field: kept across the
+            // fields they would hold 4 x 12 registers (fewer waves per SIMD)
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) asm("" : "+v"(d1[q]), "+v"(d2[q]), "+v"(d3[q]));
+        }
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
-            val[q][f] = 0.f;
-            if (!(i < g.n1 && j < g.n2 && k < g.n3)) continue;
             const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
             float w1[4], w2[4], w3[4];
             lagrange4<float>(d1[q] - f1, w1);
             lagrange4<float>(d2[q] - f2, w2);
             lagrange4<float>(d3[q] - f3, w3);
             const int b1 = i + (int)f1 - 1, b2 = j + (int)f2 - 1, b3 = k + (int)f3 - 1;
-            const int o1 = b1 - L1, o2 = b2 - L2, o3 = b3 - L3;  // >= 0 by the reduction
+            // >= 0 by the reduction for points inside the grid; the unsigned
+            // compare sends any other stencil to the global path
+            const int o1 = b1 - L1, o2 = b2 - L2, o3 = b3 - L3;
             float acc = 0.f;
-            if (o1 <= B1 - 4 && o2 <= B2 - 4 && o3 <= B3 - 4) {
+            if ((unsigned)o1 <= (unsigned)(B1 - 4) && (unsigned)o2 <= (unsigned)(B2 - 4) &&
+                (unsigned)o3 <= (unsigned)(B3 - 4)) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     // one base address per x1 plane: the row reads of the
@@ -846,7 +876,6 @@ __global__ __launch_bounds__(256) void k_departure_box(const float *__restrict__
     using BC = BoxCfg<T1, T2>;
     constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2;
     constexpr int S1 = BR2 * kPad3;
-    constexpr int RPW = (BR1 * BR2 + 3) / 4;
     extern __shared__ float box[];
     __shared__ int red[4][6];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -908,16 +937,7 @@ __global__ __launch_bounds__(256) void k_departure_box(const float *__restrict__
             const float *__restrict__ src = v + (long)c * N;
             const double ihc = c == 0 ? ih1 : c == 1 ? ih2 : ih3;
             if (c > 0) __syncthreads();  // the previous component's stencils are read
-#pragma unroll
-            for (int q = 0; q < RPW; ++q) {
-                const int r = w + 4 * q, a = r / BR2, b = r - a * BR2;
-                if (a < B1 && b < B2) {
-                    const float *grow = src + ((long)wrapg(L[0] + a, g.n1) * g.n2 + wrapg(L[1] + b, g.n2)) * g.n3;
-                    float *brow = box + r * kPad3;
-                    if (has0) load_to_lds(grow + k0, brow);
-                    if (has1) load_to_lds(grow + k1, brow + 64);
-                }
-            }
+            stage_box<BR1, BR2>(src, g, L[0], L[1], B1, B2, w, k0, k1, has0, has1, box);
             wait_lds_loads();
             __syncthreads();
 #pragma unroll 1
@@ -988,7 +1008,6 @@ __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restri
     using BC = BoxCfg<T1, T2>;
     constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, CAP = BC::CAP;
     constexpr int S1 = BR2 * kPad3;
-    constexpr int RPW = (BR1 * BR2 + 3) / 4;
     extern __shared__ float boxes2[];  // 2 x CAP floats
     const int tid = threadIdx.x, lane = tid & 63;
     // the wavefront index, wave-uniform: the compiler keeps what derives from
@@ -1010,16 +1029,7 @@ __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restri
         const int B2 = (int)min((long)tbx.H[1] + 4 - L2, (long)BR2);
         const int B3 = (int)min((long)tbx.H[2] + 4 - L3, (long)kPad3);
         const unsigned k0 = (unsigned)wrapg(L3 + lane, g.n3), k1 = (unsigned)wrapg(L3 + lane + 64, g.n3);
-#pragma unroll
-        for (int q = 0; q < RPW; ++q) {
-            const int r = w + 4 * q, a = r / BR2, b = r - a * BR2;
-            if (a < B1 && b < B2) {
-                const float *grow = src + ((long)wrapg(L1 + a, g.n1) * g.n2 + wrapg(L2 + b, g.n2)) * g.n3;
-                float *brow = bx + r * kPad3;
-                if (lane < B3) load_to_lds(grow + k0, brow);
-                if (lane + 64 < B3) load_to_lds(grow + k1, brow + 64);
-            }
-        }
+        stage_box<BR1, BR2>(src, g, L1, L2, B1, B2, w, k0, k1, lane < B3, lane + 64 < B3, bx);
     };
     // the displacements of tile t's points (points outside the grid read point 0)
     auto load_disp = [&](int t, float *e1, float *e2, float *e3) {
