@@ -259,15 +259,24 @@ lddmm_status lddmm_get_field(lddmm_plan *plan, int32_t what, int32_t j, float *o
 
 /* ---- batched form --------------------------------------------------------- */
 
-/* B independent registrations advanced together; member b has its own
- * config (grid sizes may differ) and a full plan on one of nstreams
- * library-created HIP streams (default priority).  Per Gauss-Newton
- * iteration, each member's gradient, eps_K, fixed-count PCG (device-resident
- * scalars, no host round trip), <g, v~> and first Armijo trial are one
- * sequence, replayed from a captured hipGraph when use_graph != 0; members on
- * different streams overlap.  The batch calls synchronise the device on
- * entry and their streams on return.  Arrays of device pointers are HOST
- * arrays of B entries. */
+/* B independent registrations advanced together (the data-parallel
+ * multi-image processing the paper cites as related work).  Members with the
+ * same configuration (grid size, N_t, regularisation, beta, flags) form a
+ * group whose workspaces live in one batched plan: every kernel of an
+ * iteration is launched once for all members of the group, the member index
+ * a grid dimension, so a transport step, a transform pass, a reduction or a
+ * PCG scalar update is one launch per group.  Per Gauss-Newton iteration a
+ * group's gradient, eps_K, fixed-count PCG (device-resident scalars, stops
+ * predicated per member), <g, v~> and first Armijo trial are one sequence,
+ * replayed from a captured hipGraph when use_graph != 0; groups run on up to
+ * nstreams library-created streams (default priority).  The batch calls
+ * synchronise the device on entry and their streams on return.  Arrays of
+ * device pointers are HOST arrays of B entries.
+ * lddmm_batch_plan gives member b's plan for per-member calls
+ * (lddmm_objective, lddmm_get_field, lddmm_set_beta, ...), which run on that
+ * member alone; it belongs to the batch (lddmm_plan_destroy on it: EINVAL).
+ * Members of one group must keep equal beta (lddmm_batch_gn_iterate returns
+ * EUNSUPPORTED otherwise) and the InvA preconditioner. */
 typedef struct lddmm_batch lddmm_batch;
 
 lddmm_status lddmm_batch_create(int32_t B, const lddmm_config *cfgs, int32_t nstreams,

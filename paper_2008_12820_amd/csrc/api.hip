@@ -8,6 +8,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -711,38 +712,13 @@ static double tolerance(lddmm_plan *P, double rtol, double gnorm)
     return std::min(std::sqrt(grel), 0.5);
 }
 
-}  // namespace lddmm
-
-using namespace lddmm;
-
-// ---------------------------------------------------------------------------
-// C ABI
-// ---------------------------------------------------------------------------
-extern "C" {
-
-lddmm_status lddmm_workspace_bytes(const lddmm_config *cfg, size_t *bytes)
+// A plan for members copies of one configuration (1: a plain plan): one
+// arena of members workspaces, stride bytes apart (see Mb); twiddles and tile
+// choices are shared.  Throws on failure (nothing leaks).
+lddmm_plan *create_plan(const lddmm_config *cfg, void *stream, int members)
 {
-    return guard([&] {
-        validate(cfg);
-        need(bytes, "bytes");
-        const int n[3] = {cfg->n[0], cfg->n[1], cfg->n[2]};
-        size_t tw = 0;
-        for (size_t cs : {sizeof(float2), sizeof(double2)}) {
-            tw += ((cs * n[0] + 255) & ~size_t(255)) + ((cs * n[1] + 255) & ~size_t(255));
-            tw += ((cs * (n[2] / 2) + 255) & ~size_t(255)) + ((cs * n[2] + 255) & ~size_t(255));
-        }
-        *bytes = make_layout(cfg).total + tw;
-    });
-}
-
-lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan **plan)
-{
-    lddmm_plan *P = nullptr;
-    if (plan) *plan = nullptr;
-    lddmm_status st = guard([&] {
-        validate(cfg);
-        need(plan, "plan");
-        P = new lddmm_plan();
+    lddmm_plan *P = new lddmm_plan();
+    try {
         P->cfg = *cfg;
         P->stream = (hipStream_t)stream;
         check_hip(hipGetDevice(&P->device), "hipGetDevice");
@@ -752,13 +728,16 @@ lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan
         P->h3 = P->h[0] * P->h[1] * P->h[2];
         P->dt = 1.0 / cfg->nt;
         Layout L = make_layout(cfg);
-        hipError_t e = hipMalloc(&P->arena, L.total);
+        const size_t total = L.total * (size_t)members;
+        hipError_t e = hipMalloc(&P->arena, total);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             P->arena = nullptr;
-            fail(LDDMM_ENOMEM, "workspace of " + std::to_string(L.total) + " bytes: " + hipGetErrorString(e));
+            fail(LDDMM_ENOMEM, "workspace of " + std::to_string(total) + " bytes: " + hipGetErrorString(e));
         }
-        P->arena_bytes = L.total;
+        P->arena_bytes = total;
+        P->mb.stride = members > 1 ? (long long)L.total : 0;
+        P->mb.count = members;
         char *a = (char *)P->arena;
         auto F = [&](int i) { return L.len[i] ? (float *)(a + L.off[i]) : nullptr; };
         P->m0 = F(0);
@@ -790,22 +769,112 @@ lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan
         P->dscal = (double *)(a + L.off[24]);
         assign_tile_boxes(P, a + L.off[25]);
         P->hist = (double *)(a + L.off[26]);
-        check_hip(hipHostMalloc((void **)&P->hscal, sizeof(double) * (kNumScalars + 4), hipHostMallocDefault),
+        check_hip(hipHostMalloc((void **)&P->hscal, sizeof(double) * kHostScalars * members, hipHostMallocDefault),
                   "hipHostMalloc");
         fft_init(P);
-        *plan = P;
-    });
-    if (st != LDDMM_OK && P) {
+    } catch (...) {
         plan_free(P);
-        if (plan) *plan = nullptr;
+        throw;
     }
-    return st;
+    return P;
+}
+
+// Member b of a batched plan as a plan of its own (host record only): every
+// workspace pointer shifted to the member's copy, one member, the group's
+// tables, streams and events shared.  Calls on it launch for that member
+// alone.  It owns nothing the group owns (view_free releases only what was
+// created on it afterwards).
+lddmm_plan *member_view(const lddmm_plan *G, int b)
+{
+    lddmm_plan *V = new lddmm_plan(*G);
+    const long long off = G->mb.offset((unsigned)b);
+    auto sh = [&](auto *&p) {
+        if (p) p = (std::remove_reference_t<decltype(p)>)((char *)p + off);
+    };
+    for (float **f : {&V->m0, &V->m1, &V->v, &V->dX, &V->dXa, &V->m, &V->G, &V->GX, &V->delta, &V->coef, &V->lam,
+                      &V->mt, &V->src, &V->b, &V->tmp3, &V->g, &V->px, &V->pr, &V->pz, &V->pp, &V->pq, &V->vt})
+        sh(*f);
+    sh(V->spec);
+    sh(V->red);
+    sh(V->dscal);
+    sh(V->hist);
+    for (auto &row : V->boxes)
+        for (void *&bx : row)
+            if (bx) bx = (char *)bx + off;
+    V->hscal = G->hscal + (size_t)b * kHostScalars;
+    V->mb = Mb{};
+    V->view_of = G;
+    V->arena = nullptr;
+    V->arena_bytes = 0;
+    V->h0buf = nullptr;
+    V->coarse = nullptr;
+    V->timing = PlanTiming{};
+    return V;
+}
+
+// release what a view created for itself (never the group's shared pieces)
+void view_free(lddmm_plan *V)
+{
+    if (!V) return;
+    const lddmm_plan *G = V->view_of;
+    if (V->side && V->side != G->side) {
+        (void)hipStreamSynchronize(V->side);
+        (void)hipStreamDestroy(V->side);
+    }
+    if (V->ev_fork && V->ev_fork != G->ev_fork) (void)hipEventDestroy(V->ev_fork);
+    if (V->ev_join && V->ev_join != G->ev_join) (void)hipEventDestroy(V->ev_join);
+    for (int i = 0; i < 2; ++i) {
+        if (V->ev_poll[i] && V->ev_poll[i] != G->ev_poll[i]) (void)hipEventDestroy(V->ev_poll[i]);
+        if (V->ev_inner[i] && V->ev_inner[i] != G->ev_inner[i]) (void)hipEventDestroy(V->ev_inner[i]);
+    }
+    if (V->h0buf) (void)hipFree(V->h0buf);
+    if (V->coarse) (void)lddmm_plan_destroy(V->coarse);
+    for (auto &pr : V->timing.pool) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    delete V;
+}
+
+}  // namespace lddmm
+
+using namespace lddmm;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+lddmm_status lddmm_workspace_bytes(const lddmm_config *cfg, size_t *bytes)
+{
+    return guard([&] {
+        validate(cfg);
+        need(bytes, "bytes");
+        const int n[3] = {cfg->n[0], cfg->n[1], cfg->n[2]};
+        size_t tw = 0;
+        for (size_t cs : {sizeof(float2), sizeof(double2)}) {
+            tw += ((cs * n[0] + 255) & ~size_t(255)) + ((cs * n[1] + 255) & ~size_t(255));
+            tw += ((cs * (n[2] / 2) + 255) & ~size_t(255)) + ((cs * n[2] + 255) & ~size_t(255));
+        }
+        *bytes = make_layout(cfg).total + tw;
+    });
+}
+
+lddmm_status lddmm_plan_create(const lddmm_config *cfg, void *stream, lddmm_plan **plan)
+{
+    if (plan) *plan = nullptr;
+    return guard([&] {
+        validate(cfg);
+        need(plan, "plan");
+        *plan = create_plan(cfg, stream, 1);
+    });
 }
 
 lddmm_status lddmm_plan_destroy(lddmm_plan *plan)
 {
     return guard([&] {
         need(plan, "plan");
+        if (plan->view_of) fail(LDDMM_EINVAL, "a batch member's plan belongs to the batch (lddmm_batch_destroy)");
         (void)hipStreamSynchronize(plan->stream);
         plan_free(plan);
     });

@@ -1,13 +1,19 @@
 // Batched form: many independent registrations (uneven grid sizes) advanced
-// together.  Each member is a full plan on one of a few library-owned HIP
-// streams; one Gauss-Newton iteration of a member -- gradient, eps_K,
-// fixed-count PCG with device-resident scalars, <g, v~>, and the first
-// Armijo trial J(v + v~) -- is a single host-sync-free sequence, captured
-// once into a hipGraph and replayed, so the members' small kernels overlap
-// across streams and their launch cost is paid once per graph.  Only the
-// line-search decision needs the host; rejected trials (rare) run eagerly.
+// together.  Members of one configuration (grid size, N_t, regularisation,
+// beta, flags) form a group whose workspaces sit in one batched plan: every
+// kernel of a Gauss-Newton iteration is launched once for all members of the
+// group, the member index a grid dimension (see Mb), so a phase of the
+// iteration -- a transport step, a transform pass, a reduction, a PCG scalar
+// update -- is one launch per group instead of one per member.  The
+// iteration up to the first Armijo trial (gradient, eps_K, fixed-count PCG
+// with device-resident scalars predicated per member, <g, v~>, the trial
+// state and J) is captured once per group into a hipGraph and replayed; the
+// groups run on their own streams.  Only the line-search decisions need the
+// host; rejected trials (rare) run eagerly on the member alone, through the
+// member's view of its group.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -15,7 +21,9 @@
 
 namespace lddmm {
 
-struct MemberGraph {
+struct Group {
+    lddmm_plan *P = nullptr;  // the batched plan of the group's members
+    std::vector<int> members;  // batch indices, in member order
     hipGraphExec_t exec = nullptr;
     int max_pcg = -1;
     double rtol = 0.0;
@@ -26,9 +34,10 @@ struct MemberGraph {
 
 struct lddmm_batch {
     int B = 0;
-    std::vector<lddmm_plan *> plans;
+    std::vector<lddmm::Group> groups;
     std::vector<hipStream_t> streams;
-    std::vector<lddmm::MemberGraph> graphs;
+    std::vector<lddmm_plan *> views;  // member b's plan: a view of its group's plan
+    std::vector<int> group_of, index_of;
 };
 
 namespace lddmm {
@@ -51,10 +60,11 @@ static lddmm_status bguard(F &&f)
 static void batch_free(lddmm_batch *Bt)
 {
     if (!Bt) return;
-    for (auto &g : Bt->graphs)
+    for (lddmm_plan *V : Bt->views) view_free(V);
+    for (Group &g : Bt->groups) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    for (lddmm_plan *p : Bt->plans)
-        if (p) (void)lddmm_plan_destroy(p);
+        if (g.P) (void)lddmm_plan_destroy(g.P);
+    }
     for (hipStream_t s : Bt->streams) (void)hipStreamDestroy(s);
     delete Bt;
 }
@@ -64,23 +74,76 @@ static void sync_all(lddmm_batch *Bt)
     for (hipStream_t s : Bt->streams) check_hip(hipStreamSynchronize(s), "stream sync");
 }
 
-static void copy_scalars_async(lddmm_plan *P)
+static bool same_config(const lddmm_config &a, const lddmm_config &b)
 {
-    check_hip(hipMemcpyAsync(P->hscal, P->dscal, sizeof(double) * kNumScalars, hipMemcpyDeviceToHost,
-                             P->stream),
-              "scalar copy");
+    return a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2] && a.nt == b.nt && a.reg == b.reg &&
+           a.leray == b.leray && a.flags == b.flags && a.beta == b.beta;
 }
 
-static void capture_member(lddmm_batch *Bt, int b, int max_pcg, double rtol)
+// the group's state as its members' views see it
+static void to_views(lddmm_batch *Bt, const Group &g)
 {
-    lddmm_plan *P = Bt->plans[b];
-    MemberGraph &G = Bt->graphs[b];
+    const lddmm_plan *P = g.P;
+    for (int b : g.members) {
+        lddmm_plan *V = Bt->views[b];
+        V->have_images = P->have_images;
+        V->have_velocity = P->have_velocity;
+        V->have_grad = P->have_grad;
+        V->have_matvec = P->have_matvec;
+        V->have_disp = P->have_disp;
+        V->have_vjp = P->have_vjp;
+        V->boxes_valid = P->boxes_valid;
+        V->vel_gen = P->vel_gen;
+        V->gather_mode = P->gather_mode;
+        V->gather_mode3 = P->gather_mode3;
+        V->departure_mode = P->departure_mode;
+        V->gather_tuned = P->gather_tuned;
+        V->fft = P->fft;
+    }
+}
+
+// members' settings the group's launches take as one argument: beta (equal
+// over the group), the preconditioner (InvA)
+static void from_views(lddmm_batch *Bt, Group &g)
+{
+    lddmm_plan *P = g.P;
+    const double beta = Bt->views[g.members[0]]->cfg.beta;
+    for (int b : g.members) {
+        const lddmm_plan *V = Bt->views[b];
+        if (V->cfg.beta != beta)
+            fail(LDDMM_EUNSUPPORTED, "members " + std::to_string(g.members[0]) + " and " + std::to_string(b) +
+                                         " share a grid size but not beta");
+        if (V->pc_kind != 0)
+            fail(LDDMM_EUNSUPPORTED, "member " + std::to_string(b) + ": the batched iteration runs InvA only");
+    }
+    if (P->cfg.beta != beta) {
+        P->cfg.beta = beta;
+        ++P->enqueue_gen;  // beta is an argument of the captured kernels
+    }
+}
+
+// every member's scalars into its block of the pinned host mirror
+static void copy_scalars_async(lddmm_plan *P)
+{
+    if (P->mb.count == 1)
+        check_hip(hipMemcpyAsync(P->hscal, P->dscal, sizeof(double) * kNumScalars, hipMemcpyDeviceToHost, P->stream),
+                  "scalar copy");
+    else
+        check_hip(hipMemcpy2DAsync(P->hscal, sizeof(double) * kHostScalars, P->dscal, (size_t)P->mb.stride,
+                                   sizeof(double) * kNumScalars, (size_t)P->mb.count, hipMemcpyDeviceToHost,
+                                   P->stream),
+                  "scalar copy");
+}
+
+static void capture_group(Group &g, int max_pcg, double rtol)
+{
+    lddmm_plan *P = g.P;
     // kernel arguments such as beta are baked into the graph: recapture when
     // the plan's enqueue generation moved since the capture
-    if (G.exec && G.max_pcg == max_pcg && G.rtol == rtol && G.gen == P->enqueue_gen) return;
-    if (G.exec) {
-        check_hip(hipGraphExecDestroy(G.exec), "hipGraphExecDestroy");
-        G.exec = nullptr;
+    if (g.exec && g.max_pcg == max_pcg && g.rtol == rtol && g.gen == P->enqueue_gen) return;
+    if (g.exec) {
+        check_hip(hipGraphExecDestroy(g.exec), "hipGraphExecDestroy");
+        g.exec = nullptr;
     }
     const bool timing = P->timing.on;
     P->timing.on = false;  // no event nodes in the graph
@@ -97,12 +160,12 @@ static void capture_member(lddmm_batch *Bt, int b, int max_pcg, double rtol)
     }
     check_hip(hipStreamEndCapture(P->stream, &graph), "hipStreamEndCapture");
     P->timing.on = timing;
-    hipError_t e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     check_hip(e, "hipGraphInstantiate");
-    G.max_pcg = max_pcg;
-    G.rtol = rtol;
-    G.gen = P->enqueue_gen;
+    g.max_pcg = max_pcg;
+    g.rtol = rtol;
+    g.gen = P->enqueue_gen;
 }
 
 }  // namespace lddmm
@@ -119,27 +182,41 @@ lddmm_status lddmm_batch_create(int32_t B, const lddmm_config *cfgs, int32_t nst
         if (!out || !cfgs) fail(LDDMM_EINVAL, "NULL argument");
         if (B < 1 || B > 4096) fail(LDDMM_EINVAL, "B must be in [1, 4096]");
         if (nstreams < 1 || nstreams > 32) fail(LDDMM_EINVAL, "nstreams must be in [1, 32]");
+        for (int b = 0; b < B; ++b) {
+            size_t bytes = 0;
+            const lddmm_status s = lddmm_workspace_bytes(&cfgs[b], &bytes);
+            if (s != LDDMM_OK) fail(s, "member " + std::to_string(b) + ": " + lddmm_last_error());
+            if (cfgs[b].flags & LDDMM_FLAG_TRANSPORT_ONLY) fail(LDDMM_EINVAL, "batch members need full plans");
+        }
         Bt = new lddmm_batch();
         Bt->B = B;
-        const int S = std::min(nstreams, B);
+        Bt->group_of.assign(B, -1);
+        Bt->index_of.assign(B, -1);
+        for (int b = 0; b < B; ++b) {
+            int g = 0;
+            while (g < (int)Bt->groups.size() && !same_config(Bt->groups[g].P ? Bt->groups[g].P->cfg : cfgs[Bt->groups[g].members[0]], cfgs[b]))
+                ++g;
+            if (g == (int)Bt->groups.size()) Bt->groups.emplace_back();
+            Bt->group_of[b] = g;
+            Bt->index_of[b] = (int)Bt->groups[g].members.size();
+            Bt->groups[g].members.push_back(b);
+        }
+        const int S = std::min<int>(nstreams, (int)Bt->groups.size());
         for (int s = 0; s < S; ++s) {
             hipStream_t h;
             check_hip(hipStreamCreateWithFlags(&h, hipStreamNonBlocking), "hipStreamCreate");
             Bt->streams.push_back(h);
         }
-        Bt->plans.assign(B, nullptr);
-        Bt->graphs.assign(B, MemberGraph{});
-        for (int b = 0; b < B; ++b) {
-            if (cfgs[b].flags & LDDMM_FLAG_TRANSPORT_ONLY)
-                fail(LDDMM_EINVAL, "batch members need full plans");
-            lddmm_status s = lddmm_plan_create(&cfgs[b], (void *)Bt->streams[b % S], &Bt->plans[b]);
-            if (s != LDDMM_OK)
-                fail(s, "member " + std::to_string(b) + ": " + lddmm_last_error());
-            // FFT tiles per grid size (the cache makes repeated sizes free)
-            s = lddmm_autotune(Bt->plans[b]);
-            if (s != LDDMM_OK)
-                fail(s, "member " + std::to_string(b) + " autotune: " + lddmm_last_error());
+        for (int g = 0; g < (int)Bt->groups.size(); ++g) {
+            Group &G = Bt->groups[g];
+            G.P = create_plan(&cfgs[G.members[0]], (void *)Bt->streams[g % S], (int)G.members.size());
+            // FFT tiles per grid size (timed on the batched launches)
+            const lddmm_status s = lddmm_autotune(G.P);
+            if (s != LDDMM_OK) fail(s, "group autotune: " + std::string(lddmm_last_error()));
         }
+        Bt->views.assign(B, nullptr);
+        for (int b = 0; b < B; ++b)
+            Bt->views[b] = member_view(Bt->groups[Bt->group_of[b]].P, Bt->index_of[b]);
         *out = Bt;
     });
     if (st != LDDMM_OK) batch_free(Bt);
@@ -160,7 +237,7 @@ lddmm_status lddmm_batch_plan(lddmm_batch *Bt, int32_t b, lddmm_plan **plan)
     return bguard([&] {
         if (!Bt || !plan) fail(LDDMM_EINVAL, "NULL argument");
         if (b < 0 || b >= Bt->B) fail(LDDMM_EINVAL, "member index out of range");
-        *plan = Bt->plans[b];
+        *plan = Bt->views[b];
     });
 }
 
@@ -170,8 +247,13 @@ lddmm_status lddmm_batch_set_images(lddmm_batch *Bt, const float *const *m0, con
         if (!Bt || !m0 || !m1) fail(LDDMM_EINVAL, "NULL argument");
         check_hip(hipDeviceSynchronize(), "device sync");
         for (int b = 0; b < Bt->B; ++b) {
-            lddmm_status s = lddmm_set_images(Bt->plans[b], m0[b], m1[b]);
+            const lddmm_status s = lddmm_set_images(Bt->views[b], m0[b], m1[b]);
             if (s != LDDMM_OK) fail(s, "member " + std::to_string(b) + ": " + lddmm_last_error());
+        }
+        for (Group &g : Bt->groups) {
+            g.P->have_images = 1;
+            g.P->have_velocity = 0;
+            to_views(Bt, g);
         }
         sync_all(Bt);
     });
@@ -181,10 +263,20 @@ lddmm_status lddmm_batch_set_velocity(lddmm_batch *Bt, const float *const *v)
 {
     return bguard([&] {
         if (!Bt || !v) fail(LDDMM_EINVAL, "NULL argument");
+        for (int b = 0; b < Bt->B; ++b)
+            if (!v[b] || (uintptr_t)v[b] % 16) fail(LDDMM_EINVAL, "v entry NULL or misaligned");
+        for (const Group &g : Bt->groups)
+            if (!g.P->have_images) fail(LDDMM_ESTATE, "set_images has not been called");
         check_hip(hipDeviceSynchronize(), "device sync");
+        // each member's velocity into its workspace, then the per-velocity
+        // state of all members of a group in batched launches
         for (int b = 0; b < Bt->B; ++b) {
-            lddmm_status s = lddmm_set_velocity(Bt->plans[b], v[b]);
-            if (s != LDDMM_OK) fail(s, "member " + std::to_string(b) + ": " + lddmm_last_error());
+            lddmm_plan *V = Bt->views[b];
+            copy_kernel(V, 3 * V->N, v[b], V->v);
+        }
+        for (Group &g : Bt->groups) {
+            velocity_state(g.P);
+            to_views(Bt, g);
         }
         sync_all(Bt);
     });
@@ -197,29 +289,28 @@ lddmm_status lddmm_batch_gn_iterate(lddmm_batch *Bt, int32_t max_pcg, double rto
         if (!Bt || !v_inout) fail(LDDMM_EINVAL, "NULL argument");
         if (max_pcg < 0) fail(LDDMM_EINVAL, "max_pcg must be >= 0");
         for (int b = 0; b < Bt->B; ++b) {
-            lddmm_plan *P = Bt->plans[b];
-            if (!P->have_images || !P->have_velocity)
+            const lddmm_plan *V = Bt->views[b];
+            if (!V->have_images || !V->have_velocity)
                 fail(LDDMM_ESTATE, "member " + std::to_string(b) + " has no velocity state");
             if (!v_inout[b] || (uintptr_t)v_inout[b] % 16) fail(LDDMM_EINVAL, "v_inout entry NULL or misaligned");
-            if (P->pc_kind != 0)
-                fail(LDDMM_EUNSUPPORTED, "member " + std::to_string(b) + ": the batched iteration runs InvA only");
         }
+        for (Group &g : Bt->groups) from_views(Bt, g);
         check_hip(hipDeviceSynchronize(), "device sync");
-        // phase 1: every member's iteration up to the first Armijo trial
-        for (int b = 0; b < Bt->B; ++b) {
-            lddmm_plan *P = Bt->plans[b];
+        // phase 1: every group's iteration up to the first Armijo trial
+        for (Group &g : Bt->groups) {
             if (use_graph) {
-                capture_member(Bt, b, max_pcg, rtol);
-                check_hip(hipGraphLaunch(Bt->graphs[b].exec, P->stream), "hipGraphLaunch");
+                capture_group(g, max_pcg, rtol);
+                check_hip(hipGraphLaunch(g.exec, g.P->stream), "hipGraphLaunch");
             } else {
-                gn_trial_enqueue(P, max_pcg, rtol, P->px);
-                copy_scalars_async(P);
+                gn_trial_enqueue(g.P, max_pcg, rtol, g.P->px);
+                copy_scalars_async(g.P);
             }
         }
         sync_all(Bt);
+        for (Group &g : Bt->groups) to_views(Bt, g);
         // phase 2: line-search decisions (Armijo, c1 = 1e-4, halving, 10 trials)
         for (int b = 0; b < Bt->B; ++b) {
-            lddmm_plan *P = Bt->plans[b];
+            lddmm_plan *P = Bt->views[b];
             const double *h = P->hscal;
             const long M = 3 * P->N;
             const double J0 = h[S_J0], gv = h[S_GV];

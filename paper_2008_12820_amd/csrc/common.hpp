@@ -30,6 +30,26 @@ __host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2
 __host__ __device__ inline float2 cmuli(float2 a) { return make_float2(-a.y, a.x); }  // i * a
 
 // ---------------------------------------------------------------------------
+// Members of a batched plan: count copies of one plan's workspace, stride
+// bytes apart (a batch of registrations of one grid size).  A kernel launched
+// for all of them takes its member index from a grid dimension and shifts
+// every workspace pointer it was given by index * stride; tables the members
+// share (FFT twiddles) are not shifted.  A plain plan: stride 0, count 1.
+// ---------------------------------------------------------------------------
+struct Mb {
+    long long stride = 0;
+    int count = 1;
+    __host__ __device__ long long offset(unsigned idx) const { return (long long)idx * stride; }
+};
+
+// p + off bytes; NULL stays NULL
+template <class T>
+__device__ __forceinline__ T *mshift(T *p, long long off)
+{
+    return p ? reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)off) : p;
+}
+
+// ---------------------------------------------------------------------------
 // FFT line plans
 // ---------------------------------------------------------------------------
 constexpr int kMaxPasses = 12;

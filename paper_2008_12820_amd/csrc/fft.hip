@@ -617,8 +617,10 @@ __device__ __forceinline__ void rw_run(C *v, C *X, const C *__restrict__ tw)
 template <class R, int M, int RB>
 __global__ __launch_bounds__(RB * M / 8) void k_r2c_reg(RealIn in, char *__restrict__ spec, long slot_bytes, int slot0,
                                                  long nrow, const typename CplxOf<R>::type *__restrict__ tw_m,
-                                                 const typename CplxOf<R>::type *__restrict__ tw_n)
+                                                 const typename CplxOf<R>::type *__restrict__ tw_n, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); for (int c_ = 0; c_ < 8; ++c_) in.p[c_] = mshift(in.p[c_], mo_); spec = mshift(spec, mo_);
     using C = typename CplxOf<R>::type;
     using S = RowShape<M, RB>;
     constexpr int R0 = S::P::radix(0), RL = S::P::radix(S::NP - 1);
@@ -670,8 +672,10 @@ __global__ __launch_bounds__(RB * M / 8) void k_r2c_reg(RealIn in, char *__restr
 template <int M, int RB>
 __global__ __launch_bounds__(RB * M / 8) void k_c2r_reg(const char *__restrict__ spec, long slot_bytes, int slot0,
                                                  RealOut out, long nrow, const float2 *__restrict__ tw_m,
-                                                 const float2 *__restrict__ tw_n, float scale)
+                                                 const float2 *__restrict__ tw_n, float scale, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_); for (int c_ = 0; c_ < 8; ++c_) out.p[c_] = mshift(out.p[c_], mo_);
     using S = RowShape<M, RB>;
     constexpr int RA = S::P::radix(S::NP - 1), R1 = S::P::radix(0);  // first and last inverse radices
     extern __shared__ char lds_raw[];
@@ -725,8 +729,10 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, char *__restr
                                                         long slot_bytes, int slot0, long nrow, int n3_rt,
                                                         int TWR, RadixPlan rp,
                                                         const typename CplxOf<R>::type *__restrict__ tw_m3,
-                                                        const typename CplxOf<R>::type *__restrict__ tw_n3)
+                                                        const typename CplxOf<R>::type *__restrict__ tw_n3, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); for (int c_ = 0; c_ < 8; ++c_) in.p[c_] = mshift(in.p[c_], mo_); spec = mshift(spec, mo_);
     using C = typename CplxOf<R>::type;
     extern __shared__ char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
@@ -772,8 +778,10 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const char *__restrict__
                                                         int slot0, RealOut out, long nrow, int n3_rt,
                                                         int TWR, RadixPlan rp,
                                                         const float2 *__restrict__ tw_m3,
-                                                        const float2 *__restrict__ tw_n3, float scale)
+                                                        const float2 *__restrict__ tw_n3, float scale, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_); for (int c_ = 0; c_ < 8; ++c_) out.p[c_] = mshift(out.p[c_], mo_);
     extern __shared__ char lds_raw[];
     float2 *lds = reinterpret_cast<float2 *>(lds_raw);
     const int n3 = LF > 0 ? 2 * LF : n3_rt;
@@ -866,8 +874,10 @@ template <bool INV, class R, int LF>
 __global__ __launch_bounds__(kFftThreads) void k_fft_cols(char *__restrict__ spec, long slot_bytes,
                                                           int slot0, ColDesc d, int TW, int logTW,
                                                           RadixPlan rp,
-                                                          const typename CplxOf<R>::type *__restrict__ tw)
+                                                          const typename CplxOf<R>::type *__restrict__ tw, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     using C = typename CplxOf<R>::type;
     extern __shared__ char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
@@ -875,7 +885,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(char *__restrict__ spe
     C *A = lds, *B = lds + L * TW;
     const int tid = threadIdx.x, nthr = kFftThreads;
     const TilePos tp = tile_pos();
-    C *base = reinterpret_cast<C *>(spec + (long)(slot0 + blockIdx.z) * slot_bytes) + d.base_off +
+    C *base = reinterpret_cast<C *>(spec + (long)(slot0 + bz_) * slot_bytes) + d.base_off +
               (long)tp.y * d.ostride;
     const int col0 = tp.x * TW;
     tile_load(A, base, d, L, TW, logTW, col0, tid, nthr);
@@ -1050,14 +1060,16 @@ __device__ __forceinline__ void st_inv(C *v, C *X, StoreF &&store, const C *__re
 // Column pass with register line FFTs (lengths with a RegPlan)
 template <bool INV, class R, int L>
 __global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long slot_bytes, int slot0, ColDesc d,
-                                                  const typename CplxOf<R>::type *__restrict__ tw)
+                                                  const typename CplxOf<R>::type *__restrict__ tw, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     using C = typename CplxOf<R>::type;
     using S = RegShape<L>;
     extern __shared__ char lds_raw[];
     C *X = reinterpret_cast<C *>(lds_raw);
     const TilePos tp = tile_pos();
-    C *base = reinterpret_cast<C *>(spec + (long)(slot0 + blockIdx.z) * slot_bytes) + d.base_off +
+    C *base = reinterpret_cast<C *>(spec + (long)(slot0 + bz_) * slot_bytes) + d.base_off +
               (long)tp.y * d.ostride;
     const int col0 = tp.x * S::TW;
     C out[S::T2][S::R2];
@@ -1116,8 +1128,10 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_scalar(char *__restrict__ sp
                                                            int in0, int out0, ColDesc d, int nyq,
                                                            int TW, int logTW, RadixPlan rp,
                                                            const typename CplxOf<R>::type *__restrict__ tw,
-                                                           SymCtx sc)
+                                                           SymCtx sc, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     using C = typename CplxOf<R>::type;
     extern __shared__ char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
@@ -1126,8 +1140,8 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_scalar(char *__restrict__ sp
     const TilePos tp = tile_pos();
     const int tid = threadIdx.x, nthr = kFftThreads, col0 = tp.x * TW;
     const long off = d.base_off + (long)tp.y * d.ostride;
-    const C *src = reinterpret_cast<const C *>(spec + (long)(in0 + blockIdx.z) * slot_bytes) + off;
-    float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + blockIdx.z) * slot_bytes) + off;
+    const C *src = reinterpret_cast<const C *>(spec + (long)(in0 + bz_) * slot_bytes) + off;
+    float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + bz_) * slot_bytes) + off;
     tile_load(load_target(rp, A, B), src, d, L, TW, logTW, col0, tid, nthr);
     __syncthreads();
     lds_fft_any<false, true, LF>(load_target(rp, A, B), load_target(rp, B, A), TW, logTW, 0, rp, tw, tid, nthr);
@@ -1159,8 +1173,10 @@ template <int LF>
 __global__ __launch_bounds__(kFftThreads) void k_x1_grad(char *__restrict__ spec, long slot_bytes, int in0,
                                                          int out0, ColDesc d, int nyq, int TW, int logTW,
                                                          RadixPlan rp, const double2 *__restrict__ twd,
-                                                         const float2 *__restrict__ twf, SymCtx sc)
+                                                         const float2 *__restrict__ twf, SymCtx sc, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     extern __shared__ char lds_raw[];
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile;
@@ -1169,7 +1185,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_grad(char *__restrict__ spec
     const TilePos tp = tile_pos();
     const int tid = threadIdx.x, nthr = kFftThreads, col0 = tp.x * TW;
     const long off = d.base_off + (long)tp.y * d.ostride;
-    const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(in0 + blockIdx.z) * slot_bytes) + off;
+    const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(in0 + bz_) * slot_bytes) + off;
     tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
     __syncthreads();
     lds_fft_any<false, true, LF>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
@@ -1186,7 +1202,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_grad(char *__restrict__ spec
     __syncthreads();
     for (int q = 0; q < 3; ++q) {
         const float2 *res = lds_fft_any<true, true, LF>(O + q * tile, S, TW, logTW, 0, rp, twf, tid, nthr);
-        float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + 3 * blockIdx.z + q) * slot_bytes) + off;
+        float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + 3 * bz_ + q) * slot_bytes) + off;
         tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
     }
@@ -1197,8 +1213,10 @@ template <int LF>
 __global__ __launch_bounds__(kFftThreads) void k_x1_div(char *__restrict__ spec, long slot_bytes, int in0,
                                                         int out0, ColDesc d, int nyq, int TW, int logTW,
                                                         RadixPlan rp, const double2 *__restrict__ twd,
-                                                        const float2 *__restrict__ twf, SymCtx sc)
+                                                        const float2 *__restrict__ twf, SymCtx sc, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     extern __shared__ char lds_raw[];
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile, *ACC = WB + tile;
@@ -1207,7 +1225,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_div(char *__restrict__ spec,
     const long off = d.base_off + (long)tp.y * d.ostride;
     const ColCtx cc{nyq, tp.y};
     for (int q = 0; q < 3; ++q) {
-        const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(in0 + 3 * blockIdx.z + q) * slot_bytes) + off;
+        const double2 *src = reinterpret_cast<const double2 *>(spec + (long)(in0 + 3 * bz_ + q) * slot_bytes) + off;
         tile_load(load_target(rp, WA, WB), src, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
         lds_fft_any<false, true, LF>(load_target(rp, WA, WB), load_target(rp, WB, WA), TW, logTW, 0, rp, twd, tid, nthr);
@@ -1225,7 +1243,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_div(char *__restrict__ spec,
     for (int idx = tid; idx < tile; idx += nthr) FA[idx] = to_f2(ACC[idx]);
     __syncthreads();
     const float2 *res = lds_fft_any<true, true, LF>(FA, FB, TW, logTW, 0, rp, twf, tid, nthr);
-    float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + blockIdx.z) * slot_bytes) + off;
+    float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + bz_) * slot_bytes) + off;
     tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
 }
 
@@ -1251,8 +1269,10 @@ template <int LF>
 __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spec, long slot_bytes, int in0,
                                                           int out0, ColDesc d, int nyq, int TW, int logTW,
                                                           RadixPlan rp, const float2 *__restrict__ twf,
-                                                          SymCtx sc)
+                                                          SymCtx sc, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     extern __shared__ char lds_raw[];
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     float2 *T = reinterpret_cast<float2 *>(lds_raw);  // three field tiles, then scratch
@@ -1261,7 +1281,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
     const int tid = threadIdx.x, nthr = kFftThreads, col0 = tp.x * TW;
     const long off = d.base_off + (long)tp.y * d.ostride;
     for (int q = 0; q < 3; ++q) {
-        const float2 *src = reinterpret_cast<const float2 *>(spec + (long)(in0 + 3 * blockIdx.z + q) * slot_bytes) + off;
+        const float2 *src = reinterpret_cast<const float2 *>(spec + (long)(in0 + 3 * bz_ + q) * slot_bytes) + off;
         float2 *home = T + q * tile;
         tile_load(load_target(rp, home, S), src, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
@@ -1285,7 +1305,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
     __syncthreads();
     for (int q = 0; q < 3; ++q) {
         const float2 *res = lds_fft_any<true, true, LF>(T + q * tile, S, TW, logTW, 0, rp, twf, tid, nthr);
-        float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + 3 * blockIdx.z + q) * slot_bytes) + off;
+        float2 *dst = reinterpret_cast<float2 *>(spec + (long)(out0 + 3 * bz_ + q) * slot_bytes) + off;
         tile_store(dst, res, d, L, TW, logTW, col0, tid, nthr);
         __syncthreads();
     }
@@ -1301,14 +1321,16 @@ template <int OP, int L, int TW>
 __global__ __launch_bounds__(TW * L / 8) void k_x1_reg(char *__restrict__ spec, long slot_bytes, int in0,
                                                          int out0, ColDesc d, int nyq,
                                                          const double2 *__restrict__ twd,
-                                                         const float2 *__restrict__ twf, SymCtx sc)
+                                                         const float2 *__restrict__ twf, SymCtx sc, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     using S = StShape<L, TW>;
     extern __shared__ char lds_raw[];
     double2 *XD = reinterpret_cast<double2 *>(lds_raw);
     float2 *XF = reinterpret_cast<float2 *>(lds_raw);
     const TilePos tp = tile_pos();
-    const int col0 = tp.x * TW, z = (int)blockIdx.z;
+    const int col0 = tp.x * TW, z = (int)bz_;
     const long off = d.base_off + (long)tp.y * d.ostride;
     const ColCtx cc{nyq, tp.y};
     auto load_d = [&](int slot) {
@@ -1486,8 +1508,10 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_assemble(char *__restrict__ 
                                                              int w0, int b0, int out0, ColDesc d, int nyq,
                                                              int TW, int logTW, RadixPlan rp,
                                                              const double2 *__restrict__ twd,
-                                                             const float2 *__restrict__ twf, SymCtx sc)
+                                                             const float2 *__restrict__ twf, SymCtx sc, Mb mb)
 {
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     extern __shared__ char lds_raw[];
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile;
@@ -1554,8 +1578,9 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_assemble(char *__restrict__ 
 }
 
 // standard half-spectrum layout <-> internal layout (FP32 slots)
-__global__ void k_pack_standard(const float2 *__restrict__ spec, float2 *__restrict__ dst, long nrow, int m3)
+__global__ void k_pack_standard(const float2 *__restrict__ spec, float2 *__restrict__ dst, long nrow, int m3, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.z); spec = mshift(spec, mo_); dst = mshift(dst, mo_);
     const long total = nrow * (m3 + 1);
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
         const long row = i / (m3 + 1);
@@ -1564,8 +1589,9 @@ __global__ void k_pack_standard(const float2 *__restrict__ spec, float2 *__restr
     }
 }
 
-__global__ void k_unpack_standard(const float2 *__restrict__ srcp, float2 *__restrict__ spec, long nrow, int m3)
+__global__ void k_unpack_standard(const float2 *__restrict__ srcp, float2 *__restrict__ spec, long nrow, int m3, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.z); srcp = mshift(srcp, mo_); spec = mshift(spec, mo_);
     const long total = nrow * (m3 + 1);
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
         const long row = i / (m3 + 1);
@@ -1605,6 +1631,14 @@ static int col_tile(int L, size_t bytes_per_elem, int ncols, size_t budget);
 static void col_descs(const FftCtx &F, int axis, struct ColDesc dd[2], int outer[2]);
 static size_t x1_bytes_per_elem(int op);
 static void default_tiles(FftCtx &F);
+
+// a launch grid over every member of the plan: the member index is folded
+// into z (z = index within the launch + extent * member)
+static dim3 mgrid(const lddmm_plan *P, dim3 g)
+{
+    g.z *= (unsigned)P->mb.count;
+    return g;
+}
 
 template <class C>
 static C *upload_twiddles(int L)
@@ -1750,12 +1784,12 @@ void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int slot0, bool dbl)
                 const dim3 blk(RS::NT);
                 if (dbl) {
                     if (ldsr > 65536) allow_big_lds((const void *)(k_r2c_reg<double, LF, RB>));
-                    hipLaunchKernelGGL((k_r2c_reg<double, LF, RB>), gr, blk, ldsr, P->stream, in, P->spec,
-                                       P->slot_bytes, slot0, F.nrow, F.tw3d, F.twN3d);
+                    hipLaunchKernelGGL((k_r2c_reg<double, LF, RB>), mgrid(P, gr), blk, ldsr, P->stream, in, P->spec,
+                                       P->slot_bytes, slot0, F.nrow, F.tw3d, F.twN3d, P->mb);
                 } else {
                     if (ldsr > 65536) allow_big_lds((const void *)(k_r2c_reg<float, LF, RB>));
-                    hipLaunchKernelGGL((k_r2c_reg<float, LF, RB>), gr, blk, ldsr, P->stream, in, P->spec,
-                                       P->slot_bytes, slot0, F.nrow, F.tw3, F.twN3);
+                    hipLaunchKernelGGL((k_r2c_reg<float, LF, RB>), mgrid(P, gr), blk, ldsr, P->stream, in, P->spec,
+                                       P->slot_bytes, slot0, F.nrow, F.tw3, F.twN3, P->mb);
                 }
             };
             if (TWR >= RowPlan<LF>::RBA)
@@ -1771,11 +1805,11 @@ void r2c_fields(lddmm_plan *P, const RealIn &in, int count, int slot0, bool dbl)
     }
     with_len(F.m3, [&]<int LF>() {
         if (dbl)
-            FFT_LAUNCH((k_r2c_x3<double, LF>), grid, lds, P->stream, in, P->spec,
-                               P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3d, F.twN3d);
+            FFT_LAUNCH((k_r2c_x3<double, LF>), mgrid(P, grid), lds, P->stream, in, P->spec,
+                               P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3d, F.twN3d, P->mb);
         else
-            FFT_LAUNCH((k_r2c_x3<float, LF>), grid, lds, P->stream, in, P->spec,
-                               P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3);
+            FFT_LAUNCH((k_r2c_x3<float, LF>), mgrid(P, grid), lds, P->stream, in, P->spec,
+                               P->slot_bytes, slot0, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3, P->mb);
     });
     check_hip(hipGetLastError(), "k_r2c_x3");
 }
@@ -1797,8 +1831,8 @@ void c2r_fields(lddmm_plan *P, int slot0, int count, const RealOut &out, float s
                 check_lds(ldsr, "c2r_x3");
                 const dim3 gr((unsigned)((F.nrow + RB - 1) / RB), count);
                 if (ldsr > 65536) allow_big_lds((const void *)(k_c2r_reg<LF, RB>));
-                hipLaunchKernelGGL((k_c2r_reg<LF, RB>), gr, dim3(RS::NT), ldsr, P->stream, P->spec, P->slot_bytes,
-                                   slot0, out, F.nrow, F.tw3, F.twN3, scale);
+                hipLaunchKernelGGL((k_c2r_reg<LF, RB>), mgrid(P, gr), dim3(RS::NT), ldsr, P->stream, P->spec, P->slot_bytes,
+                                   slot0, out, F.nrow, F.tw3, F.twN3, scale, P->mb);
             };
             if (TWR >= RowPlan<LF>::RBA)
                 go.template operator()<RowPlan<LF>::RBA>();
@@ -1812,8 +1846,8 @@ void c2r_fields(lddmm_plan *P, int slot0, int count, const RealOut &out, float s
         return;
     }
     with_len(F.m3, [&]<int LF>() {
-        FFT_LAUNCH((k_c2r_x3<LF>), grid, lds, P->stream, P->spec, P->slot_bytes,
-                           slot0, out, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3, scale);
+        FFT_LAUNCH((k_c2r_x3<LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
+                           slot0, out, F.nrow, F.n3, TWR, F.rp3, F.tw3, F.twN3, scale, P->mb);
     });
     check_hip(hipGetLastError(), "k_c2r_x3");
 }
@@ -1857,19 +1891,19 @@ static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool invers
                 if (dbl) {
                     const double2 *tw = axis == 1 ? F.tw2d : F.tw1d;
                     if (inverse)
-                        FFT_LAUNCH((k_cols_reg<true, double, LF>), grid, lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, d, tw);
+                        FFT_LAUNCH((k_cols_reg<true, double, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, d, tw, P->mb);
                     else
-                        FFT_LAUNCH((k_cols_reg<false, double, LF>), grid, lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, d, tw);
+                        FFT_LAUNCH((k_cols_reg<false, double, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, d, tw, P->mb);
                 } else {
                     const float2 *tw = axis == 1 ? F.tw2 : F.tw1;
                     if (inverse)
-                        FFT_LAUNCH((k_cols_reg<true, float, LF>), grid, lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, d, tw);
+                        FFT_LAUNCH((k_cols_reg<true, float, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, d, tw, P->mb);
                     else
-                        FFT_LAUNCH((k_cols_reg<false, float, LF>), grid, lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, d, tw);
+                        FFT_LAUNCH((k_cols_reg<false, float, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, d, tw, P->mb);
                 }
                 done = true;
             }
@@ -1887,19 +1921,19 @@ static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool invers
             if (dbl) {
                 const double2 *tw = axis == 1 ? F.tw2d : F.tw1d;
                 if (inverse)
-                    FFT_LAUNCH((k_fft_cols<true, double, LF>), grid, lds, P->stream,
-                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+                    FFT_LAUNCH((k_fft_cols<true, double, LF>), mgrid(P, grid), lds, P->stream,
+                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw, P->mb);
                 else
-                    FFT_LAUNCH((k_fft_cols<false, double, LF>), grid, lds, P->stream,
-                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+                    FFT_LAUNCH((k_fft_cols<false, double, LF>), mgrid(P, grid), lds, P->stream,
+                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw, P->mb);
             } else {
                 const float2 *tw = axis == 1 ? F.tw2 : F.tw1;
                 if (inverse)
-                    FFT_LAUNCH((k_fft_cols<true, float, LF>), grid, lds, P->stream,
-                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+                    FFT_LAUNCH((k_fft_cols<true, float, LF>), mgrid(P, grid), lds, P->stream,
+                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw, P->mb);
                 else
-                    FFT_LAUNCH((k_fft_cols<false, float, LF>), grid, lds, P->stream,
-                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw);
+                    FFT_LAUNCH((k_fft_cols<false, float, LF>), mgrid(P, grid), lds, P->stream,
+                                       P->spec, P->slot_bytes, slot0, d, TW, lt, rp, tw, P->mb);
             }
         });
         check_hip(hipGetLastError(), "k_fft_cols");
@@ -1978,8 +2012,8 @@ static void x1_reg_launch(lddmm_plan *P, int op, int in0, int out0, const ColDes
 #define X1R(OPV)                                                                                         \
     do {                                                                                                 \
         if (lds > 65536) allow_big_lds((const void *)(k_x1_reg<OPV, LF, TW>));                           \
-        hipLaunchKernelGGL((k_x1_reg<OPV, LF, TW>), grid, dim3(RS::NT), lds, P->stream, P->spec,         \
-                           P->slot_bytes, in0, out0, d, part, F.tw1d, F.tw1, sc);                        \
+        hipLaunchKernelGGL((k_x1_reg<OPV, LF, TW>), mgrid(P, grid), dim3(RS::NT), lds, P->stream, P->spec,         \
+                           P->slot_bytes, in0, out0, d, part, F.tw1d, F.tw1, sc, P->mb);                        \
     } while (0)
     switch (op) {
     case SOP_GRAD: X1R(SOP_GRAD); break;
@@ -2039,32 +2073,32 @@ static void x1_symbol_parts(lddmm_plan *P, int op, int in0, int out0, int nbatch
         with_len(L, [&]<int LF>() {
             switch (op) {
             case SOP_GRAD:
-                FFT_LAUNCH((k_x1_grad<LF>), dim3(gx, outer[part], nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d,
-                                   F.tw1, sc);
+                FFT_LAUNCH((k_x1_grad<LF>), mgrid(P, dim3(gx, outer[part], nbatch)), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d,
+                                   F.tw1, sc, P->mb);
                 break;
             case SOP_DIV:
-                FFT_LAUNCH((k_x1_div<LF>), dim3(gx, outer[part], nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d,
-                                   F.tw1, sc);
+                FFT_LAUNCH((k_x1_div<LF>), mgrid(P, dim3(gx, outer[part], nbatch)), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1d,
+                                   F.tw1, sc, P->mb);
                 break;
             case SOP_LERAY:
-                FFT_LAUNCH((k_x1_leray<LF>), dim3(gx, outer[part], nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1, sc);
+                FFT_LAUNCH((k_x1_leray<LF>), mgrid(P, dim3(gx, outer[part], nbatch)), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d, part, TW, lt, rp, F.tw1, sc, P->mb);
                 break;
             case SOP_ASSEMBLE:
                 for (int b = 0; b < nbatch; ++b)
-                    FFT_LAUNCH((k_x1_assemble<LF>), dim3(gx, outer[part], 1), lds, P->stream, P->spec, P->slot_bytes, in0 + 6 * b, in0 + 6 * b + 3,
-                                       out0 + 3 * b, d, part, TW, lt, rp, F.tw1d, F.tw1, sc);
+                    FFT_LAUNCH((k_x1_assemble<LF>), mgrid(P, dim3(gx, outer[part], 1)), lds, P->stream, P->spec, P->slot_bytes, in0 + 6 * b, in0 + 6 * b + 3,
+                                       out0 + 3 * b, d, part, TW, lt, rp, F.tw1d, F.tw1, sc, P->mb);
                 break;
             case SOP_REG:  // three independent fields per batch
-                FFT_LAUNCH((k_x1_scalar<double, SYM_REG, LF>), dim3(gx, outer[part], 3 * nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
-                                   part, TW, lt, rp, F.tw1d, sc);
+                FFT_LAUNCH((k_x1_scalar<double, SYM_REG, LF>), mgrid(P, dim3(gx, outer[part], 3 * nbatch)), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
+                                   part, TW, lt, rp, F.tw1d, sc, P->mb);
                 break;
             case SOP_INVREG:
-                FFT_LAUNCH((k_x1_scalar<float, SYM_INVREG, LF>), dim3(gx, outer[part], 3 * nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
-                                   part, TW, lt, rp, F.tw1, sc);
+                FFT_LAUNCH((k_x1_scalar<float, SYM_INVREG, LF>), mgrid(P, dim3(gx, outer[part], 3 * nbatch)), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
+                                   part, TW, lt, rp, F.tw1, sc, P->mb);
                 break;
             case SOP_IDENT:
-                FFT_LAUNCH((k_x1_scalar<float, SYM_IDENT, LF>), dim3(gx, outer[part], nbatch), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
-                                   part, TW, lt, rp, F.tw1, sc);
+                FFT_LAUNCH((k_x1_scalar<float, SYM_IDENT, LF>), mgrid(P, dim3(gx, outer[part], nbatch)), lds, P->stream, P->spec, P->slot_bytes, in0, out0, d,
+                                   part, TW, lt, rp, F.tw1, sc, P->mb);
                 break;
             default: fail(LDDMM_EINVAL, "unknown spectral operator");
             }
@@ -2315,8 +2349,9 @@ std::string tuning_report(const lddmm_plan *P)
 // coefficient of the same k times scale when |k_d| < nc_d/2 on every axis of
 // the coarse grid nc (coarse Nyquist modes dropped), else zero.
 __global__ void k_resample(const float2 *__restrict__ src, int s1, int s2, int sm3, float2 *__restrict__ dst,
-                           int d1, int d2, int dm3, int c1, int c2, int cm3, float scale)
+                           int d1, int d2, int dm3, int c1, int c2, int cm3, float scale, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.z); src = mshift(src, mo_); dst = mshift(dst, mo_);
     const long nrow = (long)d1 * d2, total = nrow * (dm3 + 1);
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
         long row;
@@ -2350,8 +2385,8 @@ void spectral_resample(lddmm_plan *S, int s0, lddmm_plan *D, int d0, int count)
     for (int f = 0; f < count; ++f) {
         const float2 *src = reinterpret_cast<const float2 *>(S->spec + (long)(s0 + f) * S->slot_bytes);
         float2 *dst = reinterpret_cast<float2 *>(D->spec + (long)(d0 + f) * D->slot_bytes);
-        hipLaunchKernelGGL(k_resample, dim3(1024), dim3(256), 0, D->stream, src, FS.n1, FS.n2, FS.m3, dst, FD.n1,
-                           FD.n2, FD.m3, FC.n1, FC.n2, FC.m3, scale);
+        hipLaunchKernelGGL(k_resample, mgrid(D, dim3(1024)), dim3(256), 0, D->stream, src, FS.n1, FS.n2, FS.m3, dst, FD.n1,
+                           FD.n2, FD.m3, FC.n1, FC.n2, FC.m3, scale, D->mb);
     }
     check_hip(hipGetLastError(), "k_resample");
 }
@@ -2360,8 +2395,8 @@ void pack_standard(lddmm_plan *P, int slot, float2 *dst)
 {
     FftCtx &F = P->fft;
     Scope s(P, K_PACK);
-    hipLaunchKernelGGL(k_pack_standard, dim3(1024), dim3(256), 0, P->stream,
-                       reinterpret_cast<const float2 *>(P->spec + (long)slot * P->slot_bytes), dst, F.nrow, F.m3);
+    hipLaunchKernelGGL(k_pack_standard, mgrid(P, dim3(1024)), dim3(256), 0, P->stream,
+                       reinterpret_cast<const float2 *>(P->spec + (long)slot * P->slot_bytes), dst, F.nrow, F.m3, P->mb);
     check_hip(hipGetLastError(), "k_pack_standard");
 }
 
@@ -2369,8 +2404,8 @@ void unpack_standard(lddmm_plan *P, const float2 *srcp, int slot)
 {
     FftCtx &F = P->fft;
     Scope s(P, K_PACK);
-    hipLaunchKernelGGL(k_unpack_standard, dim3(1024), dim3(256), 0, P->stream, srcp,
-                       reinterpret_cast<float2 *>(P->spec + (long)slot * P->slot_bytes), F.nrow, F.m3);
+    hipLaunchKernelGGL(k_unpack_standard, mgrid(P, dim3(1024)), dim3(256), 0, P->stream, srcp,
+                       reinterpret_cast<float2 *>(P->spec + (long)slot * P->slot_bytes), F.nrow, F.m3, P->mb);
     check_hip(hipGetLastError(), "k_unpack_standard");
 }
 

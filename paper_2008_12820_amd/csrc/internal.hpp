@@ -74,6 +74,10 @@ struct lddmm_plan {
     unsigned long coarse_gen = 0;  // vel_gen whose restricted grad m(1) the coarse plan holds
     double beta_sym = 0.0;    // > 0: beta of the (beta A)^{-1} symbol instead of cfg.beta
     int device = 0;
+    // members of a batched plan (see Mb); the arena holds mb.count copies of
+    // the workspace, mb.stride bytes apart
+    lddmm::Mb mb;
+    const lddmm_plan *view_of = nullptr;  // a batch member's plan: the batched plan it views
     long N = 0;
     int nt = 0;
     double h[3] = {0, 0, 0};
@@ -229,6 +233,9 @@ void pcg_update_xr(lddmm_plan *P, long n, float al, const float *p, const float 
                    float *r);
 constexpr int kRedBlocks = 1024;
 constexpr int kNumScalars = 32;
+// pinned host doubles per member: the scalars, then the 2-slot poll rings of
+// the PCG and of the inner PCG
+constexpr int kHostScalars = kNumScalars + 4;
 constexpr int kHistMax = 4096;  // PCG iterations whose residual is recorded
 
 // Device scalar slots (P->dscal).  0..4 serve the eager calls; the rest hold
@@ -265,5 +272,10 @@ void dev_store_scalar(lddmm_plan *P, int slot, double *dst);
 void dev_inner_link(lddmm_plan *P, double *outer);
 void dev_inner_accum(lddmm_plan *P, double *outer);
 void copy_kernel(lddmm_plan *P, long n, const float *x, float *out);
+
+// ---- batched plans (api.hip) ----------------------------------------------
+lddmm_plan *create_plan(const lddmm_config *cfg, void *stream, int members);
+lddmm_plan *member_view(const lddmm_plan *G, int b);
+void view_free(lddmm_plan *V);
 
 }  // namespace lddmm

@@ -21,8 +21,9 @@ __device__ __forceinline__ double red_term(float x, float y)
 template <int MODE>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const float *__restrict__ a,
                                                                 const float *__restrict__ b, long n,
-                                                                int vec, double *__restrict__ partial)
+                                                                int vec, double *__restrict__ partial, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); a = mshift(a, mo_); b = mshift(b, mo_); partial = mshift(partial, mo_);
     __shared__ double sh[kRedThreads];
     double acc = 0.0;
     const long stride = (long)gridDim.x * blockDim.x;
@@ -53,8 +54,9 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const float *__r
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double *__restrict__ partial,
                                                               int np, double *__restrict__ out,
-                                                              double scale)
+                                                              double scale, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); partial = mshift(partial, mo_); out = mshift(out, mo_);
     __shared__ double sh[kRedThreads];
     double acc = 0.0;
     for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[i];
@@ -96,8 +98,9 @@ __device__ __forceinline__ float4 f4axpby(float a, float4 x, float b, float4 y)
 }
 
 __global__ void k_axpby(long n, int vec, float a, const float *__restrict__ x, float b,
-                        const float *__restrict__ y, float *__restrict__ out)
+                        const float *__restrict__ y, float *__restrict__ out, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); x = mshift(x, mo_); y = mshift(y, mo_); out = mshift(out, mo_);
     if (y) {
         ew_loop(
             n, vec,
@@ -114,8 +117,9 @@ __global__ void k_axpby(long n, int vec, float a, const float *__restrict__ x, f
     }
 }
 
-__global__ void k_fill(long n, int vec, float value, float *__restrict__ out)
+__global__ void k_fill(long n, int vec, float value, float *__restrict__ out, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); out = mshift(out, mo_);
     ew_loop(
         n, vec, [&](long i) { ((float4 *)out)[i] = make_float4(value, value, value, value); },
         [&](long i) { out[i] = value; });
@@ -144,16 +148,18 @@ __device__ __forceinline__ void xr_update(long n, int vec, float al, const float
 }
 
 __global__ void k_pcg_xr(long n, int vec, float al, const float *__restrict__ p, const float *__restrict__ q,
-                         float *__restrict__ x, float *__restrict__ r)
+                         float *__restrict__ x, float *__restrict__ r, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); p = mshift(p, mo_); q = mshift(q, mo_); x = mshift(x, mo_); r = mshift(r, mo_);
     xr_update(n, vec, al, p, q, x, r);
 }
 
 // H0 s = beta0 A s + G (G . s) (eq. h0-pc): on entry out holds A s; three
 // fields each, stride n
 __global__ void k_h0_point(long n, int vec, float beta0, const float *__restrict__ s,
-                           const float *__restrict__ G, float *__restrict__ out)
+                           const float *__restrict__ G, float *__restrict__ out, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); s = mshift(s, mo_); G = mshift(G, mo_); out = mshift(out, mo_);
     ew_loop(
         n, vec,
         [&](long i) {
@@ -181,11 +187,13 @@ __global__ void k_h0_point(long n, int vec, float beta0, const float *__restrict
 }
 
 // ---- device-resident PCG scalars ----------------------------------------
-__global__ void k_set_scalar(double *d, int slot, double value) { d[slot] = value; }
+__global__ void k_set_scalar(double *d, int slot, double value, Mb mb) {
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); d[slot] = value; }
 
 // gnorm = sqrt(<g,g>); ||g0|| latched on first use; eps_K rule when rtol <= 0
-__global__ void k_tolerance(double *d, double rtol)
+__global__ void k_tolerance(double *d, double rtol, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_);
     const double gn = sqrt(d[S_GG]);
     d[S_GNORM] = gn;
     if (d[S_G0] == 0.0) d[S_G0] = gn;
@@ -193,8 +201,9 @@ __global__ void k_tolerance(double *d, double rtol)
     d[S_RTOL] = rtol > 0.0 ? rtol : fmin(sqrt(grel), 0.5);
 }
 
-__global__ void k_pcg_init(double *d)
+__global__ void k_pcg_init(double *d, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_);
     const double r0 = sqrt(d[S_RR]);
     d[S_R0] = r0;
     d[S_DONE] = (r0 == 0.0) ? 1.0 : 0.0;
@@ -208,8 +217,9 @@ __global__ void k_pcg_init(double *d)
 }
 
 // after kappa = <p, H p>: alpha, or stop on non-finite / non-positive kappa
-__global__ void k_pcg_alpha(double *d)
+__global__ void k_pcg_alpha(double *d, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_);
     if (d[S_DONE] != 0.0) {
         d[S_ALPHA] = 0.0;
         return;
@@ -231,24 +241,27 @@ __global__ void k_pcg_alpha(double *d)
 }
 
 __global__ void k_pcg_xr_dev(long n, int vec, const double *__restrict__ d, const float *__restrict__ p,
-                             const float *__restrict__ q, float *__restrict__ x, float *__restrict__ r)
+                             const float *__restrict__ q, float *__restrict__ x, float *__restrict__ r, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); p = mshift(p, mo_); q = mshift(q, mo_); x = mshift(x, mo_); r = mshift(r, mo_);
     const float al = (float)d[S_ALPHA];
     if (al == 0.f) return;
     xr_update(n, vec, al, p, q, x, r);
 }
 
 __global__ void k_copy_if(long n, int vec, const double *__restrict__ d, const float *__restrict__ z,
-                          float *__restrict__ x)
+                          float *__restrict__ x, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); z = mshift(z, mo_); x = mshift(x, mo_);
     if (d[S_COPYZ] == 0.0) return;
     ew_loop(
         n, vec, [&](long i) { ((float4 *)x)[i] = ((const float4 *)z)[i]; }, [&](long i) { x[i] = z[i]; });
 }
 
 // after rr = <r, r>: relative residual and the stopping test
-__global__ void k_pcg_conv(double *d)
+__global__ void k_pcg_conv(double *d, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_);
     if (d[S_DONE] != 0.0) return;
     const double rn = sqrt(d[S_RR]);
     if (!isfinite(rn)) {
@@ -260,16 +273,18 @@ __global__ void k_pcg_conv(double *d)
     if (rn <= d[S_RTOL] * d[S_R0]) d[S_DONE] = 1.0;
 }
 
-__global__ void k_pcg_beta(double *d)
+__global__ void k_pcg_beta(double *d, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_);
     if (d[S_DONE] != 0.0) return;
     d[S_BETA] = d[S_RZN] / d[S_RZ];
     d[S_RZ] = d[S_RZN];
 }
 
 __global__ void k_pcg_p(long n, int vec, const double *__restrict__ d, const float *__restrict__ z,
-                        float *__restrict__ p)
+                        float *__restrict__ p, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); z = mshift(z, mo_); p = mshift(p, mo_);
     if (d[S_DONE] != 0.0) return;
     const float be = (float)d[S_BETA];
     ew_loop(
@@ -284,19 +299,24 @@ __global__ void k_pcg_p(long n, int vec, const double *__restrict__ d, const flo
         [&](long i) { p[i] = __builtin_fmaf(be, p[i], z[i]); });
 }
 
-__global__ void k_sum2(double *d, int dst, int a, int b) { d[dst] = d[a] + d[b]; }
-__global__ void k_inner_link(double *inner, const double *outer)
+__global__ void k_sum2(double *d, int dst, int a, int b, Mb mb) {
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); d[dst] = d[a] + d[b]; }
+__global__ void k_inner_link(double *inner, const double *outer, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); inner = mshift(inner, mo_); outer = mshift(outer, mo_);
     if (outer[S_DONE] != 0.0) inner[S_DONE] = 1.0;
 }
-__global__ void k_inner_accum(const double *inner, double *outer)
+__global__ void k_inner_accum(const double *inner, double *outer, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); inner = mshift(inner, mo_); outer = mshift(outer, mo_);
     if (outer[S_DONE] == 0.0) outer[S_INNER] += inner[S_ITERS];
 }
-__global__ void k_store_scalar(const double *d, int slot, double *dst) { dst[0] = d[slot]; }
+__global__ void k_store_scalar(const double *d, int slot, double *dst, Mb mb) {
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); dst = mshift(dst, mo_); dst[0] = d[slot]; }
 
-__global__ void k_copy(long n, int vec, const float *__restrict__ x, float *__restrict__ out)
+__global__ void k_copy(long n, int vec, const float *__restrict__ x, float *__restrict__ out, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); x = mshift(x, mo_); out = mshift(out, mo_);
     ew_loop(
         n, vec, [&](long i) { ((float4 *)out)[i] = ((const float4 *)x)[i]; }, [&](long i) { out[i] = x[i]; });
 }
@@ -322,22 +342,22 @@ static unsigned vec_blocks(long n, int vec = 0)
 void dot_async(lddmm_plan *P, const float *a, const float *b, long n, int slot, double scale)
 {
     Scope s(P, K_DOT);
-    hipLaunchKernelGGL(k_reduce_partial<0>, dim3(kRedBlocks), dim3(kRedThreads), 0, P->stream, a, b,
-                       n, vec_ok({a, b}), P->red);
+    hipLaunchKernelGGL(k_reduce_partial<0>, dim3(kRedBlocks, P->mb.count), dim3(kRedThreads), 0, P->stream, a, b,
+                       n, vec_ok({a, b}), P->red, P->mb);
     check_hip(hipGetLastError(), "k_reduce_partial");
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, P->stream, P->red, kRedBlocks,
-                       scalars(P) + slot, scale);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1, P->mb.count), dim3(kRedThreads), 0, P->stream, P->red, kRedBlocks,
+                       scalars(P) + slot, scale, P->mb);
     check_hip(hipGetLastError(), "k_reduce_final");
 }
 
 void sqdiff_async(lddmm_plan *P, const float *a, const float *b, long n, int slot, double scale)
 {
     Scope s(P, K_DOT);
-    hipLaunchKernelGGL(k_reduce_partial<1>, dim3(kRedBlocks), dim3(kRedThreads), 0, P->stream, a, b,
-                       n, vec_ok({a, b}), P->red);
+    hipLaunchKernelGGL(k_reduce_partial<1>, dim3(kRedBlocks, P->mb.count), dim3(kRedThreads), 0, P->stream, a, b,
+                       n, vec_ok({a, b}), P->red, P->mb);
     check_hip(hipGetLastError(), "k_reduce_partial");
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, P->stream, P->red, kRedBlocks,
-                       scalars(P) + slot, scale);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1, P->mb.count), dim3(kRedThreads), 0, P->stream, P->red, kRedBlocks,
+                       scalars(P) + slot, scale, P->mb);
     check_hip(hipGetLastError(), "k_reduce_final");
 }
 
@@ -354,7 +374,8 @@ void axpby(lddmm_plan *P, long n, float a, const float *x, float b, const float 
 {
     Scope s(P, K_VECOP);
     const int vec = vec_ok({x, y, out});
-    hipLaunchKernelGGL(k_axpby, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, a, x, b, y, out);
+    hipLaunchKernelGGL(k_axpby, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, a, x, b, y, out,
+                       P->mb);
     check_hip(hipGetLastError(), "k_axpby");
 }
 
@@ -362,7 +383,7 @@ void fill(lddmm_plan *P, long n, float value, float *out)
 {
     Scope s(P, K_VECOP);
     const int vec = vec_ok({out});
-    hipLaunchKernelGGL(k_fill, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, value, out);
+    hipLaunchKernelGGL(k_fill, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, value, out, P->mb);
     check_hip(hipGetLastError(), "k_fill");
 }
 
@@ -370,14 +391,15 @@ void pcg_update_xr(lddmm_plan *P, long n, float al, const float *p, const float 
 {
     Scope s(P, K_VECOP);
     const int vec = vec_ok({p, q, x, r});
-    hipLaunchKernelGGL(k_pcg_xr, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, al, p, q, x, r);
+    hipLaunchKernelGGL(k_pcg_xr, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, al, p, q, x, r,
+                       P->mb);
     check_hip(hipGetLastError(), "k_pcg_xr");
 }
 
 #define LAUNCH1(kern, ...)                                                                  \
     do {                                                                                    \
         Scope s_(P, K_VECOP);                                                               \
-        hipLaunchKernelGGL(kern, dim3(1), dim3(1), 0, P->stream, __VA_ARGS__);              \
+        hipLaunchKernelGGL(kern, dim3(1, P->mb.count), dim3(1), 0, P->stream, __VA_ARGS__, P->mb); \
         check_hip(hipGetLastError(), #kern);                                                \
     } while (0)
 
@@ -396,8 +418,8 @@ void dev_pcg_xr(lddmm_plan *P, long n, const float *p, const float *q, float *x,
 {
     Scope s(P, K_VECOP);
     const int vec = vec_ok({p, q, x, r});
-    hipLaunchKernelGGL(k_pcg_xr_dev, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, scalars(P), p, q, x,
-                       r);
+    hipLaunchKernelGGL(k_pcg_xr_dev, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, scalars(P),
+                       p, q, x, r, P->mb);
     check_hip(hipGetLastError(), "k_pcg_xr_dev");
 }
 
@@ -405,7 +427,8 @@ void dev_copy_if(lddmm_plan *P, long n, const float *z, float *x)
 {
     Scope s(P, K_VECOP);
     const int vec = vec_ok({z, x});
-    hipLaunchKernelGGL(k_copy_if, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, scalars(P), z, x);
+    hipLaunchKernelGGL(k_copy_if, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, scalars(P), z,
+                       x, P->mb);
     check_hip(hipGetLastError(), "k_copy_if");
 }
 
@@ -413,7 +436,8 @@ void dev_pcg_p(lddmm_plan *P, long n, const float *z, float *p)
 {
     Scope s(P, K_VECOP);
     const int vec = vec_ok({z, p});
-    hipLaunchKernelGGL(k_pcg_p, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, scalars(P), z, p);
+    hipLaunchKernelGGL(k_pcg_p, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, scalars(P), z, p,
+                       P->mb);
     check_hip(hipGetLastError(), "k_pcg_p");
 }
 
@@ -422,7 +446,8 @@ void h0_point(lddmm_plan *P, const float *s, const float *G, float *out, float b
     Scope sc(P, K_VECOP);
     const long n = P->N;
     const int vec = vec_ok({s, s + n, G, G + n, out, out + n});
-    hipLaunchKernelGGL(k_h0_point, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, beta0, s, G, out);
+    hipLaunchKernelGGL(k_h0_point, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, beta0, s, G,
+                       out, P->mb);
     check_hip(hipGetLastError(), "k_h0_point");
 }
 
@@ -430,7 +455,7 @@ void copy_kernel(lddmm_plan *P, long n, const float *x, float *out)
 {
     Scope s(P, K_VECOP);
     const int vec = vec_ok({x, out});
-    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n, vec)), dim3(256), 0, P->stream, n, vec, x, out);
+    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, x, out, P->mb);
     check_hip(hipGetLastError(), "k_copy");
 }
 

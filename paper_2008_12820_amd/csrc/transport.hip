@@ -234,8 +234,9 @@ template <int ORDER>
 __global__ __launch_bounds__(kPtThreads) void k_departure(const float *__restrict__ v,
                                                           float *__restrict__ dX,
                                                           float *__restrict__ dXa, Grid3 g, double dt,
-                                                          double ih1, double ih2, double ih3)
+                                                          double ih1, double ih2, double ih3, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); v = mshift(v, mo_); dX = mshift(dX, mo_); dXa = mshift(dXa, mo_);
     const int p = point_index();
     if (p >= g.N) return;
     int i, j, k;
@@ -292,8 +293,9 @@ template <int NTC>
 __global__ __launch_bounds__(kPtThreads) void k_body_force(const float4 *__restrict__ lam,
                                                            const float4 *__restrict__ lamN, float scaleN,
                                                            const float4 *__restrict__ G, float4 *__restrict__ b,
-                                                           long N4, int nt_rt, float dt)
+                                                           long N4, int nt_rt, float dt, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); lam = mshift(lam, mo_); lamN = mshift(lamN, mo_); G = mshift(G, mo_); b = mshift(b, mo_);
     const int nt = NTC > 0 ? NTC : nt_rt;
     const long p = (long)xcd_block((int)blockIdx.x, (int)gridDim.x) * kPtThreads + threadIdx.x;
     if (p >= N4) return;
@@ -413,6 +415,7 @@ struct NoIn {
 };
 struct EpiCopy {  // out = I[src]
     static constexpr int NF = 1;
+    __device__ void shift(long long o) { src = mshift(src, o); dst = mshift(dst, o); }
     using In = NoIn;
     const float *src;
     float *dst;
@@ -422,6 +425,7 @@ struct EpiCopy {  // out = I[src]
 };
 struct EpiAdj {  // out = scale * c * I[src]
     static constexpr int NF = 1;
+    __device__ void shift(long long o) { src = mshift(src, o); coef = mshift(coef, o); dst = mshift(dst, o); }
     struct In {
         float c;
     };
@@ -434,6 +438,7 @@ struct EpiAdj {  // out = scale * c * I[src]
 };
 struct EpiInc {  // out = I[src] - dt/2 s
     static constexpr int NF = 1;
+    __device__ void shift(long long o) { src = mshift(src, o); s = mshift(s, o); dst = mshift(dst, o); }
     struct In {
         float s;
     };
@@ -446,6 +451,7 @@ struct EpiInc {  // out = I[src] - dt/2 s
 };
 struct EpiAdjCoef {  // c = 1 + dt/2 (delta_a + delta (1 + dt delta_a)), delta_a = I[delta](Xa)
     static constexpr int NF = 1;
+    __device__ void shift(long long o) { delta = mshift(delta, o); coef = mshift(coef, o); }
     struct In {
         float d;
     };
@@ -462,6 +468,7 @@ struct EpiAdjCoef {  // c = 1 + dt/2 (delta_a + delta (1 + dt delta_a)), delta_a
 };
 struct EpiVec3 {  // three fields (stride N): out_c = I[src_c]
     static constexpr int NF = 3;
+    __device__ void shift(long long o) { src = mshift(src, o); dst = mshift(dst, o); }
     using In = NoIn;
     const float *src;
     float *dst;
@@ -485,6 +492,7 @@ struct EpiVec3 {  // three fields (stride N): out_c = I[src_c]
 template <int NTC>
 struct EpiIncSrc {
     static constexpr int NF = 3;
+    __device__ void shift(long long o) { vt = mshift(vt, o); GX = mshift(GX, o); G = mshift(G, o); mt1 = mshift(mt1, o); src = mshift(src, o); }
     struct In {
         float v[3], gx[NTC > 0 ? NTC : 1][3], g1[NTC > 0 ? NTC : 1][3];
     };
@@ -545,6 +553,7 @@ struct EpiIncSrc {
 template <int NTC>
 struct EpiAdjBody {
     static constexpr int NF = 1;
+    __device__ void shift(long long o) { src = mshift(src, o); coef = mshift(coef, o); lam0 = mshift(lam0, o); lam = mshift(lam, o); lamN = mshift(lamN, o); G = mshift(G, o); b = mshift(b, o); }
     struct In {
         float c, lam[NTC > 0 ? NTC : 1], g[NTC > 0 ? NTC + 1 : 1][3];  // lam[j-1] = lam_j, j = 1 .. N_t
     };
@@ -699,8 +708,9 @@ struct TileBox {
 
 template <int T1, int T2>
 __global__ __launch_bounds__(256) void k_tile_boxes(Grid3 g, const float *__restrict__ disp, TileBox *__restrict__ out,
-                                                    int nt2, int nt3)
+                                                    int nt2, int nt3, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); disp = mshift(disp, mo_); out = mshift(out, mo_);
     __shared__ int red[4][6];
     const int tid = threadIdx.x, lane = tid & 63;
     // the wavefront index, wave-uniform: the compiler keeps what derives from
@@ -725,8 +735,9 @@ __global__ __launch_bounds__(256) void k_tile_boxes(Grid3 g, const float *__rest
 // boxes != nullptr: the extents come from k_tile_boxes for this displacement field
 template <int T1, int T2, class Epi>
 __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ disp, Epi epi, int nt2, int nt3,
-                                             const TileBox *__restrict__ boxes)
+                                             const TileBox *__restrict__ boxes, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); disp = mshift(disp, mo_); boxes = mshift(boxes, mo_); epi.shift(mo_);
     using BC = BoxCfg<T1, T2>;
     constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, NF = Epi::NF;
     constexpr int S1 = BR2 * kPad3;  // box stride along x1 (x2: kPad3)
@@ -871,8 +882,9 @@ __device__ __forceinline__ double predictor_disp(const float *__restrict__ v, lo
 template <int T1, int T2>
 __global__ __launch_bounds__(256) void k_departure_box(const float *__restrict__ v, float *__restrict__ dX,
                                                        float *__restrict__ dXa, Grid3 g, int nt2, int nt3, double dt,
-                                                       double ih1, double ih2, double ih3)
+                                                       double ih1, double ih2, double ih3, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); v = mshift(v, mo_); dX = mshift(dX, mo_); dXa = mshift(dXa, mo_);
     using BC = BoxCfg<T1, T2>;
     constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2;
     constexpr int S1 = BR2 * kPad3;
@@ -1002,8 +1014,9 @@ __global__ __launch_bounds__(256) void k_departure_box(const float *__restrict__
 // one wait and one barrier per tile.  Same stencil sums, bitwise, as k_box.
 template <int T1, int T2, class Epi>
 __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restrict__ disp, Epi epi, int nt2,
-                                                  int nt3, const TileBox *__restrict__ boxes, int ntiles)
+                                                  int nt3, const TileBox *__restrict__ boxes, int ntiles, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); disp = mshift(disp, mo_); boxes = mshift(boxes, mo_); epi.shift(mo_);
     static_assert(Epi::NF == 1, "one field");
     using BC = BoxCfg<T1, T2>;
     constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, CAP = BC::CAP;
@@ -1146,8 +1159,9 @@ __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restri
 
 // direct gathers, one thread per point, stencil loads from L1/L2
 template <class Epi>
-__global__ __launch_bounds__(kPtThreads) void k_direct(Grid3 g, const float *__restrict__ disp, Epi epi)
+__global__ __launch_bounds__(kPtThreads) void k_direct(Grid3 g, const float *__restrict__ disp, Epi epi, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); disp = mshift(disp, mo_); epi.shift(mo_);
     const int p = point_index();
     if (p >= g.N) return;
     int i, j, k;
@@ -1163,8 +1177,9 @@ __global__ __launch_bounds__(kPtThreads) void k_direct(Grid3 g, const float *__r
 
 // trilinear gathers (LDDMM_FLAG_LINEAR_IP): eight nodes per point from L1/L2
 template <class Epi>
-__global__ __launch_bounds__(kPtThreads) void k_direct_lin(Grid3 g, const float *__restrict__ disp, Epi epi)
+__global__ __launch_bounds__(kPtThreads) void k_direct_lin(Grid3 g, const float *__restrict__ disp, Epi epi, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.y); disp = mshift(disp, mo_); epi.shift(mo_);
     const int p = point_index();
     if (p >= g.N) return;
     int i, j, k;
@@ -1222,8 +1237,9 @@ __device__ __forceinline__ float fd8_at(const float *__restrict__ f, int n1, int
 
 __global__ __launch_bounds__(256) void k_fd8_grad(const float *__restrict__ f, float *__restrict__ g1,
                                                   float *__restrict__ g2, float *__restrict__ g3, int n1, int n2,
-                                                  int n3, float ih1, float ih2, float ih3)
+                                                  int n3, float ih1, float ih2, float ih3, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.z); f = mshift(f, mo_); g1 = mshift(g1, mo_); g2 = mshift(g2, mo_); g3 = mshift(g3, mo_);
     const int nkt = (n3 + 63) / 64;
     const int kt = (int)blockIdx.x % nkt, jt = (int)blockIdx.x / nkt, i = (int)blockIdx.y;
     const int k = kt * 64 + (int)(threadIdx.x & 63), j = jt * 4 + (int)(threadIdx.x >> 6);
@@ -1235,8 +1251,9 @@ __global__ __launch_bounds__(256) void k_fd8_grad(const float *__restrict__ f, f
 }
 
 __global__ __launch_bounds__(256) void k_fd8_div(const float *__restrict__ v, float *__restrict__ out, int n1,
-                                                 int n2, int n3, long N, float ih1, float ih2, float ih3)
+                                                 int n2, int n3, long N, float ih1, float ih2, float ih3, Mb mb)
 {
+    const long long mo_ = mb.offset(blockIdx.z); v = mshift(v, mo_); out = mshift(out, mo_);
     const int nkt = (n3 + 63) / 64;
     const int kt = (int)blockIdx.x % nkt, jt = (int)blockIdx.x / nkt, i = (int)blockIdx.y;
     const int k = kt * 64 + (int)(threadIdx.x & 63), j = jt * 4 + (int)(threadIdx.x >> 6);
@@ -1266,20 +1283,20 @@ static Grid3 grid_of(const lddmm_plan *P)
 
 static dim3 blocks_of(const lddmm_plan *P)
 {
-    return dim3((unsigned)((P->N + kPtThreads - 1) / kPtThreads));
+    return dim3((unsigned)((P->N + kPtThreads - 1) / kPtThreads), (unsigned)P->mb.count);
 }
 
 static dim3 fd8_grid(const lddmm_plan *P)
 {
     const int n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
-    return dim3((unsigned)(((n3 + 63) / 64) * ((n2 + 3) / 4)), (unsigned)n1);
+    return dim3((unsigned)(((n3 + 63) / 64) * ((n2 + 3) / 4)), (unsigned)n1, (unsigned)P->mb.count);
 }
 
 void launch_fd8_grad(lddmm_plan *P, const float *f, float *g1, float *g2, float *g3)
 {
     Scope s(P, K_FD8);
     hipLaunchKernelGGL(k_fd8_grad, fd8_grid(P), dim3(256), 0, P->stream, f, g1, g2, g3, P->cfg.n[0], P->cfg.n[1],
-                       P->cfg.n[2], (float)(1.0 / P->h[0]), (float)(1.0 / P->h[1]), (float)(1.0 / P->h[2]));
+                       P->cfg.n[2], (float)(1.0 / P->h[0]), (float)(1.0 / P->h[1]), (float)(1.0 / P->h[2]), P->mb);
     check_hip(hipGetLastError(), "k_fd8_grad");
 }
 
@@ -1287,7 +1304,7 @@ void launch_fd8_div(lddmm_plan *P, const float *v, float *out)
 {
     Scope s(P, K_FD8);
     hipLaunchKernelGGL(k_fd8_div, fd8_grid(P), dim3(256), 0, P->stream, v, out, P->cfg.n[0], P->cfg.n[1],
-                       P->cfg.n[2], P->N, (float)(1.0 / P->h[0]), (float)(1.0 / P->h[1]), (float)(1.0 / P->h[2]));
+                       P->cfg.n[2], P->N, (float)(1.0 / P->h[0]), (float)(1.0 / P->h[1]), (float)(1.0 / P->h[2]), P->mb);
     check_hip(hipGetLastError(), "k_fd8_div");
 }
 
@@ -1312,8 +1329,8 @@ static void launch_departure_box(lddmm_plan *P, const float *v, float *dX, float
     int nt2, nt3;
     const unsigned ntiles = tiles_of<T1, T2>(P, nt2, nt3);
     const size_t lds = sizeof(float) * BoxCfg<T1, T2>::CAP;
-    hipLaunchKernelGGL((k_departure_box<T1, T2>), dim3(ntiles), dim3(256), lds, P->stream, v, dX, dXa, grid_of(P),
-                       nt2, nt3, P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2]);
+    hipLaunchKernelGGL((k_departure_box<T1, T2>), dim3(ntiles, P->mb.count), dim3(256), lds, P->stream, v, dX, dXa, grid_of(P),
+                       nt2, nt3, P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2], P->mb);
     check_hip(hipGetLastError(), "k_departure_box");
 }
 
@@ -1322,14 +1339,14 @@ void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa)
     Scope s(P, K_DEPARTURE);
     if (linear_ip(P)) {
         hipLaunchKernelGGL(k_departure<1>, blocks_of(P), dim3(kPtThreads), 0, P->stream, v, dX, dXa, grid_of(P),
-                           P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2]);
+                           P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2], P->mb);
         check_hip(hipGetLastError(), "k_departure");
         return;  // the trilinear gathers stage no boxes
     }
     switch (departure_mode(P)) {
     case 0:
         hipLaunchKernelGGL(k_departure<3>, blocks_of(P), dim3(kPtThreads), 0, P->stream, v, dX, dXa, grid_of(P),
-                           P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2]);
+                           P->dt, 1.0 / P->h[0], 1.0 / P->h[1], 1.0 / P->h[2], P->mb);
         check_hip(hipGetLastError(), "k_departure");
         break;
     case 1: launch_departure_box<2, 4>(P, v, dX, dXa); break;
@@ -1345,7 +1362,8 @@ void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa)
 // the chip, else 2x4
 static int gather_mode(const lddmm_plan *P)
 {
-    if (P->gather_mode >= 0) return P->gather_mode;
+    // a batched plan walks its members' tiles with one workgroup per tile
+    if (P->gather_mode >= 0) return P->mb.count > 1 && P->gather_mode >= 3 ? P->gather_mode - 2 : P->gather_mode;
     const long n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
     const long tiles = ((n1 + 3) / 4) * ((n2 + 3) / 4) * ((n3 + kT3 - 1) / kT3);
     return tiles >= 4096 ? 2 : 1;
@@ -1381,8 +1399,8 @@ static void launch_box(lddmm_plan *P, const float *disp, const Epi &epi, int kid
     const size_t lds = sizeof(float) * BoxCfg<T1, T2>::CAP;
     static_assert(sizeof(float) * BoxCfg<4, 4>::CAP <= 64 * 1024, "box exceeds the default LDS limit");
     Scope s(P, kid);
-    hipLaunchKernelGGL((k_box<T1, T2, Epi>), dim3(ntiles), dim3(256), lds, P->stream, grid_of(P), disp, epi, nt2,
-                       nt3, boxes_for<T1, T2>(P, disp));
+    hipLaunchKernelGGL((k_box<T1, T2, Epi>), dim3(ntiles, P->mb.count), dim3(256), lds, P->stream, grid_of(P), disp, epi, nt2,
+                       nt3, boxes_for<T1, T2>(P, disp), P->mb);
     check_hip(hipGetLastError(), "k_box");
 }
 
@@ -1425,8 +1443,8 @@ static void launch_box_pipe1(lddmm_plan *P, const float *disp, const Epi &epi, i
     }
     const unsigned nb = std::min((unsigned)grid, ntiles);
     Scope s(P, kid);
-    hipLaunchKernelGGL((k_box_pipe<T1, T2, Epi>), dim3(nb), dim3(256), lds, P->stream, grid_of(P), disp, epi, nt2,
-                       nt3, bx, (int)ntiles);
+    hipLaunchKernelGGL((k_box_pipe<T1, T2, Epi>), dim3(nb, P->mb.count), dim3(256), lds, P->stream, grid_of(P), disp, epi, nt2,
+                       nt3, bx, (int)ntiles, P->mb);
     check_hip(hipGetLastError(), "k_box_pipe");
 }
 
@@ -1457,11 +1475,11 @@ void launch_tile_boxes(lddmm_plan *P)
     for (int f = 0; f < 2; ++f) {
         const float *disp = f == 0 ? P->dX : P->dXa;
         unsigned nb = tiles_of<2, 4>(P, nt2, nt3);
-        hipLaunchKernelGGL((k_tile_boxes<2, 4>), dim3(nb), dim3(256), 0, P->stream, grid_of(P), disp,
-                           (TileBox *)P->boxes[f][0], nt2, nt3);
+        hipLaunchKernelGGL((k_tile_boxes<2, 4>), dim3(nb, P->mb.count), dim3(256), 0, P->stream, grid_of(P), disp,
+                           (TileBox *)P->boxes[f][0], nt2, nt3, P->mb);
         nb = tiles_of<4, 4>(P, nt2, nt3);
-        hipLaunchKernelGGL((k_tile_boxes<4, 4>), dim3(nb), dim3(256), 0, P->stream, grid_of(P), disp,
-                           (TileBox *)P->boxes[f][1], nt2, nt3);
+        hipLaunchKernelGGL((k_tile_boxes<4, 4>), dim3(nb, P->mb.count), dim3(256), 0, P->stream, grid_of(P), disp,
+                           (TileBox *)P->boxes[f][1], nt2, nt3, P->mb);
     }
     check_hip(hipGetLastError(), "k_tile_boxes");
     P->boxes_valid = 1;
@@ -1472,7 +1490,7 @@ static void tiled(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
 {
     if (linear_ip(P)) {
         Scope s(P, kid);
-        hipLaunchKernelGGL((k_direct_lin<Epi>), blocks_of(P), dim3(kPtThreads), 0, P->stream, grid_of(P), disp, epi);
+        hipLaunchKernelGGL((k_direct_lin<Epi>), blocks_of(P), dim3(kPtThreads), 0, P->stream, grid_of(P), disp, epi, P->mb);
         check_hip(hipGetLastError(), "k_direct_lin");
         return;
     }
@@ -1480,7 +1498,7 @@ static void tiled(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
     switch (mode) {
     case 0: {
         Scope s(P, kid);
-        hipLaunchKernelGGL((k_direct<Epi>), blocks_of(P), dim3(kPtThreads), 0, P->stream, grid_of(P), disp, epi);
+        hipLaunchKernelGGL((k_direct<Epi>), blocks_of(P), dim3(kPtThreads), 0, P->stream, grid_of(P), disp, epi, P->mb);
         check_hip(hipGetLastError(), "k_direct");
         break;
     }
@@ -1630,10 +1648,10 @@ void launch_body_force(lddmm_plan *P, const float *lam, const float *lamN, float
 {
     Scope s(P, K_BODY_FORCE);
     const long N4 = P->N / 4;
-    const dim3 grid((unsigned)((N4 + kPtThreads - 1) / kPtThreads));
+    const dim3 grid((unsigned)((N4 + kPtThreads - 1) / kPtThreads), (unsigned)P->mb.count);
 #define BODY(NTC)                                                                                              \
     hipLaunchKernelGGL((k_body_force<NTC>), grid, dim3(kPtThreads), 0, P->stream, (const float4 *)lam,          \
-                       (const float4 *)lamN, scaleN, (const float4 *)G, (float4 *)b, N4, P->nt, (float)P->dt)
+                       (const float4 *)lamN, scaleN, (const float4 *)G, (float4 *)b, N4, P->nt, (float)P->dt, P->mb)
     switch (P->nt) {
     case 4: BODY(4); break;
     case 8: BODY(8); break;

@@ -105,3 +105,55 @@ def test_batch_graph_follows_set_beta():
             say(f"  iteration {it} beta {beta} member {b}: rel {e:.2e}")
             assert e < 1e-6, (it, b)
     Bt.close()
+
+
+@pytest.mark.timeout(900)
+def test_batch_64_uneven_members_match_plain_and_oracle():
+    """The batched workload: 64 registrations with grid sizes drawn from
+    {64, 96, 128, 160}^3, N_t = 4, H2 beta = 1e-3, 5 Gauss-Newton iterations
+    of 8 PCG iterations each (rtol 1e-30: every member runs all 8).  Each
+    member's final velocity equals its plain per-plan run; four members (the
+    64^3 ones first in the draw) against the FP64 oracle's five iterations."""
+    rng = np.random.default_rng(4000)
+    sizes = [int(x) for x in rng.choice([64, 96, 128, 160], size=64)]
+    shapes = [(n, n, n) for n in sizes]
+    say(f"64-member batch: sizes {dict((n, sizes.count(n)) for n in (64, 96, 128, 160))}")
+    m0s, m1s, host = [], [], []
+    for b, s in enumerate(shapes):
+        m0 = synth.f32(synth.blob_image(s, 40, 4000 + 10 * b))
+        m1 = synth.f32(synth.blob_image(s, 40, 4000 + 10 * b + 2))
+        m0s.append(to_dev(m0))
+        m1s.append(to_dev(m1))
+        host.append((m0, m1))
+    GN, PCG, TOL = 5, 8, 1e-30
+    Bt = Batch(shapes, 4, reg=2, beta=1e-3, nstreams=4)
+    vb = [torch.zeros((3,) + s, device=DEV) for s in shapes]
+    Bt.set_images(m0s, m1s)
+    Bt.set_velocity(vb)
+    for _ in range(GN):
+        infos = Bt.gn_iterate(vb, PCG, TOL, use_graph=True)
+        assert all(i["pcg_iters"] == PCG for i in infos)
+    Bt.close()
+    worst = 0.0
+    for b, s in enumerate(shapes):
+        P = Plan(s, 4, reg=2, beta=1e-3)
+        P.set_images(m0s[b], m1s[b])
+        v = torch.zeros((3,) + s, device=DEV)
+        P.set_velocity(v)
+        for _ in range(GN):
+            P.gn_iterate(v, PCG, TOL)
+        e = rel(to_np(vb[b]), to_np(v))
+        worst = max(worst, e)
+        P.close()
+    say(f"  batch vs plain, worst member rel {worst:.2e}")
+    assert worst <= 1e-5
+    small = [b for b, n in enumerate(sizes) if n == 64][:4]
+    for b in small:
+        ref = oracle.Problem(shapes[b], 4, reg=2, beta=1e-3)
+        ref.set_images(synth.f64(host[b][0]), synth.f64(host[b][1]))
+        ref.set_velocity(np.zeros((3,) + shapes[b]))
+        for _ in range(GN):
+            v_ref, _ = ref.gn_iterate(PCG, TOL)
+        e = rel(to_np(vb[b]), v_ref)
+        say(f"  member {b} ({sizes[b]}^3) vs oracle after {GN} iterations: rel {e:.2e}")
+        assert e < 1e-5
