@@ -620,14 +620,16 @@ __global__ __launch_bounds__(RB * M / 8) void k_r2c_reg(RealIn in, char *__restr
                                                  const typename CplxOf<R>::type *__restrict__ tw_n, Mb mb)
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
-    const long long mo_ = mb.offset(blockIdx.z / zc_); for (int c_ = 0; c_ < 8; ++c_) in.p[c_] = mshift(in.p[c_], mo_); spec = mshift(spec, mo_);
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     using C = typename CplxOf<R>::type;
     using S = RowShape<M, RB>;
     constexpr int R0 = S::P::radix(0), RL = S::P::radix(S::NP - 1);
     extern __shared__ char lds_raw[];
     C *X = reinterpret_cast<C *>(lds_raw);
     const int f = blockIdx.y;
-    const float2 *__restrict__ src = reinterpret_cast<const float2 *>(in.p[f]);
+    // the kernel-argument array is indexed by f and never copied (a copy
+    // indexed at run time would live in scratch memory)
+    const float2 *__restrict__ src = reinterpret_cast<const float2 *>(mshift(in.p[f], mo_));
     const long row0 = (long)blockIdx.x * S::RB;
     C v[8];
 #pragma unroll
@@ -675,7 +677,7 @@ __global__ __launch_bounds__(RB * M / 8) void k_c2r_reg(const char *__restrict__
                                                  const float2 *__restrict__ tw_n, float scale, Mb mb)
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
-    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_); for (int c_ = 0; c_ < 8; ++c_) out.p[c_] = mshift(out.p[c_], mo_);
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     using S = RowShape<M, RB>;
     constexpr int RA = S::P::radix(S::NP - 1), R1 = S::P::radix(0);  // first and last inverse radices
     extern __shared__ char lds_raw[];
@@ -707,7 +709,7 @@ __global__ __launch_bounds__(RB * M / 8) void k_c2r_reg(const char *__restrict__
         }
     }
     rw_run<M, RB, false, true, 0, 1>(v, X, tw_m);
-    float *__restrict__ dst = out.p[f];
+    float *__restrict__ dst = mshift(out.p[f], mo_);
 #pragma unroll
     for (int t = 0; t < 8 / R1; ++t) {
         const long row = row0 + rw_line<M, RB, R1>(t);
@@ -732,7 +734,7 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, char *__restr
                                                         const typename CplxOf<R>::type *__restrict__ tw_n3, Mb mb)
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
-    const long long mo_ = mb.offset(blockIdx.z / zc_); for (int c_ = 0; c_ < 8; ++c_) in.p[c_] = mshift(in.p[c_], mo_); spec = mshift(spec, mo_);
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     using C = typename CplxOf<R>::type;
     extern __shared__ char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
@@ -740,7 +742,7 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, char *__restr
     const int m3 = n3 >> 1, LP = m3 + 1;
     C *A = lds, *B = lds + TWR * LP;
     const int f = blockIdx.y;
-    const float *__restrict__ src = in.p[f];
+    const float *__restrict__ src = mshift(in.p[f], mo_);
     const long row0 = (long)blockIdx.x * TWR;
     const int tid = threadIdx.x, nthr = kFftThreads;
     R *Af = reinterpret_cast<R *>(A);
@@ -781,7 +783,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const char *__restrict__
                                                         const float2 *__restrict__ tw_n3, float scale, Mb mb)
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
-    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_); for (int c_ = 0; c_ < 8; ++c_) out.p[c_] = mshift(out.p[c_], mo_);
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
     extern __shared__ char lds_raw[];
     float2 *lds = reinterpret_cast<float2 *>(lds_raw);
     const int n3 = LF > 0 ? 2 * LF : n3_rt;
@@ -810,7 +812,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const char *__restrict__
     }
     __syncthreads();
     const float2 *z = lds_fft_any<true, false, LF>(A, B, TWR, 0, LP, rp, tw_m3, tid, nthr);
-    float *__restrict__ dst = out.p[f];
+    float *__restrict__ dst = mshift(out.p[f], mo_);
     for (int idx = tid; idx < TWR * m3; idx += nthr) {
         const int c = idx / m3, n = idx - c * m3;
         const long row = row0 + c;

@@ -733,11 +733,18 @@ __global__ __launch_bounds__(256) void k_tile_boxes(Grid3 g, const float *__rest
 }
 
 // boxes != nullptr: the extents come from k_tile_boxes for this displacement field
-template <int T1, int T2, class Epi>
+// MB: a batched plan (the member from blockIdx.y); plain plans run the
+// kernel without the member shift
+template <int T1, int T2, class Epi, bool MB>
 __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ disp, Epi epi, int nt2, int nt3,
                                              const TileBox *__restrict__ boxes, Mb mb)
 {
-    const long long mo_ = mb.offset(blockIdx.y); disp = mshift(disp, mo_); boxes = mshift(boxes, mo_); epi.shift(mo_);
+    if constexpr (MB) {
+        const long long mo_ = mb.offset(blockIdx.y);
+        disp = mshift(disp, mo_);
+        boxes = mshift(boxes, mo_);
+        epi.shift(mo_);
+    }
     using BC = BoxCfg<T1, T2>;
     constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, NF = Epi::NF;
     constexpr int S1 = BR2 * kPad3;  // box stride along x1 (x2: kPad3)
@@ -1399,8 +1406,12 @@ static void launch_box(lddmm_plan *P, const float *disp, const Epi &epi, int kid
     const size_t lds = sizeof(float) * BoxCfg<T1, T2>::CAP;
     static_assert(sizeof(float) * BoxCfg<4, 4>::CAP <= 64 * 1024, "box exceeds the default LDS limit");
     Scope s(P, kid);
-    hipLaunchKernelGGL((k_box<T1, T2, Epi>), dim3(ntiles, P->mb.count), dim3(256), lds, P->stream, grid_of(P), disp, epi, nt2,
-                       nt3, boxes_for<T1, T2>(P, disp), P->mb);
+    if (P->mb.count > 1)
+        hipLaunchKernelGGL((k_box<T1, T2, Epi, true>), dim3(ntiles, P->mb.count), dim3(256), lds, P->stream,
+                           grid_of(P), disp, epi, nt2, nt3, boxes_for<T1, T2>(P, disp), P->mb);
+    else
+        hipLaunchKernelGGL((k_box<T1, T2, Epi, false>), dim3(ntiles), dim3(256), lds, P->stream, grid_of(P), disp,
+                           epi, nt2, nt3, boxes_for<T1, T2>(P, disp), P->mb);
     check_hip(hipGetLastError(), "k_box");
 }
 
