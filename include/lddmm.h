@@ -245,7 +245,15 @@ lddmm_status lddmm_interp(lddmm_plan *plan, int32_t nfields, const float *fields
  * last PCG of lddmm_newton_step / lddmm_gn_iterate left (after k iterations
  * without a stop: r_k, z_k and p_k = z_k + beta_k p_{k-1}, the state from
  * which iteration k + 1 starts; Algorithm "GNK" solves eq. "iter" with it);
- * unspecified before the first Newton step.
+ * unspecified before the first Newton step.  With the InvA preconditioner
+ * the PCG keeps r and p as spectra (see below): r and z are then returned as
+ * their FP32 inverse transforms, p as the physical field the transport
+ * sweeps of the next matvec read.
+ * LDDMM_FIELD_PCG_R_HAT, _PCG_P_HAT (3 n1 n2 (n3/2 + 1) complex values,
+ * interleaved FP32, i.e. 6 n1 n2 (n3/2 + 1) floats): the spectra of r and p
+ * themselves, in the standard half-spectrum layout [c][k1][k2][k3], k3 <= n3/2,
+ * unnormalised (the forward DFT, sum_x f(x) e^{-i k.x}); ESTATE when the last
+ * PCG ran in physical space (InvH0, 2LInvH0) or none has run.
  * After lddmm_transport_forward or lddmm_transport_vjp (e.g. on a
  * transport-only plan) the displacements are available, and after a VJP
  * also div v, the adjoint lam_j of that sweep (final value grad_m1) and, when
@@ -254,7 +262,7 @@ lddmm_status lddmm_interp(lddmm_plan *plan, int32_t nfields, const float *fields
 enum { LDDMM_FIELD_DISP = 1, LDDMM_FIELD_DISP_ADJ = 2, LDDMM_FIELD_STATE = 3,
        LDDMM_FIELD_GRAD_STATE = 4, LDDMM_FIELD_DIV = 5, LDDMM_FIELD_INC_STATE = 6,
        LDDMM_FIELD_ADJOINT = 7, LDDMM_FIELD_PCG_R = 8, LDDMM_FIELD_PCG_Z = 9,
-       LDDMM_FIELD_PCG_P = 10 };
+       LDDMM_FIELD_PCG_P = 10, LDDMM_FIELD_PCG_R_HAT = 11, LDDMM_FIELD_PCG_P_HAT = 12 };
 lddmm_status lddmm_get_field(lddmm_plan *plan, int32_t what, int32_t j, float *out);
 
 /* ---- batched form --------------------------------------------------------- */

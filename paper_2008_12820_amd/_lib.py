@@ -16,7 +16,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOTCONV, EUNSUPPORTED = range(7)
 REG_H1S, REG_H2S = 1, 2
 OP_GRAD, OP_DIV, OP_REG, OP_INVREG, OP_LERAY = 1, 2, 3, 4, 5
 FIELD_DISP, FIELD_DISP_ADJ, FIELD_STATE, FIELD_GRAD_STATE, FIELD_DIV, FIELD_INC_STATE, \
-    FIELD_ADJOINT, FIELD_PCG_R, FIELD_PCG_Z, FIELD_PCG_P = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
+    FIELD_ADJOINT, FIELD_PCG_R, FIELD_PCG_Z, FIELD_PCG_P, FIELD_PCG_R_HAT, FIELD_PCG_P_HAT = \
+    1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12
 
 
 FLAG_TRANSPORT_ONLY = 1

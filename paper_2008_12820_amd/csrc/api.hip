@@ -145,9 +145,12 @@ static Layout make_layout(const lddmm_config *cfg)
     L.add(3 * f);                          // 13 b
     L.add(3 * f);                          // 14 tmp3
     L.add(full * 3 * f);                   // 15 g
-    for (int i = 0; i < 6; ++i) L.add(full * 3 * f);  // 16..21 pcg x r z p q vt
+    // 16..21 PCG x r z p q, Newton step vt; r, z and q also hold the spectra r^,
+    // p^ and (H p)^ of the spectral-domain loop, so they take either size
+    const size_t rzq = std::max(3 * f, 3 * spec);
+    for (int i = 0; i < 6; ++i) L.add(full * ((i == 1 || i == 2 || i == 4) ? rzq : 3 * f));
     L.add(spectral_slots(cfg) * 2 * spec);  // 22 spec (slots sized for FP64)
-    L.add(sizeof(double) * kRedBlocks);     // 23 red
+    L.add(sizeof(double) * 2 * kRedBlocks);  // 23 red (two sets of partials)
     L.add(sizeof(double) * 2 * kNumScalars);  // 24 dscal (two banks)
     L.add(2 * tile_boxes_bytes(cfg->n));     // 25 stencil extents per gather tile (dX, dXa)
     L.add(sizeof(double) * kHistMax);       // 26 PCG residual history
@@ -351,15 +354,17 @@ static double gradient_impl(lddmm_plan *P, float *g)
     return gn;
 }
 
-void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
+// The transport sweeps of the matvec (eqs. incsta, incadj, matvec): the
+// incremental state from vt, the incremental adjoint and the body force into
+// P->b; after_start() runs once the incremental-state start is enqueued.
+template <class F>
+static void matvec_sweeps(lddmm_plan *P, const float *vt, F &&after_start)
 {
     const long N = P->N;
     const int nt = P->nt;
     float *mt[2] = {P->mt, P->mt + N};
     launch_incstate_init(P, vt, mt[0]);
-    // forked after the start gather, which streams at full bandwidth: the
-    // transform then shares the device with the issue-bound gather steps
-    const bool started = assemble_prefetch(P, vt, hvt);
+    after_start();
     for (int j = 1; j < nt; ++j)
         launch_incstate_step(P, mt[(j - 1) & 1], P->src + (long)(j - 1) * N, mt[j & 1]);
     const float *mtN = mt[(nt - 1) & 1];
@@ -371,7 +376,26 @@ void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
         for (int j = nt - 2; j >= 1; --j) launch_adj_step(P, lam + (long)(j + 1) * N, lam + (long)j * N, 1.f);
         launch_adj_body(P, lam + N, 1.f, lam, lam, mtN, -1.f);
     }
+}
+
+void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
+{
+    bool started = false;
+    // the transform of vt is forked after the start gather, which streams at
+    // full bandwidth: it then shares the device with the issue-bound steps
+    matvec_sweeps(P, vt, [&] { started = assemble_prefetch(P, vt, hvt); });
     assemble(P, vt, P->b, hvt, started);
+    P->have_matvec = 1;
+}
+
+// H p for the spectral-domain PCG: p in physical space (the transport
+// sweeps) and as its spectrum ph (the beta A p term); the result stays in
+// the spectral domain (qh) and <p, H p> goes to S_KAPPA
+static void matvec_spectral(lddmm_plan *P, const float *p, const float2 *ph, float2 *qh)
+{
+    matvec_sweeps(P, p, [] {});
+    spec_forward3(P, P->b, 0);
+    spcg_assemble(P, 0, ph, qh, S_KAPPA);
     P->have_matvec = 1;
 }
 
@@ -589,6 +613,55 @@ static void precondition(lddmm_plan *P, const float *r, float *z, double tol_out
         inv_reg(P, r, z);
 }
 
+// the spectra of the spectral-domain PCG live in the physical loop's r and z
+// buffers (sized for either): r^ in r, p^ in z, (H p)^ in q
+static float2 *spec_r(lddmm_plan *P) { return reinterpret_cast<float2 *>(P->pr); }
+static float2 *spec_p(lddmm_plan *P) { return reinterpret_cast<float2 *>(P->pz); }
+
+// PCG on H x = sign * rhs, x0 = 0, M^{-1} = (beta A)^{-1}, with r, p and H p
+// kept as spectra: the iteration, its scalars and its predicated stop are
+// those of the physical-space loop below; the preconditioner and beta A p
+// are pointwise in k, and each iteration transforms the body force forward
+// and the new search direction back.  x stays in physical space.  poll: the
+// lagged stop test; NULL enqueues max_it iterations, those after a stop
+// predicated off.  Slot S_RTOL must hold the tolerance.
+static void spcg_run(lddmm_plan *P, const float *rhs, float sign, int max_it, float *x, StopPoll *poll)
+{
+    const long M = 3 * P->N;
+    float2 *rh = spec_r(P), *ph = spec_p(P), *qh = reinterpret_cast<float2 *>(P->pq);
+    // transform slots: the forward transforms (rhs, body force) and the copy
+    // of p that its inverse transform consumes
+    constexpr int kFwd = 0, kInv = 3;
+    float *p = P->pp;
+    P->pcg_spectral = 1;
+    spec_forward3(P, rhs, kFwd);
+    spcg_start(P, kFwd, sign, rh, ph, kInv, S_RR, S_RZ);
+    dev_pcg_init(P);
+    spec_inverse3(P, kInv, p);
+    fill(P, M, 0.f, x);
+    for (int it = 0; it < max_it; ++it) {
+        matvec_spectral(P, p, ph, qh);
+        dev_pcg_alpha(P);
+        dev_pcg_x(P, M, p, x);
+        dev_copy_if(P, M, p, x);  // curvature stop at the first iteration: x = p0 = M^{-1} r0
+        spcg_r(P, rh, qh, S_RR, S_RZN);
+        dev_pcg_conv(P);
+        if (it < kHistMax) dev_store_scalar(P, S_REL, P->hist + it);
+        dev_pcg_beta(P);
+        spcg_p(P, rh, ph, kInv);
+        spec_inverse3(P, kInv, p);
+        if (poll && poll->after(it)) break;  // iteration it is queued, predicated off
+    }
+}
+
+static int pcg_finish(lddmm_plan *P, lddmm_newton_info &info);
+
+// the last PCG on this plan (or, for a batch member, on its group) kept r and p as spectra
+static bool spectral_pcg_state(const lddmm_plan *P)
+{
+    return P->pr && (P->pcg_spectral || (P->view_of && P->view_of->pcg_spectral));
+}
+
 // Preconditioned CG on H x = rhs, x0 = 0, M^{-1} = (beta A)^{-1} or the InvH0
 // / 2LInvH0 inner solve, every scalar on the device (bank 0): iteration k is
 // enqueued before the host reads the stop flag of iteration k - 1, so the
@@ -602,6 +675,11 @@ static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, fl
     float *r = P->pr, *z = P->pz, *p = P->pp, *q = P->pq;
     StopPoll poll(P, P->ev_poll, P->hscal + kNumScalars);
     dev_set_scalar(P, S_RTOL, rtol);
+    if (P->pc_kind == 0) {
+        spcg_run(P, rhs, 1.f, max_it, x, &poll);
+        return pcg_finish(P, info);
+    }
+    P->pcg_spectral = 0;
     copy_kernel(P, M, rhs, r);
     fill(P, M, 0.f, x);
     dot_async(P, r, r, M, S_RR, P->h3);
@@ -624,6 +702,12 @@ static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, fl
         dev_pcg_p(P, M, z, p);
         if (poll.after(it)) break;  // iteration it is queued, predicated off
     }
+    return pcg_finish(P, info);
+}
+
+// the PCG's outcome from the device scalars (synchronises the stream)
+static int pcg_finish(lddmm_plan *P, lddmm_newton_info &info)
+{
     check_hip(hipMemcpyAsync(P->hscal, P->dscal, sizeof(double) * kNumScalars, hipMemcpyDeviceToHost, P->stream),
               "scalar copy");
     check_hip(hipStreamSynchronize(P->stream), "stream sync");
@@ -663,28 +747,7 @@ static void objective_impl(lddmm_plan *P, double &J, double &mis, double &reg)
 // g must hold the gradient and slot S_RTOL the tolerance.
 void pcg_enqueue(lddmm_plan *P, const float *g, int max_it, float *x)
 {
-    const long M = 3 * P->N;
-    float *r = P->pr, *z = P->pz, *p = P->pp, *q = P->pq;
-    axpby(P, M, -1.f, g, 0.f, nullptr, r);
-    fill(P, M, 0.f, x);
-    dot_async(P, r, r, M, S_RR, P->h3);
-    dev_pcg_init(P);
-    inv_reg(P, r, z);
-    copy_dev(P, p, z, M);
-    dot_async(P, r, z, M, S_RZ, P->h3);
-    for (int it = 0; it < max_it; ++it) {
-        matvec_impl(P, p, q);
-        dot_async(P, p, q, M, S_KAPPA, P->h3);
-        dev_pcg_alpha(P);
-        dev_pcg_xr(P, M, p, q, x, r);
-        dev_copy_if(P, M, z, x);
-        dot_async(P, r, r, M, S_RR, P->h3);
-        dev_pcg_conv(P);
-        inv_reg(P, r, z);
-        dot_async(P, r, z, M, S_RZN, P->h3);
-        dev_pcg_beta(P);
-        dev_pcg_p(P, M, z, p);
-    }
+    spcg_run(P, g, -1.f, max_it, x, nullptr);
 }
 
 // One Gauss-Newton iteration up to and including the first line-search
@@ -1305,9 +1368,24 @@ lddmm_status lddmm_get_field(lddmm_plan *P, int32_t what, int32_t j, float *out)
             if (!P->have_matvec) fail(LDDMM_ESTATE, "no matvec has been computed");
             copy_dev(P, out, P->mt + (long)((nt - 1) & 1) * N, N);
             break;
-        case LDDMM_FIELD_PCG_R: copy_dev(P, out, P->pr, 3 * N); break;
-        case LDDMM_FIELD_PCG_Z: copy_dev(P, out, P->pz, 3 * N); break;
+        case LDDMM_FIELD_PCG_R:
+        case LDDMM_FIELD_PCG_Z:
+            if (spectral_pcg_state(P)) {  // the inverse transforms of r and M^{-1} r
+                spec_copy3(P, spec_r(P), 0, what == LDDMM_FIELD_PCG_Z);
+                spec_inverse3(P, 0, out);
+            } else {
+                copy_dev(P, out, what == LDDMM_FIELD_PCG_R ? P->pr : P->pz, 3 * N);
+            }
+            break;
         case LDDMM_FIELD_PCG_P: copy_dev(P, out, P->pp, 3 * N); break;
+        case LDDMM_FIELD_PCG_R_HAT:
+        case LDDMM_FIELD_PCG_P_HAT: {
+            if (!spectral_pcg_state(P)) fail(LDDMM_ESTATE, "the last PCG kept no spectra");
+            const long per = (long)P->cfg.n[0] * P->cfg.n[1] * (P->cfg.n[2] / 2 + 1);
+            spec_copy3(P, what == LDDMM_FIELD_PCG_P_HAT ? spec_p(P) : spec_r(P), 0, false);
+            for (int c = 0; c < 3; ++c) pack_standard(P, c, reinterpret_cast<float2 *>(out) + c * per);
+            break;
+        }
         case LDDMM_FIELD_ADJOINT:
             if (!P->have_grad && !P->have_matvec && !(tmap && P->have_vjp))
                 fail(LDDMM_ESTATE, "no adjoint has been computed");

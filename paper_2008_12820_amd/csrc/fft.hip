@@ -2411,4 +2411,336 @@ void unpack_standard(lddmm_plan *P, const float2 *srcp, int slot)
     check_hip(hipGetLastError(), "k_unpack_standard");
 }
 
+// ---------------------------------------------------------------------------
+// Spectral-domain PCG vectors (Algorithm "GNK" with the preconditioner
+// (beta A)^{-1}).  The residual r, the search direction p and H p are kept as
+// FP32 spectra in the internal layout, unnormalised (F f, the forward
+// transform without 1/N): the preconditioner and the beta A part of the
+// Hessian are then pointwise in k, and an iteration transforms only the body
+// force forward and the search direction back (for the transport sweeps),
+// instead of five transform passes of the physical-space loop.  Inner
+// products follow from Parseval's identity over the half spectrum:
+//   sum_x a b = (1/N) sum_k w_k Re(conj(F a)_k (F b)_k),
+// w = 1 on the planes k3 = 0 and k3 = n3/2, w = 2 elsewhere.
+// ---------------------------------------------------------------------------
+struct SpecIdx {
+    unsigned nmain;  // n1 n2 m3 entries of the main array, then the Nyquist plane
+    unsigned m3, n2;
+    // spectral indices and Hermitian weight of entry e of a field
+    __device__ __forceinline__ void at(unsigned e, int &l1, int &l2, int &l3, double &w) const
+    {
+        unsigned row;
+        if (e < nmain) {
+            row = e / m3;
+            l3 = (int)(e - row * m3);
+            w = l3 == 0 ? 1.0 : 2.0;
+        } else {
+            row = e - nmain;
+            l3 = (int)m3;
+            w = 1.0;
+        }
+        l1 = (int)(row / n2);
+        l2 = (int)(row - (unsigned)l1 * n2);
+    }
+};
+
+// (beta A)^{-1} symbol, as the InvA operator forms it (1/beta where A vanishes)
+__device__ __forceinline__ float invreg_factor(const SymCtx &sc, int l1, int l2, int l3)
+{
+    const double a = reg_symbol(sc, l1, l2, l3);
+    return (float)((a == 0.0) ? 1.0 / sc.beta : 1.0 / (sc.beta * a));
+}
+
+// deterministic sums of two values over a 256-thread workgroup (fixed tree);
+// the totals land in thread 0
+__device__ __forceinline__ void block_sum2(double &a, double &b)
+{
+    __shared__ double sa[256], sb[256];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sa[threadIdx.x] += sa[threadIdx.x + s];
+            sb[threadIdx.x] += sb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    a = sa[0];
+    b = sb[0];
+}
+
+#define SPEC_LOOP(S)                                                                                  \
+    for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < (unsigned)(S); e += gridDim.x * blockDim.x)
+
+// q = K b + beta A p (K: the Leray projection when LERAY, else the identity;
+// b the forward transform of the body force in transform slots, bstride
+// float2 apart) and the partial sums of <p, q> (one per workgroup)
+template <bool LERAY>
+__global__ __launch_bounds__(256) void k_spec_assemble(const float2 *__restrict__ b, long bstride,
+                                                       const float2 *__restrict__ p, float2 *__restrict__ q, long S,
+                                                       SpecIdx ix, SymCtx sc, double *__restrict__ partial, Mb mb)
+{
+    const long long mo_ = mb.offset(blockIdx.y);
+    b = mshift(b, mo_); p = mshift(p, mo_); q = mshift(q, mo_); partial = mshift(partial, mo_);
+    double acc = 0.0, unused = 0.0;
+    SPEC_LOOP(S)
+    {
+        int l1, l2, l3;
+        double w;
+        ix.at(e, l1, l2, l3, w);
+        float2 o[3] = {b[e], b[bstride + e], b[2 * bstride + e]};
+        if constexpr (LERAY) {
+            // the order of the fused assembly: s = sum_q (k_q / |k|^2) b_q,
+            // then b_q - k_q s, in FP32 (|k|^2 an exact integer)
+            const float ikk = leray_ikk(sc, l1, l2, l3);
+            const float k[3] = {(float)wn_odd(l1, sc.n1), (float)wn_odd(l2, sc.n2), (float)wn_odd(l3, sc.n3)};
+            float2 sd = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const float t = k[f] * ikk;
+                const float2 tb = make_float2(o[f].x * t, o[f].y * t);
+                sd = f == 0 ? tb : make_float2(sd.x + tb.x, sd.y + tb.y);
+            }
+#pragma unroll
+            for (int f = 0; f < 3; ++f) o[f] = make_float2(o[f].x - sd.x * k[f], o[f].y - sd.y * k[f]);
+        }
+        const double ba = sc.beta * reg_symbol(sc, l1, l2, l3);
+        double d = 0.0;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const float2 pv = p[f * S + e];
+            const float2 v = make_float2(o[f].x + (float)(pv.x * ba), o[f].y + (float)(pv.y * ba));
+            q[f * S + e] = v;
+            d += (double)pv.x * v.x + (double)pv.y * v.y;
+        }
+        acc += w * d;
+    }
+    block_sum2(acc, unused);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// PCG start from F(rhs) (sign * b, b in transform slots): r = sign b,
+// p = M^{-1} r, a copy of p into the transform slots c (cstride apart), and
+// the partial sums of <r, r> and <r, M^{-1} r> (partial, partial + gridDim.x)
+__global__ __launch_bounds__(256) void k_spcg_start(const float2 *__restrict__ b, long bstride, float sign,
+                                                    float2 *__restrict__ r, float2 *__restrict__ p,
+                                                    float2 *__restrict__ c, long cstride, long S, SpecIdx ix,
+                                                    SymCtx sc, double *__restrict__ partial, Mb mb)
+{
+    const long long mo_ = mb.offset(blockIdx.y);
+    b = mshift(b, mo_); r = mshift(r, mo_); p = mshift(p, mo_); c = mshift(c, mo_); partial = mshift(partial, mo_);
+    double arr = 0.0, arz = 0.0;
+    SPEC_LOOP(S)
+    {
+        int l1, l2, l3;
+        double w;
+        ix.at(e, l1, l2, l3, w);
+        const float m = invreg_factor(sc, l1, l2, l3);
+        double srr = 0.0, srz = 0.0;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const float2 bv = b[f * bstride + e];
+            const float2 rv = make_float2(sign * bv.x, sign * bv.y);
+            const float2 zv = make_float2(m * rv.x, m * rv.y);
+            r[f * S + e] = rv;
+            p[f * S + e] = zv;
+            c[f * cstride + e] = zv;
+            srr += (double)rv.x * rv.x + (double)rv.y * rv.y;
+            srz += (double)rv.x * zv.x + (double)rv.y * zv.y;
+        }
+        arr += w * srr;
+        arz += w * srz;
+    }
+    block_sum2(arr, arz);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = arr;
+        partial[gridDim.x + blockIdx.x] = arz;
+    }
+}
+
+// r -= alpha q (alpha from the device scalars d; r kept when alpha = 0, i.e.
+// after a stop), then the partial sums of <r, r> and <r, M^{-1} r>
+__global__ __launch_bounds__(256) void k_spcg_r(float2 *__restrict__ r, const float2 *__restrict__ q, long S,
+                                                SpecIdx ix, SymCtx sc, const double *__restrict__ d,
+                                                double *__restrict__ partial, Mb mb)
+{
+    const long long mo_ = mb.offset(blockIdx.y);
+    r = mshift(r, mo_); q = mshift(q, mo_); d = mshift(d, mo_); partial = mshift(partial, mo_);
+    const float al = (float)d[S_ALPHA];
+    double arr = 0.0, arz = 0.0;
+    SPEC_LOOP(S)
+    {
+        int l1, l2, l3;
+        double w;
+        ix.at(e, l1, l2, l3, w);
+        const float m = invreg_factor(sc, l1, l2, l3);
+        double srr = 0.0, srz = 0.0;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            float2 rv = r[f * S + e];
+            if (al != 0.f) {
+                const float2 qv = q[f * S + e];
+                rv = make_float2(__builtin_fmaf(-al, qv.x, rv.x), __builtin_fmaf(-al, qv.y, rv.y));
+                r[f * S + e] = rv;
+            }
+            const float2 zv = make_float2(m * rv.x, m * rv.y);
+            srr += (double)rv.x * rv.x + (double)rv.y * rv.y;
+            srz += (double)rv.x * zv.x + (double)rv.y * zv.y;
+        }
+        arr += w * srr;
+        arz += w * srz;
+    }
+    block_sum2(arr, arz);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = arr;
+        partial[gridDim.x + blockIdx.x] = arz;
+    }
+}
+
+// p = M^{-1} r + beta p (beta from the device scalars d; p kept once the PCG
+// has stopped), and a copy of p into the transform slots c
+__global__ __launch_bounds__(256) void k_spcg_p(const float2 *__restrict__ r, float2 *__restrict__ p,
+                                                float2 *__restrict__ c, long cstride, long S, SpecIdx ix,
+                                                SymCtx sc, const double *__restrict__ d, Mb mb)
+{
+    const long long mo_ = mb.offset(blockIdx.y);
+    r = mshift(r, mo_); p = mshift(p, mo_); c = mshift(c, mo_); d = mshift(d, mo_);
+    const bool upd = d[S_DONE] == 0.0;
+    const float be = (float)d[S_BETA];
+    SPEC_LOOP(S)
+    {
+        int l1, l2, l3;
+        double w;
+        ix.at(e, l1, l2, l3, w);
+        const float m = upd ? invreg_factor(sc, l1, l2, l3) : 0.f;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            float2 pv = p[f * S + e];
+            if (upd) {
+                const float2 rv = r[f * S + e];
+                const float2 zv = make_float2(m * rv.x, m * rv.y);
+                pv = make_float2(__builtin_fmaf(be, pv.x, zv.x), __builtin_fmaf(be, pv.y, zv.y));
+                p[f * S + e] = pv;
+            }
+            c[f * cstride + e] = pv;
+        }
+    }
+}
+// dst_f = src_f, or M^{-1} src_f (inv), for three spectra
+__global__ __launch_bounds__(256) void k_spec_copy3(const float2 *__restrict__ src, long sstride, float2 *__restrict__ dst,
+                                                    long dstride, long S, SpecIdx ix, SymCtx sc, int inv, Mb mb)
+{
+    const long long mo_ = mb.offset(blockIdx.y);
+    src = mshift(src, mo_); dst = mshift(dst, mo_);
+    SPEC_LOOP(S)
+    {
+        int l1, l2, l3;
+        double w;
+        ix.at(e, l1, l2, l3, w);
+        const float m = inv ? invreg_factor(sc, l1, l2, l3) : 1.f;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const float2 v = src[f * sstride + e];
+            dst[f * dstride + e] = inv ? make_float2(m * v.x, m * v.y) : v;
+        }
+    }
+}
+#undef SPEC_LOOP
+
+static SpecIdx spec_idx(const FftCtx &F)
+{
+    // 32-bit entry indices (with the grid stride added once past the end)
+    if (F.spec_stride >= (1L << 31)) fail(LDDMM_EINVAL, "spectral PCG: more than 2^31 coefficients per field");
+    SpecIdx ix;
+    ix.nmain = (unsigned)(F.nrow * F.m3);
+    ix.m3 = (unsigned)F.m3;
+    ix.n2 = (unsigned)F.n2;
+    return ix;
+}
+
+static float2 *slot_ptr(lddmm_plan *P, int slot) { return reinterpret_cast<float2 *>(P->spec + (long)slot * P->slot_bytes); }
+
+void spec_forward3(lddmm_plan *P, const float *in, int slot0)
+{
+    RealIn ri{};
+    for (int c = 0; c < 3; ++c) ri.p[c] = in + c * P->N;
+    r2c_fields(P, ri, 3, slot0, false);
+    x2_pass(P, slot0, 3, false, false);
+    x1_pass(P, slot0, 3, false, false);
+}
+
+void spec_inverse3(lddmm_plan *P, int slot0, float *out)
+{
+    x1_pass(P, slot0, 3, true, false);
+    x2_pass(P, slot0, 3, true, false);
+    RealOut ro{};
+    for (int c = 0; c < 3; ++c) ro.p[c] = out + c * P->N;
+    c2r_fields(P, slot0, 3, ro, (float)(1.0 / (double)P->N));
+}
+
+void spcg_assemble(lddmm_plan *P, int bslot, const float2 *p, float2 *q, int kslot)
+{
+    const FftCtx &F = P->fft;
+    const SymCtx sc = sym_ctx(P, P->cfg.leray);
+    {
+        Scope s(P, K_VECOP);
+        const dim3 g(kRedBlocks, P->mb.count);
+        if (sc.leray)
+            hipLaunchKernelGGL(k_spec_assemble<true>, g, dim3(256), 0, P->stream, slot_ptr(P, bslot), P->slot_bytes / 8, p,
+                               q, F.spec_stride, spec_idx(F), sc, P->red, P->mb);
+        else
+            hipLaunchKernelGGL(k_spec_assemble<false>, g, dim3(256), 0, P->stream, slot_ptr(P, bslot), P->slot_bytes / 8, p,
+                               q, F.spec_stride, spec_idx(F), sc, P->red, P->mb);
+        check_hip(hipGetLastError(), "k_spec_assemble");
+    }
+    dev_reduce_final(P, P->red, kslot, P->h3 / (double)P->N);
+}
+
+void spcg_start(lddmm_plan *P, int bslot, float sign, float2 *r, float2 *p, int cslot, int rr_slot, int rz_slot)
+{
+    const FftCtx &F = P->fft;
+    {
+        Scope s(P, K_VECOP);
+        hipLaunchKernelGGL(k_spcg_start, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, slot_ptr(P, bslot),
+                           P->slot_bytes / 8, sign, r, p, slot_ptr(P, cslot), P->slot_bytes / 8, F.spec_stride,
+                           spec_idx(F), sym_ctx(P, 0), P->red, P->mb);
+        check_hip(hipGetLastError(), "k_spcg_start");
+    }
+    dev_reduce_final(P, P->red, rr_slot, P->h3 / (double)P->N);
+    dev_reduce_final(P, P->red + kRedBlocks, rz_slot, P->h3 / (double)P->N);
+}
+
+void spcg_r(lddmm_plan *P, float2 *r, const float2 *q, int rr_slot, int rz_slot)
+{
+    const FftCtx &F = P->fft;
+    {
+        Scope s(P, K_VECOP);
+        hipLaunchKernelGGL(k_spcg_r, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, r, q, F.spec_stride,
+                           spec_idx(F), sym_ctx(P, 0), (const double *)scalars(P), P->red, P->mb);
+        check_hip(hipGetLastError(), "k_spcg_r");
+    }
+    dev_reduce_final(P, P->red, rr_slot, P->h3 / (double)P->N);
+    dev_reduce_final(P, P->red + kRedBlocks, rz_slot, P->h3 / (double)P->N);
+}
+
+void spcg_p(lddmm_plan *P, const float2 *r, float2 *p, int cslot)
+{
+    const FftCtx &F = P->fft;
+    Scope s(P, K_VECOP);
+    hipLaunchKernelGGL(k_spcg_p, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, r, p, slot_ptr(P, cslot),
+                       P->slot_bytes / 8, F.spec_stride, spec_idx(F), sym_ctx(P, 0), (const double *)scalars(P), P->mb);
+    check_hip(hipGetLastError(), "k_spcg_p");
+}
+
+void spec_copy3(lddmm_plan *P, const float2 *src, int dst_slot, bool inv)
+{
+    const FftCtx &F = P->fft;
+    Scope s(P, K_VECOP);
+    hipLaunchKernelGGL(k_spec_copy3, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, src, F.spec_stride,
+                       slot_ptr(P, dst_slot), P->slot_bytes / 8, F.spec_stride, spec_idx(F), sym_ctx(P, 0), inv ? 1 : 0,
+                       P->mb);
+    check_hip(hipGetLastError(), "k_spec_copy3");
+}
+
 }  // namespace lddmm

@@ -100,7 +100,8 @@ struct lddmm_plan {
     char *spec = nullptr;    // spectral scratch: nspec slots of slot_bytes (FP64-sized)
     long slot_bytes = 0;
     int nspec = 0;
-    double *red = nullptr;   // reduction partials
+    int pcg_spectral = 0;    // 1: the last PCG kept r and p as spectra (in pr and pz)
+    double *red = nullptr;   // reduction partials (two sets of kRedBlocks)
     double *hist = nullptr;  // ||r_k|| / ||r0|| per PCG iteration (device, kHistMax)
     std::vector<double> pcg_hist;  // the last PCG's history (host)
     double *dscal = nullptr; // device scalars, two banks of kNumScalars (see ScalarSlot)
@@ -185,6 +186,24 @@ std::string tuning_report(const lddmm_plan *P);
 // standard half-spectrum [n1][n2][n3/2+1] <-> internal layout
 void pack_standard(lddmm_plan *P, int spec_field, float2 *dst);
 void unpack_standard(lddmm_plan *P, const float2 *srcp, int spec_field);
+// spectral-domain PCG with M^{-1} = (beta A)^{-1}: FP32 spectra (internal
+// layout, unnormalised) of three fields, 3 * spec_stride float2 per vector.
+// three real fields (stride N) -> their spectra in slots [slot0, slot0 + 3)
+void spec_forward3(lddmm_plan *P, const float *in, int slot0);
+// spectra in slots [slot0, slot0 + 3) (overwritten) -> three real fields
+void spec_inverse3(lddmm_plan *P, int slot0, float *out);
+// q = K b + beta A p (b: the spectra in slots bslot..); <p, q> into scalar kslot
+void spcg_assemble(lddmm_plan *P, int bslot, const float2 *p, float2 *q, int kslot);
+// r = sign b (b in slots bslot..), p = M^{-1} r copied into slots cslot..;
+// <r, r> and <r, M^{-1} r> into scalars rr_slot, rz_slot
+void spcg_start(lddmm_plan *P, int bslot, float sign, float2 *r, float2 *p, int cslot, int rr_slot, int rz_slot);
+// r -= alpha q (device alpha); <r, r> and <r, M^{-1} r> into rr_slot, rz_slot
+void spcg_r(lddmm_plan *P, float2 *r, const float2 *q, int rr_slot, int rz_slot);
+// p = M^{-1} r + beta p (device beta, kept after a stop), copied into slots cslot..
+void spcg_p(lddmm_plan *P, const float2 *r, float2 *p, int cslot);
+// three spectra (3 * spec_stride float2 at src) into slots dst_slot..,
+// times M^{-1} when inv
+void spec_copy3(lddmm_plan *P, const float2 *src, int dst_slot, bool inv);
 
 // ---- transport.hip ----------------------------------------------------------
 void launch_departure(lddmm_plan *P, const float *v, float *dX, float *dXa);
@@ -261,6 +280,10 @@ void dev_pcg_init(lddmm_plan *P);
 void dev_pcg_alpha(lddmm_plan *P);
 void dev_pcg_xr(lddmm_plan *P, long n, const float *p, const float *q, float *x, float *r);
 void dev_copy_if(lddmm_plan *P, long n, const float *z, float *x);
+// x += alpha p with the device alpha (nothing when it is 0)
+void dev_pcg_x(lddmm_plan *P, long n, const float *p, float *x);
+// scalars(P)[slot] = scale * (sum of kRedBlocks partials)
+void dev_reduce_final(lddmm_plan *P, const double *partial, int slot, double scale);
 void dev_pcg_conv(lddmm_plan *P);
 void dev_pcg_beta(lddmm_plan *P);
 void dev_pcg_p(lddmm_plan *P, long n, const float *z, float *p);

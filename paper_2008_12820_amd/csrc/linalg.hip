@@ -249,6 +249,24 @@ __global__ void k_pcg_xr_dev(long n, int vec, const double *__restrict__ d, cons
     xr_update(n, vec, al, p, q, x, r);
 }
 
+// x += alpha p (alpha from the device scalars; nothing when it is 0)
+__global__ void k_pcg_x_dev(long n, int vec, const double *__restrict__ d, const float *__restrict__ p,
+                            float *__restrict__ x, Mb mb)
+{
+    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); p = mshift(p, mo_); x = mshift(x, mo_);
+    const float al = (float)d[S_ALPHA];
+    if (al == 0.f) return;
+    ew_loop(
+        n, vec,
+        [&](long i) {
+            float4 *x4 = (float4 *)x + i;
+            const float4 pv = ((const float4 *)p)[i], xv = *x4;
+            *x4 = make_float4(__builtin_fmaf(al, pv.x, xv.x), __builtin_fmaf(al, pv.y, xv.y),
+                              __builtin_fmaf(al, pv.z, xv.z), __builtin_fmaf(al, pv.w, xv.w));
+        },
+        [&](long i) { x[i] = __builtin_fmaf(al, p[i], x[i]); });
+}
+
 __global__ void k_copy_if(long n, int vec, const double *__restrict__ d, const float *__restrict__ z,
                           float *__restrict__ x, Mb mb)
 {
@@ -421,6 +439,23 @@ void dev_pcg_xr(lddmm_plan *P, long n, const float *p, const float *q, float *x,
     hipLaunchKernelGGL(k_pcg_xr_dev, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, scalars(P),
                        p, q, x, r, P->mb);
     check_hip(hipGetLastError(), "k_pcg_xr_dev");
+}
+
+void dev_pcg_x(lddmm_plan *P, long n, const float *p, float *x)
+{
+    Scope s(P, K_VECOP);
+    const int vec = vec_ok({p, x});
+    hipLaunchKernelGGL(k_pcg_x_dev, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, scalars(P),
+                       p, x, P->mb);
+    check_hip(hipGetLastError(), "k_pcg_x_dev");
+}
+
+void dev_reduce_final(lddmm_plan *P, const double *partial, int slot, double scale)
+{
+    Scope s(P, K_DOT);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1, P->mb.count), dim3(kRedThreads), 0, P->stream, partial, kRedBlocks,
+                       scalars(P) + slot, scale, P->mb);
+    check_hip(hipGetLastError(), "k_reduce_final");
 }
 
 void dev_copy_if(lddmm_plan *P, long n, const float *z, float *x)

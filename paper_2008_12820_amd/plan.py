@@ -176,6 +176,11 @@ class Plan:
         return out[0] if single else out
 
     def get_field(self, what, j=0):
+        if what in (L.FIELD_PCG_R_HAT, L.FIELD_PCG_P_HAT):  # three half spectra, complex64
+            n1, n2, n3 = self.shape
+            out = torch.empty((3, n1, n2, n3 // 2 + 1), device=self.device, dtype=torch.complex64)
+            L.lddmm_get_field(self._h, what, j, torch.view_as_real(out))
+            return out
         vec = what in (L.FIELD_DISP, L.FIELD_DISP_ADJ, L.FIELD_GRAD_STATE, L.FIELD_PCG_R, L.FIELD_PCG_Z,
                        L.FIELD_PCG_P)
         out = self._vector() if vec else self._scalar()
