@@ -390,12 +390,12 @@ void matvec_impl(lddmm_plan *P, const float *vt, float *hvt)
 
 // H p for the spectral-domain PCG: p in physical space (the transport
 // sweeps) and as its spectrum ph (the beta A p term); the result stays in
-// the spectral domain (qh) and <p, H p> goes to S_KAPPA
+// the spectral domain (qh), <p, H p> goes to S_KAPPA and alpha follows
 static void matvec_spectral(lddmm_plan *P, const float *p, const float2 *ph, float2 *qh)
 {
     matvec_sweeps(P, p, [] {});
     spec_forward3(P, P->b, 0);
-    spcg_assemble(P, 0, ph, qh, S_KAPPA);
+    spcg_assemble(P, 0, ph, qh, S_KAPPA, P->cfg.leray, kAfterAlpha);
     P->have_matvec = 1;
 }
 
@@ -432,10 +432,13 @@ struct Beta0Scope {
     ~Beta0Scope() { P->beta_sym = 0.0; }
 };
 
-static float *h0_vectors(lddmm_plan *P)
+// The vectors of the H0 solves, FP32 spectra of three fields each (see
+// spcg_run): [0] the solution (the outer PCG's M^{-1} r), [1] the inner
+// residual, [2] the inner search direction, [3] H0 p.  Allocated on first use.
+static float2 *h0_vectors(lddmm_plan *P)
 {
     if (!P->h0buf) {
-        const size_t bytes = sizeof(float) * 4 * 3 * (size_t)P->N;
+        const size_t bytes = sizeof(float2) * 4 * 3 * (size_t)P->fft.spec_stride;
         hipError_t e = hipMalloc((void **)&P->h0buf, bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -443,7 +446,7 @@ static float *h0_vectors(lddmm_plan *P)
             fail(LDDMM_ENOMEM, "InvH0 vectors of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
         }
     }
-    return P->h0buf;
+    return reinterpret_cast<float2 *>(P->h0buf);
 }
 
 // The stop test of a device-resident PCG loop: iteration k has been
@@ -479,49 +482,82 @@ struct BankScope {
     ~BankScope() { P->bank = keep; }
 };
 
-// s ~= H0^{-1} r: PCG on H0 s = r preconditioned by (beta0 A)^{-1}, from
-// s = (beta0 A)^{-1} r, until ||r - H0 s|| <= tol ||r||, max_it iterations or
-// <p, H0 p> <= 0; every scalar on the device (bank 1 of P), the stop test
-// lagged by one iteration.  outer (may be NULL): the bank-0 scalars of the
-// outer PCG this solve preconditions; the solve then does nothing once that
-// PCG has stopped and adds its iterations to the outer S_INNER.
-static void invh0_dev(lddmm_plan *P, const float *r, float *s, double tol, int max_it, double *outer)
+// the spectra of the spectral-domain PCG live in the r, z and q buffers of
+// the workspace (sized for a physical field or a spectrum): r^ in r, p^ in z,
+// (H p)^ in q
+static float2 *spec_r(lddmm_plan *P) { return reinterpret_cast<float2 *>(P->pr); }
+static float2 *spec_p(lddmm_plan *P) { return reinterpret_cast<float2 *>(P->pz); }
+
+// transform slots of the spectral PCG loops: the forward transforms (the
+// right-hand side, the body force, G (G . p)) and the copy of p its inverse
+// transform consumes
+constexpr int kSlotFwd = 0, kSlotInv = 3;
+
+// qh = H0 p for the spectrum ph of p: beta0 A p pointwise, the rank-one part
+// G (G . p) (G = grad m(1)) in physical space between an inverse and a
+// forward transform; with kappa, <p, H0 p> into S_KAPPA and alpha.  copied:
+// slots kSlotInv.. already hold ph
+static void h0_apply_spec(lddmm_plan *P, const float2 *ph, float2 *qh, bool kappa, bool copied)
 {
-    const long M = 3 * P->N;
-    float *w = h0_vectors(P);
-    float *ri = w, *zi = w + M, *pi = w + 2 * M, *qi = w + 3 * M;
+    const long N = P->N;
+    const float *G1 = P->G + (long)P->nt * 3 * N;
+    if (!copied) spec_copy3(P, ph, kSlotInv, false);
+    x1_pass(P, kSlotInv, 3, true, false);
+    x2_pass(P, kSlotInv, 3, true, false);
+    if (!x3_rank1(P, kSlotInv, kSlotFwd, G1)) {  // x3 lengths without a register plan
+        RealOut ro{};
+        RealIn ri{};
+        for (int c = 0; c < 3; ++c) {
+            ro.p[c] = P->tmp3 + c * N;
+            ri.p[c] = P->b + c * N;
+        }
+        c2r_fields(P, kSlotInv, 3, ro, (float)(1.0 / (double)N));
+        h0_rank1(P, P->tmp3, G1, P->b);  // b: free outside the matvec
+        r2c_fields(P, ri, 3, kSlotFwd, false);
+    }
+    x2_pass(P, kSlotFwd, 3, false, false);
+    x1_pass(P, kSlotFwd, 3, false, false);
+    spcg_assemble(P, kSlotFwd, ph, qh, kappa ? S_KAPPA : -1, 0, kappa ? kAfterAlpha : 0);
+}
+
+// sh ~= H0^{-1} rh (spectra): PCG on H0 s = r preconditioned by
+// (beta0 A)^{-1}, from s = (beta0 A)^{-1} r, until ||r - H0 s|| <= tol ||r||,
+// max_it iterations or <p, H0 p> <= 0; every scalar on the device (bank 1 of
+// P), the stop test lagged by one iteration; the vectors as spectra (the
+// preconditioner pointwise, one transform round trip per iteration for the
+// rank-one part).  outer (may be NULL): the bank-0 scalars of the outer PCG
+// this solve preconditions; the solve then does nothing once that PCG has
+// stopped and adds its iterations to the outer S_INNER.  rh and sh must not
+// be the inner vectors [1..3] of P.
+static void invh0_spec(lddmm_plan *P, const float2 *rh, float2 *sh, double tol, int max_it, double *outer)
+{
+    const long S3 = 3 * P->fft.spec_stride;
+    float2 *w = h0_vectors(P);
+    float2 *ri = w + S3, *pi = w + 2 * S3, *qi = w + 3 * S3;
     Beta0Scope b0(P);
     BankScope bk(P, 1);
     StopPoll poll(P, P->ev_inner, P->hscal + kNumScalars + 2);
     dev_set_scalar(P, S_RTOL, tol);
-    dot_async(P, r, r, M, S_RR, P->h3);
+    spec_dot(P, rh, rh, S_RR);
     dev_pcg_init(P);  // S_R0 = ||r||; stopped when r = 0
     if (outer) dev_inner_link(P, outer);
-    inv_reg(P, r, s);
-    h0_apply(P, s, qi);
-    axpby(P, M, 1.f, r, -1.f, qi, ri);
-    dot_async(P, ri, ri, M, S_RR, P->h3);
+    spec_invreg3(P, rh, sh);
+    h0_apply_spec(P, sh, qi, false, false);
+    axpby(P, 2 * S3, 1.f, (const float *)rh, -1.f, (const float *)qi, (float *)ri);
+    // <r, r> and <r, (beta0 A)^{-1} r> of the start residual, p = (beta0 A)^{-1} r
+    // (copied into the slots its inverse transform reads)
+    spcg_start(P, ri, P->fft.spec_stride, 1.f, nullptr, pi, kSlotInv, S_RR, S_RZ);
     dev_pcg_conv(P);  // the start may already meet the tolerance
-    inv_reg(P, ri, zi);
-    copy_kernel(P, M, zi, pi);
-    dot_async(P, ri, zi, M, S_RZ, P->h3);
     for (int it = 0; it < max_it; ++it) {
-        h0_apply(P, pi, qi);
-        dot_async(P, pi, qi, M, S_KAPPA, P->h3);
-        dev_pcg_alpha(P);
-        dev_pcg_xr(P, M, pi, qi, s, ri);
-        dot_async(P, ri, ri, M, S_RR, P->h3);
-        dev_pcg_conv(P);
-        inv_reg(P, ri, zi);
-        dot_async(P, ri, zi, M, S_RZN, P->h3);
-        dev_pcg_beta(P);
-        dev_pcg_p(P, M, zi, pi);
+        h0_apply_spec(P, pi, qi, true, true);                                  // kappa, alpha
+        spcg_r(P, ri, qi, sh, pi, S_RR, S_RZN, kAfterConv | kAfterBeta, nullptr);  // s, r; conv, beta
+        spcg_p(P, ri, nullptr, pi, kSlotInv);
         if (poll.after(it)) break;
     }
     if (outer) dev_inner_accum(P, outer);
 }
 
-// iterations of the last invh0_dev on P (synchronises the stream)
+// iterations of the last inner solve on P (synchronises the stream)
 static int inner_iterations(lddmm_plan *P)
 {
     BankScope bk(P, 1);
@@ -567,89 +603,103 @@ static void resample3(lddmm_plan *F, const float *in, lddmm_plan *C, float *out)
     c2r_fields(C, 0, 3, ro, (float)(1.0 / (double)C->N));
 }
 
-// s ~= 2LInvH0(r).  The paper's steps s_f = (b0 A)^{-1} r, s_c = R s_f, coarse
-// PCG on H0_c s_c = R r from s_c, s_f = P s_c + (s_f - P R s_f) are run as
-// s_f = (b0 A)^{-1} r + P (s_c - s_c0) with s_c0 = (b0 A_c)^{-1} R r, the same
-// coarse start: R and (b0 A)^{-1} commute (the same symbol at every kept
-// wavenumber), so R s_f = s_c0 and one fine restriction is saved.  The coarse
-// plan holds R grad m(1) in its grad m_{N_t} slot, refreshed per velocity.
-static void twolevel_dev(lddmm_plan *P, const float *r, float *s, double tol, int max_it, double *outer)
+// sh ~= 2LInvH0(rh), spectra.  The paper's steps s_f = (b0 A)^{-1} r,
+// s_c = R s_f, coarse PCG on H0_c s_c = R r from s_c, s_f = P s_c + (s_f -
+// P R s_f) are run as s_f = (b0 A)^{-1} r + P (s_c - s_c0) with s_c0 =
+// (b0 A_c)^{-1} R r, the same coarse start: R and (b0 A)^{-1} commute (the
+// same symbol at every kept wavenumber), so R s_f = s_c0.  On spectra the
+// restriction R and the prolongation P are coefficient copies (truncation,
+// zero padding).  The coarse plan holds R grad m(1) in its grad m_{N_t} slot,
+// refreshed per velocity.
+static void twolevel_spec(lddmm_plan *P, const float2 *rh, float2 *sh, double tol, int max_it, double *outer)
 {
     lddmm_plan *C = coarse_plan(P);
     // the half-grid H0 and (beta0 A_c)^{-1} take the fine plan's beta0: the
     // identity R (beta0 A)^{-1} = (beta0 A_c)^{-1} R used below needs one beta0
     C->cfg.beta = P->cfg.beta;
-    const long M = 3 * P->N, Mc = 3 * C->N;
     if (P->coarse_gen != P->vel_gen) {
         resample3(P, P->G + (long)P->nt * 3 * P->N, C, C->G + (long)C->nt * 3 * C->N);
         P->coarse_gen = P->vel_gen;
     }
-    float *rc = C->pr, *sc = C->px, *sc0 = C->pz;  // the half-grid plan runs no PCG of its own
-    float *tmp = h0_vectors(P);
+    const long S3c = 3 * C->fft.spec_stride;
+    // the half-grid plan runs no outer PCG of its own: its r, z, q buffers
+    // hold R r, s_c0 and s_c
+    float2 *rc = spec_r(C), *sc0 = spec_p(C), *sc = reinterpret_cast<float2 *>(C->pq);
+    float2 *tmp = h0_vectors(P) + 3 * P->fft.spec_stride;
     {
         Beta0Scope b0(P);
-        inv_reg(P, r, s);
+        spec_invreg3(P, rh, sh);
     }
-    resample3(P, r, C, rc);
+    spec_resample3(P, rh, C, rc);
     {
         Beta0Scope b0(C);
-        inv_reg(C, rc, sc0);
+        spec_invreg3(C, rc, sc0);
     }
-    invh0_dev(C, rc, sc, tol, max_it, outer);
-    axpby(C, Mc, 1.f, sc, -1.f, sc0, sc);
-    resample3(C, sc, P, tmp);
-    axpby(P, M, 1.f, s, 1.f, tmp, s);
+    invh0_spec(C, rc, sc, tol, max_it, outer);
+    axpby(C, 2 * S3c, 1.f, (const float *)sc, -1.f, (const float *)sc0, (float *)sc);
+    spec_resample3(C, sc, P, tmp);
+    axpby(P, 6 * P->fft.spec_stride, 1.f, (const float *)sh, 1.f, (const float *)tmp, (float *)sh);
 }
 
-// the preconditioner M^{-1} r of the outer PCG (tol_outer: its tolerance);
-// InvH0 and 2LInvH0 add their inner iterations to the outer S_INNER
-static void precondition(lddmm_plan *P, const float *r, float *z, double tol_outer)
+// zh = M^{-1} rh of the outer PCG for InvH0 / 2LInvH0 (tol_outer: its
+// tolerance); the inner iterations are added to the outer S_INNER
+static void precondition_spec(lddmm_plan *P, const float2 *rh, float2 *zh, double tol_outer)
 {
     if (P->pc_kind == 1)
-        invh0_dev(P, r, z, P->pc_eps_h0 * tol_outer, P->pc_max_inner, P->dscal);
-    else if (P->pc_kind == 2)
-        twolevel_dev(P, r, z, P->pc_eps_h0 * tol_outer, P->pc_max_inner, P->dscal);
+        invh0_spec(P, rh, zh, P->pc_eps_h0 * tol_outer, P->pc_max_inner, P->dscal);
     else
-        inv_reg(P, r, z);
+        twolevel_spec(P, rh, zh, P->pc_eps_h0 * tol_outer, P->pc_max_inner, P->dscal);
 }
 
-// the spectra of the spectral-domain PCG live in the physical loop's r and z
-// buffers (sized for either): r^ in r, p^ in z, (H p)^ in q
-static float2 *spec_r(lddmm_plan *P) { return reinterpret_cast<float2 *>(P->pr); }
-static float2 *spec_p(lddmm_plan *P) { return reinterpret_cast<float2 *>(P->pz); }
-
-// PCG on H x = sign * rhs, x0 = 0, M^{-1} = (beta A)^{-1}, with r, p and H p
-// kept as spectra: the iteration, its scalars and its predicated stop are
-// those of the physical-space loop below; the preconditioner and beta A p
-// are pointwise in k, and each iteration transforms the body force forward
-// and the new search direction back.  x stays in physical space.  poll: the
-// lagged stop test; NULL enqueues max_it iterations, those after a stop
+// PCG on H x = sign * rhs, x0 = 0, with r, p and H p kept as FP32 spectra
+// (internal layout, unnormalised) and x in physical space.  Iteration k:
+// kappa = <p, H p>, alpha = <r, z> / kappa, x += alpha p, r -= alpha q,
+// z = M^{-1} r, beta = <r, z>_new / <r, z>, p = z + beta p; the stop on
+// ||r|| <= rtol ||r0||, max_it iterations or kappa <= 0 (then x = M^{-1} r0
+// at the first iteration).  The inner products follow from Parseval's
+// identity over the half spectrum, in FP64.  With M^{-1} = (beta A)^{-1}
+// (InvA) the preconditioner is pointwise in k and fused into the updates;
+// InvH0 and 2LInvH0 run their inner solves on spectra too.  Each iteration
+// transforms the body force forward and the new p back (for the transport
+// sweeps of the next matvec).  Scalars on the device (bank 0); poll: the
+// lagged stop test, or NULL to enqueue max_it iterations, those after a stop
 // predicated off.  Slot S_RTOL must hold the tolerance.
-static void spcg_run(lddmm_plan *P, const float *rhs, float sign, int max_it, float *x, StopPoll *poll)
+static void spcg_run(lddmm_plan *P, const float *rhs, float sign, int max_it, float *x, StopPoll *poll, double rtol)
 {
     const long M = 3 * P->N;
     float2 *rh = spec_r(P), *ph = spec_p(P), *qh = reinterpret_cast<float2 *>(P->pq);
-    // transform slots: the forward transforms (rhs, body force) and the copy
-    // of p that its inverse transform consumes
-    constexpr int kFwd = 0, kInv = 3;
+    const bool inva = P->pc_kind == 0;
+    float2 *zh = inva ? nullptr : h0_vectors(P);
     float *p = P->pp;
     P->pcg_spectral = 1;
-    spec_forward3(P, rhs, kFwd);
-    spcg_start(P, kFwd, sign, rh, ph, kInv, S_RR, S_RZ);
-    dev_pcg_init(P);
-    spec_inverse3(P, kInv, p);
+    spec_forward3(P, rhs, kSlotFwd);
+    if (inva) {
+        spcg_start(P, spec_slot(P, kSlotFwd), P->slot_bytes / 8, sign, rh, ph, kSlotInv, S_RR, S_RZ);
+        dev_pcg_init(P);
+    } else {
+        spcg_start(P, spec_slot(P, kSlotFwd), P->slot_bytes / 8, sign, rh, nullptr, -1, S_RR, -1);
+        dev_pcg_init(P);
+        precondition_spec(P, rh, zh, rtol);
+        spec_dot(P, rh, zh, S_RZ);
+        copy_kernel(P, 6 * P->fft.spec_stride, (const float *)zh, (float *)ph);
+        spec_copy3(P, ph, kSlotInv, false);
+    }
+    spec_inverse3(P, kSlotInv, p);
     fill(P, M, 0.f, x);
     for (int it = 0; it < max_it; ++it) {
-        matvec_spectral(P, p, ph, qh);
-        dev_pcg_alpha(P);
-        dev_pcg_x(P, M, p, x);
-        dev_copy_if(P, M, p, x);  // curvature stop at the first iteration: x = p0 = M^{-1} r0
-        spcg_r(P, rh, qh, S_RR, S_RZN);
-        dev_pcg_conv(P);
-        if (it < kHistMax) dev_store_scalar(P, S_REL, P->hist + it);
-        dev_pcg_beta(P);
-        spcg_p(P, rh, ph, kInv);
-        spec_inverse3(P, kInv, p);
+        matvec_spectral(P, p, ph, qh);  // kappa, alpha
+        dev_pcg_x(P, M, p, x);          // (or x = p0 = M^{-1} r0 after a first-iteration curvature stop)
+        const int hist = it < kHistMax ? kAfterHist : 0;
+        double *hdst = hist ? P->hist + it : nullptr;
+        if (inva) {
+            spcg_r(P, rh, qh, nullptr, nullptr, S_RR, S_RZN, kAfterConv | hist | kAfterBeta, hdst);
+        } else {
+            spcg_r(P, rh, qh, nullptr, nullptr, S_RR, -1, kAfterConv | hist, hdst);
+            precondition_spec(P, rh, zh, rtol);
+            spec_dot(P, rh, zh, S_RZN, kAfterBeta);
+        }
+        spcg_p(P, rh, zh, ph, kSlotInv);
+        spec_inverse3(P, kSlotInv, p);
         if (poll && poll->after(it)) break;  // iteration it is queued, predicated off
     }
 }
@@ -662,46 +712,13 @@ static bool spectral_pcg_state(const lddmm_plan *P)
     return P->pr && (P->pcg_spectral || (P->view_of && P->view_of->pcg_spectral));
 }
 
-// Preconditioned CG on H x = rhs, x0 = 0, M^{-1} = (beta A)^{-1} or the InvH0
-// / 2LInvH0 inner solve, every scalar on the device (bank 0): iteration k is
-// enqueued before the host reads the stop flag of iteration k - 1, so the
-// stream never drains between iterations; after a stop the one iteration
-// already queued is predicated off (its matvec runs, its updates do not),
-// which gives the early exit of a host loop with the same arithmetic.
+// The PCG of the Newton step (spcg_run) with the host's lagged stop test.
 static int pcg_impl(lddmm_plan *P, const float *rhs, int max_it, double rtol, float *x,
                     lddmm_newton_info &info)
 {
-    const long M = 3 * P->N;
-    float *r = P->pr, *z = P->pz, *p = P->pp, *q = P->pq;
     StopPoll poll(P, P->ev_poll, P->hscal + kNumScalars);
     dev_set_scalar(P, S_RTOL, rtol);
-    if (P->pc_kind == 0) {
-        spcg_run(P, rhs, 1.f, max_it, x, &poll);
-        return pcg_finish(P, info);
-    }
-    P->pcg_spectral = 0;
-    copy_kernel(P, M, rhs, r);
-    fill(P, M, 0.f, x);
-    dot_async(P, r, r, M, S_RR, P->h3);
-    dev_pcg_init(P);
-    precondition(P, r, z, rtol);
-    copy_kernel(P, M, z, p);
-    dot_async(P, r, z, M, S_RZ, P->h3);
-    for (int it = 0; it < max_it; ++it) {
-        matvec_impl(P, p, q);
-        dot_async(P, p, q, M, S_KAPPA, P->h3);
-        dev_pcg_alpha(P);
-        dev_pcg_xr(P, M, p, q, x, r);
-        dev_copy_if(P, M, z, x);
-        dot_async(P, r, r, M, S_RR, P->h3);
-        dev_pcg_conv(P);
-        if (it < kHistMax) dev_store_scalar(P, S_REL, P->hist + it);
-        precondition(P, r, z, rtol);
-        dot_async(P, r, z, M, S_RZN, P->h3);
-        dev_pcg_beta(P);
-        dev_pcg_p(P, M, z, p);
-        if (poll.after(it)) break;  // iteration it is queued, predicated off
-    }
+    spcg_run(P, rhs, 1.f, max_it, x, &poll, rtol);
     return pcg_finish(P, info);
 }
 
@@ -747,7 +764,7 @@ static void objective_impl(lddmm_plan *P, double &J, double &mis, double &reg)
 // g must hold the gradient and slot S_RTOL the tolerance.
 void pcg_enqueue(lddmm_plan *P, const float *g, int max_it, float *x)
 {
-    spcg_run(P, g, -1.f, max_it, x, nullptr);
+    spcg_run(P, g, -1.f, max_it, x, nullptr, 0.0);
 }
 
 // One Gauss-Newton iteration up to and including the first line-search
@@ -1370,12 +1387,14 @@ lddmm_status lddmm_get_field(lddmm_plan *P, int32_t what, int32_t j, float *out)
             break;
         case LDDMM_FIELD_PCG_R:
         case LDDMM_FIELD_PCG_Z:
-            if (spectral_pcg_state(P)) {  // the inverse transforms of r and M^{-1} r
+            if (!spectral_pcg_state(P)) fail(LDDMM_ESTATE, "no PCG has run");
+            // the inverse transforms of r and M^{-1} r (InvA: pointwise; InvH0
+            // and 2LInvH0: the last inner solve's result)
+            if (what == LDDMM_FIELD_PCG_Z && P->pc_kind != 0)
+                spec_copy3(P, h0_vectors(P), 0, false);
+            else
                 spec_copy3(P, spec_r(P), 0, what == LDDMM_FIELD_PCG_Z);
-                spec_inverse3(P, 0, out);
-            } else {
-                copy_dev(P, out, what == LDDMM_FIELD_PCG_R ? P->pr : P->pz, 3 * N);
-            }
+            spec_inverse3(P, 0, out);
             break;
         case LDDMM_FIELD_PCG_P: copy_dev(P, out, P->pp, 3 * N); break;
         case LDDMM_FIELD_PCG_R_HAT:
@@ -1506,7 +1525,12 @@ lddmm_status lddmm_apply_invh0(lddmm_plan *P, const float *r, double tol, int32_
         if (!(tol >= 0.0) || max_inner < 0) fail(LDDMM_EINVAL, "tol must be >= 0 and max_inner >= 0");
         need_full(P);
         need_velocity(P);
-        invh0_dev(P, r, s, tol, max_inner, nullptr);
+        float2 *rh = reinterpret_cast<float2 *>(P->pq), *sh = h0_vectors(P);
+        spec_forward3(P, r, kSlotFwd);
+        spec_from_slots(P, kSlotFwd, rh);
+        invh0_spec(P, rh, sh, tol, max_inner, nullptr);
+        spec_copy3(P, sh, kSlotInv, false);
+        spec_inverse3(P, kSlotInv, s);
         const int it = inner_iterations(P);
         if (iters) *iters = it;
     });
@@ -1523,7 +1547,12 @@ lddmm_status lddmm_apply_2linvh0(lddmm_plan *P, const float *r, double tol, int3
         if (!halves(P->cfg)) fail(LDDMM_EINVAL, "2LInvH0 needs every grid size divisible by 4 and at least 16");
         need_full(P);
         need_velocity(P);
-        twolevel_dev(P, r, s, tol, max_inner, nullptr);
+        float2 *rh = reinterpret_cast<float2 *>(P->pq), *sh = h0_vectors(P);
+        spec_forward3(P, r, kSlotFwd);
+        spec_from_slots(P, kSlotFwd, rh);
+        twolevel_spec(P, rh, sh, tol, max_inner, nullptr);
+        spec_copy3(P, sh, kSlotInv, false);
+        spec_inverse3(P, kSlotInv, s);
         const int it = inner_iterations(coarse_plan(P));
         if (iters) *iters = it;
     });

@@ -723,6 +723,125 @@ __global__ __launch_bounds__(RB * M / 8) void k_c2r_reg(const char *__restrict__
     }
 }
 
+// The rank-one part of H0 (eq. h0-pc) along x3 rows: the spectra of p in
+// slots in0.. (three fields, after the inverse x1 and x2 passes) go back
+// along x3 as in k_c2r_reg (times scale), t = G (G . p) is formed per point
+// with G = grad m(1) (three physical fields, n3 = 2M floats per row), and t
+// goes forward along x3 as in k_r2c_reg (FP32) into slots out0..; p and t
+// never reach HBM.  The arithmetic of c2r, k_h0_rank1 and r2c in turn.
+template <int M, int RB>
+__global__ __launch_bounds__(RB * M / 8) void k_x3_rank1(char *__restrict__ spec, long slot_bytes, int in0, int out0,
+                                                  const float *__restrict__ G, long nrow,
+                                                  const float2 *__restrict__ tw_m, const float2 *__restrict__ tw_n,
+                                                  float scale, Mb mb)
+{
+    const long long mo_ = mb.offset(blockIdx.z);
+    spec = mshift(spec, mo_);
+    G = mshift(G, mo_);
+    using S = RowShape<M, RB>;
+    constexpr int RA = S::P::radix(S::NP - 1), R1 = S::P::radix(0);  // first and last inverse radices
+    constexpr int R0 = R1, RL = RA;                                   // first and last forward radices
+    extern __shared__ char lds_raw[];
+    float2 *X = reinterpret_cast<float2 *>(lds_raw);
+    const long row0 = (long)blockIdx.x * S::RB;
+    const long n3 = 2L * M, N = nrow * n3;
+    float2 pv[3][8];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        if (f > 0) __syncthreads();  // the exchange buffer is reused
+        const float2 *inm = reinterpret_cast<const float2 *>(spec + (long)(in0 + f) * slot_bytes);
+        const float2 *inq = inm + nrow * M;
+        for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += S::NT) {
+            const int c = idx / (M + 1), k = idx - c * (M + 1);
+            const long row = row0 + c;
+            float2 Xv = make_float2(0.f, 0.f);
+            if (row < nrow) Xv = (k < M) ? inm[row * M + k] : inq[row];
+            X[c * S::RPITCH + rw_slot(k)] = Xv;
+        }
+        __syncthreads();
+        float2 v[8];
+#pragma unroll
+        for (int t = 0; t < 8 / RA; ++t) {
+            const int c = rw_line<M, RB, RA>(t);
+#pragma unroll
+            for (int r = 0; r < RA; ++r) {
+                const int k = rw_but<M, RB, RA>(t) + r * (M / RA);
+                const float2 Xk = X[c * S::RPITCH + rw_slot(k)];
+                const float2 Xc = conj_(X[c * S::RPITCH + rw_slot(M - k)]);
+                const float2 E = add(Xk, Xc);
+                const float2 O = mulc(sub(Xk, Xc), tw_n[k]);
+                v[t * RA + r] = add(E, muli(O));
+            }
+        }
+        rw_run<M, RB, false, true, 0, 1>(v, X, tw_m);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) pv[f][i] = make_float2(v[i].x * scale, v[i].y * scale);
+    }
+    // t = G (G . p) at the points this thread holds (x3 = 2e, 2e + 1 of its rows)
+#pragma unroll
+    for (int t = 0; t < 8 / R1; ++t) {
+        const long row = row0 + rw_line<M, RB, R1>(t);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int i = t * R1 + r;
+            if (row >= nrow) {
+                pv[0][i] = pv[1][i] = pv[2][i] = make_float2(0.f, 0.f);
+                continue;
+            }
+            const long o = row * n3 + 2 * rw_out_elem<M, RB, R1, M / R1>(t, r);
+            const float2 g0 = *reinterpret_cast<const float2 *>(G + o), g1 = *reinterpret_cast<const float2 *>(G + N + o),
+                         g2 = *reinterpret_cast<const float2 *>(G + 2 * N + o);
+            const float dx = g0.x * pv[0][i].x + g1.x * pv[1][i].x + g2.x * pv[2][i].x;
+            const float dy = g0.y * pv[0][i].y + g1.y * pv[1][i].y + g2.y * pv[2][i].y;
+            pv[0][i] = make_float2(g0.x * dx, g0.y * dy);
+            pv[1][i] = make_float2(g1.x * dx, g1.y * dy);
+            pv[2][i] = make_float2(g2.x * dx, g2.y * dy);
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        // t to LDS in natural order, then the forward pass's own distribution
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 8 / R1; ++t)
+#pragma unroll
+            for (int r = 0; r < R1; ++r)
+                X[rw_line<M, RB, R1>(t) * S::RPITCH + rw_slot(rw_out_elem<M, RB, R1, M / R1>(t, r))] = pv[f][t * R1 + r];
+        __syncthreads();
+        float2 v[8];
+#pragma unroll
+        for (int t = 0; t < 8 / R0; ++t)
+#pragma unroll
+            for (int r = 0; r < R0; ++r)
+                v[t * R0 + r] = X[rw_line<M, RB, R0>(t) * S::RPITCH + rw_slot(rw_but<M, RB, R0>(t) + r * (M / R0))];
+        rw_run<M, RB, true, false, 0, 1>(v, X, tw_m);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 8 / RL; ++t)
+#pragma unroll
+            for (int r = 0; r < RL; ++r)
+                X[rw_line<M, RB, RL>(t) * S::RPITCH + rw_slot(rw_out_elem<M, RB, RL, M / RL>(t, r))] = v[t * RL + r];
+        __syncthreads();
+        float2 *outm = reinterpret_cast<float2 *>(spec + (long)(out0 + f) * slot_bytes);
+        float2 *outq = outm + nrow * M;
+        for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += S::NT) {
+            const int c = idx / (M + 1), k = idx - c * (M + 1);
+            const long row = row0 + c;
+            if (row >= nrow) continue;
+            const float2 zk = X[c * S::RPITCH + rw_slot(k == M ? 0 : k)];
+            const float2 zc = conj_(X[c * S::RPITCH + rw_slot(k == 0 ? 0 : M - k)]);
+            const float2 E = scl(add(zk, zc), 0.5f);
+            const float2 D = scl(sub(zk, zc), 0.5f);
+            const float2 O = mk<float2>(D.y, -D.x);  // D / i
+            const float2 Xk = add(E, mul(tw_n[k], O));
+            if (k < M)
+                outm[row * M + k] = Xk;
+            else
+                outq[row] = Xk;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // x3 pass: real rows -> half spectrum (main + Nyquist plane), computed in R
 // ---------------------------------------------------------------------------
@@ -1061,7 +1180,11 @@ __device__ __forceinline__ void st_inv(C *v, C *X, StoreF &&store, const C *__re
 
 // Column pass with register line FFTs (lengths with a RegPlan)
 template <bool INV, class R, int L>
-__global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long slot_bytes, int slot0, ColDesc d,
+// Both parts of the spectrum in one launch: the tiles of the main array
+// (gx0 x outer0, descriptor d0) and then those of the Nyquist plane (gx1,
+// descriptor d1) along a one-dimensional grid, in the XCD order of tile_pos.
+__global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long slot_bytes, int slot0, ColDesc d0,
+                                                  ColDesc d1, int gx0, int outer0,
                                                   const typename CplxOf<R>::type *__restrict__ tw, Mb mb)
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
@@ -1070,7 +1193,11 @@ __global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long 
     using S = RegShape<L>;
     extern __shared__ char lds_raw[];
     C *X = reinterpret_cast<C *>(lds_raw);
-    const TilePos tp = tile_pos();
+    const TilePos lp = tile_pos();  // gridDim.y = 1: lp.x is the linear tile index
+    const int t0 = gx0 * outer0;
+    const bool nyq = lp.x >= t0;
+    const ColDesc &d = nyq ? d1 : d0;
+    const TilePos tp = nyq ? TilePos{lp.x - t0, 0} : TilePos{lp.x % gx0, lp.x / gx0};
     C *base = reinterpret_cast<C *>(spec + (long)(slot0 + bz_) * slot_bytes) + d.base_off +
               (long)tp.y * d.ostride;
     const int col0 = tp.x * S::TW;
@@ -1854,6 +1981,33 @@ void c2r_fields(lddmm_plan *P, int slot0, int count, const RealOut &out, float s
     check_hip(hipGetLastError(), "k_c2r_x3");
 }
 
+bool x3_rank1(lddmm_plan *P, int in0, int out0, const float *G)
+{
+    FftCtx &F = P->fft;
+    bool done = false;
+    with_len(F.m3, [&]<int LF>() {
+        if constexpr (RowPlan<LF>::ok) {
+            auto go = [&]<int RB>() {
+                using RS = RowShape<LF, RB>;
+                const size_t lds = sizeof(float2) * RS::XCH;
+                check_lds(lds, "x3_rank1");
+                if (lds > 65536) allow_big_lds((const void *)(k_x3_rank1<LF, RB>));
+                const dim3 gr((unsigned)((F.nrow + RB - 1) / RB), 1, P->mb.count);
+                Scope s(P, K_C2R_X3);
+                hipLaunchKernelGGL((k_x3_rank1<LF, RB>), gr, dim3(RS::NT), lds, P->stream, P->spec, P->slot_bytes, in0,
+                                   out0, G, F.nrow, F.tw3, F.twN3, (float)(1.0 / (double)P->N), P->mb);
+            };
+            if (F.twr_c2r >= RowPlan<LF>::RBA)
+                go.template operator()<RowPlan<LF>::RBA>();
+            else
+                go.template operator()<RowPlan<LF>::RBB>();
+            done = true;
+        }
+    });
+    if (done) check_hip(hipGetLastError(), "k_x3_rank1");
+    return done;
+}
+
 // column descriptors: main array and Nyquist plane, along x2 (axis 1) or x1 (axis 0)
 static void col_descs(const FftCtx &F, int axis, ColDesc dd[2], int outer[2])
 {
@@ -1886,33 +2040,37 @@ static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool invers
         bool done = false;
         with_len(rp.L, [&]<int LF>() {
             if constexpr (RegPlan<LF>::ok) {
+                // both parts in one launch (only_part selects one for the autotuner)
                 using RS = RegShape<LF>;
-                dim3 grid((unsigned)((d.ncols + RS::TW - 1) / RS::TW), outer[part], count);
+                const int g0 = (dd[0].ncols + RS::TW - 1) / RS::TW, g1 = (dd[1].ncols + RS::TW - 1) / RS::TW;
+                const int o0 = (only_part == 1) ? 0 : outer[0];
+                const unsigned tiles = (unsigned)(g0 * o0 + (only_part == 0 ? 0 : g1));
+                const dim3 grid(tiles, 1, count);
                 const size_t lds = cs * RS::XCH;
                 check_lds(lds, "fft_cols");
                 if (dbl) {
                     const double2 *tw = axis == 1 ? F.tw2d : F.tw1d;
                     if (inverse)
                         FFT_LAUNCH((k_cols_reg<true, double, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, d, tw, P->mb);
+                                   slot0, dd[0], dd[1], g0, o0, tw, P->mb);
                     else
                         FFT_LAUNCH((k_cols_reg<false, double, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, d, tw, P->mb);
+                                   slot0, dd[0], dd[1], g0, o0, tw, P->mb);
                 } else {
                     const float2 *tw = axis == 1 ? F.tw2 : F.tw1;
                     if (inverse)
                         FFT_LAUNCH((k_cols_reg<true, float, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, d, tw, P->mb);
+                                   slot0, dd[0], dd[1], g0, o0, tw, P->mb);
                     else
                         FFT_LAUNCH((k_cols_reg<false, float, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, d, tw, P->mb);
+                                   slot0, dd[0], dd[1], g0, o0, tw, P->mb);
                 }
                 done = true;
             }
         });
         if (done) {
             check_hip(hipGetLastError(), "k_cols_reg");
-            continue;
+            break;  // both parts launched
         }
         const int TW = F.tw_cols[axis == 1 ? 1 : 0][part][dbl ? 1 : 0];
         const size_t lds = 2 * cs * rp.L * TW;
@@ -2412,14 +2570,13 @@ void unpack_standard(lddmm_plan *P, const float2 *srcp, int slot)
 }
 
 // ---------------------------------------------------------------------------
-// Spectral-domain PCG vectors (Algorithm "GNK" with the preconditioner
-// (beta A)^{-1}).  The residual r, the search direction p and H p are kept as
-// FP32 spectra in the internal layout, unnormalised (F f, the forward
-// transform without 1/N): the preconditioner and the beta A part of the
-// Hessian are then pointwise in k, and an iteration transforms only the body
-// force forward and the search direction back (for the transport sweeps),
-// instead of five transform passes of the physical-space loop.  Inner
-// products follow from Parseval's identity over the half spectrum:
+// Spectral-domain PCG vectors (Algorithm "GNK").  The PCG keeps its residual
+// r, search direction p and H p as FP32 spectra in the internal layout,
+// unnormalised (F f, the forward transform without 1/N): the preconditioner
+// (beta A)^{-1} and the beta A part of the Hessian are then pointwise in k,
+// and an iteration transforms only the body force forward and the search
+// direction back (for the transport sweeps).  Inner products follow from
+// Parseval's identity over the half spectrum:
 //   sum_x a b = (1/N) sum_k w_k Re(conj(F a)_k (F b)_k),
 // w = 1 on the planes k3 = 0 and k3 = n3/2, w = 2 elsewhere.
 // ---------------------------------------------------------------------------
@@ -2520,9 +2677,10 @@ __global__ __launch_bounds__(256) void k_spec_assemble(const float2 *__restrict_
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
-// PCG start from F(rhs) (sign * b, b in transform slots): r = sign b,
-// p = M^{-1} r, a copy of p into the transform slots c (cstride apart), and
-// the partial sums of <r, r> and <r, M^{-1} r> (partial, partial + gridDim.x)
+// PCG start from r = sign b (b: spectra bstride float2 apart, e.g. F(rhs) in
+// transform slots): r written unless NULL; p = M^{-1} r unless NULL, with a
+// copy into c (cstride apart) unless NULL; the partial sums of <r, r> and
+// <r, M^{-1} r> (partial, partial + gridDim.x)
 __global__ __launch_bounds__(256) void k_spcg_start(const float2 *__restrict__ b, long bstride, float sign,
                                                     float2 *__restrict__ r, float2 *__restrict__ p,
                                                     float2 *__restrict__ c, long cstride, long S, SpecIdx ix,
@@ -2543,9 +2701,9 @@ __global__ __launch_bounds__(256) void k_spcg_start(const float2 *__restrict__ b
             const float2 bv = b[f * bstride + e];
             const float2 rv = make_float2(sign * bv.x, sign * bv.y);
             const float2 zv = make_float2(m * rv.x, m * rv.y);
-            r[f * S + e] = rv;
-            p[f * S + e] = zv;
-            c[f * cstride + e] = zv;
+            if (r) r[f * S + e] = rv;
+            if (p) p[f * S + e] = zv;
+            if (c) c[f * cstride + e] = zv;
             srr += (double)rv.x * rv.x + (double)rv.y * rv.y;
             srz += (double)rv.x * zv.x + (double)rv.y * zv.y;
         }
@@ -2559,14 +2717,17 @@ __global__ __launch_bounds__(256) void k_spcg_start(const float2 *__restrict__ b
     }
 }
 
-// r -= alpha q (alpha from the device scalars d; r kept when alpha = 0, i.e.
-// after a stop), then the partial sums of <r, r> and <r, M^{-1} r>
-__global__ __launch_bounds__(256) void k_spcg_r(float2 *__restrict__ r, const float2 *__restrict__ q, long S,
+// r -= alpha q and, unless x is NULL, x += alpha p (alpha from the device
+// scalars d; nothing changes when alpha = 0, i.e. after a stop), then the
+// partial sums of <r, r> and <r, M^{-1} r>
+__global__ __launch_bounds__(256) void k_spcg_r(float2 *__restrict__ r, const float2 *__restrict__ q,
+                                                float2 *__restrict__ x, const float2 *__restrict__ p, long S,
                                                 SpecIdx ix, SymCtx sc, const double *__restrict__ d,
                                                 double *__restrict__ partial, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y);
-    r = mshift(r, mo_); q = mshift(q, mo_); d = mshift(d, mo_); partial = mshift(partial, mo_);
+    r = mshift(r, mo_); q = mshift(q, mo_); x = mshift(x, mo_); p = mshift(p, mo_); d = mshift(d, mo_);
+    partial = mshift(partial, mo_);
     const float al = (float)d[S_ALPHA];
     double arr = 0.0, arz = 0.0;
     SPEC_LOOP(S)
@@ -2583,6 +2744,10 @@ __global__ __launch_bounds__(256) void k_spcg_r(float2 *__restrict__ r, const fl
                 const float2 qv = q[f * S + e];
                 rv = make_float2(__builtin_fmaf(-al, qv.x, rv.x), __builtin_fmaf(-al, qv.y, rv.y));
                 r[f * S + e] = rv;
+                if (x) {
+                    const float2 pv = p[f * S + e], xv = x[f * S + e];
+                    x[f * S + e] = make_float2(__builtin_fmaf(al, pv.x, xv.x), __builtin_fmaf(al, pv.y, xv.y));
+                }
             }
             const float2 zv = make_float2(m * rv.x, m * rv.y);
             srr += (double)rv.x * rv.x + (double)rv.y * rv.y;
@@ -2598,14 +2763,15 @@ __global__ __launch_bounds__(256) void k_spcg_r(float2 *__restrict__ r, const fl
     }
 }
 
-// p = M^{-1} r + beta p (beta from the device scalars d; p kept once the PCG
-// has stopped), and a copy of p into the transform slots c
-__global__ __launch_bounds__(256) void k_spcg_p(const float2 *__restrict__ r, float2 *__restrict__ p,
-                                                float2 *__restrict__ c, long cstride, long S, SpecIdx ix,
-                                                SymCtx sc, const double *__restrict__ d, Mb mb)
+// p = z + beta p with z = M^{-1} r, or the given z when z is not NULL (beta
+// from the device scalars d; p kept once the PCG has stopped), and a copy of
+// p into c (cstride apart) unless c is NULL
+__global__ __launch_bounds__(256) void k_spcg_p(const float2 *__restrict__ r, const float2 *__restrict__ z,
+                                                float2 *__restrict__ p, float2 *__restrict__ c, long cstride, long S,
+                                                SpecIdx ix, SymCtx sc, const double *__restrict__ d, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y);
-    r = mshift(r, mo_); p = mshift(p, mo_); c = mshift(c, mo_); d = mshift(d, mo_);
+    r = mshift(r, mo_); z = mshift(z, mo_); p = mshift(p, mo_); c = mshift(c, mo_); d = mshift(d, mo_);
     const bool upd = d[S_DONE] == 0.0;
     const float be = (float)d[S_BETA];
     SPEC_LOOP(S)
@@ -2613,19 +2779,48 @@ __global__ __launch_bounds__(256) void k_spcg_p(const float2 *__restrict__ r, fl
         int l1, l2, l3;
         double w;
         ix.at(e, l1, l2, l3, w);
-        const float m = upd ? invreg_factor(sc, l1, l2, l3) : 0.f;
+        const float m = (upd && !z) ? invreg_factor(sc, l1, l2, l3) : 0.f;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             float2 pv = p[f * S + e];
             if (upd) {
-                const float2 rv = r[f * S + e];
-                const float2 zv = make_float2(m * rv.x, m * rv.y);
+                float2 zv;
+                if (z) {
+                    zv = z[f * S + e];
+                } else {
+                    const float2 rv = r[f * S + e];
+                    zv = make_float2(m * rv.x, m * rv.y);
+                }
                 pv = make_float2(__builtin_fmaf(be, pv.x, zv.x), __builtin_fmaf(be, pv.y, zv.y));
                 p[f * S + e] = pv;
             }
-            c[f * cstride + e] = pv;
+            if (c) c[f * cstride + e] = pv;
         }
     }
+}
+
+// the partial sums of <a, b> over three spectra each
+__global__ __launch_bounds__(256) void k_spec_dot(const float2 *__restrict__ a, const float2 *__restrict__ b, long S,
+                                                  SpecIdx ix, double *__restrict__ partial, Mb mb)
+{
+    const long long mo_ = mb.offset(blockIdx.y);
+    a = mshift(a, mo_); b = mshift(b, mo_); partial = mshift(partial, mo_);
+    double acc = 0.0, unused = 0.0;
+    SPEC_LOOP(S)
+    {
+        int l1, l2, l3;
+        double w;
+        ix.at(e, l1, l2, l3, w);
+        double t = 0.0;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const float2 u = a[f * S + e], v = b[f * S + e];
+            t += (double)u.x * v.x + (double)u.y * v.y;
+        }
+        acc += w * t;
+    }
+    block_sum2(acc, unused);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 // dst_f = src_f, or M^{-1} src_f (inv), for three spectra
 __global__ __launch_bounds__(256) void k_spec_copy3(const float2 *__restrict__ src, long sstride, float2 *__restrict__ dst,
@@ -2679,10 +2874,10 @@ void spec_inverse3(lddmm_plan *P, int slot0, float *out)
     c2r_fields(P, slot0, 3, ro, (float)(1.0 / (double)P->N));
 }
 
-void spcg_assemble(lddmm_plan *P, int bslot, const float2 *p, float2 *q, int kslot)
+void spcg_assemble(lddmm_plan *P, int bslot, const float2 *p, float2 *q, int kslot, int leray, int after)
 {
     const FftCtx &F = P->fft;
-    const SymCtx sc = sym_ctx(P, P->cfg.leray);
+    const SymCtx sc = sym_ctx(P, leray);
     {
         Scope s(P, K_VECOP);
         const dim3 g(kRedBlocks, P->mb.count);
@@ -2694,53 +2889,97 @@ void spcg_assemble(lddmm_plan *P, int bslot, const float2 *p, float2 *q, int ksl
                                q, F.spec_stride, spec_idx(F), sc, P->red, P->mb);
         check_hip(hipGetLastError(), "k_spec_assemble");
     }
-    dev_reduce_final(P, P->red, kslot, P->h3 / (double)P->N);
+    if (kslot >= 0) dev_reduce_final_steps(P, P->red, kslot, -1, P->h3 / (double)P->N, after, nullptr);
 }
 
-void spcg_start(lddmm_plan *P, int bslot, float sign, float2 *r, float2 *p, int cslot, int rr_slot, int rz_slot)
+void spcg_start(lddmm_plan *P, const float2 *b, long bstride, float sign, float2 *r, float2 *p, int cslot, int rr_slot,
+                int rz_slot)
 {
     const FftCtx &F = P->fft;
     {
         Scope s(P, K_VECOP);
-        hipLaunchKernelGGL(k_spcg_start, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, slot_ptr(P, bslot),
-                           P->slot_bytes / 8, sign, r, p, slot_ptr(P, cslot), P->slot_bytes / 8, F.spec_stride,
+        hipLaunchKernelGGL(k_spcg_start, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, b, bstride, sign, r, p,
+                           cslot >= 0 ? slot_ptr(P, cslot) : nullptr, P->slot_bytes / 8, F.spec_stride,
                            spec_idx(F), sym_ctx(P, 0), P->red, P->mb);
         check_hip(hipGetLastError(), "k_spcg_start");
     }
-    dev_reduce_final(P, P->red, rr_slot, P->h3 / (double)P->N);
-    dev_reduce_final(P, P->red + kRedBlocks, rz_slot, P->h3 / (double)P->N);
+    dev_reduce_final_steps(P, P->red, rr_slot, rz_slot, P->h3 / (double)P->N, 0, nullptr);
 }
 
-void spcg_r(lddmm_plan *P, float2 *r, const float2 *q, int rr_slot, int rz_slot)
+void spcg_r(lddmm_plan *P, float2 *r, const float2 *q, float2 *x, const float2 *p, int rr_slot, int rz_slot,
+            int after, double *hist_dst)
 {
     const FftCtx &F = P->fft;
     {
         Scope s(P, K_VECOP);
-        hipLaunchKernelGGL(k_spcg_r, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, r, q, F.spec_stride,
+        hipLaunchKernelGGL(k_spcg_r, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, r, q, x, p, F.spec_stride,
                            spec_idx(F), sym_ctx(P, 0), (const double *)scalars(P), P->red, P->mb);
         check_hip(hipGetLastError(), "k_spcg_r");
     }
-    dev_reduce_final(P, P->red, rr_slot, P->h3 / (double)P->N);
-    dev_reduce_final(P, P->red + kRedBlocks, rz_slot, P->h3 / (double)P->N);
+    dev_reduce_final_steps(P, P->red, rr_slot, rz_slot, P->h3 / (double)P->N, after, hist_dst);
 }
 
-void spcg_p(lddmm_plan *P, const float2 *r, float2 *p, int cslot)
+void spcg_p(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int cslot)
 {
     const FftCtx &F = P->fft;
     Scope s(P, K_VECOP);
-    hipLaunchKernelGGL(k_spcg_p, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, r, p, slot_ptr(P, cslot),
-                       P->slot_bytes / 8, F.spec_stride, spec_idx(F), sym_ctx(P, 0), (const double *)scalars(P), P->mb);
+    hipLaunchKernelGGL(k_spcg_p, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, r, z, p,
+                       cslot >= 0 ? slot_ptr(P, cslot) : nullptr, P->slot_bytes / 8, F.spec_stride, spec_idx(F),
+                       sym_ctx(P, 0), (const double *)scalars(P), P->mb);
     check_hip(hipGetLastError(), "k_spcg_p");
+}
+
+float2 *spec_slot(lddmm_plan *P, int slot) { return slot_ptr(P, slot); }
+
+static void spec_copy3_raw(lddmm_plan *P, const float2 *src, long sstride, float2 *dst, long dstride, bool inv)
+{
+    const FftCtx &F = P->fft;
+    Scope s(P, K_VECOP);
+    hipLaunchKernelGGL(k_spec_copy3, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, src, sstride, dst, dstride,
+                       F.spec_stride, spec_idx(F), sym_ctx(P, 0), inv ? 1 : 0, P->mb);
+    check_hip(hipGetLastError(), "k_spec_copy3");
 }
 
 void spec_copy3(lddmm_plan *P, const float2 *src, int dst_slot, bool inv)
 {
+    spec_copy3_raw(P, src, P->fft.spec_stride, slot_ptr(P, dst_slot), P->slot_bytes / 8, inv);
+}
+
+void spec_from_slots(lddmm_plan *P, int src_slot, float2 *dst)
+{
+    spec_copy3_raw(P, slot_ptr(P, src_slot), P->slot_bytes / 8, dst, P->fft.spec_stride, false);
+}
+
+void spec_invreg3(lddmm_plan *P, const float2 *src, float2 *dst)
+{
+    spec_copy3_raw(P, src, P->fft.spec_stride, dst, P->fft.spec_stride, true);
+}
+
+void spec_dot(lddmm_plan *P, const float2 *a, const float2 *b, int slot, int after)
+{
     const FftCtx &F = P->fft;
-    Scope s(P, K_VECOP);
-    hipLaunchKernelGGL(k_spec_copy3, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, src, F.spec_stride,
-                       slot_ptr(P, dst_slot), P->slot_bytes / 8, F.spec_stride, spec_idx(F), sym_ctx(P, 0), inv ? 1 : 0,
-                       P->mb);
-    check_hip(hipGetLastError(), "k_spec_copy3");
+    {
+        Scope s(P, K_DOT);
+        hipLaunchKernelGGL(k_spec_dot, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, a, b, F.spec_stride,
+                           spec_idx(F), P->red, P->mb);
+        check_hip(hipGetLastError(), "k_spec_dot");
+    }
+    dev_reduce_final_steps(P, P->red, slot, -1, P->h3 / (double)P->N, after, nullptr);
+}
+
+// three spectra of plan S (contiguous) resampled into three of plan D
+void spec_resample3(lddmm_plan *S, const float2 *src, lddmm_plan *D, float2 *dst)
+{
+    const FftCtx &FS = S->fft, &FD = D->fft;
+    const bool down = FD.n1 < FS.n1;
+    const FftCtx &FC = down ? FD : FS;
+    const float scale = (float)((double)FD.n1 * FD.n2 * FD.n3 / ((double)FS.n1 * FS.n2 * FS.n3));
+    Scope sc(D, K_PACK);
+    for (int f = 0; f < 3; ++f)
+        hipLaunchKernelGGL(k_resample, mgrid(D, dim3(1024)), dim3(256), 0, D->stream, src + f * FS.spec_stride, FS.n1,
+                           FS.n2, FS.m3, dst + f * FD.spec_stride, FD.n1, FD.n2, FD.m3, FC.n1, FC.n2, FC.m3, scale,
+                           D->mb);
+    check_hip(hipGetLastError(), "k_resample");
 }
 
 }  // namespace lddmm

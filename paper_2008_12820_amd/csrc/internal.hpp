@@ -159,6 +159,11 @@ void x2_pass(lddmm_plan *P, int slot0, int count, bool inverse, bool dbl);
 void x1_pass(lddmm_plan *P, int slot0, int count, bool inverse, bool dbl);
 // FP32 spectral slots -> real fields, times scale
 void c2r_fields(lddmm_plan *P, int slot0, int count, const RealOut &out, float scale);
+// three spectra in slots in0.. (after the inverse x1 and x2 passes) -> along
+// x3 back, t = G (G . p) per point, forward along x3 -> slots out0.. (the
+// rank-one part of H0 without a trip through HBM); false (nothing done) for
+// an x3 length without a register row plan
+bool x3_rank1(lddmm_plan *P, int in0, int out0, const float *G);
 
 enum SpecOp { SOP_GRAD = 1, SOP_DIV, SOP_REG, SOP_INVREG, SOP_LERAY, SOP_ASSEMBLE, SOP_IDENT };
 // x1 forward, pointwise symbol, x1 inverse in one pass: batches of the op's
@@ -192,15 +197,34 @@ void unpack_standard(lddmm_plan *P, const float2 *srcp, int spec_field);
 void spec_forward3(lddmm_plan *P, const float *in, int slot0);
 // spectra in slots [slot0, slot0 + 3) (overwritten) -> three real fields
 void spec_inverse3(lddmm_plan *P, int slot0, float *out);
-// q = K b + beta A p (b: the spectra in slots bslot..); <p, q> into scalar kslot
-void spcg_assemble(lddmm_plan *P, int bslot, const float2 *p, float2 *q, int kslot);
-// r = sign b (b in slots bslot..), p = M^{-1} r copied into slots cslot..;
-// <r, r> and <r, M^{-1} r> into scalars rr_slot, rz_slot
-void spcg_start(lddmm_plan *P, int bslot, float sign, float2 *r, float2 *p, int cslot, int rr_slot, int rz_slot);
-// r -= alpha q (device alpha); <r, r> and <r, M^{-1} r> into rr_slot, rz_slot
-void spcg_r(lddmm_plan *P, float2 *r, const float2 *q, int rr_slot, int rz_slot);
-// p = M^{-1} r + beta p (device beta, kept after a stop), copied into slots cslot..
-void spcg_p(lddmm_plan *P, const float2 *r, float2 *p, int cslot);
+// q = K b + beta A p (b: the spectra in slots bslot..; K the Leray projection
+// when leray); <p, q> into scalar kslot unless it is negative, then the
+// scalar steps `after` (kAfter* bits)
+void spcg_assemble(lddmm_plan *P, int bslot, const float2 *p, float2 *q, int kslot, int leray, int after);
+// r = sign b (b: three spectra bstride float2 apart) unless r is NULL;
+// p = M^{-1} r unless NULL, copied into slots cslot.. unless cslot < 0;
+// <r, r> and <r, M^{-1} r> into scalars rr_slot, rz_slot (rz skipped when < 0)
+void spcg_start(lddmm_plan *P, const float2 *b, long bstride, float sign, float2 *r, float2 *p, int cslot, int rr_slot,
+                int rz_slot);
+// r -= alpha q and, unless x is NULL, x += alpha p (device alpha); <r, r>
+// and <r, M^{-1} r> into rr_slot, rz_slot (rz skipped when < 0), then the
+// scalar steps `after` (S_REL into hist_dst for kAfterHist)
+void spcg_r(lddmm_plan *P, float2 *r, const float2 *q, float2 *x, const float2 *p, int rr_slot, int rz_slot,
+            int after, double *hist_dst);
+// p = z + beta p (device beta, kept after a stop) with z = M^{-1} r when z is
+// NULL; copied into slots cslot.. unless cslot < 0
+void spcg_p(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int cslot);
+// <a, b> of three spectra each into scalar slot, then the steps `after`
+void spec_dot(lddmm_plan *P, const float2 *a, const float2 *b, int slot, int after = 0);
+// dst = M^{-1} src, three spectra each
+void spec_invreg3(lddmm_plan *P, const float2 *src, float2 *dst);
+// slots src_slot.. -> three contiguous spectra
+void spec_from_slots(lddmm_plan *P, int src_slot, float2 *dst);
+// three spectra of plan S resampled into three of plan D (a grid of half or
+// twice the size: truncation or zero padding, times N_D / N_S)
+void spec_resample3(lddmm_plan *S, const float2 *src, lddmm_plan *D, float2 *dst);
+// the FP32 view of transform slot slot
+float2 *spec_slot(lddmm_plan *P, int slot);
 // three spectra (3 * spec_stride float2 at src) into slots dst_slot..,
 // times M^{-1} when inv
 void spec_copy3(lddmm_plan *P, const float2 *src, int dst_slot, bool inv);
@@ -219,6 +243,8 @@ void launch_incstate_init(lddmm_plan *P, const float *vt, float *mt1);
 void launch_incstate_step(lddmm_plan *P, const float *min, const float *s, float *mout);
 // last adjoint step into lam0 fused with the body force into P->b
 void h0_point(lddmm_plan *P, const float *s, const float *G, float *out, float beta0);
+// out = G (G . s), the rank-one part of H0 (three fields each, stride N)
+void h0_rank1(lddmm_plan *P, const float *s, const float *G, float *out);
 // eighth-order central differences (Section 3.2): grad f into g1, g2, g3;
 // div of v (three fields, stride N) into out
 void launch_fd8_grad(lddmm_plan *P, const float *f, float *g1, float *g2, float *g3);
@@ -247,9 +273,6 @@ double fetch_scalar(lddmm_plan *P, int slot);
 void axpby(lddmm_plan *P, long n, float a, const float *x, float b, const float *y, float *out);
 // out[i] = value
 void fill(lddmm_plan *P, long n, float value, float *out);
-// PCG update: x += al p; r -= al q
-void pcg_update_xr(lddmm_plan *P, long n, float al, const float *p, const float *q, float *x,
-                   float *r);
 constexpr int kRedBlocks = 1024;
 constexpr int kNumScalars = 32;
 // pinned host doubles per member: the scalars, then the 2-slot poll rings of
@@ -277,19 +300,20 @@ inline double *scalars(lddmm_plan *P) { return P->dscal + P->bank * kNumScalars;
 void dev_set_scalar(lddmm_plan *P, int slot, double value);
 void dev_tolerance(lddmm_plan *P, double rtol);
 void dev_pcg_init(lddmm_plan *P);
-void dev_pcg_alpha(lddmm_plan *P);
-void dev_pcg_xr(lddmm_plan *P, long n, const float *p, const float *q, float *x, float *r);
-void dev_copy_if(lddmm_plan *P, long n, const float *z, float *x);
-// x += alpha p with the device alpha (nothing when it is 0)
+// x += alpha p with the device alpha (nothing when it is 0), or x = p after
+// a curvature stop at the first iteration
 void dev_pcg_x(lddmm_plan *P, long n, const float *p, float *x);
 // scalars(P)[slot] = scale * (sum of kRedBlocks partials)
 void dev_reduce_final(lddmm_plan *P, const double *partial, int slot, double scale);
+// the scalar steps of the PCG that may follow a reduction in the same launch
+enum { kAfterAlpha = 1, kAfterConv = 2, kAfterHist = 4, kAfterBeta = 8 };
+// slots a and b (b < 0: none) = scale * (sums of the kRedBlocks partials at
+// partial and partial + kRedBlocks), then the steps named in after (alpha,
+// conv, S_REL into hist_dst, beta, in that order)
+void dev_reduce_final_steps(lddmm_plan *P, const double *partial, int a, int b, double scale, int after,
+                            double *hist_dst);
 void dev_pcg_conv(lddmm_plan *P);
-void dev_pcg_beta(lddmm_plan *P);
-void dev_pcg_p(lddmm_plan *P, long n, const float *z, float *p);
 void dev_sum(lddmm_plan *P, int dst, int a, int b);
-// dst[0] = dscal[slot] (device to device, a kernel: capturable)
-void dev_store_scalar(lddmm_plan *P, int slot, double *dst);
 // the inner PCG (current bank) counts as stopped when the outer one (bank-0
 // scalars outer) has stopped; and adds its iterations to outer[S_INNER]
 void dev_inner_link(lddmm_plan *P, double *outer);

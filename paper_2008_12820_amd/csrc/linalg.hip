@@ -87,8 +87,7 @@ __device__ __forceinline__ void ew_loop(long n, int vec, F4 body4, F1 body1)
 }
 
 // The updates round as written with explicit fused multiply-adds, the same in
-// the 16-byte and the one-element paths and in the host- and device-scalar
-// forms of the PCG loop (z + beta p, x + alpha p, r - alpha q: one rounding).
+// the 16-byte and the one-element paths (a x + b y, x + alpha p: one rounding).
 __device__ __forceinline__ float axpby1(float a, float x, float b, float y) { return __builtin_fmaf(b, y, a * x); }
 
 __device__ __forceinline__ float4 f4axpby(float a, float4 x, float b, float4 y)
@@ -125,35 +124,6 @@ __global__ void k_fill(long n, int vec, float value, float *__restrict__ out, Mb
         [&](long i) { out[i] = value; });
 }
 
-// x += al p, r -= al q
-__device__ __forceinline__ void xr_update(long n, int vec, float al, const float *__restrict__ p,
-                                          const float *__restrict__ q, float *__restrict__ x,
-                                          float *__restrict__ r)
-{
-    ew_loop(
-        n, vec,
-        [&](long i) {
-            float4 *x4 = (float4 *)x + i, *r4 = (float4 *)r + i;
-            const float4 pv = ((const float4 *)p)[i], qv = ((const float4 *)q)[i];
-            const float4 xv = *x4, rv = *r4;
-            *x4 = make_float4(__builtin_fmaf(al, pv.x, xv.x), __builtin_fmaf(al, pv.y, xv.y),
-                              __builtin_fmaf(al, pv.z, xv.z), __builtin_fmaf(al, pv.w, xv.w));
-            *r4 = make_float4(__builtin_fmaf(-al, qv.x, rv.x), __builtin_fmaf(-al, qv.y, rv.y),
-                              __builtin_fmaf(-al, qv.z, rv.z), __builtin_fmaf(-al, qv.w, rv.w));
-        },
-        [&](long i) {
-            x[i] = __builtin_fmaf(al, p[i], x[i]);
-            r[i] = __builtin_fmaf(-al, q[i], r[i]);
-        });
-}
-
-__global__ void k_pcg_xr(long n, int vec, float al, const float *__restrict__ p, const float *__restrict__ q,
-                         float *__restrict__ x, float *__restrict__ r, Mb mb)
-{
-    const long long mo_ = mb.offset(blockIdx.y); p = mshift(p, mo_); q = mshift(q, mo_); x = mshift(x, mo_); r = mshift(r, mo_);
-    xr_update(n, vec, al, p, q, x, r);
-}
-
 // H0 s = beta0 A s + G (G . s) (eq. h0-pc): on entry out holds A s; three
 // fields each, stride n
 __global__ void k_h0_point(long n, int vec, float beta0, const float *__restrict__ s,
@@ -183,6 +153,33 @@ __global__ void k_h0_point(long n, int vec, float beta0, const float *__restrict
             out[i] = beta0 * out[i] + G[i] * d;
             out[n + i] = beta0 * out[n + i] + G[n + i] * d;
             out[2 * n + i] = beta0 * out[2 * n + i] + G[2 * n + i] * d;
+        });
+}
+
+// out = G (G . s): the rank-one part of H0 (eq. h0-pc); three fields each,
+// stride n
+__global__ void k_h0_rank1(long n, int vec, const float *__restrict__ s, const float *__restrict__ G,
+                           float *__restrict__ out, Mb mb)
+{
+    const long long mo_ = mb.offset(blockIdx.y); s = mshift(s, mo_); G = mshift(G, mo_); out = mshift(out, mo_);
+    ew_loop(
+        n, vec,
+        [&](long i) {
+            const float4 s0 = ((const float4 *)s)[i], s1 = ((const float4 *)(s + n))[i],
+                         s2 = ((const float4 *)(s + 2 * n))[i];
+            const float4 g0 = ((const float4 *)G)[i], g1 = ((const float4 *)(G + n))[i],
+                         g2 = ((const float4 *)(G + 2 * n))[i];
+            const float4 d = make_float4(g0.x * s0.x + g1.x * s1.x + g2.x * s2.x, g0.y * s0.y + g1.y * s1.y + g2.y * s2.y,
+                                         g0.z * s0.z + g1.z * s1.z + g2.z * s2.z, g0.w * s0.w + g1.w * s1.w + g2.w * s2.w);
+            ((float4 *)out)[i] = make_float4(g0.x * d.x, g0.y * d.y, g0.z * d.z, g0.w * d.w);
+            ((float4 *)(out + n))[i] = make_float4(g1.x * d.x, g1.y * d.y, g1.z * d.z, g1.w * d.w);
+            ((float4 *)(out + 2 * n))[i] = make_float4(g2.x * d.x, g2.y * d.y, g2.z * d.z, g2.w * d.w);
+        },
+        [&](long i) {
+            const float d = G[i] * s[i] + G[n + i] * s[n + i] + G[2 * n + i] * s[2 * n + i];
+            out[i] = G[i] * d;
+            out[n + i] = G[n + i] * d;
+            out[2 * n + i] = G[2 * n + i] * d;
         });
 }
 
@@ -217,9 +214,8 @@ __global__ void k_pcg_init(double *d, Mb mb)
 }
 
 // after kappa = <p, H p>: alpha, or stop on non-finite / non-positive kappa
-__global__ void k_pcg_alpha(double *d, Mb mb)
+__device__ void pcg_alpha_step(double *d)
 {
-    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_);
     if (d[S_DONE] != 0.0) {
         d[S_ALPHA] = 0.0;
         return;
@@ -240,20 +236,18 @@ __global__ void k_pcg_alpha(double *d, Mb mb)
     }
 }
 
-__global__ void k_pcg_xr_dev(long n, int vec, const double *__restrict__ d, const float *__restrict__ p,
-                             const float *__restrict__ q, float *__restrict__ x, float *__restrict__ r, Mb mb)
-{
-    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); p = mshift(p, mo_); q = mshift(q, mo_); x = mshift(x, mo_); r = mshift(r, mo_);
-    const float al = (float)d[S_ALPHA];
-    if (al == 0.f) return;
-    xr_update(n, vec, al, p, q, x, r);
-}
-
-// x += alpha p (alpha from the device scalars; nothing when it is 0)
+// x += alpha p (alpha from the device scalars; nothing when it is 0), or
+// x = p when the first iteration stopped on its curvature (slot S_COPYZ:
+// then p = M^{-1} r0)
 __global__ void k_pcg_x_dev(long n, int vec, const double *__restrict__ d, const float *__restrict__ p,
                             float *__restrict__ x, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); p = mshift(p, mo_); x = mshift(x, mo_);
+    if (d[S_COPYZ] != 0.0) {
+        ew_loop(
+            n, vec, [&](long i) { ((float4 *)x)[i] = ((const float4 *)p)[i]; }, [&](long i) { x[i] = p[i]; });
+        return;
+    }
     const float al = (float)d[S_ALPHA];
     if (al == 0.f) return;
     ew_loop(
@@ -267,19 +261,9 @@ __global__ void k_pcg_x_dev(long n, int vec, const double *__restrict__ d, const
         [&](long i) { x[i] = __builtin_fmaf(al, p[i], x[i]); });
 }
 
-__global__ void k_copy_if(long n, int vec, const double *__restrict__ d, const float *__restrict__ z,
-                          float *__restrict__ x, Mb mb)
-{
-    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); z = mshift(z, mo_); x = mshift(x, mo_);
-    if (d[S_COPYZ] == 0.0) return;
-    ew_loop(
-        n, vec, [&](long i) { ((float4 *)x)[i] = ((const float4 *)z)[i]; }, [&](long i) { x[i] = z[i]; });
-}
-
 // after rr = <r, r>: relative residual and the stopping test
-__global__ void k_pcg_conv(double *d, Mb mb)
+__device__ void pcg_conv_step(double *d)
 {
-    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_);
     if (d[S_DONE] != 0.0) return;
     const double rn = sqrt(d[S_RR]);
     if (!isfinite(rn)) {
@@ -291,30 +275,53 @@ __global__ void k_pcg_conv(double *d, Mb mb)
     if (rn <= d[S_RTOL] * d[S_R0]) d[S_DONE] = 1.0;
 }
 
-__global__ void k_pcg_beta(double *d, Mb mb)
+__global__ void k_pcg_conv(double *d, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_);
+    pcg_conv_step(d);
+}
+
+__device__ void pcg_beta_step(double *d)
+{
     if (d[S_DONE] != 0.0) return;
     d[S_BETA] = d[S_RZN] / d[S_RZ];
     d[S_RZ] = d[S_RZN];
 }
 
-__global__ void k_pcg_p(long n, int vec, const double *__restrict__ d, const float *__restrict__ z,
-                        float *__restrict__ p, Mb mb)
+// One or two final reductions (partial, partial + np) into scalar slots a
+// and b of d (b < 0: one), then the PCG's scalar steps that follow them, in
+// the order alpha, conv, the relative residual into hist_dst, beta (bits of
+// `after`), by thread 0: one launch instead of up to six.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final_steps(const double *__restrict__ partial, int np,
+                                                                    double *__restrict__ d, int a, int b,
+                                                                    double scale, int after,
+                                                                    double *__restrict__ hist_dst, Mb mb)
 {
-    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); z = mshift(z, mo_); p = mshift(p, mo_);
-    if (d[S_DONE] != 0.0) return;
-    const float be = (float)d[S_BETA];
-    ew_loop(
-        n, vec,
-        [&](long i) {
-            const float4 zv = ((const float4 *)z)[i];
-            float4 *p4 = (float4 *)p + i;
-            const float4 pv = *p4;
-            *p4 = make_float4(__builtin_fmaf(be, pv.x, zv.x), __builtin_fmaf(be, pv.y, zv.y),
-                              __builtin_fmaf(be, pv.z, zv.z), __builtin_fmaf(be, pv.w, zv.w));
-        },
-        [&](long i) { p[i] = __builtin_fmaf(be, p[i], z[i]); });
+    const long long mo_ = mb.offset(blockIdx.y); partial = mshift(partial, mo_); d = mshift(d, mo_);
+    hist_dst = mshift(hist_dst, mo_);
+    __shared__ double sh[2][kRedThreads];
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        acc0 += partial[i];
+        if (b >= 0) acc1 += partial[np + i];
+    }
+    sh[0][threadIdx.x] = acc0;
+    sh[1][threadIdx.x] = acc1;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    d[a] = scale * sh[0][0];
+    if (b >= 0) d[b] = scale * sh[1][0];
+    if (after & kAfterAlpha) pcg_alpha_step(d);
+    if (after & kAfterConv) pcg_conv_step(d);
+    if (after & kAfterHist) hist_dst[0] = d[S_REL];
+    if (after & kAfterBeta) pcg_beta_step(d);
 }
 
 __global__ void k_sum2(double *d, int dst, int a, int b, Mb mb) {
@@ -329,8 +336,6 @@ __global__ void k_inner_accum(const double *inner, double *outer, Mb mb)
     const long long mo_ = mb.offset(blockIdx.y); inner = mshift(inner, mo_); outer = mshift(outer, mo_);
     if (outer[S_DONE] == 0.0) outer[S_INNER] += inner[S_ITERS];
 }
-__global__ void k_store_scalar(const double *d, int slot, double *dst, Mb mb) {
-    const long long mo_ = mb.offset(blockIdx.y); d = mshift(d, mo_); dst = mshift(dst, mo_); dst[0] = d[slot]; }
 
 __global__ void k_copy(long n, int vec, const float *__restrict__ x, float *__restrict__ out, Mb mb)
 {
@@ -405,15 +410,6 @@ void fill(lddmm_plan *P, long n, float value, float *out)
     check_hip(hipGetLastError(), "k_fill");
 }
 
-void pcg_update_xr(lddmm_plan *P, long n, float al, const float *p, const float *q, float *x, float *r)
-{
-    Scope s(P, K_VECOP);
-    const int vec = vec_ok({p, q, x, r});
-    hipLaunchKernelGGL(k_pcg_xr, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, al, p, q, x, r,
-                       P->mb);
-    check_hip(hipGetLastError(), "k_pcg_xr");
-}
-
 #define LAUNCH1(kern, ...)                                                                  \
     do {                                                                                    \
         Scope s_(P, K_VECOP);                                                               \
@@ -424,22 +420,10 @@ void pcg_update_xr(lddmm_plan *P, long n, float al, const float *p, const float 
 void dev_set_scalar(lddmm_plan *P, int slot, double value) { LAUNCH1(k_set_scalar, scalars(P), slot, value); }
 void dev_tolerance(lddmm_plan *P, double rtol) { LAUNCH1(k_tolerance, scalars(P), rtol); }
 void dev_pcg_init(lddmm_plan *P) { LAUNCH1(k_pcg_init, scalars(P)); }
-void dev_pcg_alpha(lddmm_plan *P) { LAUNCH1(k_pcg_alpha, scalars(P)); }
 void dev_pcg_conv(lddmm_plan *P) { LAUNCH1(k_pcg_conv, scalars(P)); }
-void dev_pcg_beta(lddmm_plan *P) { LAUNCH1(k_pcg_beta, scalars(P)); }
 void dev_sum(lddmm_plan *P, int dst, int a, int b) { LAUNCH1(k_sum2, scalars(P), dst, a, b); }
-void dev_store_scalar(lddmm_plan *P, int slot, double *dst) { LAUNCH1(k_store_scalar, scalars(P), slot, dst); }
 void dev_inner_link(lddmm_plan *P, double *outer) { LAUNCH1(k_inner_link, scalars(P), outer); }
 void dev_inner_accum(lddmm_plan *P, double *outer) { LAUNCH1(k_inner_accum, scalars(P), outer); }
-
-void dev_pcg_xr(lddmm_plan *P, long n, const float *p, const float *q, float *x, float *r)
-{
-    Scope s(P, K_VECOP);
-    const int vec = vec_ok({p, q, x, r});
-    hipLaunchKernelGGL(k_pcg_xr_dev, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, scalars(P),
-                       p, q, x, r, P->mb);
-    check_hip(hipGetLastError(), "k_pcg_xr_dev");
-}
 
 void dev_pcg_x(lddmm_plan *P, long n, const float *p, float *x)
 {
@@ -452,28 +436,16 @@ void dev_pcg_x(lddmm_plan *P, long n, const float *p, float *x)
 
 void dev_reduce_final(lddmm_plan *P, const double *partial, int slot, double scale)
 {
+    dev_reduce_final_steps(P, partial, slot, -1, scale, 0, nullptr);
+}
+
+void dev_reduce_final_steps(lddmm_plan *P, const double *partial, int a, int b, double scale, int after,
+                            double *hist_dst)
+{
     Scope s(P, K_DOT);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1, P->mb.count), dim3(kRedThreads), 0, P->stream, partial, kRedBlocks,
-                       scalars(P) + slot, scale, P->mb);
-    check_hip(hipGetLastError(), "k_reduce_final");
-}
-
-void dev_copy_if(lddmm_plan *P, long n, const float *z, float *x)
-{
-    Scope s(P, K_VECOP);
-    const int vec = vec_ok({z, x});
-    hipLaunchKernelGGL(k_copy_if, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, scalars(P), z,
-                       x, P->mb);
-    check_hip(hipGetLastError(), "k_copy_if");
-}
-
-void dev_pcg_p(lddmm_plan *P, long n, const float *z, float *p)
-{
-    Scope s(P, K_VECOP);
-    const int vec = vec_ok({z, p});
-    hipLaunchKernelGGL(k_pcg_p, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, scalars(P), z, p,
-                       P->mb);
-    check_hip(hipGetLastError(), "k_pcg_p");
+    hipLaunchKernelGGL(k_reduce_final_steps, dim3(1, P->mb.count), dim3(kRedThreads), 0, P->stream, partial, kRedBlocks,
+                       scalars(P), a, b, scale, after, hist_dst, P->mb);
+    check_hip(hipGetLastError(), "k_reduce_final_steps");
 }
 
 void h0_point(lddmm_plan *P, const float *s, const float *G, float *out, float beta0)
@@ -484,6 +456,16 @@ void h0_point(lddmm_plan *P, const float *s, const float *G, float *out, float b
     hipLaunchKernelGGL(k_h0_point, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, beta0, s, G,
                        out, P->mb);
     check_hip(hipGetLastError(), "k_h0_point");
+}
+
+void h0_rank1(lddmm_plan *P, const float *s, const float *G, float *out)
+{
+    Scope sc(P, K_VECOP);
+    const long n = P->N;
+    const int vec = vec_ok({s, s + n, G, G + n, out, out + n});
+    hipLaunchKernelGGL(k_h0_rank1, dim3(vec_blocks(n, vec), P->mb.count), dim3(256), 0, P->stream, n, vec, s, G, out,
+                       P->mb);
+    check_hip(hipGetLastError(), "k_h0_rank1");
 }
 
 void copy_kernel(lddmm_plan *P, long n, const float *x, float *out)

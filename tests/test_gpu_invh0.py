@@ -177,3 +177,30 @@ def test_two_level_after_set_beta_matches_oracle():
     say(f"2L beta 0.2: rel {e0:.2e}; after set_beta(1e-3): rel {e1:.2e}")
     assert it == it_ref == 6
     assert e0 < 1e-5 and e1 < 1e-5
+
+
+@pytest.mark.parametrize("shape,two_level", [((16, 12, 128), False), ((32, 24, 256), True)])
+def test_fused_rank_one_rows_match_oracle(shape, two_level):
+    """x3 lengths with a register row plan (n3 = 128 on the grid the inner
+    PCG runs on): the rank-one part of H0 goes back and forth along x3 in one
+    kernel, without its physical fields in HBM; 6 inner iterations against
+    the oracle, then a Newton step whose PCG uses the preconditioner."""
+    say(f"fused x3 rank-one rows, {shape}, two-level {two_level}")
+    P, ref = _setup(shape=shape, nt=2, reg=2, beta=1e-3)
+    r = incremental(P.shape, 1550)
+    if two_level:
+        s, it = P.apply_2linvh0(to_dev(r), 0.0, 6)
+        s_ref, it_ref = ref.two_level_invh0(synth.f64(r), 0.0, 6)
+    else:
+        s, it = P.apply_invh0(to_dev(r), 0.0, 6)
+        s_ref, it_ref = ref.invh0(synth.f64(r), 0.0, 6)
+    assert it == it_ref == 6
+    e = rel(to_np(s), s_ref)
+    pc = "2linvh0" if two_level else "invh0"
+    P.set_preconditioner(pc, eps_h0=1e-3, max_inner=5)
+    vt, info = P.newton_step(3, 1e-12)
+    vt_ref, pinfo = ref.pcg(-ref.gradient(), 3, 1e-12, pc=pc, eps_h0=1e-3, max_inner=5)
+    e2 = rel(to_np(vt), vt_ref)
+    say(f"  6 inner iterations rel {e:.2e}; Newton step ({pc}) rel {e2:.2e}")
+    assert info["pcg_iters"] == pinfo["iters"] == 3 and info["inner_iters"] == pinfo["inner"]
+    assert e < 1e-5 and e2 < 1e-5
