@@ -495,14 +495,16 @@ constexpr int kSlotFwd = 0, kSlotInv = 3;
 
 // qh = H0 p for the spectrum ph of p: beta0 A p pointwise, the rank-one part
 // G (G . p) (G = grad m(1)) in physical space between an inverse and a
-// forward transform; with kappa, <p, H0 p> into S_KAPPA and alpha.  copied:
-// slots kSlotInv.. already hold ph
-static void h0_apply_spec(lddmm_plan *P, const float2 *ph, float2 *qh, bool kappa, bool copied)
+// forward transform; with kappa, <p, H0 p> into S_KAPPA and alpha.  in: what
+// slots kSlotInv.. hold on entry (kFromVector: nothing yet, kCopy: ph,
+// kAfterX1: ph after its inverse x1 pass)
+enum { kFromVector, kCopy, kAfterX1 };
+static void h0_apply_spec(lddmm_plan *P, const float2 *ph, float2 *qh, bool kappa, int in)
 {
     const long N = P->N;
     const float *G1 = P->G + (long)P->nt * 3 * N;
-    if (!copied) spec_copy3(P, ph, kSlotInv, false);
-    x1_pass(P, kSlotInv, 3, true, false);
+    if (in == kFromVector) spec_copy3(P, ph, kSlotInv, false);
+    if (in != kAfterX1) x1_pass(P, kSlotInv, 3, true, false);
     x2_pass(P, kSlotInv, 3, true, false);
     if (!x3_rank1(P, kSlotInv, kSlotFwd, G1)) {  // x3 lengths without a register plan
         RealOut ro{};
@@ -542,16 +544,16 @@ static void invh0_spec(lddmm_plan *P, const float2 *rh, float2 *sh, double tol, 
     dev_pcg_init(P);  // S_R0 = ||r||; stopped when r = 0
     if (outer) dev_inner_link(P, outer);
     spec_invreg3(P, rh, sh);
-    h0_apply_spec(P, sh, qi, false, false);
+    h0_apply_spec(P, sh, qi, false, kFromVector);
     axpby(P, 2 * S3, 1.f, (const float *)rh, -1.f, (const float *)qi, (float *)ri);
     // <r, r> and <r, (beta0 A)^{-1} r> of the start residual, p = (beta0 A)^{-1} r
     // (copied into the slots its inverse transform reads)
     spcg_start(P, ri, P->fft.spec_stride, 1.f, nullptr, pi, kSlotInv, S_RR, S_RZ);
     dev_pcg_conv(P);  // the start may already meet the tolerance
     for (int it = 0; it < max_it; ++it) {
-        h0_apply_spec(P, pi, qi, true, true);                                  // kappa, alpha
+        h0_apply_spec(P, pi, qi, true, it == 0 ? kCopy : kAfterX1);                 // kappa, alpha
         spcg_r(P, ri, qi, sh, pi, S_RR, S_RZN, kAfterConv | kAfterBeta, nullptr);  // s, r; conv, beta
-        spcg_p(P, ri, nullptr, pi, kSlotInv);
+        spcg_p_x1(P, ri, nullptr, pi, kSlotInv);                                   // p, its x1 pass
         if (poll.after(it)) break;
     }
     if (outer) dev_inner_accum(P, outer);
@@ -698,8 +700,8 @@ static void spcg_run(lddmm_plan *P, const float *rhs, float sign, int max_it, fl
             precondition_spec(P, rh, zh, rtol);
             spec_dot(P, rh, zh, S_RZN, kAfterBeta);
         }
-        spcg_p(P, rh, zh, ph, kSlotInv);
-        spec_inverse3(P, kSlotInv, p);
+        spcg_p_x1(P, rh, zh, ph, kSlotInv);  // p, and its way back to physical space
+        spec_inverse3(P, kSlotInv, p, true);
         if (poll && poll->after(it)) break;  // iteration it is queued, predicated off
     }
 }

@@ -1178,46 +1178,6 @@ __device__ __forceinline__ void st_inv(C *v, C *X, StoreF &&store, const C *__re
         for (int r = 0; r < R; ++r) store(st_out_row<L, TW, R, NS>(t, r), st_col(t, S::NT, S::TW), v[t * R + r]);
 }
 
-// Column pass with register line FFTs (lengths with a RegPlan)
-template <bool INV, class R, int L>
-// Both parts of the spectrum in one launch: the tiles of the main array
-// (gx0 x outer0, descriptor d0) and then those of the Nyquist plane (gx1,
-// descriptor d1) along a one-dimensional grid, in the XCD order of tile_pos.
-__global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long slot_bytes, int slot0, ColDesc d0,
-                                                  ColDesc d1, int gx0, int outer0,
-                                                  const typename CplxOf<R>::type *__restrict__ tw, Mb mb)
-{
-    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
-    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
-    using C = typename CplxOf<R>::type;
-    using S = RegShape<L>;
-    extern __shared__ char lds_raw[];
-    C *X = reinterpret_cast<C *>(lds_raw);
-    const TilePos lp = tile_pos();  // gridDim.y = 1: lp.x is the linear tile index
-    const int t0 = gx0 * outer0;
-    const bool nyq = lp.x >= t0;
-    const ColDesc &d = nyq ? d1 : d0;
-    const TilePos tp = nyq ? TilePos{lp.x - t0, 0} : TilePos{lp.x % gx0, lp.x / gx0};
-    C *base = reinterpret_cast<C *>(spec + (long)(slot0 + bz_) * slot_bytes) + d.base_off +
-              (long)tp.y * d.ostride;
-    const int col0 = tp.x * S::TW;
-    C out[S::T2][S::R2];
-    reg_fft<L, INV>(
-        [&](int n, int c) {
-            const int col = col0 + c;
-            return col < d.ncols ? base[n * d.nstride + col * d.cstride] : mk<C>(0, 0);
-        },
-        X, out, tw);
-#pragma unroll
-    for (int u = 0; u < S::T2; ++u) {
-        const int task = (int)threadIdx.x + 256 * u, c = task % S::TW, k1 = task / S::TW;
-        const int col = col0 + c;
-        if (col < d.ncols)
-#pragma unroll
-            for (int k2 = 0; k2 < S::R2; ++k2) base[(k1 + S::R1 * k2) * d.nstride + col * d.cstride] = out[u][k2];
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Spectral symbols.  (l1, l2, l3) index a spectral point, l3 in [0, n3/2].
 // ---------------------------------------------------------------------------
@@ -1237,6 +1197,103 @@ __device__ __forceinline__ double reg_symbol(const SymCtx &s, int l1, int l2, in
     const double k1 = wn_full(l1, s.n1), k2 = wn_full(l2, s.n2), k3 = wn_full(l3, s.n3);
     const double kk = k1 * k1 + k2 * k2 + k3 * k3;
     return s.reg == 2 ? kk * kk : kk;
+}
+
+// (beta A)^{-1} symbol, as the InvA operator forms it (1/beta where A vanishes)
+__device__ __forceinline__ float invreg_factor(const SymCtx &sc, int l1, int l2, int l3)
+{
+    const double a = reg_symbol(sc, l1, l2, l3);
+    return (float)((a == 0.0) ? 1.0 / sc.beta : 1.0 / (sc.beta * a));
+}
+
+// ---------------------------------------------------------------------------
+// Column pass with register line FFTs (lengths with a RegPlan)
+// ---------------------------------------------------------------------------
+// The search-direction update of the spectral PCG fused into the inverse x1
+// pass that starts p's way back to physical space: while a column is
+// loaded, p = z + beta p (z = M^{-1} r, or the given z; beta from the device
+// scalars d, p kept once the PCG has stopped) is formed and written back to
+// the vector; the pass then transforms it into the slots.
+struct PUpd {
+    const float2 *r, *z;  // z NULL: z = M^{-1} r with the symbol of sc
+    float2 *p;
+    long S;               // float2 per field of the vectors
+    const double *d;
+    SymCtx sc;
+};
+
+// Both parts of the spectrum in one launch: the tiles of the main array
+// (gx0 x outer0, descriptor d0) and then those of the Nyquist plane (gx1,
+// descriptor d1) along a one-dimensional grid, in the XCD order of tile_pos.
+// PUPD (inverse FP32 x1 passes only): the loaded values are p = z + beta p.
+template <bool INV, class R, int L, bool PUPD>
+__global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long slot_bytes, int slot0, ColDesc d0,
+                                                  ColDesc d1, int gx0, int outer0,
+                                                  const typename CplxOf<R>::type *__restrict__ tw, PUpd pu, Mb mb)
+{
+    const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
+    const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    using C = typename CplxOf<R>::type;
+    using S = RegShape<L>;
+    extern __shared__ char lds_raw[];
+    C *X = reinterpret_cast<C *>(lds_raw);
+    const TilePos lp = tile_pos();  // gridDim.y = 1: lp.x is the linear tile index
+    const int t0 = gx0 * outer0;
+    const bool nyq = lp.x >= t0;
+    const ColDesc &d = nyq ? d1 : d0;
+    const TilePos tp = nyq ? TilePos{lp.x - t0, 0} : TilePos{lp.x % gx0, lp.x / gx0};
+    C *base = reinterpret_cast<C *>(spec + (long)(slot0 + bz_) * slot_bytes) + d.base_off +
+              (long)tp.y * d.ostride;
+    const int col0 = tp.x * S::TW;
+    C out[S::T2][S::R2];
+    if constexpr (PUPD) {
+        static_assert(INV && std::is_same<R, float>::value, "the update precedes an inverse FP32 pass");
+        const long fo = (long)bz_ * pu.S + d.base_off + (long)tp.y * d.ostride;
+        const float2 *rr = mshift(pu.r, mo_) + fo, *zz = mshift(pu.z, mo_);
+        float2 *pp = mshift(pu.p, mo_) + fo;
+        const double *dd = mshift(pu.d, mo_);
+        if (zz) zz += fo;
+        const bool upd = dd[S_DONE] == 0.0;
+        const float be = (float)dd[S_BETA];
+        reg_fft<L, INV>(
+            [&](int n, int c) {
+                const int col = col0 + c;
+                if (col >= d.ncols) return mk<C>(0, 0);
+                const long e = n * d.nstride + col * d.cstride;
+                float2 v = pp[e];
+                if (upd) {
+                    float2 zv;
+                    if (zz) {
+                        zv = zz[e];
+                    } else {
+                        // x1 pass: the line index is k1; the Nyquist plane's columns are k2
+                        const int l2 = nyq ? col : tp.y, l3 = nyq ? (pu.sc.n3 >> 1) : col;
+                        const float m = invreg_factor(pu.sc, n, l2, l3);
+                        const float2 rv = rr[e];
+                        zv = make_float2(m * rv.x, m * rv.y);
+                    }
+                    v = make_float2(__builtin_fmaf(be, v.x, zv.x), __builtin_fmaf(be, v.y, zv.y));
+                    pp[e] = v;
+                }
+                return v;
+            },
+            X, out, tw);
+    } else {
+        reg_fft<L, INV>(
+            [&](int n, int c) {
+                const int col = col0 + c;
+                return col < d.ncols ? base[n * d.nstride + col * d.cstride] : mk<C>(0, 0);
+            },
+            X, out, tw);
+    }
+#pragma unroll
+    for (int u = 0; u < S::T2; ++u) {
+        const int task = (int)threadIdx.x + 256 * u, c = task % S::TW, k1 = task / S::TW;
+        const int col = col0 + c;
+        if (col < d.ncols)
+#pragma unroll
+            for (int k2 = 0; k2 < S::R2; ++k2) base[(k1 + S::R1 * k2) * d.nstride + col * d.cstride] = out[u][k2];
+    }
 }
 
 struct ColCtx {  // how a tile position maps to (l2, l3)
@@ -2008,6 +2065,38 @@ bool x3_rank1(lddmm_plan *P, int in0, int out0, const float *G)
     return done;
 }
 
+static void col_descs(const FftCtx &F, int axis, ColDesc dd[2], int outer[2]);
+static SymCtx sym_ctx(lddmm_plan *P, int leray);
+
+void spcg_p_x1(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int slot0)
+{
+    FftCtx &F = P->fft;
+    bool done = false;
+    with_len(F.rp1.L, [&]<int LF>() {
+        if constexpr (RegPlan<LF>::ok) {
+            using RS = RegShape<LF>;
+            ColDesc dd[2];
+            int outer[2];
+            col_descs(F, 0, dd, outer);
+            const int g0 = (dd[0].ncols + RS::TW - 1) / RS::TW, g1 = (dd[1].ncols + RS::TW - 1) / RS::TW;
+            const dim3 grid((unsigned)(g0 * outer[0] + g1), 1, 3);
+            const size_t lds = sizeof(float2) * RS::XCH;
+            check_lds(lds, "fft_cols");
+            const PUpd pu{r, z, p, F.spec_stride, scalars(P), sym_ctx(P, 0)};
+            Scope s(P, K_FFT_COLS);
+            FFT_LAUNCH((k_cols_reg<true, float, LF, true>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes, slot0,
+                       dd[0], dd[1], g0, outer[0], F.tw1, pu, P->mb);
+            done = true;
+        }
+    });
+    if (done) {
+        check_hip(hipGetLastError(), "k_cols_reg");
+        return;
+    }
+    spcg_p(P, r, z, p, slot0);
+    x1_pass(P, slot0, 3, true, false);
+}
+
 // column descriptors: main array and Nyquist plane, along x2 (axis 1) or x1 (axis 0)
 static void col_descs(const FftCtx &F, int axis, ColDesc dd[2], int outer[2])
 {
@@ -2051,19 +2140,19 @@ static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool invers
                 if (dbl) {
                     const double2 *tw = axis == 1 ? F.tw2d : F.tw1d;
                     if (inverse)
-                        FFT_LAUNCH((k_cols_reg<true, double, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, dd[0], dd[1], g0, o0, tw, P->mb);
+                        FFT_LAUNCH((k_cols_reg<true, double, LF, false>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, P->mb);
                     else
-                        FFT_LAUNCH((k_cols_reg<false, double, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, dd[0], dd[1], g0, o0, tw, P->mb);
+                        FFT_LAUNCH((k_cols_reg<false, double, LF, false>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, P->mb);
                 } else {
                     const float2 *tw = axis == 1 ? F.tw2 : F.tw1;
                     if (inverse)
-                        FFT_LAUNCH((k_cols_reg<true, float, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, dd[0], dd[1], g0, o0, tw, P->mb);
+                        FFT_LAUNCH((k_cols_reg<true, float, LF, false>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, P->mb);
                     else
-                        FFT_LAUNCH((k_cols_reg<false, float, LF>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, dd[0], dd[1], g0, o0, tw, P->mb);
+                        FFT_LAUNCH((k_cols_reg<false, float, LF, false>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
+                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, P->mb);
                 }
                 done = true;
             }
@@ -2601,13 +2690,6 @@ struct SpecIdx {
     }
 };
 
-// (beta A)^{-1} symbol, as the InvA operator forms it (1/beta where A vanishes)
-__device__ __forceinline__ float invreg_factor(const SymCtx &sc, int l1, int l2, int l3)
-{
-    const double a = reg_symbol(sc, l1, l2, l3);
-    return (float)((a == 0.0) ? 1.0 / sc.beta : 1.0 / (sc.beta * a));
-}
-
 // deterministic sums of two values over a 256-thread workgroup (fixed tree);
 // the totals land in thread 0
 __device__ __forceinline__ void block_sum2(double &a, double &b)
@@ -2865,9 +2947,9 @@ void spec_forward3(lddmm_plan *P, const float *in, int slot0)
     x1_pass(P, slot0, 3, false, false);
 }
 
-void spec_inverse3(lddmm_plan *P, int slot0, float *out)
+void spec_inverse3(lddmm_plan *P, int slot0, float *out, bool x1_done)
 {
-    x1_pass(P, slot0, 3, true, false);
+    if (!x1_done) x1_pass(P, slot0, 3, true, false);
     x2_pass(P, slot0, 3, true, false);
     RealOut ro{};
     for (int c = 0; c < 3; ++c) ro.p[c] = out + c * P->N;

@@ -195,8 +195,9 @@ void unpack_standard(lddmm_plan *P, const float2 *srcp, int spec_field);
 // layout, unnormalised) of three fields, 3 * spec_stride float2 per vector.
 // three real fields (stride N) -> their spectra in slots [slot0, slot0 + 3)
 void spec_forward3(lddmm_plan *P, const float *in, int slot0);
-// spectra in slots [slot0, slot0 + 3) (overwritten) -> three real fields
-void spec_inverse3(lddmm_plan *P, int slot0, float *out);
+// spectra in slots [slot0, slot0 + 3) (overwritten) -> three real fields;
+// x1_done: the inverse x1 pass has already run on them
+void spec_inverse3(lddmm_plan *P, int slot0, float *out, bool x1_done = false);
 // q = K b + beta A p (b: the spectra in slots bslot..; K the Leray projection
 // when leray); <p, q> into scalar kslot unless it is negative, then the
 // scalar steps `after` (kAfter* bits)
@@ -214,6 +215,10 @@ void spcg_r(lddmm_plan *P, float2 *r, const float2 *q, float2 *x, const float2 *
 // p = z + beta p (device beta, kept after a stop) with z = M^{-1} r when z is
 // NULL; copied into slots cslot.. unless cslot < 0
 void spcg_p(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int cslot);
+// the same update fused into the inverse x1 pass of p into slots slot0..
+// (where the x1 length has a register plan; else the update, its copy and
+// the pass apart): the slots then hold p after its inverse x1 pass
+void spcg_p_x1(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int slot0);
 // <a, b> of three spectra each into scalar slot, then the steps `after`
 void spec_dot(lddmm_plan *P, const float2 *a, const float2 *b, int slot, int after = 0);
 // dst = M^{-1} src, three spectra each
