@@ -150,7 +150,9 @@ static Layout make_layout(const lddmm_config *cfg)
     const size_t rzq = std::max(3 * f, 3 * spec);
     for (int i = 0; i < 6; ++i) L.add(full * ((i == 1 || i == 2 || i == 4) ? rzq : 3 * f));
     L.add(spectral_slots(cfg) * 2 * spec);  // 22 spec (slots sized for FP64)
-    L.add(sizeof(double) * 2 * kRedBlocks);  // 23 red (two sets of partials)
+    // 23 red: two sets of partials, or one per x1 column tile and field
+    const size_t red_len = std::max<size_t>(2 * kRedBlocks, 3 * ((size_t)cfg->n[1] * (cfg->n[2] / 2) + cfg->n[0]));
+    L.add(sizeof(double) * red_len);
     L.add(sizeof(double) * 2 * kNumScalars);  // 24 dscal (two banks)
     L.add(2 * tile_boxes_bytes(cfg->n));     // 25 stencil extents per gather tile (dX, dXa)
     L.add(sizeof(double) * kHistMax);       // 26 PCG residual history
@@ -518,6 +520,7 @@ static void h0_apply_spec(lddmm_plan *P, const float2 *ph, float2 *qh, bool kapp
         r2c_fields(P, ri, 3, kSlotFwd, false);
     }
     x2_pass(P, kSlotFwd, 3, false, false);
+    if (kappa && x1_fwd_h0_assemble(P, kSlotFwd, ph, qh)) return;  // x1 pass, assembly, kappa, alpha
     x1_pass(P, kSlotFwd, 3, false, false);
     spcg_assemble(P, kSlotFwd, ph, qh, kappa ? S_KAPPA : -1, 0, kappa ? kAfterAlpha : 0);
 }
@@ -613,7 +616,8 @@ static void resample3(lddmm_plan *F, const float *in, lddmm_plan *C, float *out)
 // restriction R and the prolongation P are coefficient copies (truncation,
 // zero padding).  The coarse plan holds R grad m(1) in its grad m_{N_t} slot,
 // refreshed per velocity.
-static void twolevel_spec(lddmm_plan *P, const float2 *rh, float2 *sh, double tol, int max_it, double *outer)
+static void twolevel_spec(lddmm_plan *P, const float2 *rh, float2 *sh, double tol, int max_it, double *outer,
+                          int rz_slot, int after)
 {
     lddmm_plan *C = coarse_plan(P);
     // the half-grid H0 and (beta0 A_c)^{-1} take the fine plan's beta0: the
@@ -623,34 +627,29 @@ static void twolevel_spec(lddmm_plan *P, const float2 *rh, float2 *sh, double to
         resample3(P, P->G + (long)P->nt * 3 * P->N, C, C->G + (long)C->nt * 3 * C->N);
         P->coarse_gen = P->vel_gen;
     }
-    const long S3c = 3 * C->fft.spec_stride;
     // the half-grid plan runs no outer PCG of its own: its r, z, q buffers
     // hold R r, s_c0 and s_c
     float2 *rc = spec_r(C), *sc0 = spec_p(C), *sc = reinterpret_cast<float2 *>(C->pq);
-    float2 *tmp = h0_vectors(P) + 3 * P->fft.spec_stride;
-    {
-        Beta0Scope b0(P);
-        spec_invreg3(P, rh, sh);
-    }
-    spec_resample3(P, rh, C, rc);
     {
         Beta0Scope b0(C);
-        spec_invreg3(C, rc, sc0);
+        two_level_restrict(P, rh, C, rc, sc0);
     }
     invh0_spec(C, rc, sc, tol, max_it, outer);
-    axpby(C, 2 * S3c, 1.f, (const float *)sc, -1.f, (const float *)sc0, (float *)sc);
-    spec_resample3(C, sc, P, tmp);
-    axpby(P, 6 * P->fft.spec_stride, 1.f, (const float *)sh, 1.f, (const float *)tmp, (float *)sh);
+    Beta0Scope b0(P);
+    two_level_prolong(P, rh, sh, C, sc, sc0, rz_slot, after);
 }
 
 // zh = M^{-1} rh of the outer PCG for InvH0 / 2LInvH0 (tol_outer: its
-// tolerance); the inner iterations are added to the outer S_INNER
-static void precondition_spec(lddmm_plan *P, const float2 *rh, float2 *zh, double tol_outer)
+// tolerance), then <r, z> into rz_slot and the scalar steps `after`; the
+// inner iterations are added to the outer S_INNER
+static void precondition_spec(lddmm_plan *P, const float2 *rh, float2 *zh, double tol_outer, int rz_slot, int after)
 {
-    if (P->pc_kind == 1)
+    if (P->pc_kind == 1) {
         invh0_spec(P, rh, zh, P->pc_eps_h0 * tol_outer, P->pc_max_inner, P->dscal);
-    else
-        twolevel_spec(P, rh, zh, P->pc_eps_h0 * tol_outer, P->pc_max_inner, P->dscal);
+        spec_dot(P, rh, zh, rz_slot, after);
+    } else {
+        twolevel_spec(P, rh, zh, P->pc_eps_h0 * tol_outer, P->pc_max_inner, P->dscal, rz_slot, after);
+    }
 }
 
 // PCG on H x = sign * rhs, x0 = 0, with r, p and H p kept as FP32 spectra
@@ -681,8 +680,7 @@ static void spcg_run(lddmm_plan *P, const float *rhs, float sign, int max_it, fl
     } else {
         spcg_start(P, spec_slot(P, kSlotFwd), P->slot_bytes / 8, sign, rh, nullptr, -1, S_RR, -1);
         dev_pcg_init(P);
-        precondition_spec(P, rh, zh, rtol);
-        spec_dot(P, rh, zh, S_RZ);
+        precondition_spec(P, rh, zh, rtol, S_RZ, 0);
         copy_kernel(P, 6 * P->fft.spec_stride, (const float *)zh, (float *)ph);
         spec_copy3(P, ph, kSlotInv, false);
     }
@@ -697,8 +695,7 @@ static void spcg_run(lddmm_plan *P, const float *rhs, float sign, int max_it, fl
             spcg_r(P, rh, qh, nullptr, nullptr, S_RR, S_RZN, kAfterConv | hist | kAfterBeta, hdst);
         } else {
             spcg_r(P, rh, qh, nullptr, nullptr, S_RR, -1, kAfterConv | hist, hdst);
-            precondition_spec(P, rh, zh, rtol);
-            spec_dot(P, rh, zh, S_RZN, kAfterBeta);
+            precondition_spec(P, rh, zh, rtol, S_RZN, kAfterBeta);
         }
         spcg_p_x1(P, rh, zh, ph, kSlotInv);  // p, and its way back to physical space
         spec_inverse3(P, kSlotInv, p, true);
@@ -848,6 +845,7 @@ lddmm_plan *create_plan(const lddmm_config *cfg, void *stream, int members)
         P->nspec = spectral_slots(cfg);
         P->slot_bytes = (long)sizeof(double2) * cfg->n[0] * cfg->n[1] * (cfg->n[2] / 2 + 1);
         P->red = (double *)(a + L.off[23]);
+        P->red_len = (long)(L.len[23] / sizeof(double));
         P->dscal = (double *)(a + L.off[24]);
         assign_tile_boxes(P, a + L.off[25]);
         P->hist = (double *)(a + L.off[26]);
@@ -1552,7 +1550,7 @@ lddmm_status lddmm_apply_2linvh0(lddmm_plan *P, const float *r, double tol, int3
         float2 *rh = reinterpret_cast<float2 *>(P->pq), *sh = h0_vectors(P);
         spec_forward3(P, r, kSlotFwd);
         spec_from_slots(P, kSlotFwd, rh);
-        twolevel_spec(P, rh, sh, tol, max_inner, nullptr);
+        twolevel_spec(P, rh, sh, tol, max_inner, nullptr, -1, 0);
         spec_copy3(P, sh, kSlotInv, false);
         spec_inverse3(P, kSlotInv, s);
         const int it = inner_iterations(coarse_plan(P));

@@ -1209,6 +1209,25 @@ __device__ __forceinline__ float invreg_factor(const SymCtx &sc, int l1, int l2,
 // ---------------------------------------------------------------------------
 // Column pass with register line FFTs (lengths with a RegPlan)
 // ---------------------------------------------------------------------------
+// deterministic sums of two values over a 256-thread workgroup (fixed tree);
+// the totals land in thread 0
+__device__ __forceinline__ void block_sum2(double &a, double &b)
+{
+    __shared__ double sa[256], sb[256];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sa[threadIdx.x] += sa[threadIdx.x + s];
+            sb[threadIdx.x] += sb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    a = sa[0];
+    b = sb[0];
+}
+
 // The search-direction update of the spectral PCG fused into the inverse x1
 // pass that starts p's way back to physical space: while a column is
 // loaded, p = z + beta p (z = M^{-1} r, or the given z; beta from the device
@@ -1222,14 +1241,29 @@ struct PUpd {
     SymCtx sc;
 };
 
+// The H0 assembly fused into the forward x1 pass that completes the
+// transform of t = G (G . p): each output coefficient becomes
+// q = t^ + beta0 A p (p: the vector's spectrum) and is written to the vector
+// q instead of the slot, with the partial sums of <p, q> per workgroup and
+// field (partial[field * gridDim.x + workgroup]).
+struct QAsm {
+    const float2 *p;
+    float2 *q;
+    long S;
+    double *partial;
+    SymCtx sc;
+};
+
 // Both parts of the spectrum in one launch: the tiles of the main array
 // (gx0 x outer0, descriptor d0) and then those of the Nyquist plane (gx1,
 // descriptor d1) along a one-dimensional grid, in the XCD order of tile_pos.
-// PUPD (inverse FP32 x1 passes only): the loaded values are p = z + beta p.
-template <bool INV, class R, int L, bool PUPD>
+// PUPD (inverse FP32 x1 passes only): the loaded values are p = z + beta p;
+// ASM (forward FP32 x1 passes only): the outputs are assembled into q.
+template <bool INV, class R, int L, bool PUPD, bool ASM = false>
 __global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long slot_bytes, int slot0, ColDesc d0,
                                                   ColDesc d1, int gx0, int outer0,
-                                                  const typename CplxOf<R>::type *__restrict__ tw, PUpd pu, Mb mb)
+                                                  const typename CplxOf<R>::type *__restrict__ tw, PUpd pu, QAsm qa,
+                                                  Mb mb)
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
@@ -1286,13 +1320,42 @@ __global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long 
             },
             X, out, tw);
     }
+    if constexpr (ASM) {
+        static_assert(!INV && std::is_same<R, float>::value, "the assembly follows a forward FP32 pass");
+        const long fo = (long)bz_ * qa.S + d.base_off + (long)tp.y * d.ostride;
+        const float2 *pp = mshift(qa.p, mo_) + fo;
+        float2 *qq = mshift(qa.q, mo_) + fo;
+        double acc = 0.0, unused = 0.0;
 #pragma unroll
-    for (int u = 0; u < S::T2; ++u) {
-        const int task = (int)threadIdx.x + 256 * u, c = task % S::TW, k1 = task / S::TW;
-        const int col = col0 + c;
-        if (col < d.ncols)
+        for (int u = 0; u < S::T2; ++u) {
+            const int task = (int)threadIdx.x + 256 * u, c = task % S::TW, k1 = task / S::TW;
+            const int col = col0 + c;
+            if (col < d.ncols) {
+                const int l2 = nyq ? col : tp.y, l3 = nyq ? (qa.sc.n3 >> 1) : col;
+                const double w = (nyq || col == 0) ? 1.0 : 2.0;  // Hermitian weight (l3 = 0 or n3/2: 1)
 #pragma unroll
-            for (int k2 = 0; k2 < S::R2; ++k2) base[(k1 + S::R1 * k2) * d.nstride + col * d.cstride] = out[u][k2];
+                for (int k2 = 0; k2 < S::R2; ++k2) {
+                    const int n = k1 + S::R1 * k2;
+                    const long e = n * d.nstride + col * d.cstride;
+                    const double ba = qa.sc.beta * reg_symbol(qa.sc, n, l2, l3);
+                    const float2 pv = pp[e], o = out[u][k2];
+                    const float2 v = make_float2(o.x + (float)(pv.x * ba), o.y + (float)(pv.y * ba));
+                    qq[e] = v;
+                    acc += w * ((double)pv.x * v.x + (double)pv.y * v.y);
+                }
+            }
+        }
+        block_sum2(acc, unused);
+        if (threadIdx.x == 0) mshift(qa.partial, mo_)[(long)bz_ * gridDim.x + blockIdx.x] = acc;
+    } else {
+#pragma unroll
+        for (int u = 0; u < S::T2; ++u) {
+            const int task = (int)threadIdx.x + 256 * u, c = task % S::TW, k1 = task / S::TW;
+            const int col = col0 + c;
+            if (col < d.ncols)
+#pragma unroll
+                for (int k2 = 0; k2 < S::R2; ++k2) base[(k1 + S::R1 * k2) * d.nstride + col * d.cstride] = out[u][k2];
+        }
     }
 }
 
@@ -2085,7 +2148,7 @@ void spcg_p_x1(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int s
             const PUpd pu{r, z, p, F.spec_stride, scalars(P), sym_ctx(P, 0)};
             Scope s(P, K_FFT_COLS);
             FFT_LAUNCH((k_cols_reg<true, float, LF, true>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes, slot0,
-                       dd[0], dd[1], g0, outer[0], F.tw1, pu, P->mb);
+                       dd[0], dd[1], g0, outer[0], F.tw1, pu, QAsm{}, P->mb);
             done = true;
         }
     });
@@ -2095,6 +2158,35 @@ void spcg_p_x1(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int s
     }
     spcg_p(P, r, z, p, slot0);
     x1_pass(P, slot0, 3, true, false);
+}
+
+bool x1_fwd_h0_assemble(lddmm_plan *P, int slot0, const float2 *p, float2 *q)
+{
+    FftCtx &F = P->fft;
+    bool done = false;
+    with_len(F.rp1.L, [&]<int LF>() {
+        if constexpr (RegPlan<LF>::ok) {
+            using RS = RegShape<LF>;
+            ColDesc dd[2];
+            int outer[2];
+            col_descs(F, 0, dd, outer);
+            const int g0 = (dd[0].ncols + RS::TW - 1) / RS::TW, g1 = (dd[1].ncols + RS::TW - 1) / RS::TW;
+            const int tiles = g0 * outer[0] + g1;
+            if (3L * tiles > red_capacity(P)) return;
+            const size_t lds = sizeof(float2) * RS::XCH;
+            check_lds(lds, "fft_cols");
+            const QAsm qa{p, q, F.spec_stride, P->red, sym_ctx(P, 0)};
+            {
+                Scope s(P, K_FFT_COLS);
+                FFT_LAUNCH((k_cols_reg<false, float, LF, false, true>), mgrid(P, dim3((unsigned)tiles, 1, 3)), lds,
+                           P->stream, P->spec, P->slot_bytes, slot0, dd[0], dd[1], g0, outer[0], F.tw1, PUpd{}, qa, P->mb);
+                check_hip(hipGetLastError(), "k_cols_reg");
+            }
+            dev_reduce_final_steps(P, P->red, S_KAPPA, -1, P->h3 / (double)P->N, kAfterAlpha, nullptr, 3 * tiles);
+            done = true;
+        }
+    });
+    return done;
 }
 
 // column descriptors: main array and Nyquist plane, along x2 (axis 1) or x1 (axis 0)
@@ -2141,18 +2233,18 @@ static void cols_pass(lddmm_plan *P, int axis, int slot0, int count, bool invers
                     const double2 *tw = axis == 1 ? F.tw2d : F.tw1d;
                     if (inverse)
                         FFT_LAUNCH((k_cols_reg<true, double, LF, false>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, P->mb);
+                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, QAsm{}, P->mb);
                     else
                         FFT_LAUNCH((k_cols_reg<false, double, LF, false>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, P->mb);
+                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, QAsm{}, P->mb);
                 } else {
                     const float2 *tw = axis == 1 ? F.tw2 : F.tw1;
                     if (inverse)
                         FFT_LAUNCH((k_cols_reg<true, float, LF, false>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, P->mb);
+                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, QAsm{}, P->mb);
                     else
                         FFT_LAUNCH((k_cols_reg<false, float, LF, false>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes,
-                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, P->mb);
+                                   slot0, dd[0], dd[1], g0, o0, tw, PUpd{}, QAsm{}, P->mb);
                 }
                 done = true;
             }
@@ -2669,6 +2761,29 @@ void unpack_standard(lddmm_plan *P, const float2 *srcp, int slot)
 //   sum_x a b = (1/N) sum_k w_k Re(conj(F a)_k (F b)_k),
 // w = 1 on the planes k3 = 0 and k3 = n3/2, w = 2 elsewhere.
 // ---------------------------------------------------------------------------
+// Two-level preconditioner on spectra (restriction R: truncation to the half
+// grid's wavenumbers |k_d| < n_d/4, times N_c/N_f; prolongation P: zero
+// padding, times N_f/N_c).  Fine entry (l1, l2, l3) of wavenumber k and the
+// half grid's entry of the same k: (k1 mod c1, k2 mod c2, l3) when inside.
+struct TwoGrid {
+    int f1, f2, fm3;  // fine n1, n2, n3/2
+    int c1, c2, cm3;  // coarse n1, n2, n3/2
+    __device__ __forceinline__ long coarse_of(int l1, int l2, int l3) const
+    {
+        const int k1 = 2 * l1 <= f1 ? l1 : l1 - f1, k2 = 2 * l2 <= f2 ? l2 : l2 - f2;
+        if (!(2 * abs(k1) < c1 && 2 * abs(k2) < c2 && l3 < cm3)) return -1;
+        const int m1 = k1 < 0 ? k1 + c1 : k1, m2 = k2 < 0 ? k2 + c2 : k2;
+        return ((long)m1 * c2 + m2) * cm3 + l3;
+    }
+    __device__ __forceinline__ long fine_of(int l1, int l2, int l3) const
+    {
+        const int k1 = 2 * l1 <= c1 ? l1 : l1 - c1, k2 = 2 * l2 <= c2 ? l2 : l2 - c2;
+        if (!(2 * abs(k1) < c1 && 2 * abs(k2) < c2 && l3 < cm3)) return -1;
+        const int m1 = k1 < 0 ? k1 + f1 : k1, m2 = k2 < 0 ? k2 + f2 : k2;
+        return ((long)m1 * f2 + m2) * fm3 + l3;
+    }
+};
+
 struct SpecIdx {
     unsigned nmain;  // n1 n2 m3 entries of the main array, then the Nyquist plane
     unsigned m3, n2;
@@ -2689,25 +2804,6 @@ struct SpecIdx {
         l2 = (int)(row - (unsigned)l1 * n2);
     }
 };
-
-// deterministic sums of two values over a 256-thread workgroup (fixed tree);
-// the totals land in thread 0
-__device__ __forceinline__ void block_sum2(double &a, double &b)
-{
-    __shared__ double sa[256], sb[256];
-    sa[threadIdx.x] = a;
-    sb[threadIdx.x] = b;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            sa[threadIdx.x] += sa[threadIdx.x + s];
-            sb[threadIdx.x] += sb[threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    a = sa[0];
-    b = sb[0];
-}
 
 #define SPEC_LOOP(S)                                                                                  \
     for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < (unsigned)(S); e += gridDim.x * blockDim.x)
@@ -2923,6 +3019,71 @@ __global__ __launch_bounds__(256) void k_spec_copy3(const float2 *__restrict__ s
         }
     }
 }
+// R r (coarse, three spectra rc) and s_c0 = (beta0 A_c)^{-1} R r (sc0) from
+// the fine spectra r; the loop runs over the coarse entries (sc: the coarse
+// symbol)
+__global__ __launch_bounds__(256) void k_2l_restrict(const float2 *__restrict__ r, long Sf, float2 *__restrict__ rc,
+                                                     float2 *__restrict__ sc0, long Sc, SpecIdx ixc, TwoGrid tg,
+                                                     float scale, SymCtx sc, Mb mb)
+{
+    const long long mo_ = mb.offset(blockIdx.y);
+    r = mshift(r, mo_); rc = mshift(rc, mo_); sc0 = mshift(sc0, mo_);
+    SPEC_LOOP(Sc)
+    {
+        int l1, l2, l3;
+        double w;
+        ixc.at(e, l1, l2, l3, w);
+        const long ef = tg.fine_of(l1, l2, l3);
+        const float m = invreg_factor(sc, l1, l2, l3);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            float2 v = make_float2(0.f, 0.f);
+            if (ef >= 0) {
+                const float2 u = r[f * Sf + ef];
+                v = make_float2(scale * u.x, scale * u.y);
+            }
+            rc[f * Sc + e] = v;
+            sc0[f * Sc + e] = make_float2(m * v.x, m * v.y);
+        }
+    }
+}
+
+// z = (beta0 A)^{-1} r + P (s_c - s_c0) on the fine spectra, and the
+// partial sums of <r, z> (sc: the fine symbol)
+__global__ __launch_bounds__(256) void k_2l_prolong(const float2 *__restrict__ r, float2 *__restrict__ z, long Sf,
+                                                    SpecIdx ixf, const float2 *__restrict__ scs,
+                                                    const float2 *__restrict__ sc0, long Sc, TwoGrid tg, float scale,
+                                                    SymCtx sc, double *__restrict__ partial, Mb mb)
+{
+    const long long mo_ = mb.offset(blockIdx.y);
+    r = mshift(r, mo_); z = mshift(z, mo_); scs = mshift(scs, mo_); sc0 = mshift(sc0, mo_);
+    partial = mshift(partial, mo_);
+    double acc = 0.0, unused = 0.0;
+    SPEC_LOOP(Sf)
+    {
+        int l1, l2, l3;
+        double w;
+        ixf.at(e, l1, l2, l3, w);
+        const long ec = tg.coarse_of(l1, l2, l3);
+        const float m = invreg_factor(sc, l1, l2, l3);
+        double t = 0.0;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const float2 rv = r[f * Sf + e];
+            float2 zv = make_float2(m * rv.x, m * rv.y);
+            if (ec >= 0) {
+                const float2 a = scs[f * Sc + ec], b = sc0[f * Sc + ec];
+                const float2 d = make_float2(a.x - b.x, a.y - b.y);
+                zv = make_float2(zv.x + scale * d.x, zv.y + scale * d.y);
+            }
+            z[f * Sf + e] = zv;
+            t += (double)rv.x * zv.x + (double)rv.y * zv.y;
+        }
+        acc += w * t;
+    }
+    block_sum2(acc, unused);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
 #undef SPEC_LOOP
 
 static SpecIdx spec_idx(const FftCtx &F)
@@ -3049,19 +3210,34 @@ void spec_dot(lddmm_plan *P, const float2 *a, const float2 *b, int slot, int aft
     dev_reduce_final_steps(P, P->red, slot, -1, P->h3 / (double)P->N, after, nullptr);
 }
 
-// three spectra of plan S (contiguous) resampled into three of plan D
-void spec_resample3(lddmm_plan *S, const float2 *src, lddmm_plan *D, float2 *dst)
+static TwoGrid two_grid(const FftCtx &F, const FftCtx &C)
 {
-    const FftCtx &FS = S->fft, &FD = D->fft;
-    const bool down = FD.n1 < FS.n1;
-    const FftCtx &FC = down ? FD : FS;
-    const float scale = (float)((double)FD.n1 * FD.n2 * FD.n3 / ((double)FS.n1 * FS.n2 * FS.n3));
-    Scope sc(D, K_PACK);
-    for (int f = 0; f < 3; ++f)
-        hipLaunchKernelGGL(k_resample, mgrid(D, dim3(1024)), dim3(256), 0, D->stream, src + f * FS.spec_stride, FS.n1,
-                           FS.n2, FS.m3, dst + f * FD.spec_stride, FD.n1, FD.n2, FD.m3, FC.n1, FC.n2, FC.m3, scale,
-                           D->mb);
-    check_hip(hipGetLastError(), "k_resample");
+    return TwoGrid{F.n1, F.n2, F.m3, C.n1, C.n2, C.m3};
+}
+
+void two_level_restrict(lddmm_plan *F, const float2 *r, lddmm_plan *C, float2 *rc, float2 *sc0)
+{
+    const FftCtx &FF = F->fft, &FC = C->fft;
+    const float scale = (float)((double)FC.n1 * FC.n2 * FC.n3 / ((double)FF.n1 * FF.n2 * FF.n3));
+    Scope s(C, K_PACK);
+    hipLaunchKernelGGL(k_2l_restrict, dim3(kRedBlocks, C->mb.count), dim3(256), 0, C->stream, r, FF.spec_stride, rc, sc0,
+                       FC.spec_stride, spec_idx(FC), two_grid(FF, FC), scale, sym_ctx(C, 0), C->mb);
+    check_hip(hipGetLastError(), "k_2l_restrict");
+}
+
+void two_level_prolong(lddmm_plan *F, const float2 *r, float2 *z, lddmm_plan *C, const float2 *scs,
+                       const float2 *sc0, int rz_slot, int after)
+{
+    const FftCtx &FF = F->fft, &FC = C->fft;
+    const float scale = (float)((double)FF.n1 * FF.n2 * FF.n3 / ((double)FC.n1 * FC.n2 * FC.n3));
+    {
+        Scope s(F, K_PACK);
+        hipLaunchKernelGGL(k_2l_prolong, dim3(kRedBlocks, F->mb.count), dim3(256), 0, F->stream, r, z, FF.spec_stride,
+                           spec_idx(FF), scs, sc0, FC.spec_stride, two_grid(FF, FC), scale, sym_ctx(F, 0), F->red,
+                           F->mb);
+        check_hip(hipGetLastError(), "k_2l_prolong");
+    }
+    if (rz_slot >= 0) dev_reduce_final_steps(F, F->red, rz_slot, -1, F->h3 / (double)F->N, after, nullptr);
 }
 
 }  // namespace lddmm

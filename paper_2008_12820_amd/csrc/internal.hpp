@@ -101,7 +101,8 @@ struct lddmm_plan {
     long slot_bytes = 0;
     int nspec = 0;
     int pcg_spectral = 0;    // 1: the last PCG kept r and p as spectra (in pr and pz)
-    double *red = nullptr;   // reduction partials (two sets of kRedBlocks)
+    double *red = nullptr;   // reduction partials (two sets of kRedBlocks, or per x1 tile and field)
+    long red_len = 0;        // doubles at red
     double *hist = nullptr;  // ||r_k|| / ||r0|| per PCG iteration (device, kHistMax)
     std::vector<double> pcg_hist;  // the last PCG's history (host)
     double *dscal = nullptr; // device scalars, two banks of kNumScalars (see ScalarSlot)
@@ -215,6 +216,10 @@ void spcg_r(lddmm_plan *P, float2 *r, const float2 *q, float2 *x, const float2 *
 // p = z + beta p (device beta, kept after a stop) with z = M^{-1} r when z is
 // NULL; copied into slots cslot.. unless cslot < 0
 void spcg_p(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int cslot);
+// the forward x1 pass of the spectra in slots slot0.. (t^ after the x3 and
+// x2 passes) fused with the H0 assembly q = t^ + beta0 A p into the vector q,
+// <p, q> into S_KAPPA and alpha; false (nothing done) without a register plan
+bool x1_fwd_h0_assemble(lddmm_plan *P, int slot0, const float2 *p, float2 *q);
 // the same update fused into the inverse x1 pass of p into slots slot0..
 // (where the x1 length has a register plan; else the update, its copy and
 // the pass apart): the slots then hold p after its inverse x1 pass
@@ -225,9 +230,13 @@ void spec_dot(lddmm_plan *P, const float2 *a, const float2 *b, int slot, int aft
 void spec_invreg3(lddmm_plan *P, const float2 *src, float2 *dst);
 // slots src_slot.. -> three contiguous spectra
 void spec_from_slots(lddmm_plan *P, int src_slot, float2 *dst);
-// three spectra of plan S resampled into three of plan D (a grid of half or
-// twice the size: truncation or zero padding, times N_D / N_S)
-void spec_resample3(lddmm_plan *S, const float2 *src, lddmm_plan *D, float2 *dst);
+// two-level preconditioner on spectra (plans F and C of a grid and its half):
+// rc = R r and sc0 = (beta0 A_c)^{-1} R r (C's symbol), from fine spectra r
+void two_level_restrict(lddmm_plan *F, const float2 *r, lddmm_plan *C, float2 *rc, float2 *sc0);
+// z = (beta0 A)^{-1} r + P (scs - sc0) (F's symbol); <r, z> into F's scalar
+// rz_slot (unless negative), then the steps `after`
+void two_level_prolong(lddmm_plan *F, const float2 *r, float2 *z, lddmm_plan *C, const float2 *scs,
+                       const float2 *sc0, int rz_slot, int after);
 // the FP32 view of transform slot slot
 float2 *spec_slot(lddmm_plan *P, int slot);
 // three spectra (3 * spec_stride float2 at src) into slots dst_slot..,
@@ -316,7 +325,9 @@ enum { kAfterAlpha = 1, kAfterConv = 2, kAfterHist = 4, kAfterBeta = 8 };
 // partial and partial + kRedBlocks), then the steps named in after (alpha,
 // conv, S_REL into hist_dst, beta, in that order)
 void dev_reduce_final_steps(lddmm_plan *P, const double *partial, int a, int b, double scale, int after,
-                            double *hist_dst);
+                            double *hist_dst, int np = kRedBlocks);
+// doubles of the reduction partials (P->red)
+inline long red_capacity(const lddmm_plan *P) { return P->red_len; }
 void dev_pcg_conv(lddmm_plan *P);
 void dev_sum(lddmm_plan *P, int dst, int a, int b);
 // the inner PCG (current bank) counts as stopped when the outer one (bank-0

@@ -440,10 +440,10 @@ void dev_reduce_final(lddmm_plan *P, const double *partial, int slot, double sca
 }
 
 void dev_reduce_final_steps(lddmm_plan *P, const double *partial, int a, int b, double scale, int after,
-                            double *hist_dst)
+                            double *hist_dst, int np)
 {
     Scope s(P, K_DOT);
-    hipLaunchKernelGGL(k_reduce_final_steps, dim3(1, P->mb.count), dim3(kRedThreads), 0, P->stream, partial, kRedBlocks,
+    hipLaunchKernelGGL(k_reduce_final_steps, dim3(1, P->mb.count), dim3(kRedThreads), 0, P->stream, partial, np,
                        scalars(P), a, b, scale, after, hist_dst, P->mb);
     check_hip(hipGetLastError(), "k_reduce_final_steps");
 }
