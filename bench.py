@@ -583,23 +583,30 @@ def main():
                            gradient_s=tg, tuning=tuning)
         if nt_ == 4:
             log("newton step, 10 PCG iterations")
+            vt_out, info = plan.newton_step(10, 0.0)  # warm (loads the PCG kernels)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            vt_out, info = plan.newton_step(10, 0.0)
+            for _ in range(3):
+                vt_out, info = plan.newton_step(10, 0.0)
             torch.cuda.synchronize()
-            res_nt[nt_]["newton_step_s"] = time.perf_counter() - t0
+            res_nt[nt_]["newton_step_s"] = (time.perf_counter() - t0) / 3
             res_nt[nt_]["newton_info"] = {k: info[k] for k in ("pcg_iters", "rel_res", "gnorm")}
             # Newton step to a fixed relative residual with each preconditioner
+            # (eps_H0 = 1e-3 as the paper's NIREP runs, 1e-2 as its CLARITY
+            # runs, 1e-1 beside them; the second of two calls is timed)
             pcs = {}
-            for kind in ("inva", "invh0", "2linvh0"):
-                plan.set_preconditioner(kind, eps_h0=1e-3, max_inner=50)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                _, inf = plan.newton_step(100, 1e-2)
-                torch.cuda.synchronize()
-                pcs[kind] = {"ms": 1e3 * (time.perf_counter() - t0), "pcg_iters": inf["pcg_iters"],
-                             "inner_iters": inf["inner_iters"], "rel_res": inf["rel_res"]}
-                log(f"newton step rtol 1e-2, {kind}: {pcs[kind]}")
+            for kind, eps in (("inva", 1e-3), ("invh0", 1e-3), ("2linvh0", 1e-3), ("invh0", 1e-2),
+                              ("2linvh0", 1e-2), ("2linvh0", 1e-1)):
+                plan.set_preconditioner(kind, eps_h0=eps, max_inner=50)
+                key = kind if eps == 1e-3 else f"{kind}_eps{eps:g}"
+                for _ in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, inf = plan.newton_step(100, 1e-2)
+                    torch.cuda.synchronize()
+                pcs[key] = {"ms": 1e3 * (time.perf_counter() - t0), "pcg_iters": inf["pcg_iters"],
+                            "inner_iters": inf["inner_iters"], "rel_res": inf["rel_res"], "eps_h0": eps}
+                log(f"newton step rtol 1e-2, {key}: {pcs[key]}")
             plan.set_preconditioner("inva")
             res_nt[nt_]["newton_preconditioners"] = pcs
             # the eighth-order FD first derivatives (Section 3.2) in a second plan:
