@@ -1566,9 +1566,11 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
 // x1 transform of the outputs; the same arithmetic, in the same order and
 // precision, as the LDS kernels above.  blockIdx.z is the batch index.
 // ---------------------------------------------------------------------------
+// Both parts of the spectrum in one launch, as in k_cols_reg: the main
+// array's tiles (gx0 x outer0, d0), then the Nyquist plane's (d1).
 template <int OP, int L, int TW>
 __global__ __launch_bounds__(TW * L / 8) void k_x1_reg(char *__restrict__ spec, long slot_bytes, int in0,
-                                                         int out0, ColDesc d, int nyq,
+                                                         int out0, ColDesc d0, ColDesc d1, int gx0, int outer0,
                                                          const double2 *__restrict__ twd,
                                                          const float2 *__restrict__ twf, SymCtx sc, Mb mb)
 {
@@ -1578,7 +1580,10 @@ __global__ __launch_bounds__(TW * L / 8) void k_x1_reg(char *__restrict__ spec, 
     extern __shared__ char lds_raw[];
     double2 *XD = reinterpret_cast<double2 *>(lds_raw);
     float2 *XF = reinterpret_cast<float2 *>(lds_raw);
-    const TilePos tp = tile_pos();
+    const TilePos lp = tile_pos();  // gridDim.y = 1: lp.x is the linear tile index
+    const int t0 = gx0 * outer0, nyq = lp.x >= t0 ? 1 : 0;
+    const ColDesc &d = nyq ? d1 : d0;
+    const TilePos tp = nyq ? TilePos{lp.x - t0, 0} : TilePos{lp.x % gx0, lp.x / gx0};
     const int col0 = tp.x * TW, z = (int)bz_;
     const long off = d.base_off + (long)tp.y * d.ostride;
     const ColCtx cc{nyq, tp.y};
@@ -2338,9 +2343,10 @@ static SymCtx sym_ctx(lddmm_plan *P, int leray)
 
 // x1 forward, symbol, x1 inverse for nbatch batches: inputs of batch b at
 // slots in0 + b*nin .. , outputs at out0 + b*nout ..
+// only_part: -1 both parts of the spectrum in one launch, 0 / 1 one of them
 template <int LF, int TW>
-static void x1_reg_launch(lddmm_plan *P, int op, int in0, int out0, const ColDesc &d, int part, int outer,
-                          int nbatch, const SymCtx &sc)
+static void x1_reg_launch(lddmm_plan *P, int op, int in0, int out0, const ColDesc (&dd)[2], const int (&outer)[2],
+                          int only_part, int nbatch, const SymCtx &sc)
 {
     FftCtx &F = P->fft;
     using RS = StShape<LF, TW>;
@@ -2348,13 +2354,15 @@ static void x1_reg_launch(lddmm_plan *P, int op, int in0, int out0, const ColDes
     const size_t lds = (fp64x ? sizeof(double2) : sizeof(float2)) * RS::XCH;
     check_lds(lds, "x1_symbol");
     const int nz = (op == SOP_REG || op == SOP_INVREG) ? 3 * nbatch : nbatch;
-    const dim3 grid((unsigned)((d.ncols + TW - 1) / TW), outer, nz);
+    const int g0 = (dd[0].ncols + TW - 1) / TW, g1 = (dd[1].ncols + TW - 1) / TW;
+    const int o0 = only_part == 1 ? 0 : outer[0];
+    const dim3 grid((unsigned)(g0 * o0 + (only_part == 0 ? 0 : g1)), 1, nz);
     Scope s(P, K_SPECTRAL_X1);
 #define X1R(OPV)                                                                                         \
     do {                                                                                                 \
         if (lds > 65536) allow_big_lds((const void *)(k_x1_reg<OPV, LF, TW>));                           \
         hipLaunchKernelGGL((k_x1_reg<OPV, LF, TW>), mgrid(P, grid), dim3(RS::NT), lds, P->stream, P->spec,         \
-                           P->slot_bytes, in0, out0, d, part, F.tw1d, F.tw1, sc, P->mb);                        \
+                           P->slot_bytes, in0, out0, dd[0], dd[1], g0, o0, F.tw1d, F.tw1, sc, P->mb);            \
     } while (0)
     switch (op) {
     case SOP_GRAD: X1R(SOP_GRAD); break;
@@ -2391,18 +2399,20 @@ static void x1_symbol_parts(lddmm_plan *P, int op, int in0, int out0, int nbatch
         bool done = false;
         with_len(L, [&]<int LF>() {
             if constexpr (StPlan<LF>::ok) {
+                // both parts in one launch with the main part's tile width
+                // (only_part selects one for the autotuner)
                 using SP = StPlan<LF>;
                 const bool wide = F.tw_x1[op][part] >= SP::TWA;
                 if (wide)
-                    x1_reg_launch<LF, SP::TWA>(P, op, in0, out0, d, part, outer[part], nbatch, sc);
+                    x1_reg_launch<LF, SP::TWA>(P, op, in0, out0, dd, outer, only_part, nbatch, sc);
                 else
-                    x1_reg_launch<LF, SP::TWB>(P, op, in0, out0, d, part, outer[part], nbatch, sc);
+                    x1_reg_launch<LF, SP::TWB>(P, op, in0, out0, dd, outer, only_part, nbatch, sc);
                 done = true;
             }
         });
         if (done) {
             check_hip(hipGetLastError(), "k_x1_reg");
-            continue;
+            break;  // both parts launched (or the one asked for)
         }
         const size_t per = x1_bytes_per_elem(op);  // LDS bytes per tile element
         const int TW = F.tw_x1[op][part];
