@@ -275,9 +275,11 @@ lddmm_status lddmm_get_field(lddmm_plan *plan, int32_t what, int32_t j, float *o
  * a grid dimension, so a transport step, a transform pass, a reduction or a
  * PCG scalar update is one launch per group.  Per Gauss-Newton iteration a
  * group's gradient, eps_K, fixed-count PCG (device-resident scalars, stops
- * predicated per member), <g, v~> and first Armijo trial are one sequence,
- * replayed from a captured hipGraph when use_graph != 0; groups run on up to
- * nstreams library-created streams (default priority).  The batch calls
+ * predicated per member), <g, v~> and first Armijo trial are one sequence;
+ * groups run on up to nstreams library-created streams (default priority).
+ * With use_graph != 0 the sequences of all groups are replayed from one
+ * hipGraph captured for the whole batch (the group streams fork from the
+ * first stream and join it inside the capture).  The batch calls
  * synchronise the device on entry and their streams on return.  Arrays of
  * device pointers are HOST arrays of B entries.
  * lddmm_batch_plan gives member b's plan for per-member calls

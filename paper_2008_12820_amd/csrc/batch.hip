@@ -7,8 +7,10 @@
 // update -- is one launch per group instead of one per member.  The
 // iteration up to the first Armijo trial (gradient, eps_K, fixed-count PCG
 // with device-resident scalars predicated per member, <g, v~>, the trial
-// state and J) is captured once per group into a hipGraph and replayed; the
-// groups run on their own streams.  Only the line-search decisions need the
+// state and J) of every group is captured once into one hipGraph for the
+// whole batch and replayed: the groups' streams fork from the first and join
+// it again inside the capture, so the groups still run side by side.  Only
+// the line-search decisions need the
 // host; rejected trials (rare) run eagerly on the member alone, through the
 // member's view of its group.
 #include <algorithm>
@@ -24,10 +26,7 @@ namespace lddmm {
 struct Group {
     lddmm_plan *P = nullptr;  // the batched plan of the group's members
     std::vector<int> members;  // batch indices, in member order
-    hipGraphExec_t exec = nullptr;
-    int max_pcg = -1;
-    double rtol = 0.0;
-    unsigned long gen = 0;  // the plan's enqueue generation at capture
+    unsigned long gen = 0;     // the plan's enqueue generation at the capture
 };
 
 }  // namespace lddmm
@@ -36,6 +35,12 @@ struct lddmm_batch {
     int B = 0;
     std::vector<lddmm::Group> groups;
     std::vector<hipStream_t> streams;
+    // the batch's captured Gauss-Newton trial iteration, its arguments, and
+    // the fork / join events of the capture (one per stream)
+    hipGraphExec_t exec = nullptr;
+    int max_pcg = -1;
+    double rtol = 0.0;
+    std::vector<hipEvent_t> ev_fork, ev_join;
     std::vector<lddmm_plan *> views;  // member b's plan: a view of its group's plan
     std::vector<int> group_of, index_of;
 };
@@ -61,10 +66,11 @@ static void batch_free(lddmm_batch *Bt)
 {
     if (!Bt) return;
     for (lddmm_plan *V : Bt->views) view_free(V);
-    for (Group &g : Bt->groups) {
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (Bt->exec) (void)hipGraphExecDestroy(Bt->exec);
+    for (Group &g : Bt->groups)
         if (g.P) (void)lddmm_plan_destroy(g.P);
-    }
+    for (hipEvent_t e : Bt->ev_fork) (void)hipEventDestroy(e);
+    for (hipEvent_t e : Bt->ev_join) (void)hipEventDestroy(e);
     for (hipStream_t s : Bt->streams) (void)hipStreamDestroy(s);
     delete Bt;
 }
@@ -135,37 +141,62 @@ static void copy_scalars_async(lddmm_plan *P)
                   "scalar copy");
 }
 
-static void capture_group(Group &g, int max_pcg, double rtol)
+// One graph for the whole batch: the first stream begins the capture, the
+// others join it through an event, every group enqueues its trial iteration
+// on its own stream, and the others' events join the first stream again
+// before the capture ends.  Kernel arguments such as beta are baked into the
+// graph: it is captured again when an argument or a group plan's enqueue
+// generation moved.
+static void capture_batch(lddmm_batch *Bt, int max_pcg, double rtol)
 {
-    lddmm_plan *P = g.P;
-    // kernel arguments such as beta are baked into the graph: recapture when
-    // the plan's enqueue generation moved since the capture
-    if (g.exec && g.max_pcg == max_pcg && g.rtol == rtol && g.gen == P->enqueue_gen) return;
-    if (g.exec) {
-        check_hip(hipGraphExecDestroy(g.exec), "hipGraphExecDestroy");
-        g.exec = nullptr;
+    bool fresh = Bt->exec && Bt->max_pcg == max_pcg && Bt->rtol == rtol;
+    for (const Group &g : Bt->groups) fresh = fresh && g.gen == g.P->enqueue_gen;
+    if (fresh) return;
+    if (Bt->exec) {
+        check_hip(hipGraphExecDestroy(Bt->exec), "hipGraphExecDestroy");
+        Bt->exec = nullptr;
     }
-    const bool timing = P->timing.on;
-    P->timing.on = false;  // no event nodes in the graph
+    const size_t S = Bt->streams.size();
+    while (Bt->ev_fork.size() < S) {
+        hipEvent_t a = nullptr, b = nullptr;
+        check_hip(hipEventCreateWithFlags(&a, hipEventDisableTiming), "hipEventCreateWithFlags");
+        Bt->ev_fork.push_back(a);
+        check_hip(hipEventCreateWithFlags(&b, hipEventDisableTiming), "hipEventCreateWithFlags");
+        Bt->ev_join.push_back(b);
+    }
+    std::vector<bool> timing;
+    for (Group &g : Bt->groups) {
+        timing.push_back(g.P->timing.on);
+        g.P->timing.on = false;  // no event nodes in the graph
+    }
+    hipStream_t s0 = Bt->streams[0];
     hipGraph_t graph = nullptr;
-    check_hip(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    check_hip(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
-        gn_trial_enqueue(P, max_pcg, rtol, P->px);
-        copy_scalars_async(P);
+        check_hip(hipEventRecord(Bt->ev_fork[0], s0), "hipEventRecord");
+        for (size_t i = 1; i < S; ++i) check_hip(hipStreamWaitEvent(Bt->streams[i], Bt->ev_fork[0], 0), "fork");
+        for (Group &g : Bt->groups) {
+            gn_trial_enqueue(g.P, max_pcg, rtol, g.P->px);
+            copy_scalars_async(g.P);
+        }
+        for (size_t i = 1; i < S; ++i) {
+            check_hip(hipEventRecord(Bt->ev_join[i], Bt->streams[i]), "hipEventRecord");
+            check_hip(hipStreamWaitEvent(s0, Bt->ev_join[i], 0), "join");
+        }
     } catch (...) {
-        (void)hipStreamEndCapture(P->stream, &graph);
+        (void)hipStreamEndCapture(s0, &graph);
         if (graph) (void)hipGraphDestroy(graph);
-        P->timing.on = timing;
+        for (size_t i = 0; i < Bt->groups.size(); ++i) Bt->groups[i].P->timing.on = timing[i];
         throw;
     }
-    check_hip(hipStreamEndCapture(P->stream, &graph), "hipStreamEndCapture");
-    P->timing.on = timing;
-    hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    check_hip(hipStreamEndCapture(s0, &graph), "hipStreamEndCapture");
+    for (size_t i = 0; i < Bt->groups.size(); ++i) Bt->groups[i].P->timing.on = timing[i];
+    hipError_t e = hipGraphInstantiate(&Bt->exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     check_hip(e, "hipGraphInstantiate");
-    g.max_pcg = max_pcg;
-    g.rtol = rtol;
-    g.gen = P->enqueue_gen;
+    Bt->max_pcg = max_pcg;
+    Bt->rtol = rtol;
+    for (Group &g : Bt->groups) g.gen = g.P->enqueue_gen;
 }
 
 }  // namespace lddmm
@@ -296,12 +327,13 @@ lddmm_status lddmm_batch_gn_iterate(lddmm_batch *Bt, int32_t max_pcg, double rto
         }
         for (Group &g : Bt->groups) from_views(Bt, g);
         check_hip(hipDeviceSynchronize(), "device sync");
-        // phase 1: every group's iteration up to the first Armijo trial
-        for (Group &g : Bt->groups) {
-            if (use_graph) {
-                capture_group(g, max_pcg, rtol);
-                check_hip(hipGraphLaunch(g.exec, g.P->stream), "hipGraphLaunch");
-            } else {
+        // phase 1: every group's iteration up to the first Armijo trial (one
+        // graph for the batch, or eagerly on the groups' streams)
+        if (use_graph) {
+            capture_batch(Bt, max_pcg, rtol);
+            check_hip(hipGraphLaunch(Bt->exec, Bt->streams[0]), "hipGraphLaunch");
+        } else {
+            for (Group &g : Bt->groups) {
                 gn_trial_enqueue(g.P, max_pcg, rtol, g.P->px);
                 copy_scalars_async(g.P);
             }
