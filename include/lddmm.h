@@ -244,16 +244,17 @@ lddmm_status lddmm_interp(lddmm_plan *plan, int32_t nfields, const float *fields
  * preconditioned residual z = M^{-1} r and the search direction p that the
  * last PCG of lddmm_newton_step / lddmm_gn_iterate left (after k iterations
  * without a stop: r_k, z_k and p_k = z_k + beta_k p_{k-1}, the state from
- * which iteration k + 1 starts; Algorithm "GNK" solves eq. "iter" with it);
- * unspecified before the first Newton step.  With the InvA preconditioner
- * the PCG keeps r and p as spectra (see below): r and z are then returned as
- * their FP32 inverse transforms, p as the physical field the transport
- * sweeps of the next matvec read.
+ * which iteration k + 1 starts; Algorithm "GNK" solves eq. "iter" with it).
+ * The PCG keeps r and p as spectra (see below): r and z are returned as
+ * their FP32 inverse transforms (z = (beta A)^{-1} r for InvA, the last
+ * inner solve's result for InvH0 and 2LInvH0), p as the physical field the
+ * transport sweeps of the next matvec read; ESTATE for r and z before the
+ * first PCG, p unspecified then.
  * LDDMM_FIELD_PCG_R_HAT, _PCG_P_HAT (3 n1 n2 (n3/2 + 1) complex values,
  * interleaved FP32, i.e. 6 n1 n2 (n3/2 + 1) floats): the spectra of r and p
  * themselves, in the standard half-spectrum layout [c][k1][k2][k3], k3 <= n3/2,
- * unnormalised (the forward DFT, sum_x f(x) e^{-i k.x}); ESTATE when the last
- * PCG ran in physical space (InvH0, 2LInvH0) or none has run.
+ * unnormalised (the forward DFT, sum_x f(x) e^{-i k.x}); ESTATE before the
+ * first PCG.
  * After lddmm_transport_forward or lddmm_transport_vjp (e.g. on a
  * transport-only plan) the displacements are available, and after a VJP
  * also div v, the adjoint lam_j of that sweep (final value grad_m1) and, when

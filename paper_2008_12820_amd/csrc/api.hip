@@ -1399,7 +1399,7 @@ lddmm_status lddmm_get_field(lddmm_plan *P, int32_t what, int32_t j, float *out)
         case LDDMM_FIELD_PCG_P: copy_dev(P, out, P->pp, 3 * N); break;
         case LDDMM_FIELD_PCG_R_HAT:
         case LDDMM_FIELD_PCG_P_HAT: {
-            if (!spectral_pcg_state(P)) fail(LDDMM_ESTATE, "the last PCG kept no spectra");
+            if (!spectral_pcg_state(P)) fail(LDDMM_ESTATE, "no PCG has run");
             const long per = (long)P->cfg.n[0] * P->cfg.n[1] * (P->cfg.n[2] / 2 + 1);
             spec_copy3(P, what == LDDMM_FIELD_PCG_P_HAT ? spec_p(P) : spec_r(P), 0, false);
             for (int c = 0; c < 3; ++c) pack_standard(P, c, reinterpret_cast<float2 *>(out) + c * per);

@@ -100,7 +100,7 @@ struct lddmm_plan {
     char *spec = nullptr;    // spectral scratch: nspec slots of slot_bytes (FP64-sized)
     long slot_bytes = 0;
     int nspec = 0;
-    int pcg_spectral = 0;    // 1: the last PCG kept r and p as spectra (in pr and pz)
+    int pcg_spectral = 0;    // 1: a PCG has run (its r and p spectra are in pr and pz)
     double *red = nullptr;   // reduction partials (two sets of kRedBlocks, or per x1 tile and field)
     long red_len = 0;        // doubles at red
     double *hist = nullptr;  // ||r_k|| / ||r0|| per PCG iteration (device, kHistMax)

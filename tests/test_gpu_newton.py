@@ -157,6 +157,34 @@ def test_state_errors():
         P.gradient()
 
 
+def test_pcg_spectra_and_their_physical_images():
+    """The PCG keeps r and p as spectra: before any PCG they cannot be read
+    (ESTATE); after one, the residual field is the inverse transform of the
+    residual spectrum, z that of (beta A)^{-1} r, and the search direction
+    field the inverse transform of p's spectrum (all within FP32 transform
+    rounding); ||r|| / ||r0|| of the history is that of these spectra."""
+    shape, nt, reg, beta = (24, 20, 30), 2, 2, 1e-3
+    say("PCG spectra and physical images")
+    m0, m1, vtrue, v, ref = problem(shape, nt, reg, beta, False, disp=2.0)
+    P = _plan(shape, nt, reg, beta, False, m0, m1, v)
+    for f in (L.FIELD_PCG_R_HAT, L.FIELD_PCG_P_HAT, L.FIELD_PCG_R):
+        with pytest.raises(LddmmError) as e:
+            P.get_field(f)
+        assert e.value.status == ESTATE
+    g, _ = P.gradient()
+    g0 = np.linalg.norm(to_np(g))
+    P.newton_step(3, 1e-30)
+    hats = [P.get_field(f).cpu().numpy().astype(np.complex128) for f in (L.FIELD_PCG_R_HAT, L.FIELD_PCG_P_HAT)]
+    r_hat, p_hat = (np.fft.irfftn(h, s=shape, axes=(1, 2, 3)) for h in hats)
+    r, z, p = (to_np(P.get_field(f)) for f in (L.FIELD_PCG_R, L.FIELD_PCG_Z, L.FIELD_PCG_P))
+    er, ep = rel(r, r_hat), rel(p, p_hat)
+    ez = rel(z, oracle.reg_inverse(r_hat, reg, beta))
+    hist = P.pcg_history()
+    eh = abs(np.linalg.norm(r_hat) / g0 - hist[-1]) / hist[-1]
+    say(f"  r {er:.2e}, z {ez:.2e}, p {ep:.2e}, history {eh:.2e}")
+    assert er < 1e-6 and ez < 1e-6 and ep < 1e-6 and eh < 1e-6
+
+
 def test_negative_curvature_is_reported():
     """With the Leray projection the matvec is beta A v~ + P b~, and for a
     first search direction p = (beta A)^{-1}(-g) that is mostly curl free
