@@ -90,6 +90,26 @@ def test_inv_reg_and_newton_step_match_oracle_pcg():
     assert abs(info["rel_res"] - pinfo["rel_res"]) < 1e-3 * max(pinfo["rel_res"], 1e-3)
 
 
+@pytest.mark.parametrize("shape,leray", [((30, 12, 20), True), ((20, 18, 10), False), ((64, 20, 24), True)])
+def test_spectral_pcg_on_mixed_grids(shape, leray):
+    """The spectral-domain PCG on grids with radix-3 and -5 transforms and
+    x3 lengths whose half (n3/2 = 10, 5) is odd, where the Hermitian weights
+    of the inner products sit on the planes k3 = 0 and k3 = n3/2 of short
+    rows, and on an x1 length with a register pass (the fused p update and
+    inverse x1 pass): a 6-iteration Newton step against the oracle's FP64
+    PCG."""
+    nt, reg, beta = 2, 2, 1e-3
+    say(f"spectral PCG {shape} leray {leray}")
+    m0, m1, vtrue, v, ref = problem(shape, nt, reg, beta, leray, disp=2.0)
+    P = _plan(shape, nt, reg, beta, leray, m0, m1, v)
+    vt, info = P.newton_step(6, 1e-12)
+    vt_ref, pinfo = ref.pcg(-ref.gradient(), 6, 1e-12)
+    e = rel(to_np(vt), vt_ref)
+    say(f"  6-iteration Newton step rel {e:.2e}, rel_res {info['rel_res']:.6e} vs {pinfo['rel_res']:.6e}")
+    assert info["pcg_iters"] == pinfo["iters"] == 6
+    assert e < 1e-5
+
+
 @pytest.mark.parametrize("leray", [True, False])
 def test_overlapped_assembly_is_bitwise_the_same(leray):
     """With overlap on, the forward transform of the assembly's first operand
