@@ -330,6 +330,19 @@ __global__ __launch_bounds__(kPtThreads) void k_body_force(const float4 *__restr
 // kPad3 - 67 along x3) gathers from global memory instead.
 // ---------------------------------------------------------------------------
 constexpr int kT3 = 64;    // tile extent along x3 (one wavefront)
+// Half tiles: where the last x3 tile of a row would hold at most 32 points
+// (n3 mod 64 in (0, 32], e.g. n3 = 96, 160), tiles are 32 points wide and a
+// wavefront takes two rows at a time (lanes 0-31 one row, lanes 32-63 the
+// row PPT/2 iterations further), so no tile leaves half its lanes idle.
+__host__ __device__ constexpr bool half_tiles_for(int n3) { return n3 % 64 != 0 && n3 % 64 <= 32; }
+template <bool HALF>
+struct TileMap {
+    static constexpr int W3 = HALF ? 32 : kT3;  // x3 points per tile
+    // x3 index of a lane's points in tile column t3
+    __device__ static int k_of(int t3, int lane) { return t3 * W3 + (HALF ? (lane & 31) : lane); }
+    // the tile row (e = 0 .. T1 T2 - 1) of a lane's point q (q < NQ)
+    __device__ static int row_of(int w, int q, int lane, int nq) { return w + 4 * (HALF ? q + (lane >> 5) * nq : q); }
+};
 constexpr int kBoxH = 1;   // tolerated spread of floor(d) across the tile, x1 and x2
 constexpr int kPad3 = 72;  // box row pitch along x3 (floats)
 
@@ -649,17 +662,20 @@ __device__ __forceinline__ void epi_finish_tile(const Epi &epi, const long (&pp)
 // Stencil extents of one tile: the smallest first node (L) and the largest
 // (H) along each axis over the tile's grid points, reduced over the
 // workgroup; L1 > H1 when no point of the tile is inside the grid.
-template <int T1, int T2>
-__device__ __forceinline__ void tile_extents(const Grid3 &g, const float *__restrict__ disp, int i0, int j0, int k,
+template <int T1, int T2, bool HALF>
+__device__ __forceinline__ void tile_extents(const Grid3 &g, const float *__restrict__ disp, int i0, int j0, int t3,
                                              int w, int lane, int (*red)[6], int L[3], int H[3])
 {
     using BC = BoxCfg<T1, T2>;
+    using TM = TileMap<HALF>;
+    constexpr int NQ = HALF ? BC::PPT / 2 : BC::PPT;
     const long N = g.N;
+    const int k = TM::k_of(t3, lane);
     int lo1 = 0x7fffffff, lo2 = 0x7fffffff, lo3 = 0x7fffffff;
     int hi1 = (int)0x80000000, hi2 = (int)0x80000000, hi3 = (int)0x80000000;
 #pragma unroll
-    for (int q = 0; q < BC::PPT; ++q) {
-        const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+    for (int q = 0; q < NQ; ++q) {
+        const int e = TM::row_of(w, q, lane, NQ), i = i0 + e / T2, j = j0 + e % T2;
         if (i < g.n1 && j < g.n2 && k < g.n3) {
             const long p = ((long)i * g.n2 + j) * g.n3 + k;
             const int b1 = i + (int)floorf(clamp_disp(disp[p])) - 1;
@@ -706,7 +722,7 @@ struct TileBox {
     int L[3], H[3], pad[2];
 };
 
-template <int T1, int T2>
+template <int T1, int T2, bool HALF>
 __global__ __launch_bounds__(256) void k_tile_boxes(Grid3 g, const float *__restrict__ disp, TileBox *__restrict__ out,
                                                     int nt2, int nt3, Mb mb)
 {
@@ -719,7 +735,7 @@ __global__ __launch_bounds__(256) void k_tile_boxes(Grid3 g, const float *__rest
     const int tb = (int)blockIdx.x;
     const int u3 = tb % nt3, rr = tb / nt3, u2 = rr % nt2, u1 = rr / nt2;
     int L[3], H[3];
-    tile_extents<T1, T2>(g, disp, u1 * T1, u2 * T2, u3 * kT3 + lane, w, lane, red, L, H);
+    tile_extents<T1, T2, HALF>(g, disp, u1 * T1, u2 * T2, u3, w, lane, red, L, H);
     if (tid == 0) {
         TileBox b;
 #pragma unroll
@@ -735,7 +751,8 @@ __global__ __launch_bounds__(256) void k_tile_boxes(Grid3 g, const float *__rest
 // boxes != nullptr: the extents come from k_tile_boxes for this displacement field
 // MB: a batched plan (the member from blockIdx.y); plain plans run the
 // kernel without the member shift
-template <int T1, int T2, class Epi, bool MB>
+// HALF: half tiles (see TileMap)
+template <int T1, int T2, class Epi, bool MB, bool HALF>
 __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ disp, Epi epi, int nt2, int nt3,
                                              const TileBox *__restrict__ boxes, Mb mb)
 {
@@ -746,17 +763,21 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
         epi.shift(mo_);
     }
     using BC = BoxCfg<T1, T2>;
-    constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, NF = Epi::NF;
+    using TM = TileMap<HALF>;
+    // points per thread: PPT rows of one tile row each, or PPT / 2 when a
+    // wavefront takes two rows at a time (half tiles)
+    constexpr int PPT = HALF ? BC::PPT / 2 : BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, NF = Epi::NF;
     constexpr int S1 = BR2 * kPad3;  // box stride along x1 (x2: kPad3)
     extern __shared__ float box[];   // CAP floats
     __shared__ int red[4][6];
     const int tid = threadIdx.x, lane = tid & 63;
     // the wavefront index, wave-uniform: the compiler keeps what derives from
     // it (the rows of a point, their bounds and base addresses) in scalars
+    // (for full tiles; half tiles give each half of the wavefront its row)
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int t3 = tb % nt3, rr = tb / nt3, t2 = rr % nt2, t1 = rr / nt2;
-    const int i0 = t1 * T1, j0 = t2 * T2, k = t3 * kT3 + lane;
+    const int i0 = t1 * T1, j0 = t2 * T2, k = TM::k_of(t3, lane);
     const long N = g.N;
     int Lx[3], Hx[3];
     if (boxes) {
@@ -767,14 +788,14 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
             Hx[a] = tbx.H[a];
         }
     } else {
-        tile_extents<T1, T2>(g, disp, i0, j0, k, w, lane, red, Lx, Hx);
+        tile_extents<T1, T2, HALF>(g, disp, i0, j0, t3, w, lane, red, Lx, Hx);
     }
     const int L1 = Lx[0], L2 = Lx[1], L3 = Lx[2], H1 = Hx[0], H2 = Hx[1], H3 = Hx[2];
     if (L1 > H1) return;  // no point of the tile is inside the grid (uniform)
     float d1[PPT], d2[PPT], d3[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+        const int e = TM::row_of(w, q, lane, PPT), i = i0 + e / T2, j = j0 + e % T2;
         // points outside the grid (ragged tiles) read point 0 and use d = 0;
         // their sums are formed (wrapped, valid) and never stored, so no
         // lane of the contraction branches on them
@@ -812,7 +833,7 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
         }
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-            const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+            const int e = TM::row_of(w, q, lane, PPT), i = i0 + e / T2, j = j0 + e % T2;
             const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
             float w1[4], w2[4], w3[4];
             lagrange4<float>(d1[q] - f1, w1);
@@ -862,7 +883,7 @@ __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ 
     bool ok[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        const int e = w + 4 * q, i = i0 + e / T2, j = j0 + e % T2;
+        const int e = TM::row_of(w, q, lane, PPT), i = i0 + e / T2, j = j0 + e % T2;
         ok[q] = i < g.n1 && j < g.n2 && k < g.n3;
         pp[q] = ((long)i * g.n2 + j) * g.n3 + k;
     }
@@ -1319,7 +1340,10 @@ static bool linear_ip(const lddmm_plan *P) { return (P->cfg.flags & LDDMM_FLAG_L
 
 static int gather_mode(const lddmm_plan *P);
 template <int T1, int T2>
-static unsigned tiles_of(const lddmm_plan *P, int &nt2, int &nt3);
+static unsigned tiles_of(const lddmm_plan *P, int &nt2, int &nt3, int w3 = kT3);
+// the box gathers' tiles are half tiles on this plan's grid
+static bool half_tiles(const lddmm_plan *P) { return half_tiles_for(P->cfg.n[2]); }
+static int gather_w3(const lddmm_plan *P) { return half_tiles(P) ? 32 : kT3; }
 
 // departure strategy: P->departure_mode 0 direct, 1 box tiles 2x4x64, 2 box
 // tiles 4x4x64; -1 the tile shape of the gather strategy
@@ -1377,12 +1401,12 @@ static int gather_mode(const lddmm_plan *P)
 }
 
 template <int T1, int T2>
-static unsigned tiles_of(const lddmm_plan *P, int &nt2, int &nt3)
+static unsigned tiles_of(const lddmm_plan *P, int &nt2, int &nt3, int w3)
 {
     const int n1 = P->cfg.n[0], n2 = P->cfg.n[1], n3 = P->cfg.n[2];
     const int nt1 = (n1 + T1 - 1) / T1;
     nt2 = (n2 + T2 - 1) / T2;
-    nt3 = (n3 + kT3 - 1) / kT3;
+    nt3 = (n3 + w3 - 1) / w3;
     return (unsigned)((long)nt1 * nt2 * nt3);
 }
 
@@ -1398,21 +1422,30 @@ static const TileBox *boxes_for(const lddmm_plan *P, const float *disp)
     return nullptr;
 }
 
-template <int T1, int T2, class Epi>
-static void launch_box(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
+template <int T1, int T2, class Epi, bool HALF>
+static void launch_box_as(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
 {
     int nt2, nt3;
-    const unsigned ntiles = tiles_of<T1, T2>(P, nt2, nt3);
+    const unsigned ntiles = tiles_of<T1, T2>(P, nt2, nt3, TileMap<HALF>::W3);
     const size_t lds = sizeof(float) * BoxCfg<T1, T2>::CAP;
     static_assert(sizeof(float) * BoxCfg<4, 4>::CAP <= 64 * 1024, "box exceeds the default LDS limit");
     Scope s(P, kid);
     if (P->mb.count > 1)
-        hipLaunchKernelGGL((k_box<T1, T2, Epi, true>), dim3(ntiles, P->mb.count), dim3(256), lds, P->stream,
+        hipLaunchKernelGGL((k_box<T1, T2, Epi, true, HALF>), dim3(ntiles, P->mb.count), dim3(256), lds, P->stream,
                            grid_of(P), disp, epi, nt2, nt3, boxes_for<T1, T2>(P, disp), P->mb);
     else
-        hipLaunchKernelGGL((k_box<T1, T2, Epi, false>), dim3(ntiles), dim3(256), lds, P->stream, grid_of(P), disp,
-                           epi, nt2, nt3, boxes_for<T1, T2>(P, disp), P->mb);
+        hipLaunchKernelGGL((k_box<T1, T2, Epi, false, HALF>), dim3(ntiles), dim3(256), lds, P->stream, grid_of(P),
+                           disp, epi, nt2, nt3, boxes_for<T1, T2>(P, disp), P->mb);
     check_hip(hipGetLastError(), "k_box");
+}
+
+template <int T1, int T2, class Epi>
+static void launch_box(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
+{
+    if (half_tiles(P))
+        launch_box_as<T1, T2, Epi, true>(P, disp, epi, kid);
+    else
+        launch_box_as<T1, T2, Epi, false>(P, disp, epi, kid);
 }
 
 // Pipelined gathers: as many workgroups as stay resident on the device at
@@ -1435,7 +1468,7 @@ template <int T1, int T2, class Epi>
 static void launch_box_pipe1(lddmm_plan *P, const float *disp, const Epi &epi, int kid)
 {
     const TileBox *bx = boxes_for<T1, T2>(P, disp);
-    if (!bx) {
+    if (!bx || half_tiles(P)) {  // the pipelined kernel walks full tiles only
         launch_box<T1, T2>(P, disp, epi, kid);
         return;
     }
@@ -1462,8 +1495,9 @@ static void launch_box_pipe1(lddmm_plan *P, const float *disp, const Epi &epi, i
 // extents tables of the plan's two displacement fields for both tile shapes
 size_t tile_boxes_bytes(const int n[3])
 {
+    const int w3 = half_tiles_for(n[2]) ? 32 : kT3;
     auto cnt = [&](int T1, int T2) {
-        return (size_t)((n[0] + T1 - 1) / T1) * ((n[1] + T2 - 1) / T2) * ((n[2] + kT3 - 1) / kT3);
+        return (size_t)((n[0] + T1 - 1) / T1) * ((n[1] + T2 - 1) / T2) * ((n[2] + w3 - 1) / w3);
     };
     return sizeof(TileBox) * (cnt(2, 4) + cnt(4, 4));
 }
@@ -1471,7 +1505,7 @@ size_t tile_boxes_bytes(const int n[3])
 void assign_tile_boxes(lddmm_plan *P, char *base)
 {
     int nt2, nt3;
-    const size_t n24 = tiles_of<2, 4>(P, nt2, nt3), per = tile_boxes_bytes(P->cfg.n);
+    const size_t n24 = tiles_of<2, 4>(P, nt2, nt3, gather_w3(P)), per = tile_boxes_bytes(P->cfg.n);
     for (int f = 0; f < 2; ++f) {
         P->boxes[f][0] = base + f * per;
         P->boxes[f][1] = base + f * per + sizeof(TileBox) * n24;
@@ -1483,14 +1517,24 @@ void launch_tile_boxes(lddmm_plan *P)
 {
     if (!P->boxes[0][0]) return;
     int nt2, nt3;
+    const bool half = half_tiles(P);
+    const int w3 = gather_w3(P);
     for (int f = 0; f < 2; ++f) {
         const float *disp = f == 0 ? P->dX : P->dXa;
-        unsigned nb = tiles_of<2, 4>(P, nt2, nt3);
-        hipLaunchKernelGGL((k_tile_boxes<2, 4>), dim3(nb, P->mb.count), dim3(256), 0, P->stream, grid_of(P), disp,
-                           (TileBox *)P->boxes[f][0], nt2, nt3, P->mb);
-        nb = tiles_of<4, 4>(P, nt2, nt3);
-        hipLaunchKernelGGL((k_tile_boxes<4, 4>), dim3(nb, P->mb.count), dim3(256), 0, P->stream, grid_of(P), disp,
-                           (TileBox *)P->boxes[f][1], nt2, nt3, P->mb);
+        unsigned nb = tiles_of<2, 4>(P, nt2, nt3, w3);
+        if (half)
+            hipLaunchKernelGGL((k_tile_boxes<2, 4, true>), dim3(nb, P->mb.count), dim3(256), 0, P->stream, grid_of(P),
+                               disp, (TileBox *)P->boxes[f][0], nt2, nt3, P->mb);
+        else
+            hipLaunchKernelGGL((k_tile_boxes<2, 4, false>), dim3(nb, P->mb.count), dim3(256), 0, P->stream, grid_of(P),
+                               disp, (TileBox *)P->boxes[f][0], nt2, nt3, P->mb);
+        nb = tiles_of<4, 4>(P, nt2, nt3, w3);
+        if (half)
+            hipLaunchKernelGGL((k_tile_boxes<4, 4, true>), dim3(nb, P->mb.count), dim3(256), 0, P->stream, grid_of(P),
+                               disp, (TileBox *)P->boxes[f][1], nt2, nt3, P->mb);
+        else
+            hipLaunchKernelGGL((k_tile_boxes<4, 4, false>), dim3(nb, P->mb.count), dim3(256), 0, P->stream, grid_of(P),
+                               disp, (TileBox *)P->boxes[f][1], nt2, nt3, P->mb);
     }
     check_hip(hipGetLastError(), "k_tile_boxes");
     P->boxes_valid = 1;
