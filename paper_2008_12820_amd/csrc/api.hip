@@ -484,6 +484,20 @@ struct BankScope {
     ~BankScope() { P->bank = keep; }
 };
 
+// the stop flags the vector kernels of P's launches test (Mb::stopped) for
+// the duration of the scope: a loop's own and, for an inner solve, the outer
+// loop's (either may be NULL)
+struct SkipScope {
+    lddmm_plan *P;
+    Mb keep;
+    SkipScope(lddmm_plan *p, const double *own, const double *outer) : P(p), keep(p->mb)
+    {
+        P->mb.done = own;
+        P->mb.done2 = outer;
+    }
+    ~SkipScope() { P->mb = keep; }
+};
+
 // the spectra of the spectral-domain PCG live in the r, z and q buffers of
 // the workspace (sized for a physical field or a spectrum): r^ in r, p^ in z,
 // (H p)^ in q
@@ -542,10 +556,12 @@ static void invh0_spec(lddmm_plan *P, const float2 *rh, float2 *sh, double tol, 
     Beta0Scope b0(P);
     BankScope bk(P, 1);
     StopPoll poll(P, P->ev_inner, P->hscal + kNumScalars + 2);
+    SkipScope sk0(P, outer ? outer + S_DONE : nullptr, nullptr);
     dev_set_scalar(P, S_RTOL, tol);
     spec_dot(P, rh, rh, S_RR);
     dev_pcg_init(P);  // S_R0 = ||r||; stopped when r = 0
     if (outer) dev_inner_link(P, outer);
+    SkipScope sk1(P, scalars(P) + S_DONE, outer ? outer + S_DONE : nullptr);
     spec_invreg3(P, rh, sh);
     h0_apply_spec(P, sh, qi, false, kFromVector);
     axpby(P, 2 * S3, 1.f, (const float *)rh, -1.f, (const float *)qi, (float *)ri);
@@ -686,6 +702,7 @@ static void spcg_run(lddmm_plan *P, const float *rhs, float sign, int max_it, fl
     }
     spec_inverse3(P, kSlotInv, p);
     fill(P, M, 0.f, x);
+    SkipScope sk(P, scalars(P) + S_DONE, nullptr);
     for (int it = 0; it < max_it; ++it) {
         matvec_spectral(P, p, ph, qh);  // kappa, alpha
         dev_pcg_x(P, M, p, x);          // (or x = p0 = M^{-1} r0 after a first-iteration curvature stop)

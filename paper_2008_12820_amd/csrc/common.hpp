@@ -36,18 +36,29 @@ __host__ __device__ inline float2 cmuli(float2 a) { return make_float2(-a.y, a.x
 // every workspace pointer it was given by index * stride; tables the members
 // share (FFT twiddles) are not shifted.  A plain plan: stride 0, count 1.
 // ---------------------------------------------------------------------------
-struct Mb {
-    long long stride = 0;
-    int count = 1;
-    __host__ __device__ long long offset(unsigned idx) const { return (long long)idx * stride; }
-};
-
 // p + off bytes; NULL stays NULL
 template <class T>
 __device__ __forceinline__ T *mshift(T *p, long long off)
 {
     return p ? reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)off) : p;
 }
+
+struct Mb {
+    long long stride = 0;
+    int count = 1;
+    // Inside a device-resident PCG loop: the loop's stop flag and that of the
+    // PCG it preconditions, or NULL (member 0's; the members' at the same
+    // stride).  The vector kernels of an iteration queued after a stop
+    // (transport gathers, transform passes, spectral updates, reductions)
+    // then return at once: their results would go only to steps the stop
+    // predicates off.  Both NULL outside such loops.
+    const double *done = nullptr, *done2 = nullptr;
+    __host__ __device__ long long offset(unsigned idx) const { return (long long)idx * stride; }
+    __device__ bool stopped(long long off) const
+    {
+        return (done && *mshift(done, off) != 0.0) || (done2 && *mshift(done2, off) != 0.0);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // FFT line plans

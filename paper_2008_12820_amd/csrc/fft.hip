@@ -621,6 +621,7 @@ __global__ __launch_bounds__(RB * M / 8) void k_r2c_reg(RealIn in, char *__restr
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     using C = typename CplxOf<R>::type;
     using S = RowShape<M, RB>;
     constexpr int R0 = S::P::radix(0), RL = S::P::radix(S::NP - 1);
@@ -678,6 +679,7 @@ __global__ __launch_bounds__(RB * M / 8) void k_c2r_reg(const char *__restrict__
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     using S = RowShape<M, RB>;
     constexpr int RA = S::P::radix(S::NP - 1), R1 = S::P::radix(0);  // first and last inverse radices
     extern __shared__ char lds_raw[];
@@ -736,6 +738,7 @@ __global__ __launch_bounds__(RB * M / 8) void k_x3_rank1(char *__restrict__ spec
                                                   float scale, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.z);
+    if (mb.stopped(mo_)) return;
     spec = mshift(spec, mo_);
     G = mshift(G, mo_);
     using S = RowShape<M, RB>;
@@ -854,6 +857,7 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_x3(RealIn in, char *__restr
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     using C = typename CplxOf<R>::type;
     extern __shared__ char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
@@ -903,6 +907,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_x3(const char *__restrict__
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     extern __shared__ char lds_raw[];
     float2 *lds = reinterpret_cast<float2 *>(lds_raw);
     const int n3 = LF > 0 ? 2 * LF : n3_rt;
@@ -999,6 +1004,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(char *__restrict__ spe
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     using C = typename CplxOf<R>::type;
     extern __shared__ char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
@@ -1267,6 +1273,7 @@ __global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long 
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     using C = typename CplxOf<R>::type;
     using S = RegShape<L>;
     extern __shared__ char lds_raw[];
@@ -1381,6 +1388,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_scalar(char *__restrict__ sp
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     using C = typename CplxOf<R>::type;
     extern __shared__ char lds_raw[];
     C *lds = reinterpret_cast<C *>(lds_raw);
@@ -1426,6 +1434,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_grad(char *__restrict__ spec
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     extern __shared__ char lds_raw[];
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile;
@@ -1466,6 +1475,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_div(char *__restrict__ spec,
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     extern __shared__ char lds_raw[];
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile, *ACC = WB + tile;
@@ -1522,6 +1532,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_leray(char *__restrict__ spe
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     extern __shared__ char lds_raw[];
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     float2 *T = reinterpret_cast<float2 *>(lds_raw);  // three field tiles, then scratch
@@ -1576,6 +1587,7 @@ __global__ __launch_bounds__(TW * L / 8) void k_x1_reg(char *__restrict__ spec, 
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     using S = StShape<L, TW>;
     extern __shared__ char lds_raw[];
     double2 *XD = reinterpret_cast<double2 *>(lds_raw);
@@ -1766,6 +1778,7 @@ __global__ __launch_bounds__(kFftThreads) void k_x1_assemble(char *__restrict__ 
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
+    if (mb.stopped(mo_)) return;
     extern __shared__ char lds_raw[];
     const int L = LF > 0 ? LF : rp.L, tile = L * TW;
     double2 *WA = reinterpret_cast<double2 *>(lds_raw), *WB = WA + tile;
@@ -2827,6 +2840,7 @@ __global__ __launch_bounds__(256) void k_spec_assemble(const float2 *__restrict_
                                                        SpecIdx ix, SymCtx sc, double *__restrict__ partial, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y);
+    if (mb.stopped(mo_)) return;
     b = mshift(b, mo_); p = mshift(p, mo_); q = mshift(q, mo_); partial = mshift(partial, mo_);
     double acc = 0.0, unused = 0.0;
     SPEC_LOOP(S)
@@ -2875,6 +2889,7 @@ __global__ __launch_bounds__(256) void k_spcg_start(const float2 *__restrict__ b
                                                     SymCtx sc, double *__restrict__ partial, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y);
+    if (mb.stopped(mo_)) return;
     b = mshift(b, mo_); r = mshift(r, mo_); p = mshift(p, mo_); c = mshift(c, mo_); partial = mshift(partial, mo_);
     double arr = 0.0, arz = 0.0;
     SPEC_LOOP(S)
@@ -2914,6 +2929,7 @@ __global__ __launch_bounds__(256) void k_spcg_r(float2 *__restrict__ r, const fl
                                                 double *__restrict__ partial, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y);
+    if (mb.stopped(mo_)) return;
     r = mshift(r, mo_); q = mshift(q, mo_); x = mshift(x, mo_); p = mshift(p, mo_); d = mshift(d, mo_);
     partial = mshift(partial, mo_);
     const float al = (float)d[S_ALPHA];
@@ -2959,6 +2975,7 @@ __global__ __launch_bounds__(256) void k_spcg_p(const float2 *__restrict__ r, co
                                                 SpecIdx ix, SymCtx sc, const double *__restrict__ d, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y);
+    if (mb.stopped(mo_)) return;
     r = mshift(r, mo_); z = mshift(z, mo_); p = mshift(p, mo_); c = mshift(c, mo_); d = mshift(d, mo_);
     const bool upd = d[S_DONE] == 0.0;
     const float be = (float)d[S_BETA];
@@ -2992,6 +3009,7 @@ __global__ __launch_bounds__(256) void k_spec_dot(const float2 *__restrict__ a, 
                                                   SpecIdx ix, double *__restrict__ partial, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y);
+    if (mb.stopped(mo_)) return;
     a = mshift(a, mo_); b = mshift(b, mo_); partial = mshift(partial, mo_);
     double acc = 0.0, unused = 0.0;
     SPEC_LOOP(S)
@@ -3015,6 +3033,7 @@ __global__ __launch_bounds__(256) void k_spec_copy3(const float2 *__restrict__ s
                                                     long dstride, long S, SpecIdx ix, SymCtx sc, int inv, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y);
+    if (mb.stopped(mo_)) return;
     src = mshift(src, mo_); dst = mshift(dst, mo_);
     SPEC_LOOP(S)
     {
@@ -3037,6 +3056,7 @@ __global__ __launch_bounds__(256) void k_2l_restrict(const float2 *__restrict__ 
                                                      float scale, SymCtx sc, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y);
+    if (mb.stopped(mo_)) return;
     r = mshift(r, mo_); rc = mshift(rc, mo_); sc0 = mshift(sc0, mo_);
     SPEC_LOOP(Sc)
     {
@@ -3066,6 +3086,7 @@ __global__ __launch_bounds__(256) void k_2l_prolong(const float2 *__restrict__ r
                                                     SymCtx sc, double *__restrict__ partial, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y);
+    if (mb.stopped(mo_)) return;
     r = mshift(r, mo_); z = mshift(z, mo_); scs = mshift(scs, mo_); sc0 = mshift(sc0, mo_);
     partial = mshift(partial, mo_);
     double acc = 0.0, unused = 0.0;

@@ -24,6 +24,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const float *__r
                                                                 int vec, double *__restrict__ partial, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); a = mshift(a, mo_); b = mshift(b, mo_); partial = mshift(partial, mo_);
+    if (mb.stopped(mo_)) return;
     __shared__ double sh[kRedThreads];
     double acc = 0.0;
     const long stride = (long)gridDim.x * blockDim.x;
@@ -57,6 +58,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double *__re
                                                               double scale, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); partial = mshift(partial, mo_); out = mshift(out, mo_);
+    if (mb.stopped(mo_)) return;
     __shared__ double sh[kRedThreads];
     double acc = 0.0;
     for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[i];
@@ -100,6 +102,7 @@ __global__ void k_axpby(long n, int vec, float a, const float *__restrict__ x, f
                         const float *__restrict__ y, float *__restrict__ out, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); x = mshift(x, mo_); y = mshift(y, mo_); out = mshift(out, mo_);
+    if (mb.stopped(mo_)) return;
     if (y) {
         ew_loop(
             n, vec,
@@ -130,6 +133,7 @@ __global__ void k_h0_point(long n, int vec, float beta0, const float *__restrict
                            const float *__restrict__ G, float *__restrict__ out, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); s = mshift(s, mo_); G = mshift(G, mo_); out = mshift(out, mo_);
+    if (mb.stopped(mo_)) return;
     ew_loop(
         n, vec,
         [&](long i) {
@@ -162,6 +166,7 @@ __global__ void k_h0_rank1(long n, int vec, const float *__restrict__ s, const f
                            float *__restrict__ out, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); s = mshift(s, mo_); G = mshift(G, mo_); out = mshift(out, mo_);
+    if (mb.stopped(mo_)) return;
     ew_loop(
         n, vec,
         [&](long i) {
@@ -298,6 +303,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final_steps(const double
                                                                     double *__restrict__ hist_dst, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); partial = mshift(partial, mo_); d = mshift(d, mo_);
+    const bool skip = mb.stopped(mo_);  // the partials are stale: keep the slots, run the (predicated) steps
     hist_dst = mshift(hist_dst, mo_);
     __shared__ double sh[2][kRedThreads];
     double acc0 = 0.0, acc1 = 0.0;
@@ -316,8 +322,10 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final_steps(const double
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
-    d[a] = scale * sh[0][0];
-    if (b >= 0) d[b] = scale * sh[1][0];
+    if (!skip) {
+        d[a] = scale * sh[0][0];
+        if (b >= 0) d[b] = scale * sh[1][0];
+    }
     if (after & kAfterAlpha) pcg_alpha_step(d);
     if (after & kAfterConv) pcg_conv_step(d);
     if (after & kAfterHist) hist_dst[0] = d[S_REL];
@@ -340,6 +348,7 @@ __global__ void k_inner_accum(const double *inner, double *outer, Mb mb)
 __global__ void k_copy(long n, int vec, const float *__restrict__ x, float *__restrict__ out, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); x = mshift(x, mo_); out = mshift(out, mo_);
+    if (mb.stopped(mo_)) return;
     ew_loop(
         n, vec, [&](long i) { ((float4 *)out)[i] = ((const float4 *)x)[i]; }, [&](long i) { out[i] = x[i]; });
 }

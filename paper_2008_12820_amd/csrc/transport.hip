@@ -296,6 +296,7 @@ __global__ __launch_bounds__(kPtThreads) void k_body_force(const float4 *__restr
                                                            long N4, int nt_rt, float dt, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); lam = mshift(lam, mo_); lamN = mshift(lamN, mo_); G = mshift(G, mo_); b = mshift(b, mo_);
+    if (mb.stopped(mo_)) return;
     const int nt = NTC > 0 ? NTC : nt_rt;
     const long p = (long)xcd_block((int)blockIdx.x, (int)gridDim.x) * kPtThreads + threadIdx.x;
     if (p >= N4) return;
@@ -756,6 +757,7 @@ template <int T1, int T2, class Epi, bool MB, bool HALF>
 __global__ __launch_bounds__(256) void k_box(Grid3 g, const float *__restrict__ disp, Epi epi, int nt2, int nt3,
                                              const TileBox *__restrict__ boxes, Mb mb)
 {
+    if (mb.stopped(MB ? mb.offset(blockIdx.y) : 0)) return;  // a PCG iteration after the stop
     if constexpr (MB) {
         const long long mo_ = mb.offset(blockIdx.y);
         disp = mshift(disp, mo_);
@@ -1045,6 +1047,7 @@ __global__ __launch_bounds__(256) void k_box_pipe(Grid3 g, const float *__restri
                                                   int nt3, const TileBox *__restrict__ boxes, int ntiles, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); disp = mshift(disp, mo_); boxes = mshift(boxes, mo_); epi.shift(mo_);
+    if (mb.stopped(mo_)) return;
     static_assert(Epi::NF == 1, "one field");
     using BC = BoxCfg<T1, T2>;
     constexpr int PPT = BC::PPT, BR1 = BC::BR1, BR2 = BC::BR2, CAP = BC::CAP;
@@ -1190,6 +1193,7 @@ template <class Epi>
 __global__ __launch_bounds__(kPtThreads) void k_direct(Grid3 g, const float *__restrict__ disp, Epi epi, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); disp = mshift(disp, mo_); epi.shift(mo_);
+    if (mb.stopped(mo_)) return;
     const int p = point_index();
     if (p >= g.N) return;
     int i, j, k;
@@ -1208,6 +1212,7 @@ template <class Epi>
 __global__ __launch_bounds__(kPtThreads) void k_direct_lin(Grid3 g, const float *__restrict__ disp, Epi epi, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y); disp = mshift(disp, mo_); epi.shift(mo_);
+    if (mb.stopped(mo_)) return;
     const int p = point_index();
     if (p >= g.N) return;
     int i, j, k;
@@ -1268,6 +1273,7 @@ __global__ __launch_bounds__(256) void k_fd8_grad(const float *__restrict__ f, f
                                                   int n3, float ih1, float ih2, float ih3, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.z); f = mshift(f, mo_); g1 = mshift(g1, mo_); g2 = mshift(g2, mo_); g3 = mshift(g3, mo_);
+    if (mb.stopped(mo_)) return;
     const int nkt = (n3 + 63) / 64;
     const int kt = (int)blockIdx.x % nkt, jt = (int)blockIdx.x / nkt, i = (int)blockIdx.y;
     const int k = kt * 64 + (int)(threadIdx.x & 63), j = jt * 4 + (int)(threadIdx.x >> 6);
@@ -1282,6 +1288,7 @@ __global__ __launch_bounds__(256) void k_fd8_div(const float *__restrict__ v, fl
                                                  int n2, int n3, long N, float ih1, float ih2, float ih3, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.z); v = mshift(v, mo_); out = mshift(out, mo_);
+    if (mb.stopped(mo_)) return;
     const int nkt = (n3 + 63) / 64;
     const int kt = (int)blockIdx.x % nkt, jt = (int)blockIdx.x / nkt, i = (int)blockIdx.y;
     const int k = kt * 64 + (int)(threadIdx.x & 63), j = jt * 4 + (int)(threadIdx.x >> 6);
