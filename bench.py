@@ -611,8 +611,24 @@ def main():
                 pcs[key] = {"ms": 1e3 * (time.perf_counter() - t0), "pcg_iters": inf["pcg_iters"],
                             "inner_iters": inf["inner_iters"], "rel_res": inf["rel_res"], "eps_h0": eps}
                 log(f"newton step rtol 1e-2, {key}: {pcs[key]}")
+            # the same step at a smaller beta (the H0 solves keep their beta0 of 5e-2)
+            pcs_small = {}
+            plan.set_beta(1e-4)
+            for kind, eps in (("inva", 1e-3), ("2linvh0", 1e-1)):
+                plan.set_preconditioner(kind, eps_h0=eps, max_inner=50)
+                key = kind if kind == "inva" else f"{kind}_eps{eps:g}"
+                for _ in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, inf = plan.newton_step(300, 1e-2, allow_notconv=True)
+                    torch.cuda.synchronize()
+                pcs_small[key] = {"ms": 1e3 * (time.perf_counter() - t0), "pcg_iters": inf["pcg_iters"],
+                                  "inner_iters": inf["inner_iters"], "rel_res": inf["rel_res"], "eps_h0": eps}
+                log(f"newton step rtol 1e-2, beta 1e-4, {key}: {pcs_small[key]}")
+            plan.set_beta(5e-4)
             plan.set_preconditioner("inva")
             res_nt[nt_]["newton_preconditioners"] = pcs
+            res_nt[nt_]["newton_preconditioners_beta1e-4"] = pcs_small
             # the eighth-order FD first derivatives (Section 3.2) in a second plan:
             # per-velocity precompute, derivative kernel time, scheme difference
             g_spec, _ = plan.gradient()
@@ -718,6 +734,7 @@ def main():
         "newton_step_10pcg_ms": 1e3 * r4.get("newton_step_s", float("nan")),
         "newton_info": r4.get("newton_info"),
         "newton_rtol_1e-2": r4.get("newton_preconditioners"),
+        "newton_rtol_1e-2_beta1e-4": r4.get("newton_preconditioners_beta1e-4"),
         "fd8": r4.get("fd8"),
         "fft_tiles": r4["tuning"],
         "overlap": not args.no_overlap,
