@@ -522,6 +522,8 @@ def main():
     ap.add_argument("--no-autograd", action="store_true", help="skip the 512^3 autograd run")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the matvec lines (no Leray-off, FFT, SYN, 128^3 Newton, batched, autograd)")
+    ap.add_argument("--no-newton", action="store_true",
+                    help="no Newton steps (the matvec kernels alone, e.g. for hardware counters)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -585,7 +587,7 @@ def main():
         res_nt[nt_] = dict(elapsed=el, steps=steps, kt=kt, prof_steps=prof_steps, kt_dom=kt_dom, dom=dom_,
                            precompute_s=pre, spread=spread,
                            gradient_s=tg, tuning=tuning)
-        if nt_ == 4:
+        if nt_ == 4 and not args.no_newton:
             log("newton step, 10 PCG iterations")
             vt_out, info = plan.newton_step(10, 0.0)  # warm (loads the PCG kernels)
             torch.cuda.synchronize()
@@ -731,7 +733,7 @@ def main():
         "kernels": kernels,
         "precompute_ms": 1e3 * r4["precompute_s"],
         "gradient_ms": 1e3 * r4["gradient_s"],
-        "newton_step_10pcg_ms": 1e3 * r4.get("newton_step_s", float("nan")),
+        "newton_step_10pcg_ms": 1e3 * r4["newton_step_s"] if "newton_step_s" in r4 else None,
         "newton_info": r4.get("newton_info"),
         "newton_rtol_1e-2": r4.get("newton_preconditioners"),
         "newton_rtol_1e-2_beta1e-4": r4.get("newton_preconditioners_beta1e-4"),
