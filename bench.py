@@ -187,8 +187,9 @@ def bench_config2(torch, dev):
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / 3
     m1h = m1.cpu().numpy()
+    tiles = P.tuning()
     P.close()
-    return {"grid": list(n), "pcg_iters": info["pcg_iters"], "newton_step_ms": 1e3 * el}, (m0, m1h)
+    return {"grid": list(n), "pcg_iters": info["pcg_iters"], "newton_step_ms": 1e3 * el, "fft_tiles": tiles}, (m0, m1h)
 
 
 def bench_leray_off(torch, dev, n, m0d, m1d, vd, vtd, steps, warmup):
