@@ -725,12 +725,48 @@ __global__ __launch_bounds__(RB * M / 8) void k_c2r_reg(const char *__restrict__
     }
 }
 
+// rw_run over NF row sets at once (v[f], exchange buffer X + f XCH): one
+// pair of barriers per pass for all of them, and NF independent butterfly
+// chains per thread; per set the arithmetic of rw_run
+template <int M, int RB, bool FWD, bool INV, int P0, int NS, int NF, class C>
+__device__ __forceinline__ void rw_run_n(C (*v)[8], C *X, const C *__restrict__ tw)
+{
+    using S = RowShape<M, RB>;
+    constexpr int R = FWD ? S::P::radix(P0) : S::P::radix(S::NP - 1 - P0);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) rw_butterflies<M, RB, R, NS, INV>(v[f], tw);
+    if constexpr (P0 + 1 < S::NP) {
+        constexpr int R2 = FWD ? S::P::radix(P0 + 1) : S::P::radix(S::NP - 2 - P0);
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int t = 0; t < 8 / R; ++t)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    X[f * S::XCH + rw_line<M, RB, R>(t) * S::RPITCH + rw_slot(rw_out_elem<M, RB, R, NS>(t, r))] =
+                        v[f][t * R + r];
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int t = 0; t < 8 / R2; ++t)
+#pragma unroll
+                for (int r = 0; r < R2; ++r)
+                    v[f][t * R2 + r] =
+                        X[f * S::XCH + rw_line<M, RB, R2>(t) * S::RPITCH + rw_slot(rw_but<M, RB, R2>(t) + r * (M / R2))];
+        rw_run_n<M, RB, FWD, INV, P0 + 1, NS * R, NF>(v, X, tw);
+    }
+}
+
 // The rank-one part of H0 (eq. h0-pc) along x3 rows: the spectra of p in
 // slots in0.. (three fields, after the inverse x1 and x2 passes) go back
 // along x3 as in k_c2r_reg (times scale), t = G (G . p) is formed per point
 // with G = grad m(1) (three physical fields, n3 = 2M floats per row), and t
 // goes forward along x3 as in k_r2c_reg (FP32) into slots out0..; p and t
-// never reach HBM.  The arithmetic of c2r, k_h0_rank1 and r2c in turn.
+// never reach HBM.  The arithmetic of c2r, k_h0_rank1 and r2c in turn; the
+// three fields go through their passes together (three exchange buffers of
+// XCH values in LDS).
 template <int M, int RB>
 __global__ __launch_bounds__(RB * M / 8) void k_x3_rank1(char *__restrict__ spec, long slot_bytes, int in0, int out0,
                                                   const float *__restrict__ G, long nrow,
@@ -745,41 +781,45 @@ __global__ __launch_bounds__(RB * M / 8) void k_x3_rank1(char *__restrict__ spec
     constexpr int RA = S::P::radix(S::NP - 1), R1 = S::P::radix(0);  // first and last inverse radices
     constexpr int R0 = R1, RL = RA;                                   // first and last forward radices
     extern __shared__ char lds_raw[];
-    float2 *X = reinterpret_cast<float2 *>(lds_raw);
+    float2 *X = reinterpret_cast<float2 *>(lds_raw);  // field f: X + f XCH
     const long row0 = (long)blockIdx.x * S::RB;
     const long n3 = 2L * M, N = nrow * n3;
-    float2 pv[3][8];
+    for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += S::NT) {
+        const int c = idx / (M + 1), k = idx - c * (M + 1);
+        const long row = row0 + c;
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        if (f > 0) __syncthreads();  // the exchange buffer is reused
-        const float2 *inm = reinterpret_cast<const float2 *>(spec + (long)(in0 + f) * slot_bytes);
-        const float2 *inq = inm + nrow * M;
-        for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += S::NT) {
-            const int c = idx / (M + 1), k = idx - c * (M + 1);
-            const long row = row0 + c;
+        for (int f = 0; f < 3; ++f) {
+            const float2 *inm = reinterpret_cast<const float2 *>(spec + (long)(in0 + f) * slot_bytes);
+            const float2 *inq = inm + nrow * M;
             float2 Xv = make_float2(0.f, 0.f);
             if (row < nrow) Xv = (k < M) ? inm[row * M + k] : inq[row];
-            X[c * S::RPITCH + rw_slot(k)] = Xv;
+            X[f * S::XCH + c * S::RPITCH + rw_slot(k)] = Xv;
         }
-        __syncthreads();
-        float2 v[8];
+    }
+    __syncthreads();
+    float2 v[3][8];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const float2 *Xf = X + f * S::XCH;
 #pragma unroll
         for (int t = 0; t < 8 / RA; ++t) {
             const int c = rw_line<M, RB, RA>(t);
 #pragma unroll
             for (int r = 0; r < RA; ++r) {
                 const int k = rw_but<M, RB, RA>(t) + r * (M / RA);
-                const float2 Xk = X[c * S::RPITCH + rw_slot(k)];
-                const float2 Xc = conj_(X[c * S::RPITCH + rw_slot(M - k)]);
+                const float2 Xk = Xf[c * S::RPITCH + rw_slot(k)];
+                const float2 Xc = conj_(Xf[c * S::RPITCH + rw_slot(M - k)]);
                 const float2 E = add(Xk, Xc);
                 const float2 O = mulc(sub(Xk, Xc), tw_n[k]);
-                v[t * RA + r] = add(E, muli(O));
+                v[f][t * RA + r] = add(E, muli(O));
             }
         }
-        rw_run<M, RB, false, true, 0, 1>(v, X, tw_m);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) pv[f][i] = make_float2(v[i].x * scale, v[i].y * scale);
     }
+    rw_run_n<M, RB, false, true, 0, 1, 3>(v, X, tw_m);
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[f][i] = make_float2(v[f][i].x * scale, v[f][i].y * scale);
     // t = G (G . p) at the points this thread holds (x3 = 2e, 2e + 1 of its rows)
 #pragma unroll
     for (int t = 0; t < 8 / R1; ++t) {
@@ -788,59 +828,67 @@ __global__ __launch_bounds__(RB * M / 8) void k_x3_rank1(char *__restrict__ spec
         for (int r = 0; r < R1; ++r) {
             const int i = t * R1 + r;
             if (row >= nrow) {
-                pv[0][i] = pv[1][i] = pv[2][i] = make_float2(0.f, 0.f);
+                v[0][i] = v[1][i] = v[2][i] = make_float2(0.f, 0.f);
                 continue;
             }
             const long o = row * n3 + 2 * rw_out_elem<M, RB, R1, M / R1>(t, r);
             const float2 g0 = *reinterpret_cast<const float2 *>(G + o), g1 = *reinterpret_cast<const float2 *>(G + N + o),
                          g2 = *reinterpret_cast<const float2 *>(G + 2 * N + o);
-            const float dx = g0.x * pv[0][i].x + g1.x * pv[1][i].x + g2.x * pv[2][i].x;
-            const float dy = g0.y * pv[0][i].y + g1.y * pv[1][i].y + g2.y * pv[2][i].y;
-            pv[0][i] = make_float2(g0.x * dx, g0.y * dy);
-            pv[1][i] = make_float2(g1.x * dx, g1.y * dy);
-            pv[2][i] = make_float2(g2.x * dx, g2.y * dy);
+            const float dx = g0.x * v[0][i].x + g1.x * v[1][i].x + g2.x * v[2][i].x;
+            const float dy = g0.y * v[0][i].y + g1.y * v[1][i].y + g2.y * v[2][i].y;
+            v[0][i] = make_float2(g0.x * dx, g0.y * dy);
+            v[1][i] = make_float2(g1.x * dx, g1.y * dy);
+            v[2][i] = make_float2(g2.x * dx, g2.y * dy);
         }
     }
+    // t to LDS in natural order, then the forward pass's own distribution
+    __syncthreads();
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        // t to LDS in natural order, then the forward pass's own distribution
-        __syncthreads();
+    for (int f = 0; f < 3; ++f)
 #pragma unroll
         for (int t = 0; t < 8 / R1; ++t)
 #pragma unroll
             for (int r = 0; r < R1; ++r)
-                X[rw_line<M, RB, R1>(t) * S::RPITCH + rw_slot(rw_out_elem<M, RB, R1, M / R1>(t, r))] = pv[f][t * R1 + r];
-        __syncthreads();
-        float2 v[8];
+                X[f * S::XCH + rw_line<M, RB, R1>(t) * S::RPITCH + rw_slot(rw_out_elem<M, RB, R1, M / R1>(t, r))] =
+                    v[f][t * R1 + r];
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
 #pragma unroll
         for (int t = 0; t < 8 / R0; ++t)
 #pragma unroll
             for (int r = 0; r < R0; ++r)
-                v[t * R0 + r] = X[rw_line<M, RB, R0>(t) * S::RPITCH + rw_slot(rw_but<M, RB, R0>(t) + r * (M / R0))];
-        rw_run<M, RB, true, false, 0, 1>(v, X, tw_m);
-        __syncthreads();
+                v[f][t * R0 + r] =
+                    X[f * S::XCH + rw_line<M, RB, R0>(t) * S::RPITCH + rw_slot(rw_but<M, RB, R0>(t) + r * (M / R0))];
+    rw_run_n<M, RB, true, false, 0, 1, 3>(v, X, tw_m);
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
 #pragma unroll
         for (int t = 0; t < 8 / RL; ++t)
 #pragma unroll
             for (int r = 0; r < RL; ++r)
-                X[rw_line<M, RB, RL>(t) * S::RPITCH + rw_slot(rw_out_elem<M, RB, RL, M / RL>(t, r))] = v[t * RL + r];
-        __syncthreads();
-        float2 *outm = reinterpret_cast<float2 *>(spec + (long)(out0 + f) * slot_bytes);
-        float2 *outq = outm + nrow * M;
-        for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += S::NT) {
-            const int c = idx / (M + 1), k = idx - c * (M + 1);
-            const long row = row0 + c;
-            if (row >= nrow) continue;
-            const float2 zk = X[c * S::RPITCH + rw_slot(k == M ? 0 : k)];
-            const float2 zc = conj_(X[c * S::RPITCH + rw_slot(k == 0 ? 0 : M - k)]);
+                X[f * S::XCH + rw_line<M, RB, RL>(t) * S::RPITCH + rw_slot(rw_out_elem<M, RB, RL, M / RL>(t, r))] =
+                    v[f][t * RL + r];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < S::RB * (M + 1); idx += S::NT) {
+        const int c = idx / (M + 1), k = idx - c * (M + 1);
+        const long row = row0 + c;
+        if (row >= nrow) continue;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const float2 *Xf = X + f * S::XCH;
+            const float2 zk = Xf[c * S::RPITCH + rw_slot(k == M ? 0 : k)];
+            const float2 zc = conj_(Xf[c * S::RPITCH + rw_slot(k == 0 ? 0 : M - k)]);
             const float2 E = scl(add(zk, zc), 0.5f);
             const float2 D = scl(sub(zk, zc), 0.5f);
             const float2 O = mk<float2>(D.y, -D.x);  // D / i
             const float2 Xk = add(E, mul(tw_n[k], O));
+            float2 *outm = reinterpret_cast<float2 *>(spec + (long)(out0 + f) * slot_bytes);
             if (k < M)
                 outm[row * M + k] = Xk;
             else
-                outq[row] = Xk;
+                outm[nrow * M + row] = Xk;
         }
     }
 }
@@ -2127,7 +2175,7 @@ bool x3_rank1(lddmm_plan *P, int in0, int out0, const float *G)
         if constexpr (RowPlan<LF>::ok) {
             auto go = [&]<int RB>() {
                 using RS = RowShape<LF, RB>;
-                const size_t lds = sizeof(float2) * RS::XCH;
+                const size_t lds = sizeof(float2) * 3 * RS::XCH;  // an exchange buffer per field
                 check_lds(lds, "x3_rank1");
                 if (lds > 65536) allow_big_lds((const void *)(k_x3_rank1<LF, RB>));
                 const dim3 gr((unsigned)((F.nrow + RB - 1) / RB), 1, P->mb.count);
