@@ -702,7 +702,7 @@ def main():
     def matvec_alg_bytes(nt_):  # whole-matvec algorithmic bytes (Leray on): the classes' sum
         return sum(kernel_bytes(k, n, nt_) for k in MATVEC_CLASSES)
 
-    def survey_bytes(nt_):  # the unfused step count, (136 + 132 N_t) B per grid point (Leray on)
+    def unfused_bytes(nt_):  # the unfused step count, (136 + 132 N_t) B per grid point (Leray on)
         return (136 + 132 * nt_) * N
 
     out = {
@@ -728,8 +728,8 @@ def main():
         "transport": transport_rate(r4, 4),
         "matvec_alg_bytes_per_pt": matvec_alg_bytes(nt) / N,
         "matvec_alg_hbm_frac": matvec_alg_bytes(nt) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-        "matvec_unfused_bytes_per_pt": survey_bytes(nt) / N,
-        "matvec_unfused_hbm_frac": survey_bytes(nt) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "matvec_unfused_bytes_per_pt": unfused_bytes(nt) / N,
+        "matvec_unfused_hbm_frac": unfused_bytes(nt) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
         "matvec_events": r4["spread"],
         "kernels": kernels,
         "precompute_ms": 1e3 * r4["precompute_s"],
@@ -748,7 +748,7 @@ def main():
         out["nt8"] = {"matvecs_per_s": r8["steps"] / r8["elapsed"], "ms_per_matvec": ms8,
                       "transport": transport_rate(r8, 8),
                       "matvec_alg_hbm_frac": matvec_alg_bytes(8) / (ms8 * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                      "matvec_unfused_hbm_frac": survey_bytes(8) / (ms8 * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                      "matvec_unfused_hbm_frac": unfused_bytes(8) / (ms8 * 1e-3) / 1e9 / PEAK_HBM_GBS,
                       "matvec_events": r8["spread"],
                       "precompute_ms": 1e3 * r8["precompute_s"]}
     if args.copy_calibration:

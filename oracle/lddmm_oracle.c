@@ -17,7 +17,7 @@
  *   vector fields are stored component-major: v[c*N + p], c = 0,1,2;
  *   N_t time steps of size dt = 1/N_t.
  *
- * Readings where the paper is silent (each one is listed in the design doc):
+ * Readings where the paper is silent:
  *   RK2 = Heun; the same cubic interpolation evaluates v at the predictor;
  *   cubic Lagrange nodes floor(u)-1 .. floor(u)+2, indices mod n;
  *   the adjoint reaction term is stepped with Heun along the characteristic;
