@@ -205,6 +205,34 @@ def test_pcg_spectra_and_their_physical_images():
     assert er < 1e-6 and ez < 1e-6 and ep < 1e-6 and eh < 1e-6
 
 
+def test_pcg_stops_on_its_tolerance_mid_stream():
+    """The PCG's stop test is read one iteration late and the iterations
+    queued after a stop skip their vector kernels: a solve that meets its
+    tolerance after k of at most 20 iterations must return the oracle's x_k
+    (iteration count, x and relative residual), and a second solve on the same
+    plan (its stop flag reset) must give the same result bitwise."""
+    shape, nt, reg, beta = (24, 20, 30), 2, 2, 1e-3
+    say("PCG stop on the tolerance, mid-stream")
+    m0, m1, vtrue, v, ref = problem(shape, nt, reg, beta, True, disp=2.0)
+    g_ref = ref.gradient()
+    _, _, hist = ref.pcg_history(-g_ref, 10, 1e-30)
+    # a tolerance between the residuals after iterations 5 and 6, clear of both
+    k = next(i for i in range(4, 9) if hist[i - 1] / hist[i] > 1.05)
+    rtol = float(np.sqrt(hist[k - 1] * hist[k]))
+    x_ref, info_ref = ref.pcg(-g_ref, 20, rtol)
+    assert info_ref["iters"] == k + 1
+    P = _plan(shape, nt, reg, beta, True, m0, m1, v)
+    vt, info = P.newton_step(20, rtol)
+    x1 = to_np(vt).copy()
+    e = rel(x1, x_ref)
+    say(f"  stop after {info['pcg_iters']} (oracle {info_ref['iters']}) of 20, rtol {rtol:.3e}: x rel {e:.2e}, "
+        f"rel_res {info['rel_res']:.4e} vs {info_ref['rel_res']:.4e}")
+    assert info["pcg_iters"] == info_ref["iters"] and e < 1e-5
+    assert abs(info["rel_res"] - info_ref["rel_res"]) / info_ref["rel_res"] < 1e-5
+    vt2, info2 = P.newton_step(20, rtol)
+    assert info2["pcg_iters"] == info["pcg_iters"] and np.array_equal(to_np(vt2), x1)
+
+
 def test_negative_curvature_is_reported():
     """With the Leray projection the matvec is beta A v~ + P b~, and for a
     first search direction p = (beta A)^{-1}(-g) that is mostly curl free
