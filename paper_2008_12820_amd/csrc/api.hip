@@ -571,8 +571,8 @@ static void invh0_spec(lddmm_plan *P, const float2 *rh, float2 *sh, double tol, 
     dev_pcg_conv(P);  // the start may already meet the tolerance
     for (int it = 0; it < max_it; ++it) {
         h0_apply_spec(P, pi, qi, true, it == 0 ? kCopy : kAfterX1);                 // kappa, alpha
-        spcg_r(P, ri, qi, sh, pi, S_RR, S_RZN, kAfterConv | kAfterBeta, nullptr);  // s, r; conv, beta
-        spcg_p_x1(P, ri, nullptr, pi, kSlotInv);                                   // p, its x1 pass
+        spcg_r(P, ri, qi, nullptr, nullptr, S_RR, S_RZN, kAfterConv | kAfterBeta, nullptr);  // r; conv, beta
+        spcg_p_x1(P, ri, nullptr, pi, kSlotInv, sh);  // s += alpha p, then p and its x1 pass
         if (poll.after(it)) break;
     }
     if (outer) dev_inner_accum(P, outer);

@@ -1293,6 +1293,7 @@ struct PUpd {
     long S;               // float2 per field of the vectors
     const double *d;
     SymCtx sc;
+    float2 *s = nullptr;  // unless NULL: s += alpha p with p as loaded (before its update)
 };
 
 // The H0 assembly fused into the forward x1 pass that completes the
@@ -1321,7 +1322,11 @@ __global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long 
 {
     const unsigned zc_ = gridDim.z / (unsigned)mb.count, bz_ = blockIdx.z % zc_;
     const long long mo_ = mb.offset(blockIdx.z / zc_); spec = mshift(spec, mo_);
-    if (mb.stopped(mo_)) return;
+    if (mb.stopped(mo_)) {
+        // after a stop only the stopping iteration's s update (alpha != 0) is left
+        if constexpr (!PUPD) return;
+        else if (!pu.s || mshift(pu.d, mo_)[S_ALPHA] == 0.0) return;
+    }
     using C = typename CplxOf<R>::type;
     using S = RegShape<L>;
     extern __shared__ char lds_raw[];
@@ -1342,14 +1347,20 @@ __global__ __launch_bounds__(256) void k_cols_reg(char *__restrict__ spec, long 
         float2 *pp = mshift(pu.p, mo_) + fo;
         const double *dd = mshift(pu.d, mo_);
         if (zz) zz += fo;
+        float2 *ss = mshift(pu.s, mo_);
+        if (ss) ss += fo;
         const bool upd = dd[S_DONE] == 0.0;
-        const float be = (float)dd[S_BETA];
+        const float be = (float)dd[S_BETA], al = (float)dd[S_ALPHA];
         reg_fft<L, INV>(
             [&](int n, int c) {
                 const int col = col0 + c;
                 if (col >= d.ncols) return mk<C>(0, 0);
                 const long e = n * d.nstride + col * d.cstride;
                 float2 v = pp[e];
+                if (ss && al != 0.f) {
+                    const float2 sv = ss[e];
+                    ss[e] = make_float2(__builtin_fmaf(al, v.x, sv.x), __builtin_fmaf(al, v.y, sv.y));
+                }
                 if (upd) {
                     float2 zv;
                     if (zz) {
@@ -2197,7 +2208,7 @@ bool x3_rank1(lddmm_plan *P, int in0, int out0, const float *G)
 static void col_descs(const FftCtx &F, int axis, ColDesc dd[2], int outer[2]);
 static SymCtx sym_ctx(lddmm_plan *P, int leray);
 
-void spcg_p_x1(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int slot0)
+void spcg_p_x1(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int slot0, float2 *sx)
 {
     FftCtx &F = P->fft;
     bool done = false;
@@ -2211,7 +2222,7 @@ void spcg_p_x1(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int s
             const dim3 grid((unsigned)(g0 * outer[0] + g1), 1, 3);
             const size_t lds = sizeof(float2) * RS::XCH;
             check_lds(lds, "fft_cols");
-            const PUpd pu{r, z, p, F.spec_stride, scalars(P), sym_ctx(P, 0)};
+            const PUpd pu{r, z, p, F.spec_stride, scalars(P), sym_ctx(P, 0), sx};
             Scope s(P, K_FFT_COLS);
             FFT_LAUNCH((k_cols_reg<true, float, LF, true>), mgrid(P, grid), lds, P->stream, P->spec, P->slot_bytes, slot0,
                        dd[0], dd[1], g0, outer[0], F.tw1, pu, QAsm{}, P->mb);
@@ -2222,7 +2233,7 @@ void spcg_p_x1(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int s
         check_hip(hipGetLastError(), "k_cols_reg");
         return;
     }
-    spcg_p(P, r, z, p, slot0);
+    spcg_p(P, r, z, p, slot0, sx);
     x1_pass(P, slot0, 3, true, false);
 }
 
@@ -3017,16 +3028,20 @@ __global__ __launch_bounds__(256) void k_spcg_r(float2 *__restrict__ r, const fl
 
 // p = z + beta p with z = M^{-1} r, or the given z when z is not NULL (beta
 // from the device scalars d; p kept once the PCG has stopped), and a copy of
-// p into c (cstride apart) unless c is NULL
+// p into c (cstride apart) unless c is NULL; unless s is NULL first s +=
+// alpha p (the p before its update)
 __global__ __launch_bounds__(256) void k_spcg_p(const float2 *__restrict__ r, const float2 *__restrict__ z,
                                                 float2 *__restrict__ p, float2 *__restrict__ c, long cstride, long S,
-                                                SpecIdx ix, SymCtx sc, const double *__restrict__ d, Mb mb)
+                                                SpecIdx ix, SymCtx sc, const double *__restrict__ d,
+                                                float2 *__restrict__ s, Mb mb)
 {
     const long long mo_ = mb.offset(blockIdx.y);
-    if (mb.stopped(mo_)) return;
+    // after a stop only the stopping iteration's s update (alpha != 0) is left
+    if (mb.stopped(mo_) && (!s || mshift(d, mo_)[S_ALPHA] == 0.0)) return;
     r = mshift(r, mo_); z = mshift(z, mo_); p = mshift(p, mo_); c = mshift(c, mo_); d = mshift(d, mo_);
+    s = mshift(s, mo_);
     const bool upd = d[S_DONE] == 0.0;
-    const float be = (float)d[S_BETA];
+    const float be = (float)d[S_BETA], al = (float)d[S_ALPHA];
     SPEC_LOOP(S)
     {
         int l1, l2, l3;
@@ -3036,6 +3051,10 @@ __global__ __launch_bounds__(256) void k_spcg_p(const float2 *__restrict__ r, co
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             float2 pv = p[f * S + e];
+            if (s && al != 0.f) {
+                const float2 sv = s[f * S + e];
+                s[f * S + e] = make_float2(__builtin_fmaf(al, pv.x, sv.x), __builtin_fmaf(al, pv.y, sv.y));
+            }
             if (upd) {
                 float2 zv;
                 if (z) {
@@ -3241,13 +3260,13 @@ void spcg_r(lddmm_plan *P, float2 *r, const float2 *q, float2 *x, const float2 *
     dev_reduce_final_steps(P, P->red, rr_slot, rz_slot, P->h3 / (double)P->N, after, hist_dst);
 }
 
-void spcg_p(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int cslot)
+void spcg_p(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int cslot, float2 *sx)
 {
     const FftCtx &F = P->fft;
     Scope s(P, K_VECOP);
     hipLaunchKernelGGL(k_spcg_p, dim3(kRedBlocks, P->mb.count), dim3(256), 0, P->stream, r, z, p,
                        cslot >= 0 ? slot_ptr(P, cslot) : nullptr, P->slot_bytes / 8, F.spec_stride, spec_idx(F),
-                       sym_ctx(P, 0), (const double *)scalars(P), P->mb);
+                       sym_ctx(P, 0), (const double *)scalars(P), sx, P->mb);
     check_hip(hipGetLastError(), "k_spcg_p");
 }
 

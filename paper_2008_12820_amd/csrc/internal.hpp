@@ -214,8 +214,9 @@ void spcg_start(lddmm_plan *P, const float2 *b, long bstride, float sign, float2
 void spcg_r(lddmm_plan *P, float2 *r, const float2 *q, float2 *x, const float2 *p, int rr_slot, int rz_slot,
             int after, double *hist_dst);
 // p = z + beta p (device beta, kept after a stop) with z = M^{-1} r when z is
-// NULL; copied into slots cslot.. unless cslot < 0
-void spcg_p(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int cslot);
+// NULL; copied into slots cslot.. unless cslot < 0; unless sx is NULL, first
+// sx += alpha p (device alpha, the p before its update)
+void spcg_p(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int cslot, float2 *sx = nullptr);
 // the forward x1 pass of the spectra in slots slot0.. (t^ after the x3 and
 // x2 passes) fused with the H0 assembly q = t^ + beta0 A p into the vector q,
 // <p, q> into S_KAPPA and alpha; false (nothing done) without a register plan
@@ -223,7 +224,7 @@ bool x1_fwd_h0_assemble(lddmm_plan *P, int slot0, const float2 *p, float2 *q);
 // the same update fused into the inverse x1 pass of p into slots slot0..
 // (where the x1 length has a register plan; else the update, its copy and
 // the pass apart): the slots then hold p after its inverse x1 pass
-void spcg_p_x1(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int slot0);
+void spcg_p_x1(lddmm_plan *P, const float2 *r, const float2 *z, float2 *p, int slot0, float2 *sx = nullptr);
 // <a, b> of three spectra each into scalar slot, then the steps `after`
 void spec_dot(lddmm_plan *P, const float2 *a, const float2 *b, int slot, int after = 0);
 // dst = M^{-1} src, three spectra each
