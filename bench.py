@@ -107,6 +107,30 @@ def measured_traffic(kernel, workload):
     return ent.get("bytes_per_launch")
 
 
+def measured_matvec_bytes(workload, launches):
+    """HBM bytes of one matvec from the committed PMC summary: the gather
+    classes' bytes per launch times their launches per matvec (`launches`,
+    class -> count) plus the transform classes' bytes per matvec; None when
+    a class is missing or its source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh).get(workload, {})
+    total = 0.0
+    for cls in MATVEC_CLASSES:
+        ent = data.get(cls)
+        if not ent or ent.get("source_hash") != source_hash(KERNEL_SOURCE[cls]):
+            return None
+        if "bytes_per_matvec" in ent:
+            total += ent["bytes_per_matvec"]
+        elif cls in launches:
+            total += ent["bytes_per_launch"] * launches[cls]
+        else:
+            return None
+    return total
+
+
 def make_inputs(n, seed=3000):
     import numpy as np
     import synth
@@ -705,6 +729,10 @@ def main():
     def unfused_bytes(nt_):  # the unfused step count, (136 + 132 N_t) B per grid point (Leray on)
         return (136 + 132 * nt_) * N
 
+    # measured (FETCH_SIZE + WRITE_SIZE) bytes of one matvec from the committed counters
+    meas = measured_matvec_bytes(workload, {"incstate_init": 1, "incstate_step": nt - 1, "adj_step": nt - 1,
+                                            "adj_body": 1})
+
     out = {
         "metric": "Hessian matvecs/s and transport grid-pts/s at 256^3 FP32; % HBM roofline",
         "value": value,
@@ -730,6 +758,8 @@ def main():
         "matvec_alg_hbm_frac": matvec_alg_bytes(nt) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
         "matvec_unfused_bytes_per_pt": unfused_bytes(nt) / N,
         "matvec_unfused_hbm_frac": unfused_bytes(nt) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "matvec_measured_bytes": meas,
+        "matvec_measured_hbm_frac": meas / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS if meas else None,
         "matvec_events": r4["spread"],
         "kernels": kernels,
         "precompute_ms": 1e3 * r4["precompute_s"],
