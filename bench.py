@@ -547,6 +547,9 @@ def main():
     ap.add_argument("--no-autograd", action="store_true", help="skip the 512^3 autograd run")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the matvec lines (no Leray-off, FFT, SYN, 128^3 Newton, batched, autograd)")
+    ap.add_argument("--pcg-only", action="store_true",
+                    help="only Newton steps of 10 PCG iterations on the N_t = 4 plan (one warm, three timed), "
+                         "e.g. under a kernel trace")
     ap.add_argument("--no-newton", action="store_true",
                     help="no Newton steps (the matvec kernels alone, e.g. for hardware counters)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -582,6 +585,16 @@ def main():
         tuning = plan.autotune()  # gather strategy, timed on this velocity's displacements
         plan.set_overlap(False)  # the per-class profile below attributes time without sharing
         log(f"autotuned: {tuning}")
+        if args.pcg_only:
+            plan.newton_step(10, 0.0)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                _, info = plan.newton_step(10, 0.0)
+            torch.cuda.synchronize()
+            print(json.dumps({"pcg_only": True, "grid": list(n), "nt": nt_, "pcg_iters": info["pcg_iters"],
+                              "newton_step_10pcg_ms": 1e3 * (time.perf_counter() - t0) / 3}), flush=True)
+            return
         # per-velocity precompute and reduced gradient, warm (the first call of
         # each loads its kernels), mean of three calls
         plan.set_velocity(vd)
