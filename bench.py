@@ -754,6 +754,7 @@ def main():
         "steps": r4["steps"],
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "timed_s": r4["elapsed"],  # the timed region (K matvecs between two synchronisations)
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
